@@ -1,0 +1,448 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics,
+independently of the oracle's own code.
+
+Each test names what it pins and which plausible mistake it would catch:
+
+* scalar harmonics vs scipy.special.sph_harm_y (library routine) -- wrong
+  normalisation, missing Condon-Shortley phase, wrong negative-order rule;
+* vector harmonics vs a brute-force assembly of Definition 3.1 from sympy's
+  exact Clebsch-Gordan coefficients -- any typo in the nine closed forms
+  eq. (ninecoeff), in c_l/d_l, or in eq. (Blm1)/(Blm2)/(vsh2);
+* tangency x . Y = 0 (invariant) and the l = 1 closed forms;
+* surface-gradient identity by finite differences of scipy's Y -- pins the
+  reading Y^div = grad* Y / sqrt(l(l+1)), Y^curl = x cross that;
+* discrete orthonormality (Gram = I) on exact Gauss-Legendre grids and the
+  forward-of-adjoint round trip -- catches a dropped term, a transposed
+  operand or a wrong conjugation in the sums;
+* Parseval identity (Section 4.3, adjoint error paragraph);
+* Theorems 1 and 2 as an independent route (scalar transforms + CG
+  recombination, coefficients from sympy) -- including the full-range
+  reading of nu^(2), nu^(4) and the failure of the literal zero cases;
+* radial invariance, the dot-product adjoint identity, and Tangent Field A's
+  closed-form coefficients (Section 5.2, fixture tests/golden/field_a.txt).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.special import sph_harm_y
+
+import vsht_inputs as vi
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def rel_l2(x, y):
+    x = np.asarray(x).ravel()
+    y = np.asarray(y).ravel()
+    return np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300)
+
+
+def sph_coords(xyz):
+    xyz = np.asarray(xyz)
+    z = np.clip(xyz[:, 2], -1.0, 1.0)
+    theta = np.arccos(z)
+    phi = np.arctan2(xyz[:, 1], xyz[:, 0])
+    return theta, phi
+
+
+def scipy_Y(l, m, xyz):
+    """Y_{l,m} at points via scipy (polar angle theta, azimuth phi)."""
+    if l < 0 or abs(m) > l:
+        return np.zeros(len(xyz), np.complex128)
+    theta, phi = sph_coords(xyz)
+    return sph_harm_y(l, m, theta, phi)
+
+
+def random_sphere(n, seed):
+    xyz, _ = vi.uniform_points(n, seed)
+    return xyz
+
+
+# --------------------------------------------------------------------------
+# scalar harmonics
+# --------------------------------------------------------------------------
+def test_sph_harm_matches_scipy(orc):
+    Lmax = 12
+    xyz = random_sphere(200, 11)
+    Y = orc.sph_harm(Lmax, xyz)
+    err = 0.0
+    for l in range(Lmax + 1):
+        for m in range(-l, l + 1):
+            ref = scipy_Y(l, m, xyz)
+            err = max(err, np.max(np.abs(Y[:, l * l + l + m] - ref)))
+    assert err < 1e-13, err
+
+
+def test_sph_harm_poles(orc):
+    xyz = np.array([[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]])
+    Y = orc.sph_harm(6, xyz)
+    for l in range(7):
+        for m in range(-l, l + 1):
+            ref = math.sqrt((2 * l + 1) / (4 * math.pi)) if m == 0 else 0.0
+            assert abs(Y[0, l * l + l + m] - ref) < 1e-14
+            assert abs(Y[1, l * l + l + m] - (ref * (-1) ** l)) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# vector harmonics: brute force from sympy CG + scipy Y
+# --------------------------------------------------------------------------
+def _cg(j1, m1, j2, m2, J, M):
+    """Standard <j1 m1 j2 m2 | J M> (sympy, exact), zero outside its range."""
+    from sympy.physics.wigner import clebsch_gordan
+    if j1 < 0 or J < 0 or abs(m1) > j1 or abs(m2) > j2 or abs(M) > J or m1 + m2 != M:
+        return 0.0
+    if not (abs(j1 - j2) <= J <= j1 + j2):
+        return 0.0
+    return float(clebsch_gordan(j1, j2, J, m1, m2, M))
+
+
+def test_paper_cg_definition_is_standard():
+    """Section 3 defines C via the 3j symbol; check it is the standard CG."""
+    from sympy.physics.wigner import wigner_3j
+    for l in range(1, 5):
+        for m in range(-l, l + 1):
+            for (j1, m1, j2, m2) in [(l - 1, m - 1, 1, 1), (l + 1, m + 1, 1, -1), (l, m, 1, 0)]:
+                if abs(m1) > j1 or j1 < 0:
+                    continue
+                paper = (-1) ** (m + j1 - j2) * math.sqrt(2 * l + 1) * float(
+                    wigner_3j(j1, j2, l, m1, m2, -m))
+                assert abs(paper - _cg(j1, m1, j2, m2, l, m)) < 1e-14
+
+
+def brute_vsh(L, xyz):
+    """Definition 3.1 written out with sympy CG and scipy Y."""
+    n = len(xyz)
+    K = L * (L + 2)
+    div = np.zeros((n, K, 3), np.complex128)
+    curl = np.zeros((n, K, 3), np.complex128)
+    r2 = math.sqrt(2.0)
+    for l in range(1, L + 1):
+        cl = math.sqrt((l + 1) / (2 * l + 1))
+        dl = math.sqrt(l / (2 * l + 1))
+        for m in range(-l, l + 1):
+            Bp = cl * _cg(l - 1, m - 1, 1, 1, l, m) * scipy_Y(l - 1, m - 1, xyz) + \
+                dl * _cg(l + 1, m - 1, 1, 1, l, m) * scipy_Y(l + 1, m - 1, xyz)
+            B0 = cl * _cg(l - 1, m, 1, 0, l, m) * scipy_Y(l - 1, m, xyz) + \
+                dl * _cg(l + 1, m, 1, 0, l, m) * scipy_Y(l + 1, m, xyz)
+            Bm = cl * _cg(l - 1, m + 1, 1, -1, l, m) * scipy_Y(l - 1, m + 1, xyz) + \
+                dl * _cg(l + 1, m + 1, 1, -1, l, m) * scipy_Y(l + 1, m + 1, xyz)
+            Dp = 1j * _cg(l, m - 1, 1, 1, l, m) * scipy_Y(l, m - 1, xyz)
+            D0 = 1j * _cg(l, m, 1, 0, l, m) * scipy_Y(l, m, xyz)
+            Dm = 1j * _cg(l, m + 1, 1, -1, l, m) * scipy_Y(l, m + 1, xyz)
+            j = l * l + l + m - 1
+            div[:, j, 0] = -(Bp - Bm) / r2
+            div[:, j, 1] = -1j * (Bp + Bm) / r2
+            div[:, j, 2] = B0
+            curl[:, j, 0] = -(Dp - Dm) / r2
+            curl[:, j, 1] = -1j * (Dp + Dm) / r2
+            curl[:, j, 2] = D0
+    return div, curl
+
+
+def test_vsh_matches_brute_force_cg(orc):
+    L = 6
+    xyz = random_sphere(64, 12)
+    d, c = orc.vsh(L, xyz)
+    bd, bc = brute_vsh(L, xyz)
+    assert np.max(np.abs(d - bd)) < 1e-13
+    assert np.max(np.abs(c - bc)) < 1e-13
+
+
+def test_vsh_tangent(orc):
+    L = 10
+    xyz = random_sphere(100, 13)
+    d, c = orc.vsh(L, xyz)
+    assert np.max(np.abs(np.einsum("nkc,nc->nk", d, xyz))) < 1e-13
+    assert np.max(np.abs(np.einsum("nkc,nc->nk", c, xyz))) < 1e-13
+
+
+def test_vsh_l1_closed_forms(orc):
+    xyz = random_sphere(50, 14)
+    d, c = orc.vsh(1, xyz)
+    zhat = np.array([0.0, 0.0, 1.0])
+    z = xyz[:, 2:3]
+    f10 = math.sqrt(3.0 / (8.0 * math.pi)) * (zhat[None, :] - z * xyz)
+    f11 = -math.sqrt(3.0 / (16.0 * math.pi)) * (
+        np.array([1.0, 1j, 0.0])[None, :] - (xyz[:, 0:1] + 1j * xyz[:, 1:2]) * xyz)
+    j10, j11 = 1, 2  # index l*l+l+m-1
+    assert np.max(np.abs(d[:, j10] - f10)) < 1e-14
+    assert np.max(np.abs(c[:, j10] - math.sqrt(3.0 / (8.0 * math.pi)) * np.cross(xyz, zhat))) < 1e-14
+    assert np.max(np.abs(d[:, j11] - f11)) < 1e-14
+    assert np.max(np.abs(c[:, j11] - np.cross(xyz, f11))) < 1e-14
+
+
+def fd_surface_grad(l, m, xyz, h=1e-6):
+    """grad of Y_{l,m}(x/|x|) by central differences (tangent at |x| = 1)."""
+    g = np.zeros((len(xyz), 3), np.complex128)
+    for c in range(3):
+        e = np.zeros(3)
+        e[c] = h
+        xp = xyz + e
+        xm = xyz - e
+        xp = xp / np.linalg.norm(xp, axis=1, keepdims=True)
+        xm = xm / np.linalg.norm(xm, axis=1, keepdims=True)
+        g[:, c] = (scipy_Y(l, m, xp) - scipy_Y(l, m, xm)) / (2 * h)
+    return g
+
+
+def test_vsh_gradient_identity(orc):
+    """Y^div = grad* Y / sqrt(l(l+1)) and Y^curl = x cross Y^div."""
+    L = 5
+    xyz = random_sphere(40, 15)
+    xyz = xyz[np.abs(xyz[:, 2]) < 0.95]
+    d, c = orc.vsh(L, xyz)
+    for l in range(1, L + 1):
+        for m in range(-l, l + 1):
+            j = l * l + l + m - 1
+            g = fd_surface_grad(l, m, xyz) / math.sqrt(l * (l + 1))
+            assert np.max(np.abs(d[:, j] - g)) < 2e-8, (l, m)
+            assert np.max(np.abs(c[:, j] - np.cross(xyz, g))) < 2e-8, (l, m)
+
+
+# --------------------------------------------------------------------------
+# quadrature facts
+# --------------------------------------------------------------------------
+def gram(orc, L, xyz, w):
+    d, c = orc.vsh(L, xyz)
+    V = np.concatenate([d, c], axis=1)  # (n, 2K, 3)
+    return np.einsum("n,nic,njc->ij", w, V.conj(), V)
+
+
+@pytest.mark.parametrize("grid,exact", [("Lp1x2Lp2", True), ("Lp1x2Lp1", True), ("Lx2Lp2", False)])
+def test_discrete_orthonormality_gl(orc, grid, exact):
+    L = 6
+    nt, npf = {"Lp1x2Lp2": (L + 1, 2 * L + 2), "Lp1x2Lp1": (L + 1, 2 * L + 1),
+               "Lx2Lp2": (L, 2 * L + 2)}[grid]
+    xyz, w = vi.gl_grid(L, nt, npf)
+    assert abs(w.sum() - 4 * math.pi) < 1e-13
+    G = gram(orc, L, xyz, w)
+    err = np.max(np.abs(G - np.eye(G.shape[0])))
+    if exact:
+        assert err < 1e-13, err
+    else:
+        assert err > 0.1, err
+
+
+def test_roundtrip_gl(orc):
+    L = 12
+    xyz, w = vi.gl_grid(L)
+    a, b = vi.random_coeffs(L, 0)
+    T = orc.adjoint(L, a, b, xyz)
+    a2, b2 = orc.forward(L, xyz, w, T)
+    assert rel_l2(np.concatenate([a2, b2]), np.concatenate([a, b])) < 1e-13
+
+
+def test_parseval_gl(orc):
+    L = 10
+    xyz, w = vi.gl_grid(L)
+    a, b = vi.random_coeffs(L, 3)
+    T = orc.adjoint(L, a, b, xyz)
+    lhs = np.sum(w * np.sum(np.abs(T) ** 2, axis=1))
+    rhs = np.sum(np.abs(a) ** 2) + np.sum(np.abs(b) ** 2)
+    assert abs(lhs - rhs) / rhs < 1e-13
+
+
+def test_radial_invariance(orc):
+    L = 8
+    xyz, w = vi.gl_grid(L)
+    T = vi.random_field(len(w), 5)
+    f = vi.random_field(len(w), 6)[:, 0]
+    a1, b1 = orc.forward(L, xyz, w, T)
+    a2, b2 = orc.forward(L, xyz, w, T + f[:, None] * xyz)
+    assert rel_l2(np.concatenate([a2, b2]), np.concatenate([a1, b1])) < 1e-13
+
+
+def test_dot_product_adjoint(orc):
+    L = 9
+    xyz, _ = vi.uniform_points(300, 7)
+    a, b = vi.random_coeffs(L, 8, scale="none")
+    T = vi.random_field(len(xyz), 9)
+    lhs = np.sum(orc.adjoint(L, a, b, xyz).conj() * T)
+    a2, b2 = orc.forward(L, xyz, np.ones(len(xyz)), T)
+    rhs = np.sum(a.conj() * a2) + np.sum(b.conj() * b2)
+    assert abs(lhs - rhs) / abs(rhs) < 1e-13
+
+
+def test_forward_subset_matches_full(orc):
+    L = 9
+    for xyz, w in (vi.gl_grid(L), vi.uniform_points(500, 21)):
+        T = vi.random_field(len(w), 4)
+        a, b = orc.forward(L, xyz, w, T)
+        idx = vi.sample_indices(L * (L + 2), 30, 1)
+        idx = np.unique(np.concatenate([idx, [0, 1, 2, L * (L + 2) - 1]]))
+        sa, sb = orc.forward_subset(L, xyz, w, T, idx)
+        assert np.max(np.abs(sa - a[idx])) < 1e-13 * np.max(np.abs(a))
+        assert np.max(np.abs(sb - b[idx])) < 1e-13 * np.max(np.abs(b))
+
+
+# --------------------------------------------------------------------------
+# Theorems 1 and 2 as an independent route
+# --------------------------------------------------------------------------
+def _c(l):
+    return math.sqrt((l + 1) / (2 * l + 1)) if l >= 0 else 0.0
+
+
+def _d(l):
+    return math.sqrt(l / (2 * l + 1)) if l >= 0 else 0.0
+
+
+def scalar_forward(xyz, w, f, Lmax):
+    """eq. (Flm): F_{l,m}(f) = sum_k w_k f_k Y_{l,m}(x_k)^*, via scipy."""
+    F = {}
+    for l in range(Lmax + 1):
+        for m in range(-l, l + 1):
+            F[(l, m)] = np.sum(w * f * scipy_Y(l, m, xyz).conj())
+    return F
+
+
+def theorem1_forward(L, xyz, w, T):
+    """Forward VSHT by Theorem 1 (eq. almblmviaFlm)."""
+    F1 = scalar_forward(xyz, w, T[:, 0], L + 1)
+    F2 = scalar_forward(xyz, w, T[:, 1], L + 1)
+    F3 = scalar_forward(xyz, w, T[:, 2], L + 1)
+    g = lambda F, l, m: F.get((l, m), 0.0) if l >= 0 and abs(m) <= l else 0.0
+    xi1 = lambda l, m: _c(l + 1) * _cg(l, m, 1, 1, l + 1, m + 1)
+    xi2 = lambda l, m: _d(l - 1) * _cg(l, m, 1, 1, l - 1, m + 1)
+    xi3 = lambda l, m: _c(l + 1) * _cg(l, m, 1, -1, l + 1, m - 1)
+    xi4 = lambda l, m: _d(l - 1) * _cg(l, m, 1, -1, l - 1, m - 1)
+    xi5 = lambda l, m: _c(l + 1) * _cg(l, m, 1, 0, l + 1, m)
+    xi6 = lambda l, m: _d(l - 1) * _cg(l, m, 1, 0, l - 1, m)
+    mu1 = lambda l, m: _cg(l, m, 1, 1, l, m + 1)
+    mu2 = lambda l, m: _cg(l, m, 1, 0, l, m)
+    mu3 = lambda l, m: _cg(l, m, 1, -1, l, m - 1)
+    K = L * (L + 2)
+    a = np.zeros(K, np.complex128)
+    b = np.zeros(K, np.complex128)
+    r2 = math.sqrt(2.0)
+    for l in range(1, L + 1):
+        for m in range(-l, l + 1):
+            j = l * l + l + m - 1
+            a[j] = (1 / r2) * (
+                xi1(l - 1, m - 1) * (-g(F1, l - 1, m - 1) + 1j * g(F2, l - 1, m - 1))
+                + xi2(l + 1, m - 1) * (-g(F1, l + 1, m - 1) + 1j * g(F2, l + 1, m - 1))
+                + xi3(l - 1, m + 1) * (g(F1, l - 1, m + 1) + 1j * g(F2, l - 1, m + 1))
+                + xi4(l + 1, m + 1) * (g(F1, l + 1, m + 1) + 1j * g(F2, l + 1, m + 1))) \
+                + xi5(l - 1, m) * g(F3, l - 1, m) + xi6(l + 1, m) * g(F3, l + 1, m)
+            b[j] = -(1j / r2) * (
+                mu1(l, m - 1) * (-g(F1, l, m - 1) + 1j * g(F2, l, m - 1))
+                + mu3(l, m + 1) * (g(F1, l, m + 1) + 1j * g(F2, l, m + 1))) \
+                - 1j * mu2(l, m) * g(F3, l, m)
+    return a, b
+
+
+def theorem2_adjoint(L, a, b, xyz, literal_zero_cases=False):
+    """Adjoint VSHT by Theorem 2 (eq. SLvecviascal) with nu, eta of
+    eq. (nulm1), (nulm2), (etalm).  Coefficients outside 1 <= l <= L, |m| <= l
+    are zero.  With literal_zero_cases the printed zero cases of nu^(2) and
+    nu^(4) are applied as written."""
+    A = lambda l, m: a[l * l + l + m - 1] if 1 <= l <= L and abs(m) <= l else 0.0
+    B = lambda l, m: b[l * l + l + m - 1] if 1 <= l <= L and abs(m) <= l else 0.0
+    comps = [np.zeros(len(xyz), np.complex128) for _ in range(3)]
+    r2 = math.sqrt(2.0)
+    for l in range(0, L + 2):
+        for m in range(-l, l + 1):
+            Y = scipy_Y(l, m, xyz)
+            nu = [0.0] * 7
+            if l <= L - 1:
+                p = A(l + 1, m + 1) * _cg(l, m, 1, 1, l + 1, m + 1)
+                q = A(l + 1, m - 1) * _cg(l, m, 1, -1, l + 1, m - 1)
+                nu[1] = _c(l + 1) * (p - q)
+                nu[3] = 1j * _c(l + 1) * (p + q)
+                nu[5] = A(l + 1, m) * _c(l + 1) * _cg(l, m, 1, 0, l + 1, m)
+            if 2 <= l <= L + 1:
+                p = A(l - 1, m + 1) * _cg(l, m, 1, 1, l - 1, m + 1)
+                q = A(l - 1, m - 1) * _cg(l, m, 1, -1, l - 1, m - 1)
+                nu[2] = _d(l - 1) * (p - q)
+                nu[4] = 1j * _d(l - 1) * (p + q)
+                nu[6] = A(l - 1, m) * _d(l - 1) * _cg(l, m, 1, 0, l - 1, m)
+                if literal_zero_cases:
+                    if abs(m) in (l - 1, l):
+                        nu[2] = 0.0
+                    if abs(m) in (l - 2, l - 1):
+                        nu[4] = 0.0
+            eta1 = eta2 = eta3 = 0.0
+            if 1 <= l <= L:
+                p = B(l, m + 1) * _cg(l, m, 1, 1, l, m + 1)
+                q = B(l, m - 1) * _cg(l, m, 1, -1, l, m - 1)
+                eta1 = 1j * (p - q)
+                eta2 = p + q
+                eta3 = 1j * B(l, m) * _cg(l, m, 1, 0, l, m)
+            comps[0] += -(1 / r2) * (nu[1] + nu[2] + eta1) * Y
+            comps[1] += -(1 / r2) * (nu[3] + nu[4] - eta2) * Y
+            comps[2] += (nu[5] + nu[6] + eta3) * Y
+    return np.stack(comps, axis=1)
+
+
+def test_theorem1_route(orc):
+    L = 5
+    xyz, w = vi.uniform_points(120, 31)
+    T = vi.random_field(120, 32)
+    a, b = orc.forward(L, xyz, w, T)
+    ta, tb = theorem1_forward(L, xyz, w, T)
+    assert rel_l2(np.concatenate([ta, tb]), np.concatenate([a, b])) < 1e-13
+
+
+def test_theorem2_route_full_nu(orc):
+    L = 5
+    xyz, _ = vi.uniform_points(80, 33)
+    a, b = vi.random_coeffs(L, 34, scale="none")
+    T = orc.adjoint(L, a, b, xyz)
+    T2 = theorem2_adjoint(L, a, b, xyz)
+    assert rel_l2(T2, T) < 1e-13
+
+
+def test_theorem2_literal_zero_cases_disagree(orc):
+    """The printed zero cases of nu^(2), nu^(4) do not reproduce eq. (SLvec)."""
+    L = 4
+    xyz, _ = vi.uniform_points(40, 35)
+    a, b = vi.random_coeffs(L, 36, scale="none")
+    T = orc.adjoint(L, a, b, xyz)
+    T2 = theorem2_adjoint(L, a, b, xyz, literal_zero_cases=True)
+    assert rel_l2(T2, T) > 1e-2
+
+
+# --------------------------------------------------------------------------
+# Tangent Field A (Section 5.2): closed-form coefficients
+# --------------------------------------------------------------------------
+def load_field_a():
+    terms = []
+    with open(os.path.join(GOLDEN, "field_a.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            role, l, m, c = line.split()
+            terms.append((role, int(l), int(m), float(c)))
+    return terms
+
+
+def test_field_a_coefficients(orc):
+    """Build T = x cross grad* s1 + grad* v1 with finite-difference gradients of
+    scipy's Y; its forward transform on an exact GL grid has the closed-form
+    coefficients a = sqrt(l(l+1)) * (potential coeff), b = sqrt(l(l+1)) *
+    (stream coeff), all others zero.  The paper leaves the sign of its
+    surface-curl operator undefined; here L s = x cross grad* s."""
+    terms = load_field_a()
+    assert terms[0][3] == pytest.approx(-1 / math.sqrt(3), rel=1e-15)
+    assert terms[1][3] == pytest.approx(8 * math.sqrt(2) / (3 * math.sqrt(385)), rel=1e-15)
+    L = 8
+    xyz, w = vi.gl_grid(L)
+    T = np.zeros((len(w), 3), np.complex128)
+    K = L * (L + 2)
+    a_ref = np.zeros(K, np.complex128)
+    b_ref = np.zeros(K, np.complex128)
+    for role, l, m, c in terms:
+        g = fd_surface_grad(l, m, xyz, h=1e-6)
+        j = l * l + l + m - 1
+        if role == "potential":
+            T += c * g
+            a_ref[j] = c * math.sqrt(l * (l + 1))
+        else:
+            T += c * np.cross(xyz, g)
+            b_ref[j] = c * math.sqrt(l * (l + 1))
+    a, b = orc.forward(L, xyz, w, T)
+    assert np.max(np.abs(a - a_ref)) < 1e-7
+    assert np.max(np.abs(b - b_ref)) < 1e-7
+    assert abs(a_ref[4 * 4 + 4 + 0 - 1] - math.sqrt(20) / 25) < 1e-15
+    assert abs(a_ref[6 * 6 + 6 - 3 - 1] - math.sqrt(42) / 25) < 1e-15
