@@ -1,0 +1,146 @@
+/*
+ * vsht.h -- C interface of the MI355X (gfx950) vector spherical harmonic
+ * transform library.
+ *
+ * The library computes the two transforms of Le Gia, Li and Wang, "FaVeST:
+ * fast vector spherical harmonic transforms" for tangent fields T: S^2 -> C^3:
+ *
+ *   forward  (Definition 4.1, eq. (fwdvsht2)), for 1 <= l <= L, |m| <= l:
+ *       a_{l,m} = sum_{k=1}^{N} w_k Y^div_{l,m}(x_k)^* T_k
+ *       b_{l,m} = sum_{k=1}^{N} w_k Y^curl_{l,m}(x_k)^* T_k
+ *   adjoint  (Definition 4.2, eq. (SLvec)), at every point x_i of the plan:
+ *       T(x_i) = sum_{l=1}^{L} sum_{m=-l}^{l} a_{l,m} Y^div_{l,m}(x_i) + b_{l,m} Y^curl_{l,m}(x_i)
+ *
+ * with Y^div, Y^curl the vector spherical harmonics of Definition 3.1 (built
+ * from 4pi-orthonormal scalar harmonics with the Condon-Shortley phase; the
+ * negative orders satisfy Y_{l,-m} = (-1)^m conj(Y_{l,m})).  The quadrature
+ * rule Q_N = {(w_k, x_k)} is the one of Section 4.1.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Points    host array xyz[n][3] of binary64 unit vectors, row-major.
+ * Weights   host array w[n] of binary64 (the quadrature weights).
+ * Field T   device array of n x 3 complex numbers, row-major, each complex as
+ *           (re, im) adjacent: complex128 for VSHT_FP64, complex64 otherwise.
+ * Coeffs    device arrays a, b of vsht_num_coeffs(L) = L(L+2) complex numbers
+ *           in the order l = 1..L, m = -l..l, i.e. a[l*l + l + m - 1]
+ *           (same complex type as T).  There is no l = 0 entry.
+ * Streams   `stream` is a hipStream_t passed as void* (NULL = the null
+ *           stream).  Every call enqueues work on that stream and returns
+ *           without waiting; buffers must stay valid until the stream has
+ *           finished.  A plan must not run on two streams at the same time
+ *           (it owns one workspace); create one plan per concurrent stream.
+ * Ownership The plan deep-copies points and weights at creation and owns its
+ *           device tables and workspace; the caller owns T, a and b.
+ * Errors    Every function returns a vsht_status and never throws; on an
+ *           error the outputs are unspecified.  vsht_last_error() returns a
+ *           thread-local description of the last error on the calling thread.
+ *
+ * Point sets
+ * ----------
+ * The fast path needs iso-latitude rings: the points are grouped into
+ * consecutive runs with bitwise-equal z (one run per ring), each run holding
+ * n_phi >= 1 points at longitudes phi_0 + 2 pi j / n_phi, j = 0..n_phi-1 (in
+ * this order), all with the same weight, and no ring at a pole.  Rings whose
+ * z values are exact negatives of each other are paired (north/south).  The
+ * Gauss-Legendre product grids of Section 5.1 are of this kind.  Other point
+ * sets are "scattered": they are accepted for the adjoint only.
+ */
+#ifndef VSHT_H
+#define VSHT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vsht_plan_s *vsht_plan_t;
+
+typedef enum {
+    VSHT_OK = 0,
+    VSHT_EINVAL = 1,      /* invalid argument (sizes, null pointers, non-unit or non-finite points) */
+    VSHT_ENOWEIGHTS = 2,  /* forward called on a plan created without weights */
+    VSHT_ENOMEM = 3,      /* host or device allocation failed */
+    VSHT_EDEVICE = 4,     /* a HIP call failed; vsht_last_error() has the detail */
+    VSHT_EUNSUPPORTED = 5 /* valid request this build cannot serve (e.g. forward on scattered points) */
+} vsht_status;
+
+typedef enum {
+    VSHT_FP64 = 0,   /* complex128 I/O, binary64 arithmetic throughout */
+    VSHT_FP32 = 1,   /* complex64 I/O, binary32 contraction and FFT, binary64 Legendre recurrence */
+    VSHT_BF16X3 = 2  /* complex64 I/O, Legendre contraction as three bf16 split products with
+                        binary32 accumulation, binary64 Legendre recurrence */
+} vsht_precision;
+
+typedef struct {
+    int precision; /* a vsht_precision value */
+    int device;    /* HIP device ordinal; -1 = the calling thread's current device */
+} vsht_opts;
+
+/* Plan kinds reported by vsht_plan_info. */
+typedef enum { VSHT_PLAN_RINGS = 0, VSHT_PLAN_SCATTERED = 1 } vsht_plan_kind;
+
+typedef struct {
+    int L;
+    int precision;
+    int kind;           /* vsht_plan_kind */
+    int64_t n_points;
+    int64_t n_rings;    /* rings found (0 for scattered) */
+    int64_t n_pairs;    /* north/south ring pairs incl. unpaired rings (0 for scattered) */
+    int64_t max_nphi;   /* longest ring */
+    int has_weights;
+    size_t workspace_bytes;
+    size_t table_bytes;
+} vsht_plan_info_t;
+
+/* Number of coefficients of each kind for bandlimit L: L(L+2) (L >= 1), else 0. */
+int64_t vsht_num_coeffs(int L);
+
+/* Create a plan for bandlimit L >= 1 on n points.
+ *   xyz     host, n x 3 binary64 unit vectors (| |x| - 1 | <= 1e-12), finite.
+ *   w       host, n binary64 weights, or NULL for an adjoint-only plan.
+ *   opts    NULL for defaults (VSHT_FP64, current device).
+ *   out     receives the plan on success.
+ * Requirements: n >= 1; a plan with weights needs n >= 2 (Section 4.1, the
+ * quadrature rule has N >= 2 nodes).  Returns VSHT_EINVAL on a violation,
+ * VSHT_ENOMEM / VSHT_EDEVICE on allocation or HIP failures. */
+vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w,
+                      const vsht_opts *opts, vsht_plan_t *out);
+
+/* Forward transform (Definition 4.1, eq. (fwdvsht2)): T (device, n x 3) ->
+ * a, b (device, L(L+2) each).  VSHT_ENOWEIGHTS if the plan has no weights,
+ * VSHT_EUNSUPPORTED on a scattered plan. */
+vsht_status vsht_forward(vsht_plan_t plan, const void *T, void *a, void *b, void *stream);
+
+/* Forward transform with unit weights, i.e. the exact adjoint (Hermitian
+ * transpose) of vsht_adjoint as a linear map C^{2K} -> C^{3n}:
+ *   a_{l,m} = sum_k Y^div_{l,m}(x_k)^* T_k, b likewise.
+ * Used as the backward of the adjoint in automatic differentiation.  Works on
+ * plans with or without weights; VSHT_EUNSUPPORTED on a scattered plan. */
+vsht_status vsht_forward_unweighted(vsht_plan_t plan, const void *T, void *a, void *b,
+                                    void *stream);
+
+/* Adjoint transform (Definition 4.2, eq. (SLvec)): a, b (device) -> T
+ * (device, n x 3) at every point of the plan, in the plan's point order. */
+vsht_status vsht_adjoint(vsht_plan_t plan, const void *a, const void *b, void *T, void *stream);
+
+/* Describe a plan (host-side; no device work). */
+vsht_status vsht_plan_info(vsht_plan_t plan, vsht_plan_info_t *info);
+
+/* Release a plan and everything it owns (waits for the device first).
+ * Passing NULL is allowed and returns VSHT_OK. */
+vsht_status vsht_plan_destroy(vsht_plan_t plan);
+
+/* Static description of a status code. */
+const char *vsht_status_string(vsht_status s);
+
+/* Thread-local detail of the last error raised on the calling thread ("" if none). */
+const char *vsht_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VSHT_H */

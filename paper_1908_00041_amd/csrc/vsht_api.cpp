@@ -1,0 +1,431 @@
+// vsht_api.cpp -- host side of the library: argument checking, analysis of
+// the point set (rings, north/south pairs), binary64 tables, workspace, and
+// the extern "C" entry points declared in include/vsht.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "vsht_internal.h"
+
+namespace vsht {
+hipError_t launch_seed_kernel(const double *pair_s, int NP, int L, double *seeds, hipStream_t st);
+hipError_t set_kernel_attributes();
+}  // namespace vsht
+
+using namespace vsht;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+vsht_status fail(vsht_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+vsht_status hip_fail(hipError_t e, const char *what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? VSHT_ENOMEM : VSHT_EDEVICE;
+}
+
+// Largest sizes the ring kernels are compiled for.
+constexpr int64_t kMaxNphi = 3072;
+constexpr int kMaxLRings = 2047;
+
+struct DeviceGuard {
+    int old = -1;
+    bool changed = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&old) == hipSuccess && old != dev) {
+            if (hipSetDevice(dev) == hipSuccess) changed = true;
+        }
+    }
+    ~DeviceGuard() {
+        if (changed) (void)hipSetDevice(old);
+    }
+};
+
+template <typename T>
+hipError_t upload(T **dst, const std::vector<T> &src, size_t *bytes) {
+    *dst = nullptr;
+    if (src.empty()) return hipSuccess;
+    hipError_t e = hipMalloc((void **)dst, sizeof(T) * src.size());
+    if (e != hipSuccess) return e;
+    *bytes += sizeof(T) * src.size();
+    return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+}
+
+void free_plan_memory(Plan *p) {
+    void *ptrs[] = {p->d_rings, p->d_pairs, p->d_ffts, p->d_tw,  p->d_pair_z, p->d_recA,
+                    p->d_recB,  p->d_seeds, p->d_weights, p->d_xyz, p->d_pb,  p->d_fg,
+                    p->d_state};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+}
+
+// Factor n for the Stockham stages: radix 4 first, then 2, then odd primes ascending.
+std::vector<int> factorize(int n) {
+    std::vector<int> f;
+    while (n % 4 == 0) { f.push_back(4); n /= 4; }
+    while (n % 2 == 0) { f.push_back(2); n /= 2; }
+    for (int p = 3; (long)p * p <= n; p += 2)
+        while (n % p == 0) { f.push_back(p); n /= p; }
+    if (n > 1) f.push_back(n);
+    return f;
+}
+
+struct RingScan {
+    bool ok = true;
+    std::string why;
+    std::vector<RingDesc> rings;
+};
+
+// Group consecutive points with bitwise-equal z into rings and check each is
+// an equispaced circle not at a pole.
+RingScan scan_rings(int64_t n, const double *xyz, const double *w) {
+    RingScan rs;
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    int64_t i = 0;
+    while (i < n) {
+        int64_t j = i + 1;
+        const double z = xyz[3 * i + 2];
+        while (j < n && xyz[3 * j + 2] == z) ++j;
+        const int64_t cnt = j - i;
+        RingDesc r{};
+        r.z = z;
+        r.s = std::sqrt((1.0 - z) * (1.0 + z));
+        r.offset = i;
+        r.nphi = (int32_t)cnt;
+        if (!(r.s > 0.0)) {
+            rs.ok = false;
+            rs.why = "point at a pole";
+            return rs;
+        }
+        if (cnt > kMaxNphi) {
+            rs.ok = false;
+            rs.why = "ring longer than supported";
+            return rs;
+        }
+        r.phi0 = std::atan2(xyz[3 * i + 1], xyz[3 * i]);
+        r.c0 = std::cos(r.phi0);
+        r.s0 = std::sin(r.phi0);
+        for (int64_t t = 0; t < cnt; ++t) {
+            const long double ph = (long double)r.phi0 + two_pi * (long double)t / (long double)cnt;
+            const double ex = (double)((long double)r.s * cosl(ph));
+            const double ey = (double)((long double)r.s * sinl(ph));
+            if (std::fabs(xyz[3 * (i + t)] - ex) > 1e-12 || std::fabs(xyz[3 * (i + t) + 1] - ey) > 1e-12) {
+                rs.ok = false;
+                rs.why = "ring points not equispaced in longitude";
+                return rs;
+            }
+        }
+        r.uniform_w = 1;
+        r.w = w ? w[i] : 1.0;
+        if (w)
+            for (int64_t t = 1; t < cnt; ++t)
+                if (w[i + t] != w[i]) r.uniform_w = 0;
+        rs.rings.push_back(r);
+        i = j;
+    }
+    return rs;
+}
+
+}  // namespace
+
+struct vsht_plan_s {
+    Plan p;
+};
+
+extern "C" {
+
+int64_t vsht_num_coeffs(int L) { return L >= 1 ? (int64_t)L * (L + 2) : 0; }
+
+const char *vsht_status_string(vsht_status s) {
+    switch (s) {
+        case VSHT_OK: return "VSHT_OK";
+        case VSHT_EINVAL: return "VSHT_EINVAL: invalid argument";
+        case VSHT_ENOWEIGHTS: return "VSHT_ENOWEIGHTS: plan has no quadrature weights";
+        case VSHT_ENOMEM: return "VSHT_ENOMEM: out of memory";
+        case VSHT_EDEVICE: return "VSHT_EDEVICE: HIP error";
+        case VSHT_EUNSUPPORTED: return "VSHT_EUNSUPPORTED: not supported for this plan";
+    }
+    return "unknown vsht_status";
+}
+
+const char *vsht_last_error(void) { return g_last_error.c_str(); }
+
+vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w, const vsht_opts *opts,
+                      vsht_plan_t *out) {
+    g_last_error.clear();
+    if (!out) return fail(VSHT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (L < 1) return fail(VSHT_EINVAL, "L must be >= 1");
+    if (L > 65535) return fail(VSHT_EINVAL, "L too large");
+    if (n < 1) return fail(VSHT_EINVAL, "n must be >= 1");
+    if (w && n < 2) return fail(VSHT_EINVAL, "a quadrature rule needs n >= 2 points");
+    if (!xyz) return fail(VSHT_EINVAL, "xyz is NULL");
+    const int precision = opts ? opts->precision : VSHT_FP64;
+    if (precision != VSHT_FP64 && precision != VSHT_FP32 && precision != VSHT_BF16X3)
+        return fail(VSHT_EINVAL, "unknown precision");
+    for (int64_t k = 0; k < n; ++k) {
+        const double x = xyz[3 * k], y = xyz[3 * k + 1], z = xyz[3 * k + 2];
+        if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z))
+            return fail(VSHT_EINVAL, "non-finite point at index " + std::to_string(k));
+        const double r = std::sqrt(x * x + y * y + z * z);
+        if (std::fabs(r - 1.0) > 1e-12)
+            return fail(VSHT_EINVAL, "point " + std::to_string(k) + " is not a unit vector");
+        if (w && !std::isfinite(w[k]))
+            return fail(VSHT_EINVAL, "non-finite weight at index " + std::to_string(k));
+    }
+    if (precision == VSHT_BF16X3) return fail(VSHT_EUNSUPPORTED, "bf16x3 not built yet");
+
+    int dev = 0;
+    if (opts && opts->device >= 0) {
+        dev = opts->device;
+    } else {
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    }
+    DeviceGuard guard(dev);
+    {
+        static std::once_flag attr_once;
+        static hipError_t attr_err = hipSuccess;
+        std::call_once(attr_once, [] { attr_err = set_kernel_attributes(); });
+        if (attr_err != hipSuccess) return hip_fail(attr_err, "hipFuncSetAttribute");
+    }
+
+    auto *h = new (std::nothrow) vsht_plan_s();
+    if (!h) return fail(VSHT_ENOMEM, "host allocation");
+    Plan &P = h->p;
+    P.L = L;
+    P.precision = precision;
+    P.device = dev;
+    P.n = n;
+    P.has_weights = w ? 1 : 0;
+    P.tri_size = tri_size(L);
+    const size_t rsz = precision == VSHT_FP64 ? 8 : 4;  // bytes per real
+
+    RingScan scan = scan_rings(n, xyz, w);
+    if (scan.ok && (int64_t)scan.rings.size() * 2 > n && n > 8) {
+        scan.ok = false;
+        scan.why = "too many rings";
+    }
+    if (scan.ok && L > kMaxLRings) {
+        scan.ok = false;
+        scan.why = "L too large for the ring kernels";
+    }
+    std::vector<double> tmp;
+    hipError_t e = hipSuccess;
+
+    // recurrence tables, binary64 (computed in extended precision)
+    std::vector<double> recA(P.tri_size, 0.0), recB(P.tri_size, 0.0);
+    for (int m = 0; m <= L; ++m) {
+        const int64_t t0 = tri_offset(L, m);
+        for (int l = m + 1; l <= L + 1; ++l) {
+            const long double ll = l, mm = m;
+            if (l == m + 1) {
+                recA[t0 + l - m] = (double)sqrtl(2.0L * mm + 3.0L);
+                recB[t0 + l - m] = 0.0;
+            } else {
+                recA[t0 + l - m] = (double)sqrtl((4.0L * ll * ll - 1.0L) / (ll * ll - mm * mm));
+                recB[t0 + l - m] = (double)sqrtl((2.0L * ll + 1.0L) * ((ll - 1.0L) * (ll - 1.0L) - mm * mm) /
+                                                 ((ll * ll - mm * mm) * (2.0L * ll - 3.0L)));
+            }
+        }
+    }
+    if ((e = upload(&P.d_recA, recA, &P.table_bytes)) != hipSuccess) goto hip_error;
+    if ((e = upload(&P.d_recB, recB, &P.table_bytes)) != hipSuccess) goto hip_error;
+
+    if (scan.ok) {
+        P.kind = VSHT_PLAN_RINGS;
+        std::vector<RingDesc> &rings = scan.rings;
+        // FFT descriptors per distinct length
+        std::map<int, int> fft_index;
+        std::vector<FftDesc> ffts;
+        std::vector<double> tw;
+        for (auto &r : rings) {
+            auto it = fft_index.find(r.nphi);
+            if (it == fft_index.end()) {
+                FftDesc fd{};
+                fd.n = r.nphi;
+                std::vector<int> f = factorize(r.nphi);
+                fd.nfac = (int)f.size();
+                for (size_t q = 0; q < f.size(); ++q) fd.fac[q] = f[q];
+                fd.tw_offset = (int64_t)(tw.size() / 2);
+                const long double two_pi = 6.283185307179586476925286766559005768L;
+                for (int k = 0; k < r.nphi; ++k) {
+                    const long double a = -two_pi * (long double)k / (long double)r.nphi;
+                    tw.push_back((double)cosl(a));
+                    tw.push_back((double)sinl(a));
+                }
+                it = fft_index.emplace(r.nphi, (int)ffts.size()).first;
+                ffts.push_back(fd);
+            }
+            r.fft = it->second;
+            if (r.nphi > P.max_nphi) P.max_nphi = r.nphi;
+        }
+        // pair rings with z_S == -z_N bitwise
+        std::unordered_map<uint64_t, std::vector<int>> byz;
+        auto key = [](double z) {
+            if (z == 0.0) z = 0.0;
+            uint64_t u;
+            std::memcpy(&u, &z, 8);
+            return u;
+        };
+        for (int r = 0; r < (int)rings.size(); ++r) byz[key(rings[r].z)].push_back(r);
+        std::vector<int> used(rings.size(), 0);
+        std::vector<PairDesc> pairs;
+        for (int r = 0; r < (int)rings.size(); ++r) {
+            if (used[r]) continue;
+            used[r] = 1;
+            PairDesc pd{r, -1};
+            if (rings[r].z != 0.0) {
+                auto it = byz.find(key(-rings[r].z));
+                if (it != byz.end())
+                    for (int c : it->second)
+                        if (!used[c]) {
+                            used[c] = 1;
+                            pd.rs = c;
+                            break;
+                        }
+            }
+            pairs.push_back(pd);
+        }
+        P.n_rings = (int64_t)rings.size();
+        P.n_pairs = (int64_t)pairs.size();
+        P.n_ffts = (int)ffts.size();
+        std::vector<double> pz(pairs.size()), ps(pairs.size());
+        for (size_t q = 0; q < pairs.size(); ++q) {
+            pz[q] = rings[pairs[q].rn].z;
+            ps[q] = rings[pairs[q].rn].s;
+        }
+        bool any_nonuniform = false;
+        for (auto &r : rings) any_nonuniform |= !r.uniform_w;
+        if ((e = upload(&P.d_rings, rings, &P.table_bytes)) != hipSuccess) goto hip_error;
+        if ((e = upload(&P.d_pairs, pairs, &P.table_bytes)) != hipSuccess) goto hip_error;
+        if ((e = upload(&P.d_ffts, ffts, &P.table_bytes)) != hipSuccess) goto hip_error;
+        if ((e = upload(&P.d_tw, tw, &P.table_bytes)) != hipSuccess) goto hip_error;
+        if ((e = upload(&P.d_pair_z, pz, &P.table_bytes)) != hipSuccess) goto hip_error;
+        if (w && any_nonuniform) {
+            std::vector<double> wv(w, w + n);
+            if ((e = upload(&P.d_weights, wv, &P.table_bytes)) != hipSuccess) goto hip_error;
+        }
+        // seeds Lambda_{m,m}(z_p) on the device, binary64
+        {
+            double *d_ps = nullptr;
+            size_t dummy = 0;
+            if ((e = upload(&d_ps, ps, &dummy)) != hipSuccess) goto hip_error;
+            e = hipMalloc((void **)&P.d_seeds, sizeof(double) * (size_t)(L + 1) * P.n_pairs);
+            if (e == hipSuccess) {
+                P.table_bytes += sizeof(double) * (size_t)(L + 1) * P.n_pairs;
+                e = launch_seed_kernel(d_ps, (int)P.n_pairs, L, P.d_seeds, nullptr);
+            }
+            if (e == hipSuccess) e = hipDeviceSynchronize();
+            (void)hipFree(d_ps);
+            if (e != hipSuccess) goto hip_error;
+        }
+        // workspace
+        {
+            const size_t pb = (size_t)(L + 1) * P.n_pairs * 8 * 2 * rsz;
+            const size_t fg = (size_t)P.tri_size * 4 * 2 * rsz;
+            const size_t stb = (size_t)(L + 1) * P.n_pairs * 2 * sizeof(double);
+            if ((e = hipMalloc(&P.d_pb, pb)) != hipSuccess) goto hip_error;
+            if ((e = hipMalloc(&P.d_fg, fg)) != hipSuccess) goto hip_error;
+            if ((e = hipMalloc(&P.d_state, stb)) != hipSuccess) goto hip_error;
+            P.workspace_bytes = pb + fg + stb;
+        }
+    } else {
+        P.kind = VSHT_PLAN_SCATTERED;
+        std::vector<double> xv(xyz, xyz + 3 * n);
+        if ((e = upload(&P.d_xyz, xv, &P.table_bytes)) != hipSuccess) goto hip_error;
+        const size_t fg = (size_t)P.tri_size * 4 * 2 * rsz;
+        if ((e = hipMalloc(&P.d_fg, fg)) != hipSuccess) goto hip_error;
+        P.workspace_bytes = fg;
+    }
+    *out = h;
+    return VSHT_OK;
+
+hip_error:
+    free_plan_memory(&P);
+    delete h;
+    return hip_fail(e, "plan setup");
+}
+
+static vsht_status check_call(vsht_plan_t plan, const void *x, const void *y, const void *z) {
+    g_last_error.clear();
+    if (!plan) return fail(VSHT_EINVAL, "plan is NULL");
+    if (!x || !y || !z) return fail(VSHT_EINVAL, "NULL buffer");
+    return VSHT_OK;
+}
+
+vsht_status vsht_forward(vsht_plan_t plan, const void *T, void *a, void *b, void *stream) {
+    vsht_status s = check_call(plan, T, a, b);
+    if (s != VSHT_OK) return s;
+    const Plan &P = plan->p;
+    if (!P.has_weights) return fail(VSHT_ENOWEIGHTS, "forward needs a plan created with weights");
+    if (P.kind != VSHT_PLAN_RINGS)
+        return fail(VSHT_EUNSUPPORTED, "forward transform on a scattered point set");
+    DeviceGuard guard(P.device);
+    hipError_t e = launch_forward(P, T, a, b, true, (hipStream_t)stream);
+    return e == hipSuccess ? VSHT_OK : hip_fail(e, "forward launch");
+}
+
+vsht_status vsht_forward_unweighted(vsht_plan_t plan, const void *T, void *a, void *b,
+                                    void *stream) {
+    vsht_status s = check_call(plan, T, a, b);
+    if (s != VSHT_OK) return s;
+    const Plan &P = plan->p;
+    if (P.kind != VSHT_PLAN_RINGS)
+        return fail(VSHT_EUNSUPPORTED, "forward transform on a scattered point set");
+    DeviceGuard guard(P.device);
+    hipError_t e = launch_forward(P, T, a, b, false, (hipStream_t)stream);
+    return e == hipSuccess ? VSHT_OK : hip_fail(e, "forward launch");
+}
+
+vsht_status vsht_adjoint(vsht_plan_t plan, const void *a, const void *b, void *T, void *stream) {
+    vsht_status s = check_call(plan, a, b, T);
+    if (s != VSHT_OK) return s;
+    const Plan &P = plan->p;
+    DeviceGuard guard(P.device);
+    hipError_t e = launch_adjoint(P, a, b, T, (hipStream_t)stream);
+    return e == hipSuccess ? VSHT_OK : hip_fail(e, "adjoint launch");
+}
+
+vsht_status vsht_plan_info(vsht_plan_t plan, vsht_plan_info_t *info) {
+    g_last_error.clear();
+    if (!plan || !info) return fail(VSHT_EINVAL, "NULL argument");
+    const Plan &P = plan->p;
+    info->L = P.L;
+    info->precision = P.precision;
+    info->kind = P.kind;
+    info->n_points = P.n;
+    info->n_rings = P.n_rings;
+    info->n_pairs = P.n_pairs;
+    info->max_nphi = P.max_nphi;
+    info->has_weights = P.has_weights;
+    info->workspace_bytes = P.workspace_bytes;
+    info->table_bytes = P.table_bytes;
+    return VSHT_OK;
+}
+
+vsht_status vsht_plan_destroy(vsht_plan_t plan) {
+    g_last_error.clear();
+    if (!plan) return VSHT_OK;
+    {
+        DeviceGuard guard(plan->p.device);
+        (void)hipDeviceSynchronize();
+        free_plan_memory(&plan->p);
+    }
+    delete plan;
+    return VSHT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// vsht_internal.h -- plan structure and kernel launch interface shared by the
+// host code (vsht_plan.cpp, vsht_api.cpp) and the gfx950 kernels (*.hip).
+//
+// Formulation used by every kernel:
+// with Lambda_{l,m}(z) the 4pi-normalised associated Legendre function
+// (Condon-Shortley phase; Lambda_{l,-m} = (-1)^m Lambda_{l,m}) and
+// e_{l,m} = sqrt((l^2-m^2)/(4l^2-1)), the polar derivative obeys
+//     s dLambda_{l,m}/dtheta = l e_{l+1,m} Lambda_{l+1,m} - (l+1) e_{l,m} Lambda_{l-1,m}.
+// Writing the tangent field in the (e_theta, e_phi) frame, Y^div = grad* Y /
+// sqrt(l(l+1)) and Y^curl = x cross Y^div (the Clebsch-Gordan vectors of
+// Definition 3.1 reduce to these), the forward transform becomes two scalar
+// spin-frame transforms of degree L+1,
+//     F^{theta,phi}_{l',m} = sum_k (w_k / s_k) Lambda_{l',m}(z_k) e^{-i m phi_k} T^{theta,phi}_k,
+// followed by a three-term recombination in l', and the adjoint is the
+// transpose: three-term "prep" in l', then scalar syntheses divided by s.
+// Both Legendre stages therefore contract against Lambda only, one real
+// value per (m, l', ring pair), with four complex columns (theta/phi x +-m).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/vsht.h"
+
+namespace vsht {
+
+// Per ring (iso-latitude circle of equispaced points).
+struct RingDesc {
+    double z;        // cos(theta), identical for every point of the ring
+    double s;        // sin(theta) = sqrt((1-z)(1+z)) > 0
+    double w;        // common weight of the ring's points (if uniform_w)
+    double c0, s0;   // cos(phi_0), sin(phi_0)
+    double phi0;     // first longitude
+    int64_t offset;  // index of the first point
+    int32_t nphi;    // points on the ring
+    int32_t fft;     // index of the FFT descriptor for nphi
+    int32_t uniform_w;
+    int32_t pad;
+};
+
+// North/south pair of rings with z_S == -z_N bitwise; rs < 0 for an unpaired ring.
+struct PairDesc {
+    int32_t rn, rs;
+};
+
+// Mixed-radix Stockham descriptor for one DFT length.
+constexpr int kMaxFactors = 24;
+struct FftDesc {
+    int32_t n;
+    int32_t nfac;
+    int64_t tw_offset;  // offset (in complex entries) of e^{-2 pi i k / n}, k < n
+    int32_t fac[kMaxFactors];
+};
+
+// Workspace layout (all in the plan's real type):
+//  PB   pair buffer  [(L+1)][NP][2][4] complex.
+//       forward: slot 0 = S = G_N + G_S, slot 1 = D = G_N - G_S
+//       adjoint: slot 0 = sum over even l'+m, slot 1 = sum over odd l'+m
+//       4 complex = (theta,+m) (phi,+m) (theta,-m) (phi,-m)
+//  FG   triangle buffer [tri(L)][4] complex, tri index (m, l') for
+//       0 <= m <= L, m <= l' <= L+1: forward F, adjoint prep g.
+struct Plan {
+    int L = 0;
+    int precision = VSHT_FP64;
+    int device = 0;
+    int kind = VSHT_PLAN_RINGS;
+    int has_weights = 0;
+    int64_t n = 0;
+    int64_t n_rings = 0, n_pairs = 0;
+    int64_t max_nphi = 0;
+    int64_t tri_size = 0;
+
+    // device tables
+    RingDesc *d_rings = nullptr;
+    PairDesc *d_pairs = nullptr;
+    FftDesc *d_ffts = nullptr;
+    double *d_tw = nullptr;        // twiddles, complex as (re, im)
+    double *d_pair_z = nullptr;    // z of each pair's northern ring
+    double *d_recA = nullptr;      // recurrence Lambda_l = A z Lambda_{l-1} - B Lambda_{l-2}
+    double *d_recB = nullptr;
+    double *d_seeds = nullptr;     // Lambda_{m,m}(z_p), [(L+1)][NP]
+    double *d_weights = nullptr;   // per-point weights (rings with non-uniform weights)
+    double *d_xyz = nullptr;       // points (scattered plans)
+    size_t table_bytes = 0;
+
+    // workspace
+    void *d_pb = nullptr;
+    void *d_fg = nullptr;
+    void *d_state = nullptr;       // Legendre recurrence state
+    size_t workspace_bytes = 0;
+    int n_ffts = 0;
+};
+
+__host__ __device__ inline int64_t tri_offset(int L, int m) {
+    // sum_{m' < m} (L + 2 - m')
+    return (int64_t)m * (L + 2) - (int64_t)m * (m - 1) / 2;
+}
+__host__ __device__ inline int64_t tri_size(int L) { return tri_offset(L, L + 1); }
+
+// Kernel launchers (vsht_kernels.hip).  Each returns the hipError_t of the launch.
+hipError_t launch_forward(const Plan &p, const void *T, void *a, void *b, bool weighted,
+                          hipStream_t st);
+hipError_t launch_adjoint(const Plan &p, const void *a, const void *b, void *T, hipStream_t st);
+
+}  // namespace vsht

@@ -1,0 +1,92 @@
+"""CPU checks of the C interface: the library loads, exports every function
+include/vsht.h declares, and rejects invalid arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1908_00041_amd as v
+from paper_1908_00041_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "vsht.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vsht_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    lib = v.load_library()
+    names = declared_functions()
+    assert names, "no declarations parsed"
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(B.EXPORTED) == names
+
+
+def test_num_coeffs():
+    for L, K in [(0, 0), (-3, 0), (1, 3), (16, 288), (1024, 1050624)]:
+        assert v.vsht_num_coeffs(L) == K
+
+
+def _plan(L, xyz, w=None, opts=None):
+    lib = v.load_library()
+    h = ctypes.c_void_p()
+    xyz = None if xyz is None else np.ascontiguousarray(xyz, np.float64)
+    w = None if w is None else np.ascontiguousarray(w, np.float64)
+    n = 0 if xyz is None else len(xyz)
+    st = lib.vsht_plan(L, n if xyz is not None else 5,
+                       None if xyz is None else xyz.ctypes.data_as(ctypes.c_void_p),
+                       None if w is None else w.ctypes.data_as(ctypes.c_void_p),
+                       opts, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("case", ["L0", "n0", "null_xyz", "non_unit", "nan", "one_point_weights",
+                                  "bad_precision"])
+def test_plan_rejects_invalid(case):
+    lib = v.load_library()
+    xyz = np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    w = np.ones(3)
+    opts = None
+    if case == "L0":
+        st, h = _plan(0, xyz, w)
+    elif case == "n0":
+        h = ctypes.c_void_p()
+        st = lib.vsht_plan(4, 0, xyz.ctypes.data_as(ctypes.c_void_p), None, None, ctypes.byref(h))
+    elif case == "null_xyz":
+        st, h = _plan(4, None)
+    elif case == "non_unit":
+        st, h = _plan(4, xyz * 1.001, w)
+    elif case == "nan":
+        bad = xyz.copy()
+        bad[1, 2] = np.nan
+        st, h = _plan(4, bad, w)
+    elif case == "one_point_weights":
+        st, h = _plan(4, xyz[:1], w[:1])
+    else:
+        st, h = _plan(4, xyz, w, ctypes.byref(B.vsht_opts(7, -1)))
+    assert st == B.VSHT_EINVAL
+    assert not h.value
+    assert len(lib.vsht_last_error()) > 0
+
+
+def test_null_arguments():
+    lib = v.load_library()
+    assert lib.vsht_forward(None, None, None, None, None) == B.VSHT_EINVAL
+    assert lib.vsht_adjoint(None, None, None, None, None) == B.VSHT_EINVAL
+    assert lib.vsht_forward_unweighted(None, None, None, None, None) == B.VSHT_EINVAL
+    assert lib.vsht_plan_info(None, None) == B.VSHT_EINVAL
+    assert lib.vsht_plan_destroy(None) == B.VSHT_OK
+    h = ctypes.c_void_p()
+    assert lib.vsht_plan(4, 3, None, None, None, None) == B.VSHT_EINVAL
+
+
+def test_status_strings():
+    lib = v.load_library()
+    for s in range(6):
+        assert lib.vsht_status_string(s).decode().startswith("VSHT_")
