@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark: forward + adjoint VSHT at L = 1024 on one MI355X.
+
+Workload (one "step"): the adjoint transform of seeded random coefficients
+(a, b) (re, im iid N(0,1), scaled by 1/l) onto the Gauss-Legendre grid of
+1025 x 2050 = 2,101,250 points, then the forward transform of that field back
+to coefficients.  Inputs are resident in HBM before the timed region.
+
+Printed: ONE JSON line with the headline FP64 number (`value`, fwd+adj
+transforms/s), the roofline record of the dominant kernel (HIP-event
+durations measured here), the error against the CPU oracle on sampled outputs,
+the oracle itself timed on the host (`cpu_baseline`), and the same
+measurements for the lower-precision variants under `variants`.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--L 1024]
+                    [--oracle-coeffs C] [--oracle-points P] [--no-oracle]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+FP32_VALU_TFLOPS = 78.6   # non-packed binary32 VALU (packed FP32 disabled at build)
+FP32_MFMA_TFLOPS = 157.3
+BF16_MFMA_TFLOPS = 2516.6
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def folded_elements(L, n_pairs):
+    """(m >= 0, m <= l' <= L+1, ring pair) elements of one Legendre stage."""
+    return n_pairs * ((L + 2) * (L + 3) // 2 - 1)
+
+
+def time_steps(torch, plan, a, b, steps, warmup):
+    for _ in range(warmup):
+        T = plan.adjoint(a, b)
+        plan.forward(T)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        T = plan.adjoint(a, b)
+        a2, b2 = plan.forward(T)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, T, a2, b2
+
+
+def stage_profile(torch, plan, a, b, reps):
+    plan.set_stage_timing(True)
+    plan.stage_times()
+    for _ in range(reps):
+        T = plan.adjoint(a, b)
+        plan.forward(T)
+    torch.cuda.synchronize()
+    st = plan.stage_times()
+    plan.set_stage_timing(False)
+    return {k: (ms / c if c else 0.0) for k, (ms, c) in st.items() if c}
+
+
+def rel_l2(x, y):
+    x = np.asarray(x).ravel()
+    y = np.asarray(y).ravel()
+    return float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--L", type=int, default=1024)
+    ap.add_argument("--oracle-coeffs", type=int, default=1024)
+    ap.add_argument("--oracle-points", type=int, default=512)
+    ap.add_argument("--no-oracle", action="store_true")
+    ap.add_argument("--precisions", default="fp64,fp32")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the transform would shard by ring pairs and by order m with one all-to-all; "
+              "see the design notes).  Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1908_00041_amd as vsht
+    import vsht_inputs as vi
+
+    L = args.L
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log("grid L=%d" % L)
+    xyz, w = vi.gl_grid(L)
+    N = len(w)
+    a_np, b_np = vi.random_coeffs(L, 0, scale="inv_l")
+    K = L * (L + 2)
+
+    # oracle samples (shared by all precisions)
+    pidx = vi.sample_indices(N, args.oracle_points, 3)
+    cidx = vi.sample_indices(K, args.oracle_coeffs, 4)
+    Tr_np = vi.random_field(N, 5)
+
+    results = {}
+    for prec in args.precisions.split(","):
+        log("precision", prec)
+        t_plan = time.perf_counter()
+        plan = vsht.Plan(L, xyz, w, precision=prec)
+        t_plan = time.perf_counter() - t_plan
+        info = plan.info()
+        cdt = plan.dtype
+        a = torch.from_numpy(a_np).to(dev, cdt)
+        b = torch.from_numpy(b_np).to(dev, cdt)
+        sec, T, a2, b2 = time_steps(torch, plan, a, b, args.steps, args.warmup)
+        log("%s: %.3f ms/step" % (prec, sec * 1e3))
+        stages = stage_profile(torch, plan, a, b, max(3, min(args.steps, 10)))
+        log("%s stages (ms): %s" % (prec, {k: round(v, 4) for k, v in stages.items()}))
+        # errors: round trip (full size), adjoint at sampled points, forward at sampled coeffs
+        rt = rel_l2(np.concatenate([a2.cpu().numpy(), b2.cpu().numpy()]),
+                    np.concatenate([a_np, b_np]))
+        Tg = T.cpu().numpy().astype(np.complex128)
+        ga, gb = plan.forward(torch.from_numpy(Tr_np).to(dev, cdt))
+        torch.cuda.synchronize()
+        results[prec] = dict(sec=sec, stages=stages, roundtrip=rt, T_sample=Tg[pidx],
+                             fa=ga.cpu().numpy()[cidx].astype(np.complex128),
+                             fb=gb.cpu().numpy()[cidx].astype(np.complex128),
+                             plan_s=t_plan, info=info)
+        del T, a2, b2, ga, gb
+        plan.close()
+
+    cpu = None
+    if not args.no_oracle:
+        import oracle
+        oracle.build(force=False)
+        log("oracle: %d coefficients + %d points" % (len(cidx), len(pidx)))
+        t0 = time.perf_counter()
+        oa, ob = oracle.forward_subset(L, xyz, w, Tr_np, cidx)
+        t_fwd = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oT = oracle.adjoint(L, a_np, b_np, xyz[pidx])
+        t_adj = time.perf_counter() - t0
+        # scale each sample to the full transform: forward is linear in the number of
+        # coefficients, the adjoint in the number of points
+        t_full = t_fwd * K / len(cidx) + t_adj * N / len(pidx)
+        cpu = {"value": 1.0 / t_full, "unit": "transforms/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": ("CPU FP64 direct-sum oracle on the same L=%d GL workload: forward for "
+                          "%d sampled coefficients (all %d points, %.2f s) and adjoint at %d "
+                          "sampled points (all %d coefficients, %.2f s), each scaled linearly "
+                          "to the full transform" % (L, len(cidx), N, t_fwd, len(pidx), 2 * K,
+                                                     t_adj))}
+        log("oracle sample %.2f s + %.2f s -> %.3g transforms/s" % (t_fwd, t_adj, cpu["value"]))
+        for prec, r in results.items():
+            r["err_adj"] = rel_l2(r["T_sample"], oT)
+            r["err_fwd"] = rel_l2(np.concatenate([r["fa"], r["fb"]]), np.concatenate([oa, ob]))
+
+    def roofline(prec, r):
+        st = r["stages"]
+        dom = max(("leg_fwd", "leg_adj"), key=lambda k: st.get(k, 0.0))
+        t = st[dom] * 1e-3
+        E = folded_elements(L, r["info"]["n_pairs"])
+        flops = 16.0 * E
+        peak = FP64_VALU_TFLOPS if prec == "fp64" else FP32_VALU_TFLOPS
+        ach = flops / t / 1e12
+        return {"bound": "alu", "kernel": "k_leg_adj" if dom == "leg_adj" else "k_leg_fwd",
+                "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(ach / peak, 4), "traffic": None,
+                "launch_us": round(st[dom] * 1e3, 2), "flops_per_launch": flops}
+
+    main_r = results.get("fp64") or next(iter(results.values()))
+    main_prec = "fp64" if "fp64" in results else next(iter(results))
+    ms = main_r["sec"] * 1e3
+    out = {
+        "metric": "VSHT fwd+adj transforms/s at L=1024 + % HBM/MFMA roofline, at stated error vs FP64",
+        "value": round(1.0 / main_r["sec"], 2),
+        "unit": "transforms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_prec == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "forward+adjoint VSHT, Gauss-Legendre grid %dx%d (%d points), "
+                               "L=%d, random coefficients scaled 1/l, seed 0" % (L + 1, 2 * L + 2, N, L),
+                   "L": L, "points": N, "coefficients": 2 * K, "precision": main_prec},
+        "roofline": roofline(main_prec, main_r),
+        "stages_us": {k: round(v * 1e3, 2) for k, v in main_r["stages"].items()},
+        "errors": {"roundtrip_rel_l2": main_r["roundtrip"]},
+        "cpu_baseline": cpu,
+    }
+    if "err_adj" in main_r:
+        out["errors"].update(adjoint_vs_oracle_rel_l2=main_r["err_adj"],
+                             forward_vs_oracle_rel_l2=main_r["err_fwd"],
+                             oracle_sample={"coefficients": int(len(cidx)), "points": int(len(pidx))})
+    variants = {}
+    for prec, r in results.items():
+        if prec == main_prec:
+            continue
+        v = {"value": round(1.0 / r["sec"], 2), "ms_per_step": round(r["sec"] * 1e3, 4),
+             "roofline": roofline(prec, r),
+             "stages_us": {k: round(x * 1e3, 2) for k, x in r["stages"].items()},
+             "errors": {"roundtrip_rel_l2": r["roundtrip"]}}
+        if "err_adj" in r:
+            v["errors"].update(adjoint_vs_oracle_rel_l2=r["err_adj"],
+                               forward_vs_oracle_rel_l2=r["err_fwd"])
+        variants[prec] = v
+    if variants:
+        out["variants"] = variants
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -129,6 +129,27 @@ vsht_status vsht_adjoint(vsht_plan_t plan, const void *a, const void *b, void *T
 /* Describe a plan (host-side; no device work). */
 vsht_status vsht_plan_info(vsht_plan_t plan, vsht_plan_info_t *info);
 
+/* Stages of the pipeline, for vsht_get_stage_times. */
+typedef enum {
+    VSHT_STAGE_RING_FWD = 0,   /* Cartesian -> (theta, phi), longitude DFT, N/S fold */
+    VSHT_STAGE_LEG_FWD = 1,    /* Legendre analysis (contraction over ring pairs) */
+    VSHT_STAGE_RECOMBINE = 2,  /* three-term recombination -> a, b */
+    VSHT_STAGE_PREP = 3,       /* a, b -> spin-frame scalar coefficients */
+    VSHT_STAGE_LEG_ADJ = 4,    /* Legendre synthesis */
+    VSHT_STAGE_RING_ADJ = 5,   /* N/S unfold, inverse longitude DFT, -> Cartesian */
+    VSHT_STAGE_SCATTERED = 6,  /* adjoint evaluation at scattered points */
+    VSHT_NUM_STAGES = 7
+} vsht_stage;
+
+/* Profiling aid.  With enable != 0 every later call records a pair of HIP
+ * events around each kernel on the caller's stream (a small overhead);
+ * vsht_get_stage_times waits for those events and returns, per stage, the
+ * summed duration in milliseconds (ms[s]) and the number of launches
+ * (count[s]) since the previous read, then clears them.  nstages entries are
+ * written (at most VSHT_NUM_STAGES).  Disabling drops pending records. */
+vsht_status vsht_set_stage_timing(vsht_plan_t plan, int enable);
+vsht_status vsht_get_stage_times(vsht_plan_t plan, double *ms, int64_t *count, int nstages);
+
 /* Release a plan and everything it owns (waits for the device first).
  * Passing NULL is allowed and returns VSHT_OK. */
 vsht_status vsht_plan_destroy(vsht_plan_t plan);

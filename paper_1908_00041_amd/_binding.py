@@ -20,7 +20,8 @@ PLAN_RINGS, PLAN_SCATTERED = 0, 1
 # every symbol include/vsht.h declares
 EXPORTED = ("vsht_num_coeffs", "vsht_plan", "vsht_forward", "vsht_forward_unweighted",
             "vsht_adjoint", "vsht_plan_info", "vsht_plan_destroy", "vsht_status_string",
-            "vsht_last_error")
+            "vsht_last_error", "vsht_set_stage_timing", "vsht_get_stage_times")
+STAGES = ("ring_fwd", "leg_fwd", "recombine", "prep", "leg_adj", "ring_adj", "scattered")
 
 
 class vsht_opts(ctypes.Structure):
@@ -71,6 +72,11 @@ def load_library(path=LIB_PATH):
     lib.vsht_status_string.restype = ctypes.c_char_p
     lib.vsht_last_error.argtypes = []
     lib.vsht_last_error.restype = ctypes.c_char_p
+    lib.vsht_set_stage_timing.argtypes = [vp, ci]
+    lib.vsht_set_stage_timing.restype = ci
+    lib.vsht_get_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int64), ci]
+    lib.vsht_get_stage_times.restype = ci
     _lib = lib
     return lib
 
@@ -199,6 +205,18 @@ class Plan:
         _raise_for(vsht_adjoint(self._h, a.data_ptr(), b.data_ptr(), T.data_ptr(), self._stream()),
                    "vsht_adjoint")
         return T
+
+    def set_stage_timing(self, enable):
+        _raise_for(load_library().vsht_set_stage_timing(self._h, 1 if enable else 0),
+                   "vsht_set_stage_timing")
+
+    def stage_times(self):
+        """{stage: (total_ms, launches)} recorded since the previous read."""
+        n = len(STAGES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _raise_for(load_library().vsht_get_stage_times(self._h, ms, cnt, n), "vsht_get_stage_times")
+        return {STAGES[i]: (ms[i], cnt[i]) for i in range(n)}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -64,8 +64,8 @@ hipError_t upload(T **dst, const std::vector<T> &src, size_t *bytes) {
 }
 
 void free_plan_memory(Plan *p) {
-    void *ptrs[] = {p->d_rings, p->d_pairs, p->d_ffts, p->d_tw,  p->d_pair_z, p->d_recA,
-                    p->d_recB,  p->d_seeds, p->d_weights, p->d_xyz, p->d_pb,  p->d_fg,
+    void *ptrs[] = {p->d_rings, p->d_pairs, p->d_ffts, p->d_tw,  p->d_pair_z, p->d_aprime,
+                    p->d_cscale,  p->d_seeds, p->d_weights, p->d_xyz, p->d_pb,  p->d_fg,
                     p->d_state};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -225,24 +225,36 @@ vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w, cons
     std::vector<double> tmp;
     hipError_t e = hipSuccess;
 
-    // recurrence tables, binary64 (computed in extended precision)
-    std::vector<double> recA(P.tri_size, 0.0), recB(P.tri_size, 0.0);
+    // scaled recurrence tables, binary64 (computed in extended precision):
+    // Lambda_{l,m} = c_{l,m} Q_{l,m},  Q_l = a'_l z Q_{l-1} - Q_{l-2},
+    // c_m = c_{m+1} = 1, c_l = (alpha_l / alpha_{l-1}) c_{l-2}, a'_l = alpha_l c_{l-1} / c_l,
+    // alpha_l = sqrt((4 l^2 - 1) / (l^2 - m^2)); a'_{m+1} = sqrt(2m+3); a'_m is unused (0).
+    std::vector<double> aprime(P.tri_size, 0.0), cscale(P.tri_size, 1.0);
     for (int m = 0; m <= L; ++m) {
         const int64_t t0 = tri_offset(L, m);
-        for (int l = m + 1; l <= L + 1; ++l) {
-            const long double ll = l, mm = m;
-            if (l == m + 1) {
-                recA[t0 + l - m] = (double)sqrtl(2.0L * mm + 3.0L);
-                recB[t0 + l - m] = 0.0;
-            } else {
-                recA[t0 + l - m] = (double)sqrtl((4.0L * ll * ll - 1.0L) / (ll * ll - mm * mm));
-                recB[t0 + l - m] = (double)sqrtl((2.0L * ll + 1.0L) * ((ll - 1.0L) * (ll - 1.0L) - mm * mm) /
-                                                 ((ll * ll - mm * mm) * (2.0L * ll - 3.0L)));
-            }
+        const long double mm = m;
+        auto alpha = [&](int l) {
+            const long double ll = l;
+            return sqrtl((4.0L * ll * ll - 1.0L) / (ll * ll - mm * mm));
+        };
+        long double cprev2 = 1.0L, cprev1 = 1.0L;  // c_{l-2}, c_{l-1}
+        aprime[t0] = 0.0;
+        cscale[t0] = 1.0;
+        if (m + 1 <= L + 1) {
+            aprime[t0 + 1] = (double)sqrtl(2.0L * mm + 3.0L);
+            cscale[t0 + 1] = 1.0;
+        }
+        for (int l = m + 2; l <= L + 1; ++l) {
+            const long double al = alpha(l), alm1 = alpha(l - 1);
+            const long double cl = (al / alm1) * cprev2;
+            aprime[t0 + l - m] = (double)(al * cprev1 / cl);
+            cscale[t0 + l - m] = (double)cl;
+            cprev2 = cprev1;
+            cprev1 = cl;
         }
     }
-    if ((e = upload(&P.d_recA, recA, &P.table_bytes)) != hipSuccess) goto hip_error;
-    if ((e = upload(&P.d_recB, recB, &P.table_bytes)) != hipSuccess) goto hip_error;
+    if ((e = upload(&P.d_aprime, aprime, &P.table_bytes)) != hipSuccess) goto hip_error;
+    if ((e = upload(&P.d_cscale, cscale, &P.table_bytes)) != hipSuccess) goto hip_error;
 
     if (scan.ok) {
         P.kind = VSHT_PLAN_RINGS;
@@ -416,12 +428,58 @@ vsht_status vsht_plan_info(vsht_plan_t plan, vsht_plan_info_t *info) {
     return VSHT_OK;
 }
 
+static void drop_records(Plan &P) {
+    for (auto &r : P.records) {
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    P.records.clear();
+}
+
+vsht_status vsht_set_stage_timing(vsht_plan_t plan, int enable) {
+    g_last_error.clear();
+    if (!plan) return fail(VSHT_EINVAL, "plan is NULL");
+    DeviceGuard guard(plan->p.device);
+    if (!enable) {
+        (void)hipDeviceSynchronize();
+        drop_records(plan->p);
+    }
+    plan->p.timing = enable ? 1 : 0;
+    return VSHT_OK;
+}
+
+vsht_status vsht_get_stage_times(vsht_plan_t plan, double *ms, int64_t *count, int nstages) {
+    g_last_error.clear();
+    if (!plan || !ms || !count || nstages < 0) return fail(VSHT_EINVAL, "NULL argument");
+    if (nstages > VSHT_NUM_STAGES) nstages = VSHT_NUM_STAGES;
+    for (int s = 0; s < nstages; ++s) {
+        ms[s] = 0.0;
+        count[s] = 0;
+    }
+    Plan &P = plan->p;
+    DeviceGuard guard(P.device);
+    hipError_t err = hipSuccess;
+    for (auto &r : P.records) {
+        hipError_t e = hipEventSynchronize(r.stop);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, r.start, r.stop);
+        if (e != hipSuccess) err = e;
+        else if (r.stage < nstages) {
+            ms[r.stage] += t;
+            count[r.stage] += 1;
+        }
+    }
+    drop_records(P);
+    return err == hipSuccess ? VSHT_OK : hip_fail(err, "stage timing");
+}
+
 vsht_status vsht_plan_destroy(vsht_plan_t plan) {
     g_last_error.clear();
     if (!plan) return VSHT_OK;
     {
         DeviceGuard guard(plan->p.device);
         (void)hipDeviceSynchronize();
+        drop_records(plan->p);
         free_plan_memory(&plan->p);
     }
     delete plan;

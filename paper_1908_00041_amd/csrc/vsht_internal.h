@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/vsht.h"
 
 namespace vsht {
@@ -76,8 +78,8 @@ struct Plan {
     FftDesc *d_ffts = nullptr;
     double *d_tw = nullptr;        // twiddles, complex as (re, im)
     double *d_pair_z = nullptr;    // z of each pair's northern ring
-    double *d_recA = nullptr;      // recurrence Lambda_l = A z Lambda_{l-1} - B Lambda_{l-2}
-    double *d_recB = nullptr;
+    double *d_aprime = nullptr;    // scaled recurrence Q_l = a'_l z Q_{l-1} - Q_{l-2}, [tri]
+    double *d_cscale = nullptr;    // Lambda_{l,m} = c_{l,m} Q_{l,m}, [tri]
     double *d_seeds = nullptr;     // Lambda_{m,m}(z_p), [(L+1)][NP]
     double *d_weights = nullptr;   // per-point weights (rings with non-uniform weights)
     double *d_xyz = nullptr;       // points (scattered plans)
@@ -89,6 +91,40 @@ struct Plan {
     void *d_state = nullptr;       // Legendre recurrence state
     size_t workspace_bytes = 0;
     int n_ffts = 0;
+
+    // optional per-stage event timing
+    struct StageRecord {
+        int stage;
+        hipEvent_t start, stop;
+    };
+    int timing = 0;
+    mutable std::vector<StageRecord> records;
+};
+
+// Record events around a kernel launch when the plan's timing is enabled.
+struct StageScope {
+    const Plan &p;
+    hipStream_t st;
+    Plan::StageRecord rec{};
+    bool on;
+    StageScope(const Plan &plan, int stage, hipStream_t stream) : p(plan), st(stream) {
+        on = plan.timing != 0;
+        if (on) {
+            rec.stage = stage;
+            on = hipEventCreate(&rec.start) == hipSuccess;
+            if (on && hipEventCreate(&rec.stop) != hipSuccess) {
+                (void)hipEventDestroy(rec.start);
+                on = false;
+            }
+            if (on) (void)hipEventRecord(rec.start, st);
+        }
+    }
+    ~StageScope() {
+        if (on) {
+            (void)hipEventRecord(rec.stop, st);
+            p.records.push_back(rec);
+        }
+    }
 };
 
 __host__ __device__ inline int64_t tri_offset(int L, int m) {

@@ -39,6 +39,14 @@ __device__ __forceinline__ C2<real> cmul(C2<real> a, C2<real> b) {
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Value of a binary64 register in lane `lane` (wave-uniform result).
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // ---------------------------------------------------------------------------
 // Seeds Lambda_{m,m}(z_p) = (-1)^m sqrt((2m+1)/(4pi) prod_{k<=m} (2k-1)/(2k)) s^m,
 // built as a running product whose binary exponent is carried separately, so
@@ -298,33 +306,235 @@ __global__ __launch_bounds__(kRingNT) void k_ring_adj(RingArgs<real> A) {
 }
 
 // ---------------------------------------------------------------------------
-// Forward Legendre contraction: FG[tri(m, l')][c] = sum_p Lambda_{l',m}(z_p) PB[m][p][(l'+m)&1][c].
-// Workgroup = 3 waves for one m.  Per chunk of 128 degrees and tile of 64
-// pairs: wave 0 (lane = pair) advances the recurrence 128 steps and stores
-// Lambda into LDS split by parity; waves 1, 2 (lane = degree of one parity)
-// accumulate over the tile's pairs with the pair data in scalar registers.
+// Scaled Legendre recurrence.  With Lambda_{l,m} = c_{l,m} Q_{l,m} and
+// c_{m,m} = c_{m+1,m} = 1, c_{l,m} = (alpha_l / alpha_{l-1}) c_{l-2,m}, the
+// three-term recurrence becomes
+//     Q_l = a'_l z Q_{l-1} - Q_{l-2},   a'_l = alpha_l c_{l-1} / c_l,
+// two binary64 operations per step.  Starting from the state
+// (Q_{m-1}, Q_{m-2}) = (0, -Lambda_{m,m}) the first step yields Q_m itself.
+// c_{l,m} stays in [0.24, 1.13] for L <= 1024, so nothing is lost; it is
+// applied to the outputs (analysis) or folded into the coefficients (synthesis).
+// ---------------------------------------------------------------------------
+
+// ---------------------------------------------------------------------------
+// Forward Legendre contraction on MFMA:
+//   FG[tri(m, l')][c] = c_{l'} sum_p Q_{l',m}(z_p) PB[m][p][(l'+m)&1][c].
+// Workgroup = 5 waves for one order m.  Wave 4 (the producer, lane = ring
+// pair) advances the recurrence 64 degrees for 64 pairs and stores Q into a
+// double-buffered LDS tile, and copies the tile's 64 x 16 pair data next to
+// it.  Waves 0..3 (consumers) each own 16 consecutive degrees and multiply
+// Q[16 x 4 pairs] by PB[4 pairs x 16 columns] with v_mfma_f64_16x16x4; the 16
+// columns are 8 of the even-parity sum S and 8 of the odd-parity difference D,
+// and each output row keeps the half that matches its parity.
+// ---------------------------------------------------------------------------
+constexpr int kFwRows = 64;          // degrees per chunk (4 consumer waves x 16)
+constexpr int kFwTile = 64;          // ring pairs per tile (producer lanes)
+constexpr int kFwPitch = kFwTile + 1;
+constexpr int kFwThreads = 320;
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+struct LegFwdArgs64 {
+    const double *PB;      // [(L+1)][NP][16]
+    double *F;             // [tri][8]
+    const double *seeds;   // [(L+1)][NP]
+    const double *pz;
+    const double *aprime;  // [tri]
+    const double *cscale;  // [tri]
+    double *state;         // [(L+1)][NP][2]
+    int L;
+    int NP;
+};
+
+__global__ __launch_bounds__(kFwThreads) void k_leg_fwd_mfma64(LegFwdArgs64 A) {
+    extern __shared__ unsigned char smem_raw[];
+    double *qbuf = reinterpret_cast<double *>(smem_raw);                 // [2][kFwRows][kFwPitch]
+    double *gbuf = qbuf + 2 * kFwRows * kFwPitch;                        // [2][kFwTile][16]
+    const int L = A.L, NP = A.NP;
+    const int m = blockIdx.x;
+    const int wave = uniform_int(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t t0 = tri_offset(L, m);
+    const int nl = L + 2 - m;
+    const int nchunk = (nl + kFwRows - 1) / kFwRows;
+    const int ntile = (NP + kFwTile - 1) / kFwTile;
+    const int total = nchunk * ntile;
+    double *state = A.state + (size_t)m * NP * 2;
+
+    f64x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    for (int it = 0; it <= total; ++it) {
+        if (wave == 4 && it < total) {
+            const int ch = it / ntile, t = it - ch * ntile;
+            const int base = m + ch * kFwRows;
+            const int p = t * kFwTile + lane;
+            const bool valid = p < NP;
+            double *qb = qbuf + (it & 1) * kFwRows * kFwPitch;
+            double *gb = gbuf + (it & 1) * kFwTile * 16;
+            // pair data for this tile (zero beyond the last pair)
+            {
+                const double *src = A.PB + ((size_t)m * NP + p) * 16;
+#pragma unroll
+                for (int c = 0; c < 16; ++c) gb[lane * 16 + c] = valid ? src[c] : 0.0;
+            }
+            const double z = valid ? A.pz[p] : 0.0;
+            double q1, q2;
+            if (ch == 0) {
+                q1 = 0.0;
+                q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+            } else {
+                q1 = valid ? state[2 * p] : 0.0;
+                q2 = valid ? state[2 * p + 1] : 0.0;
+            }
+            // this chunk's a' values, one per lane, broadcast step by step
+            const int lpl = base + lane;
+            const double areg = lpl <= L + 1 ? A.aprime[t0 + lpl - m] : 0.0;
+#pragma unroll
+            for (int s = 0; s < kFwRows; ++s) {
+                const double as = readlane_f64(areg, s);
+                const double v = fma(as, z * q1, -q2);
+                qb[s * kFwPitch + lane] = v;
+                q2 = q1;
+                q1 = v;
+            }
+            if (valid) {
+                state[2 * p] = q1;
+                state[2 * p + 1] = q2;
+            }
+        }
+        if (wave < 4 && it >= 1) {
+            const int jt = it - 1;
+            const int ch = jt / ntile, t = jt - ch * ntile;
+            const double *qb = qbuf + (jt & 1) * kFwRows * kFwPitch;
+            const double *gb = gbuf + (jt & 1) * kFwTile * 16;
+            if (t == 0) {
+                acc0 = f64x4{0, 0, 0, 0};
+                acc1 = f64x4{0, 0, 0, 0};
+            }
+            const int i = lane & 15, k = lane >> 4;
+            const double *arow = qb + (wave * 16 + i) * kFwPitch + k;
+            const double *bcol = gb + k * 16 + i;
+            double av[16], bv[16];
+#pragma unroll
+            for (int g = 0; g < 16; ++g) {
+                av[g] = arow[4 * g];
+                bv[g] = bcol[4 * g * 16];
+            }
+#pragma unroll
+            for (int g = 0; g < 16; g += 2) {
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[g], bv[g], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[g + 1], bv[g + 1], acc1, 0, 0, 0);
+            }
+            if (t == ntile - 1) {
+                const int base = m + ch * kFwRows + wave * 16;
+                const int j = lane & 15;
+                // v_mfma_f64_16x16x4 result: lane l, register r holds row 4r + l/16,
+                // column l%16 (measured on gfx950).  Row parity (lp + m) & 1 equals
+                // (l/16) & 1 and selects S (column < 8) or D (column >= 8).
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int lp = base + 4 * r + (lane >> 4);
+                    if (lp <= L + 1 && ((j >> 3) == ((lane >> 4) & 1))) {
+                        const int64_t ti = t0 + lp - m;
+                        A.F[ti * 8 + (j & 7)] = A.cscale[ti] * (acc0[r] + acc1[r]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint Legendre synthesis (VALU): for pair p and order m,
+//   PB[m][p][0][c] = sum_{l'+m even} Q_{l',m}(z_p) FG[tri(m,l')][c]
+//   PB[m][p][1][c] = sum_{l'+m odd}  Q_{l',m}(z_p) FG[tri(m,l')][c]
+// (FG already carries c_{l'}).  One wave per (64 pairs, m); the coefficients
+// and a' are wave-uniform and live in scalar registers.
+// ---------------------------------------------------------------------------
+template <typename real>
+struct LegArgs {
+    const C2<real> *FGin;
+    C2<real> *PBout;
+    const double *seeds;
+    const double *pz;
+    const double *aprime;
+    int L;
+    int NP;
+};
+
+template <typename real>
+__global__ __launch_bounds__(64) void k_leg_adj(LegArgs<real> A) {
+    const int L = A.L, NP = A.NP;
+    const int m = blockIdx.y;
+    const int p = blockIdx.x * 64 + threadIdx.x;
+    const bool valid = p < NP;
+    const int64_t t0 = tri_offset(L, m);
+    const double *ap = A.aprime + t0 - m;       // indexed by l'
+    const C2<real> *g = A.FGin + (t0 - m) * 4;  // indexed by l'
+    const double z = valid ? A.pz[p] : 0.0;
+    double q1 = 0.0;
+    double q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+    C2<real> E[4], O[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) E[c] = O[c] = {0, 0};
+    int lp = m;
+    for (; lp + 1 <= L + 1; lp += 2) {
+        const double v1 = fma(ap[lp], z * q1, -q2);       // parity even (lp - m even)
+        const double v2 = fma(ap[lp + 1], z * v1, -q1);   // parity odd
+        const real a1 = (real)v1, a2 = (real)v2;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            E[c].x += a1 * g[lp * 4 + c].x;
+            E[c].y += a1 * g[lp * 4 + c].y;
+            O[c].x += a2 * g[(lp + 1) * 4 + c].x;
+            O[c].y += a2 * g[(lp + 1) * 4 + c].y;
+        }
+        q2 = v1;
+        q1 = v2;
+    }
+    if (lp <= L + 1) {
+        const double v1 = fma(ap[lp], z * q1, -q2);
+        const real a1 = (real)v1;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            E[c].x += a1 * g[lp * 4 + c].x;
+            E[c].y += a1 * g[lp * 4 + c].y;
+        }
+    }
+    if (valid) {
+        C2<real> *o = A.PBout + ((size_t)m * NP + p) * 8;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            o[c] = E[c];
+            o[4 + c] = O[c];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward Legendre contraction (VALU, any arithmetic type): one lane per
+// degree, recurrence by a producer wave through LDS as in the MFMA kernel,
+// ring-pair data in scalar registers.  Used for binary32.
 // ---------------------------------------------------------------------------
 constexpr int kLfChunk = 128;
 constexpr int kLfTile = 64;
 constexpr int kLfPitch = kLfTile + 1;
 
 template <typename real>
-struct LegArgs {
+struct LegFwdArgs {
     const C2<real> *PBin;
-    C2<real> *PBout;
-    const C2<real> *FGin;
     C2<real> *FGout;
     const double *seeds;
     const double *pz;
-    const double *recA;
-    const double *recB;
+    const double *aprime;
+    const double *cscale;
     double *state;
     int L;
     int NP;
 };
 
 template <typename real>
-__global__ __launch_bounds__(192) void k_leg_fwd(LegArgs<real> A) {
+__global__ __launch_bounds__(192) void k_leg_fwd(LegFwdArgs<real> A) {
     extern __shared__ unsigned char smem_raw[];
     real *tile = reinterpret_cast<real *>(smem_raw);  // [2][64][kLfPitch]
     const int L = A.L, NP = A.NP;
@@ -332,12 +542,11 @@ __global__ __launch_bounds__(192) void k_leg_fwd(LegArgs<real> A) {
     const int wave = uniform_int(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int64_t t0 = tri_offset(L, m);
-    const int nl = L + 2 - m;  // degrees m..L+1
+    const int nl = L + 2 - m;
     const int nchunk = (nl + kLfChunk - 1) / kLfChunk;
     const int ntile = (NP + kLfTile - 1) / kLfTile;
     double *state = A.state + (size_t)m * NP * 2;
-    const double *recA = A.recA + t0 - m;  // indexed by l'
-    const double *recB = A.recB + t0 - m;
+    const double *ap = A.aprime + t0 - m;
 
     for (int ch = 0; ch < nchunk; ++ch) {
         const int base = m + ch * kLfChunk;
@@ -349,27 +558,23 @@ __global__ __launch_bounds__(192) void k_leg_fwd(LegArgs<real> A) {
                 const int p = t * kLfTile + lane;
                 const bool valid = p < NP;
                 const double z = valid ? A.pz[p] : 0.0;
-                double l1 = 0.0, l2 = 0.0;
-                if (ch > 0 && valid) {
-                    l1 = state[2 * p];
-                    l2 = state[2 * p + 1];
+                double q1 = 0.0, q2 = 0.0;
+                if (ch == 0) {
+                    q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+                } else if (valid) {
+                    q1 = state[2 * p];
+                    q2 = state[2 * p + 1];
                 }
                 for (int s = 0; s < kLfChunk; ++s) {
                     const int lp = base + s;
-                    double v;
-                    if (lp == m)
-                        v = valid ? A.seeds[(size_t)m * NP + p] : 0.0;
-                    else if (lp <= L + 1)
-                        v = recA[lp] * z * l1 - recB[lp] * l2;
-                    else
-                        v = 0.0;
+                    const double v = lp <= L + 1 ? fma(ap[lp], z * q1, -q2) : 0.0;
                     tile[((s & 1) * 64 + (s >> 1)) * kLfPitch + lane] = (real)v;
-                    l2 = l1;
-                    l1 = v;
+                    q2 = q1;
+                    q1 = v;
                 }
                 if (valid) {
-                    state[2 * p] = l1;
-                    state[2 * p + 1] = l2;
+                    state[2 * p] = q1;
+                    state[2 * p + 1] = q2;
                 }
             }
             __syncthreads();
@@ -393,72 +598,11 @@ __global__ __launch_bounds__(192) void k_leg_fwd(LegArgs<real> A) {
         if (wave >= 1) {
             const int lp = base + 2 * lane + (wave - 1);
             if (lp <= L + 1) {
+                const real cs = (real)A.cscale[t0 + lp - m];
                 C2<real> *o = A.FGout + (t0 + lp - m) * 4;
 #pragma unroll
-                for (int c = 0; c < 4; ++c) o[c] = acc[c];
+                for (int c = 0; c < 4; ++c) o[c] = {cs * acc[c].x, cs * acc[c].y};
             }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Adjoint Legendre synthesis: for pair p and order m,
-//   PB[m][p][0][c] = sum_{l'+m even} Lambda_{l',m}(z_p) FG[tri(m,l')][c]
-//   PB[m][p][1][c] = sum_{l'+m odd}  Lambda_{l',m}(z_p) FG[tri(m,l')][c]
-// One wave per (64 pairs, m); coefficients are wave-uniform.
-// ---------------------------------------------------------------------------
-template <typename real>
-__global__ __launch_bounds__(64) void k_leg_adj(LegArgs<real> A) {
-    const int L = A.L, NP = A.NP;
-    const int m = blockIdx.y;
-    const int p = blockIdx.x * 64 + threadIdx.x;
-    const bool valid = p < NP;
-    const int64_t t0 = tri_offset(L, m);
-    const double *recA = A.recA + t0 - m;
-    const double *recB = A.recB + t0 - m;
-    const C2<real> *g = A.FGin + (t0 - m) * 4;  // indexed by l'
-    const double z = valid ? A.pz[p] : 0.0;
-    double l1 = valid ? A.seeds[(size_t)m * NP + p] : 0.0;  // Lambda_{m}
-    double l2 = 0.0;
-    C2<real> E[4], O[4];
-    {
-        const real lam = (real)l1;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            E[c] = {lam * g[m * 4 + c].x, lam * g[m * 4 + c].y};
-            O[c] = {0, 0};
-        }
-    }
-    int lp = m + 1;
-    for (; lp + 1 <= L + 1; lp += 2) {
-        const double v1 = recA[lp] * z * l1 - recB[lp] * l2;  // odd parity (lp - m odd)
-        const double v2 = recA[lp + 1] * z * v1 - recB[lp + 1] * l1;
-        const real a1 = (real)v1, a2 = (real)v2;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            O[c].x += a1 * g[lp * 4 + c].x;
-            O[c].y += a1 * g[lp * 4 + c].y;
-            E[c].x += a2 * g[(lp + 1) * 4 + c].x;
-            E[c].y += a2 * g[(lp + 1) * 4 + c].y;
-        }
-        l2 = v1;
-        l1 = v2;
-    }
-    if (lp <= L + 1) {
-        const double v1 = recA[lp] * z * l1 - recB[lp] * l2;
-        const real a1 = (real)v1;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            O[c].x += a1 * g[lp * 4 + c].x;
-            O[c].y += a1 * g[lp * 4 + c].y;
-        }
-    }
-    if (valid) {
-        C2<real> *o = A.PBout + ((size_t)m * NP + p) * 8;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            o[c] = E[c];
-            o[4 + c] = O[c];
         }
     }
 }
@@ -475,6 +619,7 @@ struct CoefArgs {
     C2<real> *FGout;
     const C2<real> *ain, *bin;
     C2<real> *aout, *bout;
+    const double *cscale;
     int L;
 };
 
@@ -519,7 +664,7 @@ __global__ void k_recombine(CoefArgs<real> A) {
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint prep: FG[tri(m, l')] = (g^th_{+m}, g^ph_{+m}, (-1)^m g^th_{-m}, (-1)^m g^ph_{-m}),
+// Adjoint prep: FG[tri(m, l')] = c_{l'} (g^th_{+m}, g^ph_{+m}, (-1)^m g^th_{-m}, (-1)^m g^ph_{-m}),
 //   g^th_{l',mu} = (l'-1) e_{l'} at_{l'-1} - (l'+2) e_{l'+1} at_{l'+1} - i mu bt_{l'}
 //   g^ph_{l',mu} = (l'-1) e_{l'} bt_{l'-1} - (l'+2) e_{l'+1} bt_{l'+1} + i mu at_{l'}
 // with at = a / sqrt(l(l+1)) (zero outside 1 <= l <= L, |mu| <= l).
@@ -539,8 +684,10 @@ __global__ void k_prep(CoefArgs<real> A) {
     const int lp = m + blockIdx.x * blockDim.x + threadIdx.x;
     if (lp > L + 1) return;
     const int64_t t0 = tri_offset(L, m);
-    const real c1 = (real)((lp - 1) * (lp >= 1 ? e_lm(lp, m) : 0.0));
-    const real c2 = (real)((lp + 2) * e_lm(lp + 1, m));
+    const double cs = A.cscale[t0 + lp - m];  // Lambda = c Q: fold c_{l'} in
+    const real c1 = (real)(cs * (lp - 1) * (lp >= 1 ? e_lm(lp, m) : 0.0));
+    const real c2 = (real)(cs * (lp + 2) * e_lm(lp + 1, m));
+    const real csr = (real)cs;
     C2<real> *o = A.FGout + (t0 + lp - m) * 4;
     for (int sgn = 0; sgn < 2; ++sgn) {
         const int mu = sgn == 0 ? m : -m;
@@ -551,10 +698,10 @@ __global__ void k_prep(CoefArgs<real> A) {
         const C2<real> a0 = coef_scaled(A.ain, L, lp, mu), b0 = coef_scaled(A.bin, L, lp, mu);
         C2<real> gth, gph;
         // -i mu b = (mu b.y, -mu b.x); +i mu a = (-mu a.y, mu a.x)
-        gth.x = parity * (c1 * am1.x - c2 * ap1.x + fmu * b0.y);
-        gth.y = parity * (c1 * am1.y - c2 * ap1.y - fmu * b0.x);
-        gph.x = parity * (c1 * bm1.x - c2 * bp1.x - fmu * a0.y);
-        gph.y = parity * (c1 * bm1.y - c2 * bp1.y + fmu * a0.x);
+        gth.x = parity * (c1 * am1.x - c2 * ap1.x + csr * fmu * b0.y);
+        gth.y = parity * (c1 * am1.y - c2 * ap1.y - csr * fmu * b0.x);
+        gph.x = parity * (c1 * bm1.x - c2 * bp1.x - csr * fmu * a0.y);
+        gph.y = parity * (c1 * bm1.y - c2 * bp1.y + csr * fmu * a0.x);
         o[2 * sgn] = gth;
         o[2 * sgn + 1] = gph;
     }
@@ -571,8 +718,8 @@ template <typename real>
 struct ScatArgs {
     const C2<real> *FG;
     const double *xyz;
-    const double *recA;
-    const double *recB;
+    const double *aprime;
+    const double *cscale;
     C2<real> *Tout;
     int64_t n;
     int L;
@@ -608,17 +755,14 @@ __global__ __launch_bounds__(64) void k_adj_scattered(ScatArgs<real> A) {
         }
         const int64_t t0 = tri_offset(L, m);
         const C2<real> *g = A.FG + (t0 - m) * 4;
-        const double *rA = A.recA + t0 - m;
-        const double *rB = A.recB + t0 - m;
+        const double *ap = A.aprime + t0 - m;
         double h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (!pole) {
-            double l1 = ldexp(mant, e2), l2 = 0.0;
+            double q1 = 0.0, q2 = -ldexp(mant, e2);
             for (int lp = m; lp <= L + 1; ++lp) {
-                double v = lp == m ? l1 : rA[lp] * z * l1 - rB[lp] * l2;
-                if (lp > m) {
-                    l2 = l1;
-                    l1 = v;
-                }
+                const double v = fma(ap[lp], z * q1, -q2);
+                q2 = q1;
+                q1 = v;
 #pragma unroll
                 for (int cc = 0; cc < 4; ++cc) {
                     h[2 * cc] += v * (double)g[lp * 4 + cc].x;
@@ -626,9 +770,11 @@ __global__ __launch_bounds__(64) void k_adj_scattered(ScatArgs<real> A) {
                 }
             }
         } else if (m == 1) {
+            // the coefficients carry c_{l'}: divide it out of the limit of Lambda/s
+            const double *cs = A.cscale + t0 - m;
             for (int lp = 1; lp <= L + 1; ++lp) {
                 const double ll = (double)lp * (lp + 1);
-                double v = -sqrt((2.0 * lp + 1.0) / (4.0 * M_PI * ll)) * ll * 0.5;
+                double v = -sqrt((2.0 * lp + 1.0) / (4.0 * M_PI * ll)) * ll * 0.5 / cs[lp];
                 if (z < 0 && ((lp + 1) & 1)) v = -v;
 #pragma unroll
                 for (int cc = 0; cc < 4; ++cc) {
@@ -680,22 +826,42 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
     R.NP = (int)p.n_pairs;
     R.weighted = weighted ? 1 : 0;
     const size_t lds = ring_lds_bytes(p, sizeof(real));
-    hipLaunchKernelGGL(k_ring_fwd<real>, dim3((unsigned)p.n_pairs), dim3(kRingNT), lds, st, R);
+    {
+        StageScope sc(p, VSHT_STAGE_RING_FWD, st);
+        hipLaunchKernelGGL(k_ring_fwd<real>, dim3((unsigned)p.n_pairs), dim3(kRingNT), lds, st, R);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
 
-    LegArgs<real> G{};
-    G.PBin = static_cast<const C2<real> *>(p.d_pb);
-    G.FGout = static_cast<C2<real> *>(p.d_fg);
-    G.seeds = p.d_seeds;
-    G.pz = p.d_pair_z;
-    G.recA = p.d_recA;
-    G.recB = p.d_recB;
-    G.state = static_cast<double *>(p.d_state);
-    G.L = p.L;
-    G.NP = (int)p.n_pairs;
-    const size_t lds2 = (size_t)2 * 64 * kLfPitch * sizeof(real);
-    hipLaunchKernelGGL(k_leg_fwd<real>, dim3(p.L + 1), dim3(192), lds2, st, G);
+    if constexpr (sizeof(real) == 8) {
+        LegFwdArgs64 G{};
+        G.PB = static_cast<const double *>(p.d_pb);
+        G.F = static_cast<double *>(p.d_fg);
+        G.seeds = p.d_seeds;
+        G.pz = p.d_pair_z;
+        G.aprime = p.d_aprime;
+        G.cscale = p.d_cscale;
+        G.state = static_cast<double *>(p.d_state);
+        G.L = p.L;
+        G.NP = (int)p.n_pairs;
+        const size_t lds2 = (size_t)(2 * kFwRows * kFwPitch + 2 * kFwTile * 16) * sizeof(double);
+        StageScope sc(p, VSHT_STAGE_LEG_FWD, st);
+        hipLaunchKernelGGL(k_leg_fwd_mfma64, dim3(p.L + 1), dim3(kFwThreads), lds2, st, G);
+    } else {
+        LegFwdArgs<real> G{};
+        G.PBin = static_cast<const C2<real> *>(p.d_pb);
+        G.FGout = static_cast<C2<real> *>(p.d_fg);
+        G.seeds = p.d_seeds;
+        G.pz = p.d_pair_z;
+        G.aprime = p.d_aprime;
+        G.cscale = p.d_cscale;
+        G.state = static_cast<double *>(p.d_state);
+        G.L = p.L;
+        G.NP = (int)p.n_pairs;
+        const size_t lds2 = (size_t)2 * 64 * kLfPitch * sizeof(real);
+        StageScope sc(p, VSHT_STAGE_LEG_FWD, st);
+        hipLaunchKernelGGL(k_leg_fwd<real>, dim3(p.L + 1), dim3(192), lds2, st, G);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
 
@@ -704,7 +870,10 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
     C.aout = static_cast<C2<real> *>(a);
     C.bout = static_cast<C2<real> *>(b);
     C.L = p.L;
-    hipLaunchKernelGGL(k_recombine<real>, dim3((p.L + 255) / 256, p.L + 1), dim3(256), 0, st, C);
+    {
+        StageScope sc(p, VSHT_STAGE_RECOMBINE, st);
+        hipLaunchKernelGGL(k_recombine<real>, dim3((p.L + 255) / 256, p.L + 1), dim3(256), 0, st, C);
+    }
     return hipGetLastError();
 }
 
@@ -715,8 +884,12 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
     C.ain = static_cast<const C2<real> *>(a);
     C.bin = static_cast<const C2<real> *>(b);
     C.FGout = static_cast<C2<real> *>(p.d_fg);
+    C.cscale = p.d_cscale;
     C.L = p.L;
-    hipLaunchKernelGGL(k_prep<real>, dim3((p.L + 2 + 255) / 256, p.L + 1), dim3(256), 0, st, C);
+    {
+        StageScope sc(p, VSHT_STAGE_PREP, st);
+        hipLaunchKernelGGL(k_prep<real>, dim3((p.L + 2 + 255) / 256, p.L + 1), dim3(256), 0, st, C);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
 
@@ -724,11 +897,12 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
         ScatArgs<real> S{};
         S.FG = static_cast<const C2<real> *>(p.d_fg);
         S.xyz = p.d_xyz;
-        S.recA = p.d_recA;
-        S.recB = p.d_recB;
+        S.aprime = p.d_aprime;
+        S.cscale = p.d_cscale;
         S.Tout = static_cast<C2<real> *>(T);
         S.n = p.n;
         S.L = p.L;
+        StageScope sc(p, VSHT_STAGE_SCATTERED, st);
         hipLaunchKernelGGL(k_adj_scattered<real>, dim3((unsigned)((p.n + 63) / 64)), dim3(64), 0,
                            st, S);
         return hipGetLastError();
@@ -739,12 +913,14 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
     G.PBout = static_cast<C2<real> *>(p.d_pb);
     G.seeds = p.d_seeds;
     G.pz = p.d_pair_z;
-    G.recA = p.d_recA;
-    G.recB = p.d_recB;
+    G.aprime = p.d_aprime;
     G.L = p.L;
     G.NP = (int)p.n_pairs;
-    hipLaunchKernelGGL(k_leg_adj<real>, dim3((unsigned)((p.n_pairs + 63) / 64), p.L + 1),
-                       dim3(64), 0, st, G);
+    {
+        StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
+        hipLaunchKernelGGL(k_leg_adj<real>, dim3((unsigned)((p.n_pairs + 63) / 64), p.L + 1),
+                           dim3(64), 0, st, G);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
 
@@ -758,7 +934,10 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
     R.L = p.L;
     R.NP = (int)p.n_pairs;
     const size_t lds = ring_lds_bytes(p, sizeof(real));
-    hipLaunchKernelGGL(k_ring_adj<real>, dim3((unsigned)p.n_pairs), dim3(kRingNT), lds, st, R);
+    {
+        StageScope sc(p, VSHT_STAGE_RING_ADJ, st);
+        hipLaunchKernelGGL(k_ring_adj<real>, dim3((unsigned)p.n_pairs), dim3(kRingNT), lds, st, R);
+    }
     return hipGetLastError();
 }
 
@@ -789,7 +968,7 @@ hipError_t set_kernel_attributes() {
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_ring_adj<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_leg_fwd<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = hipFuncSetAttribute((const void *)k_leg_fwd_mfma64, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void *)k_leg_fwd<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
