@@ -3,6 +3,7 @@
 // the extern "C" entry points declared in include/vsht.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -65,7 +66,7 @@ hipError_t upload(T **dst, const std::vector<T> &src, size_t *bytes) {
 
 void free_plan_memory(Plan *p) {
     void *ptrs[] = {p->d_rings, p->d_pairs, p->d_ffts, p->d_tw,  p->d_pair_z, p->d_aprime,
-                    p->d_cscale,  p->d_seeds, p->d_weights, p->d_xyz, p->d_pb,  p->d_fg,
+                    p->d_cscale, p->d_etab, p->d_rsq,  p->d_seeds, p->d_weights, p->d_xyz, p->d_pb,  p->d_fg,
                     p->d_state};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -255,6 +256,20 @@ vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w, cons
     }
     if ((e = upload(&P.d_aprime, aprime, &P.table_bytes)) != hipSuccess) goto hip_error;
     if ((e = upload(&P.d_cscale, cscale, &P.table_bytes)) != hipSuccess) goto hip_error;
+    {
+        // e_{l,m} = sqrt((l^2 - m^2) / (4 l^2 - 1)) and 1 / sqrt(l (l+1))
+        std::vector<double> etab(P.tri_size, 0.0), rsq(L + 2, 0.0);
+        for (int m = 0; m <= L; ++m) {
+            const int64_t t0 = tri_offset(L, m);
+            for (int l = m; l <= L + 1; ++l) {
+                const long double ll = l, mm = m;
+                etab[t0 + l - m] = l == 0 ? 0.0 : (double)sqrtl((ll * ll - mm * mm) / (4.0L * ll * ll - 1.0L));
+            }
+        }
+        for (int l = 1; l <= L + 1; ++l) rsq[l] = (double)(1.0L / sqrtl((long double)l * (l + 1)));
+        if ((e = upload(&P.d_etab, etab, &P.table_bytes)) != hipSuccess) goto hip_error;
+        if ((e = upload(&P.d_rsq, rsq, &P.table_bytes)) != hipSuccess) goto hip_error;
+    }
 
     if (scan.ok) {
         P.kind = VSHT_PLAN_RINGS;
@@ -311,6 +326,14 @@ vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w, cons
             }
             pairs.push_back(pd);
         }
+        for (size_t q = 0; q < pairs.size(); ++q) {
+            rings[pairs[q].rn].pair = (int32_t)q;
+            rings[pairs[q].rn].south = 0;
+            if (pairs[q].rs >= 0) {
+                rings[pairs[q].rs].pair = (int32_t)q;
+                rings[pairs[q].rs].south = 1;
+            }
+        }
         P.n_rings = (int64_t)rings.size();
         P.n_pairs = (int64_t)pairs.size();
         P.n_ffts = (int)ffts.size();
@@ -346,13 +369,13 @@ vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w, cons
         }
         // workspace
         {
-            const size_t pb = (size_t)(L + 1) * P.n_pairs * 8 * 2 * rsz;
+            // ring buffer [(L+1)][NR][4] (forward) and pair buffer [(L+1)][NP][8] (adjoint)
+            const size_t per_m = std::max((size_t)P.n_rings * 4, (size_t)P.n_pairs * 8);
+            const size_t pb = (size_t)(L + 1) * per_m * 2 * rsz;
             const size_t fg = (size_t)P.tri_size * 4 * 2 * rsz;
-            const size_t stb = (size_t)(L + 1) * P.n_pairs * 2 * sizeof(double);
             if ((e = hipMalloc(&P.d_pb, pb)) != hipSuccess) goto hip_error;
             if ((e = hipMalloc(&P.d_fg, fg)) != hipSuccess) goto hip_error;
-            if ((e = hipMalloc(&P.d_state, stb)) != hipSuccess) goto hip_error;
-            P.workspace_bytes = pb + fg + stb;
+            P.workspace_bytes = pb + fg;
         }
     } else {
         P.kind = VSHT_PLAN_SCATTERED;

@@ -37,6 +37,8 @@ struct RingDesc {
     int32_t nphi;    // points on the ring
     int32_t fft;     // index of the FFT descriptor for nphi
     int32_t uniform_w;
+    int32_t pair;    // index of the ring's north/south pair
+    int32_t south;   // 1 if the ring is the southern member of its pair
     int32_t pad;
 };
 
@@ -55,10 +57,11 @@ struct FftDesc {
 };
 
 // Workspace layout (all in the plan's real type):
-//  PB   pair buffer  [(L+1)][NP][2][4] complex.
-//       forward: slot 0 = S = G_N + G_S, slot 1 = D = G_N - G_S
-//       adjoint: slot 0 = sum over even l'+m, slot 1 = sum over odd l'+m
-//       4 complex = (theta,+m) (phi,+m) (theta,-m) (phi,-m)
+//  RB   ring buffer (forward)  [(L+1)][NR][4] complex, the ring DFTs scaled by
+//       e^{-+i m phi_0} w / s: (theta,+m) (phi,+m) (theta,-m) (phi,-m)
+//  PB   pair buffer (adjoint)  [(L+1)][NP][2][4] complex: slot 0 = sum over
+//       even l'+m, slot 1 = sum over odd l'+m, same 4 columns
+//  RB and PB share one allocation.
 //  FG   triangle buffer [tri(L)][4] complex, tri index (m, l') for
 //       0 <= m <= L, m <= l' <= L+1: forward F, adjoint prep g.
 struct Plan {
@@ -80,6 +83,8 @@ struct Plan {
     double *d_pair_z = nullptr;    // z of each pair's northern ring
     double *d_aprime = nullptr;    // scaled recurrence Q_l = a'_l z Q_{l-1} - Q_{l-2}, [tri]
     double *d_cscale = nullptr;    // Lambda_{l,m} = c_{l,m} Q_{l,m}, [tri]
+    double *d_etab = nullptr;      // e_{l,m} = sqrt((l^2-m^2)/(4l^2-1)), [tri]
+    double *d_rsq = nullptr;       // 1/sqrt(l(l+1)), [L+2] (0 at l = 0)
     double *d_seeds = nullptr;     // Lambda_{m,m}(z_p), [(L+1)][NP]
     double *d_weights = nullptr;   // per-point weights (rings with non-uniform weights)
     double *d_xyz = nullptr;       // points (scattered plans)

@@ -71,82 +71,292 @@ __global__ void k_seeds(const double *__restrict__ pair_s, int NP, int L,
 }
 
 // ---------------------------------------------------------------------------
-// LDS mixed-radix Stockham DFT of `nseq` sequences of length n stored
-// back-to-back in `buf`.  Stage with radix R and span Ns maps input index
-// j + t n/R (t < R) to output (j / Ns) Ns R + (j mod Ns) + k Ns with
-//     X = sum_t x[j + t n/R] * w^(t q),  w = e^{-+2 pi i / (Ns R)},  q = (j mod Ns) + k Ns,
-// which leaves the result in natural order after the last stage.  Every
-// thread computes up to MAXO outputs per stage into registers, the block
-// synchronises, then the outputs overwrite the inputs.  Twiddles are read
-// from the plan's binary64 table e^{-2 pi i k / n}.
+// LDS mixed-radix Stockham DFT of two sequences of length n stored
+// back-to-back in `buf`.  A stage with radix R and span Ns reads x[j + t n/R]
+// (t < R) for butterfly j, multiplies input t by W^t with
+// W = e^{-+2 pi i (j mod Ns) / (Ns R)}, applies an R-point DFT and writes
+// output k to (j / Ns) Ns R + (j mod Ns) + k Ns, which leaves natural order
+// after the last stage.  Each thread keeps its outputs in registers across
+// one barrier and then overwrites the inputs in place.
+//   R = 2, 3, 4, 5   whole butterflies with fixed constants;
+//   other odd R      u_t = y_t + y_{R-t}, v_t = y_t - y_{R-t} and
+//                    X_k, X_{R-k} = x_0 + sum_t u_t cos(2pi tk/R) +- i v_t sin(2pi tk/R),
+//                    one work item per (butterfly, group of kKP output pairs).
+// Twiddles: one entry of the binary64 table e^{-2 pi i k/n} per butterfly,
+// powers by repeated binary64 multiplication.
 // ---------------------------------------------------------------------------
-template <typename real, int NT, int MAXO>
-__device__ void fft_lds(C2<real> *buf, int nseq, const FftDesc &fd, const double *__restrict__ tw,
-                        bool inverse) {
-    const int n = fd.n;
-    const int total = nseq * n;
-    const double *twn = tw + 2 * fd.tw_offset;
-    int Ns = 1;
-    for (int f = 0; f < fd.nfac; ++f) {
-        const int R = fd.fac[f];
-        const int nR = n / R;
-        const int step = n / (Ns * R);
-        C2<real> out[MAXO];
+struct CD {
+    double x, y;
+};
+__device__ __forceinline__ CD cd_mul(CD a, CD b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename real>
+__device__ __forceinline__ C2<real> cmul_d(C2<real> v, CD w) {
+    const double vx = v.x, vy = v.y;
+    return {(real)(vx * w.x - vy * w.y), (real)(vx * w.y + vy * w.x)};
+}
+template <typename real>
+__device__ __forceinline__ C2<real> cadd(C2<real> a, C2<real> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename real>
+__device__ __forceinline__ C2<real> csub(C2<real> a, C2<real> b) { return {a.x - b.x, a.y - b.y}; }
+// a + i s b (s = +-1)
+template <typename real>
+__device__ __forceinline__ C2<real> cadd_i(C2<real> a, C2<real> b, real s) {
+    return {a.x - s * b.y, a.y + s * b.x};
+}
+__device__ __forceinline__ CD tw_at(const double *twn, int k, bool inv) {
+    return {twn[2 * k], inv ? -twn[2 * k + 1] : twn[2 * k + 1]};
+}
+
+// Thread index hidden from loop-invariant code motion: every FFT stage is
+// inlined into one kernel, and hoisting each stage's index arithmetic out of
+// the stage loop would keep all of it live at once.
+__device__ __forceinline__ int opaque_tid() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+// R-point DFT of x into y; sg = -1 forward (e^{-i}), +1 inverse.
+template <typename real, int R>
+__device__ __forceinline__ void dft_small(const C2<real> *x, C2<real> *y, real sg) {
+    if constexpr (R == 2) {
+        y[0] = cadd(x[0], x[1]);
+        y[1] = csub(x[0], x[1]);
+    } else if constexpr (R == 3) {
+        const real h = (real)0.5, s3 = (real)0.86602540378443864676372317075294;
+        const C2<real> sum = cadd(x[1], x[2]), dif = csub(x[1], x[2]);
+        y[0] = cadd(x[0], sum);
+        const C2<real> t1 = {x[0].x - h * sum.x, x[0].y - h * sum.y};
+        const C2<real> t2 = {s3 * dif.x, s3 * dif.y};
+        y[1] = cadd_i(t1, t2, sg);
+        y[2] = cadd_i(t1, t2, -sg);
+    } else if constexpr (R == 4) {
+        const C2<real> a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
+        const C2<real> c = cadd(x[1], x[3]), d = csub(x[1], x[3]);
+        y[0] = cadd(a, c);
+        y[2] = csub(a, c);
+        y[1] = cadd_i(b, d, sg);
+        y[3] = cadd_i(b, d, -sg);
+    } else if constexpr (R == 5) {
+        const real c1 = (real)0.30901699437494742410229341718282;   // cos(2pi/5)
+        const real c2 = (real)-0.80901699437494742410229341718282;  // cos(4pi/5)
+        const real s1 = (real)0.95105651629515357211643933337938;   // sin(2pi/5)
+        const real s2 = (real)0.58778525229247312916870595463907;   // sin(4pi/5)
+        const C2<real> u1 = cadd(x[1], x[4]), u2 = cadd(x[2], x[3]);
+        const C2<real> v1 = csub(x[1], x[4]), v2 = csub(x[2], x[3]);
+        y[0] = cadd(x[0], cadd(u1, u2));
+        const C2<real> a1 = {x[0].x + c1 * u1.x + c2 * u2.x, x[0].y + c1 * u1.y + c2 * u2.y};
+        const C2<real> a2 = {x[0].x + c2 * u1.x + c1 * u2.x, x[0].y + c2 * u1.y + c1 * u2.y};
+        const C2<real> b1 = {s1 * v1.x + s2 * v2.x, s1 * v1.y + s2 * v2.y};
+        const C2<real> b2 = {s2 * v1.x - s1 * v2.x, s2 * v1.y - s1 * v2.y};
+        y[1] = cadd_i(a1, b1, sg);
+        y[4] = cadd_i(a1, b1, -sg);
+        y[2] = cadd_i(a2, b2, sg);
+        y[3] = cadd_i(a2, b2, -sg);
+    }
+}
+
+template <typename real, int NT, int R, int MAXI>
+__device__ __forceinline__ void fft_stage_small(C2<real> *buf, int n, int Ns, const double *__restrict__ twn,
+                                bool inv) {
+    const int nb = n / R;
+    const int items = nb;
+    const int step = n / (Ns * R);
+    const real sg = inv ? (real)1 : (real)-1;
+    const int tid = opaque_tid();
+    C2<real> out[MAXI][R];
+    int dst[MAXI];
 #pragma unroll
-        for (int i = 0; i < MAXO; ++i) {
-            const int o = threadIdx.x + i * NT;
-            if (o < total) {
-                const int sq = o / n;
-                const int oo = o - sq * n;
-                const int jr = oo % Ns;
-                const int k = (oo / Ns) % R;
-                const int jq = oo / (Ns * R);
-                const int j = jq * Ns + jr;
-                const int dq = (jr + k * Ns) * step;  // < n
-                const C2<real> *x = buf + sq * n + j;
-                real ar = 0, ai = 0;
-                int ti = 0;
-                for (int t = 0; t < R; ++t) {
-                    const C2<real> v = x[t * nR];
-                    const real wr = (real)twn[2 * ti];
-                    const real wi = inverse ? -(real)twn[2 * ti + 1] : (real)twn[2 * ti + 1];
-                    ar += v.x * wr - v.y * wi;
-                    ai += v.x * wi + v.y * wr;
-                    ti += dq;
-                    if (ti >= n) ti -= n;
+    for (int i = 0; i < MAXI; ++i) {
+        const int it = tid + i * NT;
+        dst[i] = -1;
+        if (it < items) {
+            const int j = it;
+            const int jr = j % Ns;
+            const C2<real> *src = buf + j;
+            C2<real> x[R];
+            x[0] = src[0];
+            if (jr == 0) {
+#pragma unroll
+                for (int t = 1; t < R; ++t) x[t] = src[t * nb];
+            } else {
+                const CD W = tw_at(twn, jr * step, inv);
+                CD Wt = W;
+#pragma unroll
+                for (int t = 1; t < R; ++t) {
+                    x[t] = cmul_d(src[t * nb], Wt);
+                    if (t + 1 < R) Wt = cd_mul(Wt, W);
                 }
-                out[i] = {ar, ai};
+            }
+            dft_small<real, R>(x, out[i], sg);
+            dst[i] = (j / Ns) * Ns * R + jr;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i)
+        if (dst[i] >= 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[dst[i] + r * Ns] = out[i][r];
+        }
+    __syncthreads();
+}
+
+constexpr int kKP = 2;          // output pairs per work item of a generic odd radix
+constexpr int kSmallTab = 128;  // largest odd radix whose cos/sin table is staged in LDS
+
+template <typename real, int NT, int MAXI>
+__device__ __forceinline__ void fft_stage_odd(C2<real> *buf, int n, int R, int Ns, const double *__restrict__ twn,
+                              const CD *wR, bool inv) {
+    const int nb = n / R;
+    const int half = (R - 1) / 2;
+    const int G = (half + kKP - 1) / kKP;
+    const int items = nb * G;
+    const int step = n / (Ns * R);
+    const int stepR = n / R;  // table stride of omega_R
+    const int tid = opaque_tid();
+    C2<real> out[MAXI][2 * kKP + 1];
+    int dst[MAXI], grp[MAXI];
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) {
+        const int it = tid + i * NT;
+        dst[i] = -1;
+        grp[i] = 0;
+        if (it < items) {
+            const int g = it % G;
+            const int j = it / G;
+            const int jr = j % Ns;
+            const C2<real> *src = buf + j;
+            const C2<real> x0 = src[0];
+            const CD W = tw_at(twn, jr * step, inv);
+            const CD WR = tw_at(twn, (int)(((int64_t)jr * R * step) % n), inv);  // W^R
+            C2<real> A[kKP], B[kKP], S = {0, 0};
+            int q[kKP], kq[kKP];
+#pragma unroll
+            for (int kk = 0; kk < kKP; ++kk) {
+                A[kk] = B[kk] = {0, 0};
+                kq[kk] = g * kKP + kk + 1;
+                q[kk] = 0;
+            }
+            CD Wt = {1.0, 0.0};
+#pragma unroll 1
+            for (int t = 1; t <= half; ++t) {
+                Wt = cd_mul(Wt, W);
+                const CD Wm = cd_mul(WR, CD{Wt.x, -Wt.y});  // W^{R-t}
+                const C2<real> yt = cmul_d(src[t * nb], Wt);
+                const C2<real> ym = cmul_d(src[(R - t) * nb], Wm);
+                const C2<real> u = cadd(yt, ym), v = csub(yt, ym);
+                S = cadd(S, u);
+#pragma unroll
+                for (int kk = 0; kk < kKP; ++kk) {
+                    q[kk] += kq[kk];
+                    if (q[kk] >= R) q[kk] -= R;
+                    const CD w = R <= kSmallTab ? wR[q[kk]] : tw_at(twn, q[kk] * stepR, inv);
+                    const real wc = (real)w.x, ws = (real)w.y;
+                    A[kk].x += u.x * wc;
+                    A[kk].y += u.y * wc;
+                    B[kk].x += v.x * ws;
+                    B[kk].y += v.y * ws;
+                }
+            }
+            // X_k = x0 + A + i B,  X_{R-k} = x0 + A - i B  (w carries the direction's sign)
+#pragma unroll
+            for (int kk = 0; kk < kKP; ++kk) {
+                const C2<real> a = cadd(x0, A[kk]);
+                out[i][2 * kk] = cadd_i(a, B[kk], (real)1);
+                out[i][2 * kk + 1] = cadd_i(a, B[kk], (real)-1);
+            }
+            out[i][2 * kKP] = cadd(x0, S);
+            dst[i] = (j / Ns) * Ns * R + jr;
+            grp[i] = g;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i)
+        if (dst[i] >= 0) {
+#pragma unroll
+            for (int kk = 0; kk < kKP; ++kk) {
+                const int k = grp[i] * kKP + kk + 1;
+                if (k <= half) {
+                    buf[dst[i] + k * Ns] = out[i][2 * kk];
+                    buf[dst[i] + (R - k) * Ns] = out[i][2 * kk + 1];
+                }
+            }
+            if (grp[i] == 0) buf[dst[i]] = out[i][2 * kKP];
+        }
+    __syncthreads();
+}
+
+// Two sequences of length fdp->n in buf; wR is an LDS scratch of kSmallTab entries.
+// The number of work items per thread (MAXI) is chosen per stage so that the
+// outputs kept across the barrier fit in registers.
+template <typename real, int NT, int R>
+__device__ __forceinline__ void fft_small_dispatch(C2<real> *buf, int n, int Ns, const double *twn,
+                                                   bool inv) {
+    const int per = (n / R + NT - 1) / NT;
+    if (per <= 1) fft_stage_small<real, NT, R, 1>(buf, n, Ns, twn, inv);
+    else if (per <= 2) fft_stage_small<real, NT, R, 2>(buf, n, Ns, twn, inv);
+    else fft_stage_small<real, NT, R, 4>(buf, n, Ns, twn, inv);
+}
+
+// Stages are applied to one sequence at a time (the two sequences of a ring
+// share each stage's twiddle set), so a thread holds at most 4 small
+// butterflies or 2 odd-radix work items across a barrier (n <= 3072).
+template <typename real, int NT>
+__device__ __forceinline__ void fft_lds(C2<real> *buf, const FftDesc *fdp, const double *__restrict__ tw,
+                                        CD *wR, bool inv) {
+    const int n = fdp->n;
+    const int nfac = fdp->nfac;
+    const double *twn = tw + 2 * fdp->tw_offset;
+    int Ns = 1;
+    for (int f = 0; f < nfac; ++f) {
+        const int R = fdp->fac[f];
+        if (R > 5 && R <= kSmallTab) {
+            for (int qq = threadIdx.x; qq < R; qq += NT) wR[qq] = tw_at(twn, qq * (n / R), inv);
+            __syncthreads();
+        }
+        for (int sq = 0; sq < 2; ++sq) {
+            C2<real> *b = buf + sq * n;
+            switch (R) {
+                case 2: fft_small_dispatch<real, NT, 2>(b, n, Ns, twn, inv); break;
+                case 3: fft_small_dispatch<real, NT, 3>(b, n, Ns, twn, inv); break;
+                case 4: fft_small_dispatch<real, NT, 4>(b, n, Ns, twn, inv); break;
+                case 5: fft_small_dispatch<real, NT, 5>(b, n, Ns, twn, inv); break;
+                default: {
+                    const int items = (n / R) * (((R - 1) / 2 + kKP - 1) / kKP);
+                    if (items <= NT) fft_stage_odd<real, NT, 1>(b, n, R, Ns, twn, wR, inv);
+                    else fft_stage_odd<real, NT, 2>(b, n, R, Ns, twn, wR, inv);
+                    break;
+                }
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < MAXO; ++i) {
-            const int o = threadIdx.x + i * NT;
-            if (o < total) buf[o] = out[i];
-        }
-        __syncthreads();
         Ns *= R;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Forward ring stage: per pair, per ring: T_theta = e_theta . (w T),
-// T_phi = e_phi . (w T), DFT over longitude, scale by e^{-+ i m phi_0} / s,
-// then fold N/S.  Output PB[m][p][0] = N + S, PB[m][p][1] = N - S.
+// Ring stages: one workgroup per ring.
+//   forward: T_theta = e_theta . (w T), T_phi = e_phi . (w T), DFT over
+//            longitude, scale by e^{-+ i m phi_0} / s, store
+//            RB[m][r] = (G^th_{+m}, G^ph_{+m}, G^th_{-m}, G^ph_{-m}) for 0 <= m <= L.
+//   adjoint: H_m = (E_m +- O_m) e^{i m phi_0} / s (sign + for the northern
+//            ring of a pair, - for the southern) placed in bin m mod n with all
+//            aliases summed, inverse DFT, T = T_theta e_theta + T_phi e_phi.
+// The north/south fold of the forward transform happens when the Legendre
+// stage loads RB.
 // ---------------------------------------------------------------------------
 constexpr int kRingNT = 512;
-constexpr int kRingMaxO = 12;  // 2 sequences: 2 * nphi <= kRingNT * kRingMaxO
-constexpr int kRingMaxM = 4;   // L + 1 <= kRingNT * kRingMaxM
-constexpr int kRingMaxB = 6;   // nphi <= kRingNT * kRingMaxB
 
 template <typename real>
 struct RingArgs {
     const C2<real> *Tin;
     C2<real> *Tout;
     const double *weights;
-    C2<real> *PB;
+    C2<real> *buf;  // RB (forward) or PB (adjoint)
     const RingDesc *rings;
-    const PairDesc *pairs;
     const FftDesc *ffts;
     const double *tw;
     int L;
@@ -155,153 +365,107 @@ struct RingArgs {
 };
 
 template <typename real>
-__global__ __launch_bounds__(kRingNT) void k_ring_fwd(RingArgs<real> A) {
+__global__ __launch_bounds__(kRingNT, 2) void k_ring_fwd(RingArgs<real> A) {
     extern __shared__ unsigned char smem_raw[];
-    C2<real> *buf = reinterpret_cast<C2<real> *>(smem_raw);
-    const int p = blockIdx.x;
-    const PairDesc pd = A.pairs[p];
+    CD *wR = reinterpret_cast<CD *>(smem_raw);
+    C2<real> *buf = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
+    const int r = blockIdx.x;
+    const int NR = gridDim.x;
     const int L = A.L;
-    C2<real> st[kRingMaxM][4];
-#pragma unroll
-    for (int i = 0; i < kRingMaxM; ++i)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) st[i][c] = {0, 0};
-
-    for (int side = 0; side < 2; ++side) {
-        const int r = side == 0 ? pd.rn : pd.rs;
-        if (r < 0) break;
-        const RingDesc rd = A.rings[r];
-        const FftDesc fd = A.ffts[rd.fft];
-        const int n = rd.nphi;
-        const double *twn = A.tw + 2 * fd.tw_offset;
-        for (int j = threadIdx.x; j < n; j += kRingNT) {
-            // e^{i phi_j} = e^{i phi_0} conj(e^{-2 pi i j / n})
-            const double er = twn[2 * j], ei = -twn[2 * j + 1];
-            const real c = (real)(rd.c0 * er - rd.s0 * ei);
-            const real sn = (real)(rd.s0 * er + rd.c0 * ei);
-            const int64_t k = rd.offset + j;
-            real w = 1;
-            if (A.weighted) w = (real)(rd.uniform_w ? rd.w : A.weights[k]);
-            const C2<real> t1 = A.Tin[3 * k], t2 = A.Tin[3 * k + 1], t3 = A.Tin[3 * k + 2];
-            const real z = (real)rd.z, s = (real)rd.s;
-            C2<real> th, ph;
-            th.x = w * (z * (c * t1.x + sn * t2.x) - s * t3.x);
-            th.y = w * (z * (c * t1.y + sn * t2.y) - s * t3.y);
-            ph.x = w * (c * t2.x - sn * t1.x);
-            ph.y = w * (c * t2.y - sn * t1.y);
-            buf[j] = th;
-            buf[n + j] = ph;
-        }
-        __syncthreads();
-        fft_lds<real, kRingNT, kRingMaxO>(buf, 2, fd, A.tw, false);
-        const double inv_s = 1.0 / rd.s;
-#pragma unroll
-        for (int i = 0; i < kRingMaxM; ++i) {
-            const int m = threadIdx.x + i * kRingNT;
-            if (m <= L) {
-                const int bp = m % n;
-                const int bm = bp == 0 ? 0 : n - bp;
-                double cph = 1.0, sph = 0.0;
-                if (rd.phi0 != 0.0) sincos(m * rd.phi0, &sph, &cph);
-                // +m: times e^{-i m phi0} / s ; -m: times e^{+i m phi0} / s
-                const C2<real> fp = {(real)(cph * inv_s), (real)(-sph * inv_s)};
-                const C2<real> fm = {(real)(cph * inv_s), (real)(sph * inv_s)};
-                C2<real> v[4];
-                v[0] = cmul(buf[bp], fp);
-                v[1] = cmul(buf[n + bp], fp);
-                v[2] = cmul(buf[bm], fm);
-                v[3] = cmul(buf[n + bm], fm);
-                if (side == 0) {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) st[i][c] = v[c];
-                } else {
-                    C2<real> *o = A.PB + ((size_t)m * A.NP + p) * 8;
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        o[c] = {st[i][c].x + v[c].x, st[i][c].y + v[c].y};
-                        o[4 + c] = {st[i][c].x - v[c].x, st[i][c].y - v[c].y};
-                    }
-                }
-            }
-        }
-        __syncthreads();
+    const RingDesc rd = A.rings[r];
+    const FftDesc *fdp = A.ffts + rd.fft;
+    const int n = rd.nphi;
+    const double *twn = A.tw + 2 * fdp->tw_offset;
+    for (int j = threadIdx.x; j < n; j += kRingNT) {
+        // e^{i phi_j} = e^{i phi_0} conj(e^{-2 pi i j / n})
+        const double er = twn[2 * j], ei = -twn[2 * j + 1];
+        const real c = (real)(rd.c0 * er - rd.s0 * ei);
+        const real sn = (real)(rd.s0 * er + rd.c0 * ei);
+        const int64_t k = rd.offset + j;
+        real w = 1;
+        if (A.weighted) w = (real)(rd.uniform_w ? rd.w : A.weights[k]);
+        const C2<real> t1 = A.Tin[3 * k], t2 = A.Tin[3 * k + 1], t3 = A.Tin[3 * k + 2];
+        const real z = (real)rd.z, s = (real)rd.s;
+        C2<real> th, ph;
+        th.x = w * (z * (c * t1.x + sn * t2.x) - s * t3.x);
+        th.y = w * (z * (c * t1.y + sn * t2.y) - s * t3.y);
+        ph.x = w * (c * t2.x - sn * t1.x);
+        ph.y = w * (c * t2.y - sn * t1.y);
+        buf[j] = th;
+        buf[n + j] = ph;
     }
-    if (pd.rs < 0) {
-#pragma unroll
-        for (int i = 0; i < kRingMaxM; ++i) {
-            const int m = threadIdx.x + i * kRingNT;
-            if (m <= L) {
-                C2<real> *o = A.PB + ((size_t)m * A.NP + p) * 8;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    o[c] = st[i][c];
-                    o[4 + c] = st[i][c];
-                }
-            }
-        }
+    __syncthreads();
+    fft_lds<real, kRingNT>(buf, fdp, A.tw, wR, false);
+    const double inv_s = 1.0 / rd.s;
+    for (int m = threadIdx.x; m <= L; m += kRingNT) {
+        const int bp = m % n;
+        const int bm = bp == 0 ? 0 : n - bp;
+        double cph = 1.0, sph = 0.0;
+        if (rd.phi0 != 0.0) sincos(m * rd.phi0, &sph, &cph);
+        // +m: times e^{-i m phi0} / s ; -m: times e^{+i m phi0} / s
+        const C2<real> fp = {(real)(cph * inv_s), (real)(-sph * inv_s)};
+        const C2<real> fm = {(real)(cph * inv_s), (real)(sph * inv_s)};
+        C2<real> *o = A.buf + ((size_t)m * NR + r) * 4;
+        o[0] = cmul(buf[bp], fp);
+        o[1] = cmul(buf[n + bp], fp);
+        o[2] = cmul(buf[bm], fm);
+        o[3] = cmul(buf[n + bm], fm);
     }
 }
 
-// ---------------------------------------------------------------------------
-// Adjoint ring stage: per pair, per ring: H_m = (E_m +- O_m) e^{i m phi_0} / s
-// placed in longitude bin m mod n (all aliases summed), inverse DFT, then
-// T = T_theta e_theta + T_phi e_phi.
-// ---------------------------------------------------------------------------
 template <typename real>
-__global__ __launch_bounds__(kRingNT) void k_ring_adj(RingArgs<real> A) {
+__global__ __launch_bounds__(kRingNT, 2) void k_ring_adj(RingArgs<real> A) {
     extern __shared__ unsigned char smem_raw[];
-    C2<real> *buf = reinterpret_cast<C2<real> *>(smem_raw);
-    const int p = blockIdx.x;
-    const PairDesc pd = A.pairs[p];
+    CD *wR = reinterpret_cast<CD *>(smem_raw);
+    C2<real> *buf = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
+    const int r = blockIdx.x;
     const int L = A.L;
-    for (int side = 0; side < 2; ++side) {
-        const int r = side == 0 ? pd.rn : pd.rs;
-        if (r < 0) break;
-        const real sgn = side == 0 ? (real)1 : (real)-1;
-        const RingDesc rd = A.rings[r];
-        const FftDesc fd = A.ffts[rd.fft];
-        const int n = rd.nphi;
-        const double inv_s = 1.0 / rd.s;
-        for (int b = threadIdx.x; b < n; b += kRingNT) {
-            C2<real> hth = {0, 0}, hph = {0, 0};
-            // orders m = b + k n (k >= 0) and m = b - k n (k >= 1) with |m| <= L
-            for (int pass = 0; pass < 2; ++pass) {
-                int m = pass == 0 ? b : b - n;
-                while (pass == 0 ? (m <= L) : (m >= -L)) {
-                    const int am = m < 0 ? -m : m;
-                    const int slot = m < 0 ? 2 : 0;
-                    const C2<real> *e = A.PB + ((size_t)am * A.NP + p) * 8;
-                    const C2<real> eth = e[slot], eph = e[slot + 1];
-                    const C2<real> oth = e[4 + slot], oph = e[4 + slot + 1];
-                    double cph = 1.0, sph = 0.0;
-                    if (rd.phi0 != 0.0) sincos(m * rd.phi0, &sph, &cph);
-                    const C2<real> f = {(real)(cph * inv_s), (real)(sph * inv_s)};
-                    const C2<real> th = {eth.x + sgn * oth.x, eth.y + sgn * oth.y};
-                    const C2<real> ph = {eph.x + sgn * oph.x, eph.y + sgn * oph.y};
-                    const C2<real> a = cmul(th, f), c = cmul(ph, f);
-                    hth.x += a.x; hth.y += a.y;
-                    hph.x += c.x; hph.y += c.y;
-                    m = pass == 0 ? m + n : m - n;
-                }
+    const RingDesc rd = A.rings[r];
+    const FftDesc *fdp = A.ffts + rd.fft;
+    const int n = rd.nphi;
+    const int p = rd.pair;
+    const real sgn = rd.south ? (real)-1 : (real)1;
+    const double inv_s = 1.0 / rd.s;
+    for (int b = threadIdx.x; b < n; b += kRingNT) {
+        C2<real> hth = {0, 0}, hph = {0, 0};
+        // orders m = b + k n (k >= 0) and m = b - k n (k >= 1) with |m| <= L
+        for (int pass = 0; pass < 2; ++pass) {
+            int m = pass == 0 ? b : b - n;
+            while (pass == 0 ? (m <= L) : (m >= -L)) {
+                const int am = m < 0 ? -m : m;
+                const int slot = m < 0 ? 2 : 0;
+                const C2<real> *e = A.buf + ((size_t)am * A.NP + p) * 8;
+                const C2<real> eth = e[slot], eph = e[slot + 1];
+                const C2<real> oth = e[4 + slot], oph = e[4 + slot + 1];
+                double cph = 1.0, sph = 0.0;
+                if (rd.phi0 != 0.0) sincos(m * rd.phi0, &sph, &cph);
+                const C2<real> f = {(real)(cph * inv_s), (real)(sph * inv_s)};
+                const C2<real> th = {eth.x + sgn * oth.x, eth.y + sgn * oth.y};
+                const C2<real> ph = {eph.x + sgn * oph.x, eph.y + sgn * oph.y};
+                const C2<real> a = cmul(th, f), c = cmul(ph, f);
+                hth.x += a.x;
+                hth.y += a.y;
+                hph.x += c.x;
+                hph.y += c.y;
+                m = pass == 0 ? m + n : m - n;
             }
-            buf[b] = hth;
-            buf[n + b] = hph;
         }
-        __syncthreads();
-        fft_lds<real, kRingNT, kRingMaxO>(buf, 2, fd, A.tw, true);
-        const double *twn = A.tw + 2 * fd.tw_offset;
-        for (int j = threadIdx.x; j < n; j += kRingNT) {
-            const double er = twn[2 * j], ei = -twn[2 * j + 1];
-            const real c = (real)(rd.c0 * er - rd.s0 * ei);
-            const real sn = (real)(rd.s0 * er + rd.c0 * ei);
-            const real z = (real)rd.z, s = (real)rd.s;
-            const C2<real> th = buf[j], ph = buf[n + j];
-            const int64_t k = rd.offset + j;
-            A.Tout[3 * k] = {z * c * th.x - sn * ph.x, z * c * th.y - sn * ph.y};
-            A.Tout[3 * k + 1] = {z * sn * th.x + c * ph.x, z * sn * th.y + c * ph.y};
-            A.Tout[3 * k + 2] = {-s * th.x, -s * th.y};
-        }
-        __syncthreads();
+        buf[b] = hth;
+        buf[n + b] = hph;
+    }
+    __syncthreads();
+    fft_lds<real, kRingNT>(buf, fdp, A.tw, wR, true);
+    const double *twn = A.tw + 2 * fdp->tw_offset;
+    for (int j = threadIdx.x; j < n; j += kRingNT) {
+        const double er = twn[2 * j], ei = -twn[2 * j + 1];
+        const real c = (real)(rd.c0 * er - rd.s0 * ei);
+        const real sn = (real)(rd.s0 * er + rd.c0 * ei);
+        const real z = (real)rd.z, s = (real)rd.s;
+        const C2<real> th = buf[j], ph = buf[n + j];
+        const int64_t k = rd.offset + j;
+        A.Tout[3 * k] = {z * c * th.x - sn * ph.x, z * c * th.y - sn * ph.y};
+        A.Tout[3 * k + 1] = {z * sn * th.x + c * ph.x, z * sn * th.y + c * ph.y};
+        A.Tout[3 * k + 2] = {-s * th.x, -s * th.y};
     }
 }
 
@@ -317,144 +481,161 @@ __global__ __launch_bounds__(kRingNT) void k_ring_adj(RingArgs<real> A) {
 // ---------------------------------------------------------------------------
 
 // ---------------------------------------------------------------------------
-// Forward Legendre contraction on MFMA:
-//   FG[tri(m, l')][c] = c_{l'} sum_p Q_{l',m}(z_p) PB[m][p][(l'+m)&1][c].
-// Workgroup = 5 waves for one order m.  Wave 4 (the producer, lane = ring
-// pair) advances the recurrence 64 degrees for 64 pairs and stores Q into a
-// double-buffered LDS tile, and copies the tile's 64 x 16 pair data next to
-// it.  Waves 0..3 (consumers) each own 16 consecutive degrees and multiply
-// Q[16 x 4 pairs] by PB[4 pairs x 16 columns] with v_mfma_f64_16x16x4; the 16
-// columns are 8 of the even-parity sum S and 8 of the odd-parity difference D,
-// and each output row keeps the half that matches its parity.
+// Legendre stages on MFMA.  Every wave owns a tile of 64 ring pairs (lane =
+// pair) and advances the scaled recurrence itself, 16 degrees at a time; the
+// 16 x 64 block of Q goes through a wave-private LDS tile (pair index
+// XOR-swizzled with the row, conflict-free both ways) into the layout of a
+// 16x16x4 MFMA (binary64 or binary32).
+//
+// forward  F[tri(m,l')][c] = c_{l'} sum_p Q_{l',m}(z_p) X_p[(l'+m)&1][c],
+//          X_p[0] = RB[m][rN] + RB[m][rS], X_p[1] = RB[m][rN] - RB[m][rS]:
+//          rows = 16 degrees, K = 4 pairs, columns = 8 of X[0] then 8 of X[1]
+//          (each row keeps the half matching its parity).  The wave's X block
+//          stays in the MFMA B registers for all degrees; the partial sums of
+//          the waves of a workgroup (one per tile) are added through LDS.
+// adjoint  PB[m][p][q][c] = sum_{l'+m = q mod 2} Q_{l',m}(z_p) FG[tri(m,l')][c]:
+//          rows = 16 pairs, K = 4 degrees, columns = 8 for even l'+m then 8
+//          for odd (B is zero in the other half).  No barriers: each wave
+//          accumulates its 64 pairs over all degrees.
 // ---------------------------------------------------------------------------
-constexpr int kFwRows = 64;          // degrees per chunk (4 consumer waves x 16)
-constexpr int kFwTile = 64;          // ring pairs per tile (producer lanes)
-constexpr int kFwPitch = kFwTile + 1;
-constexpr int kFwThreads = 320;
-
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-struct LegFwdArgs64 {
-    const double *PB;      // [(L+1)][NP][16]
-    double *F;             // [tri][8]
+template <typename real>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    typedef f64x4 acc_t;
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // lane l, register r holds row 4r + l/16, column l%16 (measured on gfx950)
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <>
+struct Mfma<float> {
+    typedef f32x4 acc_t;
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // lane l, register r holds row 4(l/16) + r, column l%16 (measured on gfx950)
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+constexpr int kTileP = 64;   // ring pairs per wave
+constexpr int kRowsB = 16;   // degrees per block
+__device__ __forceinline__ int qswz(int row, int pair) { return row * kTileP + (pair ^ (row & 15)); }
+
+// Advance the recurrence 16 degrees (lp0 .. lp0+15) for the wave's pairs and
+// store Q into the wave's tile.  areg holds a'_{lp0 + lane} in lanes 0..15.
+template <typename real>
+__device__ __forceinline__ void recur16(real *qt, double areg, double z, double &q1, double &q2,
+                                        int lane) {
+#pragma unroll
+    for (int s = 0; s < kRowsB; ++s) {
+        const double az = readlane_f64(areg, s) * z;
+        const double v = fma(az, q1, -q2);
+        qt[qswz(s, lane)] = (real)v;
+        q2 = q1;
+        q1 = v;
+    }
+}
+
+template <typename real>
+struct LegFwdArgs {
+    const real *RB;        // [(L+1)][NR][8]
+    real *F;               // [tri][8]
+    const PairDesc *pairs;
     const double *seeds;   // [(L+1)][NP]
     const double *pz;
     const double *aprime;  // [tri]
     const double *cscale;  // [tri]
-    double *state;         // [(L+1)][NP][2]
     int L;
     int NP;
+    int NR;
+    int atomic;            // 1: several workgroups share an order m (accumulate into F)
 };
 
-__global__ __launch_bounds__(kFwThreads) void k_leg_fwd_mfma64(LegFwdArgs64 A) {
+template <typename real>
+__global__ __launch_bounds__(1024) void k_leg_fwd_mfma(LegFwdArgs<real> A) {
+    typedef typename Mfma<real>::acc_t acc_t;
     extern __shared__ unsigned char smem_raw[];
-    double *qbuf = reinterpret_cast<double *>(smem_raw);                 // [2][kFwRows][kFwPitch]
-    double *gbuf = qbuf + 2 * kFwRows * kFwPitch;                        // [2][kFwTile][16]
-    const int L = A.L, NP = A.NP;
+    const int L = A.L, NP = A.NP, NR = A.NR;
     const int m = blockIdx.x;
+    const int nw = blockDim.x >> 6;
     const int wave = uniform_int(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
+    const int tile = blockIdx.y * nw + wave;
+    real *qt = reinterpret_cast<real *>(smem_raw) + wave * kRowsB * kTileP;  // private tile
     const int64_t t0 = tri_offset(L, m);
-    const int nl = L + 2 - m;
-    const int nchunk = (nl + kFwRows - 1) / kFwRows;
-    const int ntile = (NP + kFwTile - 1) / kFwTile;
-    const int total = nchunk * ntile;
-    double *state = A.state + (size_t)m * NP * 2;
+    const real *RBm = A.RB + (size_t)m * NR * 8;
 
-    f64x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    for (int it = 0; it <= total; ++it) {
-        if (wave == 4 && it < total) {
-            const int ch = it / ntile, t = it - ch * ntile;
-            const int base = m + ch * kFwRows;
-            const int p = t * kFwTile + lane;
-            const bool valid = p < NP;
-            double *qb = qbuf + (it & 1) * kFwRows * kFwPitch;
-            double *gb = gbuf + (it & 1) * kFwTile * 16;
-            // pair data for this tile (zero beyond the last pair)
-            {
-                const double *src = A.PB + ((size_t)m * NP + p) * 16;
+    // the tile's folded ring data in MFMA B layout: lane (j + 16k) holds
+    // X[pair 4g + k][column j] for g = 0..15
+    const int j = lane & 15, k = lane >> 4;
+    real bv[16];
 #pragma unroll
-                for (int c = 0; c < 16; ++c) gb[lane * 16 + c] = valid ? src[c] : 0.0;
-            }
-            const double z = valid ? A.pz[p] : 0.0;
-            double q1, q2;
-            if (ch == 0) {
-                q1 = 0.0;
-                q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
-            } else {
-                q1 = valid ? state[2 * p] : 0.0;
-                q2 = valid ? state[2 * p + 1] : 0.0;
-            }
-            // this chunk's a' values, one per lane, broadcast step by step
-            const int lpl = base + lane;
-            const double areg = lpl <= L + 1 ? A.aprime[t0 + lpl - m] : 0.0;
-#pragma unroll
-            for (int s = 0; s < kFwRows; ++s) {
-                const double as = readlane_f64(areg, s);
-                const double v = fma(as, z * q1, -q2);
-                qb[s * kFwPitch + lane] = v;
-                q2 = q1;
-                q1 = v;
-            }
-            if (valid) {
-                state[2 * p] = q1;
-                state[2 * p + 1] = q2;
-            }
+    for (int g = 0; g < 16; ++g) {
+        const int pp = tile * kTileP + 4 * g + k;
+        real v = 0;
+        if (pp < NP) {
+            const PairDesc pd = A.pairs[pp];
+            const real xn = RBm[(size_t)pd.rn * 8 + (j & 7)];
+            const real xs = pd.rs >= 0 ? RBm[(size_t)pd.rs * 8 + (j & 7)] : (real)0;
+            v = j < 8 ? xn + xs : xn - xs;
         }
-        if (wave < 4 && it >= 1) {
-            const int jt = it - 1;
-            const int ch = jt / ntile, t = jt - ch * ntile;
-            const double *qb = qbuf + (jt & 1) * kFwRows * kFwPitch;
-            const double *gb = gbuf + (jt & 1) * kFwTile * 16;
-            if (t == 0) {
-                acc0 = f64x4{0, 0, 0, 0};
-                acc1 = f64x4{0, 0, 0, 0};
-            }
-            const int i = lane & 15, k = lane >> 4;
-            const double *arow = qb + (wave * 16 + i) * kFwPitch + k;
-            const double *bcol = gb + k * 16 + i;
-            double av[16], bv[16];
+        bv[g] = v;
+    }
+    const int p = tile * kTileP + lane;
+    const bool valid = p < NP;
+    const double z = valid ? A.pz[p] : 0.0;
+    double q1 = 0.0, q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+    const int nl = L + 2 - m;
+    const int nblk = (nl + kRowsB - 1) / kRowsB;
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int lp0 = m + blk * kRowsB;
+        const int la = lp0 + (lane & 15);
+        const double areg = la <= L + 1 ? A.aprime[t0 + la - m] : 0.0;
+        recur16<real>(qt, areg, z, q1, q2, lane);
+        acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
 #pragma unroll
-            for (int g = 0; g < 16; ++g) {
-                av[g] = arow[4 * g];
-                bv[g] = bcol[4 * g * 16];
-            }
+        for (int g = 0; g < 16; g += 2) {
+            const real a0 = qt[qswz(j, 4 * g + k)];
+            const real a1 = qt[qswz(j, 4 * (g + 1) + k)];
+            acc0 = Mfma<real>::mma(a0, bv[g], acc0);
+            acc1 = Mfma<real>::mma(a1, bv[g + 1], acc1);
+        }
+        // partial sums of this wave -> its tile area (reused), then add across waves
+        real *red = qt;
 #pragma unroll
-            for (int g = 0; g < 16; g += 2) {
-                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[g], bv[g], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[g + 1], bv[g + 1], acc1, 0, 0, 0);
-            }
-            if (t == ntile - 1) {
-                const int base = m + ch * kFwRows + wave * 16;
-                const int j = lane & 15;
-                // v_mfma_f64_16x16x4 result: lane l, register r holds row 4r + l/16,
-                // column l%16 (measured on gfx950).  Row parity (lp + m) & 1 equals
-                // (l/16) & 1 and selects S (column < 8) or D (column >= 8).
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int lp = base + 4 * r + (lane >> 4);
-                    if (lp <= L + 1 && ((j >> 3) == ((lane >> 4) & 1))) {
-                        const int64_t ti = t0 + lp - m;
-                        A.F[ti * 8 + (j & 7)] = A.cscale[ti] * (acc0[r] + acc1[r]);
-                    }
-                }
+        for (int r = 0; r < 4; ++r) red[r * 64 + lane] = acc0[r] + acc1[r];
+        __syncthreads();
+        for (int o = threadIdx.x; o < 256; o += blockDim.x) {
+            const int r = o >> 6, ln = o & 63;
+            const int row = Mfma<real>::row(ln, r);
+            const int col = ln & 15;
+            const int lp = lp0 + row;
+            // (lp + m) & 1 == row & 1 selects S (column < 8) or D (column >= 8)
+            if (lp <= L + 1 && ((col >> 3) == (row & 1))) {
+                real sum = 0;
+                const real *base = reinterpret_cast<real *>(smem_raw);
+                for (int w = 0; w < nw; ++w) sum += base[w * kRowsB * kTileP + r * 64 + ln];
+                const int64_t ti = t0 + lp - m;
+                const real v = (real)A.cscale[ti] * sum;
+                if (A.atomic)
+                    atomicAdd(&A.F[ti * 8 + (col & 7)], v);
+                else
+                    A.F[ti * 8 + (col & 7)] = v;
             }
         }
         __syncthreads();
     }
 }
 
-// ---------------------------------------------------------------------------
-// Adjoint Legendre synthesis (VALU): for pair p and order m,
-//   PB[m][p][0][c] = sum_{l'+m even} Q_{l',m}(z_p) FG[tri(m,l')][c]
-//   PB[m][p][1][c] = sum_{l'+m odd}  Q_{l',m}(z_p) FG[tri(m,l')][c]
-// (FG already carries c_{l'}).  One wave per (64 pairs, m); the coefficients
-// and a' are wave-uniform and live in scalar registers.
-// ---------------------------------------------------------------------------
 template <typename real>
 struct LegArgs {
-    const C2<real> *FGin;
-    C2<real> *PBout;
+    const real *FG;       // [tri][8]
+    real *PB;             // [(L+1)][NP][16]
     const double *seeds;
     const double *pz;
     const double *aprime;
@@ -463,146 +644,59 @@ struct LegArgs {
 };
 
 template <typename real>
-__global__ __launch_bounds__(64) void k_leg_adj(LegArgs<real> A) {
+__global__ __launch_bounds__(256) void k_leg_adj_mfma(LegArgs<real> A) {
+    typedef typename Mfma<real>::acc_t acc_t;
+    extern __shared__ unsigned char smem_raw[];
     const int L = A.L, NP = A.NP;
     const int m = blockIdx.y;
-    const int p = blockIdx.x * 64 + threadIdx.x;
-    const bool valid = p < NP;
-    const int64_t t0 = tri_offset(L, m);
-    const double *ap = A.aprime + t0 - m;       // indexed by l'
-    const C2<real> *g = A.FGin + (t0 - m) * 4;  // indexed by l'
-    const double z = valid ? A.pz[p] : 0.0;
-    double q1 = 0.0;
-    double q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
-    C2<real> E[4], O[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) E[c] = O[c] = {0, 0};
-    int lp = m;
-    for (; lp + 1 <= L + 1; lp += 2) {
-        const double v1 = fma(ap[lp], z * q1, -q2);       // parity even (lp - m even)
-        const double v2 = fma(ap[lp + 1], z * v1, -q1);   // parity odd
-        const real a1 = (real)v1, a2 = (real)v2;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            E[c].x += a1 * g[lp * 4 + c].x;
-            E[c].y += a1 * g[lp * 4 + c].y;
-            O[c].x += a2 * g[(lp + 1) * 4 + c].x;
-            O[c].y += a2 * g[(lp + 1) * 4 + c].y;
-        }
-        q2 = v1;
-        q1 = v2;
-    }
-    if (lp <= L + 1) {
-        const double v1 = fma(ap[lp], z * q1, -q2);
-        const real a1 = (real)v1;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            E[c].x += a1 * g[lp * 4 + c].x;
-            E[c].y += a1 * g[lp * 4 + c].y;
-        }
-    }
-    if (valid) {
-        C2<real> *o = A.PBout + ((size_t)m * NP + p) * 8;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            o[c] = E[c];
-            o[4 + c] = O[c];
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Forward Legendre contraction (VALU, any arithmetic type): one lane per
-// degree, recurrence by a producer wave through LDS as in the MFMA kernel,
-// ring-pair data in scalar registers.  Used for binary32.
-// ---------------------------------------------------------------------------
-constexpr int kLfChunk = 128;
-constexpr int kLfTile = 64;
-constexpr int kLfPitch = kLfTile + 1;
-
-template <typename real>
-struct LegFwdArgs {
-    const C2<real> *PBin;
-    C2<real> *FGout;
-    const double *seeds;
-    const double *pz;
-    const double *aprime;
-    const double *cscale;
-    double *state;
-    int L;
-    int NP;
-};
-
-template <typename real>
-__global__ __launch_bounds__(192) void k_leg_fwd(LegFwdArgs<real> A) {
-    extern __shared__ unsigned char smem_raw[];
-    real *tile = reinterpret_cast<real *>(smem_raw);  // [2][64][kLfPitch]
-    const int L = A.L, NP = A.NP;
-    const int m = blockIdx.x;
+    const int nw = blockDim.x >> 6;
     const int wave = uniform_int(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * nw + wave;
+    if (tile * kTileP >= NP) return;  // whole wave idle (no barriers below)
+    real *qt = reinterpret_cast<real *>(smem_raw) + wave * kRowsB * kTileP;
     const int64_t t0 = tri_offset(L, m);
+    const real *g = A.FG + (t0 - m) * 8;  // indexed by l'
+    const int p = tile * kTileP + lane;
+    const bool valid = p < NP;
+    const double z = valid ? A.pz[p] : 0.0;
+    double q1 = 0.0, q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+    const int j = lane & 15, k = lane >> 4;
+    acc_t acc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = acc_t{0, 0, 0, 0};
     const int nl = L + 2 - m;
-    const int nchunk = (nl + kLfChunk - 1) / kLfChunk;
-    const int ntile = (NP + kLfTile - 1) / kLfTile;
-    double *state = A.state + (size_t)m * NP * 2;
-    const double *ap = A.aprime + t0 - m;
-
-    for (int ch = 0; ch < nchunk; ++ch) {
-        const int base = m + ch * kLfChunk;
-        C2<real> acc[4];
+    const int nblk = (nl + kRowsB - 1) / kRowsB;
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int lp0 = m + blk * kRowsB;
+        const int la = lp0 + (lane & 15);
+        const double areg = la <= L + 1 ? A.aprime[t0 + la - m] : 0.0;
+        // B operands: lane (j + 16k) holds g[row 4gg + k][j & 7] if the row's
+        // parity matches the column half (row parity == (lp - m) & 1 == k & 1)
+        real bv[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = {0, 0};
-        for (int t = 0; t < ntile; ++t) {
-            if (wave == 0) {
-                const int p = t * kLfTile + lane;
-                const bool valid = p < NP;
-                const double z = valid ? A.pz[p] : 0.0;
-                double q1 = 0.0, q2 = 0.0;
-                if (ch == 0) {
-                    q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
-                } else if (valid) {
-                    q1 = state[2 * p];
-                    q2 = state[2 * p + 1];
-                }
-                for (int s = 0; s < kLfChunk; ++s) {
-                    const int lp = base + s;
-                    const double v = lp <= L + 1 ? fma(ap[lp], z * q1, -q2) : 0.0;
-                    tile[((s & 1) * 64 + (s >> 1)) * kLfPitch + lane] = (real)v;
-                    q2 = q1;
-                    q1 = v;
-                }
-                if (valid) {
-                    state[2 * p] = q1;
-                    state[2 * p + 1] = q2;
-                }
-            }
-            __syncthreads();
-            if (wave >= 1) {
-                const int q = wave - 1;
-                const int npt = min(kLfTile, NP - t * kLfTile);
-                const C2<real> *g = A.PBin + ((size_t)m * NP + (size_t)t * kLfTile) * 8 + q * 4;
-                const real *trow = tile + (q * 64 + lane) * kLfPitch;
-                for (int pp = 0; pp < npt; ++pp) {
-                    const real lam = trow[pp];
-                    const C2<real> *gp = g + pp * 8;
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        acc[c].x += lam * gp[c].x;
-                        acc[c].y += lam * gp[c].y;
-                    }
-                }
-            }
-            __syncthreads();
+        for (int gg = 0; gg < 4; ++gg) {
+            const int lp = lp0 + 4 * gg + k;
+            bv[gg] = (lp <= L + 1 && (j >> 3) == (k & 1)) ? g[(int64_t)lp * 8 + (j & 7)] : (real)0;
         }
-        if (wave >= 1) {
-            const int lp = base + 2 * lane + (wave - 1);
-            if (lp <= L + 1) {
-                const real cs = (real)A.cscale[t0 + lp - m];
-                C2<real> *o = A.FGout + (t0 + lp - m) * 4;
+        recur16<real>(qt, areg, z, q1, q2, lane);
 #pragma unroll
-                for (int c = 0; c < 4; ++c) o[c] = {cs * acc[c].x, cs * acc[c].y};
+        for (int gg = 0; gg < 4; ++gg) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                // A: lane (i + 16k) holds Q[row 4gg + k][pair 16b + i]
+                const real a = qt[qswz(4 * gg + k, 16 * b + j)];
+                acc[b] = Mfma<real>::mma(a, bv[gg], acc[b]);
             }
+        }
+    }
+    // accumulator b: lane l, register r -> pair 16b + row, column l%16
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int pp = tile * kTileP + 16 * b + Mfma<real>::row(lane, r);
+            if (pp < NP) A.PB[((size_t)m * NP + pp) * 16 + j] = acc[b][r];
         }
     }
 }
@@ -611,7 +705,9 @@ __global__ __launch_bounds__(192) void k_leg_fwd(LegFwdArgs<real> A) {
 // Three-term recombination (forward):
 //   a_{l,mu} = [l e_{l+1} F^th_{l+1} - (l+1) e_l F^th_{l-1} - i mu F^ph_l] / sqrt(l(l+1))
 //   b_{l,mu} = [l e_{l+1} F^ph_{l+1} - (l+1) e_l F^ph_{l-1} + i mu F^th_l] / sqrt(l(l+1))
-// with e_l = sqrt((l^2-m^2)/(4l^2-1)) and F_{.,-m} = (-1)^m FG[.][2..3].
+// with e_l = e_{l,m} = sqrt((l^2-m^2)/(4l^2-1)) (plan table) and
+// F_{.,-m} = (-1)^m FG[.][2..3].  One thread per (l, m >= 0); threads of a
+// block share l and run over m, so the coefficient writes are contiguous.
 // ---------------------------------------------------------------------------
 template <typename real>
 struct CoefArgs {
@@ -619,47 +715,50 @@ struct CoefArgs {
     C2<real> *FGout;
     const C2<real> *ain, *bin;
     C2<real> *aout, *bout;
-    const double *cscale;
+    const double *cscale;   // [tri] c_{l',m}
+    const double *etab;     // [tri] e_{l',m}
+    const double *rsq;      // [L+2] 1 / sqrt(l (l+1)), 0 for l = 0
     int L;
 };
-
-__device__ __forceinline__ double e_lm(int l, int m) {
-    const double L = l, M = m;
-    return sqrt((L * L - M * M) / (4.0 * L * L - 1.0));
-}
 
 template <typename real>
 __global__ void k_recombine(CoefArgs<real> A) {
     const int L = A.L;
-    const int m = blockIdx.y;
-    const int l = (m > 1 ? m : 1) + blockIdx.x * blockDim.x + threadIdx.x;
-    if (l > L) return;
+    const int l = blockIdx.y + 1;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m > l) return;
     const int64_t t0 = tri_offset(L, m);
     const C2<real> *F = A.FG + (t0 - m) * 4;  // indexed by l'
-    const double ep = e_lm(l + 1, m), em = (l - 1 >= m) ? e_lm(l, m) : 0.0;
-    const double inv = 1.0 / sqrt((double)l * (l + 1));
-    const real cp = (real)(l * ep * inv), cm = (real)((l + 1) * em * inv);
-    for (int sgn = 0; sgn < (m == 0 ? 1 : 2); ++sgn) {
+    const double *et = A.etab + t0 - m;
+    const double inv = A.rsq[l];
+    const real cp = (real)(l * et[l + 1] * inv);
+    const real cm = (real)((l + 1) * (l - 1 >= m ? et[l] : 0.0) * inv);
+    C2<real> f[3][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        f[0][c] = l - 1 >= m ? F[(l - 1) * 4 + c] : C2<real>{0, 0};
+        f[1][c] = F[l * 4 + c];
+        f[2][c] = F[(l + 1) * 4 + c];
+    }
+    const int64_t base = (int64_t)l * l + l - 1;
+#pragma unroll
+    for (int sgn = 0; sgn < 2; ++sgn) {
+        if (sgn == 1 && m == 0) break;
         const int mu = sgn == 0 ? m : -m;
-        const int off = sgn == 0 ? 0 : 2;
+        const int off = 2 * sgn;
         const real parity = (sgn == 1 && (m & 1)) ? (real)-1 : (real)1;
         const real fmu = (real)(mu * inv);
-        const C2<real> th1 = F[(l + 1) * 4 + off], ph1 = F[(l + 1) * 4 + off + 1];
-        const C2<real> th0 = F[l * 4 + off], ph0 = F[l * 4 + off + 1];
-        C2<real> thm = {0, 0}, phm = {0, 0};
-        if (l - 1 >= m) {
-            thm = F[(l - 1) * 4 + off];
-            phm = F[(l - 1) * 4 + off + 1];
-        }
+        const C2<real> th1 = f[2][off], ph1 = f[2][off + 1];
+        const C2<real> th0 = f[1][off], ph0 = f[1][off + 1];
+        const C2<real> thm = f[0][off], phm = f[0][off + 1];
         C2<real> av, bv;
-        // -i mu F^ph  = (mu F^ph.y, -mu F^ph.x);  +i mu F^th = (-mu F^th.y, mu F^th.x)
+        // -i mu F^ph = (mu F^ph.y, -mu F^ph.x);  +i mu F^th = (-mu F^th.y, mu F^th.x)
         av.x = parity * (cp * th1.x - cm * thm.x + fmu * ph0.y);
         av.y = parity * (cp * th1.y - cm * thm.y - fmu * ph0.x);
         bv.x = parity * (cp * ph1.x - cm * phm.x - fmu * th0.y);
         bv.y = parity * (cp * ph1.y - cm * phm.y + fmu * th0.x);
-        const int64_t j = (int64_t)l * l + l + mu - 1;
-        A.aout[j] = av;
-        A.bout[j] = bv;
+        A.aout[base + mu] = av;
+        A.bout[base + mu] = bv;
     }
 }
 
@@ -667,35 +766,40 @@ __global__ void k_recombine(CoefArgs<real> A) {
 // Adjoint prep: FG[tri(m, l')] = c_{l'} (g^th_{+m}, g^ph_{+m}, (-1)^m g^th_{-m}, (-1)^m g^ph_{-m}),
 //   g^th_{l',mu} = (l'-1) e_{l'} at_{l'-1} - (l'+2) e_{l'+1} at_{l'+1} - i mu bt_{l'}
 //   g^ph_{l',mu} = (l'-1) e_{l'} bt_{l'-1} - (l'+2) e_{l'+1} bt_{l'+1} + i mu at_{l'}
-// with at = a / sqrt(l(l+1)) (zero outside 1 <= l <= L, |mu| <= l).
+// with at = a / sqrt(l(l+1)) (zero outside 1 <= l <= L, |mu| <= l).  One thread
+// per (l', m); threads of a block share l' and run over m, so the coefficient
+// reads are contiguous.
 // ---------------------------------------------------------------------------
 template <typename real>
-__device__ __forceinline__ C2<real> coef_scaled(const C2<real> *c, int L, int l, int mu) {
+__device__ __forceinline__ C2<real> coef_at(const C2<real> *c, int L, int l, int mu, double rs) {
     if (l < 1 || l > L || mu > l || -mu > l) return {0, 0};
     const C2<real> v = c[(int64_t)l * l + l + mu - 1];
-    const real f = (real)(1.0 / sqrt((double)l * (l + 1)));
-    return {v.x * f, v.y * f};
+    return {v.x * (real)rs, v.y * (real)rs};
 }
 
 template <typename real>
 __global__ void k_prep(CoefArgs<real> A) {
     const int L = A.L;
-    const int m = blockIdx.y;
-    const int lp = m + blockIdx.x * blockDim.x + threadIdx.x;
-    if (lp > L + 1) return;
-    const int64_t t0 = tri_offset(L, m);
-    const double cs = A.cscale[t0 + lp - m];  // Lambda = c Q: fold c_{l'} in
-    const real c1 = (real)(cs * (lp - 1) * (lp >= 1 ? e_lm(lp, m) : 0.0));
-    const real c2 = (real)(cs * (lp + 2) * e_lm(lp + 1, m));
+    const int lp = blockIdx.y;                    // 0 .. L+1
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m > lp || m > L) return;
+    const int64_t ti = tri_offset(L, m) + lp - m;
+    const double cs = A.cscale[ti];  // Lambda = c Q: fold c_{l'} in
+    const double elp = A.etab[ti];
+    const double elp1 = lp + 1 <= L + 1 ? A.etab[ti + 1] : 0.0;
+    const real c1 = (real)(cs * (lp - 1) * elp);
+    const real c2 = (real)(cs * (lp + 2) * elp1);
     const real csr = (real)cs;
-    C2<real> *o = A.FGout + (t0 + lp - m) * 4;
+    const double rm = lp >= 2 ? A.rsq[lp - 1] : 0.0, r0 = A.rsq[lp], rp = A.rsq[lp + 1 <= L ? lp + 1 : 0];
+    C2<real> *o = A.FGout + ti * 4;
+#pragma unroll
     for (int sgn = 0; sgn < 2; ++sgn) {
         const int mu = sgn == 0 ? m : -m;
         const real parity = (sgn == 1 && (m & 1)) ? (real)-1 : (real)1;
         const real fmu = (real)mu;
-        const C2<real> am1 = coef_scaled(A.ain, L, lp - 1, mu), ap1 = coef_scaled(A.ain, L, lp + 1, mu);
-        const C2<real> bm1 = coef_scaled(A.bin, L, lp - 1, mu), bp1 = coef_scaled(A.bin, L, lp + 1, mu);
-        const C2<real> a0 = coef_scaled(A.ain, L, lp, mu), b0 = coef_scaled(A.bin, L, lp, mu);
+        const C2<real> am1 = coef_at(A.ain, L, lp - 1, mu, rm), ap1 = coef_at(A.ain, L, lp + 1, mu, rp);
+        const C2<real> bm1 = coef_at(A.bin, L, lp - 1, mu, rm), bp1 = coef_at(A.bin, L, lp + 1, mu, rp);
+        const C2<real> a0 = coef_at(A.ain, L, lp, mu, r0), b0 = coef_at(A.bin, L, lp, mu, r0);
         C2<real> gth, gph;
         // -i mu b = (mu b.y, -mu b.x); +i mu a = (-mu a.y, mu a.x)
         gth.x = parity * (c1 * am1.x - c2 * ap1.x + csr * fmu * b0.y);
@@ -808,7 +912,7 @@ __global__ __launch_bounds__(64) void k_adj_scattered(ScatArgs<real> A) {
 // launchers
 // ===========================================================================
 static size_t ring_lds_bytes(const Plan &p, size_t real_size) {
-    return (size_t)2 * p.max_nphi * 2 * real_size;
+    return kSmallTab * sizeof(CD) + (size_t)2 * p.max_nphi * 2 * real_size;
 }
 
 template <typename real>
@@ -817,9 +921,8 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
     RingArgs<real> R{};
     R.Tin = static_cast<const C2<real> *>(T);
     R.weights = p.d_weights;
-    R.PB = static_cast<C2<real> *>(p.d_pb);
+    R.buf = static_cast<C2<real> *>(p.d_pb);
     R.rings = p.d_rings;
-    R.pairs = p.d_pairs;
     R.ffts = p.d_ffts;
     R.tw = p.d_tw;
     R.L = p.L;
@@ -828,39 +931,34 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
     const size_t lds = ring_lds_bytes(p, sizeof(real));
     {
         StageScope sc(p, VSHT_STAGE_RING_FWD, st);
-        hipLaunchKernelGGL(k_ring_fwd<real>, dim3((unsigned)p.n_pairs), dim3(kRingNT), lds, st, R);
+        hipLaunchKernelGGL(k_ring_fwd<real>, dim3((unsigned)p.n_rings), dim3(kRingNT), lds, st, R);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
 
-    if constexpr (sizeof(real) == 8) {
-        LegFwdArgs64 G{};
-        G.PB = static_cast<const double *>(p.d_pb);
-        G.F = static_cast<double *>(p.d_fg);
-        G.seeds = p.d_seeds;
-        G.pz = p.d_pair_z;
-        G.aprime = p.d_aprime;
-        G.cscale = p.d_cscale;
-        G.state = static_cast<double *>(p.d_state);
-        G.L = p.L;
-        G.NP = (int)p.n_pairs;
-        const size_t lds2 = (size_t)(2 * kFwRows * kFwPitch + 2 * kFwTile * 16) * sizeof(double);
+    LegFwdArgs<real> G{};
+    G.RB = static_cast<const real *>(p.d_pb);
+    G.F = static_cast<real *>(p.d_fg);
+    G.pairs = p.d_pairs;
+    G.seeds = p.d_seeds;
+    G.pz = p.d_pair_z;
+    G.aprime = p.d_aprime;
+    G.cscale = p.d_cscale;
+    G.L = p.L;
+    G.NP = (int)p.n_pairs;
+    G.NR = (int)p.n_rings;
+    {
+        const int ntile = (int)((p.n_pairs + kTileP - 1) / kTileP);
+        const int ngroup = (ntile + 15) / 16;               // at most 16 waves per workgroup
+        const int nw = (ntile + ngroup - 1) / ngroup;
+        G.atomic = ngroup > 1 ? 1 : 0;
         StageScope sc(p, VSHT_STAGE_LEG_FWD, st);
-        hipLaunchKernelGGL(k_leg_fwd_mfma64, dim3(p.L + 1), dim3(kFwThreads), lds2, st, G);
-    } else {
-        LegFwdArgs<real> G{};
-        G.PBin = static_cast<const C2<real> *>(p.d_pb);
-        G.FGout = static_cast<C2<real> *>(p.d_fg);
-        G.seeds = p.d_seeds;
-        G.pz = p.d_pair_z;
-        G.aprime = p.d_aprime;
-        G.cscale = p.d_cscale;
-        G.state = static_cast<double *>(p.d_state);
-        G.L = p.L;
-        G.NP = (int)p.n_pairs;
-        const size_t lds2 = (size_t)2 * 64 * kLfPitch * sizeof(real);
-        StageScope sc(p, VSHT_STAGE_LEG_FWD, st);
-        hipLaunchKernelGGL(k_leg_fwd<real>, dim3(p.L + 1), dim3(192), lds2, st, G);
+        if (G.atomic) {
+            e = hipMemsetAsync(p.d_fg, 0, (size_t)p.tri_size * 8 * sizeof(real), st);
+            if (e != hipSuccess) return e;
+        }
+        const size_t lds2 = (size_t)nw * kRowsB * kTileP * sizeof(real);
+        hipLaunchKernelGGL(k_leg_fwd_mfma<real>, dim3(p.L + 1, ngroup), dim3(nw * 64), lds2, st, G);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -869,10 +967,12 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
     C.FG = static_cast<const C2<real> *>(p.d_fg);
     C.aout = static_cast<C2<real> *>(a);
     C.bout = static_cast<C2<real> *>(b);
+    C.etab = p.d_etab;
+    C.rsq = p.d_rsq;
     C.L = p.L;
     {
         StageScope sc(p, VSHT_STAGE_RECOMBINE, st);
-        hipLaunchKernelGGL(k_recombine<real>, dim3((p.L + 255) / 256, p.L + 1), dim3(256), 0, st, C);
+        hipLaunchKernelGGL(k_recombine<real>, dim3((p.L + 1 + 255) / 256, p.L), dim3(256), 0, st, C);
     }
     return hipGetLastError();
 }
@@ -885,10 +985,12 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
     C.bin = static_cast<const C2<real> *>(b);
     C.FGout = static_cast<C2<real> *>(p.d_fg);
     C.cscale = p.d_cscale;
+    C.etab = p.d_etab;
+    C.rsq = p.d_rsq;
     C.L = p.L;
     {
         StageScope sc(p, VSHT_STAGE_PREP, st);
-        hipLaunchKernelGGL(k_prep<real>, dim3((p.L + 2 + 255) / 256, p.L + 1), dim3(256), 0, st, C);
+        hipLaunchKernelGGL(k_prep<real>, dim3((p.L + 1 + 255) / 256, p.L + 2), dim3(256), 0, st, C);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -909,26 +1011,28 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
     }
 
     LegArgs<real> G{};
-    G.FGin = static_cast<const C2<real> *>(p.d_fg);
-    G.PBout = static_cast<C2<real> *>(p.d_pb);
+    G.FG = static_cast<const real *>(p.d_fg);
+    G.PB = static_cast<real *>(p.d_pb);
     G.seeds = p.d_seeds;
     G.pz = p.d_pair_z;
     G.aprime = p.d_aprime;
     G.L = p.L;
     G.NP = (int)p.n_pairs;
     {
+        const int ntile = (int)((p.n_pairs + kTileP - 1) / kTileP);
+        const int nw = ntile < 4 ? ntile : 4;
+        const size_t lds2 = (size_t)nw * kRowsB * kTileP * sizeof(real);
         StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
-        hipLaunchKernelGGL(k_leg_adj<real>, dim3((unsigned)((p.n_pairs + 63) / 64), p.L + 1),
-                           dim3(64), 0, st, G);
+        hipLaunchKernelGGL(k_leg_adj_mfma<real>, dim3((ntile + nw - 1) / nw, p.L + 1), dim3(nw * 64),
+                           lds2, st, G);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
 
     RingArgs<real> R{};
     R.Tout = static_cast<C2<real> *>(T);
-    R.PB = static_cast<C2<real> *>(p.d_pb);
+    R.buf = static_cast<C2<real> *>(p.d_pb);
     R.rings = p.d_rings;
-    R.pairs = p.d_pairs;
     R.ffts = p.d_ffts;
     R.tw = p.d_tw;
     R.L = p.L;
@@ -936,7 +1040,7 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
     const size_t lds = ring_lds_bytes(p, sizeof(real));
     {
         StageScope sc(p, VSHT_STAGE_RING_ADJ, st);
-        hipLaunchKernelGGL(k_ring_adj<real>, dim3((unsigned)p.n_pairs), dim3(kRingNT), lds, st, R);
+        hipLaunchKernelGGL(k_ring_adj<real>, dim3((unsigned)p.n_rings), dim3(kRingNT), lds, st, R);
     }
     return hipGetLastError();
 }
@@ -968,9 +1072,13 @@ hipError_t set_kernel_attributes() {
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_ring_adj<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_leg_fwd_mfma64, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = hipFuncSetAttribute((const void *)k_leg_fwd_mfma<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)k_leg_fwd<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = hipFuncSetAttribute((const void *)k_leg_fwd_mfma<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_leg_adj_mfma<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)k_leg_adj_mfma<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
 
 }  // namespace vsht
