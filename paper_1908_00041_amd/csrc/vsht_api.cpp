@@ -326,6 +326,16 @@ vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w, cons
             }
             pairs.push_back(pd);
         }
+        // the ring at z = 0 (if any) goes last: its Legendre values are known in
+        // closed form and the kernels treat it separately
+        for (size_t q = 0; q < pairs.size(); ++q)
+            if (pairs[q].rs < 0 && rings[pairs[q].rn].z == 0.0) {
+                PairDesc eq = pairs[q];
+                pairs.erase(pairs.begin() + q);
+                pairs.push_back(eq);
+                P.eq_ring = eq.rn;
+                break;
+            }
         for (size_t q = 0; q < pairs.size(); ++q) {
             rings[pairs[q].rn].pair = (int32_t)q;
             rings[pairs[q].rn].south = 0;

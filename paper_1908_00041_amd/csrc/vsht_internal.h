@@ -74,6 +74,7 @@ struct Plan {
     int64_t n_rings = 0, n_pairs = 0;
     int64_t max_nphi = 0;
     int64_t tri_size = 0;
+    int eq_ring = -1;       // ring at z = 0 (always the last pair), handled in closed form
 
     // device tables
     RingDesc *d_rings = nullptr;

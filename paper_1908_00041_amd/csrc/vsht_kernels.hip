@@ -524,18 +524,32 @@ struct Mfma<float> {
 
 constexpr int kTileP = 64;   // ring pairs per wave
 constexpr int kRowsB = 16;   // degrees per block
-__device__ __forceinline__ int qswz(int row, int pair) { return row * kTileP + (pair ^ (row & 15)); }
+// Tile swizzles (64 banks of 4 bytes): the recurrence writes one row for 64
+// consecutive pairs; the analysis MFMA reads, per 32 lanes, 16 rows x 2
+// pairs; the synthesis MFMA reads 2 rows x 16 pairs.  XOR-ing the pair with
+// 2 (row & 15) resp. 16 (row & 3) makes each of these access groups hit
+// distinct banks.
+struct SwzFwd {
+    static __device__ __forceinline__ int at(int row, int pair) {
+        return row * kTileP + (pair ^ ((row & 15) << 1));
+    }
+};
+struct SwzAdj {
+    static __device__ __forceinline__ int at(int row, int pair) {
+        return row * kTileP + (pair ^ ((row & 3) << 4));
+    }
+};
 
 // Advance the recurrence 16 degrees (lp0 .. lp0+15) for the wave's pairs and
 // store Q into the wave's tile.  areg holds a'_{lp0 + lane} in lanes 0..15.
-template <typename real>
+template <typename real, typename Swz>
 __device__ __forceinline__ void recur16(real *qt, double areg, double z, double &q1, double &q2,
                                         int lane) {
 #pragma unroll
     for (int s = 0; s < kRowsB; ++s) {
         const double az = readlane_f64(areg, s) * z;
         const double v = fma(az, q1, -q2);
-        qt[qswz(s, lane)] = (real)v;
+        qt[Swz::at(s, lane)] = (real)v;
         q2 = q1;
         q1 = v;
     }
@@ -551,22 +565,59 @@ struct LegFwdArgs {
     const double *aprime;  // [tri]
     const double *cscale;  // [tri]
     int L;
-    int NP;
+    int NP;                // all pairs (seed / pair table stride)
+    int NPT;               // pairs handled by the tiles (the equator, if any, is pair NPT)
     int NR;
+    int eq_ring;           // ring at z = 0 handled in closed form, or -1
     int atomic;            // 1: several workgroups share an order m (accumulate into F)
+};
+
+// Valid half of a 16x16 analysis block in compact form: 128 values per wave.
+template <typename real>
+struct FwdCompact;
+template <>
+struct FwdCompact<double> {
+    // lane l holds rows 4r + l/16; row parity (l/16)&1 must equal column half j/8
+    static __device__ __forceinline__ bool lane_valid(int lane) {
+        return ((lane & 15) >> 3) == ((lane >> 4) & 1);
+    }
+    static __device__ __forceinline__ bool valid(int lane, int r) { return lane_valid(lane); }
+    static __device__ __forceinline__ int slot(int lane, int r) {
+        return ((lane >> 4) * 8 + (lane & 7)) * 4 + r;
+    }
+    // inverse: compact slot -> (row, column)
+    static __device__ __forceinline__ void rc(int o, int &row, int &col) {
+        const int r = o & 3, c = o >> 2, k4 = c >> 3;
+        row = 4 * r + k4;
+        col = (k4 & 1) * 8 + (c & 7);
+    }
+};
+template <>
+struct FwdCompact<float> {
+    // lane l holds rows 4(l/16) + r; row parity r&1 must equal column half j/8
+    static __device__ __forceinline__ bool valid(int lane, int r) { return (r & 1) == ((lane & 15) >> 3); }
+    static __device__ __forceinline__ int slot(int lane, int r) { return lane * 2 + (r >> 1); }
+    static __device__ __forceinline__ void rc(int o, int &row, int &col) {
+        const int lane = o >> 1, h = o & 1;
+        const int j = lane & 15;
+        const int r = 2 * h + (j >> 3);
+        row = 4 * (lane >> 4) + r;
+        col = j;
+    }
 };
 
 template <typename real>
 __global__ __launch_bounds__(1024) void k_leg_fwd_mfma(LegFwdArgs<real> A) {
     typedef typename Mfma<real>::acc_t acc_t;
     extern __shared__ unsigned char smem_raw[];
-    const int L = A.L, NP = A.NP, NR = A.NR;
+    const int L = A.L, NP = A.NP, NPT = A.NPT, NR = A.NR;
     const int m = blockIdx.x;
     const int nw = blockDim.x >> 6;
     const int wave = uniform_int(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int tile = blockIdx.y * nw + wave;
-    real *qt = reinterpret_cast<real *>(smem_raw) + wave * kRowsB * kTileP;  // private tile
+    real *qt = reinterpret_cast<real *>(smem_raw) + wave * kRowsB * kTileP;     // private tile
+    real *red = reinterpret_cast<real *>(smem_raw) + nw * kRowsB * kTileP;      // [2][nw][128]
     const int64_t t0 = tri_offset(L, m);
     const real *RBm = A.RB + (size_t)m * NR * 8;
 
@@ -578,7 +629,7 @@ __global__ __launch_bounds__(1024) void k_leg_fwd_mfma(LegFwdArgs<real> A) {
     for (int g = 0; g < 16; ++g) {
         const int pp = tile * kTileP + 4 * g + k;
         real v = 0;
-        if (pp < NP) {
+        if (pp < NPT) {
             const PairDesc pd = A.pairs[pp];
             const real xn = RBm[(size_t)pd.rn * 8 + (j & 7)];
             const real xs = pd.rs >= 0 ? RBm[(size_t)pd.rs * 8 + (j & 7)] : (real)0;
@@ -587,40 +638,50 @@ __global__ __launch_bounds__(1024) void k_leg_fwd_mfma(LegFwdArgs<real> A) {
         bv[g] = v;
     }
     const int p = tile * kTileP + lane;
-    const bool valid = p < NP;
+    const bool valid = p < NPT;
     const double z = valid ? A.pz[p] : 0.0;
     double q1 = 0.0, q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+    // equator ring (z = 0): Q_{m+2k} = (-1)^k Lambda_{m,m}(0), odd degrees vanish
+    const double seq = A.eq_ring >= 0 ? A.seeds[(size_t)m * NP + NPT] : 0.0;
+    const real *xeq = A.eq_ring >= 0 ? RBm + (size_t)A.eq_ring * 8 : nullptr;
     const int nl = L + 2 - m;
     const int nblk = (nl + kRowsB - 1) / kRowsB;
     for (int blk = 0; blk < nblk; ++blk) {
         const int lp0 = m + blk * kRowsB;
         const int la = lp0 + (lane & 15);
         const double areg = la <= L + 1 ? A.aprime[t0 + la - m] : 0.0;
-        recur16<real>(qt, areg, z, q1, q2, lane);
+        recur16<real, SwzFwd>(qt, areg, z, q1, q2, lane);
         acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
 #pragma unroll
         for (int g = 0; g < 16; g += 2) {
-            const real a0 = qt[qswz(j, 4 * g + k)];
-            const real a1 = qt[qswz(j, 4 * (g + 1) + k)];
+            const real a0 = qt[SwzFwd::at(j, 4 * g + k)];
+            const real a1 = qt[SwzFwd::at(j, 4 * (g + 1) + k)];
             acc0 = Mfma<real>::mma(a0, bv[g], acc0);
             acc1 = Mfma<real>::mma(a1, bv[g + 1], acc1);
         }
-        // partial sums of this wave -> its tile area (reused), then add across waves
-        real *red = qt;
+        // valid half of this wave's partial block -> red[blk & 1][wave]
+        real *rw = red + ((blk & 1) * nw + wave) * 128;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) red[r * 64 + lane] = acc0[r] + acc1[r];
+        for (int r = 0; r < 4; ++r)
+            if (FwdCompact<real>::valid(lane, r)) rw[FwdCompact<real>::slot(lane, r)] = acc0[r] + acc1[r];
         __syncthreads();
-        for (int o = threadIdx.x; o < 256; o += blockDim.x) {
-            const int r = o >> 6, ln = o & 63;
-            const int row = Mfma<real>::row(ln, r);
-            const int col = ln & 15;
+        // sum over waves and store; the buffer of block blk is rewritten at
+        // blk + 2, after the next barrier, so one barrier per block suffices
+        for (int o = threadIdx.x; o < 128; o += blockDim.x) {
+            int row, col;
+            FwdCompact<real>::rc(o, row, col);
             const int lp = lp0 + row;
-            // (lp + m) & 1 == row & 1 selects S (column < 8) or D (column >= 8)
-            if (lp <= L + 1 && ((col >> 3) == (row & 1))) {
+            if (lp <= L + 1) {
+                const real *rb = red + (blk & 1) * nw * 128;
                 real sum = 0;
-                const real *base = reinterpret_cast<real *>(smem_raw);
-                for (int w = 0; w < nw; ++w) sum += base[w * kRowsB * kTileP + r * 64 + ln];
+                for (int w = 0; w < nw; ++w) sum += rb[w * 128 + o];
                 const int64_t ti = t0 + lp - m;
+                if (xeq && col < 8 && blockIdx.y == 0) {
+                    // even-parity row: the equator adds Q_{lp}(0) X_eq
+                    const int kk = (lp - m) >> 1;
+                    const double qe = (kk & 1) ? -seq : seq;
+                    sum += (real)qe * xeq[col];
+                }
                 const real v = (real)A.cscale[ti] * sum;
                 if (A.atomic)
                     atomicAdd(&A.F[ti * 8 + (col & 7)], v);
@@ -628,7 +689,6 @@ __global__ __launch_bounds__(1024) void k_leg_fwd_mfma(LegFwdArgs<real> A) {
                     A.F[ti * 8 + (col & 7)] = v;
             }
         }
-        __syncthreads();
     }
 }
 
@@ -641,6 +701,7 @@ struct LegArgs {
     const double *aprime;
     int L;
     int NP;
+    int NPT;              // pairs handled by the tiles (the equator, if any, is pair NPT)
 };
 
 template <typename real>
@@ -652,13 +713,14 @@ __global__ __launch_bounds__(256) void k_leg_adj_mfma(LegArgs<real> A) {
     const int nw = blockDim.x >> 6;
     const int wave = uniform_int(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
+    const int NPT = A.NPT;
     const int tile = blockIdx.x * nw + wave;
-    if (tile * kTileP >= NP) return;  // whole wave idle (no barriers below)
+    if (tile * kTileP >= NPT) return;  // whole wave idle (no barriers below)
     real *qt = reinterpret_cast<real *>(smem_raw) + wave * kRowsB * kTileP;
     const int64_t t0 = tri_offset(L, m);
     const real *g = A.FG + (t0 - m) * 8;  // indexed by l'
     const int p = tile * kTileP + lane;
-    const bool valid = p < NP;
+    const bool valid = p < NPT;
     const double z = valid ? A.pz[p] : 0.0;
     double q1 = 0.0, q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
     const int j = lane & 15, k = lane >> 4;
@@ -679,13 +741,13 @@ __global__ __launch_bounds__(256) void k_leg_adj_mfma(LegArgs<real> A) {
             const int lp = lp0 + 4 * gg + k;
             bv[gg] = (lp <= L + 1 && (j >> 3) == (k & 1)) ? g[(int64_t)lp * 8 + (j & 7)] : (real)0;
         }
-        recur16<real>(qt, areg, z, q1, q2, lane);
+        recur16<real, SwzAdj>(qt, areg, z, q1, q2, lane);
 #pragma unroll
         for (int gg = 0; gg < 4; ++gg) {
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 // A: lane (i + 16k) holds Q[row 4gg + k][pair 16b + i]
-                const real a = qt[qswz(4 * gg + k, 16 * b + j)];
+                const real a = qt[SwzAdj::at(4 * gg + k, 16 * b + j)];
                 acc[b] = Mfma<real>::mma(a, bv[gg], acc[b]);
             }
         }
@@ -696,8 +758,37 @@ __global__ __launch_bounds__(256) void k_leg_adj_mfma(LegArgs<real> A) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int pp = tile * kTileP + 16 * b + Mfma<real>::row(lane, r);
-            if (pp < NP) A.PB[((size_t)m * NP + pp) * 16 + j] = acc[b][r];
+            if (pp < NPT) A.PB[((size_t)m * NP + pp) * 16 + j] = acc[b][r];
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Equator ring (z = 0) of the synthesis: Q_{m+2k}(0) = (-1)^k Lambda_{m,m}(0)
+// and odd degrees vanish, so PB[m][eq][0][c] = Lambda_{m,m}(0) sum_k (-1)^k
+// FG[tri(m, m+2k)][c] and PB[m][eq][1] = 0.  One wave per order m.
+// ---------------------------------------------------------------------------
+template <typename real>
+__global__ __launch_bounds__(64) void k_equator_adj(LegArgs<real> A) {
+    const int L = A.L, NP = A.NP;
+    const int m = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t t0 = tri_offset(L, m);
+    const real *g = A.FG + t0 * 8;  // row l' = m + i
+    const int c = lane & 7, lg = lane >> 3;  // 8 lanes per column group
+    real acc = 0;
+    for (int kk = lg; 2 * kk <= L + 1 - m; kk += 8) {
+        const real v = g[(int64_t)(2 * kk) * 8 + c];
+        acc += (kk & 1) ? -v : v;
+    }
+    // sum the 8 partial sums of each column (lanes c, c+8, ..., c+56)
+    acc += __shfl_xor(acc, 8);
+    acc += __shfl_xor(acc, 16);
+    acc += __shfl_xor(acc, 32);
+    real *o = A.PB + ((size_t)m * NP + A.NPT) * 16;
+    if (lane < 8) {
+        o[c] = (real)A.seeds[(size_t)m * NP + A.NPT] * acc;
+        o[8 + c] = 0;
     }
 }
 
@@ -946,18 +1037,20 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
     G.cscale = p.d_cscale;
     G.L = p.L;
     G.NP = (int)p.n_pairs;
+    G.NPT = (int)(p.n_pairs - (p.eq_ring >= 0 ? 1 : 0));
     G.NR = (int)p.n_rings;
+    G.eq_ring = p.eq_ring;
     {
-        const int ntile = (int)((p.n_pairs + kTileP - 1) / kTileP);
-        const int ngroup = (ntile + 15) / 16;               // at most 16 waves per workgroup
-        const int nw = (ntile + ngroup - 1) / ngroup;
+        const int ntile = (G.NPT + kTileP - 1) / kTileP;
+        const int ngroup = ntile > 16 ? (ntile + 15) / 16 : 1;  // at most 16 waves per workgroup
+        const int nw = ntile > 0 ? (ntile + ngroup - 1) / ngroup : 1;
         G.atomic = ngroup > 1 ? 1 : 0;
         StageScope sc(p, VSHT_STAGE_LEG_FWD, st);
         if (G.atomic) {
             e = hipMemsetAsync(p.d_fg, 0, (size_t)p.tri_size * 8 * sizeof(real), st);
             if (e != hipSuccess) return e;
         }
-        const size_t lds2 = (size_t)nw * kRowsB * kTileP * sizeof(real);
+        const size_t lds2 = (size_t)nw * (kRowsB * kTileP + 2 * 128) * sizeof(real);
         hipLaunchKernelGGL(k_leg_fwd_mfma<real>, dim3(p.L + 1, ngroup), dim3(nw * 64), lds2, st, G);
     }
     e = hipGetLastError();
@@ -1018,13 +1111,18 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
     G.aprime = p.d_aprime;
     G.L = p.L;
     G.NP = (int)p.n_pairs;
+    G.NPT = (int)(p.n_pairs - (p.eq_ring >= 0 ? 1 : 0));
     {
-        const int ntile = (int)((p.n_pairs + kTileP - 1) / kTileP);
-        const int nw = ntile < 4 ? ntile : 4;
-        const size_t lds2 = (size_t)nw * kRowsB * kTileP * sizeof(real);
         StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
-        hipLaunchKernelGGL(k_leg_adj_mfma<real>, dim3((ntile + nw - 1) / nw, p.L + 1), dim3(nw * 64),
-                           lds2, st, G);
+        const int ntile = (G.NPT + kTileP - 1) / kTileP;
+        if (ntile > 0) {
+            const int nw = ntile < 4 ? ntile : 4;
+            const size_t lds2 = (size_t)nw * kRowsB * kTileP * sizeof(real);
+            hipLaunchKernelGGL(k_leg_adj_mfma<real>, dim3((ntile + nw - 1) / nw, p.L + 1),
+                               dim3(nw * 64), lds2, st, G);
+        }
+        if (p.eq_ring >= 0)
+            hipLaunchKernelGGL(k_equator_adj<real>, dim3(p.L + 1), dim3(64), 0, st, G);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
