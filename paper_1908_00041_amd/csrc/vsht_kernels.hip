@@ -88,6 +88,9 @@ __global__ void k_seeds(const double *__restrict__ pair_s, int NP, int L,
 struct CD {
     double x, y;
 };
+// LDS index of element i of the ring buffers: one pad element after every 16,
+// which spreads the strided Stockham writes over the banks.
+__device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
 __device__ __forceinline__ CD cd_mul(CD a, CD b) {
     return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
@@ -159,13 +162,14 @@ __device__ __forceinline__ void dft_small(const C2<real> *x, C2<real> *y, real s
 }
 
 template <typename real, int NT, int R, int MAXI>
-__device__ __forceinline__ void fft_stage_small(C2<real> *buf, int n, int Ns, const double *__restrict__ twn,
-                                bool inv) {
+__device__ __forceinline__ void fft_stage_small(C2<real> *buf, int buf_off, int n, int Ns,
+                                                const double *__restrict__ twn, bool inv) {
     const int nb = n / R;
     const int items = nb;
     const int step = n / (Ns * R);
     const real sg = inv ? (real)1 : (real)-1;
     const int tid = opaque_tid();
+    const int off = buf_off;
     C2<real> out[MAXI][R];
     int dst[MAXI];
 #pragma unroll
@@ -175,23 +179,22 @@ __device__ __forceinline__ void fft_stage_small(C2<real> *buf, int n, int Ns, co
         if (it < items) {
             const int j = it;
             const int jr = j % Ns;
-            const C2<real> *src = buf + j;
             C2<real> x[R];
-            x[0] = src[0];
+            x[0] = buf[pad16(off + j)];
             if (jr == 0) {
 #pragma unroll
-                for (int t = 1; t < R; ++t) x[t] = src[t * nb];
+                for (int t = 1; t < R; ++t) x[t] = buf[pad16(off + j + t * nb)];
             } else {
                 const CD W = tw_at(twn, jr * step, inv);
                 CD Wt = W;
 #pragma unroll
                 for (int t = 1; t < R; ++t) {
-                    x[t] = cmul_d(src[t * nb], Wt);
+                    x[t] = cmul_d(buf[pad16(off + j + t * nb)], Wt);
                     if (t + 1 < R) Wt = cd_mul(Wt, W);
                 }
             }
             dft_small<real, R>(x, out[i], sg);
-            dst[i] = (j / Ns) * Ns * R + jr;
+            dst[i] = off + (j / Ns) * Ns * R + jr;
         }
     }
     __syncthreads();
@@ -199,7 +202,7 @@ __device__ __forceinline__ void fft_stage_small(C2<real> *buf, int n, int Ns, co
     for (int i = 0; i < MAXI; ++i)
         if (dst[i] >= 0) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[dst[i] + r * Ns] = out[i][r];
+            for (int r = 0; r < R; ++r) buf[pad16(dst[i] + r * Ns)] = out[i][r];
         }
     __syncthreads();
 }
@@ -208,8 +211,8 @@ constexpr int kKP = 2;          // output pairs per work item of a generic odd r
 constexpr int kSmallTab = 128;  // largest odd radix whose cos/sin table is staged in LDS
 
 template <typename real, int NT, int MAXI>
-__device__ __forceinline__ void fft_stage_odd(C2<real> *buf, int n, int R, int Ns, const double *__restrict__ twn,
-                              const CD *wR, bool inv) {
+__device__ __forceinline__ void fft_stage_odd(C2<real> *buf, int buf_off, int n, int R, int Ns,
+                                              const double *__restrict__ twn, const CD *wR, bool inv) {
     const int nb = n / R;
     const int half = (R - 1) / 2;
     const int G = (half + kKP - 1) / kKP;
@@ -217,6 +220,7 @@ __device__ __forceinline__ void fft_stage_odd(C2<real> *buf, int n, int R, int N
     const int step = n / (Ns * R);
     const int stepR = n / R;  // table stride of omega_R
     const int tid = opaque_tid();
+    const int off = buf_off;
     C2<real> out[MAXI][2 * kKP + 1];
     int dst[MAXI], grp[MAXI];
 #pragma unroll
@@ -228,8 +232,8 @@ __device__ __forceinline__ void fft_stage_odd(C2<real> *buf, int n, int R, int N
             const int g = it % G;
             const int j = it / G;
             const int jr = j % Ns;
-            const C2<real> *src = buf + j;
-            const C2<real> x0 = src[0];
+            const int sb = off + j;
+            const C2<real> x0 = buf[pad16(sb)];
             const CD W = tw_at(twn, jr * step, inv);
             const CD WR = tw_at(twn, (int)(((int64_t)jr * R * step) % n), inv);  // W^R
             C2<real> A[kKP], B[kKP], S = {0, 0};
@@ -245,8 +249,8 @@ __device__ __forceinline__ void fft_stage_odd(C2<real> *buf, int n, int R, int N
             for (int t = 1; t <= half; ++t) {
                 Wt = cd_mul(Wt, W);
                 const CD Wm = cd_mul(WR, CD{Wt.x, -Wt.y});  // W^{R-t}
-                const C2<real> yt = cmul_d(src[t * nb], Wt);
-                const C2<real> ym = cmul_d(src[(R - t) * nb], Wm);
+                const C2<real> yt = cmul_d(buf[pad16(sb + t * nb)], Wt);
+                const C2<real> ym = cmul_d(buf[pad16(sb + (R - t) * nb)], Wm);
                 const C2<real> u = cadd(yt, ym), v = csub(yt, ym);
                 S = cadd(S, u);
 #pragma unroll
@@ -269,7 +273,7 @@ __device__ __forceinline__ void fft_stage_odd(C2<real> *buf, int n, int R, int N
                 out[i][2 * kk + 1] = cadd_i(a, B[kk], (real)-1);
             }
             out[i][2 * kKP] = cadd(x0, S);
-            dst[i] = (j / Ns) * Ns * R + jr;
+            dst[i] = off + (j / Ns) * Ns * R + jr;
             grp[i] = g;
         }
     }
@@ -281,25 +285,26 @@ __device__ __forceinline__ void fft_stage_odd(C2<real> *buf, int n, int R, int N
             for (int kk = 0; kk < kKP; ++kk) {
                 const int k = grp[i] * kKP + kk + 1;
                 if (k <= half) {
-                    buf[dst[i] + k * Ns] = out[i][2 * kk];
-                    buf[dst[i] + (R - k) * Ns] = out[i][2 * kk + 1];
+                    buf[pad16(dst[i] + k * Ns)] = out[i][2 * kk];
+                    buf[pad16(dst[i] + (R - k) * Ns)] = out[i][2 * kk + 1];
                 }
             }
-            if (grp[i] == 0) buf[dst[i]] = out[i][2 * kKP];
+            if (grp[i] == 0) buf[pad16(dst[i])] = out[i][2 * kKP];
         }
     __syncthreads();
 }
 
-// Two sequences of length fdp->n in buf; wR is an LDS scratch of kSmallTab entries.
+// Two sequences of length fdp->n in buf (element i at pad16(i)); wR is an LDS
+// scratch of kSmallTab entries.
 // The number of work items per thread (MAXI) is chosen per stage so that the
 // outputs kept across the barrier fit in registers.
 template <typename real, int NT, int R>
-__device__ __forceinline__ void fft_small_dispatch(C2<real> *buf, int n, int Ns, const double *twn,
-                                                   bool inv) {
+__device__ __forceinline__ void fft_small_dispatch(C2<real> *buf, int off, int n, int Ns,
+                                                   const double *twn, bool inv) {
     const int per = (n / R + NT - 1) / NT;
-    if (per <= 1) fft_stage_small<real, NT, R, 1>(buf, n, Ns, twn, inv);
-    else if (per <= 2) fft_stage_small<real, NT, R, 2>(buf, n, Ns, twn, inv);
-    else fft_stage_small<real, NT, R, 4>(buf, n, Ns, twn, inv);
+    if (per <= 1) fft_stage_small<real, NT, R, 1>(buf, off, n, Ns, twn, inv);
+    else if (per <= 2) fft_stage_small<real, NT, R, 2>(buf, off, n, Ns, twn, inv);
+    else fft_stage_small<real, NT, R, 4>(buf, off, n, Ns, twn, inv);
 }
 
 // Stages are applied to one sequence at a time (the two sequences of a ring
@@ -319,16 +324,16 @@ __device__ __forceinline__ void fft_lds(C2<real> *buf, const FftDesc *fdp, const
             __syncthreads();
         }
         for (int sq = 0; sq < 2; ++sq) {
-            C2<real> *b = buf + sq * n;
+            const int off = sq * n;
             switch (R) {
-                case 2: fft_small_dispatch<real, NT, 2>(b, n, Ns, twn, inv); break;
-                case 3: fft_small_dispatch<real, NT, 3>(b, n, Ns, twn, inv); break;
-                case 4: fft_small_dispatch<real, NT, 4>(b, n, Ns, twn, inv); break;
-                case 5: fft_small_dispatch<real, NT, 5>(b, n, Ns, twn, inv); break;
+                case 2: fft_small_dispatch<real, NT, 2>(buf, off, n, Ns, twn, inv); break;
+                case 3: fft_small_dispatch<real, NT, 3>(buf, off, n, Ns, twn, inv); break;
+                case 4: fft_small_dispatch<real, NT, 4>(buf, off, n, Ns, twn, inv); break;
+                case 5: fft_small_dispatch<real, NT, 5>(buf, off, n, Ns, twn, inv); break;
                 default: {
                     const int items = (n / R) * (((R - 1) / 2 + kKP - 1) / kKP);
-                    if (items <= NT) fft_stage_odd<real, NT, 1>(b, n, R, Ns, twn, wR, inv);
-                    else fft_stage_odd<real, NT, 2>(b, n, R, Ns, twn, wR, inv);
+                    if (items <= NT) fft_stage_odd<real, NT, 1>(buf, off, n, R, Ns, twn, wR, inv);
+                    else fft_stage_odd<real, NT, 2>(buf, off, n, R, Ns, twn, wR, inv);
                     break;
                 }
             }
@@ -391,8 +396,8 @@ __global__ __launch_bounds__(kRingNT, 2) void k_ring_fwd(RingArgs<real> A) {
         th.y = w * (z * (c * t1.y + sn * t2.y) - s * t3.y);
         ph.x = w * (c * t2.x - sn * t1.x);
         ph.y = w * (c * t2.y - sn * t1.y);
-        buf[j] = th;
-        buf[n + j] = ph;
+        buf[pad16(j)] = th;
+        buf[pad16(n + j)] = ph;
     }
     __syncthreads();
     fft_lds<real, kRingNT>(buf, fdp, A.tw, wR, false);
@@ -406,10 +411,10 @@ __global__ __launch_bounds__(kRingNT, 2) void k_ring_fwd(RingArgs<real> A) {
         const C2<real> fp = {(real)(cph * inv_s), (real)(-sph * inv_s)};
         const C2<real> fm = {(real)(cph * inv_s), (real)(sph * inv_s)};
         C2<real> *o = A.buf + ((size_t)m * NR + r) * 4;
-        o[0] = cmul(buf[bp], fp);
-        o[1] = cmul(buf[n + bp], fp);
-        o[2] = cmul(buf[bm], fm);
-        o[3] = cmul(buf[n + bm], fm);
+        o[0] = cmul(buf[pad16(bp)], fp);
+        o[1] = cmul(buf[pad16(n + bp)], fp);
+        o[2] = cmul(buf[pad16(bm)], fm);
+        o[3] = cmul(buf[pad16(n + bm)], fm);
     }
 }
 
@@ -450,8 +455,8 @@ __global__ __launch_bounds__(kRingNT, 2) void k_ring_adj(RingArgs<real> A) {
                 m = pass == 0 ? m + n : m - n;
             }
         }
-        buf[b] = hth;
-        buf[n + b] = hph;
+        buf[pad16(b)] = hth;
+        buf[pad16(n + b)] = hph;
     }
     __syncthreads();
     fft_lds<real, kRingNT>(buf, fdp, A.tw, wR, true);
@@ -461,7 +466,7 @@ __global__ __launch_bounds__(kRingNT, 2) void k_ring_adj(RingArgs<real> A) {
         const real c = (real)(rd.c0 * er - rd.s0 * ei);
         const real sn = (real)(rd.s0 * er + rd.c0 * ei);
         const real z = (real)rd.z, s = (real)rd.s;
-        const C2<real> th = buf[j], ph = buf[n + j];
+        const C2<real> th = buf[pad16(j)], ph = buf[pad16(n + j)];
         const int64_t k = rd.offset + j;
         A.Tout[3 * k] = {z * c * th.x - sn * ph.x, z * c * th.y - sn * ph.y};
         A.Tout[3 * k + 1] = {z * sn * th.x + c * ph.x, z * sn * th.y + c * ph.y};
@@ -812,44 +817,56 @@ struct CoefArgs {
     int L;
 };
 
+// Both coefficient kernels work on tiles of kTM orders x kTL degrees staged in
+// LDS, so that the coefficient side (contiguous in m for fixed l) and the
+// triangle side (contiguous in l' for fixed m) are both read and written in
+// contiguous runs.
+constexpr int kTM = 16, kTL = 32;
+
 template <typename real>
-__global__ void k_recombine(CoefArgs<real> A) {
+__global__ __launch_bounds__(256) void k_recombine(CoefArgs<real> A) {
+    __shared__ real fs[kTM][kTL + 2][8 + 1];  // F rows l0-1 .. l0+kTL, 8 reals (+1 pad)
     const int L = A.L;
-    const int l = blockIdx.y + 1;
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m > l) return;
-    const int64_t t0 = tri_offset(L, m);
-    const C2<real> *F = A.FG + (t0 - m) * 4;  // indexed by l'
-    const double *et = A.etab + t0 - m;
-    const double inv = A.rsq[l];
-    const real cp = (real)(l * et[l + 1] * inv);
-    const real cm = (real)((l + 1) * (l - 1 >= m ? et[l] : 0.0) * inv);
-    C2<real> f[3][4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        f[0][c] = l - 1 >= m ? F[(l - 1) * 4 + c] : C2<real>{0, 0};
-        f[1][c] = F[l * 4 + c];
-        f[2][c] = F[(l + 1) * 4 + c];
+    const int l0 = 1 + blockIdx.x * kTL, m0 = blockIdx.y * kTM;
+    if (m0 > L || m0 > l0 + kTL - 1) return;
+    for (int idx = threadIdx.x; idx < kTM * (kTL + 2) * 8; idx += blockDim.x) {
+        const int c = idx & 7, i = (idx >> 3) % (kTL + 2), mi = (idx >> 3) / (kTL + 2);
+        const int m = m0 + mi, lp = l0 - 1 + i;
+        real v = 0;
+        if (m <= L && lp >= m && lp <= L + 1)
+            v = reinterpret_cast<const real *>(A.FG)[(tri_offset(L, m) + lp - m) * 8 + c];
+        fs[mi][i][c] = v;
     }
-    const int64_t base = (int64_t)l * l + l - 1;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kTM * kTL; idx += blockDim.x) {
+        const int mi = idx % kTM, li = idx / kTM;
+        const int l = l0 + li, m = m0 + mi;
+        if (l > L || m > l) continue;
+        const double *et = A.etab + tri_offset(L, m) - m;  // indexed by l'
+        const double inv = A.rsq[l];
+        const real cp = (real)(l * et[l + 1] * inv);
+        const real cm = (real)((l + 1) * (l - 1 >= m ? et[l] : 0.0) * inv);
+        const int64_t base = (int64_t)l * l + l - 1;
 #pragma unroll
-    for (int sgn = 0; sgn < 2; ++sgn) {
-        if (sgn == 1 && m == 0) break;
-        const int mu = sgn == 0 ? m : -m;
-        const int off = 2 * sgn;
-        const real parity = (sgn == 1 && (m & 1)) ? (real)-1 : (real)1;
-        const real fmu = (real)(mu * inv);
-        const C2<real> th1 = f[2][off], ph1 = f[2][off + 1];
-        const C2<real> th0 = f[1][off], ph0 = f[1][off + 1];
-        const C2<real> thm = f[0][off], phm = f[0][off + 1];
-        C2<real> av, bv;
-        // -i mu F^ph = (mu F^ph.y, -mu F^ph.x);  +i mu F^th = (-mu F^th.y, mu F^th.x)
-        av.x = parity * (cp * th1.x - cm * thm.x + fmu * ph0.y);
-        av.y = parity * (cp * th1.y - cm * thm.y - fmu * ph0.x);
-        bv.x = parity * (cp * ph1.x - cm * phm.x - fmu * th0.y);
-        bv.y = parity * (cp * ph1.y - cm * phm.y + fmu * th0.x);
-        A.aout[base + mu] = av;
-        A.bout[base + mu] = bv;
+        for (int sgn = 0; sgn < 2; ++sgn) {
+            if (sgn == 1 && m == 0) break;
+            const int mu = sgn == 0 ? m : -m;
+            const int off = 4 * sgn;  // reals of (theta,+-m) (phi,+-m)
+            const real parity = (sgn == 1 && (m & 1)) ? (real)-1 : (real)1;
+            const real fmu = (real)(mu * inv);
+            const real *fm = fs[mi][li], *f0 = fs[mi][li + 1], *fp = fs[mi][li + 2];
+            const real th1x = fp[off], th1y = fp[off + 1], ph1x = fp[off + 2], ph1y = fp[off + 3];
+            const real th0x = f0[off], th0y = f0[off + 1], ph0x = f0[off + 2], ph0y = f0[off + 3];
+            const real thmx = fm[off], thmy = fm[off + 1], phmx = fm[off + 2], phmy = fm[off + 3];
+            C2<real> av, bv;
+            // -i mu F^ph = (mu F^ph.y, -mu F^ph.x);  +i mu F^th = (-mu F^th.y, mu F^th.x)
+            av.x = parity * (cp * th1x - cm * thmx + fmu * ph0y);
+            av.y = parity * (cp * th1y - cm * thmy - fmu * ph0x);
+            bv.x = parity * (cp * ph1x - cm * phmx - fmu * th0y);
+            bv.y = parity * (cp * ph1y - cm * phmy + fmu * th0x);
+            A.aout[base + mu] = av;
+            A.bout[base + mu] = bv;
+        }
     }
 }
 
@@ -857,48 +874,58 @@ __global__ void k_recombine(CoefArgs<real> A) {
 // Adjoint prep: FG[tri(m, l')] = c_{l'} (g^th_{+m}, g^ph_{+m}, (-1)^m g^th_{-m}, (-1)^m g^ph_{-m}),
 //   g^th_{l',mu} = (l'-1) e_{l'} at_{l'-1} - (l'+2) e_{l'+1} at_{l'+1} - i mu bt_{l'}
 //   g^ph_{l',mu} = (l'-1) e_{l'} bt_{l'-1} - (l'+2) e_{l'+1} bt_{l'+1} + i mu at_{l'}
-// with at = a / sqrt(l(l+1)) (zero outside 1 <= l <= L, |mu| <= l).  One thread
-// per (l', m); threads of a block share l' and run over m, so the coefficient
-// reads are contiguous.
+// with at = a / sqrt(l(l+1)) (zero outside 1 <= l <= L, |mu| <= l).
 // ---------------------------------------------------------------------------
 template <typename real>
-__device__ __forceinline__ C2<real> coef_at(const C2<real> *c, int L, int l, int mu, double rs) {
-    if (l < 1 || l > L || mu > l || -mu > l) return {0, 0};
-    const C2<real> v = c[(int64_t)l * l + l + mu - 1];
-    return {v.x * (real)rs, v.y * (real)rs};
-}
-
-template <typename real>
-__global__ void k_prep(CoefArgs<real> A) {
+__global__ __launch_bounds__(256) void k_prep(CoefArgs<real> A) {
+    // coefficients of degrees l0-1 .. l0+kTL for the tile's orders: [l][m][sign][a,b]
+    __shared__ C2<real> cs[kTL + 2][kTM][2][2];
     const int L = A.L;
-    const int lp = blockIdx.y;                    // 0 .. L+1
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m > lp || m > L) return;
-    const int64_t ti = tri_offset(L, m) + lp - m;
-    const double cs = A.cscale[ti];  // Lambda = c Q: fold c_{l'} in
-    const double elp = A.etab[ti];
-    const double elp1 = lp + 1 <= L + 1 ? A.etab[ti + 1] : 0.0;
-    const real c1 = (real)(cs * (lp - 1) * elp);
-    const real c2 = (real)(cs * (lp + 2) * elp1);
-    const real csr = (real)cs;
-    const double rm = lp >= 2 ? A.rsq[lp - 1] : 0.0, r0 = A.rsq[lp], rp = A.rsq[lp + 1 <= L ? lp + 1 : 0];
-    C2<real> *o = A.FGout + ti * 4;
+    const int l0 = blockIdx.x * kTL, m0 = blockIdx.y * kTM;  // l' in [l0, l0+kTL)
+    if (m0 > L || m0 > l0 + kTL - 1) return;
+    for (int idx = threadIdx.x; idx < (kTL + 2) * 2 * 2 * kTM; idx += blockDim.x) {
+        const int mi = idx % kTM, r = idx / kTM;
+        const int ab = r & 1, sg = (r >> 1) & 1, i = r >> 2;
+        const int l = l0 - 1 + i, m = m0 + mi;
+        C2<real> v = {0, 0};
+        if (l >= 1 && l <= L && m <= l) {
+            const int mu = sg ? -m : m;
+            const C2<real> c = (ab ? A.bin : A.ain)[(int64_t)l * l + l + mu - 1];
+            const real rs = (real)A.rsq[l];
+            v = {c.x * rs, c.y * rs};
+        }
+        cs[i][mi][sg][ab] = v;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kTM * kTL; idx += blockDim.x) {
+        const int li = idx % kTL, mi = idx / kTL;
+        const int lp = l0 + li, m = m0 + mi;
+        if (m > L || lp < m || lp > L + 1) continue;
+        const int64_t ti = tri_offset(L, m) + lp - m;
+        const double csc = A.cscale[ti];  // Lambda = c Q: fold c_{l'} in
+        const double elp = A.etab[ti];
+        const double elp1 = lp + 1 <= L + 1 ? A.etab[ti + 1] : 0.0;
+        const real c1 = (real)(csc * (lp - 1) * elp);
+        const real c2 = (real)(csc * (lp + 2) * elp1);
+        const real csr = (real)csc;
+        C2<real> *o = A.FGout + ti * 4;
 #pragma unroll
-    for (int sgn = 0; sgn < 2; ++sgn) {
-        const int mu = sgn == 0 ? m : -m;
-        const real parity = (sgn == 1 && (m & 1)) ? (real)-1 : (real)1;
-        const real fmu = (real)mu;
-        const C2<real> am1 = coef_at(A.ain, L, lp - 1, mu, rm), ap1 = coef_at(A.ain, L, lp + 1, mu, rp);
-        const C2<real> bm1 = coef_at(A.bin, L, lp - 1, mu, rm), bp1 = coef_at(A.bin, L, lp + 1, mu, rp);
-        const C2<real> a0 = coef_at(A.ain, L, lp, mu, r0), b0 = coef_at(A.bin, L, lp, mu, r0);
-        C2<real> gth, gph;
-        // -i mu b = (mu b.y, -mu b.x); +i mu a = (-mu a.y, mu a.x)
-        gth.x = parity * (c1 * am1.x - c2 * ap1.x + csr * fmu * b0.y);
-        gth.y = parity * (c1 * am1.y - c2 * ap1.y - csr * fmu * b0.x);
-        gph.x = parity * (c1 * bm1.x - c2 * bp1.x - csr * fmu * a0.y);
-        gph.y = parity * (c1 * bm1.y - c2 * bp1.y + csr * fmu * a0.x);
-        o[2 * sgn] = gth;
-        o[2 * sgn + 1] = gph;
+        for (int sgn = 0; sgn < 2; ++sgn) {
+            const int mu = sgn == 0 ? m : -m;
+            const real parity = (sgn == 1 && (m & 1)) ? (real)-1 : (real)1;
+            const real fmu = (real)mu;
+            const C2<real> am1 = cs[li][mi][sgn][0], bm1 = cs[li][mi][sgn][1];
+            const C2<real> a0 = cs[li + 1][mi][sgn][0], b0 = cs[li + 1][mi][sgn][1];
+            const C2<real> ap1 = cs[li + 2][mi][sgn][0], bp1 = cs[li + 2][mi][sgn][1];
+            C2<real> gth, gph;
+            // -i mu b = (mu b.y, -mu b.x); +i mu a = (-mu a.y, mu a.x)
+            gth.x = parity * (c1 * am1.x - c2 * ap1.x + csr * fmu * b0.y);
+            gth.y = parity * (c1 * am1.y - c2 * ap1.y - csr * fmu * b0.x);
+            gph.x = parity * (c1 * bm1.x - c2 * bp1.x - csr * fmu * a0.y);
+            gph.y = parity * (c1 * bm1.y - c2 * bp1.y + csr * fmu * a0.x);
+            o[2 * sgn] = gth;
+            o[2 * sgn + 1] = gph;
+        }
     }
 }
 
@@ -1003,7 +1030,8 @@ __global__ __launch_bounds__(64) void k_adj_scattered(ScatArgs<real> A) {
 // launchers
 // ===========================================================================
 static size_t ring_lds_bytes(const Plan &p, size_t real_size) {
-    return kSmallTab * sizeof(CD) + (size_t)2 * p.max_nphi * 2 * real_size;
+    const size_t elems = 2 * p.max_nphi;
+    return kSmallTab * sizeof(CD) + (elems + elems / 16 + 1) * 2 * real_size;
 }
 
 template <typename real>
@@ -1065,7 +1093,8 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
     C.L = p.L;
     {
         StageScope sc(p, VSHT_STAGE_RECOMBINE, st);
-        hipLaunchKernelGGL(k_recombine<real>, dim3((p.L + 1 + 255) / 256, p.L), dim3(256), 0, st, C);
+        hipLaunchKernelGGL(k_recombine<real>, dim3((p.L + kTL - 1) / kTL, (p.L + 1 + kTM - 1) / kTM),
+                           dim3(256), 0, st, C);
     }
     return hipGetLastError();
 }
@@ -1083,7 +1112,8 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
     C.L = p.L;
     {
         StageScope sc(p, VSHT_STAGE_PREP, st);
-        hipLaunchKernelGGL(k_prep<real>, dim3((p.L + 1 + 255) / 256, p.L + 2), dim3(256), 0, st, C);
+        hipLaunchKernelGGL(k_prep<real>, dim3((p.L + 2 + kTL - 1) / kTL, (p.L + 1 + kTM - 1) / kTM),
+                           dim3(256), 0, st, C);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
