@@ -28,10 +28,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP64_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
-FP32_VALU_TFLOPS = 78.6   # non-packed binary32 VALU (packed FP32 disabled at build)
+FP64_MFMA_TFLOPS = 78.6   # dense MFMA peaks of the MI355X
 FP32_MFMA_TFLOPS = 157.3
 BF16_MFMA_TFLOPS = 2516.6
+KERNEL_SRC = os.path.join(ROOT, "paper_1908_00041_amd", "csrc", "vsht_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def measured_traffic(kernel, prec, L):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None
+    when there is none or the kernel source changed after it was measured."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        with open(KERNEL_SRC, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != digest or rec.get("L") != L:
+        return None
+    v = rec.get("bytes_per_launch", {}).get("%s<%s>" % (kernel, "double" if prec == "fp64" else "float"))
+    return None if v is None else int(v)
 
 
 def log(*a):
@@ -84,6 +102,8 @@ def main():
     ap.add_argument("--oracle-points", type=int, default=512)
     ap.add_argument("--no-oracle", action="store_true")
     ap.add_argument("--precisions", default="fp64,fp32")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -136,6 +156,18 @@ def main():
         del T, a2, b2, ga, gb
         plan.close()
 
+    if args.copy_mb > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the
+        # scale from counter units to bytes
+        src = torch.empty(args.copy_mb * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied %d MiB" % args.copy_mb)
+        del src, dst
+
     cpu = None
     if not args.no_oracle:
         import oracle
@@ -163,16 +195,21 @@ def main():
             r["err_fwd"] = rel_l2(np.concatenate([r["fa"], r["fb"]]), np.concatenate([oa, ob]))
 
     def roofline(prec, r):
+        # dominant kernel: the larger Legendre stage.  Algorithmic work = 16 flops per
+        # (m >= 0, m <= l' <= L+1, ring pair) element: 8 real multiply-adds (theta/phi x
+        # +-m x re/im) against one Legendre value.  Both stages run on 16x16x4 MFMA
+        # whose column half of the other parity is wasted, so 100% MFMA busy is 50%.
         st = r["stages"]
         dom = max(("leg_fwd", "leg_adj"), key=lambda k: st.get(k, 0.0))
         t = st[dom] * 1e-3
         E = folded_elements(L, r["info"]["n_pairs"])
         flops = 16.0 * E
-        peak = FP64_VALU_TFLOPS if prec == "fp64" else FP32_VALU_TFLOPS
+        peak = FP64_MFMA_TFLOPS if prec == "fp64" else FP32_MFMA_TFLOPS
         ach = flops / t / 1e12
-        return {"bound": "alu", "kernel": "k_leg_adj" if dom == "leg_adj" else "k_leg_fwd",
-                "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(ach / peak, 4), "traffic": None,
+        kern = "k_leg_adj_mfma" if dom == "leg_adj" else "k_leg_fwd_mfma"
+        return {"bound": "mfma", "kernel": kern, "achieved": round(ach, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+                "traffic": measured_traffic(kern, prec, L),
                 "launch_us": round(st[dom] * 1e3, 2), "flops_per_launch": flops}
 
     main_r = results.get("fp64") or next(iter(results.values()))
