@@ -41,7 +41,8 @@
  * The fast path needs iso-latitude rings: the points are grouped into
  * consecutive runs with bitwise-equal z (one run per ring), each run holding
  * n_phi >= 1 points at longitudes phi_0 + 2 pi j / n_phi, j = 0..n_phi-1 (in
- * this order), all with the same weight, and no ring at a pole.  Rings whose
+ * this order), and no ring at a pole (weights may differ from point to point;
+ * a ring of equal weights takes a faster path).  Rings whose
  * z values are exact negatives of each other are paired (north/south).  The
  * Gauss-Legendre product grids of Section 5.1 are of this kind.  Other point
  * sets are "scattered": they are accepted for the adjoint only.
