@@ -127,6 +127,28 @@ vsht_status vsht_forward_unweighted(vsht_plan_t plan, const void *T, void *a, vo
  * (device, n x 3) at every point of the plan, in the plan's point order. */
 vsht_status vsht_adjoint(vsht_plan_t plan, const void *a, const void *b, void *T, void *stream);
 
+/* Flags of the *_many calls. */
+enum {
+    VSHT_UNIT_WEIGHTS = 1, /* forward: unit weights (S^H, as vsht_forward_unweighted) */
+    VSHT_TIMES_WEIGHTS = 2 /* adjoint: T_k = w_k (S(a, b))_k, the Hermitian transpose of vsht_forward */
+};
+
+/* count fields through one plan, one after another on `stream`.  The fields
+ * are contiguous: T holds count blocks of n x 3 complex values, a and b count
+ * blocks of L(L+2) each.  vsht_forward_many computes the forward transform of
+ * eq. (fwdvsht2) for every block (with VSHT_UNIT_WEIGHTS: with w_k = 1);
+ * vsht_adjoint_many the adjoint of eq. (SLvec) (with VSHT_TIMES_WEIGHTS: each
+ * output point multiplied by its weight, which makes it the Hermitian
+ * transpose of the weighted forward; needs a plan with weights).  These are
+ * the backward maps of the differentiable transforms: the gradient of the
+ * adjoint is the unit-weight forward and the gradient of the forward the
+ * weighted adjoint.  count = 0 does nothing.  VSHT_EINVAL for count < 0 or an
+ * unknown flag; other errors as vsht_forward / vsht_adjoint. */
+vsht_status vsht_forward_many(vsht_plan_t plan, int64_t count, const void *T, void *a, void *b,
+                              int flags, void *stream);
+vsht_status vsht_adjoint_many(vsht_plan_t plan, int64_t count, const void *a, const void *b, void *T,
+                              int flags, void *stream);
+
 /* Describe a plan (host-side; no device work). */
 vsht_status vsht_plan_info(vsht_plan_t plan, vsht_plan_info_t *info);
 

@@ -8,8 +8,19 @@ streams.
 """
 from ._binding import (EXPORTED, LIB_PATH, PRECISIONS, Plan, VshtError, load_library,
                        vsht_adjoint, vsht_forward, vsht_forward_unweighted, vsht_num_coeffs,
-                       vsht_plan, vsht_plan_destroy, vsht_plan_info)
+                       vsht_plan, vsht_plan_destroy, vsht_plan_info, vsht_forward_many,
+                       vsht_adjoint_many, VSHT_UNIT_WEIGHTS, VSHT_TIMES_WEIGHTS)
 
 __all__ = ["Plan", "VshtError", "load_library", "vsht_num_coeffs", "vsht_plan", "vsht_forward",
            "vsht_forward_unweighted", "vsht_adjoint", "vsht_plan_info", "vsht_plan_destroy",
-           "EXPORTED", "LIB_PATH", "PRECISIONS"]
+           "vsht_forward_many", "vsht_adjoint_many", "VSHT_UNIT_WEIGHTS", "VSHT_TIMES_WEIGHTS",
+           "EXPORTED", "LIB_PATH", "PRECISIONS", "AdjointVSHT", "ForwardVSHT", "adjoint_vsht",
+           "forward_vsht"]
+
+
+def __getattr__(name):
+    # the autograd functions import torch; load them on first use
+    if name in ("AdjointVSHT", "ForwardVSHT", "adjoint_vsht", "forward_vsht"):
+        from . import autograd
+        return getattr(autograd, name)
+    raise AttributeError(name)

@@ -20,7 +20,9 @@ PLAN_RINGS, PLAN_SCATTERED = 0, 1
 # every symbol include/vsht.h declares
 EXPORTED = ("vsht_num_coeffs", "vsht_plan", "vsht_forward", "vsht_forward_unweighted",
             "vsht_adjoint", "vsht_plan_info", "vsht_plan_destroy", "vsht_status_string",
-            "vsht_last_error", "vsht_set_stage_timing", "vsht_get_stage_times")
+            "vsht_last_error", "vsht_set_stage_timing", "vsht_get_stage_times",
+            "vsht_forward_many", "vsht_adjoint_many")
+VSHT_UNIT_WEIGHTS, VSHT_TIMES_WEIGHTS = 1, 2
 STAGES = ("ring_fwd", "leg_fwd", "recombine", "prep", "leg_adj", "ring_adj", "scattered")
 
 
@@ -64,6 +66,9 @@ def load_library(path=LIB_PATH):
         getattr(lib, name).restype = ci
     lib.vsht_adjoint.argtypes = [vp, vp, vp, vp, vp]
     lib.vsht_adjoint.restype = ci
+    for name in ("vsht_forward_many", "vsht_adjoint_many"):
+        getattr(lib, name).argtypes = [vp, i64, vp, vp, vp, ci, vp]
+        getattr(lib, name).restype = ci
     lib.vsht_plan_info.argtypes = [vp, ctypes.POINTER(vsht_plan_info_t)]
     lib.vsht_plan_info.restype = ci
     lib.vsht_plan_destroy.argtypes = [vp]
@@ -107,6 +112,14 @@ def vsht_forward_unweighted(plan, T_ptr, a_ptr, b_ptr, stream):
 
 def vsht_adjoint(plan, a_ptr, b_ptr, T_ptr, stream):
     return load_library().vsht_adjoint(plan, a_ptr, b_ptr, T_ptr, stream)
+
+
+def vsht_forward_many(plan, count, T_ptr, a_ptr, b_ptr, flags, stream):
+    return load_library().vsht_forward_many(plan, count, T_ptr, a_ptr, b_ptr, flags, stream)
+
+
+def vsht_adjoint_many(plan, count, a_ptr, b_ptr, T_ptr, flags, stream):
+    return load_library().vsht_adjoint_many(plan, count, a_ptr, b_ptr, T_ptr, flags, stream)
 
 
 def vsht_plan_info(plan, info):
@@ -204,6 +217,44 @@ class Plan:
             T = torch.empty((self.n, 3), dtype=self.dtype, device=self.device)
         _raise_for(vsht_adjoint(self._h, a.data_ptr(), b.data_ptr(), T.data_ptr(), self._stream()),
                    "vsht_adjoint")
+        return T
+
+    def _check_batch(self, t, tail, name):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a torch tensor" % name)
+        if t.device != self.device or t.dtype != self.dtype or tuple(t.shape[t.dim() - len(tail):]) != tail \
+                or t.dim() < len(tail):
+            raise ValueError("%s must be a %s tensor of shape (..., %s) on %s (got %s %s on %s)" % (
+                name, self.dtype, ", ".join(map(str, tail)), self.device, t.dtype, tuple(t.shape), t.device))
+        return t.contiguous()
+
+    def forward_many(self, T, unit_weights=False):
+        """Forward transform of every field of T (..., n, 3) -> a, b (..., K)."""
+        torch = _torch()
+        T = self._check_batch(T, (self.n, 3), "T")
+        lead = tuple(T.shape[:-2])
+        count = int(np.prod(lead)) if lead else 1
+        a = torch.empty(lead + (self.K,), dtype=self.dtype, device=self.device)
+        b = torch.empty_like(a)
+        _raise_for(vsht_forward_many(self._h, count, T.data_ptr(), a.data_ptr(), b.data_ptr(),
+                                     VSHT_UNIT_WEIGHTS if unit_weights else 0, self._stream()),
+                   "vsht_forward_many")
+        return a, b
+
+    def adjoint_many(self, a, b, times_weights=False):
+        """Adjoint transform of every coefficient block a, b (..., K) -> T (..., n, 3)."""
+        torch = _torch()
+        a = self._check_batch(a, (self.K,), "a")
+        b = self._check_batch(b, (self.K,), "b")
+        if a.shape != b.shape:
+            raise ValueError("a and b must have the same shape")
+        lead = tuple(a.shape[:-1])
+        count = int(np.prod(lead)) if lead else 1
+        T = torch.empty(lead + (self.n, 3), dtype=self.dtype, device=self.device)
+        _raise_for(vsht_adjoint_many(self._h, count, a.data_ptr(), b.data_ptr(), T.data_ptr(),
+                                     VSHT_TIMES_WEIGHTS if times_weights else 0, self._stream()),
+                   "vsht_adjoint_many")
         return T
 
     def set_stage_timing(self, enable):

@@ -391,6 +391,10 @@ vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w, cons
         P.kind = VSHT_PLAN_SCATTERED;
         std::vector<double> xv(xyz, xyz + 3 * n);
         if ((e = upload(&P.d_xyz, xv, &P.table_bytes)) != hipSuccess) goto hip_error;
+        if (w) {
+            std::vector<double> wv(w, w + n);
+            if ((e = upload(&P.d_weights, wv, &P.table_bytes)) != hipSuccess) goto hip_error;
+        }
         const size_t fg = (size_t)P.tri_size * 4 * 2 * rsz;
         if ((e = hipMalloc(&P.d_fg, fg)) != hipSuccess) goto hip_error;
         P.workspace_bytes = fg;
@@ -440,8 +444,54 @@ vsht_status vsht_adjoint(vsht_plan_t plan, const void *a, const void *b, void *T
     if (s != VSHT_OK) return s;
     const Plan &P = plan->p;
     DeviceGuard guard(P.device);
-    hipError_t e = launch_adjoint(P, a, b, T, (hipStream_t)stream);
+    hipError_t e = launch_adjoint(P, a, b, T, false, (hipStream_t)stream);
     return e == hipSuccess ? VSHT_OK : hip_fail(e, "adjoint launch");
+}
+
+static size_t complex_bytes(const Plan &P) { return P.precision == VSHT_FP64 ? 16 : 8; }
+
+vsht_status vsht_forward_many(vsht_plan_t plan, int64_t count, const void *T, void *a, void *b,
+                              int flags, void *stream) {
+    vsht_status s = check_call(plan, T, a, b);
+    if (s != VSHT_OK) return s;
+    const Plan &P = plan->p;
+    if (count < 0) return fail(VSHT_EINVAL, "count < 0");
+    if (flags & ~VSHT_UNIT_WEIGHTS) return fail(VSHT_EINVAL, "unknown flag for the forward transform");
+    const bool weighted = !(flags & VSHT_UNIT_WEIGHTS);
+    if (weighted && !P.has_weights) return fail(VSHT_ENOWEIGHTS, "forward needs a plan created with weights");
+    if (P.kind != VSHT_PLAN_RINGS)
+        return fail(VSHT_EUNSUPPORTED, "forward transform on a scattered point set");
+    DeviceGuard guard(P.device);
+    const size_t cb = complex_bytes(P);
+    const size_t t_stride = (size_t)P.n * 3 * cb, c_stride = (size_t)vsht_num_coeffs(P.L) * cb;
+    for (int64_t f = 0; f < count; ++f) {
+        hipError_t e = launch_forward(P, static_cast<const char *>(T) + f * t_stride,
+                                      static_cast<char *>(a) + f * c_stride,
+                                      static_cast<char *>(b) + f * c_stride, weighted, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "forward launch");
+    }
+    return VSHT_OK;
+}
+
+vsht_status vsht_adjoint_many(vsht_plan_t plan, int64_t count, const void *a, const void *b, void *T,
+                              int flags, void *stream) {
+    vsht_status s = check_call(plan, a, b, T);
+    if (s != VSHT_OK) return s;
+    const Plan &P = plan->p;
+    if (count < 0) return fail(VSHT_EINVAL, "count < 0");
+    if (flags & ~VSHT_TIMES_WEIGHTS) return fail(VSHT_EINVAL, "unknown flag for the adjoint transform");
+    const bool weighted = (flags & VSHT_TIMES_WEIGHTS) != 0;
+    if (weighted && !P.has_weights) return fail(VSHT_ENOWEIGHTS, "VSHT_TIMES_WEIGHTS needs a plan created with weights");
+    DeviceGuard guard(P.device);
+    const size_t cb = complex_bytes(P);
+    const size_t t_stride = (size_t)P.n * 3 * cb, c_stride = (size_t)vsht_num_coeffs(P.L) * cb;
+    for (int64_t f = 0; f < count; ++f) {
+        hipError_t e = launch_adjoint(P, static_cast<const char *>(a) + f * c_stride,
+                                      static_cast<const char *>(b) + f * c_stride,
+                                      static_cast<char *>(T) + f * t_stride, weighted, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+    }
+    return VSHT_OK;
 }
 
 vsht_status vsht_plan_info(vsht_plan_t plan, vsht_plan_info_t *info) {

@@ -142,6 +142,7 @@ __host__ __device__ inline int64_t tri_size(int L) { return tri_offset(L, L + 1)
 // Kernel launchers (vsht_kernels.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_forward(const Plan &p, const void *T, void *a, void *b, bool weighted,
                           hipStream_t st);
-hipError_t launch_adjoint(const Plan &p, const void *a, const void *b, void *T, hipStream_t st);
+hipError_t launch_adjoint(const Plan &p, const void *a, const void *b, void *T, bool weighted,
+                          hipStream_t st);
 
 }  // namespace vsht

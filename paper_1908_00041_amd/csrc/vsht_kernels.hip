@@ -466,8 +466,12 @@ __global__ __launch_bounds__(kRingNT, 2) void k_ring_adj(RingArgs<real> A) {
         const real c = (real)(rd.c0 * er - rd.s0 * ei);
         const real sn = (real)(rd.s0 * er + rd.c0 * ei);
         const real z = (real)rd.z, s = (real)rd.s;
-        const C2<real> th = buf[pad16(j)], ph = buf[pad16(n + j)];
+        C2<real> th = buf[pad16(j)], ph = buf[pad16(n + j)];
         const int64_t k = rd.offset + j;
+        if (A.weighted) {  // W S: the Hermitian transpose of the weighted analysis
+            const real w = (real)(rd.uniform_w ? rd.w : A.weights[k]);
+            th.x *= w; th.y *= w; ph.x *= w; ph.y *= w;
+        }
         A.Tout[3 * k] = {z * c * th.x - sn * ph.x, z * c * th.y - sn * ph.y};
         A.Tout[3 * k + 1] = {z * sn * th.x + c * ph.x, z * sn * th.y + c * ph.y};
         A.Tout[3 * k + 2] = {-s * th.x, -s * th.y};
@@ -943,8 +947,10 @@ struct ScatArgs {
     const double *aprime;
     const double *cscale;
     C2<real> *Tout;
+    const double *weights;  // per point; used when weighted != 0
     int64_t n;
     int L;
+    int weighted;
 };
 
 template <typename real>
@@ -1018,7 +1024,8 @@ __global__ __launch_bounds__(64) void k_adj_scattered(ScatArgs<real> A) {
         }
     }
     if (!valid) return;
-    const double inv_s = pole ? 1.0 : 1.0 / s;
+    double inv_s = pole ? 1.0 : 1.0 / s;
+    if (A.weighted) inv_s *= A.weights[k];
     thr *= inv_s; thi *= inv_s; phr *= inv_s; phi_ *= inv_s;
     // e_theta = (z c, z sn, -s), e_phi = (-sn, c, 0)
     A.Tout[3 * k] = {(real)(z * c * thr - sn * phr), (real)(z * c * thi - sn * phi_)};
@@ -1100,7 +1107,7 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
 }
 
 template <typename real>
-static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void *T,
+static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void *T, bool weighted,
                                hipStream_t st) {
     CoefArgs<real> C{};
     C.ain = static_cast<const C2<real> *>(a);
@@ -1125,8 +1132,10 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
         S.aprime = p.d_aprime;
         S.cscale = p.d_cscale;
         S.Tout = static_cast<C2<real> *>(T);
+        S.weights = p.d_weights;
         S.n = p.n;
         S.L = p.L;
+        S.weighted = weighted ? 1 : 0;
         StageScope sc(p, VSHT_STAGE_SCATTERED, st);
         hipLaunchKernelGGL(k_adj_scattered<real>, dim3((unsigned)((p.n + 63) / 64)), dim3(64), 0,
                            st, S);
@@ -1159,6 +1168,8 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
 
     RingArgs<real> R{};
     R.Tout = static_cast<C2<real> *>(T);
+    R.weights = p.d_weights;
+    R.weighted = weighted ? 1 : 0;
     R.buf = static_cast<C2<real> *>(p.d_pb);
     R.rings = p.d_rings;
     R.ffts = p.d_ffts;
@@ -1179,9 +1190,10 @@ hipError_t launch_forward(const Plan &p, const void *T, void *a, void *b, bool w
     return forward_impl<float>(p, T, a, b, weighted, st);
 }
 
-hipError_t launch_adjoint(const Plan &p, const void *a, const void *b, void *T, hipStream_t st) {
-    if (p.precision == VSHT_FP64) return adjoint_impl<double>(p, a, b, T, st);
-    return adjoint_impl<float>(p, a, b, T, st);
+hipError_t launch_adjoint(const Plan &p, const void *a, const void *b, void *T, bool weighted,
+                          hipStream_t st) {
+    if (p.precision == VSHT_FP64) return adjoint_impl<double>(p, a, b, T, weighted, st);
+    return adjoint_impl<float>(p, a, b, T, weighted, st);
 }
 
 hipError_t launch_seed_kernel(const double *pair_s, int NP, int L, double *seeds, hipStream_t st) {

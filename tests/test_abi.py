@@ -90,3 +90,10 @@ def test_status_strings():
     lib = v.load_library()
     for s in range(6):
         assert lib.vsht_status_string(s).decode().startswith("VSHT_")
+
+
+def test_many_null_arguments():
+    lib = v.load_library()
+    assert lib.vsht_forward_many(None, 1, None, None, None, 0, None) == B.VSHT_EINVAL
+    assert lib.vsht_adjoint_many(None, 1, None, None, None, 0, None) == B.VSHT_EINVAL
+    assert b"NULL" in lib.vsht_last_error()

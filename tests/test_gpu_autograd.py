@@ -1,0 +1,194 @@
+"""Differentiable transforms: torch.autograd Functions whose backward is the
+transposed transform (unit-weight forward for the adjoint, weighted adjoint
+for the forward).  Checked against torch.autograd.gradcheck (FP64), central
+finite differences of the least-squares loss at L=8 (FP64), and the oracle's
+gradient 2 S^H (S(a, b) - T_target) at L=64 (FP64 and FP32)."""
+import numpy as np
+import pytest
+
+import vsht_inputs as vi
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-11
+FP32_TOL = 2e-5
+
+
+def rel_l2(x, y):
+    x = np.asarray(x).ravel()
+    y = np.asarray(y).ravel()
+    return float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def vsht():
+    import paper_1908_00041_amd as v
+    v.load_library()
+    return v
+
+
+def dev(torch, x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dtype=dtype, device="cuda")
+
+
+def gl_plan(vsht, L, precision="fp64"):
+    xyz, w = vi.gl_grid(L)
+    return vsht.Plan(L, xyz, w, precision=precision), xyz, w
+
+
+def target_field(L, n_fields, xyz, seed_coef=4, seed_noise=5):
+    """T_target = Adj(a_t, b_t) + noise, Re/Im of the noise iid with variance 0.01."""
+    K = vi.num_coeffs(L)
+    a_t = np.empty((n_fields, K), complex)
+    b_t = np.empty((n_fields, K), complex)
+    for f in range(n_fields):
+        a_t[f], b_t[f] = vi.random_coeffs(L, seed_coef + 100 * f)
+    rng = np.random.default_rng(seed_noise)
+    noise = 0.1 * (rng.standard_normal((n_fields, len(xyz), 3)) +
+                   1j * rng.standard_normal((n_fields, len(xyz), 3)))
+    return a_t, b_t, noise
+
+
+def test_gradcheck_adjoint(torch, vsht):
+    print("[case] gradcheck AdjointVSHT L=3 fp64", flush=True)
+    plan, xyz, w = gl_plan(vsht, 3)
+    a, b = vi.random_coeffs(3, 11)
+    a = dev(torch, a, torch.complex128).requires_grad_()
+    b = dev(torch, b, torch.complex128).requires_grad_()
+    assert torch.autograd.gradcheck(lambda a, b: vsht.AdjointVSHT.apply(plan, a, b), (a, b),
+                                    eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+def test_gradcheck_forward(torch, vsht):
+    print("[case] gradcheck ForwardVSHT L=3 fp64", flush=True)
+    plan, xyz, w = gl_plan(vsht, 3)
+    T = dev(torch, vi.random_field(len(xyz), 12), torch.complex128).requires_grad_()
+    assert torch.autograd.gradcheck(lambda T: vsht.ForwardVSHT.apply(plan, T), (T,),
+                                    eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+def test_finite_differences_L8(torch, vsht):
+    """Central differences (h = 1e-6) of ||Adj(a,b) - T_target||^2 along random
+    complex directions vs the autograd directional derivative."""
+    print("[case] finite differences L=8 fp64", flush=True)
+    L = 8
+    plan, xyz, w = gl_plan(vsht, L)
+    a_t, b_t, noise = target_field(L, 1, xyz)
+    Tt = plan.adjoint_many(dev(torch, a_t, torch.complex128), dev(torch, b_t, torch.complex128))
+    Tt = Tt + dev(torch, noise, torch.complex128)
+    a0, b0 = vi.random_coeffs(L, 21)
+    a = dev(torch, a0, torch.complex128).requires_grad_()
+    b = dev(torch, b0, torch.complex128).requires_grad_()
+
+    def loss(a, b):
+        r = vsht.adjoint_vsht(plan, a, b) - Tt
+        return (r.real ** 2 + r.imag ** 2).sum()
+
+    l0 = loss(a, b)
+    ga, gb = torch.autograd.grad(l0, (a, b))
+    rng = np.random.default_rng(22)
+    h = 1e-6
+    for trial in range(4):
+        da = dev(torch, rng.standard_normal(a.shape) + 1j * rng.standard_normal(a.shape), torch.complex128)
+        db = dev(torch, rng.standard_normal(b.shape) + 1j * rng.standard_normal(b.shape), torch.complex128)
+        with torch.no_grad():
+            fd = (loss(a + h * da, b + h * db) - loss(a - h * da, b - h * db)).item() / (2 * h)
+        # directional derivative of a real loss: Re <grad, d>
+        an = (torch.sum(ga.conj() * da).real + torch.sum(gb.conj() * db).real).item()
+        print("[fd] trial %d fd %.12e autograd %.12e" % (trial, fd, an), flush=True)
+        assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_oracle_gradient_L64(torch, vsht, orc, precision, tol):
+    """grad_(a,b) ||S(a,b) - T_target||^2 = 2 S^H (S(a,b) - T_target), all in the oracle."""
+    print("[case] oracle gradient L=64", precision, flush=True)
+    L = 64
+    plan, xyz, w = gl_plan(vsht, L, precision)
+    a_t, b_t, noise = target_field(L, 1, xyz)
+    Tt = orc.adjoint(L, a_t[0], b_t[0], xyz) + noise[0]
+    a0, b0 = vi.random_coeffs(L, 31)
+    r = orc.adjoint(L, a0, b0, xyz) - Tt
+    ga_ref, gb_ref = orc.forward(L, xyz, np.ones(len(xyz)), r)
+    ga_ref, gb_ref = 2 * ga_ref, 2 * gb_ref
+
+    cdt = plan.dtype
+    a = dev(torch, a0, cdt).requires_grad_()
+    b = dev(torch, b0, cdt).requires_grad_()
+    Ttd = dev(torch, Tt, cdt)
+    res = vsht.adjoint_vsht(plan, a, b) - Ttd
+    loss = (res.real ** 2 + res.imag ** 2).sum()
+    loss.backward()
+    g = np.concatenate([a.grad.cpu().numpy(), b.grad.cpu().numpy()]).astype(complex)
+    err = rel_l2(g, np.concatenate([ga_ref, gb_ref]))
+    print("[err] oracle gradient L=64 %s rel_l2 %.3e" % (precision, err), flush=True)
+    assert err <= tol
+
+
+def test_forward_backward_is_weighted_adjoint(torch, vsht, orc):
+    """ForwardVSHT's backward: grad_T = w * S(ga, gb), vs the oracle (L=16, FP64)."""
+    print("[case] forward backward L=16", flush=True)
+    L = 16
+    plan, xyz, w = gl_plan(vsht, L)
+    T0 = vi.random_field(len(xyz), 41)
+    ga, gb = vi.random_coeffs(L, 42)
+    T = dev(torch, T0, torch.complex128).requires_grad_()
+    a, b = vsht.forward_vsht(plan, T)
+    a.backward(dev(torch, ga, torch.complex128), retain_graph=True)
+    gT_a = T.grad.cpu().numpy().copy()
+    T.grad = None
+    b.backward(dev(torch, gb, torch.complex128))
+    gT_b = T.grad.cpu().numpy()
+    ref_a = w[:, None] * orc.adjoint(L, ga, np.zeros_like(gb), xyz)
+    ref_b = w[:, None] * orc.adjoint(L, np.zeros_like(ga), gb, xyz)
+    assert rel_l2(gT_a, ref_a) <= FP64_TOL
+    assert rel_l2(gT_b, ref_b) <= FP64_TOL
+
+
+def test_batched_fields_match_single(torch, vsht, orc):
+    """A batch of fields through the *_many calls equals the fields one by one,
+    and the weighted adjoint equals w times the oracle adjoint."""
+    print("[case] batch of 3 fields L=24 fp64", flush=True)
+    L = 24
+    plan, xyz, w = gl_plan(vsht, L)
+    K = vi.num_coeffs(L)
+    A = np.stack([vi.random_coeffs(L, 50 + f)[0] for f in range(3)])
+    Bc = np.stack([vi.random_coeffs(L, 50 + f)[1] for f in range(3)])
+    Tb = plan.adjoint_many(dev(torch, A, torch.complex128), dev(torch, Bc, torch.complex128))
+    Tw = plan.adjoint_many(dev(torch, A, torch.complex128), dev(torch, Bc, torch.complex128),
+                           times_weights=True)
+    a2, b2 = plan.forward_many(Tb)
+    torch.cuda.synchronize()
+    for f in range(3):
+        Tref = orc.adjoint(L, A[f], Bc[f], xyz)
+        assert rel_l2(Tb[f].cpu().numpy(), Tref) <= FP64_TOL
+        assert rel_l2(Tw[f].cpu().numpy(), w[:, None] * Tref) <= FP64_TOL
+        assert rel_l2(a2[f].cpu().numpy(), A[f]) <= FP64_TOL
+        assert rel_l2(b2[f].cpu().numpy(), Bc[f]) <= FP64_TOL
+    # count = 0 is a no-op; invalid flags are rejected
+    from paper_1908_00041_amd import _binding as B
+    st = B.vsht_forward_many(plan._h, 0, Tb.data_ptr(), a2.data_ptr(), b2.data_ptr(), 0, None)
+    assert st == B.VSHT_OK
+    st = B.vsht_forward_many(plan._h, 1, Tb.data_ptr(), a2.data_ptr(), b2.data_ptr(), 2, None)
+    assert st == B.VSHT_EINVAL
+
+
+def test_scattered_weighted_adjoint(torch, vsht, orc):
+    print("[case] scattered weighted adjoint L=12", flush=True)
+    L = 12
+    xyz, w = vi.uniform_points(300, 7)
+    w = w * (1.0 + 0.5 * np.random.default_rng(8).random(len(w)))
+    plan = vsht.Plan(L, xyz, w)
+    assert plan.kind == "scattered"
+    a, b = vi.random_coeffs(L, 9)
+    T = plan.adjoint_many(dev(torch, a, torch.complex128), dev(torch, b, torch.complex128),
+                          times_weights=True)
+    assert rel_l2(T.cpu().numpy(), w[:, None] * orc.adjoint(L, a, b, xyz)) <= FP64_TOL

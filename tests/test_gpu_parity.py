@@ -174,3 +174,28 @@ def test_gl_L256_sampled_fp64(torch, vsht, orc):
     # exact quadrature: forward(adjoint) recovers every coefficient
     ga, gb = run_forward(torch, plan, T)
     assert rel_l2(np.concatenate([ga, gb]), np.concatenate([a, b])) < FP64_TOL
+
+
+# ---------------------------------------------------------------------------
+# L = 1024 on the GL grid 1025 x 2050 in the launch configuration the
+# benchmark times (one plan, adjoint then forward on the current stream):
+# sampled outputs against the oracle, and the exact round trip at full size.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_gl_L1024_sampled(torch, vsht, orc, precision, tol):
+    L = 1024
+    print_case("gl sampled", L, precision)
+    xyz, w = vi.gl_grid(L)
+    a, b = vi.random_coeffs(L, 0)
+    plan = vsht.Plan(L, xyz, w, precision=precision)
+    T = run_adjoint(torch, plan, a, b)
+    pidx = vi.sample_indices(len(w), 48, 3)
+    e_adj = rel_l2(T[pidx], orc.adjoint(L, a, b, xyz[pidx]))
+    # forward of the GPU's own synthesis vs the oracle forward of the same field
+    cidx = vi.sample_indices(L * (L + 2), 48, 4)
+    ga, gb = run_forward(torch, plan, T)
+    sa, sb = orc.forward_subset(L, xyz, w, T, cidx)
+    e_fwd = rel_l2(np.concatenate([ga[cidx], gb[cidx]]), np.concatenate([sa, sb]))
+    e_rt = rel_l2(np.concatenate([ga, gb]), np.concatenate([a, b]))
+    print("L=1024 %s adjoint %.3e forward %.3e roundtrip %.3e" % (precision, e_adj, e_fwd, e_rt))
+    assert e_adj < tol and e_fwd < tol and e_rt < tol
