@@ -48,7 +48,9 @@ def measured_traffic(kernel, prec, L):
         return None
     if rec.get("kernel_source_sha256") != digest or rec.get("L") != L:
         return None
-    v = rec.get("bytes_per_launch", {}).get("%s<%s>" % (kernel, "double" if prec == "fp64" else "float"))
+    table = rec.get("bytes_per_launch", {})
+    v = table.get(kernel) if kernel in table else \
+        table.get("%s<%s>" % (kernel, "double" if prec == "fp64" else "float"))
     return None if v is None else int(v)
 
 
@@ -101,7 +103,7 @@ def main():
     ap.add_argument("--oracle-coeffs", type=int, default=1024)
     ap.add_argument("--oracle-points", type=int, default=512)
     ap.add_argument("--no-oracle", action="store_true")
-    ap.add_argument("--precisions", default="fp64,fp32")
+    ap.add_argument("--precisions", default="fp64,fp32,bf16x3")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -195,22 +197,42 @@ def main():
             r["err_fwd"] = rel_l2(np.concatenate([r["fa"], r["fb"]]), np.concatenate([oa, ob]))
 
     def roofline(prec, r):
-        # dominant kernel: the larger Legendre stage.  Algorithmic work = 16 flops per
-        # (m >= 0, m <= l' <= L+1, ring pair) element: 8 real multiply-adds (theta/phi x
-        # +-m x re/im) against one Legendre value.  Both stages run on 16x16x4 MFMA
-        # whose column half of the other parity is wasted, so 100% MFMA busy is 50%.
+        # Dominant kernel of the step and its algorithmic work per launch.
+        # Legendre stages: 16 flops per (m >= 0, m <= l' <= L+1, ring pair) element,
+        # i.e. 8 real multiply-adds (theta/phi x +-m x re/im) against one Legendre
+        # value; BF16x3 performs each of them as 3 bf16 products, so its algorithmic
+        # count is 3 x 16 per element against the bf16 MFMA peak.  Ring stages: HBM
+        # bytes of the field (n x 3 complex) plus the ring-Fourier buffer.
         st = r["stages"]
-        dom = max(("leg_fwd", "leg_adj"), key=lambda k: st.get(k, 0.0))
+        dom = max(st, key=lambda k: st[k])
         t = st[dom] * 1e-3
-        E = folded_elements(L, r["info"]["n_pairs"])
-        flops = 16.0 * E
-        peak = FP64_MFMA_TFLOPS if prec == "fp64" else FP32_MFMA_TFLOPS
-        ach = flops / t / 1e12
-        kern = "k_leg_adj_mfma" if dom == "leg_adj" else "k_leg_fwd_mfma"
-        return {"bound": "mfma", "kernel": kern, "achieved": round(ach, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(ach / peak, 4),
-                "traffic": measured_traffic(kern, prec, L),
-                "launch_us": round(st[dom] * 1e3, 2), "flops_per_launch": flops}
+        info = r["info"]
+        cs = 16 if prec == "fp64" else 8
+        kern_names = {"leg_fwd": "k_leg_fwd_mfma", "leg_adj": "k_leg_adj_mfma",
+                      "ring_fwd": "k_ring_fwd", "ring_adj": "k_ring_adj",
+                      "recombine": "k_recombine", "prep": "k_prep"}
+        if prec == "bf16x3":
+            kern_names.update(leg_fwd="k_leg_fwd_bf16x3", leg_adj="k_leg_adj_bf16x3")
+        kern = kern_names.get(dom, dom)
+        out = {"kernel": kern, "launch_us": round(st[dom] * 1e3, 2)}
+        if dom in ("leg_fwd", "leg_adj"):
+            E = folded_elements(L, info["n_pairs"])
+            flops = (48.0 if prec == "bf16x3" else 16.0) * E
+            peak = {"fp64": FP64_MFMA_TFLOPS, "fp32": FP32_MFMA_TFLOPS}.get(prec, BF16_MFMA_TFLOPS)
+            ach = flops / t / 1e12
+            out.update(bound="mfma", achieved=round(ach, 3), peak=peak, unit="TFLOP/s",
+                       frac=round(ach / peak, 4), flops_per_launch=flops)
+        else:
+            nbuf = (L + 1) * (info["n_rings"] * 4 if dom == "ring_fwd" else info["n_pairs"] * 8)
+            if dom in ("ring_fwd", "ring_adj"):
+                by = (3 * N + nbuf) * cs
+            else:  # coefficient stages: 2K coefficients and the (L+2)-row triangle
+                by = (2 * K + 4 * (L + 1) * (L + 4) // 2) * cs
+            ach = by / t / 1e9
+            out.update(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                       frac=round(ach / HBM_PEAK_GBS, 4), bytes_per_launch=by)
+        out["traffic"] = measured_traffic(kern, prec, L)
+        return out
 
     main_r = results.get("fp64") or next(iter(results.values()))
     main_prec = "fp64" if "fp64" in results else next(iter(results))
@@ -226,7 +248,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if main_prec == "fp64" else "f32",
+        "dtype": {"fp64": "f64", "fp32": "f32"}.get(main_prec, "bf16x3/f32"),
         "data": "synthetic",
         "config": {"workload": "forward+adjoint VSHT, Gauss-Legendre grid %dx%d (%d points), "
                                "L=%d, random coefficients scaled 1/l, seed 0" % (L + 1, 2 * L + 2, N, L),

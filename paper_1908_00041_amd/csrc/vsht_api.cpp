@@ -186,7 +186,6 @@ vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w, cons
         if (w && !std::isfinite(w[k]))
             return fail(VSHT_EINVAL, "non-finite weight at index " + std::to_string(k));
     }
-    if (precision == VSHT_BF16X3) return fail(VSHT_EUNSUPPORTED, "bf16x3 not built yet");
 
     int dev = 0;
     if (opts && opts->device >= 0) {
@@ -254,6 +253,9 @@ vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w, cons
             cprev1 = cl;
         }
     }
+    // the kernels read a' in whole blocks of up to 32 degrees and mask the
+    // entries beyond L+1, so the table carries 32 zeros of padding
+    aprime.resize(aprime.size() + 32, 0.0);
     if ((e = upload(&P.d_aprime, aprime, &P.table_bytes)) != hipSuccess) goto hip_error;
     if ((e = upload(&P.d_cscale, cscale, &P.table_bytes)) != hipSuccess) goto hip_error;
     {
@@ -326,6 +328,12 @@ vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w, cons
             }
             pairs.push_back(pd);
         }
+        // pairs in order of increasing sin(theta): the first tile of 64 pairs is
+        // the one nearest the poles, which the reduced-precision syntheses
+        // compute one precision wider
+        std::stable_sort(pairs.begin(), pairs.end(), [&](const PairDesc &x, const PairDesc &y) {
+            return rings[x.rn].s < rings[y.rn].s;
+        });
         // the ring at z = 0 (if any) goes last: its Legendre values are known in
         // closed form and the kernels treat it separately
         for (size_t q = 0; q < pairs.size(); ++q)

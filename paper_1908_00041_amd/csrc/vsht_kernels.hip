@@ -713,21 +713,16 @@ struct LegArgs {
     int NPT;              // pairs handled by the tiles (the equator, if any, is pair NPT)
 };
 
-template <typename real>
-__global__ __launch_bounds__(256) void k_leg_adj_mfma(LegArgs<real> A) {
+// One wave: pairs [64 tile, 64 tile + 64) of order m, computed in `real`, with
+// FG read and PB written in `store` (binary32 storage with binary64 arithmetic
+// serves the polar tile of the binary32 path).
+template <typename real, typename store>
+__device__ __forceinline__ void adj_tile_mfma(const LegArgs<store> &A, int m, int tile, int lane,
+                                              real *qt) {
     typedef typename Mfma<real>::acc_t acc_t;
-    extern __shared__ unsigned char smem_raw[];
-    const int L = A.L, NP = A.NP;
-    const int m = blockIdx.y;
-    const int nw = blockDim.x >> 6;
-    const int wave = uniform_int(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int NPT = A.NPT;
-    const int tile = blockIdx.x * nw + wave;
-    if (tile * kTileP >= NPT) return;  // whole wave idle (no barriers below)
-    real *qt = reinterpret_cast<real *>(smem_raw) + wave * kRowsB * kTileP;
+    const int L = A.L, NP = A.NP, NPT = A.NPT;
     const int64_t t0 = tri_offset(L, m);
-    const real *g = A.FG + (t0 - m) * 8;  // indexed by l'
+    const store *g = A.FG + (t0 - m) * 8;  // indexed by l'
     const int p = tile * kTileP + lane;
     const bool valid = p < NPT;
     const double z = valid ? A.pz[p] : 0.0;
@@ -748,7 +743,7 @@ __global__ __launch_bounds__(256) void k_leg_adj_mfma(LegArgs<real> A) {
 #pragma unroll
         for (int gg = 0; gg < 4; ++gg) {
             const int lp = lp0 + 4 * gg + k;
-            bv[gg] = (lp <= L + 1 && (j >> 3) == (k & 1)) ? g[(int64_t)lp * 8 + (j & 7)] : (real)0;
+            bv[gg] = (lp <= L + 1 && (j >> 3) == (k & 1)) ? (real)g[(int64_t)lp * 8 + (j & 7)] : (real)0;
         }
         recur16<real, SwzAdj>(qt, areg, z, q1, q2, lane);
 #pragma unroll
@@ -767,9 +762,40 @@ __global__ __launch_bounds__(256) void k_leg_adj_mfma(LegArgs<real> A) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int pp = tile * kTileP + 16 * b + Mfma<real>::row(lane, r);
-            if (pp < NPT) A.PB[((size_t)m * NP + pp) * 16 + j] = acc[b][r];
+            if (pp < NPT) A.PB[((size_t)m * NP + pp) * 16 + j] = (store)acc[b][r];
         }
     }
+}
+
+// Bytes of LDS per wave of the synthesis kernels (the largest tile any path uses).
+constexpr int kAdjLdsPerWave = kRowsB * kTileP * 8;
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_leg_adj_mfma(LegArgs<real> A) {
+    extern __shared__ unsigned char smem_raw[];
+    const int nw = blockDim.x >> 6;
+    const int wave = uniform_int(threadIdx.x >> 6);
+    const int tile = blockIdx.x * nw + wave;
+    if (tile * kTileP >= A.NPT) return;  // whole wave idle (no barriers below)
+    real *qt = reinterpret_cast<real *>(smem_raw) + wave * kRowsB * kTileP;
+    adj_tile_mfma<real, real>(A, blockIdx.y, tile, threadIdx.x & 63, qt);
+}
+
+// Binary32 synthesis whose first tile (the 64 ring pairs nearest the poles:
+// pairs are sorted by increasing sin(theta)) runs in binary64.  The
+// spin-frame form divides the synthesised sums by sin(theta), which there
+// amplifies the rounding of the contraction by up to 1/sin(theta) ~ L.
+__global__ __launch_bounds__(256) void k_leg_adj_fp32_polar64(LegArgs<float> A) {
+    extern __shared__ unsigned char smem_raw[];
+    const int nw = blockDim.x >> 6;
+    const int wave = uniform_int(threadIdx.x >> 6);
+    const int tile = blockIdx.x * nw + wave;
+    if (tile * kTileP >= A.NPT) return;
+    unsigned char *lds = smem_raw + wave * kAdjLdsPerWave;
+    if (tile == 0)
+        adj_tile_mfma<double, float>(A, blockIdx.y, tile, threadIdx.x & 63, reinterpret_cast<double *>(lds));
+    else
+        adj_tile_mfma<float, float>(A, blockIdx.y, tile, threadIdx.x & 63, reinterpret_cast<float *>(lds));
 }
 
 // ---------------------------------------------------------------------------
@@ -799,6 +825,257 @@ __global__ __launch_bounds__(64) void k_equator_adj(LegArgs<real> A) {
         o[c] = (real)A.seeds[(size_t)m * NP + A.NPT] * acc;
         o[8 + c] = 0;
     }
+}
+
+// ---------------------------------------------------------------------------
+// BF16x3 Legendre stages.  A binary32 operand x is split as x = hi + lo + r
+// with hi = bf16(x), lo = bf16(x - hi) (round to nearest, |r| <= 2^-17 |x|),
+// and a product as hi*hi' + hi*lo' + lo*hi' on the 16x16x32 bf16 MFMA with
+// binary32 accumulation; the dropped lo*lo' term is below 2^-16 relative.
+// The Legendre recurrence, its seeds and its scaling stay binary64.
+// Operand layouts of v_mfma_f32_16x16x32_bf16 (measured on gfx950): lane l
+// holds A[row l%16][k 8(l/16)+t] and B[k 8(l/16)+t][col l%16], t = 0..7, and
+// D register r of lane l is [row 4(l/16)+r][col l%16].
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+struct Split8 {
+    bf16x8_t hi, lo;
+};
+
+// hi/lo split of two values, each result packed as two bf16 in 32 bits
+__device__ __forceinline__ void split2(float a, float b, uint32_t &hi, uint32_t &lo) {
+    const f32x2_t v = {a, b};
+    hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+    const float ha = __builtin_bit_cast(float, hi << 16);
+    const float hb = __builtin_bit_cast(float, hi & 0xffff0000u);
+    const f32x2_t r = {a - ha, b - hb};
+    lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2_t));
+}
+
+__device__ __forceinline__ Split8 split8(const float (&v)[8]) {
+    u32x4_t h, l;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        uint32_t hi, lo;
+        split2(v[2 * i], v[2 * i + 1], hi, lo);
+        h[i] = hi;
+        l[i] = lo;
+    }
+    return {__builtin_bit_cast(bf16x8_t, h), __builtin_bit_cast(bf16x8_t, l)};
+}
+
+__device__ __forceinline__ f32x4 mma3(const Split8 &a, const Split8 &b, f32x4 acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, acc, 0, 0, 0);
+}
+
+// a'_{lp0+s}, s < N, as wave-uniform values (scalar loads); entries beyond
+// L+1 read the table's padding or the next order's entries and are zeroed.
+template <int N>
+__device__ __forceinline__ void load_aprime(const double *__restrict__ ap, int lp0, int Lp1, double (&a)[N]) {
+#pragma unroll
+    for (int s = 0; s < N; ++s) a[s] = ap[lp0 + s];
+#pragma unroll
+    for (int s = 0; s < N; ++s)
+        if (lp0 + s > Lp1) a[s] = 0.0;
+}
+
+// Q tile of the analysis: [16 degrees][64 pairs] binary32 whose groups of 8
+// pairs are XOR-ed with the row, so that the 8 consecutive pairs one lane
+// reads stay contiguous and the 16 rows read together start in different banks.
+struct SwzFwd8 {
+    static __device__ __forceinline__ int at(int row, int pair) {
+        return row * kTileP + ((((pair >> 3) ^ (row & 7)) << 3) | (pair & 7));
+    }
+};
+
+// Analysis, BF16x3: as k_leg_fwd_mfma<float> (same grid, reduction and
+// epilogue) with the wave's 64-pair block contracted as two K = 32 chunks.
+__global__ __launch_bounds__(1024) void k_leg_fwd_bf16x3(LegFwdArgs<float> A) {
+    extern __shared__ unsigned char smem_raw[];
+    const int L = A.L, NP = A.NP, NPT = A.NPT, NR = A.NR;
+    const int m = blockIdx.x;
+    const int nw = blockDim.x >> 6;
+    const int wave = uniform_int(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int tile = blockIdx.y * nw + wave;
+    float *qt = reinterpret_cast<float *>(smem_raw) + wave * kRowsB * kTileP;
+    float *red = reinterpret_cast<float *>(smem_raw) + nw * kRowsB * kTileP;  // [2][nw][128]
+    const int64_t t0 = tri_offset(L, m);
+    const float *RBm = A.RB + (size_t)m * NR * 8;
+
+    // B: lane (j + 16kg) holds X[pair 32c + 8kg + t][column j] of chunk c
+    const int j = lane & 15, kg = lane >> 4;
+    Split8 bx[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        float v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int pp = tile * kTileP + 32 * c + 8 * kg + t;
+            float x = 0.f;
+            if (pp < NPT) {
+                const PairDesc pd = A.pairs[pp];
+                const float xn = RBm[(size_t)pd.rn * 8 + (j & 7)];
+                const float xs = pd.rs >= 0 ? RBm[(size_t)pd.rs * 8 + (j & 7)] : 0.f;
+                x = j < 8 ? xn + xs : xn - xs;
+            }
+            v[t] = x;
+        }
+        bx[c] = split8(v);
+    }
+    const int p = tile * kTileP + lane;
+    const bool valid = p < NPT;
+    const double z = valid ? A.pz[p] : 0.0;
+    double q1 = 0.0, q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+    const double seq = A.eq_ring >= 0 ? A.seeds[(size_t)m * NP + NPT] : 0.0;
+    const float *xeq = A.eq_ring >= 0 ? RBm + (size_t)A.eq_ring * 8 : nullptr;
+    const double *ap = A.aprime + t0 - m;  // indexed by l'
+    const int nl = L + 2 - m;
+    const int nblk = (nl + kRowsB - 1) / kRowsB;
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int lp0 = m + blk * kRowsB;
+        double ab[kRowsB];
+        load_aprime(ap, lp0, L + 1, ab);
+#pragma unroll
+        for (int s = 0; s < kRowsB; ++s) {
+            const double v = fma(ab[s] * z, q1, -q2);
+            qt[SwzFwd8::at(s, lane)] = (float)v;
+            q2 = q1;
+            q1 = v;
+        }
+        __builtin_amdgcn_wave_barrier();
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const float4 *src = reinterpret_cast<const float4 *>(qt + SwzFwd8::at(j, 32 * c + 8 * kg));
+            const float4 u0 = src[0], u1 = src[1];
+            const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+            acc = mma3(split8(v), bx[c], acc);
+        }
+        __builtin_amdgcn_wave_barrier();
+        float *rw = red + ((blk & 1) * nw + wave) * 128;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (FwdCompact<float>::valid(lane, r)) rw[FwdCompact<float>::slot(lane, r)] = acc[r];
+        __syncthreads();
+        for (int o = threadIdx.x; o < 128; o += blockDim.x) {
+            int row, col;
+            FwdCompact<float>::rc(o, row, col);
+            const int lp = lp0 + row;
+            if (lp <= L + 1) {
+                const float *rb = red + (blk & 1) * nw * 128;
+                float sum = 0.f;
+                for (int w = 0; w < nw; ++w) sum += rb[w * 128 + o];
+                const int64_t ti = t0 + lp - m;
+                if (xeq && col < 8 && blockIdx.y == 0) {
+                    const int kk = (lp - m) >> 1;
+                    const double qe = (kk & 1) ? -seq : seq;
+                    sum += (float)qe * xeq[col];
+                }
+                const float v = (float)A.cscale[ti] * sum;
+                if (A.atomic)
+                    atomicAdd(&A.F[ti * 8 + (col & 7)], v);
+                else
+                    A.F[ti * 8 + (col & 7)] = v;
+            }
+        }
+    }
+}
+
+// Synthesis, BF16x3: one wave per 64 ring pairs as k_leg_adj_mfma, degrees in
+// blocks of 32 (one K = 32 chunk).  Each lane advances the recurrence of its
+// own pair and writes that pair's 32 values, already split, as one row of the
+// wave's hi and lo tiles ([64 pairs][32 degrees] bf16, 16-byte slot q of pair
+// p stored at slot q ^ ((p >> 2) & 3) so that 16 lanes of a row group hit
+// distinct banks).
+constexpr int kRowsA = 32;
+
+__device__ __forceinline__ void adj_tile_bf16x3(const LegArgs<float> &A, int m, int tile, int lane,
+                                                u32x4_t *th) {
+    const int L = A.L, NP = A.NP;
+    const int NPT = A.NPT;
+    u32x4_t *tl = th + kTileP * 4;
+    const int64_t t0 = tri_offset(L, m);
+    const float *g = A.FG + (t0 - m) * 8;    // indexed by l'
+    const double *ap = A.aprime + t0 - m;    // indexed by l'
+    const int p = tile * kTileP + lane;
+    const bool valid = p < NPT;
+    const double z = valid ? A.pz[p] : 0.0;
+    double q1 = 0.0, q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+    const int j = lane & 15, kg = lane >> 4;
+    f32x4 acc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int nl = L + 2 - m;
+    const int nblk = (nl + kRowsA - 1) / kRowsA;
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int lp0 = m + blk * kRowsA;
+        // B: lane (j + 16kg) holds g[l' = lp0 + 8kg + t][j & 7] when the parity
+        // of l' - m (= t & 1) matches the column half j / 8, else 0
+        float bv[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int lp = lp0 + 8 * kg + t;
+            bv[t] = (lp <= L + 1 && (t & 1) == (j >> 3)) ? g[(int64_t)lp * 8 + (j & 7)] : 0.f;
+        }
+        const Split8 bs = split8(bv);
+        uint32_t hq[16], lq[16];
+        double ab[kRowsA];
+        load_aprime(ap, lp0, L + 1, ab);
+#pragma unroll
+        for (int s = 0; s < kRowsA; s += 2) {
+            const double v0 = fma(ab[s] * z, q1, -q2);
+            const double v1 = fma(ab[s + 1] * z, v0, -q1);
+            q2 = v0;
+            q1 = v1;
+            split2((float)v0, (float)v1, hq[s >> 1], lq[s >> 1]);
+        }
+        const int sw = (lane >> 2) & 3;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            th[lane * 4 + (q ^ sw)] = u32x4_t{hq[4 * q], hq[4 * q + 1], hq[4 * q + 2], hq[4 * q + 3]};
+            tl[lane * 4 + (q ^ sw)] = u32x4_t{lq[4 * q], lq[4 * q + 1], lq[4 * q + 2], lq[4 * q + 3]};
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            // A: lane (j + 16kg) holds Q[pair 16b + j][degrees lp0 + 8kg .. + 7]
+            const int P = 16 * b + j;
+            const int slot = P * 4 + (kg ^ ((P >> 2) & 3));
+            const Split8 qa = {__builtin_bit_cast(bf16x8_t, th[slot]), __builtin_bit_cast(bf16x8_t, tl[slot])};
+            acc[b] = mma3(qa, bs, acc[b]);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int pp = tile * kTileP + 16 * b + 4 * kg + r;
+            if (pp < NPT) A.PB[((size_t)m * NP + pp) * 16 + j] = acc[b][r];
+        }
+    }
+}
+
+// BF16x3 synthesis; the polar tile (see k_leg_adj_fp32_polar64) runs on the
+// binary32 MFMA path.
+__global__ __launch_bounds__(256) void k_leg_adj_bf16x3(LegArgs<float> A) {
+    extern __shared__ unsigned char smem_raw[];
+    const int nw = blockDim.x >> 6;
+    const int wave = uniform_int(threadIdx.x >> 6);
+    const int tile = blockIdx.x * nw + wave;
+    if (tile * kTileP >= A.NPT) return;
+    unsigned char *lds = smem_raw + wave * kAdjLdsPerWave;
+    if (tile == 0)
+        adj_tile_mfma<float, float>(A, blockIdx.y, tile, threadIdx.x & 63, reinterpret_cast<float *>(lds));
+    else
+        adj_tile_bf16x3(A, blockIdx.y, tile, threadIdx.x & 63, reinterpret_cast<u32x4_t *>(lds));
 }
 
 // ---------------------------------------------------------------------------
@@ -1086,7 +1363,15 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
             if (e != hipSuccess) return e;
         }
         const size_t lds2 = (size_t)nw * (kRowsB * kTileP + 2 * 128) * sizeof(real);
-        hipLaunchKernelGGL(k_leg_fwd_mfma<real>, dim3(p.L + 1, ngroup), dim3(nw * 64), lds2, st, G);
+        if constexpr (sizeof(real) == 4) {
+            if (p.precision == VSHT_BF16X3) {
+                hipLaunchKernelGGL(k_leg_fwd_bf16x3, dim3(p.L + 1, ngroup), dim3(nw * 64), lds2, st, G);
+            } else {
+                hipLaunchKernelGGL(k_leg_fwd_mfma<real>, dim3(p.L + 1, ngroup), dim3(nw * 64), lds2, st, G);
+            }
+        } else {
+            hipLaunchKernelGGL(k_leg_fwd_mfma<real>, dim3(p.L + 1, ngroup), dim3(nw * 64), lds2, st, G);
+        }
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1156,9 +1441,17 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
         const int ntile = (G.NPT + kTileP - 1) / kTileP;
         if (ntile > 0) {
             const int nw = ntile < 4 ? ntile : 4;
-            const size_t lds2 = (size_t)nw * kRowsB * kTileP * sizeof(real);
-            hipLaunchKernelGGL(k_leg_adj_mfma<real>, dim3((ntile + nw - 1) / nw, p.L + 1),
-                               dim3(nw * 64), lds2, st, G);
+            const dim3 grid((ntile + nw - 1) / nw, p.L + 1);
+            const size_t lds2 = (size_t)nw * (sizeof(real) == 4 ? kAdjLdsPerWave : kRowsB * kTileP * sizeof(real));
+            if constexpr (sizeof(real) == 4) {
+                if (p.precision == VSHT_BF16X3)
+                    hipLaunchKernelGGL(k_leg_adj_bf16x3, grid, dim3(nw * 64), lds2, st, G);
+                else
+                    hipLaunchKernelGGL(k_leg_adj_mfma<real>, grid, dim3(nw * 64),
+                                       (size_t)nw * kRowsB * kTileP * sizeof(real), st, G);
+            } else {
+                hipLaunchKernelGGL(k_leg_adj_mfma<real>, grid, dim3(nw * 64), lds2, st, G);
+            }
         }
         if (p.eq_ring >= 0)
             hipLaunchKernelGGL(k_equator_adj<real>, dim3(p.L + 1), dim3(64), 0, st, G);
@@ -1217,6 +1510,12 @@ hipError_t set_kernel_attributes() {
     e = hipFuncSetAttribute((const void *)k_leg_fwd_mfma<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_leg_adj_mfma<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_leg_fwd_bf16x3, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_leg_adj_bf16x3, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_leg_adj_fp32_polar64, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void *)k_leg_adj_mfma<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }

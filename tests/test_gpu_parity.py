@@ -14,6 +14,10 @@ pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-11
 FP32_TOL = 2e-5
+# BF16x3: each operand x = hi + lo + r with |lo| <= 2^-9 |x| and |r| <= 2^-18 |x|;
+# the dropped terms of one product (lo lo', r y, x r') are at most 3 * 2^-18
+# = 1.1e-5 relative, and a round trip passes through two contractions.
+BF16X3_TOL = 3e-5
 
 
 def rel_l2(x, y):
@@ -154,6 +158,21 @@ def test_gl_fp32(torch, vsht, orc, L):
     assert e_adj < FP32_TOL and e_fwd < FP32_TOL
 
 
+@pytest.mark.parametrize("L", [1, 16, 64])
+def test_gl_bf16x3(torch, vsht, orc, L):
+    print_case("gl bf16x3", L)
+    xyz, w = vi.gl_grid(L)
+    a, b = vi.random_coeffs(L, 0)
+    plan = vsht.Plan(L, xyz, w, precision="bf16x3")
+    T_ref = orc.adjoint(L, a, b, xyz)
+    T = run_adjoint(torch, plan, a, b)
+    e_adj = rel_l2(T, T_ref)
+    ga, gb = run_forward(torch, plan, T_ref)
+    e_fwd = rel_l2(np.concatenate([ga, gb]), np.concatenate([a, b]))
+    print("bf16x3 L=%d adjoint rel-L2 %.3e forward rel-L2 %.3e" % (L, e_adj, e_fwd))
+    assert e_adj < BF16X3_TOL and e_fwd < BF16X3_TOL
+
+
 # ---------------------------------------------------------------------------
 # L = 256 on the GL grid 257 x 514: sampled outputs
 # ---------------------------------------------------------------------------
@@ -181,7 +200,8 @@ def test_gl_L256_sampled_fp64(torch, vsht, orc):
 # benchmark times (one plan, adjoint then forward on the current stream):
 # sampled outputs against the oracle, and the exact round trip at full size.
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL),
+                                           ("bf16x3", BF16X3_TOL)])
 def test_gl_L1024_sampled(torch, vsht, orc, precision, tol):
     L = 1024
     print_case("gl sampled", L, precision)
