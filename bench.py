@@ -88,6 +88,102 @@ def stage_profile(torch, plan, a, b, reps):
     return {k: (ms / c if c else 0.0) for k, (ms, c) in st.items() if c}
 
 
+def run_batched(torch, vsht, vi, args):
+    """Many fields of uneven bandlimit, each on its own GL grid (L+1) x (2L+2), complex64,
+    coefficients scaled 1/l: adjoint then forward of every field, one graph replay."""
+    dev = torch.device("cuda", 0)
+    Ls = [int(L) for L in vi.batch_bandlimits(args.batch_fields, seed=1)]
+    log("batch: %d fields, L in [%d, %d], mean %.1f" % (len(Ls), min(Ls), max(Ls), np.mean(Ls)))
+    grids = [vi.gl_grid(L) for L in Ls]
+    t0 = time.perf_counter()
+    bp = vsht.BatchPlan(Ls, grids, precision="fp32")
+    t_plan = time.perf_counter() - t0
+    rng_seeds = [1000 + f for f in range(len(Ls))]
+    coeffs = [vi.random_coeffs(L, sd) for L, sd in zip(Ls, rng_seeds)]
+    a = [torch.from_numpy(c[0]).to(dev, torch.complex64) for c in coeffs]
+    b = [torch.from_numpy(c[1]).to(dev, torch.complex64) for c in coeffs]
+    T, a2, b2 = bp.empty_fields(), bp.empty_coeffs(), bp.empty_coeffs()
+    tuned_ms = bp.autotune(a, b, T, a2, b2, reps=3)
+    cfg = bp.config()
+    log("batch: autotuned %s (%.3f ms)" % (cfg, tuned_ms))
+    for _ in range(args.warmup):
+        bp.roundtrip(a, b, T, a2, b2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bp.roundtrip(a, b, T, a2, b2)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    s0, s1 = bp.field_times()
+    lat = s1 - s0
+    # errors of four fields against single-field FP64 plans on the GPU
+    errs = []
+    for f in sorted(set([0, int(np.argmax(Ls)), int(np.argmin(Ls)), len(Ls) // 2])):
+        xyz, w = grids[f]
+        p = vsht.Plan(Ls[f], xyz, w, precision="fp64")
+        T64 = p.adjoint(torch.from_numpy(coeffs[f][0]).to(dev), torch.from_numpy(coeffs[f][1]).to(dev))
+        torch.cuda.synchronize()
+        errs.append(rel_l2(T[f].cpu().numpy().astype(np.complex128), T64.cpu().numpy()))
+        errs.append(rel_l2(np.concatenate([a2[f].cpu().numpy(), b2[f].cpu().numpy()]).astype(np.complex128),
+                           np.concatenate(coeffs[f])))
+        p.close()
+    bp.close()
+    log("batch: %.3f ms per batch, %.0f fields/s" % (sec * 1e3, len(Ls) / sec))
+    return {"fields": len(Ls), "L_min": min(Ls), "L_max": max(Ls), "L_mean": round(float(np.mean(Ls)), 1),
+            "precision": "fp32", "ms_per_batch": round(sec * 1e3, 4),
+            "fields_per_s": round(len(Ls) / sec, 1),
+            "latency_us_p50": round(float(np.percentile(lat, 50)), 1),
+            "latency_us_p99": round(float(np.percentile(lat, 99)), 1),
+            "autotuned": cfg, "plan_s": round(t_plan, 2),
+            "max_rel_l2_vs_fp64_single": max(errs),
+            "note": "adjoint then forward of every field per replay; latency = first work item start to "
+                    "last work item end of each field (device wall clock)"}
+
+
+def run_differentiable(torch, vsht, vi, args):
+    """Loss ||Adj(a, b) - T_target||^2 over a batch of fields at L=512 (GL 513 x 1026), FP32;
+    one step = the transform and its backward (the unit-weight forward)."""
+    dev = torch.device("cuda", 0)
+    L, F = 512, args.grad_fields
+    xyz, w = vi.gl_grid(L)
+    plan = vsht.Plan(L, xyz, w, precision="fp32")
+    K = L * (L + 2)
+    at = np.stack([vi.random_coeffs(L, 4 + 100 * f)[0] for f in range(F)])
+    bt = np.stack([vi.random_coeffs(L, 4 + 100 * f)[1] for f in range(F)])
+    Tt = plan.adjoint_many(torch.from_numpy(at).to(dev, torch.complex64),
+                           torch.from_numpy(bt).to(dev, torch.complex64))
+    rng = np.random.default_rng(5)
+    noise = 0.1 * (rng.standard_normal((F, len(w), 3)) + 1j * rng.standard_normal((F, len(w), 3)))
+    Tt = Tt + torch.from_numpy(noise).to(dev, torch.complex64)
+    a0 = np.stack([vi.random_coeffs(L, 31 + f)[0] for f in range(F)])
+    b0 = np.stack([vi.random_coeffs(L, 31 + f)[1] for f in range(F)])
+    a = torch.from_numpy(a0).to(dev, torch.complex64).requires_grad_()
+    b = torch.from_numpy(b0).to(dev, torch.complex64).requires_grad_()
+
+    def step():
+        a.grad = None
+        b.grad = None
+        r = vsht.adjoint_vsht(plan, a, b) - Tt
+        loss = (r.real ** 2 + r.imag ** 2).sum()
+        loss.backward()
+        return loss
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    plan.close()
+    log("differentiable: %.3f ms per step (%d fields, L=%d)" % (sec * 1e3, F, L))
+    return {"fields": F, "L": L, "precision": "fp32", "ms_per_step": round(sec * 1e3, 4),
+            "fields_per_s": round(F / sec, 1),
+            "note": "loss = ||Adj(a,b) - T_target||^2 summed over fields; step = adjoint of every field, "
+                    "loss, and backward through the unit-weight forward kernels"}
+
+
 def rel_l2(x, y):
     x = np.asarray(x).ravel()
     y = np.asarray(y).ravel()
@@ -104,6 +200,10 @@ def main():
     ap.add_argument("--oracle-points", type=int, default=512)
     ap.add_argument("--no-oracle", action="store_true")
     ap.add_argument("--precisions", default="fp64,fp32,bf16x3")
+    ap.add_argument("--batch-fields", type=int, default=256,
+                    help="batched workload: this many complex64 fields, L uniform in [32, 512] (0: skip)")
+    ap.add_argument("--grad-fields", type=int, default=8,
+                    help="differentiable workload: this many fields at L=512, FP32 (0: skip)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -157,6 +257,13 @@ def main():
                              plan_s=t_plan, info=info)
         del T, a2, b2, ga, gb
         plan.close()
+
+    batched = None
+    if args.batch_fields > 0:
+        batched = run_batched(torch, vsht, vi, args)
+    differentiable = None
+    if args.grad_fields > 0:
+        differentiable = run_differentiable(torch, vsht, vi, args)
 
     if args.copy_mb > 0:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the
@@ -276,6 +383,10 @@ def main():
         variants[prec] = v
     if variants:
         out["variants"] = variants
+    if batched:
+        out["batched"] = batched
+    if differentiable:
+        out["differentiable"] = differentiable
     print(json.dumps(out), flush=True)
 
 

@@ -81,7 +81,7 @@ typedef struct {
 } vsht_opts;
 
 /* Plan kinds reported by vsht_plan_info. */
-typedef enum { VSHT_PLAN_RINGS = 0, VSHT_PLAN_SCATTERED = 1 } vsht_plan_kind;
+typedef enum { VSHT_PLAN_RINGS = 0, VSHT_PLAN_SCATTERED = 1, VSHT_PLAN_BATCH = 2 } vsht_plan_kind;
 
 typedef struct {
     int L;
@@ -172,6 +172,55 @@ typedef enum {
  * written (at most VSHT_NUM_STAGES).  Disabling drops pending records. */
 vsht_status vsht_set_stage_timing(vsht_plan_t plan, int enable);
 vsht_status vsht_get_stage_times(vsht_plan_t plan, double *ms, int64_t *count, int nstages);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many independent fields, each with its own bandlimit L[f] and its
+ * own iso-latitude ring grid (xyz[f], n[f] points, weights w[f]), one
+ * precision for all.  Every stage of the transforms of eq. (SLvec) and eq.
+ * (fwdvsht2) runs as one launch covering all fields (work items of the larger
+ * fields first), and the launches of a call are captured once into a HIP graph
+ * and replayed.  The per-field arrays a, b, T, a2, b2 are host arrays of
+ * nfields device pointers (layouts as for single plans).  When a call passes
+ * different buffers than the previous one, the library uploads the new
+ * addresses and waits for `stream` once; calls with the same buffers only
+ * replay the graph.  A batch plan must not run on two streams at the same
+ * time.  The single-plan calls return VSHT_EINVAL on a batch plan.
+ *
+ * vsht_plan_batch   nfields >= 1; every field must be a ring grid with
+ *                   weights (else VSHT_EINVAL / VSHT_EUNSUPPORTED, with the
+ *                   field named in vsht_last_error).
+ * vsht_batch_adjoint    a[f], b[f] -> T[f]   (eq. (SLvec))
+ * vsht_batch_forward    T[f] -> a[f], b[f]   (eq. (fwdvsht2))
+ * vsht_batch_roundtrip  a[f], b[f] -> T[f], then T[f] -> a2[f], b2[f], one graph.
+ * vsht_batch_set_config / get_config   launch shape: adj_nw (1, 2 or 4 tiles
+ *                   of 64 ring pairs per synthesis workgroup), fwd_merge (1: one
+ *                   analysis launch at the widest workgroup; 0: one per tile
+ *                   count), lpt (1: longest work items first), ring_nt (256 or
+ *                   512 threads per ring workgroup; rings whose DFT is longer
+ *                   than 2048 always take 512).  Results do not depend on the
+ *                   shape.  Waits for the device.
+ * vsht_batch_autotune  times every shape on the caller's buffers (roundtrip,
+ *                   `reps` replays each), keeps the fastest and writes its time
+ *                   per roundtrip in milliseconds to *best_ms (may be NULL).
+ *                   Synchronous; overwrites T, a2, b2.
+ * vsht_batch_field_times  per field, the device wall-clock time (microseconds,
+ *                   from the earliest start in the batch) when its first work
+ *                   item of the last call started and its last work item
+ *                   ended; arrays of nfields.  Waits for the device.
+ * ------------------------------------------------------------------------- */
+vsht_status vsht_plan_batch(int nfields, const int *L, const int64_t *n, const double *const *xyz,
+                            const double *const *w, const vsht_opts *opts, vsht_plan_t *out);
+vsht_status vsht_batch_adjoint(vsht_plan_t plan, const void *const *a, const void *const *b, void *const *T,
+                               void *stream);
+vsht_status vsht_batch_forward(vsht_plan_t plan, const void *const *T, void *const *a, void *const *b,
+                               void *stream);
+vsht_status vsht_batch_roundtrip(vsht_plan_t plan, const void *const *a, const void *const *b, void *const *T,
+                                 void *const *a2, void *const *b2, void *stream);
+vsht_status vsht_batch_set_config(vsht_plan_t plan, int adj_nw, int fwd_merge, int lpt, int ring_nt);
+vsht_status vsht_batch_get_config(vsht_plan_t plan, int *adj_nw, int *fwd_merge, int *lpt, int *ring_nt);
+vsht_status vsht_batch_autotune(vsht_plan_t plan, const void *const *a, const void *const *b, void *const *T,
+                                void *const *a2, void *const *b2, int reps, double *best_ms, void *stream);
+vsht_status vsht_batch_field_times(vsht_plan_t plan, double *start_us, double *end_us);
 
 /* Release a plan and everything it owns (waits for the device first).
  * Passing NULL is allowed and returns VSHT_OK. */

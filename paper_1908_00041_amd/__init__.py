@@ -6,12 +6,12 @@ include/vsht.h (libvsht.so, built in-tree by ``paper_1908_00041_amd.build``);
 this package only marshals arguments.  PyTorch provides device memory and
 streams.
 """
-from ._binding import (EXPORTED, LIB_PATH, PRECISIONS, Plan, VshtError, load_library,
+from ._binding import (EXPORTED, LIB_PATH, PRECISIONS, BatchPlan, Plan, VshtError, load_library,
                        vsht_adjoint, vsht_forward, vsht_forward_unweighted, vsht_num_coeffs,
                        vsht_plan, vsht_plan_destroy, vsht_plan_info, vsht_forward_many,
                        vsht_adjoint_many, VSHT_UNIT_WEIGHTS, VSHT_TIMES_WEIGHTS)
 
-__all__ = ["Plan", "VshtError", "load_library", "vsht_num_coeffs", "vsht_plan", "vsht_forward",
+__all__ = ["Plan", "BatchPlan", "VshtError", "load_library", "vsht_num_coeffs", "vsht_plan", "vsht_forward",
            "vsht_forward_unweighted", "vsht_adjoint", "vsht_plan_info", "vsht_plan_destroy",
            "vsht_forward_many", "vsht_adjoint_many", "VSHT_UNIT_WEIGHTS", "VSHT_TIMES_WEIGHTS",
            "EXPORTED", "LIB_PATH", "PRECISIONS", "AdjointVSHT", "ForwardVSHT", "adjoint_vsht",

@@ -15,13 +15,15 @@ LIB_PATH = os.path.join(HERE, "libvsht.so")
 
 VSHT_OK, VSHT_EINVAL, VSHT_ENOWEIGHTS, VSHT_ENOMEM, VSHT_EDEVICE, VSHT_EUNSUPPORTED = range(6)
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
-PLAN_RINGS, PLAN_SCATTERED = 0, 1
+PLAN_RINGS, PLAN_SCATTERED, PLAN_BATCH = 0, 1, 2
 
 # every symbol include/vsht.h declares
 EXPORTED = ("vsht_num_coeffs", "vsht_plan", "vsht_forward", "vsht_forward_unweighted",
             "vsht_adjoint", "vsht_plan_info", "vsht_plan_destroy", "vsht_status_string",
             "vsht_last_error", "vsht_set_stage_timing", "vsht_get_stage_times",
-            "vsht_forward_many", "vsht_adjoint_many")
+            "vsht_forward_many", "vsht_adjoint_many", "vsht_plan_batch", "vsht_batch_adjoint",
+            "vsht_batch_forward", "vsht_batch_roundtrip", "vsht_batch_set_config",
+            "vsht_batch_get_config", "vsht_batch_autotune", "vsht_batch_field_times")
 VSHT_UNIT_WEIGHTS, VSHT_TIMES_WEIGHTS = 1, 2
 STAGES = ("ring_fwd", "leg_fwd", "recombine", "prep", "leg_adj", "ring_adj", "scattered")
 
@@ -69,6 +71,25 @@ def load_library(path=LIB_PATH):
     for name in ("vsht_forward_many", "vsht_adjoint_many"):
         getattr(lib, name).argtypes = [vp, i64, vp, vp, vp, ci, vp]
         getattr(lib, name).restype = ci
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    pd = ctypes.POINTER(ctypes.c_double)
+    pi = ctypes.POINTER(ctypes.c_int)
+    lib.vsht_plan_batch.argtypes = [ci, pi, ctypes.POINTER(i64), pp, pp, ctypes.POINTER(vsht_opts),
+                                    ctypes.POINTER(vp)]
+    lib.vsht_plan_batch.restype = ci
+    for name in ("vsht_batch_adjoint", "vsht_batch_forward"):
+        getattr(lib, name).argtypes = [vp, pp, pp, pp, vp]
+        getattr(lib, name).restype = ci
+    lib.vsht_batch_roundtrip.argtypes = [vp, pp, pp, pp, pp, pp, vp]
+    lib.vsht_batch_roundtrip.restype = ci
+    lib.vsht_batch_set_config.argtypes = [vp, ci, ci, ci, ci]
+    lib.vsht_batch_set_config.restype = ci
+    lib.vsht_batch_get_config.argtypes = [vp, pi, pi, pi, pi]
+    lib.vsht_batch_get_config.restype = ci
+    lib.vsht_batch_autotune.argtypes = [vp, pp, pp, pp, pp, pp, ci, pd, vp]
+    lib.vsht_batch_autotune.restype = ci
+    lib.vsht_batch_field_times.argtypes = [vp, pd, pd]
+    lib.vsht_batch_field_times.restype = ci
     lib.vsht_plan_info.argtypes = [vp, ctypes.POINTER(vsht_plan_info_t)]
     lib.vsht_plan_info.restype = ci
     lib.vsht_plan_destroy.argtypes = [vp]
@@ -268,6 +289,153 @@ class Plan:
         cnt = (ctypes.c_int64 * n)()
         _raise_for(load_library().vsht_get_stage_times(self._h, ms, cnt, n), "vsht_get_stage_times")
         return {STAGES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().vsht_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr_array(tensors):
+    return (ctypes.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
+
+
+class BatchPlan:
+    """Many independent fields, field f with bandlimit Ls[f] on its own ring grid
+    grids[f] = (points (n_f, 3), weights (n_f,)); one precision for all.
+
+    Each call runs every stage as one launch over all fields, replayed from a
+    HIP graph on the current torch stream.  Tensors are lists with one entry
+    per field (complex128 for 'fp64', complex64 otherwise).
+    """
+
+    def __init__(self, Ls, grids, precision="fp64", device=None):
+        torch = _torch()
+        lib = load_library()
+        if precision not in PRECISIONS:
+            raise ValueError("precision must be one of %s" % sorted(PRECISIONS))
+        F = len(Ls)
+        if F != len(grids) or F == 0:
+            raise ValueError("need one grid per bandlimit")
+        pts = [np.ascontiguousarray(g[0], dtype=np.float64).reshape(-1, 3) for g in grids]
+        wts = [np.ascontiguousarray(g[1], dtype=np.float64).reshape(-1) for g in grids]
+        for p_, w_ in zip(pts, wts):
+            if len(p_) != len(w_):
+                raise ValueError("weights must have one entry per point")
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = torch.device("cuda", int(device))
+        self.precision = precision
+        self.dtype = torch.complex128 if precision == "fp64" else torch.complex64
+        self.Ls = [int(L) for L in Ls]
+        self.ns = [len(p_) for p_ in pts]
+        self.Ks = [int(lib.vsht_num_coeffs(L)) for L in self.Ls]
+        Larr = (ctypes.c_int * F)(*self.Ls)
+        narr = (ctypes.c_int64 * F)(*self.ns)
+        xarr = (ctypes.c_void_p * F)(*[p_.ctypes.data for p_ in pts])
+        warr = (ctypes.c_void_p * F)(*[w_.ctypes.data for w_ in wts])
+        opts = vsht_opts(PRECISIONS[precision], int(device))
+        h = ctypes.c_void_p()
+        st = lib.vsht_plan_batch(F, Larr, narr, xarr, warr, ctypes.byref(opts), ctypes.byref(h))
+        _raise_for(st, "vsht_plan_batch")
+        self._h = h
+
+    def __len__(self):
+        return len(self.Ls)
+
+    def _stream(self):
+        return _torch().cuda.current_stream(self.device).cuda_stream
+
+    def _check(self, ts, shapes, name):
+        torch = _torch()
+        if len(ts) != len(self.Ls):
+            raise ValueError("%s: need one tensor per field" % name)
+        out = []
+        for t, shp in zip(ts, shapes):
+            if not isinstance(t, torch.Tensor) or t.device != self.device or t.dtype != self.dtype \
+                    or tuple(t.shape) != shp:
+                raise ValueError("%s: every entry must be a %s tensor on %s of its field's shape"
+                                 % (name, self.dtype, self.device))
+            out.append(t.contiguous())
+        return out
+
+    def empty_coeffs(self):
+        torch = _torch()
+        return [torch.empty(K, dtype=self.dtype, device=self.device) for K in self.Ks]
+
+    def empty_fields(self):
+        torch = _torch()
+        return [torch.empty((n, 3), dtype=self.dtype, device=self.device) for n in self.ns]
+
+    def adjoint(self, a, b, T=None):
+        cs = [(K,) for K in self.Ks]
+        a, b = self._check(a, cs, "a"), self._check(b, cs, "b")
+        T = self.empty_fields() if T is None else self._check(T, [(n, 3) for n in self.ns], "T")
+        self._keep = (a, b, T)
+        _raise_for(load_library().vsht_batch_adjoint(self._h, _ptr_array(a), _ptr_array(b), _ptr_array(T),
+                                                     self._stream()), "vsht_batch_adjoint")
+        return T
+
+    def forward(self, T, a=None, b=None):
+        T = self._check(T, [(n, 3) for n in self.ns], "T")
+        a = self.empty_coeffs() if a is None else self._check(a, [(K,) for K in self.Ks], "a")
+        b = self.empty_coeffs() if b is None else self._check(b, [(K,) for K in self.Ks], "b")
+        self._keep = (T, a, b)
+        _raise_for(load_library().vsht_batch_forward(self._h, _ptr_array(T), _ptr_array(a), _ptr_array(b),
+                                                     self._stream()), "vsht_batch_forward")
+        return a, b
+
+    def _rt_args(self, a, b, T, a2, b2):
+        cs = [(K,) for K in self.Ks]
+        a, b = self._check(a, cs, "a"), self._check(b, cs, "b")
+        T = self.empty_fields() if T is None else self._check(T, [(n, 3) for n in self.ns], "T")
+        a2 = self.empty_coeffs() if a2 is None else self._check(a2, cs, "a2")
+        b2 = self.empty_coeffs() if b2 is None else self._check(b2, cs, "b2")
+        return a, b, T, a2, b2
+
+    def roundtrip(self, a, b, T=None, a2=None, b2=None):
+        """Adjoint a, b -> T, then forward T -> a2, b2, as one graph replay."""
+        a, b, T, a2, b2 = self._rt_args(a, b, T, a2, b2)
+        self._keep = (a, b, T, a2, b2)
+        _raise_for(load_library().vsht_batch_roundtrip(
+            self._h, _ptr_array(a), _ptr_array(b), _ptr_array(T), _ptr_array(a2), _ptr_array(b2),
+            self._stream()), "vsht_batch_roundtrip")
+        return T, a2, b2
+
+    def autotune(self, a, b, T=None, a2=None, b2=None, reps=3):
+        """Time every launch shape on these buffers, keep the fastest; returns its ms per roundtrip."""
+        a, b, T, a2, b2 = self._rt_args(a, b, T, a2, b2)
+        self._keep = (a, b, T, a2, b2)
+        best = ctypes.c_double()
+        _raise_for(load_library().vsht_batch_autotune(
+            self._h, _ptr_array(a), _ptr_array(b), _ptr_array(T), _ptr_array(a2), _ptr_array(b2),
+            int(reps), ctypes.byref(best), self._stream()), "vsht_batch_autotune")
+        return best.value
+
+    def config(self):
+        x, y, z, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _raise_for(load_library().vsht_batch_get_config(self._h, ctypes.byref(x), ctypes.byref(y),
+                                                        ctypes.byref(z), ctypes.byref(r)),
+                   "vsht_batch_get_config")
+        return {"adj_nw": x.value, "fwd_merge": y.value, "lpt": z.value, "ring_nt": r.value}
+
+    def set_config(self, adj_nw=4, fwd_merge=0, lpt=1, ring_nt=256):
+        _raise_for(load_library().vsht_batch_set_config(self._h, int(adj_nw), int(fwd_merge), int(lpt),
+                                                        int(ring_nt)), "vsht_batch_set_config")
+
+    def field_times(self):
+        """(start_us, end_us) per field of the last call, device wall clock."""
+        F = len(self.Ls)
+        t0 = (ctypes.c_double * F)()
+        t1 = (ctypes.c_double * F)()
+        _raise_for(load_library().vsht_batch_field_times(self._h, t0, t1), "vsht_batch_field_times")
+        return np.array(t0[:]), np.array(t1[:])
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

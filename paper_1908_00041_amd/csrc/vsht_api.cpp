@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -15,11 +16,6 @@
 #include <vector>
 
 #include "vsht_internal.h"
-
-namespace vsht {
-hipError_t launch_seed_kernel(const double *pair_s, int NP, int L, double *seeds, hipStream_t st);
-hipError_t set_kernel_attributes();
-}  // namespace vsht
 
 using namespace vsht;
 
@@ -72,7 +68,8 @@ void free_plan_memory(Plan *p) {
         if (q) (void)hipFree(q);
 }
 
-// Factor n for the Stockham stages: radix 4 first, then 2, then odd primes ascending.
+// Factor n for the Stockham stages: the largest prime above 5 (if any) first,
+// where the stage needs no twiddles, then radix 4, 2 and the odd primes ascending.
 std::vector<int> factorize(int n) {
     std::vector<int> f;
     while (n % 4 == 0) { f.push_back(4); n /= 4; }
@@ -80,7 +77,118 @@ std::vector<int> factorize(int n) {
     for (int p = 3; (long)p * p <= n; p += 2)
         while (n % p == 0) { f.push_back(p); n /= p; }
     if (n > 1) f.push_back(n);
+    auto big = std::max_element(f.begin(), f.end());
+    if (big != f.end() && *big > 5) std::rotate(f.begin(), big, big + 1);
     return f;
+}
+
+// Largest prime the odd-radix Stockham stage handles; longer prime factors go
+// through Bluestein's convolution (for n <= kMaxBluesteinN).
+constexpr int kMaxGenericRadix = 64;
+constexpr int kMaxBluesteinN = 2048;
+
+// In-place DFT (sign -1) of a power-of-two length, extended precision.
+void host_fft_pow2(std::vector<std::complex<long double>> &x) {
+    const size_t M = x.size();
+    for (size_t i = 1, j = 0; i < M; ++i) {
+        size_t bit = M >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(x[i], x[j]);
+    }
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (size_t len = 2; len <= M; len <<= 1) {
+        for (size_t i = 0; i < M; i += len)
+            for (size_t k = 0; k < len / 2; ++k) {
+                const long double ang = -2.0L * pi * (long double)k / (long double)len;
+                const std::complex<long double> w(cosl(ang), sinl(ang));
+                const auto u = x[i + k], v = x[i + k + len / 2] * w;
+                x[i + k] = u + v;
+                x[i + k + len / 2] = u - v;
+            }
+    }
+}
+
+void push_twiddles(int n, std::vector<double> &tw) {
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (int k = 0; k < n; ++k) {
+        const long double a = -two_pi * (long double)k / (long double)n;
+        tw.push_back((double)cosl(a));
+        tw.push_back((double)sinl(a));
+    }
+}
+
+// Index of the descriptor for DFT length n (created, with its tables, on first use).
+int fft_descriptor(int n, std::map<int, int> &index, std::vector<FftDesc> &ffts, std::vector<double> &tw) {
+    auto it = index.find(n);
+    if (it != index.end()) return it->second;
+    FftDesc fd{};
+    fd.n = n;
+    std::vector<int> f = factorize(n);
+    const int pmax = f.empty() ? 1 : *std::max_element(f.begin(), f.end());
+    if (pmax > kMaxGenericRadix && n <= kMaxBluesteinN) {
+        int M = 1;
+        while (M < 2 * n - 1) M <<= 1;
+        fd.blue = 1;
+        fd.M = M;
+        fd.mdesc = fft_descriptor(M, index, ffts, tw);  // may reallocate ffts
+        // the ring stages take e^{i phi_j} from the length-n table as well
+        fd.tw_offset = (int64_t)(tw.size() / 2);
+        push_twiddles(n, tw);
+        const long double pi = 3.141592653589793238462643383279502884L;
+        std::vector<std::complex<long double>> w(n);
+        for (int k = 0; k < n; ++k) {
+            const long long k2 = ((long long)k * k) % (2LL * n);  // exact angle reduction
+            const long double a = -pi * (long double)k2 / (long double)n;
+            w[k] = std::complex<long double>(cosl(a), sinl(a));
+        }
+        fd.chirp_offset = (int64_t)(tw.size() / 2);
+        for (int k = 0; k < n; ++k) {
+            tw.push_back((double)w[k].real());
+            tw.push_back((double)w[k].imag());
+        }
+        fd.bhat_offset = (int64_t)(tw.size() / 2);
+        for (int dir = 0; dir < 2; ++dir) {  // kernel conj(w) (forward), then w (inverse)
+            std::vector<std::complex<long double>> b(M, 0.0L);
+            for (int k = 0; k < n; ++k) {
+                const auto v = dir == 0 ? std::conj(w[k]) : w[k];
+                b[k] = v;
+                if (k > 0) b[M - k] = v;
+            }
+            host_fft_pow2(b);
+            for (int k = 0; k < M; ++k) {
+                tw.push_back((double)(b[k].real() / M));
+                tw.push_back((double)(b[k].imag() / M));
+            }
+        }
+    } else {
+        fd.nfac = (int)f.size();
+        for (size_t q = 0; q < f.size(); ++q) fd.fac[q] = f[q];
+        fd.tw_offset = (int64_t)(tw.size() / 2);
+        push_twiddles(n, tw);
+    }
+    const int id = (int)ffts.size();
+    ffts.push_back(fd);
+    index.emplace(n, id);
+    return id;
+}
+
+// Whether every stage of the DFT `fd` fits a workgroup of nt threads under the
+// kernels' per-thread work limits (the same dispatch rules as fft_core).
+bool fft_fits(const FftDesc &fd, const std::vector<FftDesc> &ffts, int nt) {
+    if (fd.blue) return fft_fits(ffts[fd.mdesc], ffts, nt);
+    const int n = fd.n;
+    for (int f = 0; f < fd.nfac; ++f) {
+        const int R = fd.fac[f];
+        const int nb = n / R, half = (R - 1) / 2;
+        if (f == 0 && R > 5 && R <= kSmallTab && 2 * nb * ((half + kKP1 - 1) / kKP1) <= nt) continue;
+        if (R <= 5) {
+            if ((nb + nt - 1) / nt > kMaxItemsSmall) return false;
+        } else if (nb * ((half + kKP - 1) / kKP) > kMaxItemsOdd * nt) {
+            return false;
+        }
+    }
+    return true;
 }
 
 struct RingScan {
@@ -139,41 +247,14 @@ RingScan scan_rings(int64_t n, const double *xyz, const double *w) {
     return rs;
 }
 
-}  // namespace
-
-struct vsht_plan_s {
-    Plan p;
-};
-
-extern "C" {
-
-int64_t vsht_num_coeffs(int L) { return L >= 1 ? (int64_t)L * (L + 2) : 0; }
-
-const char *vsht_status_string(vsht_status s) {
-    switch (s) {
-        case VSHT_OK: return "VSHT_OK";
-        case VSHT_EINVAL: return "VSHT_EINVAL: invalid argument";
-        case VSHT_ENOWEIGHTS: return "VSHT_ENOWEIGHTS: plan has no quadrature weights";
-        case VSHT_ENOMEM: return "VSHT_ENOMEM: out of memory";
-        case VSHT_EDEVICE: return "VSHT_EDEVICE: HIP error";
-        case VSHT_EUNSUPPORTED: return "VSHT_EUNSUPPORTED: not supported for this plan";
-    }
-    return "unknown vsht_status";
-}
-
-const char *vsht_last_error(void) { return g_last_error.c_str(); }
-
-vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w, const vsht_opts *opts,
-                      vsht_plan_t *out) {
-    g_last_error.clear();
-    if (!out) return fail(VSHT_EINVAL, "out is NULL");
-    *out = nullptr;
+// Validate the arguments of one plan (Section 4.1: a quadrature rule has N >= 2
+// nodes; every point a unit vector).
+vsht_status check_plan_args(int L, int64_t n, const double *xyz, const double *w, int precision) {
     if (L < 1) return fail(VSHT_EINVAL, "L must be >= 1");
     if (L > 65535) return fail(VSHT_EINVAL, "L too large");
     if (n < 1) return fail(VSHT_EINVAL, "n must be >= 1");
     if (w && n < 2) return fail(VSHT_EINVAL, "a quadrature rule needs n >= 2 points");
     if (!xyz) return fail(VSHT_EINVAL, "xyz is NULL");
-    const int precision = opts ? opts->precision : VSHT_FP64;
     if (precision != VSHT_FP64 && precision != VSHT_FP32 && precision != VSHT_BF16X3)
         return fail(VSHT_EINVAL, "unknown precision");
     for (int64_t k = 0; k < n; ++k) {
@@ -187,24 +268,28 @@ vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w, cons
             return fail(VSHT_EINVAL, "non-finite weight at index " + std::to_string(k));
     }
 
-    int dev = 0;
+    return VSHT_OK;
+}
+
+vsht_status resolve_device(const vsht_opts *opts, int *dev) {
+    *dev = 0;
     if (opts && opts->device >= 0) {
-        dev = opts->device;
+        *dev = opts->device;
     } else {
-        hipError_t e = hipGetDevice(&dev);
+        hipError_t e = hipGetDevice(dev);
         if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     }
-    DeviceGuard guard(dev);
-    {
-        static std::once_flag attr_once;
-        static hipError_t attr_err = hipSuccess;
-        std::call_once(attr_once, [] { attr_err = set_kernel_attributes(); });
-        if (attr_err != hipSuccess) return hip_fail(attr_err, "hipFuncSetAttribute");
-    }
+    DeviceGuard guard(*dev);
+    static std::once_flag attr_once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(attr_once, [] { attr_err = set_kernel_attributes(); });
+    if (attr_err != hipSuccess) return hip_fail(attr_err, "hipFuncSetAttribute");
+    return VSHT_OK;
+}
 
-    auto *h = new (std::nothrow) vsht_plan_s();
-    if (!h) return fail(VSHT_ENOMEM, "host allocation");
-    Plan &P = h->p;
+// Build the tables and workspace of one plan on the current device.
+vsht_status build_plan(Plan &P, int L, int64_t n, const double *xyz, const double *w, int precision,
+                       int dev) {
     P.L = L;
     P.precision = precision;
     P.device = dev;
@@ -281,25 +366,21 @@ vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w, cons
         std::vector<FftDesc> ffts;
         std::vector<double> tw;
         for (auto &r : rings) {
-            auto it = fft_index.find(r.nphi);
-            if (it == fft_index.end()) {
-                FftDesc fd{};
-                fd.n = r.nphi;
-                std::vector<int> f = factorize(r.nphi);
-                fd.nfac = (int)f.size();
-                for (size_t q = 0; q < f.size(); ++q) fd.fac[q] = f[q];
-                fd.tw_offset = (int64_t)(tw.size() / 2);
-                const long double two_pi = 6.283185307179586476925286766559005768L;
-                for (int k = 0; k < r.nphi; ++k) {
-                    const long double a = -two_pi * (long double)k / (long double)r.nphi;
-                    tw.push_back((double)cosl(a));
-                    tw.push_back((double)sinl(a));
-                }
-                it = fft_index.emplace(r.nphi, (int)ffts.size()).first;
-                ffts.push_back(fd);
+            r.fft = fft_descriptor(r.nphi, fft_index, ffts, tw);
+            const FftDesc &fd = ffts[r.fft];
+            P.max_nphi = std::max<int64_t>(P.max_nphi, r.nphi);
+            P.max_fft_len = std::max<int64_t>(P.max_fft_len, fd.blue ? fd.M : fd.n);
+        }
+        P.ring_nt_min = 256;
+        for (auto &r : rings) {
+            if (fft_fits(ffts[r.fft], ffts, 256)) continue;
+            if (!fft_fits(ffts[r.fft], ffts, 512)) {
+                free_plan_memory(&P);
+                P = Plan();
+                return fail(VSHT_EUNSUPPORTED, "ring length " + std::to_string(r.nphi) +
+                                                   " has prime factors the ring DFT kernels cannot take");
             }
-            r.fft = it->second;
-            if (r.nphi > P.max_nphi) P.max_nphi = r.nphi;
+            P.ring_nt_min = 512;
         }
         // pair rings with z_S == -z_N bitwise
         std::unordered_map<uint64_t, std::vector<int>> byz;
@@ -407,18 +488,89 @@ vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w, cons
         if ((e = hipMalloc(&P.d_fg, fg)) != hipSuccess) goto hip_error;
         P.workspace_bytes = fg;
     }
-    *out = h;
     return VSHT_OK;
 
 hip_error:
     free_plan_memory(&P);
-    delete h;
+    P = Plan();
     return hip_fail(e, "plan setup");
+}
+
+}  // namespace
+
+// A batch: one plan per field plus the batched launch state and its graphs.
+struct BatchPlan {
+    std::vector<Plan> fields;
+    BatchState *st = nullptr;
+    hipStream_t cap = nullptr;          // capture stream (default priority)
+    hipGraphExec_t exec[4] = {};        // by direction set: 1 adjoint, 2 forward, 3 both
+    std::vector<const void *> bound_adj, bound_fwd;
+    int last_dirs = 0;
+
+    void drop_graphs() {
+        for (auto &x : exec)
+            if (x) {
+                (void)hipGraphExecDestroy(x);
+                x = nullptr;
+            }
+    }
+    ~BatchPlan() {
+        drop_graphs();
+        if (st) batch_destroy(st);
+        if (cap) (void)hipStreamDestroy(cap);
+        for (auto &f : fields) free_plan_memory(&f);
+    }
+};
+
+struct vsht_plan_s {
+    Plan p;                       // the plan, or the summary of a batch
+    BatchPlan *batch = nullptr;   // non-null for a batch plan
+    ~vsht_plan_s() { delete batch; }
+};
+
+extern "C" {
+
+int64_t vsht_num_coeffs(int L) { return L >= 1 ? (int64_t)L * (L + 2) : 0; }
+
+const char *vsht_status_string(vsht_status s) {
+    switch (s) {
+        case VSHT_OK: return "VSHT_OK";
+        case VSHT_EINVAL: return "VSHT_EINVAL: invalid argument";
+        case VSHT_ENOWEIGHTS: return "VSHT_ENOWEIGHTS: plan has no quadrature weights";
+        case VSHT_ENOMEM: return "VSHT_ENOMEM: out of memory";
+        case VSHT_EDEVICE: return "VSHT_EDEVICE: HIP error";
+        case VSHT_EUNSUPPORTED: return "VSHT_EUNSUPPORTED: not supported for this plan";
+    }
+    return "unknown vsht_status";
+}
+
+const char *vsht_last_error(void) { return g_last_error.c_str(); }
+
+vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w, const vsht_opts *opts,
+                      vsht_plan_t *out) {
+    g_last_error.clear();
+    if (!out) return fail(VSHT_EINVAL, "out is NULL");
+    *out = nullptr;
+    const int precision = opts ? opts->precision : VSHT_FP64;
+    vsht_status s = check_plan_args(L, n, xyz, w, precision);
+    if (s != VSHT_OK) return s;
+    int dev = 0;
+    if ((s = resolve_device(opts, &dev)) != VSHT_OK) return s;
+    DeviceGuard guard(dev);
+    auto *h = new (std::nothrow) vsht_plan_s();
+    if (!h) return fail(VSHT_ENOMEM, "host allocation");
+    if ((s = build_plan(h->p, L, n, xyz, w, precision, dev)) != VSHT_OK) {
+        delete h;
+        return s;
+    }
+    *out = h;
+    return VSHT_OK;
 }
 
 static vsht_status check_call(vsht_plan_t plan, const void *x, const void *y, const void *z) {
     g_last_error.clear();
     if (!plan) return fail(VSHT_EINVAL, "plan is NULL");
+    if (plan->batch) return fail(VSHT_EINVAL, "batch plan: use the vsht_batch_* calls");
     if (!x || !y || !z) return fail(VSHT_EINVAL, "NULL buffer");
     return VSHT_OK;
 }
@@ -571,9 +723,291 @@ vsht_status vsht_plan_destroy(vsht_plan_t plan) {
         DeviceGuard guard(plan->p.device);
         (void)hipDeviceSynchronize();
         drop_records(plan->p);
-        free_plan_memory(&plan->p);
+        if (!plan->batch) free_plan_memory(&plan->p);
+        delete plan;
     }
-    delete plan;
+    return VSHT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+vsht_status vsht_plan_batch(int nfields, const int *L, const int64_t *n, const double *const *xyz,
+                            const double *const *w, const vsht_opts *opts, vsht_plan_t *out) {
+    g_last_error.clear();
+    if (!out) return fail(VSHT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nfields < 1) return fail(VSHT_EINVAL, "nfields must be >= 1");
+    if (!L || !n || !xyz || !w) return fail(VSHT_EINVAL, "NULL argument");
+    const int precision = opts ? opts->precision : VSHT_FP64;
+    for (int f = 0; f < nfields; ++f) {
+        if (!w[f]) return fail(VSHT_EINVAL, "field " + std::to_string(f) + ": weights are required");
+        vsht_status s = check_plan_args(L[f], n[f], xyz[f], w[f], precision);
+        if (s != VSHT_OK) {
+            g_last_error = "field " + std::to_string(f) + ": " + g_last_error;
+            return s;
+        }
+    }
+    int dev = 0;
+    vsht_status s = resolve_device(opts, &dev);
+    if (s != VSHT_OK) return s;
+    DeviceGuard guard(dev);
+    auto *h = new (std::nothrow) vsht_plan_s();
+    if (!h) return fail(VSHT_ENOMEM, "host allocation");
+    h->batch = new (std::nothrow) BatchPlan();
+    if (!h->batch) {
+        delete h;
+        return fail(VSHT_ENOMEM, "host allocation");
+    }
+    BatchPlan &B = *h->batch;
+    B.fields.resize(nfields);
+    Plan &S = h->p;  // summary
+    S.precision = precision;
+    S.device = dev;
+    S.kind = VSHT_PLAN_BATCH;
+    S.has_weights = 1;
+    for (int f = 0; f < nfields; ++f) {
+        s = build_plan(B.fields[f], L[f], n[f], xyz[f], w[f], precision, dev);
+        if (s == VSHT_OK && B.fields[f].kind != VSHT_PLAN_RINGS)
+            s = fail(VSHT_EUNSUPPORTED, "a batch needs iso-latitude ring grids");
+        if (s != VSHT_OK) {
+            g_last_error = "field " + std::to_string(f) + ": " + g_last_error;
+            delete h;
+            return s;
+        }
+        const Plan &F = B.fields[f];
+        S.L = std::max(S.L, F.L);
+        S.n += F.n;
+        S.n_rings += F.n_rings;
+        S.n_pairs += F.n_pairs;
+        S.max_nphi = std::max(S.max_nphi, F.max_nphi);
+        S.workspace_bytes += F.workspace_bytes;
+        S.table_bytes += F.table_bytes;
+    }
+    std::vector<const Plan *> ptrs;
+    for (auto &f : B.fields) ptrs.push_back(&f);
+    hipError_t e = batch_create(ptrs, &B.st);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "batch setup");
+    }
+    *out = h;
+    return VSHT_OK;
+}
+
+static vsht_status check_batch(vsht_plan_t plan) {
+    g_last_error.clear();
+    if (!plan) return fail(VSHT_EINVAL, "plan is NULL");
+    if (!plan->batch) return fail(VSHT_EINVAL, "not a batch plan");
+    return VSHT_OK;
+}
+
+static bool same_pointers(const std::vector<const void *> &v, std::initializer_list<const void *const *> arrs,
+                          size_t F) {
+    if (v.size() != arrs.size() * F) return false;
+    size_t k = 0;
+    for (auto a : arrs)
+        for (size_t i = 0; i < F; ++i)
+            if (v[k++] != a[i]) return false;
+    return true;
+}
+
+static void remember(std::vector<const void *> &v, std::initializer_list<const void *const *> arrs, size_t F) {
+    v.clear();
+    for (auto a : arrs)
+        for (size_t i = 0; i < F; ++i) v.push_back(a[i]);
+}
+
+static vsht_status check_ptr_arrays(std::initializer_list<const void *const *> arrs, size_t F) {
+    for (auto a : arrs) {
+        if (!a) return fail(VSHT_EINVAL, "NULL pointer array");
+        for (size_t i = 0; i < F; ++i)
+            if (!a[i]) return fail(VSHT_EINVAL, "NULL buffer for field " + std::to_string(i));
+    }
+    return VSHT_OK;
+}
+
+// Replay (capturing on first use) the graph of the stages of `dirs`.
+static vsht_status batch_run(BatchPlan &B, int dirs, hipStream_t stream) {
+    hipError_t e = hipSuccess;
+    if (!B.exec[dirs]) {
+        hipGraph_t g = nullptr;
+        e = hipStreamBeginCapture(B.cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        hipError_t el = batch_launch(B.st, dirs, B.cap);
+        e = hipStreamEndCapture(B.cap, &g);
+        if (el != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(el != hipSuccess ? el : e, "batch capture");
+        }
+        e = hipGraphInstantiate(&B.exec[dirs], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            B.exec[dirs] = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+    }
+    e = hipGraphLaunch(B.exec[dirs], stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    B.last_dirs = dirs;
+    return VSHT_OK;
+}
+
+static vsht_status batch_bind(BatchPlan &B, int dirs, const void *const *a, const void *const *b,
+                              void *const *T, void *const *a2, void *const *b2, hipStream_t stream) {
+    const size_t F = B.fields.size();
+    hipError_t e = hipSuccess;
+    if ((dirs & 1) && !same_pointers(B.bound_adj, {a, b, (const void *const *)T}, F)) {
+        e = batch_bind_adjoint(B.st, a, b, T, stream);
+        if (e != hipSuccess) return hip_fail(e, "batch bind");
+        remember(B.bound_adj, {a, b, (const void *const *)T}, F);
+    }
+    if ((dirs & 2) && !same_pointers(B.bound_fwd, {(const void *const *)T, (const void *const *)a2,
+                                                   (const void *const *)b2}, F)) {
+        e = batch_bind_forward(B.st, T, a2, b2, stream);
+        if (e != hipSuccess) return hip_fail(e, "batch bind");
+        remember(B.bound_fwd, {(const void *const *)T, (const void *const *)a2, (const void *const *)b2}, F);
+    }
+    return VSHT_OK;
+}
+
+vsht_status vsht_batch_adjoint(vsht_plan_t plan, const void *const *a, const void *const *b, void *const *T,
+                               void *stream) {
+    vsht_status s = check_batch(plan);
+    if (s != VSHT_OK) return s;
+    BatchPlan &B = *plan->batch;
+    if ((s = check_ptr_arrays({a, b, (const void *const *)T}, B.fields.size())) != VSHT_OK) return s;
+    DeviceGuard guard(plan->p.device);
+    if ((s = batch_bind(B, 1, a, b, T, nullptr, nullptr, (hipStream_t)stream)) != VSHT_OK) return s;
+    return batch_run(B, 1, (hipStream_t)stream);
+}
+
+vsht_status vsht_batch_forward(vsht_plan_t plan, const void *const *T, void *const *a, void *const *b,
+                               void *stream) {
+    vsht_status s = check_batch(plan);
+    if (s != VSHT_OK) return s;
+    BatchPlan &B = *plan->batch;
+    if ((s = check_ptr_arrays({T, (const void *const *)a, (const void *const *)b}, B.fields.size())) != VSHT_OK)
+        return s;
+    DeviceGuard guard(plan->p.device);
+    if ((s = batch_bind(B, 2, nullptr, nullptr, const_cast<void *const *>(T), a, b, (hipStream_t)stream)) != VSHT_OK)
+        return s;
+    return batch_run(B, 2, (hipStream_t)stream);
+}
+
+vsht_status vsht_batch_roundtrip(vsht_plan_t plan, const void *const *a, const void *const *b, void *const *T,
+                                 void *const *a2, void *const *b2, void *stream) {
+    vsht_status s = check_batch(plan);
+    if (s != VSHT_OK) return s;
+    BatchPlan &B = *plan->batch;
+    if ((s = check_ptr_arrays({a, b, (const void *const *)T, (const void *const *)a2, (const void *const *)b2},
+                              B.fields.size())) != VSHT_OK)
+        return s;
+    DeviceGuard guard(plan->p.device);
+    if ((s = batch_bind(B, 3, a, b, T, a2, b2, (hipStream_t)stream)) != VSHT_OK) return s;
+    return batch_run(B, 3, (hipStream_t)stream);
+}
+
+vsht_status vsht_batch_set_config(vsht_plan_t plan, int adj_nw, int fwd_merge, int lpt, int ring_nt) {
+    vsht_status s = check_batch(plan);
+    if (s != VSHT_OK) return s;
+    if (adj_nw != 1 && adj_nw != 2 && adj_nw != 4) return fail(VSHT_EINVAL, "adj_nw must be 1, 2 or 4");
+    if (ring_nt != 256 && ring_nt != 512) return fail(VSHT_EINVAL, "ring_nt must be 256 or 512");
+    BatchPlan &B = *plan->batch;
+    DeviceGuard guard(plan->p.device);
+    hipError_t e = hipDeviceSynchronize();  // no replay may still read the work lists
+    if (e == hipSuccess) {
+        B.drop_graphs();
+        BatchConfig c;
+        c.adj_nw = adj_nw;
+        c.fwd_merge = fwd_merge ? 1 : 0;
+        c.lpt = lpt ? 1 : 0;
+        c.ring_nt = ring_nt;
+        e = batch_configure(B.st, c);
+    }
+    return e == hipSuccess ? VSHT_OK : hip_fail(e, "batch configure");
+}
+
+vsht_status vsht_batch_get_config(vsht_plan_t plan, int *adj_nw, int *fwd_merge, int *lpt, int *ring_nt) {
+    vsht_status s = check_batch(plan);
+    if (s != VSHT_OK) return s;
+    if (!adj_nw || !fwd_merge || !lpt || !ring_nt) return fail(VSHT_EINVAL, "NULL argument");
+    const BatchConfig c = batch_config(plan->batch->st);
+    *adj_nw = c.adj_nw;
+    *fwd_merge = c.fwd_merge;
+    *lpt = c.lpt;
+    *ring_nt = c.ring_nt;
+    return VSHT_OK;
+}
+
+vsht_status vsht_batch_autotune(vsht_plan_t plan, const void *const *a, const void *const *b, void *const *T,
+                                void *const *a2, void *const *b2, int reps, double *best_ms, void *stream) {
+    vsht_status s = check_batch(plan);
+    if (s != VSHT_OK) return s;
+    if (reps < 1) return fail(VSHT_EINVAL, "reps must be >= 1");
+    BatchPlan &B = *plan->batch;
+    if ((s = check_ptr_arrays({a, b, (const void *const *)T, (const void *const *)a2, (const void *const *)b2},
+                              B.fields.size())) != VSHT_OK)
+        return s;
+    DeviceGuard guard(plan->p.device);
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    float best = -1.f;
+    int bn = 4, bm = 0, bl = 1, br = 256;
+    const int nws[3] = {1, 2, 4};
+    for (int i = 0; i < 3 && s == VSHT_OK; ++i)
+        for (int fm = 0; fm < 2 && s == VSHT_OK; ++fm)
+            for (int lpt = 0; lpt < 2 && s == VSHT_OK; ++lpt)
+            for (int rnt : {256, 512}) {
+                if (s != VSHT_OK) break;
+                s = vsht_batch_set_config(plan, nws[i], fm, lpt, rnt);
+                if (s == VSHT_OK) s = vsht_batch_roundtrip(plan, a, b, T, a2, b2, stream);  // capture + warm
+                if (s != VSHT_OK) break;
+                e = hipEventRecord(e0, st);
+                for (int r = 0; r < reps && e == hipSuccess; ++r)
+                    if (batch_run(B, 3, st) != VSHT_OK) e = hipErrorUnknown;
+                if (e == hipSuccess) e = hipEventRecord(e1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) {
+                    s = hip_fail(e, "autotune timing");
+                    break;
+                }
+                ms /= reps;
+                if (best < 0.f || ms < best) {
+                    best = ms;
+                    bn = nws[i];
+                    bm = fm;
+                    bl = lpt;
+                    br = rnt;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != VSHT_OK) return s;
+    if (best_ms) *best_ms = best;
+    return vsht_batch_set_config(plan, bn, bm, bl, br);
+}
+
+vsht_status vsht_batch_field_times(vsht_plan_t plan, double *start_us, double *end_us) {
+    vsht_status s = check_batch(plan);
+    if (s != VSHT_OK) return s;
+    if (!start_us || !end_us) return fail(VSHT_EINVAL, "NULL argument");
+    BatchPlan &B = *plan->batch;
+    if (!B.last_dirs) return fail(VSHT_EINVAL, "the batch has not run yet");
+    DeviceGuard guard(plan->p.device);
+    std::vector<double> t0, t1;
+    hipError_t e = batch_field_times(B.st, B.last_dirs, t0, t1);
+    if (e != hipSuccess) return hip_fail(e, "batch field times");
+    for (size_t i = 0; i < t0.size(); ++i) {
+        start_us[i] = t0[i];
+        end_us[i] = t1[i];
+    }
     return VSHT_OK;
 }
 

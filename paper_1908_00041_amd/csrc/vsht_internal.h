@@ -47,13 +47,29 @@ struct PairDesc {
     int32_t rn, rs;
 };
 
+// Limits of the ring DFT stages (shared by the kernels and the plan's check
+// that every stage of a length fits a workgroup width).
+constexpr int kKP = 2;           // output pairs per work item of a generic odd radix
+constexpr int kKP1 = 4;          // the same for the twiddle-free first odd stage
+constexpr int kSmallTab = 128;   // largest odd radix whose cos/sin table is staged in LDS
+constexpr int kMaxItemsSmall = 4;  // work items per thread of a radix-2..5 stage
+constexpr int kMaxItemsOdd = 2;    // work items per thread of a generic odd stage
+
 // Mixed-radix Stockham descriptor for one DFT length.
 constexpr int kMaxFactors = 24;
 struct FftDesc {
     int32_t n;
     int32_t nfac;
-    int64_t tw_offset;  // offset (in complex entries) of e^{-2 pi i k / n}, k < n
+    int64_t tw_offset;  // offset (in complex entries) of e^{-2 pi i k / n}, k < n (every descriptor)
     int32_t fac[kMaxFactors];
+    // Bluestein form (lengths with a large prime factor): a cyclic convolution
+    // of power-of-two length M through the descriptor mdesc
+    int32_t blue;
+    int32_t M;
+    int32_t mdesc;
+    int32_t pad;
+    int64_t chirp_offset;  // w_k = e^{-i pi k^2 / n}, k < n
+    int64_t bhat_offset;   // DFT_M of conj(w) (forward), then of w (inverse), each / M: 2M entries
 };
 
 // Workspace layout (all in the plan's real type):
@@ -73,6 +89,8 @@ struct Plan {
     int64_t n = 0;
     int64_t n_rings = 0, n_pairs = 0;
     int64_t max_nphi = 0;
+    int64_t max_fft_len = 0;   // longest stored DFT sequence (n, or M for Bluestein rings)
+    int ring_nt_min = 256;     // narrowest ring workgroup (256 or 512) every ring's DFT stages fit
     int64_t tri_size = 0;
     int eq_ring = -1;       // ring at z = 0 (always the last pair), handled in closed form
 
@@ -144,5 +162,30 @@ hipError_t launch_forward(const Plan &p, const void *T, void *a, void *b, bool w
                           hipStream_t st);
 hipError_t launch_adjoint(const Plan &p, const void *a, const void *b, void *T, bool weighted,
                           hipStream_t st);
+hipError_t launch_seed_kernel(const double *pair_s, int NP, int L, double *seeds, hipStream_t st);
+hipError_t set_kernel_attributes();
+
+// Batches (vsht_kernels.hip): every field of a batch in one launch per stage.
+struct WorkItem {
+    int32_t f, x, y, pad;  // field, block coordinates
+};
+struct BatchConfig {
+    int adj_nw = 4;     // waves (64-pair tiles) per workgroup of the Legendre synthesis: 1, 2 or 4
+    int fwd_merge = 0;  // 1: one analysis launch at the widest shape; 0: one launch per tile count
+    int lpt = 1;        // 1: work items longest first; 0: field by field
+    int ring_nt = 256;  // threads per ring workgroup (256 or 512; rings longer than 2048 always 512)
+};
+struct BatchState;
+hipError_t batch_create(const std::vector<const Plan *> &fields, BatchState **out);
+void batch_destroy(BatchState *b);
+hipError_t batch_configure(BatchState *b, const BatchConfig &cfg);
+BatchConfig batch_config(const BatchState *b);
+hipError_t batch_bind_adjoint(BatchState *b, const void *const *a, const void *const *bb, void *const *T,
+                              hipStream_t st);
+hipError_t batch_bind_forward(BatchState *b, const void *const *T, void *const *a, void *const *bb,
+                              hipStream_t st);
+hipError_t batch_launch(const BatchState *b, int dirs, hipStream_t st);  // dirs: 1 adjoint, 2 forward, 3 both
+hipError_t batch_field_times(const BatchState *b, int dirs, std::vector<double> &start_us,
+                             std::vector<double> &end_us);
 
 }  // namespace vsht

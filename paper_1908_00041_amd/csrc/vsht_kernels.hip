@@ -23,6 +23,10 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <new>
+#include <vector>
+
 #include "vsht_internal.h"
 
 namespace vsht {
@@ -38,6 +42,32 @@ __device__ __forceinline__ C2<real> cmul(C2<real> a, C2<real> b) {
 }
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Load of a value that is the same for the whole workgroup from memory that no
+// kernel writes while it runs (plan tables, argument blocks, work lists):
+// through the constant address space, so that it becomes a scalar load.
+template <typename T>
+__device__ __forceinline__ T ld_const(const T *p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return *(const __attribute__((address_space(4))) T *)p;
+#else
+    return *p;  // host pass of the kernel templates: never executed
+#endif
+}
+
+// The same for a structure read through a pointer taken from another table,
+// made wave-uniform dword by dword (keeps its fields in scalar registers).
+template <typename T>
+__device__ __forceinline__ T ld_uniform(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "dword-sized structure");
+    struct Words {
+        uint32_t d[sizeof(T) / 4];
+    };
+    Words w = *reinterpret_cast<const Words *>(p);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w.d[i] = __builtin_amdgcn_readfirstlane(w.d[i]);
+    return __builtin_bit_cast(T, w);
+}
 
 // Value of a binary64 register in lane `lane` (wave-uniform result).
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
@@ -207,8 +237,6 @@ __device__ __forceinline__ void fft_stage_small(C2<real> *buf, int buf_off, int 
     __syncthreads();
 }
 
-constexpr int kKP = 2;          // output pairs per work item of a generic odd radix
-constexpr int kSmallTab = 128;  // largest odd radix whose cos/sin table is staged in LDS
 
 template <typename real, int NT, int MAXI>
 __device__ __forceinline__ void fft_stage_odd(C2<real> *buf, int buf_off, int n, int R, int Ns,
@@ -294,6 +322,88 @@ __device__ __forceinline__ void fft_stage_odd(C2<real> *buf, int buf_off, int n,
     __syncthreads();
 }
 
+// First stage (Ns = 1, so no twiddles) of an odd prime radix R > 5, both
+// sequences in one pass: work item (sequence, column j, group g) forms the
+// outputs k = 4g+1 .. 4g+4 and R-k of the R-point DFT of column j from
+// u_t = x_t + x_{R-t}, v_t = x_t - x_{R-t}:
+//     X_k = x_0 + sum_t u_t cos(2 pi k t / R) + i sum_t v_t (-+ sin(2 pi k t / R)),
+//     X_{R-k} = the same with the second sum negated,
+// with cos/sin read from the LDS table wr (carrying the direction's sign).
+template <typename real, int NT, int MAXI>
+__device__ __forceinline__ void fft_stage_odd_first(C2<real> *buf, int stride, int n, int R,
+                                                    const C2<real> *wr) {
+    const int nb = n / R;
+    const int half = (R - 1) / 2;
+    const int G = (half + kKP1 - 1) / kKP1;
+    const int per_seq = nb * G;
+    const int tid = opaque_tid();
+    C2<real> out[MAXI][2 * kKP1 + 1];
+    int dst[MAXI], grp[MAXI];
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) {
+        const int it = tid + i * NT;
+        dst[i] = -1;
+        grp[i] = 0;
+        if (it < 2 * per_seq) {
+            const int sq = it >= per_seq ? 1 : 0;
+            const int r = it - sq * per_seq;
+            const int j = r / G, g = r - j * G;
+            const int sb = sq * stride + j;
+            const C2<real> x0 = buf[pad16(sb)];
+            C2<real> A[kKP1], B[kKP1], S = {0, 0};
+            int q[kKP1], kq[kKP1];
+#pragma unroll
+            for (int kk = 0; kk < kKP1; ++kk) {
+                A[kk] = B[kk] = {0, 0};
+                kq[kk] = g * kKP1 + kk + 1;
+                if (kq[kk] > half) kq[kk] = 0;  // beyond the last pair: contributes nothing used
+                q[kk] = 0;
+            }
+#pragma unroll 2
+            for (int t = 1; t <= half; ++t) {
+                const C2<real> xt = buf[pad16(sb + t * nb)];
+                const C2<real> xm = buf[pad16(sb + (R - t) * nb)];
+                const C2<real> u = cadd(xt, xm), v = csub(xt, xm);
+                S = cadd(S, u);
+#pragma unroll
+                for (int kk = 0; kk < kKP1; ++kk) {
+                    q[kk] += kq[kk];
+                    if (q[kk] >= R) q[kk] -= R;
+                    const C2<real> w = wr[q[kk]];
+                    A[kk].x += u.x * w.x;
+                    A[kk].y += u.y * w.x;
+                    B[kk].x += v.x * w.y;
+                    B[kk].y += v.y * w.y;
+                }
+            }
+#pragma unroll
+            for (int kk = 0; kk < kKP1; ++kk) {
+                const C2<real> a = cadd(x0, A[kk]);
+                out[i][2 * kk] = cadd_i(a, B[kk], (real)1);
+                out[i][2 * kk + 1] = cadd_i(a, B[kk], (real)-1);
+            }
+            out[i][2 * kKP1] = cadd(x0, S);
+            dst[i] = sq * stride + j * R;
+            grp[i] = g;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i)
+        if (dst[i] >= 0) {
+#pragma unroll
+            for (int kk = 0; kk < kKP1; ++kk) {
+                const int k = grp[i] * kKP1 + kk + 1;
+                if (k <= half) {
+                    buf[pad16(dst[i] + k)] = out[i][2 * kk];
+                    buf[pad16(dst[i] + R - k)] = out[i][2 * kk + 1];
+                }
+            }
+            if (grp[i] == 0) buf[pad16(dst[i])] = out[i][2 * kKP1];
+        }
+    __syncthreads();
+}
+
 // Two sequences of length fdp->n in buf (element i at pad16(i)); wR is an LDS
 // scratch of kSmallTab entries.
 // The number of work items per thread (MAXI) is chosen per stage so that the
@@ -301,30 +411,46 @@ __device__ __forceinline__ void fft_stage_odd(C2<real> *buf, int buf_off, int n,
 template <typename real, int NT, int R>
 __device__ __forceinline__ void fft_small_dispatch(C2<real> *buf, int off, int n, int Ns,
                                                    const double *twn, bool inv) {
+    static_assert(kMaxItemsSmall == 4, "dispatch below instantiates up to 4 items per thread");
     const int per = (n / R + NT - 1) / NT;
     if (per <= 1) fft_stage_small<real, NT, R, 1>(buf, off, n, Ns, twn, inv);
     else if (per <= 2) fft_stage_small<real, NT, R, 2>(buf, off, n, Ns, twn, inv);
     else fft_stage_small<real, NT, R, 4>(buf, off, n, Ns, twn, inv);
 }
 
+// Mixed-radix Stockham DFT of the two sequences at buf offsets 0 and `stride`.
 // Stages are applied to one sequence at a time (the two sequences of a ring
 // share each stage's twiddle set), so a thread holds at most 4 small
-// butterflies or 2 odd-radix work items across a barrier (n <= 3072).
+// butterflies or 2 odd-radix work items across a barrier (n <= 4096).
 template <typename real, int NT>
-__device__ __forceinline__ void fft_lds(C2<real> *buf, const FftDesc *fdp, const double *__restrict__ tw,
-                                        CD *wR, bool inv) {
-    const int n = fdp->n;
-    const int nfac = fdp->nfac;
-    const double *twn = tw + 2 * fdp->tw_offset;
+__device__ __forceinline__ void fft_core(C2<real> *buf, int stride, const FftDesc *fdp,
+                                         const double *__restrict__ tw, CD *wR, bool inv) {
+    const int n = ld_const(&fdp->n);
+    const int nfac = ld_const(&fdp->nfac);
+    const double *twn = tw + 2 * ld_const(&fdp->tw_offset);
     int Ns = 1;
     for (int f = 0; f < nfac; ++f) {
-        const int R = fdp->fac[f];
+        const int R = ld_const(&fdp->fac[f]);
+        if (f == 0 && R > 5 && R <= kSmallTab &&
+            2 * (n / R) * (((R - 1) / 2 + kKP1 - 1) / kKP1) <= NT) {
+            // twiddle-free first stage, table in the working precision (one
+            // work item per thread; longer stages take the general path below)
+            C2<real> *wr = reinterpret_cast<C2<real> *>(wR);
+            for (int qq = threadIdx.x; qq < R; qq += NT) {
+                const CD c = tw_at(twn, qq * (n / R), inv);
+                wr[qq] = {(real)c.x, (real)c.y};
+            }
+            __syncthreads();
+            fft_stage_odd_first<real, NT, 1>(buf, stride, n, R, wr);
+            Ns *= R;
+            continue;
+        }
         if (R > 5 && R <= kSmallTab) {
             for (int qq = threadIdx.x; qq < R; qq += NT) wR[qq] = tw_at(twn, qq * (n / R), inv);
             __syncthreads();
         }
         for (int sq = 0; sq < 2; ++sq) {
-            const int off = sq * n;
+            const int off = sq * stride;
             switch (R) {
                 case 2: fft_small_dispatch<real, NT, 2>(buf, off, n, Ns, twn, inv); break;
                 case 3: fft_small_dispatch<real, NT, 3>(buf, off, n, Ns, twn, inv); break;
@@ -332,6 +458,7 @@ __device__ __forceinline__ void fft_lds(C2<real> *buf, const FftDesc *fdp, const
                 case 5: fft_small_dispatch<real, NT, 5>(buf, off, n, Ns, twn, inv); break;
                 default: {
                     const int items = (n / R) * (((R - 1) / 2 + kKP - 1) / kKP);
+                    static_assert(kMaxItemsOdd == 2, "dispatch below instantiates up to 2 items per thread");
                     if (items <= NT) fft_stage_odd<real, NT, 1>(buf, off, n, R, Ns, twn, wR, inv);
                     else fft_stage_odd<real, NT, 2>(buf, off, n, R, Ns, twn, wR, inv);
                     break;
@@ -340,6 +467,61 @@ __device__ __forceinline__ void fft_lds(C2<real> *buf, const FftDesc *fdp, const
         }
         Ns *= R;
     }
+}
+
+// Storage stride of the second sequence of a ring whose DFT is described by fdp.
+__device__ __forceinline__ int seq_stride(const FftDesc *fdp) {
+    return ld_const(&fdp->blue) ? ld_const(&fdp->M) : ld_const(&fdp->n);
+}
+
+// DFT of length n of the two sequences of a ring (element i of sequence q at
+// buf[pad16(q * seq_stride + i)]), forward (e^{-2 pi i j m / n}) or inverse.
+// Lengths with a prime factor above the generic-radix limit use Bluestein's
+// identity j m = (j^2 + m^2 - (m - j)^2) / 2: with w_k = e^{-i pi k^2 / n},
+//     X_m = w_m sum_j (x_j w_j) conj(w_{m-j}),
+// a cyclic convolution of length M >= 2n - 1 (a power of two) evaluated with
+// two mixed-radix DFTs of length M and the tabulated transform of the kernel
+// (already divided by M); the inverse uses conj(w).
+template <typename real, int NT>
+__device__ __forceinline__ void fft_lds(C2<real> *buf, const FftDesc *ffts, const FftDesc *fdp,
+                                        const double *__restrict__ tw, CD *wR, bool inv) {
+    if (!ld_const(&fdp->blue)) {
+        fft_core<real, NT>(buf, ld_const(&fdp->n), fdp, tw, wR, inv);
+        return;
+    }
+    const int n = ld_const(&fdp->n), M = ld_const(&fdp->M);
+    const double *ch = tw + 2 * ld_const(&fdp->chirp_offset);
+    const double *bh = tw + 2 * (ld_const(&fdp->bhat_offset) + (inv ? M : 0));
+    for (int i = threadIdx.x; i < M; i += NT) {
+        const CD w = tw_at(ch, i < n ? i : 0, inv);
+#pragma unroll
+        for (int sq = 0; sq < 2; ++sq) {
+            C2<real> &v = buf[pad16(sq * M + i)];
+            v = i < n ? cmul_d(v, w) : C2<real>{0, 0};
+        }
+    }
+    __syncthreads();
+    const FftDesc *md = ffts + ld_const(&fdp->mdesc);
+    fft_core<real, NT>(buf, M, md, tw, wR, false);
+    for (int i = threadIdx.x; i < M; i += NT) {
+        const CD w = tw_at(bh, i, false);
+#pragma unroll
+        for (int sq = 0; sq < 2; ++sq) {
+            C2<real> &v = buf[pad16(sq * M + i)];
+            v = cmul_d(v, w);
+        }
+    }
+    __syncthreads();
+    fft_core<real, NT>(buf, M, md, tw, wR, true);
+    for (int i = threadIdx.x; i < n; i += NT) {
+        const CD w = tw_at(ch, i, inv);
+#pragma unroll
+        for (int sq = 0; sq < 2; ++sq) {
+            C2<real> &v = buf[pad16(sq * M + i)];
+            v = cmul_d(v, w);
+        }
+    }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -353,7 +535,9 @@ __device__ __forceinline__ void fft_lds(C2<real> *buf, const FftDesc *fdp, const
 // The north/south fold of the forward transform happens when the Legendre
 // stage loads RB.
 // ---------------------------------------------------------------------------
-constexpr int kRingNT = 512;
+constexpr int kRingNT = 512;  // threads per ring workgroup (256 serves rings whose DFT length is <= 2048)
+constexpr int kRingNTSmall = 256;
+constexpr int kMaxLenSmallRing = 2048;
 
 template <typename real>
 struct RingArgs {
@@ -366,22 +550,22 @@ struct RingArgs {
     const double *tw;
     int L;
     int NP;
+    int NR;
     int weighted;
 };
 
-template <typename real>
-__global__ __launch_bounds__(kRingNT, 2) void k_ring_fwd(RingArgs<real> A) {
-    extern __shared__ unsigned char smem_raw[];
+template <typename real, int NT>
+__device__ __forceinline__ void ring_fwd_body(const RingArgs<real> &A, int r, unsigned char *smem_raw) {
     CD *wR = reinterpret_cast<CD *>(smem_raw);
     C2<real> *buf = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
-    const int r = blockIdx.x;
-    const int NR = gridDim.x;
+    const int NR = A.NR;
     const int L = A.L;
-    const RingDesc rd = A.rings[r];
+    const RingDesc rd = ld_uniform(A.rings + r);
     const FftDesc *fdp = A.ffts + rd.fft;
     const int n = rd.nphi;
-    const double *twn = A.tw + 2 * fdp->tw_offset;
-    for (int j = threadIdx.x; j < n; j += kRingNT) {
+    const int n2 = seq_stride(fdp);
+    const double *twn = A.tw + 2 * ld_const(&fdp->tw_offset);
+    for (int j = threadIdx.x; j < n; j += NT) {
         // e^{i phi_j} = e^{i phi_0} conj(e^{-2 pi i j / n})
         const double er = twn[2 * j], ei = -twn[2 * j + 1];
         const real c = (real)(rd.c0 * er - rd.s0 * ei);
@@ -397,12 +581,12 @@ __global__ __launch_bounds__(kRingNT, 2) void k_ring_fwd(RingArgs<real> A) {
         ph.x = w * (c * t2.x - sn * t1.x);
         ph.y = w * (c * t2.y - sn * t1.y);
         buf[pad16(j)] = th;
-        buf[pad16(n + j)] = ph;
+        buf[pad16(n2 + j)] = ph;
     }
     __syncthreads();
-    fft_lds<real, kRingNT>(buf, fdp, A.tw, wR, false);
+    fft_lds<real, NT>(buf, A.ffts, fdp, A.tw, wR, false);
     const double inv_s = 1.0 / rd.s;
-    for (int m = threadIdx.x; m <= L; m += kRingNT) {
+    for (int m = threadIdx.x; m <= L; m += NT) {
         const int bp = m % n;
         const int bm = bp == 0 ? 0 : n - bp;
         double cph = 1.0, sph = 0.0;
@@ -412,26 +596,25 @@ __global__ __launch_bounds__(kRingNT, 2) void k_ring_fwd(RingArgs<real> A) {
         const C2<real> fm = {(real)(cph * inv_s), (real)(sph * inv_s)};
         C2<real> *o = A.buf + ((size_t)m * NR + r) * 4;
         o[0] = cmul(buf[pad16(bp)], fp);
-        o[1] = cmul(buf[pad16(n + bp)], fp);
+        o[1] = cmul(buf[pad16(n2 + bp)], fp);
         o[2] = cmul(buf[pad16(bm)], fm);
-        o[3] = cmul(buf[pad16(n + bm)], fm);
+        o[3] = cmul(buf[pad16(n2 + bm)], fm);
     }
 }
 
-template <typename real>
-__global__ __launch_bounds__(kRingNT, 2) void k_ring_adj(RingArgs<real> A) {
-    extern __shared__ unsigned char smem_raw[];
+template <typename real, int NT>
+__device__ __forceinline__ void ring_adj_body(const RingArgs<real> &A, int r, unsigned char *smem_raw) {
     CD *wR = reinterpret_cast<CD *>(smem_raw);
     C2<real> *buf = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
-    const int r = blockIdx.x;
     const int L = A.L;
-    const RingDesc rd = A.rings[r];
+    const RingDesc rd = ld_uniform(A.rings + r);
     const FftDesc *fdp = A.ffts + rd.fft;
     const int n = rd.nphi;
+    const int n2 = seq_stride(fdp);
     const int p = rd.pair;
     const real sgn = rd.south ? (real)-1 : (real)1;
     const double inv_s = 1.0 / rd.s;
-    for (int b = threadIdx.x; b < n; b += kRingNT) {
+    for (int b = threadIdx.x; b < n; b += NT) {
         C2<real> hth = {0, 0}, hph = {0, 0};
         // orders m = b + k n (k >= 0) and m = b - k n (k >= 1) with |m| <= L
         for (int pass = 0; pass < 2; ++pass) {
@@ -456,17 +639,17 @@ __global__ __launch_bounds__(kRingNT, 2) void k_ring_adj(RingArgs<real> A) {
             }
         }
         buf[pad16(b)] = hth;
-        buf[pad16(n + b)] = hph;
+        buf[pad16(n2 + b)] = hph;
     }
     __syncthreads();
-    fft_lds<real, kRingNT>(buf, fdp, A.tw, wR, true);
-    const double *twn = A.tw + 2 * fdp->tw_offset;
-    for (int j = threadIdx.x; j < n; j += kRingNT) {
+    fft_lds<real, NT>(buf, A.ffts, fdp, A.tw, wR, true);
+    const double *twn = A.tw + 2 * ld_const(&fdp->tw_offset);
+    for (int j = threadIdx.x; j < n; j += NT) {
         const double er = twn[2 * j], ei = -twn[2 * j + 1];
         const real c = (real)(rd.c0 * er - rd.s0 * ei);
         const real sn = (real)(rd.s0 * er + rd.c0 * ei);
         const real z = (real)rd.z, s = (real)rd.s;
-        C2<real> th = buf[pad16(j)], ph = buf[pad16(n + j)];
+        C2<real> th = buf[pad16(j)], ph = buf[pad16(n2 + j)];
         const int64_t k = rd.offset + j;
         if (A.weighted) {  // W S: the Hermitian transpose of the weighted analysis
             const real w = (real)(rd.uniform_w ? rd.w : A.weights[k]);
@@ -476,6 +659,18 @@ __global__ __launch_bounds__(kRingNT, 2) void k_ring_adj(RingArgs<real> A) {
         A.Tout[3 * k + 1] = {z * sn * th.x + c * ph.x, z * sn * th.y + c * ph.y};
         A.Tout[3 * k + 2] = {-s * th.x, -s * th.y};
     }
+}
+
+template <typename real, int NT>
+__global__ __launch_bounds__(NT, 2) void k_ring_fwd(RingArgs<real> A) {
+    extern __shared__ unsigned char smem_raw[];
+    ring_fwd_body<real, NT>(A, blockIdx.x, smem_raw);
+}
+
+template <typename real, int NT>
+__global__ __launch_bounds__(NT, 2) void k_ring_adj(RingArgs<real> A) {
+    extern __shared__ unsigned char smem_raw[];
+    ring_adj_body<real, NT>(A, blockIdx.x, smem_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -615,16 +810,16 @@ struct FwdCompact<float> {
     }
 };
 
+// One workgroup: order m, tiles [group nw, group nw + nw) of ring pairs.
 template <typename real>
-__global__ __launch_bounds__(1024) void k_leg_fwd_mfma(LegFwdArgs<real> A) {
+__device__ __forceinline__ void leg_fwd_body(const LegFwdArgs<real> &A, int m, int group,
+                                             unsigned char *smem_raw) {
     typedef typename Mfma<real>::acc_t acc_t;
-    extern __shared__ unsigned char smem_raw[];
     const int L = A.L, NP = A.NP, NPT = A.NPT, NR = A.NR;
-    const int m = blockIdx.x;
     const int nw = blockDim.x >> 6;
     const int wave = uniform_int(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int tile = blockIdx.y * nw + wave;
+    const int tile = group * nw + wave;
     real *qt = reinterpret_cast<real *>(smem_raw) + wave * kRowsB * kTileP;     // private tile
     real *red = reinterpret_cast<real *>(smem_raw) + nw * kRowsB * kTileP;      // [2][nw][128]
     const int64_t t0 = tri_offset(L, m);
@@ -685,7 +880,7 @@ __global__ __launch_bounds__(1024) void k_leg_fwd_mfma(LegFwdArgs<real> A) {
                 real sum = 0;
                 for (int w = 0; w < nw; ++w) sum += rb[w * 128 + o];
                 const int64_t ti = t0 + lp - m;
-                if (xeq && col < 8 && blockIdx.y == 0) {
+                if (xeq && col < 8 && group == 0) {
                     // even-parity row: the equator adds Q_{lp}(0) X_eq
                     const int kk = (lp - m) >> 1;
                     const double qe = (kk & 1) ? -seq : seq;
@@ -699,6 +894,12 @@ __global__ __launch_bounds__(1024) void k_leg_fwd_mfma(LegFwdArgs<real> A) {
             }
         }
     }
+}
+
+template <typename real>
+__global__ __launch_bounds__(1024) void k_leg_fwd_mfma(LegFwdArgs<real> A) {
+    extern __shared__ unsigned char smem_raw[];
+    leg_fwd_body(A, blockIdx.x, blockIdx.y, smem_raw);
 }
 
 template <typename real>
@@ -781,32 +982,14 @@ __global__ __launch_bounds__(256) void k_leg_adj_mfma(LegArgs<real> A) {
     adj_tile_mfma<real, real>(A, blockIdx.y, tile, threadIdx.x & 63, qt);
 }
 
-// Binary32 synthesis whose first tile (the 64 ring pairs nearest the poles:
-// pairs are sorted by increasing sin(theta)) runs in binary64.  The
-// spin-frame form divides the synthesised sums by sin(theta), which there
-// amplifies the rounding of the contraction by up to 1/sin(theta) ~ L.
-__global__ __launch_bounds__(256) void k_leg_adj_fp32_polar64(LegArgs<float> A) {
-    extern __shared__ unsigned char smem_raw[];
-    const int nw = blockDim.x >> 6;
-    const int wave = uniform_int(threadIdx.x >> 6);
-    const int tile = blockIdx.x * nw + wave;
-    if (tile * kTileP >= A.NPT) return;
-    unsigned char *lds = smem_raw + wave * kAdjLdsPerWave;
-    if (tile == 0)
-        adj_tile_mfma<double, float>(A, blockIdx.y, tile, threadIdx.x & 63, reinterpret_cast<double *>(lds));
-    else
-        adj_tile_mfma<float, float>(A, blockIdx.y, tile, threadIdx.x & 63, reinterpret_cast<float *>(lds));
-}
-
 // ---------------------------------------------------------------------------
 // Equator ring (z = 0) of the synthesis: Q_{m+2k}(0) = (-1)^k Lambda_{m,m}(0)
 // and odd degrees vanish, so PB[m][eq][0][c] = Lambda_{m,m}(0) sum_k (-1)^k
 // FG[tri(m, m+2k)][c] and PB[m][eq][1] = 0.  One wave per order m.
 // ---------------------------------------------------------------------------
 template <typename real>
-__global__ __launch_bounds__(64) void k_equator_adj(LegArgs<real> A) {
+__device__ __forceinline__ void equator_adj_body(const LegArgs<real> &A, int m) {
     const int L = A.L, NP = A.NP;
-    const int m = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t t0 = tri_offset(L, m);
     const real *g = A.FG + t0 * 8;  // row l' = m + i
@@ -825,6 +1008,11 @@ __global__ __launch_bounds__(64) void k_equator_adj(LegArgs<real> A) {
         o[c] = (real)A.seeds[(size_t)m * NP + A.NPT] * acc;
         o[8 + c] = 0;
     }
+}
+
+template <typename real>
+__global__ __launch_bounds__(64) void k_equator_adj(LegArgs<real> A) {
+    equator_adj_body(A, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -879,7 +1067,7 @@ __device__ __forceinline__ f32x4 mma3(const Split8 &a, const Split8 &b, f32x4 ac
 template <int N>
 __device__ __forceinline__ void load_aprime(const double *__restrict__ ap, int lp0, int Lp1, double (&a)[N]) {
 #pragma unroll
-    for (int s = 0; s < N; ++s) a[s] = ap[lp0 + s];
+    for (int s = 0; s < N; ++s) a[s] = ld_const(ap + lp0 + s);
 #pragma unroll
     for (int s = 0; s < N; ++s)
         if (lp0 + s > Lp1) a[s] = 0.0;
@@ -896,14 +1084,13 @@ struct SwzFwd8 {
 
 // Analysis, BF16x3: as k_leg_fwd_mfma<float> (same grid, reduction and
 // epilogue) with the wave's 64-pair block contracted as two K = 32 chunks.
-__global__ __launch_bounds__(1024) void k_leg_fwd_bf16x3(LegFwdArgs<float> A) {
-    extern __shared__ unsigned char smem_raw[];
+__device__ __forceinline__ void leg_fwd_bf16x3_body(const LegFwdArgs<float> &A, int m, int group,
+                                                    unsigned char *smem_raw) {
     const int L = A.L, NP = A.NP, NPT = A.NPT, NR = A.NR;
-    const int m = blockIdx.x;
     const int nw = blockDim.x >> 6;
     const int wave = uniform_int(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int tile = blockIdx.y * nw + wave;
+    const int tile = group * nw + wave;
     float *qt = reinterpret_cast<float *>(smem_raw) + wave * kRowsB * kTileP;
     float *red = reinterpret_cast<float *>(smem_raw) + nw * kRowsB * kTileP;  // [2][nw][128]
     const int64_t t0 = tri_offset(L, m);
@@ -973,7 +1160,7 @@ __global__ __launch_bounds__(1024) void k_leg_fwd_bf16x3(LegFwdArgs<float> A) {
                 float sum = 0.f;
                 for (int w = 0; w < nw; ++w) sum += rb[w * 128 + o];
                 const int64_t ti = t0 + lp - m;
-                if (xeq && col < 8 && blockIdx.y == 0) {
+                if (xeq && col < 8 && group == 0) {
                     const int kk = (lp - m) >> 1;
                     const double qe = (kk & 1) ? -seq : seq;
                     sum += (float)qe * xeq[col];
@@ -986,6 +1173,11 @@ __global__ __launch_bounds__(1024) void k_leg_fwd_bf16x3(LegFwdArgs<float> A) {
             }
         }
     }
+}
+
+__global__ __launch_bounds__(1024) void k_leg_fwd_bf16x3(LegFwdArgs<float> A) {
+    extern __shared__ unsigned char smem_raw[];
+    leg_fwd_bf16x3_body(A, blockIdx.x, blockIdx.y, smem_raw);
 }
 
 // Synthesis, BF16x3: one wave per 64 ring pairs as k_leg_adj_mfma, degrees in
@@ -1063,8 +1255,11 @@ __device__ __forceinline__ void adj_tile_bf16x3(const LegArgs<float> &A, int m, 
     }
 }
 
-// BF16x3 synthesis; the polar tile (see k_leg_adj_fp32_polar64) runs on the
-// binary32 MFMA path.
+// BF16x3 synthesis.  The spin-frame form divides the synthesised sums by
+// sin(theta), which near the poles amplifies the rounding of the contraction by
+// up to 1/sin(theta) ~ L; the first tile (the 64 ring pairs nearest the poles:
+// pairs are sorted by increasing sin(theta)) therefore runs on the binary32
+// MFMA path.
 __global__ __launch_bounds__(256) void k_leg_adj_bf16x3(LegArgs<float> A) {
     extern __shared__ unsigned char smem_raw[];
     const int nw = blockDim.x >> 6;
@@ -1105,10 +1300,10 @@ struct CoefArgs {
 constexpr int kTM = 16, kTL = 32;
 
 template <typename real>
-__global__ __launch_bounds__(256) void k_recombine(CoefArgs<real> A) {
+__device__ __forceinline__ void recombine_body(const CoefArgs<real> &A, int bx, int by) {
     __shared__ real fs[kTM][kTL + 2][8 + 1];  // F rows l0-1 .. l0+kTL, 8 reals (+1 pad)
     const int L = A.L;
-    const int l0 = 1 + blockIdx.x * kTL, m0 = blockIdx.y * kTM;
+    const int l0 = 1 + bx * kTL, m0 = by * kTM;
     if (m0 > L || m0 > l0 + kTL - 1) return;
     for (int idx = threadIdx.x; idx < kTM * (kTL + 2) * 8; idx += blockDim.x) {
         const int c = idx & 7, i = (idx >> 3) % (kTL + 2), mi = (idx >> 3) / (kTL + 2);
@@ -1158,11 +1353,16 @@ __global__ __launch_bounds__(256) void k_recombine(CoefArgs<real> A) {
 // with at = a / sqrt(l(l+1)) (zero outside 1 <= l <= L, |mu| <= l).
 // ---------------------------------------------------------------------------
 template <typename real>
-__global__ __launch_bounds__(256) void k_prep(CoefArgs<real> A) {
+__global__ __launch_bounds__(256) void k_recombine(CoefArgs<real> A) {
+    recombine_body(A, blockIdx.x, blockIdx.y);
+}
+
+template <typename real>
+__device__ __forceinline__ void prep_body(const CoefArgs<real> &A, int bx, int by) {
     // coefficients of degrees l0-1 .. l0+kTL for the tile's orders: [l][m][sign][a,b]
     __shared__ C2<real> cs[kTL + 2][kTM][2][2];
     const int L = A.L;
-    const int l0 = blockIdx.x * kTL, m0 = blockIdx.y * kTM;  // l' in [l0, l0+kTL)
+    const int l0 = bx * kTL, m0 = by * kTM;  // l' in [l0, l0+kTL)
     if (m0 > L || m0 > l0 + kTL - 1) return;
     for (int idx = threadIdx.x; idx < (kTL + 2) * 2 * 2 * kTM; idx += blockDim.x) {
         const int mi = idx % kTM, r = idx / kTM;
@@ -1208,6 +1408,11 @@ __global__ __launch_bounds__(256) void k_prep(CoefArgs<real> A) {
             o[2 * sgn + 1] = gph;
         }
     }
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_prep(CoefArgs<real> A) {
+    prep_body(A, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -1311,18 +1516,123 @@ __global__ __launch_bounds__(64) void k_adj_scattered(ScatArgs<real> A) {
 }
 
 // ===========================================================================
-// launchers
+// Batched stages: one launch per stage (and per workgroup shape) covers every
+// field of a batch.  Workgroup i runs work item work[i] = (field, x, y) with the
+// field's own argument block; the bodies are those of the single-field kernels.
+// The first stage of each direction stamps its items' start and the last stage
+// its items' end (wall clock) into `stamp`, from which per-field latencies are
+// read.
 // ===========================================================================
-static size_t ring_lds_bytes(const Plan &p, size_t real_size) {
-    const size_t elems = 2 * p.max_nphi;
-    return kSmallTab * sizeof(CD) + (elems + elems / 16 + 1) * 2 * real_size;
+__device__ __forceinline__ void stamp_now(unsigned long long *stamp) {
+    if (stamp && threadIdx.x == 0) stamp[blockIdx.x] = wall_clock64();
 }
 
 template <typename real>
-static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, bool weighted,
-                               hipStream_t st) {
+__global__ __launch_bounds__(256) void kb_prep(const CoefArgs<real> *__restrict__ args,
+                                               const WorkItem *__restrict__ work,
+                                               unsigned long long *stamp) {
+    const WorkItem w = ld_const(work + blockIdx.x);
+    stamp_now(stamp);
+    const CoefArgs<real> A = ld_const(args + w.f);
+    prep_body(A, w.x, w.y);
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void kb_recombine(const CoefArgs<real> *__restrict__ args,
+                                                    const WorkItem *__restrict__ work,
+                                                    unsigned long long *stamp) {
+    const WorkItem w = ld_const(work + blockIdx.x);
+    const CoefArgs<real> A = ld_const(args + w.f);
+    recombine_body(A, w.x, w.y);
+    __syncthreads();
+    stamp_now(stamp);
+}
+
+template <typename real, int NT>
+__global__ __launch_bounds__(NT, 2) void kb_ring_fwd(const RingArgs<real> *__restrict__ args,
+                                                          const WorkItem *__restrict__ work,
+                                                          unsigned long long *stamp) {
+    extern __shared__ unsigned char smem_raw[];
+    const WorkItem w = ld_const(work + blockIdx.x);
+    stamp_now(stamp);
+    const RingArgs<real> A = ld_const(args + w.f);
+    ring_fwd_body<real, NT>(A, w.x, smem_raw);
+}
+
+template <typename real, int NT>
+__global__ __launch_bounds__(NT, 2) void kb_ring_adj(const RingArgs<real> *__restrict__ args,
+                                                          const WorkItem *__restrict__ work,
+                                                          unsigned long long *stamp) {
+    extern __shared__ unsigned char smem_raw[];
+    const WorkItem w = ld_const(work + blockIdx.x);
+    const RingArgs<real> A = ld_const(args + w.f);
+    ring_adj_body<real, NT>(A, w.x, smem_raw);
+    __syncthreads();
+    stamp_now(stamp);
+}
+
+// work item (field, m, -): every tile of the field's pairs in one workgroup
+template <typename real, bool kBf16>
+__global__ __launch_bounds__(1024) void kb_leg_fwd(const LegFwdArgs<real> *__restrict__ args,
+                                                   const WorkItem *__restrict__ work,
+                                                   unsigned long long *) {
+    extern __shared__ unsigned char smem_raw[];
+    const WorkItem w = ld_const(work + blockIdx.x);
+    const LegFwdArgs<real> A = ld_const(args + w.f);
+    if constexpr (kBf16)
+        leg_fwd_bf16x3_body(A, w.x, 0, smem_raw);
+    else
+        leg_fwd_body(A, w.x, 0, smem_raw);
+}
+
+// work item (field, tile group, m)
+template <typename real, bool kBf16>
+__global__ __launch_bounds__(256) void kb_leg_adj(const LegArgs<real> *__restrict__ args,
+                                                  const WorkItem *__restrict__ work,
+                                                  unsigned long long *) {
+    extern __shared__ unsigned char smem_raw[];
+    const WorkItem w = ld_const(work + blockIdx.x);
+    const LegArgs<real> A = ld_const(args + w.f);
+    const int nw = blockDim.x >> 6;
+    const int wave = uniform_int(threadIdx.x >> 6);
+    const int tile = w.x * nw + wave;
+    if (tile * kTileP >= A.NPT) return;
+    const int lane = threadIdx.x & 63;
+    if constexpr (kBf16) {
+        unsigned char *lds = smem_raw + wave * kAdjLdsPerWave;
+        if (tile == 0)
+            adj_tile_mfma<float, float>(A, w.y, tile, lane, reinterpret_cast<float *>(lds));
+        else
+            adj_tile_bf16x3(A, w.y, tile, lane, reinterpret_cast<u32x4_t *>(lds));
+    } else {
+        real *qt = reinterpret_cast<real *>(smem_raw) + wave * kRowsB * kTileP;
+        adj_tile_mfma<real, real>(A, w.y, tile, lane, qt);
+    }
+}
+
+template <typename real>
+__global__ __launch_bounds__(64) void kb_equator_adj(const LegArgs<real> *__restrict__ args,
+                                                     const WorkItem *__restrict__ work,
+                                                     unsigned long long *) {
+    const WorkItem w = ld_const(work + blockIdx.x);
+    const LegArgs<real> A = ld_const(args + w.f);
+    equator_adj_body(A, w.x);
+}
+
+// ===========================================================================
+// launchers
+// ===========================================================================
+static size_t ring_lds_bytes_len(int64_t len, size_t real_size) {
+    const size_t elems = 2 * (size_t)len;
+    return kSmallTab * sizeof(CD) + (elems + elems / 16 + 1) * 2 * real_size;
+}
+static size_t ring_lds_bytes(const Plan &p, size_t real_size) { return ring_lds_bytes_len(p.max_fft_len, real_size); }
+
+template <typename real>
+static RingArgs<real> make_ring_args(const Plan &p, const void *Tin, void *Tout, bool weighted) {
     RingArgs<real> R{};
-    R.Tin = static_cast<const C2<real> *>(T);
+    R.Tin = static_cast<const C2<real> *>(Tin);
+    R.Tout = static_cast<C2<real> *>(Tout);
     R.weights = p.d_weights;
     R.buf = static_cast<C2<real> *>(p.d_pb);
     R.rings = p.d_rings;
@@ -1330,15 +1640,16 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
     R.tw = p.d_tw;
     R.L = p.L;
     R.NP = (int)p.n_pairs;
+    R.NR = (int)p.n_rings;
     R.weighted = weighted ? 1 : 0;
-    const size_t lds = ring_lds_bytes(p, sizeof(real));
-    {
-        StageScope sc(p, VSHT_STAGE_RING_FWD, st);
-        hipLaunchKernelGGL(k_ring_fwd<real>, dim3((unsigned)p.n_rings), dim3(kRingNT), lds, st, R);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return R;
+}
 
+static int pairs_in_tiles(const Plan &p) { return (int)(p.n_pairs - (p.eq_ring >= 0 ? 1 : 0)); }
+static int tiles_of(const Plan &p) { return (pairs_in_tiles(p) + kTileP - 1) / kTileP; }
+
+template <typename real>
+static LegFwdArgs<real> make_leg_fwd_args(const Plan &p, int atomic) {
     LegFwdArgs<real> G{};
     G.RB = static_cast<const real *>(p.d_pb);
     G.F = static_cast<real *>(p.d_fg);
@@ -1349,40 +1660,88 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
     G.cscale = p.d_cscale;
     G.L = p.L;
     G.NP = (int)p.n_pairs;
-    G.NPT = (int)(p.n_pairs - (p.eq_ring >= 0 ? 1 : 0));
+    G.NPT = pairs_in_tiles(p);
     G.NR = (int)p.n_rings;
     G.eq_ring = p.eq_ring;
+    G.atomic = atomic;
+    return G;
+}
+
+template <typename real>
+static LegArgs<real> make_leg_adj_args(const Plan &p) {
+    LegArgs<real> G{};
+    G.FG = static_cast<const real *>(p.d_fg);
+    G.PB = static_cast<real *>(p.d_pb);
+    G.seeds = p.d_seeds;
+    G.pz = p.d_pair_z;
+    G.aprime = p.d_aprime;
+    G.L = p.L;
+    G.NP = (int)p.n_pairs;
+    G.NPT = pairs_in_tiles(p);
+    return G;
+}
+
+// recombine (forward): FG -> aout, bout;  prep (adjoint): ain, bin -> FG
+template <typename real>
+static CoefArgs<real> make_coef_args(const Plan &p, const void *ain, const void *bin, void *aout, void *bout) {
+    CoefArgs<real> C{};
+    C.FG = static_cast<const C2<real> *>(p.d_fg);
+    C.FGout = static_cast<C2<real> *>(p.d_fg);
+    C.ain = static_cast<const C2<real> *>(ain);
+    C.bin = static_cast<const C2<real> *>(bin);
+    C.aout = static_cast<C2<real> *>(aout);
+    C.bout = static_cast<C2<real> *>(bout);
+    C.cscale = p.d_cscale;
+    C.etab = p.d_etab;
+    C.rsq = p.d_rsq;
+    C.L = p.L;
+    return C;
+}
+
+static size_t leg_fwd_lds(int nw, size_t rsz) { return (size_t)nw * (kRowsB * kTileP + 2 * 128) * rsz; }
+static size_t leg_adj_lds(int nw, size_t rsz, bool bf16) {
+    return (size_t)nw * (bf16 ? (size_t)kAdjLdsPerWave : (size_t)kRowsB * kTileP * rsz);
+}
+
+template <typename real>
+static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, bool weighted,
+                               hipStream_t st) {
+    const bool bf16 = p.precision == VSHT_BF16X3;
+    const RingArgs<real> R = make_ring_args<real>(p, T, nullptr, weighted);
     {
-        const int ntile = (G.NPT + kTileP - 1) / kTileP;
+        StageScope sc(p, VSHT_STAGE_RING_FWD, st);
+        if (p.ring_nt_min == kRingNTSmall && p.max_fft_len <= kMaxLenSmallRing)
+            hipLaunchKernelGGL((k_ring_fwd<real, kRingNTSmall>), dim3((unsigned)p.n_rings), dim3(kRingNTSmall),
+                               ring_lds_bytes(p, sizeof(real)), st, R);
+        else
+            hipLaunchKernelGGL((k_ring_fwd<real, kRingNT>), dim3((unsigned)p.n_rings), dim3(kRingNT),
+                               ring_lds_bytes(p, sizeof(real)), st, R);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    {
+        const int ntile = tiles_of(p);
         const int ngroup = ntile > 16 ? (ntile + 15) / 16 : 1;  // at most 16 waves per workgroup
         const int nw = ntile > 0 ? (ntile + ngroup - 1) / ngroup : 1;
-        G.atomic = ngroup > 1 ? 1 : 0;
+        const LegFwdArgs<real> G = make_leg_fwd_args<real>(p, ngroup > 1 ? 1 : 0);
         StageScope sc(p, VSHT_STAGE_LEG_FWD, st);
         if (G.atomic) {
             e = hipMemsetAsync(p.d_fg, 0, (size_t)p.tri_size * 8 * sizeof(real), st);
             if (e != hipSuccess) return e;
         }
-        const size_t lds2 = (size_t)nw * (kRowsB * kTileP + 2 * 128) * sizeof(real);
+        const dim3 grid(p.L + 1, ngroup);
         if constexpr (sizeof(real) == 4) {
-            if (p.precision == VSHT_BF16X3) {
-                hipLaunchKernelGGL(k_leg_fwd_bf16x3, dim3(p.L + 1, ngroup), dim3(nw * 64), lds2, st, G);
-            } else {
-                hipLaunchKernelGGL(k_leg_fwd_mfma<real>, dim3(p.L + 1, ngroup), dim3(nw * 64), lds2, st, G);
-            }
+            if (bf16)
+                hipLaunchKernelGGL(k_leg_fwd_bf16x3, grid, dim3(nw * 64), leg_fwd_lds(nw, 4), st, G);
+            else
+                hipLaunchKernelGGL(k_leg_fwd_mfma<real>, grid, dim3(nw * 64), leg_fwd_lds(nw, 4), st, G);
         } else {
-            hipLaunchKernelGGL(k_leg_fwd_mfma<real>, dim3(p.L + 1, ngroup), dim3(nw * 64), lds2, st, G);
+            hipLaunchKernelGGL(k_leg_fwd_mfma<real>, grid, dim3(nw * 64), leg_fwd_lds(nw, 8), st, G);
         }
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-
-    CoefArgs<real> C{};
-    C.FG = static_cast<const C2<real> *>(p.d_fg);
-    C.aout = static_cast<C2<real> *>(a);
-    C.bout = static_cast<C2<real> *>(b);
-    C.etab = p.d_etab;
-    C.rsq = p.d_rsq;
-    C.L = p.L;
+    const CoefArgs<real> C = make_coef_args<real>(p, nullptr, nullptr, a, b);
     {
         StageScope sc(p, VSHT_STAGE_RECOMBINE, st);
         hipLaunchKernelGGL(k_recombine<real>, dim3((p.L + kTL - 1) / kTL, (p.L + 1 + kTM - 1) / kTM),
@@ -1394,14 +1753,8 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
 template <typename real>
 static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void *T, bool weighted,
                                hipStream_t st) {
-    CoefArgs<real> C{};
-    C.ain = static_cast<const C2<real> *>(a);
-    C.bin = static_cast<const C2<real> *>(b);
-    C.FGout = static_cast<C2<real> *>(p.d_fg);
-    C.cscale = p.d_cscale;
-    C.etab = p.d_etab;
-    C.rsq = p.d_rsq;
-    C.L = p.L;
+    const bool bf16 = p.precision == VSHT_BF16X3;
+    const CoefArgs<real> C = make_coef_args<real>(p, a, b, nullptr, nullptr);
     {
         StageScope sc(p, VSHT_STAGE_PREP, st);
         hipLaunchKernelGGL(k_prep<real>, dim3((p.L + 2 + kTL - 1) / kTL, (p.L + 1 + kTM - 1) / kTM),
@@ -1427,30 +1780,20 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
         return hipGetLastError();
     }
 
-    LegArgs<real> G{};
-    G.FG = static_cast<const real *>(p.d_fg);
-    G.PB = static_cast<real *>(p.d_pb);
-    G.seeds = p.d_seeds;
-    G.pz = p.d_pair_z;
-    G.aprime = p.d_aprime;
-    G.L = p.L;
-    G.NP = (int)p.n_pairs;
-    G.NPT = (int)(p.n_pairs - (p.eq_ring >= 0 ? 1 : 0));
+    const LegArgs<real> G = make_leg_adj_args<real>(p);
     {
         StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
-        const int ntile = (G.NPT + kTileP - 1) / kTileP;
+        const int ntile = tiles_of(p);
         if (ntile > 0) {
             const int nw = ntile < 4 ? ntile : 4;
             const dim3 grid((ntile + nw - 1) / nw, p.L + 1);
-            const size_t lds2 = (size_t)nw * (sizeof(real) == 4 ? kAdjLdsPerWave : kRowsB * kTileP * sizeof(real));
             if constexpr (sizeof(real) == 4) {
-                if (p.precision == VSHT_BF16X3)
-                    hipLaunchKernelGGL(k_leg_adj_bf16x3, grid, dim3(nw * 64), lds2, st, G);
+                if (bf16)
+                    hipLaunchKernelGGL(k_leg_adj_bf16x3, grid, dim3(nw * 64), leg_adj_lds(nw, 4, true), st, G);
                 else
-                    hipLaunchKernelGGL(k_leg_adj_mfma<real>, grid, dim3(nw * 64),
-                                       (size_t)nw * kRowsB * kTileP * sizeof(real), st, G);
+                    hipLaunchKernelGGL(k_leg_adj_mfma<real>, grid, dim3(nw * 64), leg_adj_lds(nw, 4, false), st, G);
             } else {
-                hipLaunchKernelGGL(k_leg_adj_mfma<real>, grid, dim3(nw * 64), lds2, st, G);
+                hipLaunchKernelGGL(k_leg_adj_mfma<real>, grid, dim3(nw * 64), leg_adj_lds(nw, 8, false), st, G);
             }
         }
         if (p.eq_ring >= 0)
@@ -1459,20 +1802,15 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
     e = hipGetLastError();
     if (e != hipSuccess) return e;
 
-    RingArgs<real> R{};
-    R.Tout = static_cast<C2<real> *>(T);
-    R.weights = p.d_weights;
-    R.weighted = weighted ? 1 : 0;
-    R.buf = static_cast<C2<real> *>(p.d_pb);
-    R.rings = p.d_rings;
-    R.ffts = p.d_ffts;
-    R.tw = p.d_tw;
-    R.L = p.L;
-    R.NP = (int)p.n_pairs;
-    const size_t lds = ring_lds_bytes(p, sizeof(real));
+    const RingArgs<real> R = make_ring_args<real>(p, nullptr, T, weighted);
     {
         StageScope sc(p, VSHT_STAGE_RING_ADJ, st);
-        hipLaunchKernelGGL(k_ring_adj<real>, dim3((unsigned)p.n_rings), dim3(kRingNT), lds, st, R);
+        if (p.ring_nt_min == kRingNTSmall && p.max_fft_len <= kMaxLenSmallRing)
+            hipLaunchKernelGGL((k_ring_adj<real, kRingNTSmall>), dim3((unsigned)p.n_rings), dim3(kRingNTSmall),
+                               ring_lds_bytes(p, sizeof(real)), st, R);
+        else
+            hipLaunchKernelGGL((k_ring_adj<real, kRingNT>), dim3((unsigned)p.n_rings), dim3(kRingNT),
+                               ring_lds_bytes(p, sizeof(real)), st, R);
     }
     return hipGetLastError();
 }
@@ -1489,6 +1827,347 @@ hipError_t launch_adjoint(const Plan &p, const void *a, const void *b, void *T, 
     return adjoint_impl<float>(p, a, b, T, weighted, st);
 }
 
+// ===========================================================================
+// Batches
+// ===========================================================================
+enum BatchStage { BS_PREP, BS_LEG_ADJ, BS_EQUATOR, BS_RING_ADJ, BS_RING_FWD, BS_LEG_FWD, BS_RECOMBINE };
+static bool stage_is_adjoint(int s) { return s <= BS_RING_ADJ; }
+
+struct BatchState {
+    std::vector<const Plan *> f;
+    int precision = VSHT_FP64;
+    size_t rsz = 8;
+    BatchConfig cfg;
+    // per-field argument blocks, host copies and device tables
+    std::vector<unsigned char> h_prep, h_ladj, h_radj, h_rfwd, h_lfwd, h_rec;
+    void *d_prep = nullptr, *d_ladj = nullptr, *d_radj = nullptr, *d_rfwd = nullptr,
+         *d_lfwd = nullptr, *d_rec = nullptr;
+    // work lists: launches in execution order (adjoint stages, then forward)
+    struct Launch {
+        int stage;
+        int nw;
+        int64_t off, cnt;
+        size_t lds;
+    };
+    std::vector<WorkItem> work;
+    std::vector<Launch> launches;
+    WorkItem *d_work = nullptr;
+    size_t d_work_cap = 0;
+    unsigned long long *d_stamp = nullptr;
+    size_t d_stamp_cap = 0;
+};
+
+template <typename T>
+static hipError_t alloc_table(void **d, std::vector<unsigned char> &h, size_t count) {
+    h.assign(sizeof(T) * count, 0);
+    return hipMalloc(d, h.size());
+}
+
+template <typename real>
+static hipError_t batch_alloc_args(BatchState *b) {
+    const size_t F = b->f.size();
+    hipError_t e;
+    if ((e = alloc_table<CoefArgs<real>>(&b->d_prep, b->h_prep, F)) != hipSuccess) return e;
+    if ((e = alloc_table<LegArgs<real>>(&b->d_ladj, b->h_ladj, F)) != hipSuccess) return e;
+    if ((e = alloc_table<RingArgs<real>>(&b->d_radj, b->h_radj, F)) != hipSuccess) return e;
+    if ((e = alloc_table<RingArgs<real>>(&b->d_rfwd, b->h_rfwd, F)) != hipSuccess) return e;
+    if ((e = alloc_table<LegFwdArgs<real>>(&b->d_lfwd, b->h_lfwd, F)) != hipSuccess) return e;
+    if ((e = alloc_table<CoefArgs<real>>(&b->d_rec, b->h_rec, F)) != hipSuccess) return e;
+    // the buffer-independent blocks
+    auto *la = reinterpret_cast<LegArgs<real> *>(b->h_ladj.data());
+    auto *lf = reinterpret_cast<LegFwdArgs<real> *>(b->h_lfwd.data());
+    for (size_t i = 0; i < F; ++i) {
+        la[i] = make_leg_adj_args<real>(*b->f[i]);
+        lf[i] = make_leg_fwd_args<real>(*b->f[i], 0);
+    }
+    if ((e = hipMemcpy(b->d_ladj, b->h_ladj.data(), b->h_ladj.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+    return hipMemcpy(b->d_lfwd, b->h_lfwd.data(), b->h_lfwd.size(), hipMemcpyHostToDevice);
+}
+
+hipError_t batch_create(const std::vector<const Plan *> &fields, BatchState **out) {
+    *out = nullptr;
+    auto *b = new (std::nothrow) BatchState();
+    if (!b) return hipErrorOutOfMemory;
+    b->f = fields;
+    b->precision = fields.empty() ? VSHT_FP64 : fields[0]->precision;
+    b->rsz = b->precision == VSHT_FP64 ? 8 : 4;
+    hipError_t e = b->precision == VSHT_FP64 ? batch_alloc_args<double>(b) : batch_alloc_args<float>(b);
+    if (e == hipSuccess) e = batch_configure(b, BatchConfig{});
+    if (e != hipSuccess) {
+        batch_destroy(b);
+        return e;
+    }
+    *out = b;
+    return hipSuccess;
+}
+
+void batch_destroy(BatchState *b) {
+    if (!b) return;
+    void *ptrs[] = {b->d_prep, b->d_ladj, b->d_radj, b->d_rfwd, b->d_lfwd, b->d_rec, b->d_work, b->d_stamp};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    delete b;
+}
+
+BatchConfig batch_config(const BatchState *b) { return b->cfg; }
+
+// Work lists for a configuration.  Item costs (for the longest-first order):
+// ring stages n_phi, Legendre stages (degrees of the order) x (tiles in the
+// workgroup), coefficient tiles 1.
+hipError_t batch_configure(BatchState *b, const BatchConfig &cfg) {
+    if (cfg.adj_nw != 1 && cfg.adj_nw != 2 && cfg.adj_nw != 4) return hipErrorInvalidValue;
+    if (cfg.ring_nt != kRingNTSmall && cfg.ring_nt != kRingNT) return hipErrorInvalidValue;
+    b->cfg = cfg;
+    b->work.clear();
+    b->launches.clear();
+    const size_t rsz = b->rsz;
+    const bool bf16 = b->precision == VSHT_BF16X3;
+    struct Item {
+        WorkItem w;
+        double cost;
+    };
+    auto emit = [&](int stage, int nw, std::vector<Item> &items, size_t lds) {
+        if (items.empty()) return;
+        if (cfg.lpt)
+            std::stable_sort(items.begin(), items.end(),
+                             [](const Item &x, const Item &y) { return x.cost > y.cost; });
+        BatchState::Launch l{stage, nw, (int64_t)b->work.size(), (int64_t)items.size(), lds};
+        for (auto &it : items) b->work.push_back(it.w);
+        b->launches.push_back(l);
+    };
+    const int F = (int)b->f.size();
+    std::vector<Item> items;
+    // prep
+    for (int i = 0; i < F; ++i) {
+        const int L = b->f[i]->L;
+        for (int by = 0; by * kTM <= L; ++by)
+            for (int bx = 0; bx * kTL < L + 2; ++bx)
+                if (!(by * kTM > bx * kTL + kTL - 1)) items.push_back({{i, bx, by, 0}, 1.0});
+    }
+    emit(BS_PREP, 4, items, 0);
+    items.clear();
+    // Legendre synthesis: one shape for every field
+    size_t lds_adj = leg_adj_lds(cfg.adj_nw, rsz, bf16);
+    for (int i = 0; i < F; ++i) {
+        const Plan &p = *b->f[i];
+        const int ntile = tiles_of(p);
+        for (int tg = 0; tg * cfg.adj_nw < ntile; ++tg) {
+            const int nt = std::min(cfg.adj_nw, ntile - tg * cfg.adj_nw);
+            for (int m = 0; m <= p.L; ++m) items.push_back({{i, tg, m, 0}, (double)(p.L + 2 - m) * nt});
+        }
+    }
+    emit(BS_LEG_ADJ, cfg.adj_nw, items, lds_adj);
+    items.clear();
+    for (int i = 0; i < F; ++i)
+        if (b->f[i]->eq_ring >= 0)
+            for (int m = 0; m <= b->f[i]->L; ++m) items.push_back({{i, m, 0, 0}, (double)(b->f[i]->L + 2 - m)});
+    emit(BS_EQUATOR, 1, items, 0);
+    items.clear();
+    // ring stages: one launch per class of stored DFT length (its LDS size) and
+    // workgroup width; fields whose length exceeds the narrow width's limit use 512
+    const int64_t bounds[] = {256, 512, 1024, 2048, 1 << 30};
+    for (int dir = 0; dir < 2; ++dir) {
+        int64_t lo = 0;
+        for (int64_t hi : bounds) {
+            for (int nt : {kRingNTSmall, kRingNT}) {
+                int64_t maxlen = 0;
+                for (int i = 0; i < F; ++i) {
+                    const Plan &p = *b->f[i];
+                    if (p.max_fft_len <= lo || p.max_fft_len > hi) continue;
+                    const int want = (cfg.ring_nt == kRingNTSmall && p.ring_nt_min == kRingNTSmall &&
+                                      p.max_fft_len <= kMaxLenSmallRing)
+                                         ? kRingNTSmall : kRingNT;
+                    if (want != nt) continue;
+                    maxlen = std::max(maxlen, p.max_fft_len);
+                    for (int r = 0; r < p.n_rings; ++r) items.push_back({{i, r, 0, 0}, (double)p.max_fft_len});
+                }
+                emit(dir == 0 ? BS_RING_ADJ : BS_RING_FWD, nt / 64, items, ring_lds_bytes_len(maxlen, rsz));
+                items.clear();
+            }
+            lo = hi;
+        }
+    }
+    // Legendre analysis: one workgroup per (field, m) holding all of the field's
+    // tiles; fields grouped by tile count, or merged into the widest shape
+    int maxt = 1;
+    for (int i = 0; i < F; ++i) maxt = std::max(maxt, std::max(1, tiles_of(*b->f[i])));
+    for (int nw = 1; nw <= maxt; ++nw) {
+        for (int i = 0; i < F; ++i) {
+            const Plan &p = *b->f[i];
+            const int nt = std::max(1, tiles_of(p));
+            if (!cfg.fwd_merge && nt != nw) continue;
+            if (cfg.fwd_merge && nw != maxt) continue;
+            for (int m = 0; m <= p.L; ++m) items.push_back({{i, m, 0, 0}, (double)(p.L + 2 - m) * nt});
+        }
+        emit(BS_LEG_FWD, nw, items, leg_fwd_lds(nw, rsz));
+        items.clear();
+    }
+    // recombine
+    for (int i = 0; i < F; ++i) {
+        const int L = b->f[i]->L;
+        for (int by = 0; by * kTM <= L; ++by)
+            for (int bx = 0; bx * kTL < L; ++bx)
+                if (!(by * kTM > 1 + bx * kTL + kTL - 1)) items.push_back({{i, bx, by, 0}, 1.0});
+    }
+    emit(BS_RECOMBINE, 4, items, 0);
+    // device copies
+    const size_t need = b->work.size();
+    if (need > b->d_work_cap) {
+        if (b->d_work) (void)hipFree(b->d_work);
+        if (b->d_stamp) (void)hipFree(b->d_stamp);
+        b->d_work = nullptr;
+        b->d_stamp = nullptr;
+        b->d_work_cap = b->d_stamp_cap = 0;
+        hipError_t e = hipMalloc((void **)&b->d_work, need * sizeof(WorkItem));
+        if (e != hipSuccess) return e;
+        b->d_work_cap = need;
+        e = hipMalloc((void **)&b->d_stamp, need * sizeof(unsigned long long));
+        if (e != hipSuccess) return e;
+        b->d_stamp_cap = need;
+    }
+    return hipMemcpy(b->d_work, b->work.data(), need * sizeof(WorkItem), hipMemcpyHostToDevice);
+}
+
+template <typename real>
+static void fill_adjoint_args(BatchState *b, const void *const *a, const void *const *bb, void *const *T) {
+    auto *pr = reinterpret_cast<CoefArgs<real> *>(b->h_prep.data());
+    auto *ra = reinterpret_cast<RingArgs<real> *>(b->h_radj.data());
+    for (size_t i = 0; i < b->f.size(); ++i) {
+        pr[i] = make_coef_args<real>(*b->f[i], a[i], bb[i], nullptr, nullptr);
+        ra[i] = make_ring_args<real>(*b->f[i], nullptr, T[i], false);
+    }
+}
+
+template <typename real>
+static void fill_forward_args(BatchState *b, const void *const *T, void *const *a, void *const *bb) {
+    auto *rf = reinterpret_cast<RingArgs<real> *>(b->h_rfwd.data());
+    auto *rc = reinterpret_cast<CoefArgs<real> *>(b->h_rec.data());
+    for (size_t i = 0; i < b->f.size(); ++i) {
+        rf[i] = make_ring_args<real>(*b->f[i], T[i], nullptr, true);
+        rc[i] = make_coef_args<real>(*b->f[i], nullptr, nullptr, a[i], bb[i]);
+    }
+}
+
+// Upload the argument blocks that hold the caller's buffers (synchronous on st).
+hipError_t batch_bind_adjoint(BatchState *b, const void *const *a, const void *const *bb, void *const *T,
+                              hipStream_t st) {
+    if (b->precision == VSHT_FP64) fill_adjoint_args<double>(b, a, bb, T);
+    else fill_adjoint_args<float>(b, a, bb, T);
+    hipError_t e = hipMemcpyAsync(b->d_prep, b->h_prep.data(), b->h_prep.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_radj, b->h_radj.data(), b->h_radj.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
+}
+
+hipError_t batch_bind_forward(BatchState *b, const void *const *T, void *const *a, void *const *bb,
+                              hipStream_t st) {
+    if (b->precision == VSHT_FP64) fill_forward_args<double>(b, T, a, bb);
+    else fill_forward_args<float>(b, T, a, bb);
+    hipError_t e = hipMemcpyAsync(b->d_rfwd, b->h_rfwd.data(), b->h_rfwd.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_rec, b->h_rec.data(), b->h_rec.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
+}
+
+template <typename real, bool kBf16>
+static hipError_t batch_launch_impl(const BatchState *b, int dirs, hipStream_t st) {
+    for (const auto &l : b->launches) {
+        const bool adj = stage_is_adjoint(l.stage);
+        if (adj && !(dirs & 1)) continue;
+        if (!adj && !(dirs & 2)) continue;
+        const WorkItem *w = b->d_work + l.off;
+        unsigned long long *stamp = b->d_stamp + l.off;
+        const dim3 grid((unsigned)l.cnt);
+        switch (l.stage) {
+            case BS_PREP:
+                hipLaunchKernelGGL(kb_prep<real>, grid, dim3(256), 0, st,
+                                   static_cast<const CoefArgs<real> *>(b->d_prep), w, stamp);
+                break;
+            case BS_LEG_ADJ:
+                hipLaunchKernelGGL((kb_leg_adj<real, kBf16>), grid, dim3(64 * l.nw), l.lds, st,
+                                   static_cast<const LegArgs<real> *>(b->d_ladj), w, stamp);
+                break;
+            case BS_EQUATOR:
+                hipLaunchKernelGGL(kb_equator_adj<real>, grid, dim3(64), 0, st,
+                                   static_cast<const LegArgs<real> *>(b->d_ladj), w, stamp);
+                break;
+            case BS_RING_ADJ:
+                if (l.nw * 64 == kRingNTSmall)
+                    hipLaunchKernelGGL((kb_ring_adj<real, kRingNTSmall>), grid, dim3(kRingNTSmall), l.lds, st,
+                                       static_cast<const RingArgs<real> *>(b->d_radj), w, stamp);
+                else
+                    hipLaunchKernelGGL((kb_ring_adj<real, kRingNT>), grid, dim3(kRingNT), l.lds, st,
+                                       static_cast<const RingArgs<real> *>(b->d_radj), w, stamp);
+                break;
+            case BS_RING_FWD:
+                if (l.nw * 64 == kRingNTSmall)
+                    hipLaunchKernelGGL((kb_ring_fwd<real, kRingNTSmall>), grid, dim3(kRingNTSmall), l.lds, st,
+                                       static_cast<const RingArgs<real> *>(b->d_rfwd), w, stamp);
+                else
+                    hipLaunchKernelGGL((kb_ring_fwd<real, kRingNT>), grid, dim3(kRingNT), l.lds, st,
+                                       static_cast<const RingArgs<real> *>(b->d_rfwd), w, stamp);
+                break;
+            case BS_LEG_FWD:
+                hipLaunchKernelGGL((kb_leg_fwd<real, kBf16>), grid, dim3(64 * l.nw), l.lds, st,
+                                   static_cast<const LegFwdArgs<real> *>(b->d_lfwd), w, stamp);
+                break;
+            case BS_RECOMBINE:
+                hipLaunchKernelGGL(kb_recombine<real>, grid, dim3(256), 0, st,
+                                   static_cast<const CoefArgs<real> *>(b->d_rec), w, stamp);
+                break;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t batch_launch(const BatchState *b, int dirs, hipStream_t st) {
+    if (b->precision == VSHT_FP64) return batch_launch_impl<double, false>(b, dirs, st);
+    if (b->precision == VSHT_BF16X3) return batch_launch_impl<float, true>(b, dirs, st);
+    return batch_launch_impl<float, false>(b, dirs, st);
+}
+
+// Per-field first start and last end (device wall clock, microseconds) of the
+// stages of `dirs`, from the stamps of the last run.  Synchronous.
+hipError_t batch_field_times(const BatchState *b, int dirs, std::vector<double> &start_us,
+                             std::vector<double> &end_us) {
+    const size_t F = b->f.size();
+    std::vector<unsigned long long> st(b->work.size());
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess)
+        e = hipMemcpy(st.data(), b->d_stamp, st.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    int dev = 0, khz = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev)) != hipSuccess) return e;
+    const int first = (dirs & 1) ? BS_PREP : BS_RING_FWD;
+    const int last = (dirs & 2) ? BS_RECOMBINE : BS_RING_ADJ;
+    std::vector<unsigned long long> lo(F, ~0ull), hi(F, 0);
+    for (const auto &l : b->launches) {
+        if (l.stage != first && l.stage != last) continue;
+        for (int64_t k = 0; k < l.cnt; ++k) {
+            const WorkItem &w = b->work[l.off + k];
+            const unsigned long long t = st[l.off + k];
+            if (l.stage == first) lo[w.f] = std::min(lo[w.f], t);
+            if (l.stage == last) hi[w.f] = std::max(hi[w.f], t);
+        }
+    }
+    unsigned long long t0 = ~0ull;
+    for (size_t i = 0; i < F; ++i) t0 = std::min(t0, lo[i]);
+    start_us.resize(F);
+    end_us.resize(F);
+    const double us_per_tick = 1000.0 / (double)khz;
+    for (size_t i = 0; i < F; ++i) {
+        start_us[i] = (double)(lo[i] - t0) * us_per_tick;
+        end_us[i] = (double)(hi[i] - t0) * us_per_tick;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_seed_kernel(const double *pair_s, int NP, int L, double *seeds, hipStream_t st) {
     hipLaunchKernelGGL(k_seeds, dim3((NP + 127) / 128), dim3(128), 0, st, pair_s, NP, L, seeds);
     return hipGetLastError();
@@ -1497,13 +2176,28 @@ hipError_t launch_seed_kernel(const double *pair_s, int NP, int L, double *seeds
 hipError_t set_kernel_attributes() {
     hipError_t e;
     const int big = 160 * 1024;
-    e = hipFuncSetAttribute((const void *)k_ring_fwd<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    const void *batched[] = {(const void *)kb_ring_fwd<double, kRingNT>, (const void *)kb_ring_fwd<float, kRingNT>,
+                             (const void *)kb_ring_adj<double, kRingNT>, (const void *)kb_ring_adj<float, kRingNT>,
+                             (const void *)kb_ring_fwd<double, kRingNTSmall>,
+                             (const void *)kb_ring_fwd<float, kRingNTSmall>,
+                             (const void *)kb_ring_adj<double, kRingNTSmall>,
+                             (const void *)kb_ring_adj<float, kRingNTSmall>,
+                             (const void *)k_ring_fwd<double, kRingNTSmall>, (const void *)k_ring_fwd<float, kRingNTSmall>,
+                             (const void *)k_ring_adj<double, kRingNTSmall>, (const void *)k_ring_adj<float, kRingNTSmall>,
+                             (const void *)kb_leg_fwd<double, false>, (const void *)kb_leg_fwd<float, false>,
+                             (const void *)kb_leg_fwd<float, true>, (const void *)kb_leg_adj<double, false>,
+                             (const void *)kb_leg_adj<float, false>, (const void *)kb_leg_adj<float, true>};
+    for (const void *k : batched) {
+        e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+        if (e != hipSuccess) return e;
+    }
+    e = hipFuncSetAttribute((const void *)k_ring_fwd<double, kRingNT>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_ring_fwd<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = hipFuncSetAttribute((const void *)k_ring_fwd<float, kRingNT>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_ring_adj<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = hipFuncSetAttribute((const void *)k_ring_adj<double, kRingNT>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_ring_adj<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = hipFuncSetAttribute((const void *)k_ring_adj<float, kRingNT>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_leg_fwd_mfma<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
@@ -1514,8 +2208,6 @@ hipError_t set_kernel_attributes() {
     e = hipFuncSetAttribute((const void *)k_leg_fwd_bf16x3, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_leg_adj_bf16x3, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_leg_adj_fp32_polar64, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void *)k_leg_adj_mfma<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }

@@ -97,3 +97,34 @@ def test_many_null_arguments():
     assert lib.vsht_forward_many(None, 1, None, None, None, 0, None) == B.VSHT_EINVAL
     assert lib.vsht_adjoint_many(None, 1, None, None, None, 0, None) == B.VSHT_EINVAL
     assert b"NULL" in lib.vsht_last_error()
+
+
+def test_batch_plan_rejects_invalid():
+    """vsht_plan_batch validates every field before any device work."""
+    lib = v.load_library()
+    xyz = np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    w = np.ones(3)
+    h = ctypes.c_void_p()
+    L = (ctypes.c_int * 2)(4, 4)
+    n = (ctypes.c_int64 * 2)(3, 3)
+    X = (ctypes.c_void_p * 2)(xyz.ctypes.data, xyz.ctypes.data)
+    W = (ctypes.c_void_p * 2)(w.ctypes.data, w.ctypes.data)
+    assert lib.vsht_plan_batch(0, L, n, X, W, None, ctypes.byref(h)) == B.VSHT_EINVAL
+    assert lib.vsht_plan_batch(2, None, n, X, W, None, ctypes.byref(h)) == B.VSHT_EINVAL
+    Wnull = (ctypes.c_void_p * 2)(w.ctypes.data, None)
+    assert lib.vsht_plan_batch(2, L, n, X, Wnull, None, ctypes.byref(h)) == B.VSHT_EINVAL
+    assert b"field 1" in lib.vsht_last_error()
+    bad = xyz * 2.0
+    Xbad = (ctypes.c_void_p * 2)(xyz.ctypes.data, bad.ctypes.data)
+    assert lib.vsht_plan_batch(2, L, n, Xbad, W, None, ctypes.byref(h)) == B.VSHT_EINVAL
+    assert b"field 1" in lib.vsht_last_error()
+    assert not h.value
+
+
+def test_batch_calls_reject_null_plan():
+    lib = v.load_library()
+    assert lib.vsht_batch_roundtrip(None, None, None, None, None, None, None) == B.VSHT_EINVAL
+    assert lib.vsht_batch_adjoint(None, None, None, None, None) == B.VSHT_EINVAL
+    assert lib.vsht_batch_forward(None, None, None, None, None) == B.VSHT_EINVAL
+    assert lib.vsht_batch_set_config(None, 4, 0, 1, 256) == B.VSHT_EINVAL
+    assert lib.vsht_batch_field_times(None, None, None) == B.VSHT_EINVAL

@@ -219,3 +219,55 @@ def test_gl_L1024_sampled(torch, vsht, orc, precision, tol):
     e_rt = rel_l2(np.concatenate([ga, gb]), np.concatenate([a, b]))
     print("L=1024 %s adjoint %.3e forward %.3e roundtrip %.3e" % (precision, e_adj, e_fwd, e_rt))
     assert e_adj < tol and e_fwd < tol and e_rt < tol
+
+
+# ---------------------------------------------------------------------------
+# Ring lengths with a prime factor beyond the generic radix: Bluestein DFT.
+# GL grids at L = 66 (n_phi = 134 = 2 * 67) and L = 100 (202 = 2 * 101), a ring
+# grid with prime n_phi = 131 (and a shifted longitude origin), and a mixed
+# grid whose rings differ in length (generic and Bluestein in one plan).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["gl66", "gl100", "prime131", "mixed"])
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_bluestein_rings(torch, vsht, orc, case, precision, tol):
+    print_case("bluestein", case, precision)
+    if case == "gl66":
+        L = 66
+        xyz, w = vi.gl_grid(L)
+    elif case == "gl100":
+        L = 100
+        xyz, w = vi.gl_grid(L)
+    elif case == "prime131":
+        L = 60
+        nphi = 131
+        z, wz = vi.gl_nodes(L + 1)
+        ph = 2 * np.pi * np.arange(nphi) / nphi + 0.7
+        s = np.sqrt((1 - z) * (1 + z))
+        xyz = np.stack([np.outer(s, np.cos(ph)), np.outer(s, np.sin(ph)),
+                        np.outer(z, np.ones(nphi))], axis=-1).reshape(-1, 3)
+        w = np.repeat(wz * 2 * np.pi / nphi, nphi)
+    else:
+        L = 40
+        z, wz = vi.gl_nodes(L + 1)
+        lens = [82 if k % 2 == 0 else 89 for k in range(L + 1)]  # 89 is prime
+        # mirror rings must have the same length for the grid to stay exact
+        lens = [lens[min(k, L - k)] for k in range(L + 1)]
+        pts, wts = [], []
+        for k in range(L + 1):
+            nphi = lens[k]
+            ph = 2 * np.pi * np.arange(nphi) / nphi
+            sk = np.sqrt((1 - z[k]) * (1 + z[k]))
+            pts.append(np.stack([sk * np.cos(ph), sk * np.sin(ph), np.full(nphi, z[k])], axis=1))
+            wts.append(np.full(nphi, wz[k] * 2 * np.pi / nphi))
+        xyz, w = np.concatenate(pts), np.concatenate(wts)
+    plan = vsht.Plan(L, xyz, w, precision=precision)
+    assert plan.kind == "rings"
+    a, b = vi.random_coeffs(L, 17)
+    T = run_adjoint(torch, plan, a, b)
+    e_adj = rel_l2(T, orc.adjoint(L, a, b, xyz))
+    Tr = vi.random_field(len(w), 18)
+    ga, gb = run_forward(torch, plan, Tr)
+    a_ref, b_ref = orc.forward(L, xyz, w, Tr)
+    e_fwd = rel_l2(np.concatenate([ga, gb]), np.concatenate([a_ref, b_ref]))
+    print("bluestein %s %s adjoint %.3e forward %.3e" % (case, precision, e_adj, e_fwd))
+    assert e_adj < tol and e_fwd < tol
