@@ -88,6 +88,51 @@ def stage_profile(torch, plan, a, b, reps):
     return {k: (ms / c if c else 0.0) for k, (ms, c) in st.items() if c}
 
 
+def run_l256(torch, vsht, vi, args):
+    """L = 256: GL grid 257 x 514 forward+adjoint (FP64, FP32) and the adjoint at M = 4 L^2
+    = 262,144 points uniform on the sphere with weights 4 pi / M (FP64, FP32), coefficients
+    scaled 1/sqrt(l(l+1)); errors on sampled outputs against the oracle unless --no-oracle."""
+    dev = torch.device("cuda", 0)
+    L = 256
+    a_np, b_np = vi.random_coeffs(L, 0, scale="inv_sqrt_ll1")
+    xyz, w = vi.gl_grid(L)
+    sx, _ = vi.uniform_points(4 * L * L, 2)
+    sw = np.full(len(sx), 4 * np.pi / len(sx))
+    pidx = vi.sample_indices(len(sx), 64, 3)
+    ref = None
+    if not args.no_oracle:
+        import oracle
+        oracle.build(force=False)
+        ref = oracle.adjoint(L, a_np, b_np, sx[pidx])
+    out = {}
+    for prec in ("fp64", "fp32"):
+        cdt = torch.complex128 if prec == "fp64" else torch.complex64
+        a = torch.from_numpy(a_np).to(dev, cdt)
+        b = torch.from_numpy(b_np).to(dev, cdt)
+        plan = vsht.Plan(L, xyz, w, precision=prec)
+        sec, T, a2, b2 = time_steps(torch, plan, a, b, args.steps, args.warmup)
+        rt = rel_l2(np.concatenate([a2.cpu().numpy(), b2.cpu().numpy()]), np.concatenate([a_np, b_np]))
+        plan.close()
+        sp = vsht.Plan(L, sx, sw, precision=prec)
+        for _ in range(args.warmup):
+            Ts = sp.adjoint(a, b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            Ts = sp.adjoint(a, b)
+        torch.cuda.synchronize()
+        ssec = (time.perf_counter() - t0) / args.steps
+        r = {"gl_ms_per_fwd_adj": round(sec * 1e3, 4), "gl_roundtrip_rel_l2": rt,
+             "scattered_points": len(sx), "scattered_ms_per_adjoint": round(ssec * 1e3, 4),
+             "scattered_points_per_s": round(len(sx) / ssec, 1), "nfft_grid": sp.info()["nfft_grid"]}
+        if ref is not None:
+            r["scattered_adjoint_vs_oracle_rel_l2"] = rel_l2(Ts.cpu().numpy()[pidx].astype(np.complex128), ref)
+        sp.close()
+        out[prec] = r
+        log("L=256 %s: GL fwd+adj %.3f ms, scattered adjoint %.3f ms" % (prec, sec * 1e3, ssec * 1e3))
+    return out
+
+
 def run_batched(torch, vsht, vi, args):
     """Many fields of uneven bandlimit, each on its own GL grid (L+1) x (2L+2), complex64,
     coefficients scaled 1/l: adjoint then forward of every field, one graph replay."""
@@ -200,6 +245,8 @@ def main():
     ap.add_argument("--oracle-points", type=int, default=512)
     ap.add_argument("--no-oracle", action="store_true")
     ap.add_argument("--precisions", default="fp64,fp32,bf16x3")
+    ap.add_argument("--l256", type=int, default=1,
+                    help="also time L=256: GL 257 x 514 forward+adjoint and the adjoint at 4 L^2 scattered points")
     ap.add_argument("--batch-fields", type=int, default=256,
                     help="batched workload: this many complex64 fields, L uniform in [32, 512] (0: skip)")
     ap.add_argument("--grad-fields", type=int, default=8,
@@ -258,6 +305,9 @@ def main():
         del T, a2, b2, ga, gb
         plan.close()
 
+    l256 = None
+    if args.l256:
+        l256 = run_l256(torch, vsht, vi, args)
     batched = None
     if args.batch_fields > 0:
         batched = run_batched(torch, vsht, vi, args)
@@ -383,6 +433,8 @@ def main():
         variants[prec] = v
     if variants:
         out["variants"] = variants
+    if l256:
+        out["L256"] = l256
     if batched:
         out["batched"] = batched
     if differentiable:

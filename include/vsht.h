@@ -46,6 +46,15 @@
  * z values are exact negatives of each other are paired (north/south).  The
  * Gauss-Legendre product grids of Section 5.1 are of this kind.  Other point
  * sets are "scattered": they are accepted for the adjoint only.
+ *
+ * Scattered points (the arbitrary points of eq. (expan)) are evaluated through
+ * the double Fourier sphere: the synthesis runs on equispaced colatitudes of
+ * the doubled circle, a DFT in theta gives the exact 2-D Fourier coefficients
+ * of the spin-frame components, and every point gathers a window of an
+ * oversampled grid with the exponential-of-semicircle kernel (width 14 grid
+ * points in binary64, 8 otherwise; relative error near 1e-13 resp. 1e-6).
+ * VSHT_OPT_SCATTERED_DIRECT selects the direct O(n L^2) evaluation instead; L
+ * above 700 always uses it.
  */
 #ifndef VSHT_H
 #define VSHT_H
@@ -75,9 +84,16 @@ typedef enum {
                         binary32 accumulation, binary64 Legendre recurrence */
 } vsht_precision;
 
+/* Flags of vsht_opts. */
+enum {
+    VSHT_OPT_SCATTERED_DIRECT = 1 /* scattered points: direct evaluation (O(n L^2)) instead of
+                                     the double-Fourier-sphere grid */
+};
+
 typedef struct {
     int precision; /* a vsht_precision value */
     int device;    /* HIP device ordinal; -1 = the calling thread's current device */
+    int flags;     /* VSHT_OPT_* */
 } vsht_opts;
 
 /* Plan kinds reported by vsht_plan_info. */
@@ -94,6 +110,7 @@ typedef struct {
     int has_weights;
     size_t workspace_bytes;
     size_t table_bytes;
+    int64_t nfft_grid;  /* scattered plans: grid size of the double-Fourier-sphere path (0: direct) */
 } vsht_plan_info_t;
 
 /* Number of coefficients of each kind for bandlimit L: L(L+2) (L >= 1), else 0. */

@@ -29,7 +29,10 @@ STAGES = ("ring_fwd", "leg_fwd", "recombine", "prep", "leg_adj", "ring_adj", "sc
 
 
 class vsht_opts(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int), ("device", ctypes.c_int)]
+    _fields_ = [("precision", ctypes.c_int), ("device", ctypes.c_int), ("flags", ctypes.c_int)]
+
+
+VSHT_OPT_SCATTERED_DIRECT = 1
 
 
 class vsht_plan_info_t(ctypes.Structure):
@@ -37,7 +40,7 @@ class vsht_plan_info_t(ctypes.Structure):
                 ("n_points", ctypes.c_int64), ("n_rings", ctypes.c_int64),
                 ("n_pairs", ctypes.c_int64), ("max_nphi", ctypes.c_int64),
                 ("has_weights", ctypes.c_int), ("workspace_bytes", ctypes.c_size_t),
-                ("table_bytes", ctypes.c_size_t)]
+                ("table_bytes", ctypes.c_size_t), ("nfft_grid", ctypes.c_int64)]
 
 
 class VshtError(RuntimeError):
@@ -165,8 +168,10 @@ class Plan:
     on the current torch stream.
     """
 
-    def __init__(self, L, points, weights=None, precision="fp64", device=None):
+    def __init__(self, L, points, weights=None, precision="fp64", device=None, scattered="grid"):
         torch = _torch()
+        if scattered not in ("grid", "direct"):
+            raise ValueError("scattered must be 'grid' or 'direct'")
         lib = load_library()
         if precision not in PRECISIONS:
             raise ValueError("precision must be one of %s" % sorted(PRECISIONS))
@@ -185,7 +190,8 @@ class Plan:
         self.precision = precision
         self.dtype = torch.complex128 if precision == "fp64" else torch.complex64
         self.K = int(lib.vsht_num_coeffs(self.L))
-        opts = vsht_opts(PRECISIONS[precision], int(device))
+        opts = vsht_opts(PRECISIONS[precision], int(device),
+                         VSHT_OPT_SCATTERED_DIRECT if scattered == "direct" else 0)
         h = ctypes.c_void_p()
         st = lib.vsht_plan(self.L, n, pts.ctypes.data_as(ctypes.c_void_p),
                            None if w is None else w.ctypes.data_as(ctypes.c_void_p),
@@ -340,7 +346,7 @@ class BatchPlan:
         narr = (ctypes.c_int64 * F)(*self.ns)
         xarr = (ctypes.c_void_p * F)(*[p_.ctypes.data for p_ in pts])
         warr = (ctypes.c_void_p * F)(*[w_.ctypes.data for w_ in wts])
-        opts = vsht_opts(PRECISIONS[precision], int(device))
+        opts = vsht_opts(PRECISIONS[precision], int(device), 0)
         h = ctypes.c_void_p()
         st = lib.vsht_plan_batch(F, Larr, narr, xarr, warr, ctypes.byref(opts), ctypes.byref(h))
         _raise_for(st, "vsht_plan_batch")

@@ -61,9 +61,11 @@ hipError_t upload(T **dst, const std::vector<T> &src, size_t *bytes) {
 }
 
 void free_plan_memory(Plan *p) {
+    const NfftPlan &nf = p->nfft;
     void *ptrs[] = {p->d_rings, p->d_pairs, p->d_ffts, p->d_tw,  p->d_pair_z, p->d_aprime,
                     p->d_cscale, p->d_etab, p->d_rsq,  p->d_seeds, p->d_weights, p->d_xyz, p->d_pb,  p->d_fg,
-                    p->d_state};
+                    p->d_state, nf.d_ffts, nf.d_tw, nf.d_vz, nf.d_vs, nf.d_vseeds, nf.d_psihat, nf.d_pts,
+                    nf.d_vpb, nf.d_g1, nf.d_g};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
 }
@@ -191,6 +193,118 @@ bool fft_fits(const FftDesc &fd, const std::vector<FftDesc> &ffts, int nt) {
     return true;
 }
 
+// Smallest multiple of `mult` that is >= n and has no prime factor above 5.
+int smooth_at_least(int n, int mult) {
+    for (int m = (n + mult - 1) / mult * mult;; m += mult) {
+        int r = m;
+        for (int p : {2, 3, 5})
+            while (r % p == 0) r /= p;
+        if (r == 1) return m;
+    }
+}
+
+// Largest bandlimit the double-Fourier-sphere path serves (its DFT lengths stay
+// within the ring DFT kernels' limits).
+constexpr int kMaxNfftL = 700;
+
+// Tables of the double-Fourier-sphere evaluation of a scattered plan.
+hipError_t build_nfft(Plan &P, int64_t n, const double *xyz) {
+    NfftPlan &nf = P.nfft;
+    const int L = P.L;
+    const size_t rsz = P.precision == VSHT_FP64 ? 8 : 4;
+    nf.w = P.precision == VSHT_FP64 ? 14 : 8;
+    nf.beta = 2.30 * nf.w;
+    nf.nt = smooth_at_least(2 * L + 2, 4);
+    nf.npv = nf.nt / 4;
+    nf.ng = smooth_at_least(std::max(2 * (2 * L + 1), 2 * nf.w), 2);
+    std::map<int, int> fidx;
+    std::vector<FftDesc> ffts;
+    std::vector<double> tw;
+    nf.fft_nt = fft_descriptor(nf.nt, fidx, ffts, tw);
+    nf.fft_ng = fft_descriptor(nf.ng, fidx, ffts, tw);
+    auto stored = [&](int id) -> int64_t { return ffts[id].blue ? ffts[id].M : ffts[id].n; };
+    nf.lds_stride = std::max(stored(nf.fft_nt), stored(nf.fft_ng));
+    if (!fft_fits(ffts[nf.fft_nt], ffts, 512) || !fft_fits(ffts[nf.fft_ng], ffts, 512)) return hipErrorInvalidValue;
+    size_t bytes = 0;
+    hipError_t e;
+    if ((e = upload(&nf.d_ffts, ffts, &bytes)) != hipSuccess) return e;
+    if ((e = upload(&nf.d_tw, tw, &bytes)) != hipSuccess) return e;
+    // virtual ring pairs: northern colatitude theta_p = 2 pi (p + 1/2) / nt, p < nt/4
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<double> vz(nf.npv), vs(nf.npv);
+    for (int q = 0; q < nf.npv; ++q) {
+        const long double th = 2.0L * pi * (q + 0.5L) / nf.nt;
+        vz[q] = (double)cosl(th);
+        vs[q] = (double)sinl(th);
+    }
+    if ((e = upload(&nf.d_vz, vz, &bytes)) != hipSuccess) return e;
+    if ((e = upload(&nf.d_vs, vs, &bytes)) != hipSuccess) return e;
+    e = hipMalloc((void **)&nf.d_vseeds, sizeof(double) * (size_t)(L + 1) * nf.npv);
+    if (e != hipSuccess) return e;
+    if ((e = launch_seed_kernel(nf.d_vs, nf.npv, L, nf.d_vseeds, nullptr)) != hipSuccess) return e;
+    // window transform psih(k) = alpha int_{-1}^{1} exp(beta (sqrt(1 - t^2) - 1)) cos(k alpha t) dt,
+    // alpha = w h / 2, with t = sin(u) (a smooth integrand) and composite Simpson
+    {
+        const long double alpha = (long double)nf.w * pi / nf.ng;
+        const int nq = 4000;
+        std::vector<double> ph(2 * L + 1);
+        for (int k = -L; k <= L; ++k) {
+            long double acc = 0.0L;
+            for (int i = 0; i <= nq; ++i) {
+                const long double u = -pi / 2 + pi * i / nq;
+                const long double f = expl(nf.beta * (cosl(u) - 1.0L)) * cosl(k * alpha * sinl(u)) * cosl(u);
+                acc += f * (i == 0 || i == nq ? 1.0L : (i % 2 ? 4.0L : 2.0L));
+            }
+            ph[k + L] = (double)(alpha * acc * (pi / nq) / 3.0L);
+        }
+        if ((e = upload(&nf.d_psihat, ph, &bytes)) != hipSuccess) return e;
+    }
+    // points in grid-cell order
+    {
+        const double h = 2.0 * M_PI / nf.ng;
+        std::vector<NfftPoint> pts(n);
+        std::vector<int64_t> key(n);
+        for (int64_t k = 0; k < n; ++k) {
+            const double x = xyz[3 * k], y = xyz[3 * k + 1], z = xyz[3 * k + 2];
+            const double sn = std::sqrt(x * x + y * y);
+            NfftPoint &q = pts[k];
+            q.z = z;
+            q.s = sn;
+            q.theta = std::atan2(sn, z);
+            if (sn > 0.0) {
+                q.c = x / sn;
+                q.sn = y / sn;
+                q.phi = std::atan2(y, x);
+                if (q.phi < 0.0) q.phi += 2.0 * M_PI;
+                if (q.phi >= 2.0 * M_PI) q.phi = 0.0;
+            } else {
+                q.c = 1.0;
+                q.sn = 0.0;
+                q.phi = 0.0;
+            }
+            q.idx = k;
+            key[k] = (int64_t)(q.theta / h) * nf.ng + (int64_t)(q.phi / h);
+        }
+        std::vector<int64_t> order(n);
+        for (int64_t k = 0; k < n; ++k) order[k] = k;
+        std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+        std::vector<NfftPoint> sorted(n);
+        for (int64_t k = 0; k < n; ++k) sorted[k] = pts[order[k]];
+        if ((e = upload(&nf.d_pts, sorted, &bytes)) != hipSuccess) return e;
+    }
+    const size_t vpb = (size_t)(L + 1) * nf.npv * 16 * rsz;
+    const size_t g1 = (size_t)2 * nf.ng * (2 * L + 1) * 2 * rsz;
+    const size_t g = (size_t)2 * nf.ng * nf.ng * 2 * rsz;
+    if ((e = hipMalloc(&nf.d_vpb, vpb)) != hipSuccess) return e;
+    if ((e = hipMalloc(&nf.d_g1, g1)) != hipSuccess) return e;
+    if ((e = hipMalloc(&nf.d_g, g)) != hipSuccess) return e;
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
+    P.table_bytes += bytes + sizeof(double) * (size_t)(L + 1) * nf.npv;
+    P.workspace_bytes += vpb + g1 + g;
+    nf.on = 1;
+    return hipSuccess;
+}
+
 struct RingScan {
     bool ok = true;
     std::string why;
@@ -289,7 +403,7 @@ vsht_status resolve_device(const vsht_opts *opts, int *dev) {
 
 // Build the tables and workspace of one plan on the current device.
 vsht_status build_plan(Plan &P, int L, int64_t n, const double *xyz, const double *w, int precision,
-                       int dev) {
+                       int dev, int flags) {
     P.L = L;
     P.precision = precision;
     P.device = dev;
@@ -487,6 +601,19 @@ vsht_status build_plan(Plan &P, int L, int64_t n, const double *xyz, const doubl
         const size_t fg = (size_t)P.tri_size * 4 * 2 * rsz;
         if ((e = hipMalloc(&P.d_fg, fg)) != hipSuccess) goto hip_error;
         P.workspace_bytes = fg;
+        if (!(flags & VSHT_OPT_SCATTERED_DIRECT) && L <= kMaxNfftL) {
+            e = build_nfft(P, n, xyz);
+            if (e == hipErrorInvalidValue) {
+                e = hipSuccess;  // grid sizes the DFT kernels cannot take: direct evaluation
+                NfftPlan &nf = P.nfft;
+                void *q[] = {nf.d_ffts, nf.d_tw, nf.d_vz, nf.d_vs, nf.d_vseeds, nf.d_psihat, nf.d_pts,
+                             nf.d_vpb, nf.d_g1, nf.d_g};
+                for (void *x : q)
+                    if (x) (void)hipFree(x);
+                nf = NfftPlan();
+            }
+            if (e != hipSuccess) goto hip_error;
+        }
     }
     return VSHT_OK;
 
@@ -559,7 +686,7 @@ vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w, cons
     DeviceGuard guard(dev);
     auto *h = new (std::nothrow) vsht_plan_s();
     if (!h) return fail(VSHT_ENOMEM, "host allocation");
-    if ((s = build_plan(h->p, L, n, xyz, w, precision, dev)) != VSHT_OK) {
+    if ((s = build_plan(h->p, L, n, xyz, w, precision, dev, opts ? opts->flags : 0)) != VSHT_OK) {
         delete h;
         return s;
     }
@@ -668,6 +795,7 @@ vsht_status vsht_plan_info(vsht_plan_t plan, vsht_plan_info_t *info) {
     info->has_weights = P.has_weights;
     info->workspace_bytes = P.workspace_bytes;
     info->table_bytes = P.table_bytes;
+    info->nfft_grid = P.nfft.on ? P.nfft.ng : 0;
     return VSHT_OK;
 }
 
@@ -767,7 +895,7 @@ vsht_status vsht_plan_batch(int nfields, const int *L, const int64_t *n, const d
     S.kind = VSHT_PLAN_BATCH;
     S.has_weights = 1;
     for (int f = 0; f < nfields; ++f) {
-        s = build_plan(B.fields[f], L[f], n[f], xyz[f], w[f], precision, dev);
+        s = build_plan(B.fields[f], L[f], n[f], xyz[f], w[f], precision, dev, opts ? opts->flags : 0);
         if (s == VSHT_OK && B.fields[f].kind != VSHT_PLAN_RINGS)
             s = fail(VSHT_EUNSUPPORTED, "a batch needs iso-latitude ring grids");
         if (s != VSHT_OK) {

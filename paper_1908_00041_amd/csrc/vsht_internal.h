@@ -72,6 +72,38 @@ struct FftDesc {
     int64_t bhat_offset;   // DFT_M of conj(w) (forward), then of w (inverse), each / M: 2M entries
 };
 
+// A scattered point as the double-Fourier-sphere stages see it (sorted by grid cell).
+struct NfftPoint {
+    double theta, phi;   // colatitude in [0, pi], longitude in [0, 2 pi) (0 at a pole)
+    double z, s, c, sn;  // cos theta, sin theta, cos phi, sin phi
+    int64_t idx;         // position in the caller's point order
+};
+
+// Scattered points through the double Fourier sphere: the synthesis runs on
+// nt equispaced colatitudes theta_t = 2 pi (t + 1/2) / nt of the doubled
+// circle (nt/4 virtual north/south ring pairs), a DFT in theta gives the 2-D
+// Fourier coefficients of the spin-frame components, which are deconvolved by
+// the window transform and taken to an ng x ng grid; each point then gathers a
+// w x w window with the exponential-of-semicircle kernel
+// psi(u) = exp(beta (sqrt(1 - (2u / (w h))^2) - 1)), h = 2 pi / ng.
+struct NfftPlan {
+    int on = 0;
+    int nt = 0, npv = 0, ng = 0, w = 0;
+    double beta = 0.0;
+    int fft_nt = 0, fft_ng = 0;       // descriptors in d_ffts
+    int64_t lds_stride = 0;           // LDS sequence stride of the theta/grid DFTs
+    FftDesc *d_ffts = nullptr;
+    double *d_tw = nullptr;
+    double *d_vz = nullptr;           // z of each virtual pair's northern colatitude
+    double *d_vs = nullptr;           // its sin theta
+    double *d_vseeds = nullptr;       // Lambda_{m,m}, [(L+1)][npv]
+    double *d_psihat = nullptr;       // window transform at k = -L..L
+    NfftPoint *d_pts = nullptr;
+    void *d_vpb = nullptr;            // virtual pair buffer [(L+1)][npv][16] reals
+    void *d_g1 = nullptr;             // column pass output [2][ng][2L+1] complex
+    void *d_g = nullptr;              // grid [2][ng][ng] complex
+};
+
 // Workspace layout (all in the plan's real type):
 //  RB   ring buffer (forward)  [(L+1)][NR][4] complex, the ring DFTs scaled by
 //       e^{-+i m phi_0} w / s: (theta,+m) (phi,+m) (theta,-m) (phi,-m)
@@ -108,6 +140,8 @@ struct Plan {
     double *d_weights = nullptr;   // per-point weights (rings with non-uniform weights)
     double *d_xyz = nullptr;       // points (scattered plans)
     size_t table_bytes = 0;
+
+    NfftPlan nfft;                 // scattered plans evaluated through the double Fourier sphere
 
     // workspace
     void *d_pb = nullptr;

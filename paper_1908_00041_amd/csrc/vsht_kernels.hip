@@ -475,7 +475,7 @@ __device__ __forceinline__ int seq_stride(const FftDesc *fdp) {
 }
 
 // DFT of length n of the two sequences of a ring (element i of sequence q at
-// buf[pad16(q * seq_stride + i)]), forward (e^{-2 pi i j m / n}) or inverse.
+// buf[pad16(q * stride + i)], stride >= seq_stride), forward (e^{-2 pi i j m / n}) or inverse.
 // Lengths with a prime factor above the generic-radix limit use Bluestein's
 // identity j m = (j^2 + m^2 - (m - j)^2) / 2: with w_k = e^{-i pi k^2 / n},
 //     X_m = w_m sum_j (x_j w_j) conj(w_{m-j}),
@@ -483,10 +483,10 @@ __device__ __forceinline__ int seq_stride(const FftDesc *fdp) {
 // two mixed-radix DFTs of length M and the tabulated transform of the kernel
 // (already divided by M); the inverse uses conj(w).
 template <typename real, int NT>
-__device__ __forceinline__ void fft_lds(C2<real> *buf, const FftDesc *ffts, const FftDesc *fdp,
+__device__ __forceinline__ void fft_lds(C2<real> *buf, int stride, const FftDesc *ffts, const FftDesc *fdp,
                                         const double *__restrict__ tw, CD *wR, bool inv) {
     if (!ld_const(&fdp->blue)) {
-        fft_core<real, NT>(buf, ld_const(&fdp->n), fdp, tw, wR, inv);
+        fft_core<real, NT>(buf, stride, fdp, tw, wR, inv);
         return;
     }
     const int n = ld_const(&fdp->n), M = ld_const(&fdp->M);
@@ -496,28 +496,28 @@ __device__ __forceinline__ void fft_lds(C2<real> *buf, const FftDesc *ffts, cons
         const CD w = tw_at(ch, i < n ? i : 0, inv);
 #pragma unroll
         for (int sq = 0; sq < 2; ++sq) {
-            C2<real> &v = buf[pad16(sq * M + i)];
+            C2<real> &v = buf[pad16(sq * stride + i)];
             v = i < n ? cmul_d(v, w) : C2<real>{0, 0};
         }
     }
     __syncthreads();
     const FftDesc *md = ffts + ld_const(&fdp->mdesc);
-    fft_core<real, NT>(buf, M, md, tw, wR, false);
+    fft_core<real, NT>(buf, stride, md, tw, wR, false);
     for (int i = threadIdx.x; i < M; i += NT) {
         const CD w = tw_at(bh, i, false);
 #pragma unroll
         for (int sq = 0; sq < 2; ++sq) {
-            C2<real> &v = buf[pad16(sq * M + i)];
+            C2<real> &v = buf[pad16(sq * stride + i)];
             v = cmul_d(v, w);
         }
     }
     __syncthreads();
-    fft_core<real, NT>(buf, M, md, tw, wR, true);
+    fft_core<real, NT>(buf, stride, md, tw, wR, true);
     for (int i = threadIdx.x; i < n; i += NT) {
         const CD w = tw_at(ch, i, inv);
 #pragma unroll
         for (int sq = 0; sq < 2; ++sq) {
-            C2<real> &v = buf[pad16(sq * M + i)];
+            C2<real> &v = buf[pad16(sq * stride + i)];
             v = cmul_d(v, w);
         }
     }
@@ -584,7 +584,7 @@ __device__ __forceinline__ void ring_fwd_body(const RingArgs<real> &A, int r, un
         buf[pad16(n2 + j)] = ph;
     }
     __syncthreads();
-    fft_lds<real, NT>(buf, A.ffts, fdp, A.tw, wR, false);
+    fft_lds<real, NT>(buf, n2, A.ffts, fdp, A.tw, wR, false);
     const double inv_s = 1.0 / rd.s;
     for (int m = threadIdx.x; m <= L; m += NT) {
         const int bp = m % n;
@@ -642,7 +642,7 @@ __device__ __forceinline__ void ring_adj_body(const RingArgs<real> &A, int r, un
         buf[pad16(n2 + b)] = hph;
     }
     __syncthreads();
-    fft_lds<real, NT>(buf, A.ffts, fdp, A.tw, wR, true);
+    fft_lds<real, NT>(buf, n2, A.ffts, fdp, A.tw, wR, true);
     const double *twn = A.tw + 2 * ld_const(&fdp->tw_offset);
     for (int j = threadIdx.x; j < n; j += NT) {
         const double er = twn[2 * j], ei = -twn[2 * j + 1];
@@ -1516,6 +1516,202 @@ __global__ __launch_bounds__(64) void k_adj_scattered(ScatArgs<real> A) {
 }
 
 // ===========================================================================
+// Scattered points through the double Fourier sphere (adjoint).
+// The spin-frame components T_theta,m(theta), T_phi,m(theta) of the synthesised
+// field are, continued to theta in [0, 2 pi) with signed sin(theta),
+// trigonometric polynomials of degree <= L (derivatives of sin^m(theta) times
+// polynomials in cos(theta), and those over sin(theta)) that satisfy
+// T_m(2 pi - theta) = (-1)^{|m|+1} T_m(theta).  The synthesis runs on nt > 2L
+// equispaced colatitudes theta_t = 2 pi (t + 1/2) / nt, t < nt/2 (nt/4 virtual
+// north/south ring pairs, never at a pole), the other half follows from the
+// symmetry, and a DFT over t gives their exact Fourier coefficients
+// c_{k,m}, |k| <= L.  With the window transform
+// psih(k) = int psi(u) e^{-i k u} du, the grid values
+//     g(theta_j, phi_i) = sum_{k,m} c_{k,m} h^2 / (psih(k) psih(m)) e^{i (k theta_j + m phi_i)}
+// (two inverse DFTs of length ng) reproduce T at any point as the windowed sum
+// sum_{j,i} g(theta_j, phi_i) psi(theta - theta_j) psi(phi - phi_i), up to the
+// kernel's aliasing error.
+// ===========================================================================
+template <typename real>
+struct NfftArgs {
+    const real *PB;            // virtual pair buffer [(L+1)][npv][16]
+    C2<real> *g1;              // [2][ng][2L+1]
+    C2<real> *g;               // [2][ng][ng]
+    const double *vs;          // sin theta of each virtual pair
+    const double *psihat;      // [2L+1]
+    const FftDesc *ffts;
+    const double *tw;
+    const NfftPoint *pts;
+    const double *weights;
+    C2<real> *Tout;
+    int64_t n;
+    double beta, h;
+    int fft_nt, fft_ng;
+    int L, nt, npv, ng, w;
+    int stride;                // LDS sequence stride
+    int weighted;
+};
+
+constexpr int kNfftNT = 512;
+constexpr int kNfftMaxK = 3;   // (2L+1) / kNfftNT, rounded up, for L <= 767
+constexpr int kNfftMaxW = 16;
+
+// One workgroup per order m in [-L, L]: theta samples of T_theta,m and T_phi,m,
+// DFT of length nt, deconvolution, zero padding, inverse DFT of length ng,
+// column m of g1.
+template <typename real>
+__global__ __launch_bounds__(kNfftNT, 1) void k_nfft_cols(NfftArgs<real> A) {
+    extern __shared__ unsigned char smem_raw[];
+    CD *wR = reinterpret_cast<CD *>(smem_raw);
+    C2<real> *buf = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
+    const int L = A.L, nt = A.nt, npv = A.npv, ng = A.ng, S = A.stride;
+    const int b = blockIdx.x;  // m + L
+    const int m = b - L;
+    const int am = m < 0 ? -m : m;
+    const int slot = m < 0 ? 2 : 0;  // complex column (theta) of +-m; phi is slot + 1
+    const real ext = (am & 1) ? (real)1 : (real)-1;
+    for (int t = threadIdx.x; t < nt; t += kNfftNT) {
+        const bool upper = t < nt / 2;
+        const int tt = upper ? t : nt - 1 - t;  // sample in (0, pi)
+        const bool north = tt < nt / 4;
+        const int p = north ? tt : nt / 2 - 1 - tt;
+        const C2<real> *e = reinterpret_cast<const C2<real> *>(A.PB + ((size_t)am * npv + p) * 16);
+        const C2<real> Et = e[slot], Ep = e[slot + 1], Ot = e[4 + slot], Op = e[4 + slot + 1];
+        const real f = (upper ? (real)1 : ext) / (real)A.vs[p];
+        const real so = north ? (real)1 : (real)-1;
+        buf[pad16(t)] = {(Et.x + so * Ot.x) * f, (Et.y + so * Ot.y) * f};
+        buf[pad16(S + t)] = {(Ep.x + so * Op.x) * f, (Ep.y + so * Op.y) * f};
+    }
+    __syncthreads();
+    fft_lds<real, kNfftNT>(buf, S, A.ffts, A.ffts + A.fft_nt, A.tw, wR, false);
+    // d_k = DFT[k mod nt] e^{-i pi k / nt} / nt * h^2 / (psih(k) psih(m)), |k| <= L
+    C2<real> dk[kNfftMaxK][2];
+#pragma unroll
+    for (int q = 0; q < kNfftMaxK; ++q) {
+        const int k = threadIdx.x + q * kNfftNT - L;
+        if (k <= L) {
+            const int src = k >= 0 ? k : nt + k;
+            double sp, cp;
+            sincos(-M_PI * (double)k / (double)nt, &sp, &cp);
+            const double sc = A.h * A.h / ((double)nt * A.psihat[k + L] * A.psihat[m + L]);
+            const CD ph = {cp * sc, sp * sc};
+            dk[q][0] = cmul_d(buf[pad16(src)], ph);
+            dk[q][1] = cmul_d(buf[pad16(S + src)], ph);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ng; i += kNfftNT) {
+        buf[pad16(i)] = {0, 0};
+        buf[pad16(S + i)] = {0, 0};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kNfftMaxK; ++q) {
+        const int k = threadIdx.x + q * kNfftNT - L;
+        if (k <= L) {
+            const int dst = k >= 0 ? k : ng + k;
+            buf[pad16(dst)] = dk[q][0];
+            buf[pad16(S + dst)] = dk[q][1];
+        }
+    }
+    __syncthreads();
+    fft_lds<real, kNfftNT>(buf, S, A.ffts, A.ffts + A.fft_ng, A.tw, wR, true);
+    const int nm = 2 * L + 1;
+    for (int j = threadIdx.x; j < ng; j += kNfftNT) {
+        A.g1[(size_t)j * nm + b] = buf[pad16(j)];
+        A.g1[((size_t)ng + j) * nm + b] = buf[pad16(S + j)];
+    }
+}
+
+// One workgroup per grid row j: inverse DFT over the orders (zero padded).
+template <typename real>
+__global__ __launch_bounds__(kNfftNT, 1) void k_nfft_rows(NfftArgs<real> A) {
+    extern __shared__ unsigned char smem_raw[];
+    CD *wR = reinterpret_cast<CD *>(smem_raw);
+    C2<real> *buf = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
+    const int L = A.L, ng = A.ng, S = A.stride;
+    const int j = blockIdx.x;
+    const int nm = 2 * L + 1;
+    for (int i = threadIdx.x; i < ng; i += kNfftNT) {
+        // bin i holds order m = i (i <= L) or i - ng (i >= ng - L)
+        const int m = i <= L ? i : (i >= ng - L ? i - ng : L + 1);
+        C2<real> vt = {0, 0}, vp = {0, 0};
+        if (m <= L) {
+            vt = A.g1[(size_t)j * nm + m + L];
+            vp = A.g1[((size_t)ng + j) * nm + m + L];
+        }
+        buf[pad16(i)] = vt;
+        buf[pad16(S + i)] = vp;
+    }
+    __syncthreads();
+    fft_lds<real, kNfftNT>(buf, S, A.ffts, A.ffts + A.fft_ng, A.tw, wR, true);
+    for (int i = threadIdx.x; i < ng; i += kNfftNT) {
+        A.g[(size_t)j * ng + i] = buf[pad16(i)];
+        A.g[((size_t)ng + j) * ng + i] = buf[pad16(S + i)];
+    }
+}
+
+// One lane per point (in grid-cell order): window sum of both components,
+// rotation to Cartesian components, store at the caller's index.
+template <typename real>
+__global__ __launch_bounds__(256) void k_nfft_gather(NfftArgs<real> A) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= A.n) return;
+    const NfftPoint P = A.pts[k];
+    const int ng = A.ng, w = A.w;
+    const double hw = 0.5 * w;
+    const double u = P.theta / A.h, v = P.phi / A.h;
+    const int j0 = (int)ceil(u - hw), i0 = (int)ceil(v - hw);
+    real wt[kNfftMaxW], wp[kNfftMaxW];
+#pragma unroll
+    for (int a = 0; a < kNfftMaxW; ++a) {
+        wt[a] = wp[a] = 0;
+        if (a < w) {
+            const double dt = (u - (j0 + a)) / hw, dp = (v - (i0 + a)) / hw;
+            wt[a] = (real)(fabs(dt) < 1.0 ? exp(A.beta * (sqrt((1.0 - dt) * (1.0 + dt)) - 1.0)) : 0.0);
+            wp[a] = (real)(fabs(dp) < 1.0 ? exp(A.beta * (sqrt((1.0 - dp) * (1.0 + dp)) - 1.0)) : 0.0);
+        }
+    }
+    real thr = 0, thi = 0, phr = 0, phi_ = 0;
+    int jr = j0 % ng;
+    if (jr < 0) jr += ng;
+    int ir0 = i0 % ng;
+    if (ir0 < 0) ir0 += ng;
+#pragma unroll
+    for (int a = 0; a < kNfftMaxW; ++a) {
+        if (a < w) {
+            const C2<real> *rt = A.g + (size_t)jr * ng;
+            const C2<real> *rp = A.g + ((size_t)ng + jr) * ng;
+            real str = 0, sti = 0, spr = 0, spi = 0;
+            int ir = ir0;
+#pragma unroll
+            for (int c = 0; c < kNfftMaxW; ++c) {
+                if (c < w) {
+                    const C2<real> gt = rt[ir], gp = rp[ir];
+                    str += wp[c] * gt.x;
+                    sti += wp[c] * gt.y;
+                    spr += wp[c] * gp.x;
+                    spi += wp[c] * gp.y;
+                    if (++ir == ng) ir = 0;
+                }
+            }
+            thr += wt[a] * str;
+            thi += wt[a] * sti;
+            phr += wt[a] * spr;
+            phi_ += wt[a] * spi;
+            if (++jr == ng) jr = 0;
+        }
+    }
+    const real z = (real)P.z, s = (real)P.s, c = (real)P.c, sn = (real)P.sn;
+    real sc = 1;
+    if (A.weighted) sc = (real)A.weights[P.idx];
+    C2<real> *o = A.Tout + 3 * P.idx;
+    o[0] = {sc * (z * c * thr - sn * phr), sc * (z * c * thi - sn * phi_)};
+    o[1] = {sc * (z * sn * thr + c * phr), sc * (z * sn * thi + c * phi_)};
+    o[2] = {sc * (-s * thr), sc * (-s * thi)};
+}
+
+// ===========================================================================
 // Batched stages: one launch per stage (and per workgroup shape) covers every
 // field of a batch.  Workgroup i runs work item work[i] = (field, x, y) with the
 // field's own argument block; the bodies are those of the single-field kernels.
@@ -1762,6 +1958,64 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+
+    if (p.kind == VSHT_PLAN_SCATTERED && p.nfft.on) {
+        const NfftPlan &nf = p.nfft;
+        LegArgs<real> G{};
+        G.FG = static_cast<const real *>(p.d_fg);
+        G.PB = static_cast<real *>(nf.d_vpb);
+        G.seeds = nf.d_vseeds;
+        G.pz = nf.d_vz;
+        G.aprime = p.d_aprime;
+        G.L = p.L;
+        G.NP = nf.npv;
+        G.NPT = nf.npv;
+        {
+            StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
+            const int ntile = (nf.npv + kTileP - 1) / kTileP;
+            const int nw = ntile < 4 ? ntile : 4;
+            const dim3 grid((ntile + nw - 1) / nw, p.L + 1);
+            if constexpr (sizeof(real) == 4) {
+                if (bf16)
+                    hipLaunchKernelGGL(k_leg_adj_bf16x3, grid, dim3(nw * 64), leg_adj_lds(nw, 4, true), st, G);
+                else
+                    hipLaunchKernelGGL(k_leg_adj_mfma<real>, grid, dim3(nw * 64), leg_adj_lds(nw, 4, false), st, G);
+            } else {
+                hipLaunchKernelGGL(k_leg_adj_mfma<real>, grid, dim3(nw * 64), leg_adj_lds(nw, 8, false), st, G);
+            }
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        NfftArgs<real> N{};
+        N.PB = static_cast<const real *>(nf.d_vpb);
+        N.g1 = static_cast<C2<real> *>(nf.d_g1);
+        N.g = static_cast<C2<real> *>(nf.d_g);
+        N.vs = nf.d_vs;
+        N.psihat = nf.d_psihat;
+        N.ffts = nf.d_ffts;
+        N.tw = nf.d_tw;
+        N.pts = nf.d_pts;
+        N.weights = p.d_weights;
+        N.Tout = static_cast<C2<real> *>(T);
+        N.n = p.n;
+        N.beta = nf.beta;
+        N.h = 2.0 * M_PI / nf.ng;
+        N.fft_nt = nf.fft_nt;
+        N.fft_ng = nf.fft_ng;
+        N.L = p.L;
+        N.nt = nf.nt;
+        N.npv = nf.npv;
+        N.ng = nf.ng;
+        N.w = nf.w;
+        N.stride = (int)nf.lds_stride;
+        N.weighted = weighted ? 1 : 0;
+        const size_t lds = ring_lds_bytes_len(nf.lds_stride, sizeof(real));
+        StageScope sc(p, VSHT_STAGE_SCATTERED, st);
+        hipLaunchKernelGGL(k_nfft_cols<real>, dim3(2 * p.L + 1), dim3(kNfftNT), lds, st, N);
+        hipLaunchKernelGGL(k_nfft_rows<real>, dim3(nf.ng), dim3(kNfftNT), lds, st, N);
+        hipLaunchKernelGGL(k_nfft_gather<real>, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, st, N);
+        return hipGetLastError();
+    }
 
     if (p.kind == VSHT_PLAN_SCATTERED) {
         ScatArgs<real> S{};
@@ -2187,6 +2441,12 @@ hipError_t set_kernel_attributes() {
                              (const void *)kb_leg_fwd<double, false>, (const void *)kb_leg_fwd<float, false>,
                              (const void *)kb_leg_fwd<float, true>, (const void *)kb_leg_adj<double, false>,
                              (const void *)kb_leg_adj<float, false>, (const void *)kb_leg_adj<float, true>};
+    const void *nfft_kernels[] = {(const void *)k_nfft_cols<double>, (const void *)k_nfft_cols<float>,
+                                  (const void *)k_nfft_rows<double>, (const void *)k_nfft_rows<float>};
+    for (const void *k : nfft_kernels) {
+        e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+        if (e != hipSuccess) return e;
+    }
     for (const void *k : batched) {
         e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, big);
         if (e != hipSuccess) return e;

@@ -271,3 +271,64 @@ def test_bluestein_rings(torch, vsht, orc, case, precision, tol):
     e_fwd = rel_l2(np.concatenate([ga, gb]), np.concatenate([a_ref, b_ref]))
     print("bluestein %s %s adjoint %.3e forward %.3e" % (case, precision, e_adj, e_fwd))
     assert e_adj < tol and e_fwd < tol
+
+
+# ---------------------------------------------------------------------------
+# Scattered points through the double Fourier sphere (grid + window gather),
+# against the oracle and against the direct evaluation.
+# ---------------------------------------------------------------------------
+def scattered_points(M, seed):
+    xyz, w = vi.uniform_points(M, seed)
+    poles = np.array([[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]])
+    near = np.array([[1e-9, 0.0, np.sqrt(1 - 1e-18)], [0.0, -3e-7, -np.sqrt(1 - 9e-14)]])
+    xyz = np.concatenate([xyz, poles, near])
+    return xyz, np.full(len(xyz), 4 * np.pi / len(xyz))
+
+
+@pytest.mark.parametrize("L,precision,tol", [(8, "fp64", FP64_TOL), (64, "fp64", FP64_TOL),
+                                             (64, "fp32", FP32_TOL), (45, "bf16x3", BF16X3_TOL)])
+def test_scattered_grid_vs_oracle(torch, vsht, orc, L, precision, tol):
+    print_case("scattered grid", L, precision)
+    xyz, w = scattered_points(1500, 21)
+    plan = vsht.Plan(L, xyz, w, precision=precision)
+    assert plan.kind == "scattered" and plan.info()["nfft_grid"] > 0
+    a, b = vi.random_coeffs(L, 22)
+    T = run_adjoint(torch, plan, a, b)
+    T_ref = orc.adjoint(L, a, b, xyz)
+    err = rel_l2(T, T_ref)
+    err_poles = rel_l2(T[-4:], T_ref[-4:])
+    print("scattered grid L=%d %s rel-L2 %.3e (poles %.3e)" % (L, precision, err, err_poles))
+    assert err < tol and err_poles < 10 * tol
+
+
+def test_scattered_grid_vs_direct(torch, vsht):
+    L = 40
+    print_case("scattered grid vs direct", L)
+    xyz, w = scattered_points(3000, 23)
+    a, b = vi.random_coeffs(L, 24)
+    pg = vsht.Plan(L, xyz, w, precision="fp64")
+    pd = vsht.Plan(L, xyz, w, precision="fp64", scattered="direct")
+    assert pg.info()["nfft_grid"] > 0 and pd.info()["nfft_grid"] == 0
+    # the direct evaluation divides the spin-frame sums by sin(theta), so it
+    # loses digits within ~1e-6 of a pole (exact poles use the limit); compare
+    # away from those two points
+    keep = np.hypot(xyz[:, 0], xyz[:, 1]) > 1e-6
+    keep |= np.hypot(xyz[:, 0], xyz[:, 1]) == 0
+    Tg, Td = run_adjoint(torch, pg, a, b), run_adjoint(torch, pd, a, b)
+    assert rel_l2(Tg[keep], Td[keep]) < FP64_TOL
+
+
+def test_scattered_grid_L256_sampled(torch, vsht, orc):
+    """M = 4 L^2 = 262,144 uniform points at L = 256 (plus both poles), sampled."""
+    L = 256
+    print_case("scattered grid L=256 M=262144")
+    xyz, w = vi.uniform_points(4 * L * L, 2)
+    xyz = np.concatenate([xyz, [[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]]])
+    w = np.full(len(xyz), 4 * np.pi / len(xyz))
+    a, b = vi.random_coeffs(L, 0, scale="inv_sqrt_ll1")
+    plan = vsht.Plan(L, xyz, w, precision="fp64")
+    T = run_adjoint(torch, plan, a, b)
+    pidx = np.concatenate([vi.sample_indices(len(xyz) - 2, 64, 3), [len(xyz) - 2, len(xyz) - 1]])
+    err = rel_l2(T[pidx], orc.adjoint(L, a, b, xyz[pidx]))
+    print("scattered grid L=256 sampled rel-L2 %.3e" % err)
+    assert err < FP64_TOL
