@@ -45,7 +45,7 @@
  * a ring of equal weights takes a faster path).  Rings whose
  * z values are exact negatives of each other are paired (north/south).  The
  * Gauss-Legendre product grids of Section 5.1 are of this kind.  Other point
- * sets are "scattered": they are accepted for the adjoint only.
+ * sets are "scattered".
  *
  * Scattered points (the arbitrary points of eq. (expan)) are evaluated through
  * the double Fourier sphere: the synthesis runs on equispaced colatitudes of
@@ -54,7 +54,9 @@
  * oversampled grid with the exponential-of-semicircle kernel (width 14 grid
  * points in binary64, 8 otherwise; relative error near 1e-13 resp. 1e-6).
  * VSHT_OPT_SCATTERED_DIRECT selects the direct O(n L^2) evaluation instead; L
- * above 700 always uses it.
+ * above 700 always uses it.  The forward transforms at scattered points run
+ * the conjugate transpose of the grid path (spreading instead of gathering);
+ * a plan on the direct path serves the adjoint only (VSHT_EUNSUPPORTED).
  */
 #ifndef VSHT_H
 #define VSHT_H
@@ -129,14 +131,15 @@ vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w,
 
 /* Forward transform (Definition 4.1, eq. (fwdvsht2)): T (device, n x 3) ->
  * a, b (device, L(L+2) each).  VSHT_ENOWEIGHTS if the plan has no weights,
- * VSHT_EUNSUPPORTED on a scattered plan. */
+ * VSHT_EUNSUPPORTED on a scattered plan on the direct path. */
 vsht_status vsht_forward(vsht_plan_t plan, const void *T, void *a, void *b, void *stream);
 
 /* Forward transform with unit weights, i.e. the exact adjoint (Hermitian
  * transpose) of vsht_adjoint as a linear map C^{2K} -> C^{3n}:
  *   a_{l,m} = sum_k Y^div_{l,m}(x_k)^* T_k, b likewise.
  * Used as the backward of the adjoint in automatic differentiation.  Works on
- * plans with or without weights; VSHT_EUNSUPPORTED on a scattered plan. */
+ * plans with or without weights; VSHT_EUNSUPPORTED on a scattered plan on the
+ * direct path. */
 vsht_status vsht_forward_unweighted(vsht_plan_t plan, const void *T, void *a, void *b,
                                     void *stream);
 

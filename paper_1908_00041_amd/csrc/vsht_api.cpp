@@ -64,7 +64,7 @@ void free_plan_memory(Plan *p) {
     const NfftPlan &nf = p->nfft;
     void *ptrs[] = {p->d_rings, p->d_pairs, p->d_ffts, p->d_tw,  p->d_pair_z, p->d_aprime,
                     p->d_cscale, p->d_etab, p->d_rsq,  p->d_seeds, p->d_weights, p->d_xyz, p->d_pb,  p->d_fg,
-                    p->d_state, nf.d_ffts, nf.d_tw, nf.d_vz, nf.d_vs, nf.d_vseeds, nf.d_psihat, nf.d_pts,
+                    p->d_state, nf.d_ffts, nf.d_tw, nf.d_vpairs, nf.d_vz, nf.d_vs, nf.d_vseeds, nf.d_psihat, nf.d_pts,
                     nf.d_vpb, nf.d_g1, nf.d_g};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -238,6 +238,11 @@ hipError_t build_nfft(Plan &P, int64_t n, const double *xyz) {
         vs[q] = (double)sinl(th);
     }
     if ((e = upload(&nf.d_vz, vz, &bytes)) != hipSuccess) return e;
+    {
+        std::vector<PairDesc> vp(nf.npv);
+        for (int q = 0; q < nf.npv; ++q) vp[q] = PairDesc{q, nf.nt / 2 - 1 - q};
+        if ((e = upload(&nf.d_vpairs, vp, &bytes)) != hipSuccess) return e;
+    }
     if ((e = upload(&nf.d_vs, vs, &bytes)) != hipSuccess) return e;
     e = hipMalloc((void **)&nf.d_vseeds, sizeof(double) * (size_t)(L + 1) * nf.npv);
     if (e != hipSuccess) return e;
@@ -606,7 +611,7 @@ vsht_status build_plan(Plan &P, int L, int64_t n, const double *xyz, const doubl
             if (e == hipErrorInvalidValue) {
                 e = hipSuccess;  // grid sizes the DFT kernels cannot take: direct evaluation
                 NfftPlan &nf = P.nfft;
-                void *q[] = {nf.d_ffts, nf.d_tw, nf.d_vz, nf.d_vs, nf.d_vseeds, nf.d_psihat, nf.d_pts,
+                void *q[] = {nf.d_ffts, nf.d_tw, nf.d_vpairs, nf.d_vz, nf.d_vs, nf.d_vseeds, nf.d_psihat, nf.d_pts,
                              nf.d_vpb, nf.d_g1, nf.d_g};
                 for (void *x : q)
                     if (x) (void)hipFree(x);
@@ -707,8 +712,8 @@ vsht_status vsht_forward(vsht_plan_t plan, const void *T, void *a, void *b, void
     if (s != VSHT_OK) return s;
     const Plan &P = plan->p;
     if (!P.has_weights) return fail(VSHT_ENOWEIGHTS, "forward needs a plan created with weights");
-    if (P.kind != VSHT_PLAN_RINGS)
-        return fail(VSHT_EUNSUPPORTED, "forward transform on a scattered point set");
+    if (P.kind != VSHT_PLAN_RINGS && !P.nfft.on)
+        return fail(VSHT_EUNSUPPORTED, "forward transform on scattered points needs the grid path");
     DeviceGuard guard(P.device);
     hipError_t e = launch_forward(P, T, a, b, true, (hipStream_t)stream);
     return e == hipSuccess ? VSHT_OK : hip_fail(e, "forward launch");
@@ -719,8 +724,8 @@ vsht_status vsht_forward_unweighted(vsht_plan_t plan, const void *T, void *a, vo
     vsht_status s = check_call(plan, T, a, b);
     if (s != VSHT_OK) return s;
     const Plan &P = plan->p;
-    if (P.kind != VSHT_PLAN_RINGS)
-        return fail(VSHT_EUNSUPPORTED, "forward transform on a scattered point set");
+    if (P.kind != VSHT_PLAN_RINGS && !P.nfft.on)
+        return fail(VSHT_EUNSUPPORTED, "forward transform on scattered points needs the grid path");
     DeviceGuard guard(P.device);
     hipError_t e = launch_forward(P, T, a, b, false, (hipStream_t)stream);
     return e == hipSuccess ? VSHT_OK : hip_fail(e, "forward launch");
@@ -746,8 +751,8 @@ vsht_status vsht_forward_many(vsht_plan_t plan, int64_t count, const void *T, vo
     if (flags & ~VSHT_UNIT_WEIGHTS) return fail(VSHT_EINVAL, "unknown flag for the forward transform");
     const bool weighted = !(flags & VSHT_UNIT_WEIGHTS);
     if (weighted && !P.has_weights) return fail(VSHT_ENOWEIGHTS, "forward needs a plan created with weights");
-    if (P.kind != VSHT_PLAN_RINGS)
-        return fail(VSHT_EUNSUPPORTED, "forward transform on a scattered point set");
+    if (P.kind != VSHT_PLAN_RINGS && !P.nfft.on)
+        return fail(VSHT_EUNSUPPORTED, "forward transform on scattered points needs the grid path");
     DeviceGuard guard(P.device);
     const size_t cb = complex_bytes(P);
     const size_t t_stride = (size_t)P.n * 3 * cb, c_stride = (size_t)vsht_num_coeffs(P.L) * cb;

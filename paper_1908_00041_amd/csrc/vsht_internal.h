@@ -94,12 +94,14 @@ struct NfftPlan {
     int64_t lds_stride = 0;           // LDS sequence stride of the theta/grid DFTs
     FftDesc *d_ffts = nullptr;
     double *d_tw = nullptr;
+    PairDesc *d_vpairs = nullptr;     // virtual ring pairs (north t, south nt/2 - 1 - t)
     double *d_vz = nullptr;           // z of each virtual pair's northern colatitude
     double *d_vs = nullptr;           // its sin theta
     double *d_vseeds = nullptr;       // Lambda_{m,m}, [(L+1)][npv]
     double *d_psihat = nullptr;       // window transform at k = -L..L
     NfftPoint *d_pts = nullptr;
-    void *d_vpb = nullptr;            // virtual pair buffer [(L+1)][npv][16] reals
+    void *d_vpb = nullptr;            // virtual pair buffer [(L+1)][npv][16] reals (adjoint),
+                                      // virtual ring buffer [(L+1)][nt/2][8] reals (forward)
     void *d_g1 = nullptr;             // column pass output [2][ng][2L+1] complex
     void *d_g = nullptr;              // grid [2][ng][ng] complex
 };

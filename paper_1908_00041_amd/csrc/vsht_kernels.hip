@@ -1544,6 +1544,8 @@ struct NfftArgs {
     const NfftPoint *pts;
     const double *weights;
     C2<real> *Tout;
+    const C2<real> *Tin;       // forward: the field at the points
+    real *RB;                  // forward: ring buffer of the virtual rings [(L+1)][nt/2][8]
     int64_t n;
     double beta, h;
     int fft_nt, fft_ng;
@@ -1709,6 +1711,171 @@ __global__ __launch_bounds__(256) void k_nfft_gather(NfftArgs<real> A) {
     o[0] = {sc * (z * c * thr - sn * phr), sc * (z * c * thi - sn * phi_)};
     o[1] = {sc * (z * sn * thr + c * phr), sc * (z * sn * thi + c * phi_)};
     o[2] = {sc * (-s * thr), sc * (-s * thi)};
+}
+
+// ---------------------------------------------------------------------------
+// Forward transform at scattered points: the conjugate transpose, stage by
+// stage, of the adjoint above (weights applied at the points).  Spreading
+// (transpose of the gather) adds w_k psi psi (e_theta . T_k, e_phi . T_k) into
+// the grid with vector atomics; the row and column passes take forward DFTs
+// and keep |m|, |k| <= L; the conjugate deconvolution factors and an inverse
+// DFT of length nt give the values at the virtual colatitudes, whose
+// doubled-circle images are folded back (transpose of the extension), and the
+// result, divided by sin(theta), fills the ring buffer of the virtual rings
+// for the Legendre analysis.
+// ---------------------------------------------------------------------------
+template <typename real>
+__global__ __launch_bounds__(256) void k_fill_zero(real *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_nfft_spread(NfftArgs<real> A) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= A.n) return;
+    const NfftPoint P = A.pts[k];
+    const int ng = A.ng, w = A.w;
+    const double hw = 0.5 * w;
+    const double u = P.theta / A.h, v = P.phi / A.h;
+    const int j0 = (int)ceil(u - hw), i0 = (int)ceil(v - hw);
+    real wt[kNfftMaxW], wp[kNfftMaxW];
+#pragma unroll
+    for (int a = 0; a < kNfftMaxW; ++a) {
+        wt[a] = wp[a] = 0;
+        if (a < w) {
+            const double dt = (u - (j0 + a)) / hw, dp = (v - (i0 + a)) / hw;
+            wt[a] = (real)(fabs(dt) < 1.0 ? exp(A.beta * (sqrt((1.0 - dt) * (1.0 + dt)) - 1.0)) : 0.0);
+            wp[a] = (real)(fabs(dp) < 1.0 ? exp(A.beta * (sqrt((1.0 - dp) * (1.0 + dp)) - 1.0)) : 0.0);
+        }
+    }
+    const C2<real> *t = A.Tin + 3 * P.idx;
+    const real z = (real)P.z, s = (real)P.s, c = (real)P.c, sn = (real)P.sn;
+    real sc = 1;
+    if (A.weighted) sc = (real)A.weights[P.idx];
+    // e_theta = (z c, z sn, -s), e_phi = (-sn, c, 0)
+    const real ttr = sc * (z * c * t[0].x + z * sn * t[1].x - s * t[2].x);
+    const real tti = sc * (z * c * t[0].y + z * sn * t[1].y - s * t[2].y);
+    const real tpr = sc * (-sn * t[0].x + c * t[1].x);
+    const real tpi = sc * (-sn * t[0].y + c * t[1].y);
+    int jr = j0 % ng;
+    if (jr < 0) jr += ng;
+    int ir0 = i0 % ng;
+    if (ir0 < 0) ir0 += ng;
+#pragma unroll
+    for (int a = 0; a < kNfftMaxW; ++a) {
+        if (a < w) {
+            real *rt = reinterpret_cast<real *>(A.g + (size_t)jr * ng);
+            real *rp = reinterpret_cast<real *>(A.g + ((size_t)ng + jr) * ng);
+            int ir = ir0;
+#pragma unroll
+            for (int cc = 0; cc < kNfftMaxW; ++cc) {
+                if (cc < w) {
+                    const real f = wt[a] * wp[cc];
+                    atomicAdd(rt + 2 * ir, f * ttr);
+                    atomicAdd(rt + 2 * ir + 1, f * tti);
+                    atomicAdd(rp + 2 * ir, f * tpr);
+                    atomicAdd(rp + 2 * ir + 1, f * tpi);
+                    if (++ir == ng) ir = 0;
+                }
+            }
+            if (++jr == ng) jr = 0;
+        }
+    }
+}
+
+// One workgroup per grid row j: forward DFT over phi, keep |m| <= L.
+template <typename real>
+__global__ __launch_bounds__(kNfftNT, 1) void k_nfft_rows_fwd(NfftArgs<real> A) {
+    extern __shared__ unsigned char smem_raw[];
+    CD *wR = reinterpret_cast<CD *>(smem_raw);
+    C2<real> *buf = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
+    const int L = A.L, ng = A.ng, S = A.stride;
+    const int j = blockIdx.x;
+    const int nm = 2 * L + 1;
+    for (int i = threadIdx.x; i < ng; i += kNfftNT) {
+        buf[pad16(i)] = A.g[(size_t)j * ng + i];
+        buf[pad16(S + i)] = A.g[((size_t)ng + j) * ng + i];
+    }
+    __syncthreads();
+    fft_lds<real, kNfftNT>(buf, S, A.ffts, A.ffts + A.fft_ng, A.tw, wR, false);
+    for (int b = threadIdx.x; b < nm; b += kNfftNT) {
+        const int m = b - L;
+        const int src = m >= 0 ? m : ng + m;
+        A.g1[(size_t)j * nm + b] = buf[pad16(src)];
+        A.g1[((size_t)ng + j) * nm + b] = buf[pad16(S + src)];
+    }
+}
+
+// One workgroup per order m in [-L, L]: forward DFT over theta of column m,
+// conjugate deconvolution, inverse DFT of length nt, fold and store into the
+// virtual rings' buffer.
+template <typename real>
+__global__ __launch_bounds__(kNfftNT, 1) void k_nfft_cols_fwd(NfftArgs<real> A) {
+    extern __shared__ unsigned char smem_raw[];
+    CD *wR = reinterpret_cast<CD *>(smem_raw);
+    C2<real> *buf = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
+    const int L = A.L, nt = A.nt, ng = A.ng, S = A.stride;
+    const int b = blockIdx.x;
+    const int m = b - L;
+    const int am = m < 0 ? -m : m;
+    const int slot = m < 0 ? 2 : 0;
+    const real ext = (am & 1) ? (real)1 : (real)-1;
+    const int nm = 2 * L + 1;
+    for (int j = threadIdx.x; j < ng; j += kNfftNT) {
+        buf[pad16(j)] = A.g1[(size_t)j * nm + b];
+        buf[pad16(S + j)] = A.g1[((size_t)ng + j) * nm + b];
+    }
+    __syncthreads();
+    fft_lds<real, kNfftNT>(buf, S, A.ffts, A.ffts + A.fft_ng, A.tw, wR, false);
+    C2<real> dk[kNfftMaxK][2];
+#pragma unroll
+    for (int q = 0; q < kNfftMaxK; ++q) {
+        const int k = threadIdx.x + q * kNfftNT - L;
+        if (k <= L) {
+            const int src = k >= 0 ? k : ng + k;
+            double sp, cp;
+            sincos(M_PI * (double)k / (double)nt, &sp, &cp);  // conjugate of the adjoint's phase
+            const double sc = A.h * A.h / ((double)nt * A.psihat[k + L] * A.psihat[m + L]);
+            const CD ph = {cp * sc, sp * sc};
+            dk[q][0] = cmul_d(buf[pad16(src)], ph);
+            dk[q][1] = cmul_d(buf[pad16(S + src)], ph);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nt; i += kNfftNT) {
+        buf[pad16(i)] = {0, 0};
+        buf[pad16(S + i)] = {0, 0};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kNfftMaxK; ++q) {
+        const int k = threadIdx.x + q * kNfftNT - L;
+        if (k <= L) {
+            const int dst = k >= 0 ? k : nt + k;
+            buf[pad16(dst)] = dk[q][0];
+            buf[pad16(S + dst)] = dk[q][1];
+        }
+    }
+    __syncthreads();
+    fft_lds<real, kNfftNT>(buf, S, A.ffts, A.ffts + A.fft_nt, A.tw, wR, true);
+    // virtual ring t < nt/2 (pair p = t or nt/2 - 1 - t): its value plus its doubled-circle image
+    const int NRv = nt / 2;
+    for (int t = threadIdx.x; t < NRv; t += kNfftNT) {
+        const int p = t < nt / 4 ? t : nt / 2 - 1 - t;
+        const real f = (real)1 / (real)A.vs[p];
+        const C2<real> a0 = buf[pad16(t)], a1 = buf[pad16(nt - 1 - t)];
+        const C2<real> b0 = buf[pad16(S + t)], b1 = buf[pad16(S + nt - 1 - t)];
+        C2<real> *o = reinterpret_cast<C2<real> *>(A.RB + ((size_t)am * NRv + t) * 8);
+        const C2<real> vt = {(a0.x + ext * a1.x) * f, (a0.y + ext * a1.y) * f};
+        const C2<real> vp = {(b0.x + ext * b1.x) * f, (b0.y + ext * b1.y) * f};
+        o[slot] = vt;
+        o[slot + 1] = vp;
+        if (m == 0) {  // the -0 columns repeat +0 (unused by the recombination)
+            o[2] = vt;
+            o[3] = vp;
+        }
+    }
 }
 
 // ===========================================================================
@@ -1900,9 +2067,93 @@ static size_t leg_adj_lds(int nw, size_t rsz, bool bf16) {
 }
 
 template <typename real>
+static NfftArgs<real> make_nfft_args(const Plan &p, const void *Tin, void *Tout, bool weighted) {
+    const NfftPlan &nf = p.nfft;
+    NfftArgs<real> N{};
+    N.PB = static_cast<const real *>(nf.d_vpb);
+    N.RB = static_cast<real *>(nf.d_vpb);
+    N.g1 = static_cast<C2<real> *>(nf.d_g1);
+    N.g = static_cast<C2<real> *>(nf.d_g);
+    N.vs = nf.d_vs;
+    N.psihat = nf.d_psihat;
+    N.ffts = nf.d_ffts;
+    N.tw = nf.d_tw;
+    N.pts = nf.d_pts;
+    N.weights = p.d_weights;
+    N.Tin = static_cast<const C2<real> *>(Tin);
+    N.Tout = static_cast<C2<real> *>(Tout);
+    N.n = p.n;
+    N.beta = nf.beta;
+    N.h = 2.0 * M_PI / nf.ng;
+    N.fft_nt = nf.fft_nt;
+    N.fft_ng = nf.fft_ng;
+    N.L = p.L;
+    N.nt = nf.nt;
+    N.npv = nf.npv;
+    N.ng = nf.ng;
+    N.w = nf.w;
+    N.stride = (int)nf.lds_stride;
+    N.weighted = weighted ? 1 : 0;
+    return N;
+}
+
+template <typename real>
 static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, bool weighted,
                                hipStream_t st) {
     const bool bf16 = p.precision == VSHT_BF16X3;
+    if (p.kind == VSHT_PLAN_SCATTERED) {
+        // scattered points: spread, grid DFTs, virtual-ring values, then the ring analysis
+        const NfftPlan &nf = p.nfft;
+        const NfftArgs<real> N = make_nfft_args<real>(p, T, nullptr, weighted);
+        const size_t lds = ring_lds_bytes_len(nf.lds_stride, sizeof(real));
+        {
+            StageScope sc(p, VSHT_STAGE_SCATTERED, st);
+            const int64_t gsize = (int64_t)2 * nf.ng * nf.ng * 2;
+            hipLaunchKernelGGL(k_fill_zero<real>, dim3((unsigned)((gsize + 255) / 256)), dim3(256), 0, st,
+                               static_cast<real *>(nf.d_g), gsize);
+            hipLaunchKernelGGL(k_nfft_spread<real>, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, st, N);
+            hipLaunchKernelGGL(k_nfft_rows_fwd<real>, dim3(nf.ng), dim3(kNfftNT), lds, st, N);
+            hipLaunchKernelGGL(k_nfft_cols_fwd<real>, dim3(2 * p.L + 1), dim3(kNfftNT), lds, st, N);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        LegFwdArgs<real> G{};
+        G.RB = static_cast<const real *>(nf.d_vpb);
+        G.F = static_cast<real *>(p.d_fg);
+        G.pairs = nf.d_vpairs;
+        G.seeds = nf.d_vseeds;
+        G.pz = nf.d_vz;
+        G.aprime = p.d_aprime;
+        G.cscale = p.d_cscale;
+        G.L = p.L;
+        G.NP = nf.npv;
+        G.NPT = nf.npv;
+        G.NR = nf.nt / 2;
+        G.eq_ring = -1;
+        G.atomic = 0;
+        {
+            const int ntile = (nf.npv + kTileP - 1) / kTileP;  // <= 16 for the bandlimits served
+            StageScope sc(p, VSHT_STAGE_LEG_FWD, st);
+            const dim3 grid(p.L + 1, 1);
+            if constexpr (sizeof(real) == 4) {
+                if (bf16)
+                    hipLaunchKernelGGL(k_leg_fwd_bf16x3, grid, dim3(ntile * 64), leg_fwd_lds(ntile, 4), st, G);
+                else
+                    hipLaunchKernelGGL(k_leg_fwd_mfma<real>, grid, dim3(ntile * 64), leg_fwd_lds(ntile, 4), st, G);
+            } else {
+                hipLaunchKernelGGL(k_leg_fwd_mfma<real>, grid, dim3(ntile * 64), leg_fwd_lds(ntile, 8), st, G);
+            }
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const CoefArgs<real> C = make_coef_args<real>(p, nullptr, nullptr, a, b);
+        {
+            StageScope sc(p, VSHT_STAGE_RECOMBINE, st);
+            hipLaunchKernelGGL(k_recombine<real>, dim3((p.L + kTL - 1) / kTL, (p.L + 1 + kTM - 1) / kTM),
+                               dim3(256), 0, st, C);
+        }
+        return hipGetLastError();
+    }
     const RingArgs<real> R = make_ring_args<real>(p, T, nullptr, weighted);
     {
         StageScope sc(p, VSHT_STAGE_RING_FWD, st);
@@ -1986,29 +2237,7 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        NfftArgs<real> N{};
-        N.PB = static_cast<const real *>(nf.d_vpb);
-        N.g1 = static_cast<C2<real> *>(nf.d_g1);
-        N.g = static_cast<C2<real> *>(nf.d_g);
-        N.vs = nf.d_vs;
-        N.psihat = nf.d_psihat;
-        N.ffts = nf.d_ffts;
-        N.tw = nf.d_tw;
-        N.pts = nf.d_pts;
-        N.weights = p.d_weights;
-        N.Tout = static_cast<C2<real> *>(T);
-        N.n = p.n;
-        N.beta = nf.beta;
-        N.h = 2.0 * M_PI / nf.ng;
-        N.fft_nt = nf.fft_nt;
-        N.fft_ng = nf.fft_ng;
-        N.L = p.L;
-        N.nt = nf.nt;
-        N.npv = nf.npv;
-        N.ng = nf.ng;
-        N.w = nf.w;
-        N.stride = (int)nf.lds_stride;
-        N.weighted = weighted ? 1 : 0;
+        const NfftArgs<real> N = make_nfft_args<real>(p, nullptr, T, weighted);
         const size_t lds = ring_lds_bytes_len(nf.lds_stride, sizeof(real));
         StageScope sc(p, VSHT_STAGE_SCATTERED, st);
         hipLaunchKernelGGL(k_nfft_cols<real>, dim3(2 * p.L + 1), dim3(kNfftNT), lds, st, N);
@@ -2442,7 +2671,9 @@ hipError_t set_kernel_attributes() {
                              (const void *)kb_leg_fwd<float, true>, (const void *)kb_leg_adj<double, false>,
                              (const void *)kb_leg_adj<float, false>, (const void *)kb_leg_adj<float, true>};
     const void *nfft_kernels[] = {(const void *)k_nfft_cols<double>, (const void *)k_nfft_cols<float>,
-                                  (const void *)k_nfft_rows<double>, (const void *)k_nfft_rows<float>};
+                                  (const void *)k_nfft_rows<double>, (const void *)k_nfft_rows<float>,
+                                  (const void *)k_nfft_cols_fwd<double>, (const void *)k_nfft_cols_fwd<float>,
+                                  (const void *)k_nfft_rows_fwd<double>, (const void *)k_nfft_rows_fwd<float>};
     for (const void *k : nfft_kernels) {
         e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, big);
         if (e != hipSuccess) return e;

@@ -332,3 +332,45 @@ def test_scattered_grid_L256_sampled(torch, vsht, orc):
     err = rel_l2(T[pidx], orc.adjoint(L, a, b, xyz[pidx]))
     print("scattered grid L=256 sampled rel-L2 %.3e" % err)
     assert err < FP64_TOL
+
+
+@pytest.mark.parametrize("L,precision,tol", [(8, "fp64", FP64_TOL), (48, "fp64", FP64_TOL),
+                                             (48, "fp32", FP32_TOL)])
+def test_scattered_forward_vs_oracle(torch, vsht, orc, L, precision, tol):
+    """Forward transform at scattered points (the transpose of the grid path)."""
+    print_case("scattered forward", L, precision)
+    xyz, w = scattered_points(1200, 31)
+    w = w * (1.0 + 0.3 * np.random.default_rng(32).random(len(w)))
+    plan = vsht.Plan(L, xyz, w, precision=precision)
+    Tr = vi.random_field(len(w), 33)
+    ga, gb = run_forward(torch, plan, Tr)
+    a_ref, b_ref = orc.forward(L, xyz, w, Tr)
+    e_w = rel_l2(np.concatenate([ga, gb]), np.concatenate([a_ref, b_ref]))
+    ua, ub = run_forward(torch, plan, Tr, weighted=False)
+    a1, b1 = orc.forward(L, xyz, np.ones(len(w)), Tr)
+    e_u = rel_l2(np.concatenate([ua, ub]), np.concatenate([a1, b1]))
+    print("scattered forward L=%d %s weighted %.3e unweighted %.3e" % (L, precision, e_w, e_u))
+    assert e_w < tol and e_u < tol
+
+
+def test_scattered_dot_product(torch, vsht):
+    """<Adj(a, b), T> = <(a, b), Fwd_unweighted(T)> on the grid path (FP64)."""
+    L = 30
+    print_case("scattered dot test", L)
+    xyz, w = scattered_points(2000, 41)
+    plan = vsht.Plan(L, xyz, w)
+    a, b = vi.random_coeffs(L, 42)
+    T = vi.random_field(len(w), 43)
+    lhs = np.vdot(T, run_adjoint(torch, plan, a, b))
+    fa, fb = run_forward(torch, plan, T, weighted=False)
+    rhs = np.vdot(np.concatenate([fa, fb]), np.concatenate([a, b]))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_scattered_direct_forward_unsupported(torch, vsht):
+    from paper_1908_00041_amd import _binding as B
+    xyz, w = scattered_points(100, 51)
+    plan = vsht.Plan(8, xyz, w, scattered="direct")
+    with pytest.raises(B.VshtError) as ei:
+        run_forward(torch, plan, vi.random_field(len(w), 52))
+    assert ei.value.status == B.VSHT_EUNSUPPORTED
