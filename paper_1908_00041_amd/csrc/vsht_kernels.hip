@@ -810,6 +810,133 @@ struct FwdCompact<float> {
     }
 };
 
+// a'_{lp0+s}, s < N, as wave-uniform values (scalar loads); entries beyond
+// L+1 read the table's padding or the next order's entries and are zeroed.
+template <int N>
+__device__ __forceinline__ void load_aprime(const double *__restrict__ ap, int lp0, int Lp1, double (&a)[N]) {
+#pragma unroll
+    for (int s = 0; s < N; ++s) a[s] = ld_const(ap + lp0 + s);
+#pragma unroll
+    for (int s = 0; s < N; ++s)
+        if (lp0 + s > Lp1) a[s] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Binary64 Legendre stages on the four-block 4x4x4 MFMA (v_mfma_f64_4x4x4f64).
+// On gfx950 lane l holds A[block (l>>2)&3][row l&3][k l>>4],
+// B[block (l>>2)&3][k l>>4][column l&3] and D[block (l>>2)&3][row l>>4][column l&3]
+// (measured).  Each block is a 4 x 4 product of one parity class, so no
+// product is spent on the degrees of the other parity; per 16 degrees x 64
+// ring pairs a wave issues 32 of them (the 16x16x4 form needs 16 of four
+// times the cost, half of it on zeros).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double mma44(double a, double b, double c) {
+    return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
+// Analysis tile [16 degrees][64 pairs]: one read group is 8 consecutive rows
+// x 4 pairs; XOR-ing the pair with 4 (row & 7) puts them in distinct banks.
+struct SwzQ4Fwd {
+    static __device__ __forceinline__ int at(int row, int pair) { return row * kTileP + (pair ^ ((row & 7) << 2)); }
+};
+// Synthesis tile: one read group (32 lanes) is rows s, s+2 x 16 consecutive
+// pairs; XOR-ing the pair with 16 ((row >> 1) & 1) separates the two rows.
+struct SwzQ4Adj {
+    static __device__ __forceinline__ int at(int row, int pair) {
+        return row * kTileP + (pair ^ (((row >> 1) & 1) << 4));
+    }
+};
+
+// Analysis, binary64: workgroup = order m, waves = tiles of 64 ring pairs.
+// Instruction (row group r, pair step g): block b = (parity pi = b>>1, column
+// half h = b&1), rows = degrees lp0 + 2(4r + i) + pi, K = pairs 4g + k,
+// columns 4h + j of X[pi] (X[0] = N + S, X[1] = N - S).
+__device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, int m, int group,
+                                                  unsigned char *smem_raw) {
+    const int L = A.L, NP = A.NP, NPT = A.NPT, NR = A.NR;
+    const int nw = blockDim.x >> 6;
+    const int wave = uniform_int(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int tile = group * nw + wave;
+    double *qt = reinterpret_cast<double *>(smem_raw) + wave * kRowsB * kTileP;
+    double *red = reinterpret_cast<double *>(smem_raw) + nw * kRowsB * kTileP;  // [2][nw][128]
+    const int64_t t0 = tri_offset(L, m);
+    const double *RBm = A.RB + (size_t)m * NR * 8;
+    const int b = (lane >> 2) & 3, pi = b >> 1, h = b & 1, j = lane & 3, k = lane >> 4, i = lane & 3;
+    const int col = 4 * h + j;
+    double bv[16];
+#pragma unroll
+    for (int g = 0; g < 16; ++g) {
+        const int pp = tile * kTileP + 4 * g + k;
+        double v = 0.0;
+        if (pp < NPT) {
+            const PairDesc pd = A.pairs[pp];
+            const double xn = RBm[(size_t)pd.rn * 8 + col];
+            const double xs = pd.rs >= 0 ? RBm[(size_t)pd.rs * 8 + col] : 0.0;
+            v = pi == 0 ? xn + xs : xn - xs;
+        }
+        bv[g] = v;
+    }
+    const int p = tile * kTileP + lane;
+    const bool valid = p < NPT;
+    const double z = valid ? A.pz[p] : 0.0;
+    double q1 = 0.0, q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+    const double seq = A.eq_ring >= 0 ? A.seeds[(size_t)m * NP + NPT] : 0.0;
+    const double *xeq = A.eq_ring >= 0 ? RBm + (size_t)A.eq_ring * 8 : nullptr;
+    const double *ap = A.aprime + t0 - m;  // indexed by l'
+    const int nl = L + 2 - m;
+    const int nblk = (nl + kRowsB - 1) / kRowsB;
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int lp0 = m + blk * kRowsB;
+        double ab[kRowsB];
+        load_aprime(ap, lp0, L + 1, ab);
+#pragma unroll
+        for (int s = 0; s < kRowsB; ++s) {
+            const double v = fma(ab[s] * z, q1, -q2);
+            qt[SwzQ4Fwd::at(s, lane)] = v;
+            q2 = q1;
+            q1 = v;
+        }
+        __builtin_amdgcn_wave_barrier();
+        double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+        for (int g = 0; g < 16; ++g) {
+            const double a0 = qt[SwzQ4Fwd::at(2 * i + pi, 4 * g + k)];
+            const double a1 = qt[SwzQ4Fwd::at(8 + 2 * i + pi, 4 * g + k)];
+            acc0 = mma44(a0, bv[g], acc0);
+            acc1 = mma44(a1, bv[g], acc1);
+        }
+        __builtin_amdgcn_wave_barrier();
+        // D lane l: row (l >> 4) of block b -> degree offset 2(4r + (l>>4)) + pi, column col
+        double *rw = red + ((blk & 1) * nw + wave) * 128;
+        rw[lane] = acc0;
+        rw[64 + lane] = acc1;
+        __syncthreads();
+        for (int o = threadIdx.x; o < 128; o += blockDim.x) {
+            const int r = o >> 6, ln = o & 63;
+            const int bb = (ln >> 2) & 3, ppi = bb >> 1;
+            const int so = 2 * (4 * r + (ln >> 4)) + ppi;
+            const int c = 4 * (bb & 1) + (ln & 3);
+            const int lp = lp0 + so;
+            if (lp <= L + 1) {
+                const double *rb = red + (blk & 1) * nw * 128;
+                double sum = 0.0;
+                for (int w = 0; w < nw; ++w) sum += rb[w * 128 + o];
+                const int64_t ti = t0 + lp - m;
+                if (xeq && ppi == 0 && group == 0) {
+                    const int kk = (lp - m) >> 1;
+                    sum += ((kk & 1) ? -seq : seq) * xeq[c];
+                }
+                const double v = A.cscale[ti] * sum;
+                if (A.atomic)
+                    atomicAdd(&A.F[ti * 8 + c], v);
+                else
+                    A.F[ti * 8 + c] = v;
+            }
+        }
+    }
+}
+
 // One workgroup: order m, tiles [group nw, group nw + nw) of ring pairs.
 template <typename real>
 __device__ __forceinline__ void leg_fwd_body(const LegFwdArgs<real> &A, int m, int group,
@@ -899,7 +1026,10 @@ __device__ __forceinline__ void leg_fwd_body(const LegFwdArgs<real> &A, int m, i
 template <typename real>
 __global__ __launch_bounds__(1024) void k_leg_fwd_mfma(LegFwdArgs<real> A) {
     extern __shared__ unsigned char smem_raw[];
-    leg_fwd_body(A, blockIdx.x, blockIdx.y, smem_raw);
+    if constexpr (sizeof(real) == 8)
+        leg_fwd_f64q_body(A, blockIdx.x, blockIdx.y, smem_raw);
+    else
+        leg_fwd_body(A, blockIdx.x, blockIdx.y, smem_raw);
 }
 
 template <typename real>
@@ -913,6 +1043,77 @@ struct LegArgs {
     int NP;
     int NPT;              // pairs handled by the tiles (the equator, if any, is pair NPT)
 };
+
+// Synthesis, binary64: one wave = 64 ring pairs of order m.  Instruction
+// (pair set q, parity pi, column half h, degree step ks): block b = pairs
+// 16q + 4b + i, K = degrees lp0 + pi + 2(4ks + k), columns 4h + j of g.
+__device__ __forceinline__ void adj_tile_f64q(const LegArgs<double> &A, int m, int tile, int lane,
+                                              double *qt) {
+    const int L = A.L, NP = A.NP, NPT = A.NPT;
+    const int64_t t0 = tri_offset(L, m);
+    const double *g = A.FG + (t0 - m) * 8;  // indexed by l'
+    const double *ap = A.aprime + t0 - m;
+    const int p = tile * kTileP + lane;
+    const bool valid = p < NPT;
+    const double z = valid ? A.pz[p] : 0.0;
+    double q1 = 0.0, q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+    const int b = (lane >> 2) & 3, i = lane & 3, j = lane & 3, k = lane >> 4;
+    double acc[4][2][2];  // [pair set][parity][column half]
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int pi = 0; pi < 2; ++pi) acc[q][pi][0] = acc[q][pi][1] = 0.0;
+    const int nl = L + 2 - m;
+    const int nblk = (nl + kRowsB - 1) / kRowsB;
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int lp0 = m + blk * kRowsB;
+        // B operands: g[lp0 + pi + 2(4ks + k)][4h + j]
+        double bv[2][2][2];
+#pragma unroll
+        for (int pi = 0; pi < 2; ++pi)
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const int lp = lp0 + pi + 2 * (4 * ks + k);
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh)
+                    bv[pi][ks][hh] = lp <= L + 1 ? g[(int64_t)lp * 8 + 4 * hh + j] : 0.0;
+            }
+        double ab[kRowsB];
+        load_aprime(ap, lp0, L + 1, ab);
+#pragma unroll
+        for (int s = 0; s < kRowsB; ++s) {
+            const double v = fma(ab[s] * z, q1, -q2);
+            qt[SwzQ4Adj::at(s, lane)] = v;
+            q2 = q1;
+            q1 = v;
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int pi = 0; pi < 2; ++pi)
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double a = qt[SwzQ4Adj::at(pi + 8 * ks + 2 * k, 16 * q + 4 * b + i)];
+                    acc[q][pi][0] = mma44(a, bv[pi][ks][0], acc[q][pi][0]);
+                    acc[q][pi][1] = mma44(a, bv[pi][ks][1], acc[q][pi][1]);
+                }
+        __builtin_amdgcn_wave_barrier();
+    }
+    // D lane l: pair 16q + 4b + (l >> 4), column 4h + j of parity block pi
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int pp = tile * kTileP + 16 * q + 4 * b + (lane >> 4);
+        if (pp < NPT) {
+            double *o = A.PB + ((size_t)m * NP + pp) * 16;
+#pragma unroll
+            for (int pi = 0; pi < 2; ++pi) {
+                o[8 * pi + j] = acc[q][pi][0];
+                o[8 * pi + 4 + j] = acc[q][pi][1];
+            }
+        }
+    }
+}
 
 // One wave: pairs [64 tile, 64 tile + 64) of order m, computed in `real`, with
 // FG read and PB written in `store` (binary32 storage with binary64 arithmetic
@@ -979,7 +1180,10 @@ __global__ __launch_bounds__(256) void k_leg_adj_mfma(LegArgs<real> A) {
     const int tile = blockIdx.x * nw + wave;
     if (tile * kTileP >= A.NPT) return;  // whole wave idle (no barriers below)
     real *qt = reinterpret_cast<real *>(smem_raw) + wave * kRowsB * kTileP;
-    adj_tile_mfma<real, real>(A, blockIdx.y, tile, threadIdx.x & 63, qt);
+    if constexpr (sizeof(real) == 8)
+        adj_tile_f64q(A, blockIdx.y, tile, threadIdx.x & 63, qt);
+    else
+        adj_tile_mfma<real, real>(A, blockIdx.y, tile, threadIdx.x & 63, qt);
 }
 
 // ---------------------------------------------------------------------------
@@ -1062,16 +1266,6 @@ __device__ __forceinline__ f32x4 mma3(const Split8 &a, const Split8 &b, f32x4 ac
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, acc, 0, 0, 0);
 }
 
-// a'_{lp0+s}, s < N, as wave-uniform values (scalar loads); entries beyond
-// L+1 read the table's padding or the next order's entries and are zeroed.
-template <int N>
-__device__ __forceinline__ void load_aprime(const double *__restrict__ ap, int lp0, int Lp1, double (&a)[N]) {
-#pragma unroll
-    for (int s = 0; s < N; ++s) a[s] = ld_const(ap + lp0 + s);
-#pragma unroll
-    for (int s = 0; s < N; ++s)
-        if (lp0 + s > Lp1) a[s] = 0.0;
-}
 
 // Q tile of the analysis: [16 degrees][64 pairs] binary32 whose groups of 8
 // pairs are XOR-ed with the row, so that the 8 consecutive pairs one lane
@@ -1944,6 +2138,8 @@ __global__ __launch_bounds__(1024) void kb_leg_fwd(const LegFwdArgs<real> *__res
     const LegFwdArgs<real> A = ld_const(args + w.f);
     if constexpr (kBf16)
         leg_fwd_bf16x3_body(A, w.x, 0, smem_raw);
+    else if constexpr (sizeof(real) == 8)
+        leg_fwd_f64q_body(A, w.x, 0, smem_raw);
     else
         leg_fwd_body(A, w.x, 0, smem_raw);
 }
@@ -1969,7 +2165,10 @@ __global__ __launch_bounds__(256) void kb_leg_adj(const LegArgs<real> *__restric
             adj_tile_bf16x3(A, w.y, tile, lane, reinterpret_cast<u32x4_t *>(lds));
     } else {
         real *qt = reinterpret_cast<real *>(smem_raw) + wave * kRowsB * kTileP;
-        adj_tile_mfma<real, real>(A, w.y, tile, lane, qt);
+        if constexpr (sizeof(real) == 8)
+            adj_tile_f64q(A, w.y, tile, lane, qt);
+        else
+            adj_tile_mfma<real, real>(A, w.y, tile, lane, qt);
     }
 }
 
