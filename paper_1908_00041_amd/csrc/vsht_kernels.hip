@@ -835,9 +835,13 @@ __device__ __forceinline__ double mma44(double a, double b, double c) {
 }
 
 // Analysis tile [16 degrees][64 pairs]: one read group is 8 consecutive rows
-// x 4 pairs; XOR-ing the pair with 4 (row & 7) puts them in distinct banks.
+// x 4 pairs, read together with the same group 8 rows further (one paired
+// read); XOR-ing the pair with 4 (row & 7) and 16 (row >> 3) puts all 64
+// addresses in distinct bank pairs.
 struct SwzQ4Fwd {
-    static __device__ __forceinline__ int at(int row, int pair) { return row * kTileP + (pair ^ ((row & 7) << 2)); }
+    static __device__ __forceinline__ int at(int row, int pair) {
+        return row * kTileP + (pair ^ ((row & 7) << 2) ^ ((row & 8) << 1));
+    }
 };
 // Synthesis tile: one read group (32 lanes) is rows s, s+2 x 16 consecutive
 // pairs; XOR-ing the pair with 16 ((row >> 1) & 1) separates the two rows.
@@ -1065,10 +1069,9 @@ __device__ __forceinline__ void adj_tile_f64q(const LegArgs<double> &A, int m, i
         for (int pi = 0; pi < 2; ++pi) acc[q][pi][0] = acc[q][pi][1] = 0.0;
     const int nl = L + 2 - m;
     const int nblk = (nl + kRowsB - 1) / kRowsB;
-    for (int blk = 0; blk < nblk; ++blk) {
-        const int lp0 = m + blk * kRowsB;
-        // B operands: g[lp0 + pi + 2(4ks + k)][4h + j]
-        double bv[2][2][2];
+    // B operands of block blk: g[lp0 + pi + 2(4ks + k)][4h + j], fetched one block ahead
+    double bn[2][2][2];
+    auto fetch_b = [&](int lp0, double (&bv)[2][2][2]) {
 #pragma unroll
         for (int pi = 0; pi < 2; ++pi)
 #pragma unroll
@@ -1078,6 +1081,19 @@ __device__ __forceinline__ void adj_tile_f64q(const LegArgs<double> &A, int m, i
                 for (int hh = 0; hh < 2; ++hh)
                     bv[pi][ks][hh] = lp <= L + 1 ? g[(int64_t)lp * 8 + 4 * hh + j] : 0.0;
             }
+    };
+    fetch_b(m, bn);
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int lp0 = m + blk * kRowsB;
+        double bv[2][2][2];
+#pragma unroll
+        for (int pi = 0; pi < 2; ++pi)
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                bv[pi][ks][0] = bn[pi][ks][0];
+                bv[pi][ks][1] = bn[pi][ks][1];
+            }
+        if (blk + 1 < nblk) fetch_b(lp0 + kRowsB, bn);
         double ab[kRowsB];
         load_aprime(ap, lp0, L + 1, ab);
 #pragma unroll
