@@ -22,7 +22,7 @@
 
 #include <vector>
 
-#include "../../include/vsht.h"
+#include "vsht.h"
 
 namespace vsht {
 
