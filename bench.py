@@ -49,9 +49,12 @@ def measured_traffic(kernel, prec, L):
     if rec.get("kernel_source_sha256") != digest or rec.get("L") != L:
         return None
     table = rec.get("bytes_per_launch", {})
-    v = table.get(kernel) if kernel in table else \
-        table.get("%s<%s>" % (kernel, "double" if prec == "fp64" else "float"))
-    return None if v is None else int(v)
+    if kernel in table:
+        return int(table[kernel])
+    # templated kernels: "<name><double>" or, for the ring stages, "<name><double, 512>"
+    head = "%s<%s" % (kernel, "double" if prec == "fp64" else "float")
+    hits = [v for k, v in table.items() if k == head + ">" or k.startswith(head + ",")]
+    return int(hits[0]) if len(hits) == 1 else None
 
 
 def log(*a):
