@@ -238,6 +238,61 @@ __device__ __forceinline__ void fft_stage_small(C2<real> *buf, int buf_off, int 
 }
 
 
+// The same radix-R stage applied to both sequences of a ring in one pass
+// (sequence q at buf offset q * stride): a work item is one butterfly position
+// of both sequences, which share its twiddle, so the stage costs one barrier
+// pair instead of two.
+template <typename real, int NT, int R, int MAXI>
+__device__ __forceinline__ void fft_stage_small2(C2<real> *buf, int stride, int n, int Ns,
+                                                 const double *__restrict__ twn, bool inv) {
+    const int nb = n / R;
+    const int step = n / (Ns * R);
+    const real sg = inv ? (real)1 : (real)-1;
+    const int tid = opaque_tid();
+    C2<real> out[MAXI][2][R];
+    int dst[MAXI];
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) {
+        const int j = tid + i * NT;
+        dst[i] = -1;
+        if (j < nb) {
+            const int jr = j % Ns;
+            CD Wp[R];
+#pragma unroll
+            for (int t = 0; t < R; ++t) Wp[t] = {1.0, 0.0};
+            if (jr != 0) {
+                const CD W = tw_at(twn, jr * step, inv);
+                Wp[1] = W;
+#pragma unroll
+                for (int t = 2; t < R; ++t) Wp[t] = cd_mul(Wp[t - 1], W);
+            }
+#pragma unroll
+            for (int sq = 0; sq < 2; ++sq) {
+                C2<real> x[R];
+                const int base = sq * stride + j;
+                x[0] = buf[pad16(base)];
+#pragma unroll
+                for (int t = 1; t < R; ++t) {
+                    const C2<real> v = buf[pad16(base + t * nb)];
+                    x[t] = jr == 0 ? v : cmul_d(v, Wp[t]);
+                }
+                dft_small<real, R>(x, out[i][sq], sg);
+            }
+            dst[i] = (j / Ns) * Ns * R + jr;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i)
+        if (dst[i] >= 0) {
+#pragma unroll
+            for (int sq = 0; sq < 2; ++sq)
+#pragma unroll
+                for (int r = 0; r < R; ++r) buf[pad16(sq * stride + dst[i] + r * Ns)] = out[i][sq][r];
+        }
+    __syncthreads();
+}
+
 template <typename real, int NT, int MAXI>
 __device__ __forceinline__ void fft_stage_odd(C2<real> *buf, int buf_off, int n, int R, int Ns,
                                               const double *__restrict__ twn, const CD *wR, bool inv) {
@@ -418,6 +473,32 @@ __device__ __forceinline__ void fft_small_dispatch(C2<real> *buf, int off, int n
     else fft_stage_small<real, NT, R, 4>(buf, off, n, Ns, twn, inv);
 }
 
+// Both sequences in one pass when a thread's outputs across the barrier stay
+// within kMaxJointOut complex values; returns false (nothing done) otherwise.
+constexpr int kMaxJointOut = 16;
+template <typename real, int NT, int R>
+__device__ __forceinline__ bool fft_small_joint(C2<real> *buf, int stride, int n, int Ns,
+                                                const double *twn, bool inv) {
+    const int per = (n / R + NT - 1) / NT;
+    if (per <= 1 && 2 * R <= kMaxJointOut) {
+        fft_stage_small2<real, NT, R, 1>(buf, stride, n, Ns, twn, inv);
+        return true;
+    }
+    if constexpr (4 * R <= kMaxJointOut) {
+        if (per <= 2) {
+            fft_stage_small2<real, NT, R, 2>(buf, stride, n, Ns, twn, inv);
+            return true;
+        }
+    }
+    if constexpr (8 * R <= kMaxJointOut) {
+        if (per <= 4) {
+            fft_stage_small2<real, NT, R, 4>(buf, stride, n, Ns, twn, inv);
+            return true;
+        }
+    }
+    return false;
+}
+
 // Mixed-radix Stockham DFT of the two sequences at buf offsets 0 and `stride`.
 // Stages are applied to one sequence at a time (the two sequences of a ring
 // share each stage's twiddle set), so a thread holds at most 4 small
@@ -449,7 +530,15 @@ __device__ __forceinline__ void fft_core(C2<real> *buf, int stride, const FftDes
             for (int qq = threadIdx.x; qq < R; qq += NT) wR[qq] = tw_at(twn, qq * (n / R), inv);
             __syncthreads();
         }
-        for (int sq = 0; sq < 2; ++sq) {
+        bool joint = false;
+        switch (R) {
+            case 2: joint = fft_small_joint<real, NT, 2>(buf, stride, n, Ns, twn, inv); break;
+            case 3: joint = fft_small_joint<real, NT, 3>(buf, stride, n, Ns, twn, inv); break;
+            case 4: joint = fft_small_joint<real, NT, 4>(buf, stride, n, Ns, twn, inv); break;
+            case 5: joint = fft_small_joint<real, NT, 5>(buf, stride, n, Ns, twn, inv); break;
+            default: break;
+        }
+        for (int sq = 0; sq < (joint ? 0 : 2); ++sq) {
             const int off = sq * stride;
             switch (R) {
                 case 2: fft_small_dispatch<real, NT, 2>(buf, off, n, Ns, twn, inv); break;
