@@ -134,6 +134,7 @@ int fft_descriptor(int n, std::map<int, int> &index, std::vector<FftDesc> &ffts,
         fd.blue = 1;
         fd.M = M;
         fd.mdesc = fft_descriptor(M, index, ffts, tw);  // may reallocate ffts
+        fd.lds_shift = ffts[fd.mdesc].lds_shift;          // the ring buffer holds the length-M sequences
         // the ring stages take e^{i phi_j} from the length-n table as well
         fd.tw_offset = (int64_t)(tw.size() / 2);
         push_twiddles(n, tw);
@@ -168,6 +169,24 @@ int fft_descriptor(int n, std::map<int, int> &index, std::vector<FftDesc> &ffts,
         for (size_t q = 0; q < f.size(); ++q) fd.fac[q] = f[q];
         fd.tw_offset = (int64_t)(tw.size() / 2);
         push_twiddles(n, tw);
+        const int R = fd.nfac > 0 ? fd.fac[0] : 1;
+        // an odd first radix leaves unit and odd strides only: no LDS padding
+        fd.lds_shift = (R % 2 == 1) ? 30 : 4;
+        if (R > 5 && R <= kSmallTab) {
+            fd.rtab_offset = (int64_t)(tw.size() / 2);
+            const long double pi = 3.141592653589793238462643383279502884L;
+            std::vector<float> tf(2 * R);
+            for (int q = 0; q < R; ++q) {
+                const long double a = -2.0L * pi * (long double)q / (long double)R;
+                tw.push_back((double)cosl(a));
+                tw.push_back((double)sinl(a));
+                tf[2 * q] = (float)cosl(a);
+                tf[2 * q + 1] = (float)sinl(a);
+            }
+            std::vector<double> packed(2 * R, 0.0);  // R complex slots hold the 2R binary32 values
+            std::memcpy(packed.data(), tf.data(), tf.size() * sizeof(float));
+            tw.insert(tw.end(), packed.begin(), packed.end());
+        }
     }
     const int id = (int)ffts.size();
     ffts.push_back(fd);
@@ -183,7 +202,7 @@ bool fft_fits(const FftDesc &fd, const std::vector<FftDesc> &ffts, int nt) {
     for (int f = 0; f < fd.nfac; ++f) {
         const int R = fd.fac[f];
         const int nb = n / R, half = (R - 1) / 2;
-        if (f == 0 && R > 5 && R <= kSmallTab && 2 * nb * ((half + kKP1 - 1) / kKP1) <= nt) continue;
+        if (f == 0 && R > 5 && R <= kSmallTab && first_stage_waves(n, R) <= kMaxRoundsFirst * (nt / 64)) continue;
         if (R <= 5) {
             if ((nb + nt - 1) / nt > kMaxItemsSmall) return false;
         } else if (nb * ((half + kKP - 1) / kKP) > kMaxItemsOdd * nt) {

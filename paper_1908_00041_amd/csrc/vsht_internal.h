@@ -50,10 +50,11 @@ struct PairDesc {
 // Limits of the ring DFT stages (shared by the kernels and the plan's check
 // that every stage of a length fits a workgroup width).
 constexpr int kKP = 2;           // output pairs per work item of a generic odd radix
-constexpr int kKP1 = 4;          // the same for the twiddle-free first odd stage
 constexpr int kSmallTab = 128;   // largest odd radix whose cos/sin table is staged in LDS
 constexpr int kMaxItemsSmall = 4;  // work items per thread of a radix-2..5 stage
 constexpr int kMaxItemsOdd = 2;    // work items per thread of a generic odd stage
+constexpr int kKU = 5;             // output pairs per work item of the first odd stage
+constexpr int kMaxRoundsFirst = 2; // waves per wave slot of a workgroup in that stage
 
 // Mixed-radix Stockham descriptor for one DFT length.
 constexpr int kMaxFactors = 24;
@@ -67,10 +68,19 @@ struct FftDesc {
     int32_t blue;
     int32_t M;
     int32_t mdesc;
-    int32_t pad;
+    int32_t lds_shift;     // LDS layout of the sequences: element i at i + (i >> lds_shift)
     int64_t chirp_offset;  // w_k = e^{-i pi k^2 / n}, k < n
     int64_t bhat_offset;   // DFT_M of conj(w) (forward), then of w (inverse), each / M: 2M entries
+    // first radix R = fac[0] when 5 < R <= kSmallTab: e^{-2 pi i q / R}, q < R, as R complex
+    // binary64 values, then the same as R complex binary32 values in the next R entries
+    int64_t rtab_offset;
 };
+
+// Waves of the first odd stage of radix R on a ring's two sequences of length n:
+// one group of kKU output pairs per wave, over the 2 n / R columns of both sequences.
+__host__ __device__ inline int first_stage_waves(int n, int R) {
+    return ((R - 1) / 2 + kKU - 1) / kKU * ((2 * (n / R) + 63) / 64);
+}
 
 // A scattered point as the double-Fourier-sphere stages see it (sorted by grid cell).
 struct NfftPoint {

@@ -118,9 +118,17 @@ __global__ void k_seeds(const double *__restrict__ pair_s, int NP, int L,
 struct CD {
     double x, y;
 };
-// LDS index of element i of the ring buffers: one pad element after every 16,
-// which spreads the strided Stockham writes over the banks.
-__device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
+// Complex sequences in LDS.  Element i sits at p[i + (i >> ps)]: ps = 4 puts one
+// pad element after every 16, which spreads the stride-4 and stride-2 writes of
+// a first radix-4 or radix-2 stage over the banks; lengths whose first stage
+// has an odd radix keep unit- and odd-stride accesses only, which are free of
+// bank conflicts unpadded (ps = 30).  The choice is the DFT descriptor's.
+template <typename real>
+struct Seq {
+    C2<real> *p;
+    int ps;
+    __device__ __forceinline__ C2<real> &operator[](int i) const { return p[i + (i >> ps)]; }
+};
 __device__ __forceinline__ CD cd_mul(CD a, CD b) {
     return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
@@ -192,7 +200,7 @@ __device__ __forceinline__ void dft_small(const C2<real> *x, C2<real> *y, real s
 }
 
 template <typename real, int NT, int R, int MAXI>
-__device__ __forceinline__ void fft_stage_small(C2<real> *buf, int buf_off, int n, int Ns,
+__device__ __forceinline__ void fft_stage_small(Seq<real> buf, int buf_off, int n, int Ns,
                                                 const double *__restrict__ twn, bool inv) {
     const int nb = n / R;
     const int items = nb;
@@ -210,16 +218,16 @@ __device__ __forceinline__ void fft_stage_small(C2<real> *buf, int buf_off, int 
             const int j = it;
             const int jr = j % Ns;
             C2<real> x[R];
-            x[0] = buf[pad16(off + j)];
+            x[0] = buf[off + j];
             if (jr == 0) {
 #pragma unroll
-                for (int t = 1; t < R; ++t) x[t] = buf[pad16(off + j + t * nb)];
+                for (int t = 1; t < R; ++t) x[t] = buf[off + j + t * nb];
             } else {
                 const CD W = tw_at(twn, jr * step, inv);
                 CD Wt = W;
 #pragma unroll
                 for (int t = 1; t < R; ++t) {
-                    x[t] = cmul_d(buf[pad16(off + j + t * nb)], Wt);
+                    x[t] = cmul_d(buf[off + j + t * nb], Wt);
                     if (t + 1 < R) Wt = cd_mul(Wt, W);
                 }
             }
@@ -232,7 +240,7 @@ __device__ __forceinline__ void fft_stage_small(C2<real> *buf, int buf_off, int 
     for (int i = 0; i < MAXI; ++i)
         if (dst[i] >= 0) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[pad16(dst[i] + r * Ns)] = out[i][r];
+            for (int r = 0; r < R; ++r) buf[dst[i] + r * Ns] = out[i][r];
         }
     __syncthreads();
 }
@@ -243,7 +251,7 @@ __device__ __forceinline__ void fft_stage_small(C2<real> *buf, int buf_off, int 
 // of both sequences, which share its twiddle, so the stage costs one barrier
 // pair instead of two.
 template <typename real, int NT, int R, int MAXI>
-__device__ __forceinline__ void fft_stage_small2(C2<real> *buf, int stride, int n, int Ns,
+__device__ __forceinline__ void fft_stage_small2(Seq<real> buf, int stride, int n, int Ns,
                                                  const double *__restrict__ twn, bool inv) {
     const int nb = n / R;
     const int step = n / (Ns * R);
@@ -270,10 +278,10 @@ __device__ __forceinline__ void fft_stage_small2(C2<real> *buf, int stride, int 
             for (int sq = 0; sq < 2; ++sq) {
                 C2<real> x[R];
                 const int base = sq * stride + j;
-                x[0] = buf[pad16(base)];
+                x[0] = buf[base];
 #pragma unroll
                 for (int t = 1; t < R; ++t) {
-                    const C2<real> v = buf[pad16(base + t * nb)];
+                    const C2<real> v = buf[base + t * nb];
                     x[t] = jr == 0 ? v : cmul_d(v, Wp[t]);
                 }
                 dft_small<real, R>(x, out[i][sq], sg);
@@ -288,13 +296,13 @@ __device__ __forceinline__ void fft_stage_small2(C2<real> *buf, int stride, int 
 #pragma unroll
             for (int sq = 0; sq < 2; ++sq)
 #pragma unroll
-                for (int r = 0; r < R; ++r) buf[pad16(sq * stride + dst[i] + r * Ns)] = out[i][sq][r];
+                for (int r = 0; r < R; ++r) buf[sq * stride + dst[i] + r * Ns] = out[i][sq][r];
         }
     __syncthreads();
 }
 
 template <typename real, int NT, int MAXI>
-__device__ __forceinline__ void fft_stage_odd(C2<real> *buf, int buf_off, int n, int R, int Ns,
+__device__ __forceinline__ void fft_stage_odd(Seq<real> buf, int buf_off, int n, int R, int Ns,
                                               const double *__restrict__ twn, const CD *wR, bool inv) {
     const int nb = n / R;
     const int half = (R - 1) / 2;
@@ -316,7 +324,7 @@ __device__ __forceinline__ void fft_stage_odd(C2<real> *buf, int buf_off, int n,
             const int j = it / G;
             const int jr = j % Ns;
             const int sb = off + j;
-            const C2<real> x0 = buf[pad16(sb)];
+            const C2<real> x0 = buf[sb];
             const CD W = tw_at(twn, jr * step, inv);
             const CD WR = tw_at(twn, (int)(((int64_t)jr * R * step) % n), inv);  // W^R
             C2<real> A[kKP], B[kKP], S = {0, 0};
@@ -332,8 +340,8 @@ __device__ __forceinline__ void fft_stage_odd(C2<real> *buf, int buf_off, int n,
             for (int t = 1; t <= half; ++t) {
                 Wt = cd_mul(Wt, W);
                 const CD Wm = cd_mul(WR, CD{Wt.x, -Wt.y});  // W^{R-t}
-                const C2<real> yt = cmul_d(buf[pad16(sb + t * nb)], Wt);
-                const C2<real> ym = cmul_d(buf[pad16(sb + (R - t) * nb)], Wm);
+                const C2<real> yt = cmul_d(buf[sb + t * nb], Wt);
+                const C2<real> ym = cmul_d(buf[sb + (R - t) * nb], Wm);
                 const C2<real> u = cadd(yt, ym), v = csub(yt, ym);
                 S = cadd(S, u);
 #pragma unroll
@@ -368,78 +376,108 @@ __device__ __forceinline__ void fft_stage_odd(C2<real> *buf, int buf_off, int n,
             for (int kk = 0; kk < kKP; ++kk) {
                 const int k = grp[i] * kKP + kk + 1;
                 if (k <= half) {
-                    buf[pad16(dst[i] + k * Ns)] = out[i][2 * kk];
-                    buf[pad16(dst[i] + (R - k) * Ns)] = out[i][2 * kk + 1];
+                    buf[dst[i] + k * Ns] = out[i][2 * kk];
+                    buf[dst[i] + (R - k) * Ns] = out[i][2 * kk + 1];
                 }
             }
-            if (grp[i] == 0) buf[pad16(dst[i])] = out[i][2 * kKP];
+            if (grp[i] == 0) buf[dst[i]] = out[i][2 * kKP];
         }
     __syncthreads();
 }
 
-// First stage (Ns = 1, so no twiddles) of an odd prime radix R > 5, both
-// sequences in one pass: work item (sequence, column j, group g) forms the
-// outputs k = 4g+1 .. 4g+4 and R-k of the R-point DFT of column j from
-// u_t = x_t + x_{R-t}, v_t = x_t - x_{R-t}:
+// Entry q of the first-radix table e^{-2 pi i q / R} in the working precision,
+// read with a scalar load (q is wave-uniform).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define VSHT_CONST_AS __attribute__((address_space(4)))
+#else
+#define VSHT_CONST_AS
+#endif
+template <typename real>
+__device__ __forceinline__ const VSHT_CONST_AS C2<real> *rtab_base(const double *rtab, int R);
+template <>
+__device__ __forceinline__ const VSHT_CONST_AS C2<double> *rtab_base<double>(const double *rtab, int) {
+    return (const VSHT_CONST_AS C2<double> *)rtab;
+}
+template <>
+__device__ __forceinline__ const VSHT_CONST_AS C2<float> *rtab_base<float>(const double *rtab, int R) {
+    return (const VSHT_CONST_AS C2<float> *)(rtab + 2 * R);
+}
+
+// First stage (Ns = 1, so no twiddles) of an odd prime radix R > 5 on both
+// sequences in one pass.  Each wave owns one group g of kKU output pairs
+// k = kKU g + 1 .. kKU g + kKU (and R - k) and its lanes run over the 2 n / R
+// columns of the two sequences, so every cos/sin factor is the same across the
+// wave and comes from the scalar unit:
+//     u_t = x_t + x_{R-t},  v_t = x_t - x_{R-t},
 //     X_k = x_0 + sum_t u_t cos(2 pi k t / R) + i sum_t v_t (-+ sin(2 pi k t / R)),
-//     X_{R-k} = the same with the second sum negated,
-// with cos/sin read from the LDS table wr (carrying the direction's sign).
+//     X_{R-k} = the same with the second sum negated.
 template <typename real, int NT, int MAXI>
-__device__ __forceinline__ void fft_stage_odd_first(C2<real> *buf, int stride, int n, int R,
-                                                    const C2<real> *wr) {
+__device__ __forceinline__ void fft_stage_odd_first(Seq<real> buf, int stride, int n, int R,
+                                                    const double *rtab, bool inv) {
     const int nb = n / R;
     const int half = (R - 1) / 2;
-    const int G = (half + kKP1 - 1) / kKP1;
-    const int per_seq = nb * G;
-    const int tid = opaque_tid();
-    C2<real> out[MAXI][2 * kKP1 + 1];
+    const int cols = 2 * nb;
+    const int wpg = (cols + 63) >> 6;  // waves per group
+    const int nw = first_stage_waves(n, R);
+    const int wave0 = uniform_int(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const real bs = inv ? (real)-1 : (real)1;
+    const VSHT_CONST_AS C2<real> *tab = rtab_base<real>(rtab, R);
+    C2<real> out[MAXI][2 * kKU + 1];
     int dst[MAXI], grp[MAXI];
 #pragma unroll
     for (int i = 0; i < MAXI; ++i) {
-        const int it = tid + i * NT;
+        const int wv = wave0 + i * (NT / 64);
         dst[i] = -1;
         grp[i] = 0;
-        if (it < 2 * per_seq) {
-            const int sq = it >= per_seq ? 1 : 0;
-            const int r = it - sq * per_seq;
-            const int j = r / G, g = r - j * G;
-            const int sb = sq * stride + j;
-            const C2<real> x0 = buf[pad16(sb)];
-            C2<real> A[kKP1], B[kKP1], S = {0, 0};
-            int q[kKP1], kq[kKP1];
+        if (wv < nw) {
+            const int g = wv / wpg;
+            const int cs0 = (wv - g * wpg) * 64 + lane;
+            // lanes past the last column compute on column 0 and store nothing, so the
+            // loop stays in uniform control flow and the table reads stay scalar
+            const bool valid = cs0 < cols;
+            {
+                const int cs = valid ? cs0 : 0;
+                const int sq = cs >= nb ? 1 : 0;
+                const int j = cs - sq * nb;
+                const int sb = sq * stride + j;
+                const C2<real> x0 = buf[sb];
+                C2<real> A[kKU], B[kKU], S = {0, 0};
+                int q[kKU], kq[kKU];
 #pragma unroll
-            for (int kk = 0; kk < kKP1; ++kk) {
-                A[kk] = B[kk] = {0, 0};
-                kq[kk] = g * kKP1 + kk + 1;
-                if (kq[kk] > half) kq[kk] = 0;  // beyond the last pair: contributes nothing used
-                q[kk] = 0;
-            }
-#pragma unroll 2
-            for (int t = 1; t <= half; ++t) {
-                const C2<real> xt = buf[pad16(sb + t * nb)];
-                const C2<real> xm = buf[pad16(sb + (R - t) * nb)];
-                const C2<real> u = cadd(xt, xm), v = csub(xt, xm);
-                S = cadd(S, u);
-#pragma unroll
-                for (int kk = 0; kk < kKP1; ++kk) {
-                    q[kk] += kq[kk];
-                    if (q[kk] >= R) q[kk] -= R;
-                    const C2<real> w = wr[q[kk]];
-                    A[kk].x += u.x * w.x;
-                    A[kk].y += u.y * w.x;
-                    B[kk].x += v.x * w.y;
-                    B[kk].y += v.y * w.y;
+                for (int kk = 0; kk < kKU; ++kk) {
+                    A[kk] = B[kk] = {0, 0};
+                    kq[kk] = g * kKU + kk + 1;
+                    if (kq[kk] > half) kq[kk] = 0;  // beyond the last pair: contributes nothing used
+                    q[kk] = 0;
                 }
-            }
+#pragma unroll 2
+                for (int t = 1; t <= half; ++t) {
+                    const C2<real> xt = buf[sb + t * nb];
+                    const C2<real> xm = buf[sb + (R - t) * nb];
+                    const C2<real> u = cadd(xt, xm), v = csub(xt, xm);
+                    S = cadd(S, u);
 #pragma unroll
-            for (int kk = 0; kk < kKP1; ++kk) {
-                const C2<real> a = cadd(x0, A[kk]);
-                out[i][2 * kk] = cadd_i(a, B[kk], (real)1);
-                out[i][2 * kk + 1] = cadd_i(a, B[kk], (real)-1);
+                    for (int kk = 0; kk < kKU; ++kk) {
+                        q[kk] += kq[kk];
+                        if (q[kk] >= R) q[kk] -= R;
+                        const C2<real> w = tab[q[kk]];
+                        A[kk].x += u.x * w.x;
+                        A[kk].y += u.y * w.x;
+                        B[kk].x += v.x * w.y;
+                        B[kk].y += v.y * w.y;
+                    }
+                }
+#pragma unroll
+                for (int kk = 0; kk < kKU; ++kk) {
+                    const C2<real> a = cadd(x0, A[kk]);
+                    out[i][2 * kk] = cadd_i(a, B[kk], bs);
+                    out[i][2 * kk + 1] = cadd_i(a, B[kk], -bs);
+                }
+                out[i][2 * kKU] = cadd(x0, S);
+                dst[i] = valid ? sq * stride + j * R : -1;
+                grp[i] = g;
             }
-            out[i][2 * kKP1] = cadd(x0, S);
-            dst[i] = sq * stride + j * R;
-            grp[i] = g;
         }
     }
     __syncthreads();
@@ -447,24 +485,24 @@ __device__ __forceinline__ void fft_stage_odd_first(C2<real> *buf, int stride, i
     for (int i = 0; i < MAXI; ++i)
         if (dst[i] >= 0) {
 #pragma unroll
-            for (int kk = 0; kk < kKP1; ++kk) {
-                const int k = grp[i] * kKP1 + kk + 1;
+            for (int kk = 0; kk < kKU; ++kk) {
+                const int k = grp[i] * kKU + kk + 1;
                 if (k <= half) {
-                    buf[pad16(dst[i] + k)] = out[i][2 * kk];
-                    buf[pad16(dst[i] + R - k)] = out[i][2 * kk + 1];
+                    buf[dst[i] + k] = out[i][2 * kk];
+                    buf[dst[i] + R - k] = out[i][2 * kk + 1];
                 }
             }
-            if (grp[i] == 0) buf[pad16(dst[i])] = out[i][2 * kKP1];
+            if (grp[i] == 0) buf[dst[i]] = out[i][2 * kKU];
         }
     __syncthreads();
 }
 
-// Two sequences of length fdp->n in buf (element i at pad16(i)); wR is an LDS
+// Two sequences of length fdp->n in buf; wR is an LDS
 // scratch of kSmallTab entries.
 // The number of work items per thread (MAXI) is chosen per stage so that the
 // outputs kept across the barrier fit in registers.
 template <typename real, int NT, int R>
-__device__ __forceinline__ void fft_small_dispatch(C2<real> *buf, int off, int n, int Ns,
+__device__ __forceinline__ void fft_small_dispatch(Seq<real> buf, int off, int n, int Ns,
                                                    const double *twn, bool inv) {
     static_assert(kMaxItemsSmall == 4, "dispatch below instantiates up to 4 items per thread");
     const int per = (n / R + NT - 1) / NT;
@@ -477,7 +515,7 @@ __device__ __forceinline__ void fft_small_dispatch(C2<real> *buf, int off, int n
 // within kMaxJointOut complex values; returns false (nothing done) otherwise.
 constexpr int kMaxJointOut = 16;
 template <typename real, int NT, int R>
-__device__ __forceinline__ bool fft_small_joint(C2<real> *buf, int stride, int n, int Ns,
+__device__ __forceinline__ bool fft_small_joint(Seq<real> buf, int stride, int n, int Ns,
                                                 const double *twn, bool inv) {
     const int per = (n / R + NT - 1) / NT;
     if (per <= 1 && 2 * R <= kMaxJointOut) {
@@ -504,7 +542,7 @@ __device__ __forceinline__ bool fft_small_joint(C2<real> *buf, int stride, int n
 // share each stage's twiddle set), so a thread holds at most 4 small
 // butterflies or 2 odd-radix work items across a barrier (n <= 4096).
 template <typename real, int NT>
-__device__ __forceinline__ void fft_core(C2<real> *buf, int stride, const FftDesc *fdp,
+__device__ __forceinline__ void fft_core(Seq<real> buf, int stride, const FftDesc *fdp,
                                          const double *__restrict__ tw, CD *wR, bool inv) {
     const int n = ld_const(&fdp->n);
     const int nfac = ld_const(&fdp->nfac);
@@ -512,19 +550,21 @@ __device__ __forceinline__ void fft_core(C2<real> *buf, int stride, const FftDes
     int Ns = 1;
     for (int f = 0; f < nfac; ++f) {
         const int R = ld_const(&fdp->fac[f]);
-        if (f == 0 && R > 5 && R <= kSmallTab &&
-            2 * (n / R) * (((R - 1) / 2 + kKP1 - 1) / kKP1) <= NT) {
-            // twiddle-free first stage, table in the working precision (one
-            // work item per thread; longer stages take the general path below)
-            C2<real> *wr = reinterpret_cast<C2<real> *>(wR);
-            for (int qq = threadIdx.x; qq < R; qq += NT) {
-                const CD c = tw_at(twn, qq * (n / R), inv);
-                wr[qq] = {(real)c.x, (real)c.y};
+        if (f == 0 && R > 5 && R <= kSmallTab) {
+            // twiddle-free first stage (longer stages take the general path below)
+            static_assert(kMaxRoundsFirst == 2, "dispatch below instantiates up to 2 waves per slot");
+            const int rounds = (first_stage_waves(n, R) + NT / 64 - 1) / (NT / 64);
+            const double *rtab = tw + 2 * ld_const(&fdp->rtab_offset);
+            if (rounds <= 1) {
+                fft_stage_odd_first<real, NT, 1>(buf, stride, n, R, rtab, inv);
+                Ns *= R;
+                continue;
             }
-            __syncthreads();
-            fft_stage_odd_first<real, NT, 1>(buf, stride, n, R, wr);
-            Ns *= R;
-            continue;
+            if (rounds <= 2) {
+                fft_stage_odd_first<real, NT, 2>(buf, stride, n, R, rtab, inv);
+                Ns *= R;
+                continue;
+            }
         }
         if (R > 5 && R <= kSmallTab) {
             for (int qq = threadIdx.x; qq < R; qq += NT) wR[qq] = tw_at(twn, qq * (n / R), inv);
@@ -564,7 +604,7 @@ __device__ __forceinline__ int seq_stride(const FftDesc *fdp) {
 }
 
 // DFT of length n of the two sequences of a ring (element i of sequence q at
-// buf[pad16(q * stride + i)], stride >= seq_stride), forward (e^{-2 pi i j m / n}) or inverse.
+// buf[q * stride + i], stride >= seq_stride), forward (e^{-2 pi i j m / n}) or inverse.
 // Lengths with a prime factor above the generic-radix limit use Bluestein's
 // identity j m = (j^2 + m^2 - (m - j)^2) / 2: with w_k = e^{-i pi k^2 / n},
 //     X_m = w_m sum_j (x_j w_j) conj(w_{m-j}),
@@ -572,7 +612,7 @@ __device__ __forceinline__ int seq_stride(const FftDesc *fdp) {
 // two mixed-radix DFTs of length M and the tabulated transform of the kernel
 // (already divided by M); the inverse uses conj(w).
 template <typename real, int NT>
-__device__ __forceinline__ void fft_lds(C2<real> *buf, int stride, const FftDesc *ffts, const FftDesc *fdp,
+__device__ __forceinline__ void fft_lds(Seq<real> buf, int stride, const FftDesc *ffts, const FftDesc *fdp,
                                         const double *__restrict__ tw, CD *wR, bool inv) {
     if (!ld_const(&fdp->blue)) {
         fft_core<real, NT>(buf, stride, fdp, tw, wR, inv);
@@ -585,7 +625,7 @@ __device__ __forceinline__ void fft_lds(C2<real> *buf, int stride, const FftDesc
         const CD w = tw_at(ch, i < n ? i : 0, inv);
 #pragma unroll
         for (int sq = 0; sq < 2; ++sq) {
-            C2<real> &v = buf[pad16(sq * stride + i)];
+            C2<real> &v = buf[sq * stride + i];
             v = i < n ? cmul_d(v, w) : C2<real>{0, 0};
         }
     }
@@ -596,7 +636,7 @@ __device__ __forceinline__ void fft_lds(C2<real> *buf, int stride, const FftDesc
         const CD w = tw_at(bh, i, false);
 #pragma unroll
         for (int sq = 0; sq < 2; ++sq) {
-            C2<real> &v = buf[pad16(sq * stride + i)];
+            C2<real> &v = buf[sq * stride + i];
             v = cmul_d(v, w);
         }
     }
@@ -606,7 +646,7 @@ __device__ __forceinline__ void fft_lds(C2<real> *buf, int stride, const FftDesc
         const CD w = tw_at(ch, i, inv);
 #pragma unroll
         for (int sq = 0; sq < 2; ++sq) {
-            C2<real> &v = buf[pad16(sq * stride + i)];
+            C2<real> &v = buf[sq * stride + i];
             v = cmul_d(v, w);
         }
     }
@@ -646,11 +686,12 @@ struct RingArgs {
 template <typename real, int NT>
 __device__ __forceinline__ void ring_fwd_body(const RingArgs<real> &A, int r, unsigned char *smem_raw) {
     CD *wR = reinterpret_cast<CD *>(smem_raw);
-    C2<real> *buf = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
+    C2<real> *lds = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
     const int NR = A.NR;
     const int L = A.L;
     const RingDesc rd = ld_uniform(A.rings + r);
     const FftDesc *fdp = A.ffts + rd.fft;
+    const Seq<real> buf = {lds, ld_const(&fdp->lds_shift)};
     const int n = rd.nphi;
     const int n2 = seq_stride(fdp);
     const double *twn = A.tw + 2 * ld_const(&fdp->tw_offset);
@@ -669,8 +710,8 @@ __device__ __forceinline__ void ring_fwd_body(const RingArgs<real> &A, int r, un
         th.y = w * (z * (c * t1.y + sn * t2.y) - s * t3.y);
         ph.x = w * (c * t2.x - sn * t1.x);
         ph.y = w * (c * t2.y - sn * t1.y);
-        buf[pad16(j)] = th;
-        buf[pad16(n2 + j)] = ph;
+        buf[j] = th;
+        buf[n2 + j] = ph;
     }
     __syncthreads();
     fft_lds<real, NT>(buf, n2, A.ffts, fdp, A.tw, wR, false);
@@ -684,20 +725,21 @@ __device__ __forceinline__ void ring_fwd_body(const RingArgs<real> &A, int r, un
         const C2<real> fp = {(real)(cph * inv_s), (real)(-sph * inv_s)};
         const C2<real> fm = {(real)(cph * inv_s), (real)(sph * inv_s)};
         C2<real> *o = A.buf + ((size_t)m * NR + r) * 4;
-        o[0] = cmul(buf[pad16(bp)], fp);
-        o[1] = cmul(buf[pad16(n2 + bp)], fp);
-        o[2] = cmul(buf[pad16(bm)], fm);
-        o[3] = cmul(buf[pad16(n2 + bm)], fm);
+        o[0] = cmul(buf[bp], fp);
+        o[1] = cmul(buf[n2 + bp], fp);
+        o[2] = cmul(buf[bm], fm);
+        o[3] = cmul(buf[n2 + bm], fm);
     }
 }
 
 template <typename real, int NT>
 __device__ __forceinline__ void ring_adj_body(const RingArgs<real> &A, int r, unsigned char *smem_raw) {
     CD *wR = reinterpret_cast<CD *>(smem_raw);
-    C2<real> *buf = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
+    C2<real> *lds = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
     const int L = A.L;
     const RingDesc rd = ld_uniform(A.rings + r);
     const FftDesc *fdp = A.ffts + rd.fft;
+    const Seq<real> buf = {lds, ld_const(&fdp->lds_shift)};
     const int n = rd.nphi;
     const int n2 = seq_stride(fdp);
     const int p = rd.pair;
@@ -727,8 +769,8 @@ __device__ __forceinline__ void ring_adj_body(const RingArgs<real> &A, int r, un
                 m = pass == 0 ? m + n : m - n;
             }
         }
-        buf[pad16(b)] = hth;
-        buf[pad16(n2 + b)] = hph;
+        buf[b] = hth;
+        buf[n2 + b] = hph;
     }
     __syncthreads();
     fft_lds<real, NT>(buf, n2, A.ffts, fdp, A.tw, wR, true);
@@ -738,7 +780,7 @@ __device__ __forceinline__ void ring_adj_body(const RingArgs<real> &A, int r, un
         const real c = (real)(rd.c0 * er - rd.s0 * ei);
         const real sn = (real)(rd.s0 * er + rd.c0 * ei);
         const real z = (real)rd.z, s = (real)rd.s;
-        C2<real> th = buf[pad16(j)], ph = buf[pad16(n2 + j)];
+        C2<real> th = buf[j], ph = buf[n2 + j];
         const int64_t k = rd.offset + j;
         if (A.weighted) {  // W S: the Hermitian transpose of the weighted analysis
             const real w = (real)(rd.uniform_w ? rd.w : A.weights[k]);
@@ -1864,7 +1906,8 @@ template <typename real>
 __global__ __launch_bounds__(kNfftNT, 1) void k_nfft_cols(NfftArgs<real> A) {
     extern __shared__ unsigned char smem_raw[];
     CD *wR = reinterpret_cast<CD *>(smem_raw);
-    C2<real> *buf = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
+    C2<real> *lds = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
+    Seq<real> buf = {lds, ld_const(&A.ffts[A.fft_nt].lds_shift)};
     const int L = A.L, nt = A.nt, npv = A.npv, ng = A.ng, S = A.stride;
     const int b = blockIdx.x;  // m + L
     const int m = b - L;
@@ -1880,8 +1923,8 @@ __global__ __launch_bounds__(kNfftNT, 1) void k_nfft_cols(NfftArgs<real> A) {
         const C2<real> Et = e[slot], Ep = e[slot + 1], Ot = e[4 + slot], Op = e[4 + slot + 1];
         const real f = (upper ? (real)1 : ext) / (real)A.vs[p];
         const real so = north ? (real)1 : (real)-1;
-        buf[pad16(t)] = {(Et.x + so * Ot.x) * f, (Et.y + so * Ot.y) * f};
-        buf[pad16(S + t)] = {(Ep.x + so * Op.x) * f, (Ep.y + so * Op.y) * f};
+        buf[t] = {(Et.x + so * Ot.x) * f, (Et.y + so * Ot.y) * f};
+        buf[S + t] = {(Ep.x + so * Op.x) * f, (Ep.y + so * Op.y) * f};
     }
     __syncthreads();
     fft_lds<real, kNfftNT>(buf, S, A.ffts, A.ffts + A.fft_nt, A.tw, wR, false);
@@ -1896,14 +1939,15 @@ __global__ __launch_bounds__(kNfftNT, 1) void k_nfft_cols(NfftArgs<real> A) {
             sincos(-M_PI * (double)k / (double)nt, &sp, &cp);
             const double sc = A.h * A.h / ((double)nt * A.psihat[k + L] * A.psihat[m + L]);
             const CD ph = {cp * sc, sp * sc};
-            dk[q][0] = cmul_d(buf[pad16(src)], ph);
-            dk[q][1] = cmul_d(buf[pad16(S + src)], ph);
+            dk[q][0] = cmul_d(buf[src], ph);
+            dk[q][1] = cmul_d(buf[S + src], ph);
         }
     }
     __syncthreads();
+    buf.ps = ld_const(&A.ffts[A.fft_ng].lds_shift);  // layout of the second DFT
     for (int i = threadIdx.x; i < ng; i += kNfftNT) {
-        buf[pad16(i)] = {0, 0};
-        buf[pad16(S + i)] = {0, 0};
+        buf[i] = {0, 0};
+        buf[S + i] = {0, 0};
     }
     __syncthreads();
 #pragma unroll
@@ -1911,16 +1955,16 @@ __global__ __launch_bounds__(kNfftNT, 1) void k_nfft_cols(NfftArgs<real> A) {
         const int k = threadIdx.x + q * kNfftNT - L;
         if (k <= L) {
             const int dst = k >= 0 ? k : ng + k;
-            buf[pad16(dst)] = dk[q][0];
-            buf[pad16(S + dst)] = dk[q][1];
+            buf[dst] = dk[q][0];
+            buf[S + dst] = dk[q][1];
         }
     }
     __syncthreads();
     fft_lds<real, kNfftNT>(buf, S, A.ffts, A.ffts + A.fft_ng, A.tw, wR, true);
     const int nm = 2 * L + 1;
     for (int j = threadIdx.x; j < ng; j += kNfftNT) {
-        A.g1[(size_t)j * nm + b] = buf[pad16(j)];
-        A.g1[((size_t)ng + j) * nm + b] = buf[pad16(S + j)];
+        A.g1[(size_t)j * nm + b] = buf[j];
+        A.g1[((size_t)ng + j) * nm + b] = buf[S + j];
     }
 }
 
@@ -1929,7 +1973,8 @@ template <typename real>
 __global__ __launch_bounds__(kNfftNT, 1) void k_nfft_rows(NfftArgs<real> A) {
     extern __shared__ unsigned char smem_raw[];
     CD *wR = reinterpret_cast<CD *>(smem_raw);
-    C2<real> *buf = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
+    C2<real> *lds = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
+    Seq<real> buf = {lds, ld_const(&A.ffts[A.fft_ng].lds_shift)};
     const int L = A.L, ng = A.ng, S = A.stride;
     const int j = blockIdx.x;
     const int nm = 2 * L + 1;
@@ -1941,14 +1986,14 @@ __global__ __launch_bounds__(kNfftNT, 1) void k_nfft_rows(NfftArgs<real> A) {
             vt = A.g1[(size_t)j * nm + m + L];
             vp = A.g1[((size_t)ng + j) * nm + m + L];
         }
-        buf[pad16(i)] = vt;
-        buf[pad16(S + i)] = vp;
+        buf[i] = vt;
+        buf[S + i] = vp;
     }
     __syncthreads();
     fft_lds<real, kNfftNT>(buf, S, A.ffts, A.ffts + A.fft_ng, A.tw, wR, true);
     for (int i = threadIdx.x; i < ng; i += kNfftNT) {
-        A.g[(size_t)j * ng + i] = buf[pad16(i)];
-        A.g[((size_t)ng + j) * ng + i] = buf[pad16(S + i)];
+        A.g[(size_t)j * ng + i] = buf[i];
+        A.g[((size_t)ng + j) * ng + i] = buf[S + i];
     }
 }
 
@@ -2088,21 +2133,22 @@ template <typename real>
 __global__ __launch_bounds__(kNfftNT, 1) void k_nfft_rows_fwd(NfftArgs<real> A) {
     extern __shared__ unsigned char smem_raw[];
     CD *wR = reinterpret_cast<CD *>(smem_raw);
-    C2<real> *buf = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
+    C2<real> *lds = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
+    Seq<real> buf = {lds, ld_const(&A.ffts[A.fft_ng].lds_shift)};
     const int L = A.L, ng = A.ng, S = A.stride;
     const int j = blockIdx.x;
     const int nm = 2 * L + 1;
     for (int i = threadIdx.x; i < ng; i += kNfftNT) {
-        buf[pad16(i)] = A.g[(size_t)j * ng + i];
-        buf[pad16(S + i)] = A.g[((size_t)ng + j) * ng + i];
+        buf[i] = A.g[(size_t)j * ng + i];
+        buf[S + i] = A.g[((size_t)ng + j) * ng + i];
     }
     __syncthreads();
     fft_lds<real, kNfftNT>(buf, S, A.ffts, A.ffts + A.fft_ng, A.tw, wR, false);
     for (int b = threadIdx.x; b < nm; b += kNfftNT) {
         const int m = b - L;
         const int src = m >= 0 ? m : ng + m;
-        A.g1[(size_t)j * nm + b] = buf[pad16(src)];
-        A.g1[((size_t)ng + j) * nm + b] = buf[pad16(S + src)];
+        A.g1[(size_t)j * nm + b] = buf[src];
+        A.g1[((size_t)ng + j) * nm + b] = buf[S + src];
     }
 }
 
@@ -2113,7 +2159,8 @@ template <typename real>
 __global__ __launch_bounds__(kNfftNT, 1) void k_nfft_cols_fwd(NfftArgs<real> A) {
     extern __shared__ unsigned char smem_raw[];
     CD *wR = reinterpret_cast<CD *>(smem_raw);
-    C2<real> *buf = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
+    C2<real> *lds = reinterpret_cast<C2<real> *>(smem_raw + kSmallTab * sizeof(CD));
+    Seq<real> buf = {lds, ld_const(&A.ffts[A.fft_ng].lds_shift)};
     const int L = A.L, nt = A.nt, ng = A.ng, S = A.stride;
     const int b = blockIdx.x;
     const int m = b - L;
@@ -2122,8 +2169,8 @@ __global__ __launch_bounds__(kNfftNT, 1) void k_nfft_cols_fwd(NfftArgs<real> A) 
     const real ext = (am & 1) ? (real)1 : (real)-1;
     const int nm = 2 * L + 1;
     for (int j = threadIdx.x; j < ng; j += kNfftNT) {
-        buf[pad16(j)] = A.g1[(size_t)j * nm + b];
-        buf[pad16(S + j)] = A.g1[((size_t)ng + j) * nm + b];
+        buf[j] = A.g1[(size_t)j * nm + b];
+        buf[S + j] = A.g1[((size_t)ng + j) * nm + b];
     }
     __syncthreads();
     fft_lds<real, kNfftNT>(buf, S, A.ffts, A.ffts + A.fft_ng, A.tw, wR, false);
@@ -2137,14 +2184,15 @@ __global__ __launch_bounds__(kNfftNT, 1) void k_nfft_cols_fwd(NfftArgs<real> A) 
             sincos(M_PI * (double)k / (double)nt, &sp, &cp);  // conjugate of the adjoint's phase
             const double sc = A.h * A.h / ((double)nt * A.psihat[k + L] * A.psihat[m + L]);
             const CD ph = {cp * sc, sp * sc};
-            dk[q][0] = cmul_d(buf[pad16(src)], ph);
-            dk[q][1] = cmul_d(buf[pad16(S + src)], ph);
+            dk[q][0] = cmul_d(buf[src], ph);
+            dk[q][1] = cmul_d(buf[S + src], ph);
         }
     }
     __syncthreads();
+    buf.ps = ld_const(&A.ffts[A.fft_nt].lds_shift);  // layout of the second DFT
     for (int i = threadIdx.x; i < nt; i += kNfftNT) {
-        buf[pad16(i)] = {0, 0};
-        buf[pad16(S + i)] = {0, 0};
+        buf[i] = {0, 0};
+        buf[S + i] = {0, 0};
     }
     __syncthreads();
 #pragma unroll
@@ -2152,8 +2200,8 @@ __global__ __launch_bounds__(kNfftNT, 1) void k_nfft_cols_fwd(NfftArgs<real> A) 
         const int k = threadIdx.x + q * kNfftNT - L;
         if (k <= L) {
             const int dst = k >= 0 ? k : nt + k;
-            buf[pad16(dst)] = dk[q][0];
-            buf[pad16(S + dst)] = dk[q][1];
+            buf[dst] = dk[q][0];
+            buf[S + dst] = dk[q][1];
         }
     }
     __syncthreads();
@@ -2163,8 +2211,8 @@ __global__ __launch_bounds__(kNfftNT, 1) void k_nfft_cols_fwd(NfftArgs<real> A) 
     for (int t = threadIdx.x; t < NRv; t += kNfftNT) {
         const int p = t < nt / 4 ? t : nt / 2 - 1 - t;
         const real f = (real)1 / (real)A.vs[p];
-        const C2<real> a0 = buf[pad16(t)], a1 = buf[pad16(nt - 1 - t)];
-        const C2<real> b0 = buf[pad16(S + t)], b1 = buf[pad16(S + nt - 1 - t)];
+        const C2<real> a0 = buf[t], a1 = buf[nt - 1 - t];
+        const C2<real> b0 = buf[S + t], b1 = buf[S + nt - 1 - t];
         C2<real> *o = reinterpret_cast<C2<real> *>(A.RB + ((size_t)am * NRv + t) * 8);
         const C2<real> vt = {(a0.x + ext * a1.x) * f, (a0.y + ext * a1.y) * f};
         const C2<real> vp = {(b0.x + ext * b1.x) * f, (b0.y + ext * b1.y) * f};
