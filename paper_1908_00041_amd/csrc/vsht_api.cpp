@@ -609,7 +609,7 @@ vsht_status build_plan(Plan &P, int L, int64_t n, const double *xyz, const doubl
             // ring buffer [(L+1)][NR][4] (forward) and pair buffer [(L+1)][NP][8] (adjoint)
             const size_t per_m = std::max((size_t)P.n_rings * 4, (size_t)P.n_pairs * 8);
             const size_t pb = (size_t)(L + 1) * per_m * 2 * rsz;
-            const size_t fg = (size_t)P.tri_size * 4 * 2 * rsz;
+            const size_t fg = (size_t)(P.tri_size + kFgPadRows) * 4 * 2 * rsz;
             if ((e = hipMalloc(&P.d_pb, pb)) != hipSuccess) goto hip_error;
             if ((e = hipMalloc(&P.d_fg, fg)) != hipSuccess) goto hip_error;
             P.workspace_bytes = pb + fg;
@@ -622,7 +622,7 @@ vsht_status build_plan(Plan &P, int L, int64_t n, const double *xyz, const doubl
             std::vector<double> wv(w, w + n);
             if ((e = upload(&P.d_weights, wv, &P.table_bytes)) != hipSuccess) goto hip_error;
         }
-        const size_t fg = (size_t)P.tri_size * 4 * 2 * rsz;
+        const size_t fg = (size_t)(P.tri_size + kFgPadRows) * 4 * 2 * rsz;
         if ((e = hipMalloc(&P.d_fg, fg)) != hipSuccess) goto hip_error;
         P.workspace_bytes = fg;
         if (!(flags & VSHT_OPT_SCATTERED_DIRECT) && L <= kMaxNfftL) {

@@ -123,7 +123,10 @@ struct NfftPlan {
 //       even l'+m, slot 1 = sum over odd l'+m, same 4 columns
 //  RB and PB share one allocation.
 //  FG   triangle buffer [tri(L)][4] complex, tri index (m, l') for
-//       0 <= m <= L, m <= l' <= L+1: forward F, adjoint prep g.
+//       0 <= m <= L, m <= l' <= L+1: forward F, adjoint prep g; followed by
+//       kFgPadRows rows that the synthesis may load (never use) past the end.
+constexpr int kFgPadRows = 8;
+
 struct Plan {
     int L = 0;
     int precision = VSHT_FP64;

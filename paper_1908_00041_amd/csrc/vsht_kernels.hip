@@ -1262,6 +1262,169 @@ __device__ __forceinline__ void adj_tile_f64q(const LegArgs<double> &A, int m, i
     }
 }
 
+// Synthesis on the vector unit.  A workgroup takes one order m; each lane
+// carries kAdjPPL ring pairs through the degrees l' = m .. L+1, and each degree
+// costs, per pair, the recurrence step and eight FMAs (the four complex columns
+// of g, into the even or the odd sum).  a'_{l'} and g[l'] are the same for the
+// whole workgroup: kAdjChunk degrees at a time are staged in LDS with
+// coalesced loads issued one chunk ahead, and every lane reads them back
+// (broadcast) as vector operands.  On gfx950 the binary64 vector FMA rate
+// equals the binary64 matrix-core rate and the two share one pipe, so this
+// form gives up nothing to the matrix cores and needs neither the LDS staging
+// of the Legendre values nor products on zero parity blocks.
+constexpr int kAdjPPL = 2;     // ring pairs per lane: every staged value feeds kAdjPPL FMAs
+constexpr int kAdjChunk = 16;  // degrees per LDS buffer (two buffers)
+template <typename real>
+struct alignas(16) AdjRow {
+    real g[8];  // g[l'] (theta, phi) x (+m, -m), complex
+    double a;   // a'_{l'}
+};
+
+// acc += bcast_k(g) * r, where bcast_k(g) is g of lane k of the lane's row of 16
+// (binary64 DPP row broadcast).  The assembler form is the only one that puts
+// the broadcast on the FMA itself; g must come straight from memory (no vector
+// ALU write immediately before a DPP read of it).
+template <int K>
+__device__ __forceinline__ void fmac_row_bcast(double &acc, double g, double r) {
+    asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        : "+v"(acc)
+        : "v"(g), "v"(r), "n"(K));
+}
+template <int K0, int C = 0>
+__device__ __forceinline__ void fmac_row_bcast8(double (&S)[8], double g, double r) {
+    fmac_row_bcast<K0 + C>(S[C], g, r);
+    if constexpr (C + 1 < 8) fmac_row_bcast8<K0, C + 1>(S, g, r);
+}
+
+// Degree l' of one row for the kAdjPPL pairs of a lane, into the sums S.
+template <typename real>
+__device__ __forceinline__ void adj_row_step(const AdjRow<real> &R, const double (&z)[kAdjPPL],
+                                             double (&q1)[kAdjPPL], double (&q2)[kAdjPPL],
+                                             real (&S)[kAdjPPL][8]) {
+#pragma unroll
+    for (int u = 0; u < kAdjPPL; ++u) {
+        const double v = fma(R.a * z[u], q1[u], -q2[u]);
+        const real r = (real)v;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) S[u][c] = fma(r, R.g[c], S[u][c]);
+        q2[u] = q1[u];
+        q1[u] = v;
+    }
+}
+
+// One workgroup (any number of waves) of order m; wave w of group `grp` takes
+// ring pairs ((grp * waves + w) * kAdjPPL + u) * 64 + lane.  Every wave takes
+// part in the staging and its barriers, also one without pairs.
+template <typename real>
+__device__ __forceinline__ void adj_valu_body(const LegArgs<real> &A, int m, int grp, AdjRow<real> *buf) {
+    const int nt = blockDim.x, nw = nt >> 6;
+    const int wave = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int L = A.L, NP = A.NP, NPT = A.NPT, Lp1 = L + 1;
+    const int64_t t0 = tri_offset(L, m);
+    const real *g = A.FG + (t0 - m) * 8;  // row l' at g + 8 l'
+    const double *ap = A.aprime + t0 - m;
+    double z[kAdjPPL], q1[kAdjPPL], q2[kAdjPPL];
+    real E[kAdjPPL][8], O[kAdjPPL][8];
+#pragma unroll
+    for (int u = 0; u < kAdjPPL; ++u) {
+        const int p = ((grp * nw + wave) * kAdjPPL + u) * kTileP + lane;
+        const bool valid = p < NPT;
+        z[u] = valid ? A.pz[p] : 0.0;
+        q1[u] = 0.0;
+        q2[u] = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+        // re-define the loaded values here, so that the degree loop below does not
+        // read registers filled by loads (the wait inserted for those would also
+        // wait for the staging loads of the next chunk)
+        asm volatile("" : "+v"(z[u]), "+v"(q2[u]));
+#pragma unroll
+        for (int c = 0; c < 8; ++c) E[u][c] = O[u][c] = (real)0;
+    }
+    const int nl = Lp1 - m + 1;
+    const int nchunk = (nl + kAdjChunk - 1) / kAdjChunk;
+    // staging: item i < 8 kAdjChunk is g value (i & 7) of row i >> 3; thread t < kAdjChunk
+    // also takes a' of row t (workgroups of 64 threads take two g items each)
+    constexpr int kG = (8 * kAdjChunk + 63) / 64;
+    real sg[kG];
+    double sa = 0.0;
+    auto stage_load = [&](int k) {
+        const int lp0 = m + k * kAdjChunk;
+#pragma unroll
+        for (int r = 0; r < kG; ++r) {
+            const int i = threadIdx.x + r * nt;
+            const int lp = lp0 + (i >> 3);
+            sg[r] = (i < 8 * kAdjChunk && lp <= Lp1) ? g[(int64_t)lp * 8 + (i & 7)] : (real)0;
+        }
+        const int la = lp0 + (int)threadIdx.x;
+        sa = ((int)threadIdx.x < kAdjChunk && la <= Lp1) ? ap[la] : 0.0;
+    };
+    auto stage_store = [&](int k) {
+        AdjRow<real> *b = buf + (k & 1) * kAdjChunk;
+#pragma unroll
+        for (int r = 0; r < kG; ++r) {
+            const int i = threadIdx.x + r * nt;
+            if (i < 8 * kAdjChunk) b[i >> 3].g[i & 7] = sg[r];
+        }
+        if ((int)threadIdx.x < kAdjChunk) b[threadIdx.x].a = sa;
+    };
+    stage_load(0);
+    stage_store(0);
+    __syncthreads();
+    for (int k = 0; k < nchunk; ++k) {
+        if (k + 1 < nchunk) stage_load(k + 1);  // in flight while chunk k is used
+        const AdjRow<real> *rows = buf + (k & 1) * kAdjChunk;
+        const int nd = min(kAdjChunk, nl - k * kAdjChunk);
+        // the chunk starts an even number of degrees after m: row d has the parity of d
+        if constexpr (sizeof(real) == 8) {
+            // lanes 0-7 of every row of 16 hold g of degree d, lanes 8-15 that of d + 1;
+            // each FMA takes its value by row broadcast
+            const int sel = (lane >> 3) & 1, col = lane & 7;
+            for (int d = 0; d < nd; d += 2) {
+                const double G = rows[d + sel].g[col];
+                const double a0 = rows[d].a, a1 = rows[d + 1].a;
+#pragma unroll
+                for (int u = 0; u < kAdjPPL; ++u) {
+                    const double v = fma(a0 * z[u], q1[u], -q2[u]);
+                    fmac_row_bcast8<0>(E[u], G, v);
+                    q2[u] = q1[u];
+                    q1[u] = v;
+                }
+                if (d + 1 < nd) {
+#pragma unroll
+                    for (int u = 0; u < kAdjPPL; ++u) {
+                        const double v = fma(a1 * z[u], q1[u], -q2[u]);
+                        fmac_row_bcast8<8>(O[u], G, v);
+                        q2[u] = q1[u];
+                        q1[u] = v;
+                    }
+                }
+            }
+        } else {
+            for (int d = 0; d < nd; d += 2) {
+                const AdjRow<real> R0 = rows[d];
+                adj_row_step(R0, z, q1, q2, E);
+                if (d + 1 < nd) {
+                    const AdjRow<real> R1 = rows[d + 1];
+                    adj_row_step(R1, z, q1, q2, O);
+                }
+            }
+        }
+        if (k + 1 < nchunk) stage_store(k + 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < kAdjPPL; ++u) {
+        const int p = ((grp * nw + wave) * kAdjPPL + u) * kTileP + lane;
+        if (p < NPT) {
+            real *o = A.PB + ((size_t)m * NP + p) * 16;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                o[c] = E[u][c];
+                o[8 + c] = O[u][c];
+            }
+        }
+    }
+}
+
 // One wave: pairs [64 tile, 64 tile + 64) of order m, computed in `real`, with
 // FG read and PB written in `store` (binary32 storage with binary64 arithmetic
 // serves the polar tile of the binary32 path).
@@ -1320,17 +1483,9 @@ __device__ __forceinline__ void adj_tile_mfma(const LegArgs<store> &A, int m, in
 constexpr int kAdjLdsPerWave = kRowsB * kTileP * 8;
 
 template <typename real>
-__global__ __launch_bounds__(256) void k_leg_adj_mfma(LegArgs<real> A) {
+__global__ __launch_bounds__(256, 4) void k_leg_adj_mfma(LegArgs<real> A) {
     extern __shared__ unsigned char smem_raw[];
-    const int nw = blockDim.x >> 6;
-    const int wave = uniform_int(threadIdx.x >> 6);
-    const int tile = blockIdx.x * nw + wave;
-    if (tile * kTileP >= A.NPT) return;  // whole wave idle (no barriers below)
-    real *qt = reinterpret_cast<real *>(smem_raw) + wave * kRowsB * kTileP;
-    if constexpr (sizeof(real) == 8)
-        adj_tile_f64q(A, blockIdx.y, tile, threadIdx.x & 63, qt);
-    else
-        adj_tile_mfma<real, real>(A, blockIdx.y, tile, threadIdx.x & 63, qt);
+    adj_valu_body<real>(A, blockIdx.y, blockIdx.x, reinterpret_cast<AdjRow<real> *>(smem_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -2299,7 +2454,7 @@ __global__ __launch_bounds__(1024) void kb_leg_fwd(const LegFwdArgs<real> *__res
 
 // work item (field, tile group, m)
 template <typename real, bool kBf16>
-__global__ __launch_bounds__(256) void kb_leg_adj(const LegArgs<real> *__restrict__ args,
+__global__ __launch_bounds__(256, 4) void kb_leg_adj(const LegArgs<real> *__restrict__ args,
                                                   const WorkItem *__restrict__ work,
                                                   unsigned long long *) {
     extern __shared__ unsigned char smem_raw[];
@@ -2307,21 +2462,17 @@ __global__ __launch_bounds__(256) void kb_leg_adj(const LegArgs<real> *__restric
     const LegArgs<real> A = ld_const(args + w.f);
     const int nw = blockDim.x >> 6;
     const int wave = uniform_int(threadIdx.x >> 6);
-    const int tile = w.x * nw + wave;
-    if (tile * kTileP >= A.NPT) return;
-    const int lane = threadIdx.x & 63;
     if constexpr (kBf16) {
+        const int tile = w.x * nw + wave;
+        if (tile * kTileP >= A.NPT) return;
+        const int lane = threadIdx.x & 63;
         unsigned char *lds = smem_raw + wave * kAdjLdsPerWave;
         if (tile == 0)
             adj_tile_mfma<float, float>(A, w.y, tile, lane, reinterpret_cast<float *>(lds));
         else
             adj_tile_bf16x3(A, w.y, tile, lane, reinterpret_cast<u32x4_t *>(lds));
     } else {
-        real *qt = reinterpret_cast<real *>(smem_raw) + wave * kRowsB * kTileP;
-        if constexpr (sizeof(real) == 8)
-            adj_tile_f64q(A, w.y, tile, lane, qt);
-        else
-            adj_tile_mfma<real, real>(A, w.y, tile, lane, qt);
+        adj_valu_body<real>(A, w.y, w.x, reinterpret_cast<AdjRow<real> *>(smem_raw));
     }
 }
 
@@ -2362,6 +2513,11 @@ static RingArgs<real> make_ring_args(const Plan &p, const void *Tin, void *Tout,
 
 static int pairs_in_tiles(const Plan &p) { return (int)(p.n_pairs - (p.eq_ring >= 0 ? 1 : 0)); }
 static int tiles_of(const Plan &p) { return (pairs_in_tiles(p) + kTileP - 1) / kTileP; }
+// Waves of the synthesis: 64 pairs each for BF16x3, 64 kAdjPPL on the vector unit.
+static int adj_waves(int pairs, bool bf16) {
+    const int per = kTileP * (bf16 ? 1 : kAdjPPL);
+    return (pairs + per - 1) / per;
+}
 
 template <typename real>
 static LegFwdArgs<real> make_leg_fwd_args(const Plan &p, int atomic) {
@@ -2415,7 +2571,8 @@ static CoefArgs<real> make_coef_args(const Plan &p, const void *ain, const void 
 
 static size_t leg_fwd_lds(int nw, size_t rsz) { return (size_t)nw * (kRowsB * kTileP + 2 * 128) * rsz; }
 static size_t leg_adj_lds(int nw, size_t rsz, bool bf16) {
-    return (size_t)nw * (bf16 ? (size_t)kAdjLdsPerWave : (size_t)kRowsB * kTileP * rsz);
+    if (bf16) return (size_t)nw * kAdjLdsPerWave;
+    return 2 * kAdjChunk * (rsz == 8 ? sizeof(AdjRow<double>) : sizeof(AdjRow<float>));
 }
 
 template <typename real>
@@ -2575,7 +2732,7 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
         G.NPT = nf.npv;
         {
             StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
-            const int ntile = (nf.npv + kTileP - 1) / kTileP;
+            const int ntile = adj_waves(nf.npv, bf16);
             const int nw = ntile < 4 ? ntile : 4;
             const dim3 grid((ntile + nw - 1) / nw, p.L + 1);
             if constexpr (sizeof(real) == 4) {
@@ -2618,7 +2775,7 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
     const LegArgs<real> G = make_leg_adj_args<real>(p);
     {
         StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
-        const int ntile = tiles_of(p);
+        const int ntile = adj_waves(pairs_in_tiles(p), bf16);
         if (ntile > 0) {
             const int nw = ntile < 4 ? ntile : 4;
             const dim3 grid((ntile + nw - 1) / nw, p.L + 1);
@@ -2786,7 +2943,7 @@ hipError_t batch_configure(BatchState *b, const BatchConfig &cfg) {
     size_t lds_adj = leg_adj_lds(cfg.adj_nw, rsz, bf16);
     for (int i = 0; i < F; ++i) {
         const Plan &p = *b->f[i];
-        const int ntile = tiles_of(p);
+        const int ntile = adj_waves(pairs_in_tiles(p), bf16);
         for (int tg = 0; tg * cfg.adj_nw < ntile; ++tg) {
             const int nt = std::min(cfg.adj_nw, ntile - tg * cfg.adj_nw);
             for (int m = 0; m <= p.L; ++m) items.push_back({{i, tg, m, 0}, (double)(p.L + 2 - m) * nt});
