@@ -1273,7 +1273,7 @@ __device__ __forceinline__ void adj_tile_f64q(const LegArgs<double> &A, int m, i
 // form gives up nothing to the matrix cores and needs neither the LDS staging
 // of the Legendre values nor products on zero parity blocks.
 constexpr int kAdjPPL = 2;     // ring pairs per lane: every staged value feeds kAdjPPL FMAs
-constexpr int kAdjChunk = 16;  // degrees per LDS buffer (two buffers)
+constexpr int kAdjChunk = 32;  // degrees per LDS buffer (two buffers)
 template <typename real>
 struct alignas(16) AdjRow {
     real g[8];  // g[l'] (theta, phi) x (+m, -m), complex
@@ -1378,9 +1378,14 @@ __device__ __forceinline__ void adj_valu_body(const LegArgs<real> &A, int m, int
             // lanes 0-7 of every row of 16 hold g of degree d, lanes 8-15 that of d + 1;
             // each FMA takes its value by row broadcast
             const int sel = (lane >> 3) & 1, col = lane & 7;
+            double Gn = rows[sel].g[col], a0n = rows[0].a, a1n = rows[1].a;
             for (int d = 0; d < nd; d += 2) {
-                const double G = rows[d + sel].g[col];
-                const double a0 = rows[d].a, a1 = rows[d + 1].a;
+                const double G = Gn, a0 = a0n, a1 = a1n;
+                // the next step's operands, read while this step computes
+                const int dn = d + 2 < kAdjChunk ? d + 2 : d;
+                Gn = rows[dn + sel].g[col];
+                a0n = rows[dn].a;
+                a1n = rows[dn + 1].a;
 #pragma unroll
                 for (int u = 0; u < kAdjPPL; ++u) {
                     const double v = fma(a0 * z[u], q1[u], -q2[u]);
@@ -1485,7 +1490,12 @@ constexpr int kAdjLdsPerWave = kRowsB * kTileP * 8;
 template <typename real>
 __global__ __launch_bounds__(256, 4) void k_leg_adj_mfma(LegArgs<real> A) {
     extern __shared__ unsigned char smem_raw[];
-    adj_valu_body<real>(A, blockIdx.y, blockIdx.x, reinterpret_cast<AdjRow<real> *>(smem_raw));
+    // workgroups reach the compute units in rounds of about 256; reversing the
+    // order in every other round gives each unit long and short orders alike
+    const int y = blockIdx.y, base = y & ~255, r = y & 255;
+    const int cnt = min(256, A.L + 1 - base);
+    const int m = (y >> 8) & 1 ? base + cnt - 1 - r : y;
+    adj_valu_body<real>(A, m, blockIdx.x, reinterpret_cast<AdjRow<real> *>(smem_raw));
 }
 
 // ---------------------------------------------------------------------------
