@@ -1805,47 +1805,76 @@ struct CoefArgs {
 // contiguous runs.
 constexpr int kTM = 16, kTL = 32;
 
+// Both run with 256 threads; every thread issues all of its loads of a phase
+// before the first use, so a phase costs one memory latency.
+constexpr int kCoefNT = 256;
+
 template <typename real>
 __device__ __forceinline__ void recombine_body(const CoefArgs<real> &A, int bx, int by) {
-    __shared__ real fs[kTM][kTL + 2][8 + 1];  // F rows l0-1 .. l0+kTL, 8 reals (+1 pad)
+    // F rows l0-1 .. l0+kTL of each order: (th,+m) (ph,+m) (th,-m) (ph,-m); an odd
+    // stride between orders keeps the 16-byte reads of consecutive orders conflict free
+    constexpr int kRowR = (kTL + 2) * 4 + 1;
+    __shared__ C2<real> fs[kTM * kRowR];
     const int L = A.L;
     const int l0 = 1 + bx * kTL, m0 = by * kTM;
     if (m0 > L || m0 > l0 + kTL - 1) return;
-    for (int idx = threadIdx.x; idx < kTM * (kTL + 2) * 8; idx += blockDim.x) {
-        const int c = idx & 7, i = (idx >> 3) % (kTL + 2), mi = (idx >> 3) / (kTL + 2);
+    constexpr int kItems = kTM * (kTL + 2) * 4, kPer = (kItems + kCoefNT - 1) / kCoefNT;
+    C2<real> v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int idx = threadIdx.x + q * kCoefNT;
+        const int c = idx & 3, i = (idx >> 2) % (kTL + 2), mi = (idx >> 2) / (kTL + 2);
         const int m = m0 + mi, lp = l0 - 1 + i;
-        real v = 0;
-        if (m <= L && lp >= m && lp <= L + 1)
-            v = reinterpret_cast<const real *>(A.FG)[(tri_offset(L, m) + lp - m) * 8 + c];
-        fs[mi][i][c] = v;
+        v[q] = {0, 0};
+        if (idx < kItems && m <= L && lp >= m && lp <= L + 1) v[q] = A.FG[(tri_offset(L, m) + lp - m) * 4 + c];
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int idx = threadIdx.x + q * kCoefNT;
+        if (idx < kItems) fs[(idx / (4 * (kTL + 2))) * kRowR + idx % (4 * (kTL + 2))] = v[q];
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < kTM * kTL; idx += blockDim.x) {
+    constexpr int kOut = (kTM * kTL) / kCoefNT;
+    static_assert(kOut * kCoefNT == kTM * kTL, "whole outputs per thread");
+    double cpv[kOut], cmv[kOut], inv[kOut];
+#pragma unroll
+    for (int q = 0; q < kOut; ++q) {
+        const int idx = threadIdx.x + q * kCoefNT;
+        const int mi = idx % kTM, li = idx / kTM;
+        const int l = l0 + li, m = m0 + mi;
+        cpv[q] = cmv[q] = inv[q] = 0.0;
+        if (l <= L && m <= l) {
+            const double *et = A.etab + tri_offset(L, m) - m;  // indexed by l'
+            inv[q] = A.rsq[l];
+            cpv[q] = et[l + 1];
+            cmv[q] = l - 1 >= m ? et[l] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kOut; ++q) {
+        const int idx = threadIdx.x + q * kCoefNT;
         const int mi = idx % kTM, li = idx / kTM;
         const int l = l0 + li, m = m0 + mi;
         if (l > L || m > l) continue;
-        const double *et = A.etab + tri_offset(L, m) - m;  // indexed by l'
-        const double inv = A.rsq[l];
-        const real cp = (real)(l * et[l + 1] * inv);
-        const real cm = (real)((l + 1) * (l - 1 >= m ? et[l] : 0.0) * inv);
+        const real cp = (real)(l * cpv[q] * inv[q]);
+        const real cm = (real)((l + 1) * cmv[q] * inv[q]);
         const int64_t base = (int64_t)l * l + l - 1;
 #pragma unroll
         for (int sgn = 0; sgn < 2; ++sgn) {
             if (sgn == 1 && m == 0) break;
             const int mu = sgn == 0 ? m : -m;
-            const int off = 4 * sgn;  // reals of (theta,+-m) (phi,+-m)
             const real parity = (sgn == 1 && (m & 1)) ? (real)-1 : (real)1;
-            const real fmu = (real)(mu * inv);
-            const real *fm = fs[mi][li], *f0 = fs[mi][li + 1], *fp = fs[mi][li + 2];
-            const real th1x = fp[off], th1y = fp[off + 1], ph1x = fp[off + 2], ph1y = fp[off + 3];
-            const real th0x = f0[off], th0y = f0[off + 1], ph0x = f0[off + 2], ph0y = f0[off + 3];
-            const real thmx = fm[off], thmy = fm[off + 1], phmx = fm[off + 2], phmy = fm[off + 3];
+            const real fmu = (real)(mu * inv[q]);
+            const C2<real> *fm = fs + mi * kRowR + 4 * li, *f0 = fm + 4, *fp = fm + 8;
+            const C2<real> th1 = fp[2 * sgn], ph1 = fp[2 * sgn + 1];
+            const C2<real> th0 = f0[2 * sgn], ph0 = f0[2 * sgn + 1];
+            const C2<real> thm = fm[2 * sgn], phm = fm[2 * sgn + 1];
             C2<real> av, bv;
             // -i mu F^ph = (mu F^ph.y, -mu F^ph.x);  +i mu F^th = (-mu F^th.y, mu F^th.x)
-            av.x = parity * (cp * th1x - cm * thmx + fmu * ph0y);
-            av.y = parity * (cp * th1y - cm * thmy - fmu * ph0x);
-            bv.x = parity * (cp * ph1x - cm * phmx - fmu * th0y);
-            bv.y = parity * (cp * ph1y - cm * phmy + fmu * th0x);
+            av.x = parity * (cp * th1.x - cm * thm.x + fmu * ph0.y);
+            av.y = parity * (cp * th1.y - cm * thm.y - fmu * ph0.x);
+            bv.x = parity * (cp * ph1.x - cm * phm.x - fmu * th0.y);
+            bv.y = parity * (cp * ph1.y - cm * phm.y + fmu * th0.x);
             A.aout[base + mu] = av;
             A.bout[base + mu] = bv;
         }
@@ -1865,35 +1894,64 @@ __global__ __launch_bounds__(256) void k_recombine(CoefArgs<real> A) {
 
 template <typename real>
 __device__ __forceinline__ void prep_body(const CoefArgs<real> &A, int bx, int by) {
-    // coefficients of degrees l0-1 .. l0+kTL for the tile's orders: [l][m][sign][a,b]
-    __shared__ C2<real> cs[kTL + 2][kTM][2][2];
+    // coefficients of degrees l0-1 .. l0+kTL for the tile's orders, [l][sign][a,b][m]; an
+    // odd stride between degrees keeps the 16-byte reads of consecutive degrees conflict free
+    constexpr int kRowP = 4 * kTM + 1;
+    __shared__ C2<real> cs[(kTL + 2) * kRowP];
     const int L = A.L;
     const int l0 = bx * kTL, m0 = by * kTM;  // l' in [l0, l0+kTL)
     if (m0 > L || m0 > l0 + kTL - 1) return;
-    for (int idx = threadIdx.x; idx < (kTL + 2) * 2 * 2 * kTM; idx += blockDim.x) {
+    constexpr int kItems = (kTL + 2) * 2 * 2 * kTM, kPer = (kItems + kCoefNT - 1) / kCoefNT;
+    C2<real> v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int idx = threadIdx.x + q * kCoefNT;
         const int mi = idx % kTM, r = idx / kTM;
         const int ab = r & 1, sg = (r >> 1) & 1, i = r >> 2;
         const int l = l0 - 1 + i, m = m0 + mi;
-        C2<real> v = {0, 0};
-        if (l >= 1 && l <= L && m <= l) {
+        v[q] = {0, 0};
+        if (idx < kItems && l >= 1 && l <= L && m <= l) {
             const int mu = sg ? -m : m;
-            const C2<real> c = (ab ? A.bin : A.ain)[(int64_t)l * l + l + mu - 1];
-            const real rs = (real)A.rsq[l];
-            v = {c.x * rs, c.y * rs};
+            v[q] = (ab ? A.bin : A.ain)[(int64_t)l * l + l + mu - 1];
         }
-        cs[i][mi][sg][ab] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int idx = threadIdx.x + q * kCoefNT;
+        if (idx < kItems) {
+            const int mi = idx % kTM, r = idx / kTM;
+            const int l = l0 - 1 + (r >> 2);
+            const real rs = (l >= 1 && l <= L) ? (real)A.rsq[l] : (real)0;
+            cs[(r >> 2) * kRowP + (r & 3) * kTM + mi] = {v[q].x * rs, v[q].y * rs};
+        }
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < kTM * kTL; idx += blockDim.x) {
+    constexpr int kOut = (kTM * kTL) / kCoefNT;
+    static_assert(kOut * kCoefNT == kTM * kTL, "whole outputs per thread");
+    double cscv[kOut], e0v[kOut], e1v[kOut];
+#pragma unroll
+    for (int q = 0; q < kOut; ++q) {
+        const int idx = threadIdx.x + q * kCoefNT;
+        const int li = idx % kTL, mi = idx / kTL;
+        const int lp = l0 + li, m = m0 + mi;
+        cscv[q] = e0v[q] = e1v[q] = 0.0;
+        if (m <= L && lp >= m && lp <= L + 1) {
+            const int64_t ti = tri_offset(L, m) + lp - m;
+            cscv[q] = A.cscale[ti];  // Lambda = c Q: fold c_{l'} in
+            e0v[q] = A.etab[ti];
+            e1v[q] = lp + 1 <= L + 1 ? A.etab[ti + 1] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kOut; ++q) {
+        const int idx = threadIdx.x + q * kCoefNT;
         const int li = idx % kTL, mi = idx / kTL;
         const int lp = l0 + li, m = m0 + mi;
         if (m > L || lp < m || lp > L + 1) continue;
         const int64_t ti = tri_offset(L, m) + lp - m;
-        const double csc = A.cscale[ti];  // Lambda = c Q: fold c_{l'} in
-        const double elp = A.etab[ti];
-        const double elp1 = lp + 1 <= L + 1 ? A.etab[ti + 1] : 0.0;
-        const real c1 = (real)(csc * (lp - 1) * elp);
-        const real c2 = (real)(csc * (lp + 2) * elp1);
+        const double csc = cscv[q];
+        const real c1 = (real)(csc * (lp - 1) * e0v[q]);
+        const real c2 = (real)(csc * (lp + 2) * e1v[q]);
         const real csr = (real)csc;
         C2<real> *o = A.FGout + ti * 4;
 #pragma unroll
@@ -1901,9 +1959,10 @@ __device__ __forceinline__ void prep_body(const CoefArgs<real> &A, int bx, int b
             const int mu = sgn == 0 ? m : -m;
             const real parity = (sgn == 1 && (m & 1)) ? (real)-1 : (real)1;
             const real fmu = (real)mu;
-            const C2<real> am1 = cs[li][mi][sgn][0], bm1 = cs[li][mi][sgn][1];
-            const C2<real> a0 = cs[li + 1][mi][sgn][0], b0 = cs[li + 1][mi][sgn][1];
-            const C2<real> ap1 = cs[li + 2][mi][sgn][0], bp1 = cs[li + 2][mi][sgn][1];
+            const C2<real> *cm1 = cs + li * kRowP + 2 * sgn * kTM + mi, *c0 = cm1 + kRowP, *cp1 = c0 + kRowP;
+            const C2<real> am1 = cm1[0], bm1 = cm1[kTM];
+            const C2<real> a0 = c0[0], b0 = c0[kTM];
+            const C2<real> ap1 = cp1[0], bp1 = cp1[kTM];
             C2<real> gth, gph;
             // -i mu b = (mu b.y, -mu b.x); +i mu a = (-mu a.y, mu a.x)
             gth.x = parity * (c1 * am1.x - c2 * ap1.x + csr * fmu * b0.y);
