@@ -974,13 +974,6 @@ struct SwzQ4Fwd {
         return row * kTileP + (pair ^ ((row & 7) << 2) ^ ((row & 8) << 1));
     }
 };
-// Synthesis tile: one read group (32 lanes) is rows s, s+2 x 16 consecutive
-// pairs; XOR-ing the pair with 16 ((row >> 1) & 1) separates the two rows.
-struct SwzQ4Adj {
-    static __device__ __forceinline__ int at(int row, int pair) {
-        return row * kTileP + (pair ^ (((row >> 1) & 1) << 4));
-    }
-};
 
 // Analysis, binary64: workgroup = order m, waves = tiles of 64 ring pairs.
 // Instruction (row group r, pair step g): block b = (parity pi = b>>1, column
@@ -1178,89 +1171,6 @@ struct LegArgs {
     int NP;
     int NPT;              // pairs handled by the tiles (the equator, if any, is pair NPT)
 };
-
-// Synthesis, binary64: one wave = 64 ring pairs of order m.  Instruction
-// (pair set q, parity pi, column half h, degree step ks): block b = pairs
-// 16q + 4b + i, K = degrees lp0 + pi + 2(4ks + k), columns 4h + j of g.
-__device__ __forceinline__ void adj_tile_f64q(const LegArgs<double> &A, int m, int tile, int lane,
-                                              double *qt) {
-    const int L = A.L, NP = A.NP, NPT = A.NPT;
-    const int64_t t0 = tri_offset(L, m);
-    const double *g = A.FG + (t0 - m) * 8;  // indexed by l'
-    const double *ap = A.aprime + t0 - m;
-    const int p = tile * kTileP + lane;
-    const bool valid = p < NPT;
-    const double z = valid ? A.pz[p] : 0.0;
-    double q1 = 0.0, q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
-    const int b = (lane >> 2) & 3, i = lane & 3, j = lane & 3, k = lane >> 4;
-    double acc[4][2][2];  // [pair set][parity][column half]
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int pi = 0; pi < 2; ++pi) acc[q][pi][0] = acc[q][pi][1] = 0.0;
-    const int nl = L + 2 - m;
-    const int nblk = (nl + kRowsB - 1) / kRowsB;
-    // B operands of block blk: g[lp0 + pi + 2(4ks + k)][4h + j], fetched one block ahead
-    double bn[2][2][2];
-    auto fetch_b = [&](int lp0, double (&bv)[2][2][2]) {
-#pragma unroll
-        for (int pi = 0; pi < 2; ++pi)
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                const int lp = lp0 + pi + 2 * (4 * ks + k);
-#pragma unroll
-                for (int hh = 0; hh < 2; ++hh)
-                    bv[pi][ks][hh] = lp <= L + 1 ? g[(int64_t)lp * 8 + 4 * hh + j] : 0.0;
-            }
-    };
-    fetch_b(m, bn);
-    for (int blk = 0; blk < nblk; ++blk) {
-        const int lp0 = m + blk * kRowsB;
-        double bv[2][2][2];
-#pragma unroll
-        for (int pi = 0; pi < 2; ++pi)
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                bv[pi][ks][0] = bn[pi][ks][0];
-                bv[pi][ks][1] = bn[pi][ks][1];
-            }
-        if (blk + 1 < nblk) fetch_b(lp0 + kRowsB, bn);
-        double ab[kRowsB];
-        load_aprime(ap, lp0, L + 1, ab);
-#pragma unroll
-        for (int s = 0; s < kRowsB; ++s) {
-            const double v = fma(ab[s] * z, q1, -q2);
-            qt[SwzQ4Adj::at(s, lane)] = v;
-            q2 = q1;
-            q1 = v;
-        }
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int pi = 0; pi < 2; ++pi)
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const double a = qt[SwzQ4Adj::at(pi + 8 * ks + 2 * k, 16 * q + 4 * b + i)];
-                    acc[q][pi][0] = mma44(a, bv[pi][ks][0], acc[q][pi][0]);
-                    acc[q][pi][1] = mma44(a, bv[pi][ks][1], acc[q][pi][1]);
-                }
-        __builtin_amdgcn_wave_barrier();
-    }
-    // D lane l: pair 16q + 4b + (l >> 4), column 4h + j of parity block pi
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int pp = tile * kTileP + 16 * q + 4 * b + (lane >> 4);
-        if (pp < NPT) {
-            double *o = A.PB + ((size_t)m * NP + pp) * 16;
-#pragma unroll
-            for (int pi = 0; pi < 2; ++pi) {
-                o[8 * pi + j] = acc[q][pi][0];
-                o[8 * pi + 4 + j] = acc[q][pi][1];
-            }
-        }
-    }
-}
 
 // Synthesis on the vector unit.  A workgroup takes one order m; each lane
 // carries kAdjPPL ring pairs through the degrees l' = m .. L+1, and each degree
@@ -1488,7 +1398,7 @@ __device__ __forceinline__ void adj_tile_mfma(const LegArgs<store> &A, int m, in
 constexpr int kAdjLdsPerWave = kRowsB * kTileP * 8;
 
 template <typename real>
-__global__ __launch_bounds__(256, 4) void k_leg_adj_mfma(LegArgs<real> A) {
+__global__ __launch_bounds__(256, 4) void k_leg_adj(LegArgs<real> A) {
     extern __shared__ unsigned char smem_raw[];
     // workgroups reach the compute units in rounds of about 256; reversing the
     // order in every other round gives each unit long and short orders alike
@@ -1686,7 +1596,7 @@ __global__ __launch_bounds__(1024) void k_leg_fwd_bf16x3(LegFwdArgs<float> A) {
     leg_fwd_bf16x3_body(A, blockIdx.x, blockIdx.y, smem_raw);
 }
 
-// Synthesis, BF16x3: one wave per 64 ring pairs as k_leg_adj_mfma, degrees in
+// Synthesis, BF16x3: one wave per 64 ring pairs, degrees in
 // blocks of 32 (one K = 32 chunk).  Each lane advances the recurrence of its
 // own pair and writes that pair's 32 values, already split, as one row of the
 // wave's hi and lo tiles ([64 pairs][32 degrees] bf16, 16-byte slot q of pair
@@ -2808,9 +2718,9 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
                 if (bf16)
                     hipLaunchKernelGGL(k_leg_adj_bf16x3, grid, dim3(nw * 64), leg_adj_lds(nw, 4, true), st, G);
                 else
-                    hipLaunchKernelGGL(k_leg_adj_mfma<real>, grid, dim3(nw * 64), leg_adj_lds(nw, 4, false), st, G);
+                    hipLaunchKernelGGL(k_leg_adj<real>, grid, dim3(nw * 64), leg_adj_lds(nw, 4, false), st, G);
             } else {
-                hipLaunchKernelGGL(k_leg_adj_mfma<real>, grid, dim3(nw * 64), leg_adj_lds(nw, 8, false), st, G);
+                hipLaunchKernelGGL(k_leg_adj<real>, grid, dim3(nw * 64), leg_adj_lds(nw, 8, false), st, G);
             }
         }
         e = hipGetLastError();
@@ -2852,9 +2762,9 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
                 if (bf16)
                     hipLaunchKernelGGL(k_leg_adj_bf16x3, grid, dim3(nw * 64), leg_adj_lds(nw, 4, true), st, G);
                 else
-                    hipLaunchKernelGGL(k_leg_adj_mfma<real>, grid, dim3(nw * 64), leg_adj_lds(nw, 4, false), st, G);
+                    hipLaunchKernelGGL(k_leg_adj<real>, grid, dim3(nw * 64), leg_adj_lds(nw, 4, false), st, G);
             } else {
-                hipLaunchKernelGGL(k_leg_adj_mfma<real>, grid, dim3(nw * 64), leg_adj_lds(nw, 8, false), st, G);
+                hipLaunchKernelGGL(k_leg_adj<real>, grid, dim3(nw * 64), leg_adj_lds(nw, 8, false), st, G);
             }
         }
         if (p.eq_ring >= 0)
@@ -3272,13 +3182,13 @@ hipError_t set_kernel_attributes() {
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_leg_fwd_mfma<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_leg_adj_mfma<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = hipFuncSetAttribute((const void *)k_leg_adj<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_leg_fwd_bf16x3, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_leg_adj_bf16x3, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)k_leg_adj_mfma<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    return hipFuncSetAttribute((const void *)k_leg_adj<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
 
 }  // namespace vsht
