@@ -1014,8 +1014,25 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
     const double *ap = A.aprime + t0 - m;  // indexed by l'
     const int nl = L + 2 - m;
     const int nblk = (nl + kRowsB - 1) / kRowsB;
+    // output slots o = threadIdx.x + 64 u (u < 2) of the reduction; their c_{l'} factors
+    // are loaded at the start of each block, well before the reduction needs them
+    auto out_slot = [&](int o, int &lp_off, int &c) {
+        const int r = o >> 6, ln = o & 63;
+        const int bb = (ln >> 2) & 3;
+        lp_off = 2 * (4 * r + (ln >> 4)) + (bb >> 1);
+        c = 4 * (bb & 1) + (ln & 3);
+    };
     for (int blk = 0; blk < nblk; ++blk) {
         const int lp0 = m + blk * kRowsB;
+        double csc[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int o = threadIdx.x + u * 64;
+            int so, c;
+            out_slot(o, so, c);
+            const int lp = lp0 + so;
+            csc[u] = (o < 128 && (u == 0 || blockDim.x == 64) && lp <= L + 1) ? A.cscale[t0 + lp - m] : 0.0;
+        }
         double ab[kRowsB];
         load_aprime(ap, lp0, L + 1, ab);
 #pragma unroll
@@ -1040,11 +1057,13 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
         rw[lane] = acc0;
         rw[64 + lane] = acc1;
         __syncthreads();
-        for (int o = threadIdx.x; o < 128; o += blockDim.x) {
-            const int r = o >> 6, ln = o & 63;
-            const int bb = (ln >> 2) & 3, ppi = bb >> 1;
-            const int so = 2 * (4 * r + (ln >> 4)) + ppi;
-            const int c = 4 * (bb & 1) + (ln & 3);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int o = threadIdx.x + u * 64;
+            if (o >= 128 || (u == 1 && blockDim.x != 64)) break;
+            int so, c;
+            out_slot(o, so, c);
+            const int ppi = so & 1;
             const int lp = lp0 + so;
             if (lp <= L + 1) {
                 const double *rb = red + (blk & 1) * nw * 128;
@@ -1055,7 +1074,7 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
                     const int kk = (lp - m) >> 1;
                     sum += ((kk & 1) ? -seq : seq) * xeq[c];
                 }
-                const double v = A.cscale[ti] * sum;
+                const double v = csc[u] * sum;
                 if (A.atomic)
                     atomicAdd(&A.F[ti * 8 + c], v);
                 else
