@@ -247,7 +247,7 @@ def main():
     ap.add_argument("--oracle-coeffs", type=int, default=1024)
     ap.add_argument("--oracle-points", type=int, default=512)
     ap.add_argument("--no-oracle", action="store_true")
-    ap.add_argument("--precisions", default="fp64,fp32,bf16x3")
+    ap.add_argument("--precisions", default="fp64,fp32,bf16x3,bf16x6")
     ap.add_argument("--l256", type=int, default=1,
                     help="also time L=256: GL 257 x 514 forward+adjoint and the adjoint at 4 L^2 scattered points")
     ap.add_argument("--batch-fields", type=int, default=256,
@@ -360,8 +360,8 @@ def main():
         # Dominant kernel of the step and its algorithmic work per launch.
         # Legendre stages: 16 flops per (m >= 0, m <= l' <= L+1, ring pair) element,
         # i.e. 8 real multiply-adds (theta/phi x +-m x re/im) against one Legendre
-        # value; BF16x3 performs each of them as 3 bf16 products, so its algorithmic
-        # count is 3 x 16 per element against the bf16 MFMA peak.  Ring stages: HBM
+        # value; BF16x3 (BF16x6) performs each of them as 3 (6) bf16 products, so its
+        # algorithmic count is 3 (6) x 16 per element against the bf16 MFMA peak.  Ring stages: HBM
         # bytes of the field (n x 3 complex) plus the ring-Fourier buffer.
         st = r["stages"]
         dom = max(st, key=lambda k: st[k])
@@ -371,17 +371,18 @@ def main():
         kern_names = {"leg_fwd": "k_leg_fwd_mfma", "leg_adj": "k_leg_adj",
                       "ring_fwd": "k_ring_fwd", "ring_adj": "k_ring_adj",
                       "recombine": "k_recombine", "prep": "k_prep"}
-        if prec == "bf16x3":
-            kern_names.update(leg_fwd="k_leg_fwd_bf16x3", leg_adj="k_leg_adj_bf16x3")
+        nprod = {"bf16x3": 3, "bf16x6": 6}.get(prec, 1)
+        if nprod > 1:
+            kern_names.update(leg_fwd="k_leg_fwd_bf16<%d>" % nprod, leg_adj="k_leg_adj_bf16<%d>" % nprod)
         kern = kern_names.get(dom, dom)
         out = {"kernel": kern, "launch_us": round(st[dom] * 1e3, 2)}
         if dom in ("leg_fwd", "leg_adj"):
             E = folded_elements(L, info["n_pairs"])
-            flops = (48.0 if prec == "bf16x3" else 16.0) * E
+            flops = 16.0 * nprod * E
             peak = {"fp64": FP64_MFMA_TFLOPS, "fp32": FP32_MFMA_TFLOPS}.get(prec, BF16_MFMA_TFLOPS)
             # the binary64/binary32 synthesis runs on the vector unit, whose peaks on
             # this part equal the matrix-core ones (78.6 / 157.3 TFLOP/s)
-            bound = "alu" if (dom == "leg_adj" and prec != "bf16x3") else "mfma"
+            bound = "alu" if (dom == "leg_adj" and nprod == 1) else "mfma"
             ach = flops / t / 1e12
             out.update(bound=bound, achieved=round(ach, 3), peak=peak, unit="TFLOP/s",
                        frac=round(ach / peak, 4), flops_per_launch=flops)
@@ -411,7 +412,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32"}.get(main_prec, "bf16x3/f32"),
+        "dtype": {"fp64": "f64", "fp32": "f32"}.get(main_prec, main_prec + "/f32"),
         "data": "synthetic",
         "config": {"workload": "forward+adjoint VSHT, Gauss-Legendre grid %dx%d (%d points), "
                                "L=%d, random coefficients scaled 1/l, seed 0" % (L + 1, 2 * L + 2, N, L),

@@ -82,8 +82,10 @@ typedef enum {
 typedef enum {
     VSHT_FP64 = 0,   /* complex128 I/O, binary64 arithmetic throughout */
     VSHT_FP32 = 1,   /* complex64 I/O, binary32 contraction and FFT, binary64 Legendre recurrence */
-    VSHT_BF16X3 = 2  /* complex64 I/O, Legendre contraction as three bf16 split products with
+    VSHT_BF16X3 = 2, /* complex64 I/O, Legendre contraction as three bf16 split products with
                         binary32 accumulation, binary64 Legendre recurrence */
+    VSHT_BF16X6 = 3  /* as VSHT_BF16X3 with three bf16 parts per operand and six products
+                        (the dropped terms are below binary32 rounding) */
 } vsht_precision;
 
 /* Flags of vsht_opts. */

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvsht.so")
 
 VSHT_OK, VSHT_EINVAL, VSHT_ENOWEIGHTS, VSHT_ENOMEM, VSHT_EDEVICE, VSHT_EUNSUPPORTED = range(6)
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 PLAN_RINGS, PLAN_SCATTERED, PLAN_BATCH = 0, 1, 2
 
 # every symbol include/vsht.h declares

@@ -393,7 +393,8 @@ vsht_status check_plan_args(int L, int64_t n, const double *xyz, const double *w
     if (n < 1) return fail(VSHT_EINVAL, "n must be >= 1");
     if (w && n < 2) return fail(VSHT_EINVAL, "a quadrature rule needs n >= 2 points");
     if (!xyz) return fail(VSHT_EINVAL, "xyz is NULL");
-    if (precision != VSHT_FP64 && precision != VSHT_FP32 && precision != VSHT_BF16X3)
+    if (precision != VSHT_FP64 && precision != VSHT_FP32 && precision != VSHT_BF16X3 &&
+        precision != VSHT_BF16X6)
         return fail(VSHT_EINVAL, "unknown precision");
     for (int64_t k = 0; k < n; ++k) {
         const double x = xyz[3 * k], y = xyz[3 * k + 1], z = xyz[3 * k + 2];

@@ -1414,7 +1414,6 @@ __device__ __forceinline__ void adj_tile_mfma(const LegArgs<store> &A, int m, in
 }
 
 // Bytes of LDS per wave of the synthesis kernels (the largest tile any path uses).
-constexpr int kAdjLdsPerWave = kRowsB * kTileP * 8;
 
 template <typename real>
 __global__ __launch_bounds__(256, 4) void k_leg_adj(LegArgs<real> A) {
@@ -1461,11 +1460,15 @@ __global__ __launch_bounds__(64) void k_equator_adj(LegArgs<real> A) {
 }
 
 // ---------------------------------------------------------------------------
-// BF16x3 Legendre stages.  A binary32 operand x is split as x = hi + lo + r
-// with hi = bf16(x), lo = bf16(x - hi) (round to nearest, |r| <= 2^-17 |x|),
-// and a product as hi*hi' + hi*lo' + lo*hi' on the 16x16x32 bf16 MFMA with
-// binary32 accumulation; the dropped lo*lo' term is below 2^-16 relative.
-// The Legendre recurrence, its seeds and its scaling stay binary64.
+// BF16x3 and BF16x6 Legendre stages.  A binary32 operand x is split into bf16
+// parts by repeated rounding, x = p0 + p1 (+ p2) + r with p0 = bf16(x),
+// p1 = bf16(x - p0), p2 = bf16(x - p0 - p1) (each difference exact in binary32).
+// BF16x3 keeps two parts (|r| <= 2^-17 |x|) and forms a product as
+// p0 p0' + p0 p1' + p1 p0'; the dropped terms are below 2^-16 relative.
+// BF16x6 keeps three parts (|r| <= 2^-26 |x|) and adds p0 p2' + p1 p1' + p2 p0';
+// the dropped terms are below 2^-24 relative, binary32's own rounding.  All
+// products run on the 16x16x32 bf16 MFMA with binary32 accumulation.  The
+// Legendre recurrence, its seeds and its scaling stay binary64.
 // Operand layouts of v_mfma_f32_16x16x32_bf16 (measured on gfx950): lane l
 // holds A[row l%16][k 8(l/16)+t] and B[k 8(l/16)+t][col l%16], t = 0..7, and
 // D register r of lane l is [row 4(l/16)+r][col l%16].
@@ -1475,36 +1478,61 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
+// NP = products per product: 3 (BF16x3, two parts) or 6 (BF16x6, three parts)
+template <int NP>
+struct Bf16 {
+    static_assert(NP == 3 || NP == 6, "BF16x3 or BF16x6");
+    static constexpr int kParts = NP == 6 ? 3 : 2;
+    static constexpr int kAdjLdsPerWave = kParts * kTileP * 32 * 2;  // split Q tiles of the synthesis
+};
+template <int NP>
 struct Split8 {
-    bf16x8_t hi, lo;
+    bf16x8_t p[Bf16<NP>::kParts];
 };
 
-// hi/lo split of two values, each result packed as two bf16 in 32 bits
-__device__ __forceinline__ void split2(float a, float b, uint32_t &hi, uint32_t &lo) {
-    const f32x2_t v = {a, b};
-    hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
-    const float ha = __builtin_bit_cast(float, hi << 16);
-    const float hb = __builtin_bit_cast(float, hi & 0xffff0000u);
-    const f32x2_t r = {a - ha, b - hb};
-    lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2_t));
+// split of two values into NS parts, each part packed as two bf16 in 32 bits
+template <int NS>
+__device__ __forceinline__ void split2(float a, float b, uint32_t (&o)[NS]) {
+    float ra = a, rb = b;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const f32x2_t v = {ra, rb};
+        const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+        o[k] = h;
+        ra -= __builtin_bit_cast(float, h << 16);
+        rb -= __builtin_bit_cast(float, h & 0xffff0000u);
+    }
 }
 
-__device__ __forceinline__ Split8 split8(const float (&v)[8]) {
-    u32x4_t h, l;
+template <int NP>
+__device__ __forceinline__ Split8<NP> split8(const float (&v)[8]) {
+    constexpr int NS = Bf16<NP>::kParts;
+    u32x4_t w[NS];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        uint32_t hi, lo;
-        split2(v[2 * i], v[2 * i + 1], hi, lo);
-        h[i] = hi;
-        l[i] = lo;
+        uint32_t o[NS];
+        split2<NS>(v[2 * i], v[2 * i + 1], o);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) w[k][i] = o[k];
     }
-    return {__builtin_bit_cast(bf16x8_t, h), __builtin_bit_cast(bf16x8_t, l)};
+    Split8<NP> r;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) r.p[k] = __builtin_bit_cast(bf16x8_t, w[k]);
+    return r;
 }
 
-__device__ __forceinline__ f32x4 mma3(const Split8 &a, const Split8 &b, f32x4 acc) {
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, acc, 0, 0, 0);
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, acc, 0, 0, 0);
+// the part products p_i p_j' with i + j < parts, largest first
+template <int NP>
+__device__ __forceinline__ f32x4 mma_split(const Split8<NP> &a, const Split8<NP> &b, f32x4 acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[0], b.p[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[0], b.p[1], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[1], b.p[0], acc, 0, 0, 0);
+    if constexpr (NP == 6) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[0], b.p[2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[1], b.p[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[2], b.p[0], acc, 0, 0, 0);
+    }
+    return acc;
 }
 
 
@@ -1517,10 +1545,11 @@ struct SwzFwd8 {
     }
 };
 
-// Analysis, BF16x3: as k_leg_fwd_mfma<float> (same grid, reduction and
+// Analysis, BF16x3/BF16x6: as k_leg_fwd_mfma<float> (same grid, reduction and
 // epilogue) with the wave's 64-pair block contracted as two K = 32 chunks.
-__device__ __forceinline__ void leg_fwd_bf16x3_body(const LegFwdArgs<float> &A, int m, int group,
-                                                    unsigned char *smem_raw) {
+template <int NPROD>
+__device__ __forceinline__ void leg_fwd_bf16_body(const LegFwdArgs<float> &A, int m, int group,
+                                                  unsigned char *smem_raw) {
     const int L = A.L, NP = A.NP, NPT = A.NPT, NR = A.NR;
     const int nw = blockDim.x >> 6;
     const int wave = uniform_int(threadIdx.x >> 6);
@@ -1533,7 +1562,7 @@ __device__ __forceinline__ void leg_fwd_bf16x3_body(const LegFwdArgs<float> &A, 
 
     // B: lane (j + 16kg) holds X[pair 32c + 8kg + t][column j] of chunk c
     const int j = lane & 15, kg = lane >> 4;
-    Split8 bx[2];
+    Split8<NPROD> bx[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         float v[8];
@@ -1549,7 +1578,7 @@ __device__ __forceinline__ void leg_fwd_bf16x3_body(const LegFwdArgs<float> &A, 
             }
             v[t] = x;
         }
-        bx[c] = split8(v);
+        bx[c] = split8<NPROD>(v);
     }
     const int p = tile * kTileP + lane;
     const bool valid = p < NPT;
@@ -1578,7 +1607,7 @@ __device__ __forceinline__ void leg_fwd_bf16x3_body(const LegFwdArgs<float> &A, 
             const float4 *src = reinterpret_cast<const float4 *>(qt + SwzFwd8::at(j, 32 * c + 8 * kg));
             const float4 u0 = src[0], u1 = src[1];
             const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
-            acc = mma3(split8(v), bx[c], acc);
+            acc = mma_split<NPROD>(split8<NPROD>(v), bx[c], acc);
         }
         __builtin_amdgcn_wave_barrier();
         float *rw = red + ((blk & 1) * nw + wave) * 128;
@@ -1610,24 +1639,26 @@ __device__ __forceinline__ void leg_fwd_bf16x3_body(const LegFwdArgs<float> &A, 
     }
 }
 
-__global__ __launch_bounds__(1024) void k_leg_fwd_bf16x3(LegFwdArgs<float> A) {
+template <int NP>
+__global__ __launch_bounds__(1024) void k_leg_fwd_bf16(LegFwdArgs<float> A) {
     extern __shared__ unsigned char smem_raw[];
-    leg_fwd_bf16x3_body(A, blockIdx.x, blockIdx.y, smem_raw);
+    leg_fwd_bf16_body<NP>(A, blockIdx.x, blockIdx.y, smem_raw);
 }
 
-// Synthesis, BF16x3: one wave per 64 ring pairs, degrees in
+// Synthesis, BF16x3/BF16x6: one wave per 64 ring pairs, degrees in
 // blocks of 32 (one K = 32 chunk).  Each lane advances the recurrence of its
-// own pair and writes that pair's 32 values, already split, as one row of the
-// wave's hi and lo tiles ([64 pairs][32 degrees] bf16, 16-byte slot q of pair
+// own pair and writes that pair's 32 values, already split, as one row of each
+// of the wave's part tiles ([64 pairs][32 degrees] bf16, 16-byte slot q of pair
 // p stored at slot q ^ ((p >> 2) & 3) so that 16 lanes of a row group hit
 // distinct banks).
 constexpr int kRowsA = 32;
 
-__device__ __forceinline__ void adj_tile_bf16x3(const LegArgs<float> &A, int m, int tile, int lane,
-                                                u32x4_t *th) {
+template <int NPROD>
+__device__ __forceinline__ void adj_tile_bf16(const LegArgs<float> &A, int m, int tile, int lane,
+                                              u32x4_t *th) {
+    constexpr int NS = Bf16<NPROD>::kParts;
     const int L = A.L, NP = A.NP;
     const int NPT = A.NPT;
-    u32x4_t *tl = th + kTileP * 4;
     const int64_t t0 = tri_offset(L, m);
     const float *g = A.FG + (t0 - m) * 8;    // indexed by l'
     const double *ap = A.aprime + t0 - m;    // indexed by l'
@@ -1651,8 +1682,8 @@ __device__ __forceinline__ void adj_tile_bf16x3(const LegArgs<float> &A, int m, 
             const int lp = lp0 + 8 * kg + t;
             bv[t] = (lp <= L + 1 && (t & 1) == (j >> 3)) ? g[(int64_t)lp * 8 + (j & 7)] : 0.f;
         }
-        const Split8 bs = split8(bv);
-        uint32_t hq[16], lq[16];
+        const Split8<NPROD> bs = split8<NPROD>(bv);
+        uint32_t hq[NS][16];
         double ab[kRowsA];
         load_aprime(ap, lp0, L + 1, ab);
 #pragma unroll
@@ -1661,22 +1692,28 @@ __device__ __forceinline__ void adj_tile_bf16x3(const LegArgs<float> &A, int m, 
             const double v1 = fma(ab[s + 1] * z, v0, -q1);
             q2 = v0;
             q1 = v1;
-            split2((float)v0, (float)v1, hq[s >> 1], lq[s >> 1]);
+            uint32_t o[NS];
+            split2<NS>((float)v0, (float)v1, o);
+#pragma unroll
+            for (int k = 0; k < NS; ++k) hq[k][s >> 1] = o[k];
         }
         const int sw = (lane >> 2) & 3;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            th[lane * 4 + (q ^ sw)] = u32x4_t{hq[4 * q], hq[4 * q + 1], hq[4 * q + 2], hq[4 * q + 3]};
-            tl[lane * 4 + (q ^ sw)] = u32x4_t{lq[4 * q], lq[4 * q + 1], lq[4 * q + 2], lq[4 * q + 3]};
-        }
+        for (int k = 0; k < NS; ++k)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                th[k * kTileP * 4 + lane * 4 + (q ^ sw)] =
+                    u32x4_t{hq[k][4 * q], hq[k][4 * q + 1], hq[k][4 * q + 2], hq[k][4 * q + 3]};
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             // A: lane (j + 16kg) holds Q[pair 16b + j][degrees lp0 + 8kg .. + 7]
             const int P = 16 * b + j;
             const int slot = P * 4 + (kg ^ ((P >> 2) & 3));
-            const Split8 qa = {__builtin_bit_cast(bf16x8_t, th[slot]), __builtin_bit_cast(bf16x8_t, tl[slot])};
-            acc[b] = mma3(qa, bs, acc[b]);
+            Split8<NPROD> qa;
+#pragma unroll
+            for (int k = 0; k < NS; ++k) qa.p[k] = __builtin_bit_cast(bf16x8_t, th[k * kTileP * 4 + slot]);
+            acc[b] = mma_split<NPROD>(qa, bs, acc[b]);
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -1690,22 +1727,23 @@ __device__ __forceinline__ void adj_tile_bf16x3(const LegArgs<float> &A, int m, 
     }
 }
 
-// BF16x3 synthesis.  The spin-frame form divides the synthesised sums by
+// BF16x3/BF16x6 synthesis.  The spin-frame form divides the synthesised sums by
 // sin(theta), which near the poles amplifies the rounding of the contraction by
 // up to 1/sin(theta) ~ L; the first tile (the 64 ring pairs nearest the poles:
 // pairs are sorted by increasing sin(theta)) therefore runs on the binary32
 // MFMA path.
-__global__ __launch_bounds__(256) void k_leg_adj_bf16x3(LegArgs<float> A) {
+template <int NP>
+__global__ __launch_bounds__(256) void k_leg_adj_bf16(LegArgs<float> A) {
     extern __shared__ unsigned char smem_raw[];
     const int nw = blockDim.x >> 6;
     const int wave = uniform_int(threadIdx.x >> 6);
     const int tile = blockIdx.x * nw + wave;
     if (tile * kTileP >= A.NPT) return;
-    unsigned char *lds = smem_raw + wave * kAdjLdsPerWave;
+    unsigned char *lds = smem_raw + wave * Bf16<NP>::kAdjLdsPerWave;
     if (tile == 0)
         adj_tile_mfma<float, float>(A, blockIdx.y, tile, threadIdx.x & 63, reinterpret_cast<float *>(lds));
     else
-        adj_tile_bf16x3(A, blockIdx.y, tile, threadIdx.x & 63, reinterpret_cast<u32x4_t *>(lds));
+        adj_tile_bf16<NP>(A, blockIdx.y, tile, threadIdx.x & 63, reinterpret_cast<u32x4_t *>(lds));
 }
 
 // ---------------------------------------------------------------------------
@@ -2435,15 +2473,15 @@ __global__ __launch_bounds__(NT, 2) void kb_ring_adj(const RingArgs<real> *__res
 }
 
 // work item (field, m, -): every tile of the field's pairs in one workgroup
-template <typename real, bool kBf16>
+template <typename real, int kBf16>
 __global__ __launch_bounds__(1024) void kb_leg_fwd(const LegFwdArgs<real> *__restrict__ args,
                                                    const WorkItem *__restrict__ work,
                                                    unsigned long long *) {
     extern __shared__ unsigned char smem_raw[];
     const WorkItem w = ld_const(work + blockIdx.x);
     const LegFwdArgs<real> A = ld_const(args + w.f);
-    if constexpr (kBf16)
-        leg_fwd_bf16x3_body(A, w.x, 0, smem_raw);
+    if constexpr (kBf16 != 0)
+        leg_fwd_bf16_body<kBf16>(A, w.x, 0, smem_raw);
     else if constexpr (sizeof(real) == 8)
         leg_fwd_f64q_body(A, w.x, 0, smem_raw);
     else
@@ -2451,7 +2489,7 @@ __global__ __launch_bounds__(1024) void kb_leg_fwd(const LegFwdArgs<real> *__res
 }
 
 // work item (field, tile group, m)
-template <typename real, bool kBf16>
+template <typename real, int kBf16>
 __global__ __launch_bounds__(256, 4) void kb_leg_adj(const LegArgs<real> *__restrict__ args,
                                                   const WorkItem *__restrict__ work,
                                                   unsigned long long *) {
@@ -2460,15 +2498,15 @@ __global__ __launch_bounds__(256, 4) void kb_leg_adj(const LegArgs<real> *__rest
     const LegArgs<real> A = ld_const(args + w.f);
     const int nw = blockDim.x >> 6;
     const int wave = uniform_int(threadIdx.x >> 6);
-    if constexpr (kBf16) {
+    if constexpr (kBf16 != 0) {
         const int tile = w.x * nw + wave;
         if (tile * kTileP >= A.NPT) return;
         const int lane = threadIdx.x & 63;
-        unsigned char *lds = smem_raw + wave * kAdjLdsPerWave;
+        unsigned char *lds = smem_raw + wave * Bf16<kBf16>::kAdjLdsPerWave;
         if (tile == 0)
             adj_tile_mfma<float, float>(A, w.y, tile, lane, reinterpret_cast<float *>(lds));
         else
-            adj_tile_bf16x3(A, w.y, tile, lane, reinterpret_cast<u32x4_t *>(lds));
+            adj_tile_bf16<kBf16>(A, w.y, tile, lane, reinterpret_cast<u32x4_t *>(lds));
     } else {
         adj_valu_body<real>(A, w.y, w.x, reinterpret_cast<AdjRow<real> *>(smem_raw));
     }
@@ -2511,9 +2549,13 @@ static RingArgs<real> make_ring_args(const Plan &p, const void *Tin, void *Tout,
 
 static int pairs_in_tiles(const Plan &p) { return (int)(p.n_pairs - (p.eq_ring >= 0 ? 1 : 0)); }
 static int tiles_of(const Plan &p) { return (pairs_in_tiles(p) + kTileP - 1) / kTileP; }
-// Waves of the synthesis: 64 pairs each for BF16x3, 64 kAdjPPL on the vector unit.
-static int adj_waves(int pairs, bool bf16) {
-    const int per = kTileP * (bf16 ? 1 : kAdjPPL);
+// Products per product of a split-bf16 precision (0 for binary64 and binary32).
+static int bf16_products(int precision) {
+    return precision == VSHT_BF16X3 ? 3 : precision == VSHT_BF16X6 ? 6 : 0;
+}
+// Waves of the synthesis: 64 pairs each for the split-bf16 modes, 64 kAdjPPL on the vector unit.
+static int adj_waves(int pairs, int nprod) {
+    const int per = kTileP * (nprod ? 1 : kAdjPPL);
     return (pairs + per - 1) / per;
 }
 
@@ -2568,9 +2610,39 @@ static CoefArgs<real> make_coef_args(const Plan &p, const void *ain, const void 
 }
 
 static size_t leg_fwd_lds(int nw, size_t rsz) { return (size_t)nw * (kRowsB * kTileP + 2 * 128) * rsz; }
-static size_t leg_adj_lds(int nw, size_t rsz, bool bf16) {
-    if (bf16) return (size_t)nw * kAdjLdsPerWave;
+static size_t leg_adj_lds(int nw, size_t rsz, int nprod) {
+    if (nprod == 3) return (size_t)nw * Bf16<3>::kAdjLdsPerWave;
+    if (nprod == 6) return (size_t)nw * Bf16<6>::kAdjLdsPerWave;
     return 2 * kAdjChunk * (rsz == 8 ? sizeof(AdjRow<double>) : sizeof(AdjRow<float>));
+}
+
+// Analysis and synthesis launches in the plan's arithmetic.
+template <typename real>
+static void launch_leg_fwd(const LegFwdArgs<real> &G, dim3 grid, int nw, int nprod, hipStream_t st) {
+    if constexpr (sizeof(real) == 4) {
+        if (nprod == 3)
+            hipLaunchKernelGGL(k_leg_fwd_bf16<3>, grid, dim3(nw * 64), leg_fwd_lds(nw, 4), st, G);
+        else if (nprod == 6)
+            hipLaunchKernelGGL(k_leg_fwd_bf16<6>, grid, dim3(nw * 64), leg_fwd_lds(nw, 4), st, G);
+        else
+            hipLaunchKernelGGL(k_leg_fwd_mfma<real>, grid, dim3(nw * 64), leg_fwd_lds(nw, 4), st, G);
+    } else {
+        hipLaunchKernelGGL(k_leg_fwd_mfma<real>, grid, dim3(nw * 64), leg_fwd_lds(nw, 8), st, G);
+    }
+}
+template <typename real>
+static void launch_leg_adj(const LegArgs<real> &G, dim3 grid, int nw, int nprod, hipStream_t st) {
+    const size_t lds = leg_adj_lds(nw, sizeof(real), nprod);
+    if constexpr (sizeof(real) == 4) {
+        if (nprod == 3)
+            hipLaunchKernelGGL(k_leg_adj_bf16<3>, grid, dim3(nw * 64), lds, st, G);
+        else if (nprod == 6)
+            hipLaunchKernelGGL(k_leg_adj_bf16<6>, grid, dim3(nw * 64), lds, st, G);
+        else
+            hipLaunchKernelGGL(k_leg_adj<real>, grid, dim3(nw * 64), lds, st, G);
+    } else {
+        hipLaunchKernelGGL(k_leg_adj<real>, grid, dim3(nw * 64), lds, st, G);
+    }
 }
 
 template <typename real>
@@ -2607,7 +2679,7 @@ static NfftArgs<real> make_nfft_args(const Plan &p, const void *Tin, void *Tout,
 template <typename real>
 static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, bool weighted,
                                hipStream_t st) {
-    const bool bf16 = p.precision == VSHT_BF16X3;
+    const int nprod = bf16_products(p.precision);
     if (p.kind == VSHT_PLAN_SCATTERED) {
         // scattered points: spread, grid DFTs, virtual-ring values, then the ring analysis
         const NfftPlan &nf = p.nfft;
@@ -2641,15 +2713,7 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
         {
             const int ntile = (nf.npv + kTileP - 1) / kTileP;  // <= 16 for the bandlimits served
             StageScope sc(p, VSHT_STAGE_LEG_FWD, st);
-            const dim3 grid(p.L + 1, 1);
-            if constexpr (sizeof(real) == 4) {
-                if (bf16)
-                    hipLaunchKernelGGL(k_leg_fwd_bf16x3, grid, dim3(ntile * 64), leg_fwd_lds(ntile, 4), st, G);
-                else
-                    hipLaunchKernelGGL(k_leg_fwd_mfma<real>, grid, dim3(ntile * 64), leg_fwd_lds(ntile, 4), st, G);
-            } else {
-                hipLaunchKernelGGL(k_leg_fwd_mfma<real>, grid, dim3(ntile * 64), leg_fwd_lds(ntile, 8), st, G);
-            }
+            launch_leg_fwd<real>(G, dim3(p.L + 1, 1), ntile, nprod, st);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -2683,15 +2747,7 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
             e = hipMemsetAsync(p.d_fg, 0, (size_t)p.tri_size * 8 * sizeof(real), st);
             if (e != hipSuccess) return e;
         }
-        const dim3 grid(p.L + 1, ngroup);
-        if constexpr (sizeof(real) == 4) {
-            if (bf16)
-                hipLaunchKernelGGL(k_leg_fwd_bf16x3, grid, dim3(nw * 64), leg_fwd_lds(nw, 4), st, G);
-            else
-                hipLaunchKernelGGL(k_leg_fwd_mfma<real>, grid, dim3(nw * 64), leg_fwd_lds(nw, 4), st, G);
-        } else {
-            hipLaunchKernelGGL(k_leg_fwd_mfma<real>, grid, dim3(nw * 64), leg_fwd_lds(nw, 8), st, G);
-        }
+        launch_leg_fwd<real>(G, dim3(p.L + 1, ngroup), nw, nprod, st);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -2707,7 +2763,7 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
 template <typename real>
 static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void *T, bool weighted,
                                hipStream_t st) {
-    const bool bf16 = p.precision == VSHT_BF16X3;
+    const int nprod = bf16_products(p.precision);
     const CoefArgs<real> C = make_coef_args<real>(p, a, b, nullptr, nullptr);
     {
         StageScope sc(p, VSHT_STAGE_PREP, st);
@@ -2730,17 +2786,9 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
         G.NPT = nf.npv;
         {
             StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
-            const int ntile = adj_waves(nf.npv, bf16);
+            const int ntile = adj_waves(nf.npv, nprod);
             const int nw = ntile < 4 ? ntile : 4;
-            const dim3 grid((ntile + nw - 1) / nw, p.L + 1);
-            if constexpr (sizeof(real) == 4) {
-                if (bf16)
-                    hipLaunchKernelGGL(k_leg_adj_bf16x3, grid, dim3(nw * 64), leg_adj_lds(nw, 4, true), st, G);
-                else
-                    hipLaunchKernelGGL(k_leg_adj<real>, grid, dim3(nw * 64), leg_adj_lds(nw, 4, false), st, G);
-            } else {
-                hipLaunchKernelGGL(k_leg_adj<real>, grid, dim3(nw * 64), leg_adj_lds(nw, 8, false), st, G);
-            }
+            launch_leg_adj<real>(G, dim3((ntile + nw - 1) / nw, p.L + 1), nw, nprod, st);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -2773,18 +2821,10 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
     const LegArgs<real> G = make_leg_adj_args<real>(p);
     {
         StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
-        const int ntile = adj_waves(pairs_in_tiles(p), bf16);
+        const int ntile = adj_waves(pairs_in_tiles(p), nprod);
         if (ntile > 0) {
             const int nw = ntile < 4 ? ntile : 4;
-            const dim3 grid((ntile + nw - 1) / nw, p.L + 1);
-            if constexpr (sizeof(real) == 4) {
-                if (bf16)
-                    hipLaunchKernelGGL(k_leg_adj_bf16x3, grid, dim3(nw * 64), leg_adj_lds(nw, 4, true), st, G);
-                else
-                    hipLaunchKernelGGL(k_leg_adj<real>, grid, dim3(nw * 64), leg_adj_lds(nw, 4, false), st, G);
-            } else {
-                hipLaunchKernelGGL(k_leg_adj<real>, grid, dim3(nw * 64), leg_adj_lds(nw, 8, false), st, G);
-            }
+            launch_leg_adj<real>(G, dim3((ntile + nw - 1) / nw, p.L + 1), nw, nprod, st);
         }
         if (p.eq_ring >= 0)
             hipLaunchKernelGGL(k_equator_adj<real>, dim3(p.L + 1), dim3(64), 0, st, G);
@@ -2912,7 +2952,7 @@ hipError_t batch_configure(BatchState *b, const BatchConfig &cfg) {
     b->work.clear();
     b->launches.clear();
     const size_t rsz = b->rsz;
-    const bool bf16 = b->precision == VSHT_BF16X3;
+    const int nprod = bf16_products(b->precision);
     struct Item {
         WorkItem w;
         double cost;
@@ -2938,10 +2978,10 @@ hipError_t batch_configure(BatchState *b, const BatchConfig &cfg) {
     emit(BS_PREP, 4, items, 0);
     items.clear();
     // Legendre synthesis: one shape for every field
-    size_t lds_adj = leg_adj_lds(cfg.adj_nw, rsz, bf16);
+    size_t lds_adj = leg_adj_lds(cfg.adj_nw, rsz, nprod);
     for (int i = 0; i < F; ++i) {
         const Plan &p = *b->f[i];
-        const int ntile = adj_waves(pairs_in_tiles(p), bf16);
+        const int ntile = adj_waves(pairs_in_tiles(p), nprod);
         for (int tg = 0; tg * cfg.adj_nw < ntile; ++tg) {
             const int nt = std::min(cfg.adj_nw, ntile - tg * cfg.adj_nw);
             for (int m = 0; m <= p.L; ++m) items.push_back({{i, tg, m, 0}, (double)(p.L + 2 - m) * nt});
@@ -3062,7 +3102,7 @@ hipError_t batch_bind_forward(BatchState *b, const void *const *T, void *const *
     return e;
 }
 
-template <typename real, bool kBf16>
+template <typename real, int kBf16>
 static hipError_t batch_launch_impl(const BatchState *b, int dirs, hipStream_t st) {
     for (const auto &l : b->launches) {
         const bool adj = stage_is_adjoint(l.stage);
@@ -3116,9 +3156,10 @@ static hipError_t batch_launch_impl(const BatchState *b, int dirs, hipStream_t s
 }
 
 hipError_t batch_launch(const BatchState *b, int dirs, hipStream_t st) {
-    if (b->precision == VSHT_FP64) return batch_launch_impl<double, false>(b, dirs, st);
-    if (b->precision == VSHT_BF16X3) return batch_launch_impl<float, true>(b, dirs, st);
-    return batch_launch_impl<float, false>(b, dirs, st);
+    if (b->precision == VSHT_FP64) return batch_launch_impl<double, 0>(b, dirs, st);
+    if (b->precision == VSHT_BF16X3) return batch_launch_impl<float, 3>(b, dirs, st);
+    if (b->precision == VSHT_BF16X6) return batch_launch_impl<float, 6>(b, dirs, st);
+    return batch_launch_impl<float, 0>(b, dirs, st);
 }
 
 // Per-field first start and last end (device wall clock, microseconds) of the
@@ -3174,9 +3215,10 @@ hipError_t set_kernel_attributes() {
                              (const void *)kb_ring_adj<float, kRingNTSmall>,
                              (const void *)k_ring_fwd<double, kRingNTSmall>, (const void *)k_ring_fwd<float, kRingNTSmall>,
                              (const void *)k_ring_adj<double, kRingNTSmall>, (const void *)k_ring_adj<float, kRingNTSmall>,
-                             (const void *)kb_leg_fwd<double, false>, (const void *)kb_leg_fwd<float, false>,
-                             (const void *)kb_leg_fwd<float, true>, (const void *)kb_leg_adj<double, false>,
-                             (const void *)kb_leg_adj<float, false>, (const void *)kb_leg_adj<float, true>};
+                             (const void *)kb_leg_fwd<double, 0>, (const void *)kb_leg_fwd<float, 0>,
+                             (const void *)kb_leg_fwd<float, 3>, (const void *)kb_leg_fwd<float, 6>,
+                             (const void *)kb_leg_adj<double, 0>, (const void *)kb_leg_adj<float, 0>,
+                             (const void *)kb_leg_adj<float, 3>, (const void *)kb_leg_adj<float, 6>};
     const void *nfft_kernels[] = {(const void *)k_nfft_cols<double>, (const void *)k_nfft_cols<float>,
                                   (const void *)k_nfft_rows<double>, (const void *)k_nfft_rows<float>,
                                   (const void *)k_nfft_cols_fwd<double>, (const void *)k_nfft_cols_fwd<float>,
@@ -3203,9 +3245,13 @@ hipError_t set_kernel_attributes() {
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_leg_adj<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_leg_fwd_bf16x3, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = hipFuncSetAttribute((const void *)k_leg_fwd_bf16<3>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_leg_adj_bf16x3, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = hipFuncSetAttribute((const void *)k_leg_fwd_bf16<6>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_leg_adj_bf16<3>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_leg_adj_bf16<6>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void *)k_leg_adj<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }

@@ -63,7 +63,7 @@ def single_results(torch, vsht, Ls, grids, a, b, precision):
 LS_MIXED = [1, 7, 16, 33, 64, 100, 129, 40]   # 1..3 tiles of 64 ring pairs, odd and even ring counts
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "bf16x6"])
 def test_batch_equals_single_plans(torch, vsht, precision):
     print("[case] batch vs single plans", precision, LS_MIXED, flush=True)
     bp, grids, coeffs, a, b = make_batch(torch, vsht, LS_MIXED, precision)
