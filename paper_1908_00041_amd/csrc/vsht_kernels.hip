@@ -1211,17 +1211,23 @@ struct alignas(16) AdjRow {
 
 // acc += bcast_k(g) * r, where bcast_k(g) is g of lane k of the lane's row of 16
 // (binary64 DPP row broadcast).  The assembler form is the only one that puts
-// the broadcast on the FMA itself; g must come straight from memory (no vector
-// ALU write immediately before a DPP read of it).
-template <int K>
+// the broadcast on the FMA itself.  A DPP read needs two wait states after a
+// vector ALU write of its source, which the compiler does not see inside the
+// assembler text: the first FMA of each group of eight waits them out.
+template <int K, bool kWait>
 __device__ __forceinline__ void fmac_row_bcast(double &acc, double g, double r) {
-    asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
-        : "+v"(acc)
-        : "v"(g), "v"(r), "n"(K));
+    if constexpr (kWait)
+        asm("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+            : "+v"(acc)
+            : "v"(g), "v"(r), "n"(K));
+    else
+        asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+            : "+v"(acc)
+            : "v"(g), "v"(r), "n"(K));
 }
 template <int K0, int C = 0>
 __device__ __forceinline__ void fmac_row_bcast8(double (&S)[8], double g, double r) {
-    fmac_row_bcast<K0 + C>(S[C], g, r);
+    fmac_row_bcast<K0 + C, C == 0>(S[C], g, r);
     if constexpr (C + 1 < 8) fmac_row_bcast8<K0, C + 1>(S, g, r);
 }
 
