@@ -965,19 +965,18 @@ __device__ __forceinline__ double mma44(double a, double b, double c) {
     return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
-// Analysis tile [16 degrees][64 pairs]: one read group is 8 consecutive rows
-// x 4 pairs, read together with the same group 8 rows further (one paired
-// read); XOR-ing the pair with 4 (row & 7) and 16 (row >> 3) puts all 64
-// addresses in distinct bank pairs.
-struct SwzQ4Fwd {
-    static __device__ __forceinline__ int at(int row, int pair) {
-        return row * kTileP + (pair ^ ((row & 7) << 2) ^ ((row & 8) << 1));
-    }
+// Analysis tile of 16 degrees x 64 pairs as [64 pairs][8 slots] of 16 bytes:
+// slot q = 2i + pi of a pair holds its rows 4i + pi and 4i + pi + 2 (the two A
+// operands one lane needs for the same parity block), so a lane reads both with
+// one 16-byte access.  The slot is XOR-ed with (pair >> 1) & 7: the 16 lanes
+// of a write (one slot of 16 consecutive pairs) then cover all 16 bank groups.
+struct SwzQ2Fwd {
+    static __device__ __forceinline__ int slot(int pair, int q) { return pair * 8 + (q ^ ((pair >> 1) & 7)); }
 };
 
 // Analysis, binary64: workgroup = order m, waves = tiles of 64 ring pairs.
 // Instruction (row group r, pair step g): block b = (parity pi = b>>1, column
-// half h = b&1), rows = degrees lp0 + 2(4r + i) + pi, K = pairs 4g + k,
+// half h = b&1), rows = degrees lp0 + 4i + 2r + pi, K = pairs 4g + k,
 // columns 4h + j of X[pi] (X[0] = N + S, X[1] = N - S).
 __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, int m, int group,
                                                   unsigned char *smem_raw) {
@@ -986,7 +985,7 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
     const int wave = uniform_int(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int tile = group * nw + wave;
-    double *qt = reinterpret_cast<double *>(smem_raw) + wave * kRowsB * kTileP;
+    double2 *qt = reinterpret_cast<double2 *>(smem_raw) + wave * (kRowsB / 2) * kTileP;
     double *red = reinterpret_cast<double *>(smem_raw) + nw * kRowsB * kTileP;  // [2][nw][128]
     const int64_t t0 = tri_offset(L, m);
     const double *RBm = A.RB + (size_t)m * NR * 8;
@@ -1019,7 +1018,7 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
     auto out_slot = [&](int o, int &lp_off, int &c) {
         const int r = o >> 6, ln = o & 63;
         const int bb = (ln >> 2) & 3;
-        lp_off = 2 * (4 * r + (ln >> 4)) + (bb >> 1);
+        lp_off = 4 * (ln >> 4) + 2 * r + (bb >> 1);
         c = 4 * (bb & 1) + (ln & 3);
     };
     for (int blk = 0; blk < nblk; ++blk) {
@@ -1035,10 +1034,14 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
         }
         double ab[kRowsB];
         load_aprime(ap, lp0, L + 1, ab);
+        double held[2] = {0.0, 0.0};  // rows 4i + pi, waiting for their partner two rows on
 #pragma unroll
         for (int s = 0; s < kRowsB; ++s) {
             const double v = fma(ab[s] * z, q1, -q2);
-            qt[SwzQ4Fwd::at(s, lane)] = v;
+            if (s & 2)
+                qt[SwzQ2Fwd::slot(lane, 2 * (s >> 2) + (s & 1))] = double2{held[s & 1], v};
+            else
+                held[s & 1] = v;
             q2 = q1;
             q1 = v;
         }
@@ -1046,13 +1049,13 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
         double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll
         for (int g = 0; g < 16; ++g) {
-            const double a0 = qt[SwzQ4Fwd::at(2 * i + pi, 4 * g + k)];
-            const double a1 = qt[SwzQ4Fwd::at(8 + 2 * i + pi, 4 * g + k)];
+            const double2 av = qt[SwzQ2Fwd::slot(4 * g + k, 2 * i + pi)];
+            const double a0 = av.x, a1 = av.y;
             acc0 = mma44(a0, bv[g], acc0);
             acc1 = mma44(a1, bv[g], acc1);
         }
         __builtin_amdgcn_wave_barrier();
-        // D lane l: row (l >> 4) of block b -> degree offset 2(4r + (l>>4)) + pi, column col
+        // D lane l: row (l >> 4) of block b -> degree offset 4(l>>4) + 2r + pi, column col
         double *rw = red + ((blk & 1) * nw + wave) * 128;
         rw[lane] = acc0;
         rw[64 + lane] = acc1;
