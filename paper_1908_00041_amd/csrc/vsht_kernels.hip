@@ -1195,7 +1195,7 @@ struct LegArgs {
 };
 
 // Synthesis on the vector unit.  A workgroup takes one order m; each lane
-// carries kAdjPPL ring pairs through the degrees l' = m .. L+1, and each degree
+// carries AdjPPL<real>::n ring pairs through the degrees l' = m .. L+1, and each degree
 // costs, per pair, the recurrence step and eight FMAs (the four complex columns
 // of g, into the even or the odd sum).  a'_{l'} and g[l'] are the same for the
 // whole workgroup: kAdjChunk degrees at a time are staged in LDS with
@@ -1204,7 +1204,12 @@ struct LegArgs {
 // equals the binary64 matrix-core rate and the two share one pipe, so this
 // form gives up nothing to the matrix cores and needs neither the LDS staging
 // of the Legendre values nor products on zero parity blocks.
-constexpr int kAdjPPL = 2;     // ring pairs per lane: every staged value feeds kAdjPPL FMAs
+// Ring pairs per lane: every staged value feeds that many FMAs.  Two in binary64,
+// where the broadcast FMAs share the LDS reads; one in binary32 (twice the waves).
+template <typename real>
+struct AdjPPL {
+    static constexpr int n = sizeof(real) == 8 ? 2 : 1;
+};
 constexpr int kAdjChunk = 32;  // degrees per LDS buffer (two buffers)
 template <typename real>
 struct alignas(16) AdjRow {
@@ -1234,8 +1239,8 @@ __device__ __forceinline__ void fmac_row_bcast8(double (&S)[8], double g, double
     if constexpr (C + 1 < 8) fmac_row_bcast8<K0, C + 1>(S, g, r);
 }
 
-// Degree l' of one row for the kAdjPPL pairs of a lane, into the sums S.
-template <typename real>
+// Degree l' of one row for the pairs of a lane, into the sums S.
+template <typename real, int kAdjPPL = AdjPPL<real>::n>
 __device__ __forceinline__ void adj_row_step(const AdjRow<real> &R, const double (&z)[kAdjPPL],
                                              double (&q1)[kAdjPPL], double (&q2)[kAdjPPL],
                                              real (&S)[kAdjPPL][8]) {
@@ -1251,10 +1256,11 @@ __device__ __forceinline__ void adj_row_step(const AdjRow<real> &R, const double
 }
 
 // One workgroup (any number of waves) of order m; wave w of group `grp` takes
-// ring pairs ((grp * waves + w) * kAdjPPL + u) * 64 + lane.  Every wave takes
+// ring pairs ((grp * waves + w) * P + u) * 64 + lane, P = AdjPPL<real>::n.  Every wave takes
 // part in the staging and its barriers, also one without pairs.
 template <typename real>
 __device__ __forceinline__ void adj_valu_body(const LegArgs<real> &A, int m, int grp, AdjRow<real> *buf) {
+    constexpr int kAdjPPL = AdjPPL<real>::n;
     const int nt = blockDim.x, nw = nt >> 6;
     const int wave = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int L = A.L, NP = A.NP, NPT = A.NPT, Lp1 = L + 1;
@@ -2562,9 +2568,9 @@ static int tiles_of(const Plan &p) { return (pairs_in_tiles(p) + kTileP - 1) / k
 static int bf16_products(int precision) {
     return precision == VSHT_BF16X3 ? 3 : precision == VSHT_BF16X6 ? 6 : 0;
 }
-// Waves of the synthesis: 64 pairs each for the split-bf16 modes, 64 kAdjPPL on the vector unit.
-static int adj_waves(int pairs, int nprod) {
-    const int per = kTileP * (nprod ? 1 : kAdjPPL);
+// Waves of the synthesis: 64 pairs each for the split-bf16 modes, 64 AdjPPL on the vector unit.
+static int adj_waves(int pairs, int nprod, size_t rsz) {
+    const int per = kTileP * (nprod ? 1 : rsz == 8 ? AdjPPL<double>::n : AdjPPL<float>::n);
     return (pairs + per - 1) / per;
 }
 
@@ -2795,7 +2801,7 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
         G.NPT = nf.npv;
         {
             StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
-            const int ntile = adj_waves(nf.npv, nprod);
+            const int ntile = adj_waves(nf.npv, nprod, sizeof(real));
             const int nw = ntile < 4 ? ntile : 4;
             launch_leg_adj<real>(G, dim3((ntile + nw - 1) / nw, p.L + 1), nw, nprod, st);
         }
@@ -2830,7 +2836,7 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
     const LegArgs<real> G = make_leg_adj_args<real>(p);
     {
         StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
-        const int ntile = adj_waves(pairs_in_tiles(p), nprod);
+        const int ntile = adj_waves(pairs_in_tiles(p), nprod, sizeof(real));
         if (ntile > 0) {
             const int nw = ntile < 4 ? ntile : 4;
             launch_leg_adj<real>(G, dim3((ntile + nw - 1) / nw, p.L + 1), nw, nprod, st);
@@ -2990,7 +2996,7 @@ hipError_t batch_configure(BatchState *b, const BatchConfig &cfg) {
     size_t lds_adj = leg_adj_lds(cfg.adj_nw, rsz, nprod);
     for (int i = 0; i < F; ++i) {
         const Plan &p = *b->f[i];
-        const int ntile = adj_waves(pairs_in_tiles(p), nprod);
+        const int ntile = adj_waves(pairs_in_tiles(p), nprod, rsz);
         for (int tg = 0; tg * cfg.adj_nw < ntile; ++tg) {
             const int nt = std::min(cfg.adj_nw, ntile - tg * cfg.adj_nw);
             for (int m = 0; m <= p.L; ++m) items.push_back({{i, tg, m, 0}, (double)(p.L + 2 - m) * nt});
