@@ -1257,7 +1257,10 @@ __device__ __forceinline__ void adj_row_step(const AdjRow<real> &R, const double
 
 // One workgroup (any number of waves) of order m; wave w of group `grp` takes
 // ring pairs ((grp * waves + w) * P + u) * 64 + lane, P = AdjPPL<real>::n.  Every wave takes
-// part in the staging and its barriers, also one without pairs.
+// part in the staging and its barriers, also one without pairs.  Group 0 also
+// forms the equator pair (index NPT, when NP > NPT) from the staged rows: at
+// z = 0 the scaled recurrence gives Q_{m+2k} = (-1)^k Q_m and Q_{m+2k+1} = 0,
+// so its even sum is Lambda_{m,m}(0) sum_k (-1)^k g[m + 2k] and its odd sum 0.
 template <typename real>
 __device__ __forceinline__ void adj_valu_body(const LegArgs<real> &A, int m, int grp, AdjRow<real> *buf) {
     constexpr int kAdjPPL = AdjPPL<real>::n;
@@ -1310,6 +1313,9 @@ __device__ __forceinline__ void adj_valu_body(const LegArgs<real> &A, int m, int
         }
         if ((int)threadIdx.x < kAdjChunk) b[threadIdx.x].a = sa;
     };
+    // equator: wave 0, lane = column (lane & 7) x row group (lane >> 3) of the even rows
+    const bool eq = grp == 0 && NP > NPT && wave == 0;
+    real eacc = 0;
     stage_load(0);
     stage_store(0);
     __syncthreads();
@@ -1317,6 +1323,16 @@ __device__ __forceinline__ void adj_valu_body(const LegArgs<real> &A, int m, int
         if (k + 1 < nchunk) stage_load(k + 1);  // in flight while chunk k is used
         const AdjRow<real> *rows = buf + (k & 1) * kAdjChunk;
         const int nd = min(kAdjChunk, nl - k * kAdjChunk);
+        if (eq) {
+#pragma unroll
+            for (int e = 0; e < kAdjChunk / 16; ++e) {
+                const int d = 2 * ((lane >> 3) + 8 * e);  // even row of the chunk
+                if (d < nd) {
+                    const real v = rows[d].g[lane & 7];
+                    eacc += (((k * kAdjChunk + d) >> 1) & 1) ? -v : v;
+                }
+            }
+        }
         // the chunk starts an even number of degrees after m: row d has the parity of d
         if constexpr (sizeof(real) == 8) {
             // lanes 0-7 of every row of 16 hold g of degree d, lanes 8-15 that of d + 1;
@@ -1370,6 +1386,17 @@ __device__ __forceinline__ void adj_valu_body(const LegArgs<real> &A, int m, int
                 o[c] = E[u][c];
                 o[8 + c] = O[u][c];
             }
+        }
+    }
+    if (eq) {
+        // the eight row groups of each column (lanes c, c + 8, ..., c + 56)
+        eacc += __shfl_xor(eacc, 8);
+        eacc += __shfl_xor(eacc, 16);
+        eacc += __shfl_xor(eacc, 32);
+        if (lane < 8) {
+            real *o = A.PB + ((size_t)m * NP + NPT) * 16;
+            o[lane] = (real)A.seeds[(size_t)m * NP + NPT] * eacc;
+            o[8 + lane] = 0;
         }
     }
 }
@@ -2841,7 +2868,7 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
             const int nw = ntile < 4 ? ntile : 4;
             launch_leg_adj<real>(G, dim3((ntile + nw - 1) / nw, p.L + 1), nw, nprod, st);
         }
-        if (p.eq_ring >= 0)
+        if (p.eq_ring >= 0 && nprod != 0)  // the vector-unit synthesis forms the equator itself
             hipLaunchKernelGGL(k_equator_adj<real>, dim3(p.L + 1), dim3(64), 0, st, G);
     }
     e = hipGetLastError();
@@ -3005,7 +3032,7 @@ hipError_t batch_configure(BatchState *b, const BatchConfig &cfg) {
     emit(BS_LEG_ADJ, cfg.adj_nw, items, lds_adj);
     items.clear();
     for (int i = 0; i < F; ++i)
-        if (b->f[i]->eq_ring >= 0)
+        if (b->f[i]->eq_ring >= 0 && nprod != 0)  // the vector-unit synthesis forms the equator itself
             for (int m = 0; m <= b->f[i]->L; ++m) items.push_back({{i, m, 0, 0}, (double)(b->f[i]->L + 2 - m)});
     emit(BS_EQUATOR, 1, items, 0);
     items.clear();
