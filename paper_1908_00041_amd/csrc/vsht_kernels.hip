@@ -675,6 +675,7 @@ struct RingArgs {
     const double *weights;
     C2<real> *buf;  // RB (forward) or PB (adjoint)
     const RingDesc *rings;
+    const PairDesc *pairs;
     const FftDesc *ffts;
     const double *tw;
     int L;
@@ -682,6 +683,19 @@ struct RingArgs {
     int NR;
     int weighted;
 };
+
+// Workgroup -> ring of the single-field adjoint ring stage.  Workgroups are
+// dealt to the 8 XCDs round robin (b mod 8); with b = 16 (q / 8) + 8 s + q mod 8
+// the northern (s = 0) and southern (s = 1) rings of pair q run on one XCD, 8
+// workgroups apart, so the southern ring finds the pair's Fourier records in
+// that XCD's L2.  Returns -1 for the southern slot of an unpaired ring.
+template <typename real>
+__device__ __forceinline__ int ring_of_block(const RingArgs<real> &A, int b) {
+    const int q = 8 * (b >> 4) + (b & 7), south = (b >> 3) & 1;
+    if (q >= A.NP) return -1;
+    const PairDesc pd = ld_const(A.pairs + q);
+    return south ? pd.rs : pd.rn;
+}
 
 template <typename real, int NT>
 __device__ __forceinline__ void ring_fwd_body(const RingArgs<real> &A, int r, unsigned char *smem_raw) {
@@ -801,7 +815,9 @@ __global__ __launch_bounds__(NT, 2) void k_ring_fwd(RingArgs<real> A) {
 template <typename real, int NT>
 __global__ __launch_bounds__(NT, 2) void k_ring_adj(RingArgs<real> A) {
     extern __shared__ unsigned char smem_raw[];
-    ring_adj_body<real, NT>(A, blockIdx.x, smem_raw);
+    const int r = ring_of_block(A, blockIdx.x);
+    if (r < 0) return;
+    ring_adj_body<real, NT>(A, r, smem_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -2580,6 +2596,7 @@ static RingArgs<real> make_ring_args(const Plan &p, const void *Tin, void *Tout,
     R.weights = p.d_weights;
     R.buf = static_cast<C2<real> *>(p.d_pb);
     R.rings = p.d_rings;
+    R.pairs = p.d_pairs;
     R.ffts = p.d_ffts;
     R.tw = p.d_tw;
     R.L = p.L;
@@ -2877,11 +2894,12 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
     const RingArgs<real> R = make_ring_args<real>(p, nullptr, T, weighted);
     {
         StageScope sc(p, VSHT_STAGE_RING_ADJ, st);
+        const dim3 grid((unsigned)(16 * ((p.n_pairs + 7) / 8)));  // ring_of_block's layout
         if (p.ring_nt_min == kRingNTSmall && p.max_fft_len <= kMaxLenSmallRing)
-            hipLaunchKernelGGL((k_ring_adj<real, kRingNTSmall>), dim3((unsigned)p.n_rings), dim3(kRingNTSmall),
+            hipLaunchKernelGGL((k_ring_adj<real, kRingNTSmall>), grid, dim3(kRingNTSmall),
                                ring_lds_bytes(p, sizeof(real)), st, R);
         else
-            hipLaunchKernelGGL((k_ring_adj<real, kRingNT>), dim3((unsigned)p.n_rings), dim3(kRingNT),
+            hipLaunchKernelGGL((k_ring_adj<real, kRingNT>), grid, dim3(kRingNT),
                                ring_lds_bytes(p, sizeof(real)), st, R);
     }
     return hipGetLastError();
