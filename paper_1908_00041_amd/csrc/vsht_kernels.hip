@@ -1491,29 +1491,37 @@ __global__ __launch_bounds__(256, 4) void k_leg_adj(LegArgs<real> A) {
 // ---------------------------------------------------------------------------
 template <typename real>
 __device__ __forceinline__ void equator_adj_body(const LegArgs<real> &A, int m) {
+    // 256 threads: column c = t & 7 of row groups t >> 3 (32 of them), four rows in
+    // flight per thread; the 32 partial sums of a column meet in the wave (shuffles)
+    // and across the four waves (LDS)
+    __shared__ real part[4][8];
     const int L = A.L, NP = A.NP;
-    const int lane = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t t0 = tri_offset(L, m);
     const real *g = A.FG + t0 * 8;  // row l' = m + i
-    const int c = lane & 7, lg = lane >> 3;  // 8 lanes per column group
+    const int c = t & 7, rg = t >> 3;
+    const int nk = (L + 1 - m) / 2 + 1;  // even rows 2 kk <= L + 1 - m
     real acc = 0;
-    for (int kk = lg; 2 * kk <= L + 1 - m; kk += 8) {
+#pragma unroll 4
+    for (int kk = rg; kk < nk; kk += 32) {
         const real v = g[(int64_t)(2 * kk) * 8 + c];
         acc += (kk & 1) ? -v : v;
     }
-    // sum the 8 partial sums of each column (lanes c, c+8, ..., c+56)
     acc += __shfl_xor(acc, 8);
     acc += __shfl_xor(acc, 16);
     acc += __shfl_xor(acc, 32);
-    real *o = A.PB + ((size_t)m * NP + A.NPT) * 16;
-    if (lane < 8) {
-        o[c] = (real)A.seeds[(size_t)m * NP + A.NPT] * acc;
-        o[8 + c] = 0;
+    if (lane < 8) part[wave][lane] = acc;
+    __syncthreads();
+    if (t < 8) {
+        const real sum = (part[0][t] + part[1][t]) + (part[2][t] + part[3][t]);
+        real *o = A.PB + ((size_t)m * NP + A.NPT) * 16;
+        o[t] = (real)A.seeds[(size_t)m * NP + A.NPT] * sum;
+        o[8 + t] = 0;
     }
 }
 
 template <typename real>
-__global__ __launch_bounds__(64) void k_equator_adj(LegArgs<real> A) {
+__global__ __launch_bounds__(256) void k_equator_adj(LegArgs<real> A) {
     equator_adj_body(A, blockIdx.x);
 }
 
@@ -2571,7 +2579,7 @@ __global__ __launch_bounds__(256, 4) void kb_leg_adj(const LegArgs<real> *__rest
 }
 
 template <typename real>
-__global__ __launch_bounds__(64) void kb_equator_adj(const LegArgs<real> *__restrict__ args,
+__global__ __launch_bounds__(256) void kb_equator_adj(const LegArgs<real> *__restrict__ args,
                                                      const WorkItem *__restrict__ work,
                                                      unsigned long long *) {
     const WorkItem w = ld_const(work + blockIdx.x);
@@ -2886,7 +2894,7 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
             launch_leg_adj<real>(G, dim3((ntile + nw - 1) / nw, p.L + 1), nw, nprod, st);
         }
         if (p.eq_ring >= 0 && nprod != 0)  // the vector-unit synthesis forms the equator itself
-            hipLaunchKernelGGL(k_equator_adj<real>, dim3(p.L + 1), dim3(64), 0, st, G);
+            hipLaunchKernelGGL(k_equator_adj<real>, dim3(p.L + 1), dim3(256), 0, st, G);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -3052,7 +3060,7 @@ hipError_t batch_configure(BatchState *b, const BatchConfig &cfg) {
     for (int i = 0; i < F; ++i)
         if (b->f[i]->eq_ring >= 0 && nprod != 0)  // the vector-unit synthesis forms the equator itself
             for (int m = 0; m <= b->f[i]->L; ++m) items.push_back({{i, m, 0, 0}, (double)(b->f[i]->L + 2 - m)});
-    emit(BS_EQUATOR, 1, items, 0);
+    emit(BS_EQUATOR, 4, items, 0);
     items.clear();
     // ring stages: one launch per class of stored DFT length (its LDS size) and
     // workgroup width; fields whose length exceeds the narrow width's limit use 512
@@ -3181,7 +3189,7 @@ static hipError_t batch_launch_impl(const BatchState *b, int dirs, hipStream_t s
                                    static_cast<const LegArgs<real> *>(b->d_ladj), w, stamp);
                 break;
             case BS_EQUATOR:
-                hipLaunchKernelGGL(kb_equator_adj<real>, grid, dim3(64), 0, st,
+                hipLaunchKernelGGL(kb_equator_adj<real>, grid, dim3(256), 0, st,
                                    static_cast<const LegArgs<real> *>(b->d_ladj), w, stamp);
                 break;
             case BS_RING_ADJ:
