@@ -133,6 +133,26 @@ def test_ring_grid_variants_fp64(torch, vsht, orc, grid):
     assert rel_l2(np.concatenate([ga, gb]), np.concatenate([a_ref, b_ref])) < FP64_TOL
 
 
+@pytest.mark.parametrize("L,precision,tol", [(12, "fp64", FP64_TOL), (40, "fp64", FP64_TOL),
+                                             (40, "fp32", FP32_TOL)])
+def test_reduced_ring_grid(torch, vsht, orc, L, precision, tol):
+    """Rings of unequal length (shorter than 2L+1 near the poles, so Fourier bins
+    alias) and alternating phase: the ring path against the oracle's direct sums."""
+    print_case("reduced rings", L, precision)
+    xyz, w = vi.reduced_gl_grid(L)
+    plan = vsht.Plan(L, xyz, w, precision=precision)
+    assert plan.kind == "rings"
+    a, b = vi.random_coeffs(L, 11)
+    T = run_adjoint(torch, plan, a, b)
+    e_adj = rel_l2(T, orc.adjoint(L, a, b, xyz))
+    Tr = vi.random_field(len(w), 12)
+    ga, gb = run_forward(torch, plan, Tr)
+    a_ref, b_ref = orc.forward(L, xyz, w, Tr)
+    e_fwd = rel_l2(np.concatenate([ga, gb]), np.concatenate([a_ref, b_ref]))
+    print("reduced rings L=%d %s adjoint %.3e forward %.3e" % (L, precision, e_adj, e_fwd))
+    assert e_adj < tol and e_fwd < tol
+
+
 def test_scattered_adjoint_fp64(torch, vsht, orc):
     L = 24
     xyz, _ = vi.uniform_points(700, 2)

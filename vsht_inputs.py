@@ -96,6 +96,23 @@ def gl_grid(L, n_theta=None, n_phi=None):
     return xyz.reshape(-1, 3), w
 
 
+def reduced_gl_grid(L, min_phi=4):
+    """Reduced Gauss-Legendre iso-latitude grid: L + 1 GL rings, ring r with
+    n_r = max(min_phi, ceil((2L + 2) sin(theta_r))) equispaced longitudes and a
+    first longitude pi / n_r on every other ring (rings of unequal length and
+    phase, as in reduced and HEALPix-like grids).  Weights are the GL weight of
+    the ring times 2 pi / n_r.  Returns (xyz (N,3), w (N,)) as float64."""
+    z, wz = gl_nodes(L + 1)
+    s = np.sqrt((1.0 - z) * (1.0 + z))
+    pts, wts = [], []
+    for r in range(L + 1):
+        n = max(min_phi, int(np.ceil((2 * L + 2) * s[r])))
+        phi = 2.0 * np.pi * np.arange(n) / n + (np.pi / n if r % 2 else 0.0)
+        pts.append(np.stack([s[r] * np.cos(phi), s[r] * np.sin(phi), np.full(n, z[r])], axis=-1))
+        wts.append(np.full(n, wz[r] * 2.0 * np.pi / n))
+    return np.concatenate(pts), np.concatenate(wts)
+
+
 def uniform_points(M, seed):
     """M points uniform on S^2 and equal weights 4 pi / M."""
     rng = np.random.default_rng(seed)
