@@ -149,6 +149,22 @@ vsht_status vsht_forward_unweighted(vsht_plan_t plan, const void *T, void *a, vo
  * (device, n x 3) at every point of the plan, in the plan's point order. */
 vsht_status vsht_adjoint(vsht_plan_t plan, const void *a, const void *b, void *T, void *stream);
 
+/* Scalar transforms on ring plans, with the same stages (scalar coefficients
+ * f_{l,m}, 0 <= l <= L, |m| <= l, at index l^2 + l + m; vsht_num_sht_coeffs(L)
+ * = (L+1)^2 of them; complex128 for VSHT_FP64, complex64 otherwise).
+ *   vsht_sht_forward: the discrete forward scalar transform (FwdSHT, Section
+ *     4.1, eq. (Flm)) f (device, n values, the plan's point order) -> flm
+ *     (device), f_{l,m} = sum_k w_k f_k Y_{l,m}(x_k)^*.  VSHT_ENOWEIGHTS without
+ *     weights.
+ *   vsht_sht_adjoint: the adjoint scalar transform (AdjSHT, Section 4.2, eq.
+ *     (SLscalar)) flm (device) -> f (device, n values), f_k = S_L(f_{l,m})(x_k).
+ * Y_{l,m} is the orthonormal spherical harmonic with the Condon-Shortley phase.
+ * VSHT_EUNSUPPORTED on scattered plans.  The workspace is the plan's (calls
+ * on one plan are serialised by their stream). */
+int64_t vsht_num_sht_coeffs(int L);
+vsht_status vsht_sht_forward(vsht_plan_t plan, const void *f, void *flm, void *stream);
+vsht_status vsht_sht_adjoint(vsht_plan_t plan, const void *flm, void *f, void *stream);
+
 /* Flags of the *_many calls. */
 enum {
     VSHT_UNIT_WEIGHTS = 1, /* forward: unit weights (S^H, as vsht_forward_unweighted) */

@@ -23,7 +23,8 @@ EXPORTED = ("vsht_num_coeffs", "vsht_plan", "vsht_forward", "vsht_forward_unweig
             "vsht_last_error", "vsht_set_stage_timing", "vsht_get_stage_times",
             "vsht_forward_many", "vsht_adjoint_many", "vsht_plan_batch", "vsht_batch_adjoint",
             "vsht_batch_forward", "vsht_batch_roundtrip", "vsht_batch_set_config",
-            "vsht_batch_get_config", "vsht_batch_autotune", "vsht_batch_field_times")
+            "vsht_batch_get_config", "vsht_batch_autotune", "vsht_batch_field_times",
+            "vsht_num_sht_coeffs", "vsht_sht_forward", "vsht_sht_adjoint")
 VSHT_UNIT_WEIGHTS, VSHT_TIMES_WEIGHTS = 1, 2
 STAGES = ("ring_fwd", "leg_fwd", "recombine", "prep", "leg_adj", "ring_adj", "scattered")
 
@@ -71,6 +72,11 @@ def load_library(path=LIB_PATH):
         getattr(lib, name).restype = ci
     lib.vsht_adjoint.argtypes = [vp, vp, vp, vp, vp]
     lib.vsht_adjoint.restype = ci
+    lib.vsht_num_sht_coeffs.argtypes = [ci]
+    lib.vsht_num_sht_coeffs.restype = i64
+    for name in ("vsht_sht_forward", "vsht_sht_adjoint"):
+        getattr(lib, name).argtypes = [vp, vp, vp, vp]
+        getattr(lib, name).restype = ci
     for name in ("vsht_forward_many", "vsht_adjoint_many"):
         getattr(lib, name).argtypes = [vp, i64, vp, vp, vp, ci, vp]
         getattr(lib, name).restype = ci
@@ -136,6 +142,18 @@ def vsht_forward_unweighted(plan, T_ptr, a_ptr, b_ptr, stream):
 
 def vsht_adjoint(plan, a_ptr, b_ptr, T_ptr, stream):
     return load_library().vsht_adjoint(plan, a_ptr, b_ptr, T_ptr, stream)
+
+
+def vsht_num_sht_coeffs(L):
+    return load_library().vsht_num_sht_coeffs(L)
+
+
+def vsht_sht_forward(plan, f_ptr, flm_ptr, stream):
+    return load_library().vsht_sht_forward(plan, f_ptr, flm_ptr, stream)
+
+
+def vsht_sht_adjoint(plan, flm_ptr, f_ptr, stream):
+    return load_library().vsht_sht_adjoint(plan, flm_ptr, f_ptr, stream)
 
 
 def vsht_forward_many(plan, count, T_ptr, a_ptr, b_ptr, flags, stream):
@@ -245,6 +263,26 @@ class Plan:
         _raise_for(vsht_adjoint(self._h, a.data_ptr(), b.data_ptr(), T.data_ptr(), self._stream()),
                    "vsht_adjoint")
         return T
+
+    def sht_forward(self, f, flm=None):
+        """Scalar forward transform (ring plans with weights): f (n,) -> flm ((L+1)^2,)."""
+        torch = _torch()
+        f = self._check(f, (self.n,), "f")
+        if flm is None:
+            flm = torch.empty(vsht_num_sht_coeffs(self.L), dtype=self.dtype, device=self.device)
+        _raise_for(vsht_sht_forward(self._h, f.data_ptr(), flm.data_ptr(), self._stream()),
+                   "vsht_sht_forward")
+        return flm
+
+    def sht_adjoint(self, flm, f=None):
+        """Scalar adjoint transform (ring plans): flm ((L+1)^2,) -> f (n,)."""
+        torch = _torch()
+        flm = self._check(flm, (vsht_num_sht_coeffs(self.L),), "flm")
+        if f is None:
+            f = torch.empty(self.n, dtype=self.dtype, device=self.device)
+        _raise_for(vsht_sht_adjoint(self._h, flm.data_ptr(), f.data_ptr(), self._stream()),
+                   "vsht_sht_adjoint")
+        return f
 
     def _check_batch(self, t, tail, name):
         torch = _torch()

@@ -760,6 +760,29 @@ vsht_status vsht_adjoint(vsht_plan_t plan, const void *a, const void *b, void *T
     return e == hipSuccess ? VSHT_OK : hip_fail(e, "adjoint launch");
 }
 
+int64_t vsht_num_sht_coeffs(int L) { return L >= 0 ? (int64_t)(L + 1) * (L + 1) : 0; }
+
+vsht_status vsht_sht_forward(vsht_plan_t plan, const void *f, void *flm, void *stream) {
+    vsht_status s = check_call(plan, f, flm, flm);
+    if (s != VSHT_OK) return s;
+    const Plan &P = plan->p;
+    if (P.kind != VSHT_PLAN_RINGS) return fail(VSHT_EUNSUPPORTED, "scalar transforms need a ring plan");
+    if (!P.has_weights) return fail(VSHT_ENOWEIGHTS, "forward needs a plan created with weights");
+    DeviceGuard guard(P.device);
+    hipError_t e = launch_sht_forward(P, f, flm, (hipStream_t)stream);
+    return e == hipSuccess ? VSHT_OK : hip_fail(e, "scalar forward launch");
+}
+
+vsht_status vsht_sht_adjoint(vsht_plan_t plan, const void *flm, void *f, void *stream) {
+    vsht_status s = check_call(plan, flm, flm, f);
+    if (s != VSHT_OK) return s;
+    const Plan &P = plan->p;
+    if (P.kind != VSHT_PLAN_RINGS) return fail(VSHT_EUNSUPPORTED, "scalar transforms need a ring plan");
+    DeviceGuard guard(P.device);
+    hipError_t e = launch_sht_adjoint(P, flm, f, (hipStream_t)stream);
+    return e == hipSuccess ? VSHT_OK : hip_fail(e, "scalar adjoint launch");
+}
+
 static size_t complex_bytes(const Plan &P) { return P.precision == VSHT_FP64 ? 16 : 8; }
 
 vsht_status vsht_forward_many(vsht_plan_t plan, int64_t count, const void *T, void *a, void *b,

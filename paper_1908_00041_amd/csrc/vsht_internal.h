@@ -211,6 +211,8 @@ hipError_t launch_forward(const Plan &p, const void *T, void *a, void *b, bool w
                           hipStream_t st);
 hipError_t launch_adjoint(const Plan &p, const void *a, const void *b, void *T, bool weighted,
                           hipStream_t st);
+hipError_t launch_sht_forward(const Plan &p, const void *f, void *flm, hipStream_t st);
+hipError_t launch_sht_adjoint(const Plan &p, const void *flm, void *f, hipStream_t st);
 hipError_t launch_seed_kernel(const double *pair_s, int NP, int L, double *seeds, hipStream_t st);
 hipError_t set_kernel_attributes();
 

@@ -682,6 +682,7 @@ struct RingArgs {
     int NP;
     int NR;
     int weighted;
+    int scalar;  // scalar transforms: one complex value f per point, T_theta = s f, T_phi = 0
 };
 
 // Workgroup -> ring of the single-field adjoint ring stage.  Workgroups are
@@ -717,13 +718,21 @@ __device__ __forceinline__ void ring_fwd_body(const RingArgs<real> &A, int r, un
         const int64_t k = rd.offset + j;
         real w = 1;
         if (A.weighted) w = (real)(rd.uniform_w ? rd.w : A.weights[k]);
-        const C2<real> t1 = A.Tin[3 * k], t2 = A.Tin[3 * k + 1], t3 = A.Tin[3 * k + 2];
         const real z = (real)rd.z, s = (real)rd.s;
         C2<real> th, ph;
-        th.x = w * (z * (c * t1.x + sn * t2.x) - s * t3.x);
-        th.y = w * (z * (c * t1.y + sn * t2.y) - s * t3.y);
-        ph.x = w * (c * t2.x - sn * t1.x);
-        ph.y = w * (c * t2.y - sn * t1.y);
+        if (A.scalar) {
+            // the scalar analysis of f is the theta analysis of T_theta = s f (the
+            // output stage divides by s again)
+            const C2<real> f = A.Tin[k];
+            th = {w * s * f.x, w * s * f.y};
+            ph = {0, 0};
+        } else {
+            const C2<real> t1 = A.Tin[3 * k], t2 = A.Tin[3 * k + 1], t3 = A.Tin[3 * k + 2];
+            th.x = w * (z * (c * t1.x + sn * t2.x) - s * t3.x);
+            th.y = w * (z * (c * t1.y + sn * t2.y) - s * t3.y);
+            ph.x = w * (c * t2.x - sn * t1.x);
+            ph.y = w * (c * t2.y - sn * t1.y);
+        }
         buf[j] = th;
         buf[n2 + j] = ph;
     }
@@ -799,6 +808,10 @@ __device__ __forceinline__ void ring_adj_body(const RingArgs<real> &A, int r, un
         if (A.weighted) {  // W S: the Hermitian transpose of the weighted analysis
             const real w = (real)(rd.uniform_w ? rd.w : A.weights[k]);
             th.x *= w; th.y *= w; ph.x *= w; ph.y *= w;
+        }
+        if (A.scalar) {  // f = s T_theta: the synthesised sum before the division by s
+            A.Tout[k] = {s * th.x, s * th.y};
+            continue;
         }
         A.Tout[3 * k] = {z * c * th.x - sn * ph.x, z * c * th.y - sn * ph.y};
         A.Tout[3 * k + 1] = {z * sn * th.x + c * ph.x, z * sn * th.y + c * ph.y};
@@ -2587,6 +2600,66 @@ __global__ __launch_bounds__(256) void kb_equator_adj(const LegArgs<real> *__res
     equator_adj_body(A, w.x);
 }
 
+// ---------------------------------------------------------------------------
+// Scalar transforms (FwdSHT and AdjSHT) on the same stages.  Lambda_{l,m} is
+// normalised so that Y_{l,m} = Lambda_{l,m} e^{i m phi} (the 1/sqrt(4 pi) and the
+// Condon-Shortley phase are in the seeds), and Y_{l,-m} = (-1)^m conj(Y_{l,m}).  The
+// theta column of the spin-frame analysis of T_theta = s f is then
+// F_{l,+m} = sum_k w_k f_k Lambda_{l,m} e^{-i m phi_k} = f_{l,m}, and its -m slot holds
+// (-1)^m f_{l,-m}; the synthesis from g^th = f_{l,m} (and g^ph = 0) gives
+// s T_theta = S_L(f).  Coefficients f_{l,m}, 0 <= l <= L, |m| <= l, at index l^2 + l + m.
+// ---------------------------------------------------------------------------
+template <typename real>
+struct ShtArgs {
+    const C2<real> *flm_in;
+    C2<real> *flm_out;
+    C2<real> *FG;           // [tri][4]
+    const double *cscale;   // [tri] c_{l',m}
+    int L;
+};
+
+// one thread per triangle row (m, l'), l' = m .. L+1: FG from f_{l',+-m}
+template <typename real>
+__global__ __launch_bounds__(256) void k_sht_coef_to_fg(ShtArgs<real> A) {
+    const int L = A.L;
+    const int m = blockIdx.y;
+    const int lp = m + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (m > L || lp > L + 1) return;
+    const int64_t ti = tri_offset(L, m) + lp - m;
+    C2<real> gp = {0, 0}, gm = {0, 0};
+    if (lp <= L) {
+        const real sc = (real)A.cscale[ti];
+        const C2<real> fp = A.flm_in[(int64_t)lp * lp + lp + m];
+        gp = {sc * fp.x, sc * fp.y};
+        if (m > 0) {
+            const C2<real> fm = A.flm_in[(int64_t)lp * lp + lp - m];
+            const real sg = (m & 1) ? -sc : sc;
+            gm = {sg * fm.x, sg * fm.y};
+        }
+    }
+    C2<real> *o = A.FG + ti * 4;
+    o[0] = gp;
+    o[1] = {0, 0};
+    o[2] = gm;
+    o[3] = {0, 0};
+}
+
+// one thread per (m, l), l = m .. L: f_{l,+-m} from the theta columns of FG
+template <typename real>
+__global__ __launch_bounds__(256) void k_sht_fg_to_coef(ShtArgs<real> A) {
+    const int L = A.L;
+    const int m = blockIdx.y;
+    const int l = m + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (m > L || l > L) return;
+    const int64_t ti = tri_offset(L, m) + l - m;
+    const C2<real> *r = A.FG + ti * 4;
+    A.flm_out[(int64_t)l * l + l + m] = r[0];
+    if (m > 0) {
+        const C2<real> v = r[2];
+        A.flm_out[(int64_t)l * l + l - m] = (m & 1) ? C2<real>{-v.x, -v.y} : v;
+    }
+}
+
 // ===========================================================================
 // launchers
 // ===========================================================================
@@ -2611,6 +2684,7 @@ static RingArgs<real> make_ring_args(const Plan &p, const void *Tin, void *Tout,
     R.NP = (int)p.n_pairs;
     R.NR = (int)p.n_rings;
     R.weighted = weighted ? 1 : 0;
+    R.scalar = 0;
     return R;
 }
 
@@ -2923,6 +2997,100 @@ hipError_t launch_adjoint(const Plan &p, const void *a, const void *b, void *T, 
                           hipStream_t st) {
     if (p.precision == VSHT_FP64) return adjoint_impl<double>(p, a, b, T, weighted, st);
     return adjoint_impl<float>(p, a, b, T, weighted, st);
+}
+
+// Scalar transforms on ring plans: the ring and Legendre stages of the vector
+// path with the scalar ring input/output and the coefficient kernels above.
+template <typename real>
+static hipError_t sht_forward_impl(const Plan &p, const void *f, void *flm, hipStream_t st) {
+    const int nprod = bf16_products(p.precision);
+    RingArgs<real> R = make_ring_args<real>(p, f, nullptr, true);
+    R.scalar = 1;
+    {
+        StageScope sc(p, VSHT_STAGE_RING_FWD, st);
+        if (p.ring_nt_min == kRingNTSmall && p.max_fft_len <= kMaxLenSmallRing)
+            hipLaunchKernelGGL((k_ring_fwd<real, kRingNTSmall>), dim3((unsigned)p.n_rings), dim3(kRingNTSmall),
+                               ring_lds_bytes(p, sizeof(real)), st, R);
+        else
+            hipLaunchKernelGGL((k_ring_fwd<real, kRingNT>), dim3((unsigned)p.n_rings), dim3(kRingNT),
+                               ring_lds_bytes(p, sizeof(real)), st, R);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    {
+        const int ntile = tiles_of(p);
+        const int ngroup = ntile > 16 ? (ntile + 15) / 16 : 1;
+        const int nw = ntile > 0 ? (ntile + ngroup - 1) / ngroup : 1;
+        const LegFwdArgs<real> G = make_leg_fwd_args<real>(p, ngroup > 1 ? 1 : 0);
+        StageScope sc(p, VSHT_STAGE_LEG_FWD, st);
+        if (G.atomic) {
+            e = hipMemsetAsync(p.d_fg, 0, (size_t)p.tri_size * 8 * sizeof(real), st);
+            if (e != hipSuccess) return e;
+        }
+        launch_leg_fwd<real>(G, dim3(p.L + 1, ngroup), nw, nprod, st);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ShtArgs<real> S{};
+    S.flm_out = static_cast<C2<real> *>(flm);
+    S.FG = static_cast<C2<real> *>(p.d_fg);
+    S.cscale = p.d_cscale;
+    S.L = p.L;
+    StageScope sc(p, VSHT_STAGE_RECOMBINE, st);
+    hipLaunchKernelGGL(k_sht_fg_to_coef<real>, dim3((p.L + 1 + 255) / 256, p.L + 1), dim3(256), 0, st, S);
+    return hipGetLastError();
+}
+
+template <typename real>
+static hipError_t sht_adjoint_impl(const Plan &p, const void *flm, void *f, hipStream_t st) {
+    const int nprod = bf16_products(p.precision);
+    ShtArgs<real> S{};
+    S.flm_in = static_cast<const C2<real> *>(flm);
+    S.FG = static_cast<C2<real> *>(p.d_fg);
+    S.cscale = p.d_cscale;
+    S.L = p.L;
+    {
+        StageScope sc(p, VSHT_STAGE_PREP, st);
+        hipLaunchKernelGGL(k_sht_coef_to_fg<real>, dim3((p.L + 2 + 255) / 256, p.L + 1), dim3(256), 0, st, S);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const LegArgs<real> G = make_leg_adj_args<real>(p);
+    {
+        StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
+        const int ntile = adj_waves(pairs_in_tiles(p), nprod, sizeof(real));
+        if (ntile > 0) {
+            const int nw = ntile < 4 ? ntile : 4;
+            launch_leg_adj<real>(G, dim3((ntile + nw - 1) / nw, p.L + 1), nw, nprod, st);
+        }
+        if (p.eq_ring >= 0 && nprod != 0)
+            hipLaunchKernelGGL(k_equator_adj<real>, dim3(p.L + 1), dim3(256), 0, st, G);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    RingArgs<real> R = make_ring_args<real>(p, nullptr, f, false);
+    R.scalar = 1;
+    {
+        StageScope sc(p, VSHT_STAGE_RING_ADJ, st);
+        const dim3 grid((unsigned)(16 * ((p.n_pairs + 7) / 8)));  // ring_of_block's layout
+        if (p.ring_nt_min == kRingNTSmall && p.max_fft_len <= kMaxLenSmallRing)
+            hipLaunchKernelGGL((k_ring_adj<real, kRingNTSmall>), grid, dim3(kRingNTSmall),
+                               ring_lds_bytes(p, sizeof(real)), st, R);
+        else
+            hipLaunchKernelGGL((k_ring_adj<real, kRingNT>), grid, dim3(kRingNT),
+                               ring_lds_bytes(p, sizeof(real)), st, R);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sht_forward(const Plan &p, const void *f, void *flm, hipStream_t st) {
+    if (p.precision == VSHT_FP64) return sht_forward_impl<double>(p, f, flm, st);
+    return sht_forward_impl<float>(p, f, flm, st);
+}
+
+hipError_t launch_sht_adjoint(const Plan &p, const void *flm, void *f, hipStream_t st) {
+    if (p.precision == VSHT_FP64) return sht_adjoint_impl<double>(p, flm, f, st);
+    return sht_adjoint_impl<float>(p, flm, f, st);
 }
 
 // ===========================================================================
