@@ -28,6 +28,7 @@ import numpy as np
 import pytest
 from scipy.special import sph_harm_y
 
+import cg_routes
 import vsht_inputs as vi
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -88,14 +89,7 @@ def test_sph_harm_poles(orc):
 # --------------------------------------------------------------------------
 # vector harmonics: brute force from sympy CG + scipy Y
 # --------------------------------------------------------------------------
-def _cg(j1, m1, j2, m2, J, M):
-    """Standard <j1 m1 j2 m2 | J M> (sympy, exact), zero outside its range."""
-    from sympy.physics.wigner import clebsch_gordan
-    if j1 < 0 or J < 0 or abs(m1) > j1 or abs(m2) > j2 or abs(M) > J or m1 + m2 != M:
-        return 0.0
-    if not (abs(j1 - j2) <= J <= j1 + j2):
-        return 0.0
-    return float(clebsch_gordan(j1, j2, J, m1, m2, M))
+_cg = cg_routes.cg
 
 
 def test_paper_cg_definition_is_standard():
@@ -280,14 +274,6 @@ def test_forward_subset_matches_full(orc):
 # --------------------------------------------------------------------------
 # Theorems 1 and 2 as an independent route
 # --------------------------------------------------------------------------
-def _c(l):
-    return math.sqrt((l + 1) / (2 * l + 1)) if l >= 0 else 0.0
-
-
-def _d(l):
-    return math.sqrt(l / (2 * l + 1)) if l >= 0 else 0.0
-
-
 def scalar_forward(xyz, w, f, Lmax):
     """eq. (Flm): F_{l,m}(f) = sum_k w_k f_k Y_{l,m}(x_k)^*, via scipy."""
     F = {}
@@ -299,80 +285,19 @@ def scalar_forward(xyz, w, f, Lmax):
 
 def theorem1_forward(L, xyz, w, T):
     """Forward VSHT by Theorem 1 (eq. almblmviaFlm)."""
-    F1 = scalar_forward(xyz, w, T[:, 0], L + 1)
-    F2 = scalar_forward(xyz, w, T[:, 1], L + 1)
-    F3 = scalar_forward(xyz, w, T[:, 2], L + 1)
-    g = lambda F, l, m: F.get((l, m), 0.0) if l >= 0 and abs(m) <= l else 0.0
-    xi1 = lambda l, m: _c(l + 1) * _cg(l, m, 1, 1, l + 1, m + 1)
-    xi2 = lambda l, m: _d(l - 1) * _cg(l, m, 1, 1, l - 1, m + 1)
-    xi3 = lambda l, m: _c(l + 1) * _cg(l, m, 1, -1, l + 1, m - 1)
-    xi4 = lambda l, m: _d(l - 1) * _cg(l, m, 1, -1, l - 1, m - 1)
-    xi5 = lambda l, m: _c(l + 1) * _cg(l, m, 1, 0, l + 1, m)
-    xi6 = lambda l, m: _d(l - 1) * _cg(l, m, 1, 0, l - 1, m)
-    mu1 = lambda l, m: _cg(l, m, 1, 1, l, m + 1)
-    mu2 = lambda l, m: _cg(l, m, 1, 0, l, m)
-    mu3 = lambda l, m: _cg(l, m, 1, -1, l, m - 1)
-    K = L * (L + 2)
-    a = np.zeros(K, np.complex128)
-    b = np.zeros(K, np.complex128)
-    r2 = math.sqrt(2.0)
-    for l in range(1, L + 1):
-        for m in range(-l, l + 1):
-            j = l * l + l + m - 1
-            a[j] = (1 / r2) * (
-                xi1(l - 1, m - 1) * (-g(F1, l - 1, m - 1) + 1j * g(F2, l - 1, m - 1))
-                + xi2(l + 1, m - 1) * (-g(F1, l + 1, m - 1) + 1j * g(F2, l + 1, m - 1))
-                + xi3(l - 1, m + 1) * (g(F1, l - 1, m + 1) + 1j * g(F2, l - 1, m + 1))
-                + xi4(l + 1, m + 1) * (g(F1, l + 1, m + 1) + 1j * g(F2, l + 1, m + 1))) \
-                + xi5(l - 1, m) * g(F3, l - 1, m) + xi6(l + 1, m) * g(F3, l + 1, m)
-            b[j] = -(1j / r2) * (
-                mu1(l, m - 1) * (-g(F1, l, m - 1) + 1j * g(F2, l, m - 1))
-                + mu3(l, m + 1) * (g(F1, l, m + 1) + 1j * g(F2, l, m + 1))) \
-                - 1j * mu2(l, m) * g(F3, l, m)
-    return a, b
+    Fs = [scalar_forward(xyz, w, T[:, k], L + 1) for k in range(3)]
+    gs = [lambda l, m, F=F: F.get((l, m), 0.0) if l >= 0 and abs(m) <= l else 0.0 for F in Fs]
+    a, b = cg_routes.theorem1_combine(L, *gs)
+    return np.array(a, np.complex128), np.array(b, np.complex128)
 
 
 def theorem2_adjoint(L, a, b, xyz, literal_zero_cases=False):
     """Adjoint VSHT by Theorem 2 (eq. SLvecviascal) with nu, eta of
-    eq. (nulm1), (nulm2), (etalm).  Coefficients outside 1 <= l <= L, |m| <= l
-    are zero.  With literal_zero_cases the printed zero cases of nu^(2) and
-    nu^(4) are applied as written."""
-    A = lambda l, m: a[l * l + l + m - 1] if 1 <= l <= L and abs(m) <= l else 0.0
-    B = lambda l, m: b[l * l + l + m - 1] if 1 <= l <= L and abs(m) <= l else 0.0
-    comps = [np.zeros(len(xyz), np.complex128) for _ in range(3)]
-    r2 = math.sqrt(2.0)
-    for l in range(0, L + 2):
-        for m in range(-l, l + 1):
-            Y = scipy_Y(l, m, xyz)
-            nu = [0.0] * 7
-            if l <= L - 1:
-                p = A(l + 1, m + 1) * _cg(l, m, 1, 1, l + 1, m + 1)
-                q = A(l + 1, m - 1) * _cg(l, m, 1, -1, l + 1, m - 1)
-                nu[1] = _c(l + 1) * (p - q)
-                nu[3] = 1j * _c(l + 1) * (p + q)
-                nu[5] = A(l + 1, m) * _c(l + 1) * _cg(l, m, 1, 0, l + 1, m)
-            if 2 <= l <= L + 1:
-                p = A(l - 1, m + 1) * _cg(l, m, 1, 1, l - 1, m + 1)
-                q = A(l - 1, m - 1) * _cg(l, m, 1, -1, l - 1, m - 1)
-                nu[2] = _d(l - 1) * (p - q)
-                nu[4] = 1j * _d(l - 1) * (p + q)
-                nu[6] = A(l - 1, m) * _d(l - 1) * _cg(l, m, 1, 0, l - 1, m)
-                if literal_zero_cases:
-                    if abs(m) in (l - 1, l):
-                        nu[2] = 0.0
-                    if abs(m) in (l - 2, l - 1):
-                        nu[4] = 0.0
-            eta1 = eta2 = eta3 = 0.0
-            if 1 <= l <= L:
-                p = B(l, m + 1) * _cg(l, m, 1, 1, l, m + 1)
-                q = B(l, m - 1) * _cg(l, m, 1, -1, l, m - 1)
-                eta1 = 1j * (p - q)
-                eta2 = p + q
-                eta3 = 1j * B(l, m) * _cg(l, m, 1, 0, l, m)
-            comps[0] += -(1 / r2) * (nu[1] + nu[2] + eta1) * Y
-            comps[1] += -(1 / r2) * (nu[3] + nu[4] - eta2) * Y
-            comps[2] += (nu[5] + nu[6] + eta3) * Y
-    return np.stack(comps, axis=1)
+    eq. (nulm1), (nulm2), (etalm), synthesised with scipy's Y."""
+    comps = np.zeros((len(xyz), 3), np.complex128)
+    for (l, m), c in cg_routes.theorem2_coeffs(L, a, b, literal_zero_cases).items():
+        comps += np.outer(scipy_Y(l, m, xyz), np.array(c, np.complex128))
+    return comps
 
 
 def test_theorem1_route(orc):
