@@ -11,6 +11,10 @@ pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-11
 FP32_TOL = 2e-5
+# split-bf16 contractions: the bounds argued for the vector transforms (three
+# products drop terms up to 3 * 2^-18 relative per product; six stay below binary32)
+BF16X3_TOL = 3e-5
+BF16X6_TOL = FP32_TOL
 
 
 def rel_l2(x, y):
@@ -46,7 +50,8 @@ def grid(kind, L):
 @pytest.mark.parametrize("kind,L,precision,tol", [
     ("gl", 1, "fp64", FP64_TOL), ("gl", 7, "fp64", FP64_TOL), ("gl", 33, "fp64", FP64_TOL),
     ("reduced", 40, "fp64", FP64_TOL), ("gl", 33, "fp32", FP32_TOL),
-    ("reduced", 40, "fp32", FP32_TOL)])
+    ("reduced", 40, "fp32", FP32_TOL), ("gl", 33, "bf16x3", BF16X3_TOL),
+    ("reduced", 40, "bf16x3", BF16X3_TOL), ("gl", 33, "bf16x6", BF16X6_TOL)])
 def test_sht_forward_adjoint(torch, vsht, orc, kind, L, precision, tol):
     print("[case] sht", kind, L, precision, flush=True)
     xyz, w = grid(kind, L)
