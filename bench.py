@@ -258,9 +258,9 @@ def main():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the transform would shard by ring pairs and by order m with one all-to-all; "
-              "see the design notes).  Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the transform would shard by ring pairs and by order m with one all-to-all).  "
+              "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

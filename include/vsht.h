@@ -76,7 +76,7 @@ typedef enum {
     VSHT_ENOWEIGHTS = 2,  /* forward called on a plan created without weights */
     VSHT_ENOMEM = 3,      /* host or device allocation failed */
     VSHT_EDEVICE = 4,     /* a HIP call failed; vsht_last_error() has the detail */
-    VSHT_EUNSUPPORTED = 5 /* valid request this build cannot serve (e.g. forward on scattered points) */
+    VSHT_EUNSUPPORTED = 5 /* valid request the library cannot serve (e.g. forward on scattered points) */
 } vsht_status;
 
 typedef enum {
