@@ -28,6 +28,11 @@ def test_exports_every_declared_symbol():
     assert sorted(B.EXPORTED) == names
 
 
+def test_num_sht_coeffs():
+    lib = B.load_library()
+    assert [lib.vsht_num_sht_coeffs(L) for L in (-1, 0, 1, 2, 1024)] == [0, 1, 4, 9, 1025 ** 2]
+
+
 def test_num_coeffs():
     for L, K in [(0, 0), (-3, 0), (1, 3), (16, 288), (1024, 1050624)]:
         assert v.vsht_num_coeffs(L) == K
@@ -80,6 +85,8 @@ def test_null_arguments():
     assert lib.vsht_forward(None, None, None, None, None) == B.VSHT_EINVAL
     assert lib.vsht_adjoint(None, None, None, None, None) == B.VSHT_EINVAL
     assert lib.vsht_forward_unweighted(None, None, None, None, None) == B.VSHT_EINVAL
+    assert lib.vsht_sht_forward(None, None, None, None) == B.VSHT_EINVAL
+    assert lib.vsht_sht_adjoint(None, None, None, None) == B.VSHT_EINVAL
     assert lib.vsht_plan_info(None, None) == B.VSHT_EINVAL
     assert lib.vsht_plan_destroy(None) == B.VSHT_OK
     h = ctypes.c_void_p()
