@@ -36,6 +36,13 @@ vsht_status hip_fail(hipError_t e, const char *what) {
 // Largest sizes the ring kernels are compiled for.
 constexpr int64_t kMaxNphi = 3072;
 constexpr int kMaxLRings = 2047;
+// Largest bandlimit served.  The binary64 seeds Lambda_{m,m} = O(s^m) leave the
+// normal range for large m near the poles; up to this L every such function stays
+// below 1e-16 over all its degrees l <= L+1 on the Gauss-Legendre rings
+// (measured by a log-scaled recurrence: largest 1e-16.2 at L = 1664, 5e-7 at
+// L = 1792), so flushing those seeds loses nothing.  Beyond it the seeds and the
+// recurrence would have to carry an exponent.
+constexpr int kMaxL = 1664;
 
 struct DeviceGuard {
     int old = -1;
@@ -390,6 +397,9 @@ RingScan scan_rings(int64_t n, const double *xyz, const double *w) {
 vsht_status check_plan_args(int L, int64_t n, const double *xyz, const double *w, int precision) {
     if (L < 1) return fail(VSHT_EINVAL, "L must be >= 1");
     if (L > 65535) return fail(VSHT_EINVAL, "L too large");
+    if (L > kMaxL)
+        return fail(VSHT_EUNSUPPORTED, "L > " + std::to_string(kMaxL) +
+                                           ": binary64 seeds would underflow for functions that matter");
     if (n < 1) return fail(VSHT_EINVAL, "n must be >= 1");
     if (w && n < 2) return fail(VSHT_EINVAL, "a quadrature rule needs n >= 2 points");
     if (!xyz) return fail(VSHT_EINVAL, "xyz is NULL");

@@ -9,6 +9,7 @@ import pytest
 
 import paper_1908_00041_amd as v
 from paper_1908_00041_amd import _binding as B
+import vsht_inputs as vi
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -78,6 +79,17 @@ def test_plan_rejects_invalid(case):
     assert st == B.VSHT_EINVAL
     assert not h.value
     assert len(lib.vsht_last_error()) > 0
+
+
+def test_plan_rejects_bandlimit_beyond_seed_range():
+    """Plans above L = 1664 are refused before any device work (host check)."""
+    lib = B.load_library()
+    xyz, _ = vi.uniform_points(16, 5)
+    xyz = np.ascontiguousarray(xyz, np.float64)
+    h = ctypes.c_void_p()
+    st = lib.vsht_plan(1665, len(xyz), xyz.ctypes.data_as(ctypes.c_void_p), None, None, ctypes.byref(h))
+    assert st == B.VSHT_EUNSUPPORTED and not h.value
+    assert "1664" in B.load_library().vsht_last_error().decode()
 
 
 def test_null_arguments():
