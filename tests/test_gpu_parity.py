@@ -247,6 +247,35 @@ def test_gl_L1024_sampled(torch, vsht, orc, precision, tol):
 
 
 # ---------------------------------------------------------------------------
+# The largest sizes served: the longest ring the ring kernels take (3072 points,
+# GL at L = 1535 with 2L+2 longitudes, the exact quadrature: round trip too) and
+# the largest bandlimit (L = 1664, here on 1665 GL rings of 3072 points, where
+# the forward is checked as the discrete sum it is).  Sampled against the oracle.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L,nphi", [(1535, None), (1664, 3072)])
+def test_largest_sizes_sampled(torch, vsht, orc, L, nphi):
+    print_case("largest sizes", L, nphi)
+    xyz, w = vi.gl_grid(L, n_phi=nphi)
+    plan = vsht.Plan(L, xyz, w, precision="fp64")
+    assert plan.kind == "rings"
+    a, b = vi.random_coeffs(L, 5)
+    T = run_adjoint(torch, plan, a, b)
+    pidx = vi.sample_indices(len(w), 32, 6)
+    e_adj = rel_l2(T[pidx], orc.adjoint(L, a, b, xyz[pidx]))
+    cidx = vi.sample_indices(L * (L + 2), 32, 7)
+    ga, gb = run_forward(torch, plan, T)
+    sa, sb = orc.forward_subset(L, xyz, w, T, cidx)
+    e_fwd = rel_l2(np.concatenate([ga[cidx], gb[cidx]]), np.concatenate([sa, sb]))
+    msg = "largest L=%d nphi=%d adjoint %.3e forward %.3e" % (L, len(w) // (L + 1), e_adj, e_fwd)
+    if nphi is None:
+        e_rt = rel_l2(np.concatenate([ga, gb]), np.concatenate([a, b]))
+        msg += " roundtrip %.3e" % e_rt
+        assert e_rt < FP64_TOL
+    print(msg)
+    assert e_adj < FP64_TOL and e_fwd < FP64_TOL
+
+
+# ---------------------------------------------------------------------------
 # Ring lengths with a prime factor beyond the generic radix: Bluestein DFT.
 # GL grids at L = 66 (n_phi = 134 = 2 * 67) and L = 100 (202 = 2 * 101), a ring
 # grid with prime n_phi = 131 (and a shifted longitude origin), and a mixed
