@@ -62,8 +62,28 @@ def log(*a):
 
 
 def folded_elements(L, n_pairs):
-    """(m >= 0, m <= l' <= L+1, ring pair) elements of one Legendre stage."""
+    """(m >= 0, m <= l' <= L+1, ring pair) elements of one Legendre stage as this
+    library runs it (the spin-frame form, degrees up to L+1)."""
     return n_pairs * ((L + 2) * (L + 3) // 2 - 1)
+
+
+def method_elements(L):
+    """E(L) = ((L+1)(L+2)/2) ceil((L+1)/2): the folded (l, m >= 0, ring pair)
+    elements of the method's own dense Legendre contraction on the GL grid with
+    L+1 rings, 32 flops each per direction (two functions dP and mP/s, eight real
+    columns, multiply-add)."""
+    return (L + 1) * (L + 2) // 2 * ((L + 2) // 2)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def time_steps(torch, plan, a, b, steps, warmup):
@@ -225,9 +245,21 @@ def run_differentiable(torch, vsht, vi, args):
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / args.steps
     plan.close()
-    log("differentiable: %.3f ms per step (%d fields, L=%d)" % (sec * 1e3, F, L))
+    # error of the FP32 gradient of field 0 against the same step on the FP64 path
+    # (same binary32-representable inputs)
+    p64 = vsht.Plan(L, xyz, w, precision="fp64")
+    a64 = a.detach()[0].to(torch.complex128).requires_grad_()
+    b64 = b.detach()[0].to(torch.complex128).requires_grad_()
+    r64 = vsht.adjoint_vsht(p64, a64, b64) - Tt[0].to(torch.complex128)
+    (r64.real ** 2 + r64.imag ** 2).sum().backward()
+    g64 = torch.cat([a64.grad, b64.grad]).cpu().numpy()
+    g32 = torch.cat([a.grad[0], b.grad[0]]).cpu().numpy().astype(np.complex128)
+    p64.close()
+    gerr = rel_l2(g32, g64)
+    log("differentiable: %.3f ms per step (%d fields, L=%d), gradient error vs fp64 %.2e"
+        % (sec * 1e3, F, L, gerr))
     return {"fields": F, "L": L, "precision": "fp32", "ms_per_step": round(sec * 1e3, 4),
-            "fields_per_s": round(F / sec, 1),
+            "fields_per_s": round(F / sec, 1), "grad_rel_l2_vs_fp64": gerr,
             "note": "loss = ||Adj(a,b) - T_target||^2 summed over fields; step = adjoint of every field, "
                     "loss, and backward through the unit-weight forward kernels"}
 
@@ -244,8 +276,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--L", type=int, default=1024)
-    ap.add_argument("--oracle-coeffs", type=int, default=1024)
-    ap.add_argument("--oracle-points", type=int, default=512)
+    ap.add_argument("--oracle-coeffs", type=int, default=4096)
+    ap.add_argument("--oracle-points", type=int, default=4096)
     ap.add_argument("--no-oracle", action="store_true")
     ap.add_argument("--precisions", default="fp64,fp32,bf16x3,bf16x6")
     ap.add_argument("--l256", type=int, default=1,
@@ -345,7 +377,7 @@ def main():
         # coefficients, the adjoint in the number of points
         t_full = t_fwd * K / len(cidx) + t_adj * N / len(pidx)
         cpu = {"value": 1.0 / t_full, "unit": "transforms/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
+               "cpu_model": cpu_model(), "kind": "oracle",
                "sample": ("CPU FP64 direct-sum oracle on the same L=%d GL workload: forward for "
                           "%d sampled coefficients (all %d points, %.2f s) and adjoint at %d "
                           "sampled points (all %d coefficients, %.2f s), each scaled linearly "
@@ -356,13 +388,16 @@ def main():
             r["err_adj"] = rel_l2(r["T_sample"], oT)
             r["err_fwd"] = rel_l2(np.concatenate([r["fa"], r["fb"]]), np.concatenate([oa, ob]))
 
+    peaks = {"fp64": FP64_MFMA_TFLOPS, "fp32": FP32_MFMA_TFLOPS}
+
     def roofline(prec, r):
         # Dominant kernel of the step and its algorithmic work per launch.
-        # Legendre stages: 16 flops per (m >= 0, m <= l' <= L+1, ring pair) element,
-        # i.e. 8 real multiply-adds (theta/phi x +-m x re/im) against one Legendre
-        # value; BF16x3 (BF16x6) performs each of them as 3 (6) bf16 products, so its
-        # algorithmic count is 3 (6) x 16 per element against the bf16 MFMA peak.  Ring stages: HBM
-        # bytes of the field (n x 3 complex) plus the ring-Fourier buffer.
+        # Legendre stages: 32 flops per element of E(L) (the method's dense
+        # contraction, two functions x eight real columns x multiply-add); BF16x3
+        # (BF16x6) performs each multiply-add as 3 (6) bf16 products, counted against
+        # the bf16 MFMA peak.  Beside it, the flops this library executes: 16 per
+        # element of its spin-frame form (one function, degrees to L+1).  Ring stages:
+        # HBM bytes of the field (n x 3 complex) plus the ring-Fourier buffer.
         st = r["stages"]
         dom = max(st, key=lambda k: st[k])
         t = st[dom] * 1e-3
@@ -377,15 +412,17 @@ def main():
         kern = kern_names.get(dom, dom)
         out = {"kernel": kern, "launch_us": round(st[dom] * 1e3, 2)}
         if dom in ("leg_fwd", "leg_adj"):
-            E = folded_elements(L, info["n_pairs"])
-            flops = 16.0 * nprod * E
-            peak = {"fp64": FP64_MFMA_TFLOPS, "fp32": FP32_MFMA_TFLOPS}.get(prec, BF16_MFMA_TFLOPS)
+            flops = 32.0 * nprod * method_elements(L)
+            executed = 16.0 * nprod * folded_elements(L, info["n_pairs"])
+            peak = peaks.get(prec, BF16_MFMA_TFLOPS)
             # the binary64/binary32 synthesis runs on the vector unit, whose peaks on
             # this part equal the matrix-core ones (78.6 / 157.3 TFLOP/s)
             bound = "alu" if (dom == "leg_adj" and nprod == 1) else "mfma"
             ach = flops / t / 1e12
             out.update(bound=bound, achieved=round(ach, 3), peak=peak, unit="TFLOP/s",
-                       frac=round(ach / peak, 4), flops_per_launch=flops)
+                       frac=round(ach / peak, 4), flops_per_launch=flops,
+                       executed_flops_per_launch=executed,
+                       executed_frac=round(executed / t / 1e12 / peak, 4))
         else:
             nbuf = (L + 1) * (info["n_rings"] * 4 if dom == "ring_fwd" else info["n_pairs"] * 8)
             if dom in ("ring_fwd", "ring_adj"):
@@ -397,6 +434,20 @@ def main():
                        frac=round(ach / HBM_PEAK_GBS, 4), bytes_per_launch=by)
         out["traffic"] = measured_traffic(kern, prec, L)
         return out
+
+    def step_roofline(prec, r):
+        # the whole forward+adjoint step: t_roof = max(compulsory bytes / HBM peak,
+        # the method's Legendre flops / the precision's peak); frac = t_roof / t_step
+        cs = 16 if prec == "fp64" else 8
+        nprod = {"bf16x3": 3, "bf16x6": 6}.get(prec, 1)
+        by = 2.0 * (3 * N + 2 * K) * cs
+        fl = 64.0 * nprod * method_elements(L)
+        t_hbm = by / (HBM_PEAK_GBS * 1e9)
+        t_fl = fl / (peaks.get(prec, BF16_MFMA_TFLOPS) * 1e12)
+        t_roof = max(t_hbm, t_fl)
+        return {"bound": "hbm" if t_hbm >= t_fl else "compute",
+                "bytes": by, "flops": fl, "t_roof_us": round(t_roof * 1e6, 2),
+                "t_step_us": round(r["sec"] * 1e6, 2), "frac": round(t_roof / r["sec"], 4)}
 
     main_r = results.get("fp64") or next(iter(results.values()))
     main_prec = "fp64" if "fp64" in results else next(iter(results))
@@ -418,6 +469,8 @@ def main():
                                "L=%d, random coefficients scaled 1/l, seed 0" % (L + 1, 2 * L + 2, N, L),
                    "L": L, "points": N, "coefficients": 2 * K, "precision": main_prec},
         "roofline": roofline(main_prec, main_r),
+        "step_roofline": step_roofline(main_prec, main_r),
+        "plan_s": round(main_r["plan_s"], 3),
         "stages_us": {k: round(v * 1e3, 2) for k, v in main_r["stages"].items()},
         "errors": {"roundtrip_rel_l2": main_r["roundtrip"]},
         "cpu_baseline": cpu,
@@ -431,7 +484,8 @@ def main():
         if prec == main_prec:
             continue
         v = {"value": round(1.0 / r["sec"], 2), "ms_per_step": round(r["sec"] * 1e3, 4),
-             "roofline": roofline(prec, r),
+             "roofline": roofline(prec, r), "step_roofline": step_roofline(prec, r),
+             "plan_s": round(r["plan_s"], 3),
              "stages_us": {k: round(x * 1e3, 2) for k, x in r["stages"].items()},
              "errors": {"roundtrip_rel_l2": r["roundtrip"]}}
         if "err_adj" in r:

@@ -231,6 +231,7 @@ class Plan:
         return _torch().cuda.current_stream(self.device).cuda_stream
 
     def _check(self, t, shape, name):
+        """An input: right dtype, shape and device; a contiguous copy if it is a view."""
         torch = _torch()
         if not isinstance(t, torch.Tensor):
             raise TypeError("%s must be a torch tensor" % name)
@@ -239,13 +240,21 @@ class Plan:
                 name, self.dtype, shape, self.device, t.dtype, tuple(t.shape), t.device))
         return t.contiguous()
 
-    def forward(self, T, a=None, b=None, weighted=True):
+    def _out(self, t, shape, name):
+        """An output: allocated when None, else checked like an input and required to be
+        contiguous (the kernels write through its pointer; a copy would lose the results)."""
         torch = _torch()
+        if t is None:
+            return torch.empty(shape, dtype=self.dtype, device=self.device)
+        t2 = self._check(t, shape, name)
+        if t2.data_ptr() != t.data_ptr() or not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        return t
+
+    def forward(self, T, a=None, b=None, weighted=True):
         T = self._check(T, (self.n, 3), "T")
-        if a is None:
-            a = torch.empty(self.K, dtype=self.dtype, device=self.device)
-        if b is None:
-            b = torch.empty(self.K, dtype=self.dtype, device=self.device)
+        a = self._out(a, (self.K,), "a")
+        b = self._out(b, (self.K,), "b")
         fn = vsht_forward if weighted else vsht_forward_unweighted
         _raise_for(fn(self._h, T.data_ptr(), a.data_ptr(), b.data_ptr(), self._stream()),
                    "vsht_forward" if weighted else "vsht_forward_unweighted")
@@ -255,31 +264,25 @@ class Plan:
         return self.forward(T, a, b, weighted=False)
 
     def adjoint(self, a, b, T=None):
-        torch = _torch()
         a = self._check(a, (self.K,), "a")
         b = self._check(b, (self.K,), "b")
-        if T is None:
-            T = torch.empty((self.n, 3), dtype=self.dtype, device=self.device)
+        T = self._out(T, (self.n, 3), "T")
         _raise_for(vsht_adjoint(self._h, a.data_ptr(), b.data_ptr(), T.data_ptr(), self._stream()),
                    "vsht_adjoint")
         return T
 
     def sht_forward(self, f, flm=None):
         """Scalar forward transform (ring plans with weights): f (n,) -> flm ((L+1)^2,)."""
-        torch = _torch()
         f = self._check(f, (self.n,), "f")
-        if flm is None:
-            flm = torch.empty(vsht_num_sht_coeffs(self.L), dtype=self.dtype, device=self.device)
+        flm = self._out(flm, (vsht_num_sht_coeffs(self.L),), "flm")
         _raise_for(vsht_sht_forward(self._h, f.data_ptr(), flm.data_ptr(), self._stream()),
                    "vsht_sht_forward")
         return flm
 
     def sht_adjoint(self, flm, f=None):
         """Scalar adjoint transform (ring plans): flm ((L+1)^2,) -> f (n,)."""
-        torch = _torch()
         flm = self._check(flm, (vsht_num_sht_coeffs(self.L),), "flm")
-        if f is None:
-            f = torch.empty(self.n, dtype=self.dtype, device=self.device)
+        f = self._out(f, (self.n,), "f")
         _raise_for(vsht_sht_adjoint(self._h, flm.data_ptr(), f.data_ptr(), self._stream()),
                    "vsht_sht_adjoint")
         return f
@@ -396,7 +399,9 @@ class BatchPlan:
     def _stream(self):
         return _torch().cuda.current_stream(self.device).cuda_stream
 
-    def _check(self, ts, shapes, name):
+    def _check(self, ts, shapes, name, output=False):
+        """Inputs: right dtype, shape and device (views are copied).  Outputs: the same,
+        and contiguous (the kernels write through the pointers)."""
         torch = _torch()
         if len(ts) != len(self.Ls):
             raise ValueError("%s: need one tensor per field" % name)
@@ -406,7 +411,9 @@ class BatchPlan:
                     or tuple(t.shape) != shp:
                 raise ValueError("%s: every entry must be a %s tensor on %s of its field's shape"
                                  % (name, self.dtype, self.device))
-            out.append(t.contiguous())
+            if output and not t.is_contiguous():
+                raise ValueError("%s: output tensors must be contiguous" % name)
+            out.append(t if output else t.contiguous())
         return out
 
     def empty_coeffs(self):
@@ -420,7 +427,7 @@ class BatchPlan:
     def adjoint(self, a, b, T=None):
         cs = [(K,) for K in self.Ks]
         a, b = self._check(a, cs, "a"), self._check(b, cs, "b")
-        T = self.empty_fields() if T is None else self._check(T, [(n, 3) for n in self.ns], "T")
+        T = self.empty_fields() if T is None else self._check(T, [(n, 3) for n in self.ns], "T", True)
         self._keep = (a, b, T)
         _raise_for(load_library().vsht_batch_adjoint(self._h, _ptr_array(a), _ptr_array(b), _ptr_array(T),
                                                      self._stream()), "vsht_batch_adjoint")
@@ -428,8 +435,8 @@ class BatchPlan:
 
     def forward(self, T, a=None, b=None):
         T = self._check(T, [(n, 3) for n in self.ns], "T")
-        a = self.empty_coeffs() if a is None else self._check(a, [(K,) for K in self.Ks], "a")
-        b = self.empty_coeffs() if b is None else self._check(b, [(K,) for K in self.Ks], "b")
+        a = self.empty_coeffs() if a is None else self._check(a, [(K,) for K in self.Ks], "a", True)
+        b = self.empty_coeffs() if b is None else self._check(b, [(K,) for K in self.Ks], "b", True)
         self._keep = (T, a, b)
         _raise_for(load_library().vsht_batch_forward(self._h, _ptr_array(T), _ptr_array(a), _ptr_array(b),
                                                      self._stream()), "vsht_batch_forward")
@@ -438,9 +445,9 @@ class BatchPlan:
     def _rt_args(self, a, b, T, a2, b2):
         cs = [(K,) for K in self.Ks]
         a, b = self._check(a, cs, "a"), self._check(b, cs, "b")
-        T = self.empty_fields() if T is None else self._check(T, [(n, 3) for n in self.ns], "T")
-        a2 = self.empty_coeffs() if a2 is None else self._check(a2, cs, "a2")
-        b2 = self.empty_coeffs() if b2 is None else self._check(b2, cs, "b2")
+        T = self.empty_fields() if T is None else self._check(T, [(n, 3) for n in self.ns], "T", True)
+        a2 = self.empty_coeffs() if a2 is None else self._check(a2, cs, "a2", True)
+        b2 = self.empty_coeffs() if b2 is None else self._check(b2, cs, "b2", True)
         return a, b, T, a2, b2
 
     def roundtrip(self, a, b, T=None, a2=None, b2=None):

@@ -70,7 +70,7 @@ hipError_t upload(T **dst, const std::vector<T> &src, size_t *bytes) {
 void free_plan_memory(Plan *p) {
     const NfftPlan &nf = p->nfft;
     void *ptrs[] = {p->d_rings, p->d_pairs, p->d_ffts, p->d_tw,  p->d_pair_z, p->d_aprime,
-                    p->d_cscale, p->d_etab, p->d_rsq,  p->d_seeds, p->d_weights, p->d_xyz, p->d_pb,  p->d_fg,
+                    p->d_cscale, p->d_etab, p->d_rsq,  p->d_seeds, p->d_weights, p->d_xyz, p->d_pb,  p->d_fg,  p->d_fglo, p->d_fpart,
                     p->d_state, nf.d_ffts, nf.d_tw, nf.d_vpairs, nf.d_vz, nf.d_vs, nf.d_vseeds, nf.d_psihat, nf.d_pts,
                     nf.d_vpb, nf.d_g1, nf.d_g};
     for (void *q : ptrs)
@@ -624,6 +624,16 @@ vsht_status build_plan(Plan &P, int L, int64_t n, const double *xyz, const doubl
             if ((e = hipMalloc(&P.d_pb, pb)) != hipSuccess) goto hip_error;
             if ((e = hipMalloc(&P.d_fg, fg)) != hipSuccess) goto hip_error;
             P.workspace_bytes = pb + fg;
+            if (rsz == 4) {
+                if ((e = hipMalloc(&P.d_fglo, fg)) != hipSuccess) goto hip_error;
+                P.workspace_bytes += fg;
+            }
+            const int groups = analysis_groups(P.n_pairs, P.eq_ring);
+            if (groups > 1) {
+                const size_t part = (size_t)groups * P.tri_size * 8 * rsz;
+                if ((e = hipMalloc(&P.d_fpart, part)) != hipSuccess) goto hip_error;
+                P.workspace_bytes += part;
+            }
         }
     } else {
         P.kind = VSHT_PLAN_SCATTERED;
@@ -636,6 +646,10 @@ vsht_status build_plan(Plan &P, int L, int64_t n, const double *xyz, const doubl
         const size_t fg = (size_t)(P.tri_size + kFgPadRows) * 4 * 2 * rsz;
         if ((e = hipMalloc(&P.d_fg, fg)) != hipSuccess) goto hip_error;
         P.workspace_bytes = fg;
+        if (rsz == 4) {
+            if ((e = hipMalloc(&P.d_fglo, fg)) != hipSuccess) goto hip_error;
+            P.workspace_bytes += fg;
+        }
         if (!(flags & VSHT_OPT_SCATTERED_DIRECT) && L <= kMaxNfftL) {
             e = build_nfft(P, n, xyz);
             if (e == hipErrorInvalidValue) {
@@ -956,6 +970,10 @@ vsht_status vsht_plan_batch(int nfields, const int *L, const int64_t *n, const d
         s = build_plan(B.fields[f], L[f], n[f], xyz[f], w[f], precision, dev, opts ? opts->flags : 0);
         if (s == VSHT_OK && B.fields[f].kind != VSHT_PLAN_RINGS)
             s = fail(VSHT_EUNSUPPORTED, "a batch needs iso-latitude ring grids");
+        // the batched analysis holds all of a field's ring-pair tiles in one workgroup
+        if (s == VSHT_OK && analysis_groups(B.fields[f].n_pairs, B.fields[f].eq_ring) > 1)
+            s = fail(VSHT_EUNSUPPORTED, "a batch field may have at most 1024 ring pairs (" +
+                                            std::to_string(B.fields[f].n_pairs) + " given)");
         if (s != VSHT_OK) {
             g_last_error = "field " + std::to_string(f) + ": " + g_last_error;
             delete h;

@@ -125,7 +125,16 @@ struct NfftPlan {
 //  FG   triangle buffer [tri(L)][4] complex, tri index (m, l') for
 //       0 <= m <= L, m <= l' <= L+1: forward F, adjoint prep g; followed by
 //       kFgPadRows rows that the synthesis may load (never use) past the end.
+//  FGlo (binary32 paths) the adjoint's g - hi(g) in binary32, same layout as FG,
+//       read by the binary64 polar group of the synthesis.
 constexpr int kFgPadRows = 8;
+
+// Workgroups per order of the ring analysis: up to 16 tiles of 64 ring pairs
+// (the equator excluded) in one workgroup, more split over several.
+inline int analysis_groups(int64_t n_pairs, int eq_ring) {
+    const int64_t tiles = (n_pairs - (eq_ring >= 0 ? 1 : 0) + 63) / 64;
+    return tiles > 16 ? (int)((tiles + 15) / 16) : 1;
+}
 
 struct Plan {
     int L = 0;
@@ -161,6 +170,8 @@ struct Plan {
     // workspace
     void *d_pb = nullptr;
     void *d_fg = nullptr;
+    void *d_fglo = nullptr;        // binary32 paths: low parts of the adjoint's FG, [tri][8] float
+    void *d_fpart = nullptr;       // analysis split over g > 1 workgroups per order: [g][tri][8]
     void *d_state = nullptr;       // Legendre recurrence state
     size_t workspace_bytes = 0;
     int n_ffts = 0;

@@ -933,7 +933,8 @@ struct LegFwdArgs {
     int NPT;               // pairs handled by the tiles (the equator, if any, is pair NPT)
     int NR;
     int eq_ring;           // ring at z = 0 handled in closed form, or -1
-    int atomic;            // 1: several workgroups share an order m (accumulate into F)
+    int64_t gstride;       // several workgroups per order m: group g writes its partial
+                           // triangle at F + g gstride (summed afterwards); 0 otherwise
 };
 
 // Valid half of a 16x16 analysis block in compact form: 128 values per wave.
@@ -1106,11 +1107,7 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
                     const int kk = (lp - m) >> 1;
                     sum += ((kk & 1) ? -seq : seq) * xeq[c];
                 }
-                const double v = csc[u] * sum;
-                if (A.atomic)
-                    atomicAdd(&A.F[ti * 8 + c], v);
-                else
-                    A.F[ti * 8 + c] = v;
+                A.F[group * A.gstride + ti * 8 + c] = csc[u] * sum;
             }
         }
     }
@@ -1192,14 +1189,22 @@ __device__ __forceinline__ void leg_fwd_body(const LegFwdArgs<real> &A, int m, i
                     const double qe = (kk & 1) ? -seq : seq;
                     sum += (real)qe * xeq[col];
                 }
-                const real v = (real)A.cscale[ti] * sum;
-                if (A.atomic)
-                    atomicAdd(&A.F[ti * 8 + (col & 7)], v);
-                else
-                    A.F[ti * 8 + (col & 7)] = v;
+                A.F[group * A.gstride + ti * 8 + (col & 7)] = (real)A.cscale[ti] * sum;
             }
         }
     }
+}
+
+// F[i] = sum_g part[g n + i], g in increasing order (analysis split over several
+// workgroups per order; deterministic, no atomics)
+template <typename real>
+__global__ __launch_bounds__(256) void k_sum_groups(const real *__restrict__ part, real *__restrict__ F,
+                                                    int64_t n, int groups) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    real acc = part[i];
+    for (int g = 1; g < groups; ++g) acc += part[(int64_t)g * n + i];
+    F[i] = acc;
 }
 
 template <typename real>
@@ -1214,6 +1219,7 @@ __global__ __launch_bounds__(1024) void k_leg_fwd_mfma(LegFwdArgs<real> A) {
 template <typename real>
 struct LegArgs {
     const real *FG;       // [tri][8]
+    const float *FGlo;    // binary32 paths: FG's low parts (hi + lo = the binary64 g)
     real *PB;             // [(L+1)][NP][16]
     const double *seeds;
     const double *pz;
@@ -1221,7 +1227,18 @@ struct LegArgs {
     int L;
     int NP;
     int NPT;              // pairs handled by the tiles (the equator, if any, is pair NPT)
+    int P;                // pairs [0, P) (nearest the poles) go to the binary64 polar group
+    int gpolar;           // workgroup column (blockIdx.x) of the polar group, or -1
 };
+
+// Ring pairs of the binary32 syntheses that run in binary64 (the polar group).
+// The spin-frame synthesis divides by sin(theta) a sum whose terms near the
+// poles are up to ~1/sin(theta) larger than the sum, so binary32 rounding of the
+// Legendre values and of g is amplified there; over the L + 1 rings of a
+// Gauss-Legendre grid the squared error of ring r falls off as 1/r^2, and the
+// 32 pairs nearest the poles carry all but a few percent of it.
+constexpr int kPolarPairs = 32;
+constexpr int kPolarMaxPerLane = 4;  // pairs per lane of a polar group of one wave
 
 // Synthesis on the vector unit.  A workgroup takes one order m; each lane
 // carries AdjPPL<real>::n ring pairs through the degrees l' = m .. L+1, and each degree
@@ -1303,7 +1320,7 @@ __device__ __forceinline__ void adj_valu_body(const LegArgs<real> &A, int m, int
     real E[kAdjPPL][8], O[kAdjPPL][8];
 #pragma unroll
     for (int u = 0; u < kAdjPPL; ++u) {
-        const int p = ((grp * nw + wave) * kAdjPPL + u) * kTileP + lane;
+        const int p = A.P + ((grp * nw + wave) * kAdjPPL + u) * kTileP + lane;
         const bool valid = p < NPT;
         z[u] = valid ? A.pz[p] : 0.0;
         q1[u] = 0.0;
@@ -1393,21 +1410,36 @@ __device__ __forceinline__ void adj_valu_body(const LegArgs<real> &A, int m, int
                 }
             }
         } else {
+            // binary32: the chunk's terms go into partial sums that are added to the
+            // totals once per chunk (two-level summation: the rounding of a running
+            // sum over all L degrees would dominate the error)
+            real Ec[kAdjPPL][8], Oc[kAdjPPL][8];
+#pragma unroll
+            for (int u = 0; u < kAdjPPL; ++u)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) Ec[u][c] = Oc[u][c] = (real)0;
             for (int d = 0; d < nd; d += 2) {
                 const AdjRow<real> R0 = rows[d];
-                adj_row_step(R0, z, q1, q2, E);
+                adj_row_step(R0, z, q1, q2, Ec);
                 if (d + 1 < nd) {
                     const AdjRow<real> R1 = rows[d + 1];
-                    adj_row_step(R1, z, q1, q2, O);
+                    adj_row_step(R1, z, q1, q2, Oc);
                 }
             }
+#pragma unroll
+            for (int u = 0; u < kAdjPPL; ++u)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    E[u][c] += Ec[u][c];
+                    O[u][c] += Oc[u][c];
+                }
         }
         if (k + 1 < nchunk) stage_store(k + 1);
         __syncthreads();
     }
 #pragma unroll
     for (int u = 0; u < kAdjPPL; ++u) {
-        const int p = ((grp * nw + wave) * kAdjPPL + u) * kTileP + lane;
+        const int p = A.P + ((grp * nw + wave) * kAdjPPL + u) * kTileP + lane;
         if (p < NPT) {
             real *o = A.PB + ((size_t)m * NP + p) * 16;
 #pragma unroll
@@ -1430,6 +1462,110 @@ __device__ __forceinline__ void adj_valu_body(const LegArgs<real> &A, int m, int
     }
 }
 
+// Polar group of the binary32 syntheses: pairs [0, P) of order m in binary64,
+// with g = hi + lo (the binary64 value prep computed) and the recurrence value
+// unrounded, so that the division by sin(theta) near the poles divides an
+// accurate sum.  Lane (p, c) of wave w carries column c = lane >> 3 of g for
+// the pairs w * 8 + (lane & 7) + 8 nw u, u < ceil(P / (8 nw)); g and a' are
+// staged in LDS kAdjChunk degrees at a time, one chunk ahead, as in
+// adj_valu_body.  The E and O sums near the poles are as small as the ring
+// values themselves, so storing them in binary32 keeps their accuracy.
+struct PolarRow {
+    double g[8];
+    double a;
+};
+__device__ __forceinline__ void adj_polar_body(const LegArgs<float> &A, int m, PolarRow *buf) {
+    const int nt = blockDim.x, nw = nt >> 6;
+    const int wave = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int L = A.L, NP = A.NP, Lp1 = L + 1;
+    const int npl = uniform_int((A.P + 8 * nw - 1) / (8 * nw));
+    const int64_t t0 = tri_offset(L, m);
+    const float *gh = A.FG + (t0 - m) * 8, *gl = A.FGlo + (t0 - m) * 8;  // row l' at + 8 l'
+    const double *ap = A.aprime + t0 - m;
+    const int c = lane >> 3;
+    double z[kPolarMaxPerLane], q1[kPolarMaxPerLane], q2[kPolarMaxPerLane];
+    double E[kPolarMaxPerLane], O[kPolarMaxPerLane];
+#pragma unroll
+    for (int u = 0; u < kPolarMaxPerLane; ++u) {
+        const int p = wave * 8 + (lane & 7) + 8 * nw * u;
+        const bool valid = u < npl && p < A.P;
+        z[u] = valid ? A.pz[p] : 0.0;
+        q1[u] = 0.0;
+        q2[u] = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+        asm volatile("" : "+v"(z[u]), "+v"(q2[u]));
+        E[u] = O[u] = 0.0;
+    }
+    const int nl = Lp1 - m + 1;
+    const int nchunk = (nl + kAdjChunk - 1) / kAdjChunk;
+    constexpr int kItems = 8 * kAdjChunk;
+    constexpr int kG = (kItems + 63) / 64;
+    double sg[kG];
+    double sa = 0.0;
+    auto stage_load = [&](int k) {
+        const int lp0 = m + k * kAdjChunk;
+#pragma unroll
+        for (int r = 0; r < kG; ++r) {
+            const int i = threadIdx.x + r * nt;
+            const int lp = lp0 + (i >> 3);
+            sg[r] = 0.0;
+            if (i < kItems && lp <= Lp1) {
+                const int64_t o = (int64_t)lp * 8 + (i & 7);
+                sg[r] = (double)gh[o] + (double)gl[o];
+            }
+        }
+        const int la = lp0 + (int)threadIdx.x;
+        sa = ((int)threadIdx.x < kAdjChunk && la <= Lp1) ? ap[la] : 0.0;
+    };
+    auto stage_store = [&](int k) {
+        PolarRow *b = buf + (k & 1) * kAdjChunk;
+#pragma unroll
+        for (int r = 0; r < kG; ++r) {
+            const int i = threadIdx.x + r * nt;
+            if (i < kItems) b[i >> 3].g[i & 7] = sg[r];
+        }
+        if ((int)threadIdx.x < kAdjChunk) b[threadIdx.x].a = sa;
+    };
+    stage_load(0);
+    stage_store(0);
+    __syncthreads();
+    for (int k = 0; k < nchunk; ++k) {
+        if (k + 1 < nchunk) stage_load(k + 1);
+        const PolarRow *rows = buf + (k & 1) * kAdjChunk;
+        const int nd = min(kAdjChunk, nl - k * kAdjChunk);
+        for (int d = 0; d < nd; d += 2) {
+            const double a0 = rows[d].a, g0 = rows[d].g[c];
+            const bool odd = d + 1 < nd;
+            const double a1 = odd ? rows[d + 1].a : 0.0, g1 = odd ? rows[d + 1].g[c] : 0.0;
+#pragma unroll
+            for (int u = 0; u < kPolarMaxPerLane; ++u) {
+                if (u < npl) {
+                    const double v0 = fma(a0 * z[u], q1[u], -q2[u]);
+                    E[u] = fma(v0, g0, E[u]);
+                    q2[u] = q1[u];
+                    q1[u] = v0;
+                    if (odd) {
+                        const double v1 = fma(a1 * z[u], q1[u], -q2[u]);
+                        O[u] = fma(v1, g1, O[u]);
+                        q2[u] = q1[u];
+                        q1[u] = v1;
+                    }
+                }
+            }
+        }
+        if (k + 1 < nchunk) stage_store(k + 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < kPolarMaxPerLane; ++u) {
+        const int p = wave * 8 + (lane & 7) + 8 * nw * u;
+        if (u < npl && p < A.P) {
+            float *o = A.PB + ((size_t)m * NP + p) * 16;
+            o[c] = (float)E[u];
+            o[8 + c] = (float)O[u];
+        }
+    }
+}
+
 // One wave: pairs [64 tile, 64 tile + 64) of order m, computed in `real`, with
 // FG read and PB written in `store` (binary32 storage with binary64 arithmetic
 // serves the polar tile of the binary32 path).
@@ -1440,7 +1576,8 @@ __device__ __forceinline__ void adj_tile_mfma(const LegArgs<store> &A, int m, in
     const int L = A.L, NP = A.NP, NPT = A.NPT;
     const int64_t t0 = tri_offset(L, m);
     const store *g = A.FG + (t0 - m) * 8;  // indexed by l'
-    const int p = tile * kTileP + lane;
+    const int base = A.P;  // the tiles start after the polar group's pairs
+    const int p = base + tile * kTileP + lane;
     const bool valid = p < NPT;
     const double z = valid ? A.pz[p] : 0.0;
     double q1 = 0.0, q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
@@ -1463,22 +1600,29 @@ __device__ __forceinline__ void adj_tile_mfma(const LegArgs<store> &A, int m, in
             bv[gg] = (lp <= L + 1 && (j >> 3) == (k & 1)) ? (real)g[(int64_t)lp * 8 + (j & 7)] : (real)0;
         }
         recur16<real, SwzAdj>(qt, areg, z, q1, q2, lane);
+        // the block's 16 degrees are summed apart and then added to the totals
+        // (two-level summation over the degrees)
+        acc_t ab[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) ab[b] = acc_t{0, 0, 0, 0};
 #pragma unroll
         for (int gg = 0; gg < 4; ++gg) {
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 // A: lane (i + 16k) holds Q[row 4gg + k][pair 16b + i]
                 const real a = qt[SwzAdj::at(4 * gg + k, 16 * b + j)];
-                acc[b] = Mfma<real>::mma(a, bv[gg], acc[b]);
+                ab[b] = Mfma<real>::mma(a, bv[gg], ab[b]);
             }
         }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[b] += ab[b];
     }
     // accumulator b: lane l, register r -> pair 16b + row, column l%16
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int pp = tile * kTileP + 16 * b + Mfma<real>::row(lane, r);
+            const int pp = base + tile * kTileP + 16 * b + Mfma<real>::row(lane, r);
             if (pp < NPT) A.PB[((size_t)m * NP + pp) * 16 + j] = (store)acc[b][r];
         }
     }
@@ -1494,6 +1638,12 @@ __global__ __launch_bounds__(256, 4) void k_leg_adj(LegArgs<real> A) {
     const int y = blockIdx.y, base = y & ~255, r = y & 255;
     const int cnt = min(256, A.L + 1 - base);
     const int m = (y >> 8) & 1 ? base + cnt - 1 - r : y;
+    if constexpr (sizeof(real) == 4) {
+        if ((int)blockIdx.x == A.gpolar) {
+            adj_polar_body(A, m, reinterpret_cast<PolarRow *>(smem_raw));
+            return;
+        }
+    }
     adj_valu_body<real>(A, m, blockIdx.x, reinterpret_cast<AdjRow<real> *>(smem_raw));
 }
 
@@ -1598,6 +1748,20 @@ __device__ __forceinline__ Split8<NP> split8(const float (&v)[8]) {
 #pragma unroll
     for (int k = 0; k < NS; ++k) r.p[k] = __builtin_bit_cast(bf16x8_t, w[k]);
     return r;
+}
+
+// the leading part product into hi and the correction products into lo: lo stays
+// ~2^-8 of hi, so its rounding is negligible and hi sees one rounding per call
+template <int NP>
+__device__ __forceinline__ void mma_split2(const Split8<NP> &a, const Split8<NP> &b, f32x4 &hi, f32x4 &lo) {
+    hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[0], b.p[0], hi, 0, 0, 0);
+    lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[0], b.p[1], lo, 0, 0, 0);
+    lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[1], b.p[0], lo, 0, 0, 0);
+    if constexpr (NP == 6) {
+        lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[0], b.p[2], lo, 0, 0, 0);
+        lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[1], b.p[1], lo, 0, 0, 0);
+        lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[2], b.p[0], lo, 0, 0, 0);
+    }
 }
 
 // the part products p_i p_j' with i + j < parts, largest first
@@ -1708,11 +1872,7 @@ __device__ __forceinline__ void leg_fwd_bf16_body(const LegFwdArgs<float> &A, in
                     const double qe = (kk & 1) ? -seq : seq;
                     sum += (float)qe * xeq[col];
                 }
-                const float v = (float)A.cscale[ti] * sum;
-                if (A.atomic)
-                    atomicAdd(&A.F[ti * 8 + (col & 7)], v);
-                else
-                    A.F[ti * 8 + (col & 7)] = v;
+                A.F[group * A.gstride + ti * 8 + (col & 7)] = (float)A.cscale[ti] * sum;
             }
         }
     }
@@ -1741,14 +1901,15 @@ __device__ __forceinline__ void adj_tile_bf16(const LegArgs<float> &A, int m, in
     const int64_t t0 = tri_offset(L, m);
     const float *g = A.FG + (t0 - m) * 8;    // indexed by l'
     const double *ap = A.aprime + t0 - m;    // indexed by l'
-    const int p = tile * kTileP + lane;
+    const int base = A.P;  // the tiles start after the polar group's pairs
+    const int p = base + tile * kTileP + lane;
     const bool valid = p < NPT;
     const double z = valid ? A.pz[p] : 0.0;
     double q1 = 0.0, q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
     const int j = lane & 15, kg = lane >> 4;
-    f32x4 acc[4];
+    f32x4 acc[4], acl[4];  // leading products, correction products
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < 4; ++b) acc[b] = acl[b] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int nl = L + 2 - m;
     const int nblk = (nl + kRowsA - 1) / kRowsA;
     for (int blk = 0; blk < nblk; ++blk) {
@@ -1792,7 +1953,7 @@ __device__ __forceinline__ void adj_tile_bf16(const LegArgs<float> &A, int m, in
             Split8<NPROD> qa;
 #pragma unroll
             for (int k = 0; k < NS; ++k) qa.p[k] = __builtin_bit_cast(bf16x8_t, th[k * kTileP * 4 + slot]);
-            acc[b] = mma_split<NPROD>(qa, bs, acc[b]);
+            mma_split2<NPROD>(qa, bs, acc[b], acl[b]);
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -1800,29 +1961,39 @@ __device__ __forceinline__ void adj_tile_bf16(const LegArgs<float> &A, int m, in
     for (int b = 0; b < 4; ++b) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int pp = tile * kTileP + 16 * b + 4 * kg + r;
-            if (pp < NPT) A.PB[((size_t)m * NP + pp) * 16 + j] = acc[b][r];
+            const int pp = base + tile * kTileP + 16 * b + 4 * kg + r;
+            if (pp < NPT) A.PB[((size_t)m * NP + pp) * 16 + j] = acc[b][r] + acl[b][r];
         }
     }
 }
 
 // BF16x3/BF16x6 synthesis.  The spin-frame form divides the synthesised sums by
 // sin(theta), which near the poles amplifies the rounding of the contraction by
-// up to 1/sin(theta) ~ L; the first tile (the 64 ring pairs nearest the poles:
-// pairs are sorted by increasing sin(theta)) therefore runs on the binary32
-// MFMA path.
+// up to 1/sin(theta) ~ L.  Pairs are sorted by increasing sin(theta): the first
+// P go to the binary64 polar group (workgroup column gpolar), and the first
+// tile after them (the next 64 pairs) runs on the binary32 MFMA path.
+template <int NP>
+__device__ __forceinline__ void leg_adj_bf16_group(const LegArgs<float> &A, int m, int grp,
+                                                   unsigned char *smem_raw) {
+    if (grp == A.gpolar) {
+        adj_polar_body(A, m, reinterpret_cast<PolarRow *>(smem_raw));
+        return;
+    }
+    const int nw = blockDim.x >> 6;
+    const int wave = uniform_int(threadIdx.x >> 6);
+    const int tile = grp * nw + wave;
+    if (A.P + tile * kTileP >= A.NPT) return;
+    unsigned char *lds = smem_raw + wave * Bf16<NP>::kAdjLdsPerWave;
+    if (tile == 0)
+        adj_tile_mfma<float, float>(A, m, tile, threadIdx.x & 63, reinterpret_cast<float *>(lds));
+    else
+        adj_tile_bf16<NP>(A, m, tile, threadIdx.x & 63, reinterpret_cast<u32x4_t *>(lds));
+}
+
 template <int NP>
 __global__ __launch_bounds__(256) void k_leg_adj_bf16(LegArgs<float> A) {
     extern __shared__ unsigned char smem_raw[];
-    const int nw = blockDim.x >> 6;
-    const int wave = uniform_int(threadIdx.x >> 6);
-    const int tile = blockIdx.x * nw + wave;
-    if (tile * kTileP >= A.NPT) return;
-    unsigned char *lds = smem_raw + wave * Bf16<NP>::kAdjLdsPerWave;
-    if (tile == 0)
-        adj_tile_mfma<float, float>(A, blockIdx.y, tile, threadIdx.x & 63, reinterpret_cast<float *>(lds));
-    else
-        adj_tile_bf16<NP>(A, blockIdx.y, tile, threadIdx.x & 63, reinterpret_cast<u32x4_t *>(lds));
+    leg_adj_bf16_group<NP>(A, blockIdx.y, blockIdx.x, smem_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -1842,6 +2013,7 @@ struct CoefArgs {
     const double *cscale;   // [tri] c_{l',m}
     const double *etab;     // [tri] e_{l',m}
     const double *rsq;      // [L+2] 1 / sqrt(l (l+1)), 0 for l = 0
+    float *FGlo;            // binary32 paths: g - hi(g), [tri][8] (prep output)
     int L;
 };
 
@@ -1941,9 +2113,11 @@ __global__ __launch_bounds__(256) void k_recombine(CoefArgs<real> A) {
 template <typename real>
 __device__ __forceinline__ void prep_body(const CoefArgs<real> &A, int bx, int by) {
     // coefficients of degrees l0-1 .. l0+kTL for the tile's orders, [l][sign][a,b][m]; an
-    // odd stride between degrees keeps the 16-byte reads of consecutive degrees conflict free
+    // odd stride between degrees keeps the 16-byte reads of consecutive degrees conflict free.
+    // The map is evaluated in binary64 for every precision: the binary32 paths keep g as
+    // a binary32 pair hi + lo, whose sum the synthesis of the rings next to the poles uses.
     constexpr int kRowP = 4 * kTM + 1;
-    __shared__ C2<real> cs[(kTL + 2) * kRowP];
+    __shared__ C2<double> cs[(kTL + 2) * kRowP];
     const int L = A.L;
     const int l0 = bx * kTL, m0 = by * kTM;  // l' in [l0, l0+kTL)
     if (m0 > L || m0 > l0 + kTL - 1) return;
@@ -1967,8 +2141,8 @@ __device__ __forceinline__ void prep_body(const CoefArgs<real> &A, int bx, int b
         if (idx < kItems) {
             const int mi = idx % kTM, r = idx / kTM;
             const int l = l0 - 1 + (r >> 2);
-            const real rs = (l >= 1 && l <= L) ? (real)A.rsq[l] : (real)0;
-            cs[(r >> 2) * kRowP + (r & 3) * kTM + mi] = {v[q].x * rs, v[q].y * rs};
+            const double rs = (l >= 1 && l <= L) ? A.rsq[l] : 0.0;
+            cs[(r >> 2) * kRowP + (r & 3) * kTM + mi] = {(double)v[q].x * rs, (double)v[q].y * rs};
         }
     }
     __syncthreads();
@@ -1996,27 +2170,36 @@ __device__ __forceinline__ void prep_body(const CoefArgs<real> &A, int bx, int b
         if (m > L || lp < m || lp > L + 1) continue;
         const int64_t ti = tri_offset(L, m) + lp - m;
         const double csc = cscv[q];
-        const real c1 = (real)(csc * (lp - 1) * e0v[q]);
-        const real c2 = (real)(csc * (lp + 2) * e1v[q]);
-        const real csr = (real)csc;
+        const double c1 = csc * (lp - 1) * e0v[q];
+        const double c2 = csc * (lp + 2) * e1v[q];
+        const double csr = csc;
         C2<real> *o = A.FGout + ti * 4;
 #pragma unroll
         for (int sgn = 0; sgn < 2; ++sgn) {
             const int mu = sgn == 0 ? m : -m;
-            const real parity = (sgn == 1 && (m & 1)) ? (real)-1 : (real)1;
-            const real fmu = (real)mu;
-            const C2<real> *cm1 = cs + li * kRowP + 2 * sgn * kTM + mi, *c0 = cm1 + kRowP, *cp1 = c0 + kRowP;
-            const C2<real> am1 = cm1[0], bm1 = cm1[kTM];
-            const C2<real> a0 = c0[0], b0 = c0[kTM];
-            const C2<real> ap1 = cp1[0], bp1 = cp1[kTM];
-            C2<real> gth, gph;
+            const double parity = (sgn == 1 && (m & 1)) ? -1.0 : 1.0;
+            const double fmu = (double)mu;
+            const C2<double> *cm1 = cs + li * kRowP + 2 * sgn * kTM + mi, *c0 = cm1 + kRowP, *cp1 = c0 + kRowP;
+            const C2<double> am1 = cm1[0], bm1 = cm1[kTM];
+            const C2<double> a0 = c0[0], b0 = c0[kTM];
+            const C2<double> ap1 = cp1[0], bp1 = cp1[kTM];
+            C2<double> gth, gph;
             // -i mu b = (mu b.y, -mu b.x); +i mu a = (-mu a.y, mu a.x)
             gth.x = parity * (c1 * am1.x - c2 * ap1.x + csr * fmu * b0.y);
             gth.y = parity * (c1 * am1.y - c2 * ap1.y - csr * fmu * b0.x);
             gph.x = parity * (c1 * bm1.x - c2 * bp1.x - csr * fmu * a0.y);
             gph.y = parity * (c1 * bm1.y - c2 * bp1.y + csr * fmu * a0.x);
-            o[2 * sgn] = gth;
-            o[2 * sgn + 1] = gph;
+            if constexpr (sizeof(real) == 8) {
+                o[2 * sgn] = {gth.x, gth.y};
+                o[2 * sgn + 1] = {gph.x, gph.y};
+            } else {
+                const C2<float> th = {(float)gth.x, (float)gth.y}, ph = {(float)gph.x, (float)gph.y};
+                o[2 * sgn] = th;
+                o[2 * sgn + 1] = ph;
+                C2<float> *lo = reinterpret_cast<C2<float> *>(A.FGlo) + ti * 4;
+                lo[2 * sgn] = {(float)(gth.x - (double)th.x), (float)(gth.y - (double)th.y)};
+                lo[2 * sgn + 1] = {(float)(gph.x - (double)ph.x), (float)(gph.y - (double)ph.y)};
+            }
         }
     }
 }
@@ -2575,18 +2758,15 @@ __global__ __launch_bounds__(256, 4) void kb_leg_adj(const LegArgs<real> *__rest
     extern __shared__ unsigned char smem_raw[];
     const WorkItem w = ld_const(work + blockIdx.x);
     const LegArgs<real> A = ld_const(args + w.f);
-    const int nw = blockDim.x >> 6;
-    const int wave = uniform_int(threadIdx.x >> 6);
     if constexpr (kBf16 != 0) {
-        const int tile = w.x * nw + wave;
-        if (tile * kTileP >= A.NPT) return;
-        const int lane = threadIdx.x & 63;
-        unsigned char *lds = smem_raw + wave * Bf16<kBf16>::kAdjLdsPerWave;
-        if (tile == 0)
-            adj_tile_mfma<float, float>(A, w.y, tile, lane, reinterpret_cast<float *>(lds));
-        else
-            adj_tile_bf16<kBf16>(A, w.y, tile, lane, reinterpret_cast<u32x4_t *>(lds));
+        leg_adj_bf16_group<kBf16>(A, w.y, w.x, smem_raw);
     } else {
+        if constexpr (sizeof(real) == 4) {
+            if (w.x == A.gpolar) {
+                adj_polar_body(A, w.y, reinterpret_cast<PolarRow *>(smem_raw));
+                return;
+            }
+        }
         adj_valu_body<real>(A, w.y, w.x, reinterpret_cast<AdjRow<real> *>(smem_raw));
     }
 }
@@ -2614,6 +2794,7 @@ struct ShtArgs {
     const C2<real> *flm_in;
     C2<real> *flm_out;
     C2<real> *FG;           // [tri][4]
+    float *FGlo;            // binary32 paths: low parts of FG (see prep_body)
     const double *cscale;   // [tri] c_{l',m}
     int L;
 };
@@ -2626,22 +2807,30 @@ __global__ __launch_bounds__(256) void k_sht_coef_to_fg(ShtArgs<real> A) {
     const int lp = m + (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (m > L || lp > L + 1) return;
     const int64_t ti = tri_offset(L, m) + lp - m;
-    C2<real> gp = {0, 0}, gm = {0, 0};
+    C2<double> gp = {0, 0}, gm = {0, 0};
     if (lp <= L) {
-        const real sc = (real)A.cscale[ti];
+        const double sc = A.cscale[ti];
         const C2<real> fp = A.flm_in[(int64_t)lp * lp + lp + m];
-        gp = {sc * fp.x, sc * fp.y};
+        gp = {sc * (double)fp.x, sc * (double)fp.y};
         if (m > 0) {
             const C2<real> fm = A.flm_in[(int64_t)lp * lp + lp - m];
-            const real sg = (m & 1) ? -sc : sc;
-            gm = {sg * fm.x, sg * fm.y};
+            const double sg = (m & 1) ? -sc : sc;
+            gm = {sg * (double)fm.x, sg * (double)fm.y};
         }
     }
     C2<real> *o = A.FG + ti * 4;
-    o[0] = gp;
+    const C2<real> hp = {(real)gp.x, (real)gp.y}, hm = {(real)gm.x, (real)gm.y};
+    o[0] = hp;
     o[1] = {0, 0};
-    o[2] = gm;
+    o[2] = hm;
     o[3] = {0, 0};
+    if constexpr (sizeof(real) == 4) {
+        C2<float> *lo = reinterpret_cast<C2<float> *>(A.FGlo) + ti * 4;
+        lo[0] = {(float)(gp.x - (double)hp.x), (float)(gp.y - (double)hp.y)};
+        lo[1] = {0.f, 0.f};
+        lo[2] = {(float)(gm.x - (double)hm.x), (float)(gm.y - (double)hm.y)};
+        lo[3] = {0.f, 0.f};
+    }
 }
 
 // one thread per (m, l), l = m .. L: f_{l,+-m} from the theta columns of FG
@@ -2700,11 +2889,17 @@ static int adj_waves(int pairs, int nprod, size_t rsz) {
     return (pairs + per - 1) / per;
 }
 
+// Analysis grid: one workgroup per order m holds up to 16 tiles (waves); plans
+// with more tiles split them over `groups` workgroups, each writing a partial
+// triangle into the plan's group buffer, which k_sum_groups adds up in a fixed order.
+static int fwd_groups(const Plan &p) { return analysis_groups(p.n_pairs, p.eq_ring); }
+
 template <typename real>
-static LegFwdArgs<real> make_leg_fwd_args(const Plan &p, int atomic) {
+static LegFwdArgs<real> make_leg_fwd_args(const Plan &p, int groups) {
     LegFwdArgs<real> G{};
     G.RB = static_cast<const real *>(p.d_pb);
-    G.F = static_cast<real *>(p.d_fg);
+    G.F = static_cast<real *>(groups > 1 ? p.d_fpart : p.d_fg);
+    G.gstride = groups > 1 ? p.tri_size * 8 : 0;
     G.pairs = p.d_pairs;
     G.seeds = p.d_seeds;
     G.pz = p.d_pair_z;
@@ -2715,7 +2910,6 @@ static LegFwdArgs<real> make_leg_fwd_args(const Plan &p, int atomic) {
     G.NPT = pairs_in_tiles(p);
     G.NR = (int)p.n_rings;
     G.eq_ring = p.eq_ring;
-    G.atomic = atomic;
     return G;
 }
 
@@ -2723,6 +2917,8 @@ template <typename real>
 static LegArgs<real> make_leg_adj_args(const Plan &p) {
     LegArgs<real> G{};
     G.FG = static_cast<const real *>(p.d_fg);
+    G.FGlo = static_cast<const float *>(p.d_fglo);
+    G.gpolar = -1;
     G.PB = static_cast<real *>(p.d_pb);
     G.seeds = p.d_seeds;
     G.pz = p.d_pair_z;
@@ -2746,15 +2942,44 @@ static CoefArgs<real> make_coef_args(const Plan &p, const void *ain, const void 
     C.cscale = p.d_cscale;
     C.etab = p.d_etab;
     C.rsq = p.d_rsq;
+    C.FGlo = static_cast<float *>(p.d_fglo);
     C.L = p.L;
     return C;
 }
 
 static size_t leg_fwd_lds(int nw, size_t rsz) { return (size_t)nw * (kRowsB * kTileP + 2 * 128) * rsz; }
 static size_t leg_adj_lds(int nw, size_t rsz, int nprod) {
-    if (nprod == 3) return (size_t)nw * Bf16<3>::kAdjLdsPerWave;
-    if (nprod == 6) return (size_t)nw * Bf16<6>::kAdjLdsPerWave;
-    return 2 * kAdjChunk * (rsz == 8 ? sizeof(AdjRow<double>) : sizeof(AdjRow<float>));
+    // the binary32 paths' launches also hold the polar group (PolarRow staging)
+    const size_t polar = rsz == 4 ? 2 * kAdjChunk * sizeof(PolarRow) : 0;
+    if (nprod == 3) return std::max(polar, (size_t)nw * Bf16<3>::kAdjLdsPerWave);
+    if (nprod == 6) return std::max(polar, (size_t)nw * Bf16<6>::kAdjLdsPerWave);
+    return std::max(polar, 2 * kAdjChunk * (rsz == 8 ? sizeof(AdjRow<double>) : sizeof(AdjRow<float>)));
+}
+
+// Synthesis grid: `groups` workgroups of nw waves over the pairs [P, NPT) (at least
+// one: group 0 also forms the equator on the vector-unit path) and, on the binary32
+// paths, the polar group for pairs [0, P) in workgroup column gpolar = groups.
+struct AdjGrid {
+    int P, nw, groups, gx;
+};
+static AdjGrid adj_shape(int NPT, bool has_lo, size_t rsz, int nprod, int nw) {
+    AdjGrid a;
+    a.P = (rsz == 4 && has_lo) ? std::min(NPT, kPolarPairs) : 0;
+    const int ntile = adj_waves(NPT - a.P, nprod, rsz);
+    a.nw = nw;
+    a.groups = std::max(1, (ntile + nw - 1) / nw);
+    a.gx = a.groups + (a.P > 0 ? 1 : 0);
+    return a;
+}
+template <typename real>
+static AdjGrid adj_grid(LegArgs<real> &G, int nprod, int nw_cap) {
+    const bool lo = G.FGlo != nullptr;
+    const int ntile = adj_waves(G.NPT - ((sizeof(real) == 4 && lo) ? std::min(G.NPT, kPolarPairs) : 0),
+                                nprod, sizeof(real));
+    const AdjGrid a = adj_shape(G.NPT, lo, sizeof(real), nprod, std::max(1, std::min(ntile, nw_cap)));
+    G.P = a.P;
+    G.gpolar = a.P > 0 ? a.groups : -1;
+    return a;
 }
 
 // Analysis and synthesis launches in the plan's arithmetic.
@@ -2850,7 +3075,7 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
         G.NPT = nf.npv;
         G.NR = nf.nt / 2;
         G.eq_ring = -1;
-        G.atomic = 0;
+        G.gstride = 0;
         {
             const int ntile = (nf.npv + kTileP - 1) / kTileP;  // <= 16 for the bandlimits served
             StageScope sc(p, VSHT_STAGE_LEG_FWD, st);
@@ -2880,15 +3105,15 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
     if (e != hipSuccess) return e;
     {
         const int ntile = tiles_of(p);
-        const int ngroup = ntile > 16 ? (ntile + 15) / 16 : 1;  // at most 16 waves per workgroup
+        const int ngroup = fwd_groups(p);  // at most 16 waves per workgroup
         const int nw = ntile > 0 ? (ntile + ngroup - 1) / ngroup : 1;
-        const LegFwdArgs<real> G = make_leg_fwd_args<real>(p, ngroup > 1 ? 1 : 0);
+        const LegFwdArgs<real> G = make_leg_fwd_args<real>(p, ngroup);
         StageScope sc(p, VSHT_STAGE_LEG_FWD, st);
-        if (G.atomic) {
-            e = hipMemsetAsync(p.d_fg, 0, (size_t)p.tri_size * 8 * sizeof(real), st);
-            if (e != hipSuccess) return e;
-        }
         launch_leg_fwd<real>(G, dim3(p.L + 1, ngroup), nw, nprod, st);
+        if (ngroup > 1)
+            hipLaunchKernelGGL(k_sum_groups<real>, dim3((unsigned)((p.tri_size * 8 + 255) / 256)), dim3(256), 0,
+                               st, static_cast<const real *>(p.d_fpart), static_cast<real *>(p.d_fg),
+                               p.tri_size * 8, ngroup);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -2925,11 +3150,11 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
         G.L = p.L;
         G.NP = nf.npv;
         G.NPT = nf.npv;
+        G.FGlo = static_cast<const float *>(p.d_fglo);
         {
             StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
-            const int ntile = adj_waves(nf.npv, nprod, sizeof(real));
-            const int nw = ntile < 4 ? ntile : 4;
-            launch_leg_adj<real>(G, dim3((ntile + nw - 1) / nw, p.L + 1), nw, nprod, st);
+            const AdjGrid ag = adj_grid(G, nprod, 4);
+            launch_leg_adj<real>(G, dim3(ag.gx, p.L + 1), ag.nw, nprod, st);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -2959,14 +3184,11 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
         return hipGetLastError();
     }
 
-    const LegArgs<real> G = make_leg_adj_args<real>(p);
+    LegArgs<real> G = make_leg_adj_args<real>(p);
     {
         StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
-        const int ntile = adj_waves(pairs_in_tiles(p), nprod, sizeof(real));
-        if (ntile > 0) {
-            const int nw = ntile < 4 ? ntile : 4;
-            launch_leg_adj<real>(G, dim3((ntile + nw - 1) / nw, p.L + 1), nw, nprod, st);
-        }
+        const AdjGrid ag = adj_grid(G, nprod, 4);
+        launch_leg_adj<real>(G, dim3(ag.gx, p.L + 1), ag.nw, nprod, st);
         if (p.eq_ring >= 0 && nprod != 0)  // the vector-unit synthesis forms the equator itself
             hipLaunchKernelGGL(k_equator_adj<real>, dim3(p.L + 1), dim3(256), 0, st, G);
     }
@@ -3019,15 +3241,15 @@ static hipError_t sht_forward_impl(const Plan &p, const void *f, void *flm, hipS
     if (e != hipSuccess) return e;
     {
         const int ntile = tiles_of(p);
-        const int ngroup = ntile > 16 ? (ntile + 15) / 16 : 1;
+        const int ngroup = fwd_groups(p);  // at most 16 waves per workgroup
         const int nw = ntile > 0 ? (ntile + ngroup - 1) / ngroup : 1;
-        const LegFwdArgs<real> G = make_leg_fwd_args<real>(p, ngroup > 1 ? 1 : 0);
+        const LegFwdArgs<real> G = make_leg_fwd_args<real>(p, ngroup);
         StageScope sc(p, VSHT_STAGE_LEG_FWD, st);
-        if (G.atomic) {
-            e = hipMemsetAsync(p.d_fg, 0, (size_t)p.tri_size * 8 * sizeof(real), st);
-            if (e != hipSuccess) return e;
-        }
         launch_leg_fwd<real>(G, dim3(p.L + 1, ngroup), nw, nprod, st);
+        if (ngroup > 1)
+            hipLaunchKernelGGL(k_sum_groups<real>, dim3((unsigned)((p.tri_size * 8 + 255) / 256)), dim3(256), 0,
+                               st, static_cast<const real *>(p.d_fpart), static_cast<real *>(p.d_fg),
+                               p.tri_size * 8, ngroup);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -3047,6 +3269,7 @@ static hipError_t sht_adjoint_impl(const Plan &p, const void *flm, void *f, hipS
     ShtArgs<real> S{};
     S.flm_in = static_cast<const C2<real> *>(flm);
     S.FG = static_cast<C2<real> *>(p.d_fg);
+    S.FGlo = static_cast<float *>(p.d_fglo);
     S.cscale = p.d_cscale;
     S.L = p.L;
     {
@@ -3055,14 +3278,11 @@ static hipError_t sht_adjoint_impl(const Plan &p, const void *flm, void *f, hipS
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const LegArgs<real> G = make_leg_adj_args<real>(p);
+    LegArgs<real> G = make_leg_adj_args<real>(p);
     {
         StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
-        const int ntile = adj_waves(pairs_in_tiles(p), nprod, sizeof(real));
-        if (ntile > 0) {
-            const int nw = ntile < 4 ? ntile : 4;
-            launch_leg_adj<real>(G, dim3((ntile + nw - 1) / nw, p.L + 1), nw, nprod, st);
-        }
+        const AdjGrid ag = adj_grid(G, nprod, 4);
+        launch_leg_adj<real>(G, dim3(ag.gx, p.L + 1), ag.nw, nprod, st);
         if (p.eq_ring >= 0 && nprod != 0)
             hipLaunchKernelGGL(k_equator_adj<real>, dim3(p.L + 1), dim3(256), 0, st, G);
     }
@@ -3144,7 +3364,7 @@ static hipError_t batch_alloc_args(BatchState *b) {
     auto *lf = reinterpret_cast<LegFwdArgs<real> *>(b->h_lfwd.data());
     for (size_t i = 0; i < F; ++i) {
         la[i] = make_leg_adj_args<real>(*b->f[i]);
-        lf[i] = make_leg_fwd_args<real>(*b->f[i], 0);
+        lf[i] = make_leg_fwd_args<real>(*b->f[i], 1);
     }
     if ((e = hipMemcpy(b->d_ladj, b->h_ladj.data(), b->h_ladj.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return e;
@@ -3177,6 +3397,19 @@ void batch_destroy(BatchState *b) {
 }
 
 BatchConfig batch_config(const BatchState *b) { return b->cfg; }
+
+// The synthesis argument blocks' polar group column follows the workgroup width.
+template <typename real>
+static hipError_t batch_set_polar(BatchState *b) {
+    auto *la = reinterpret_cast<LegArgs<real> *>(b->h_ladj.data());
+    for (size_t i = 0; i < b->f.size(); ++i) {
+        const AdjGrid ag = adj_shape(la[i].NPT, la[i].FGlo != nullptr, sizeof(real),
+                                     bf16_products(b->precision), b->cfg.adj_nw);
+        la[i].P = ag.P;
+        la[i].gpolar = ag.P > 0 ? ag.groups : -1;
+    }
+    return hipMemcpy(b->d_ladj, b->h_ladj.data(), b->h_ladj.size(), hipMemcpyHostToDevice);
+}
 
 // Work lists for a configuration.  Item costs (for the longest-first order):
 // ring stages n_phi, Legendre stages (degrees of the order) x (tiles in the
@@ -3213,17 +3446,25 @@ hipError_t batch_configure(BatchState *b, const BatchConfig &cfg) {
     }
     emit(BS_PREP, 4, items, 0);
     items.clear();
-    // Legendre synthesis: one shape for every field
+    // Legendre synthesis: one shape for every field; the polar group (binary32
+    // paths) is work item column `groups` of its field
     size_t lds_adj = leg_adj_lds(cfg.adj_nw, rsz, nprod);
     for (int i = 0; i < F; ++i) {
         const Plan &p = *b->f[i];
-        const int ntile = adj_waves(pairs_in_tiles(p), nprod, rsz);
-        for (int tg = 0; tg * cfg.adj_nw < ntile; ++tg) {
-            const int nt = std::min(cfg.adj_nw, ntile - tg * cfg.adj_nw);
+        const AdjGrid ag = adj_shape(pairs_in_tiles(p), p.d_fglo != nullptr, rsz, nprod, cfg.adj_nw);
+        const int ntile = adj_waves(pairs_in_tiles(p) - ag.P, nprod, rsz);
+        for (int tg = 0; tg < ag.groups; ++tg) {
+            const int nt = std::max(1, std::min(cfg.adj_nw, ntile - tg * cfg.adj_nw));
             for (int m = 0; m <= p.L; ++m) items.push_back({{i, tg, m, 0}, (double)(p.L + 2 - m) * nt});
         }
+        if (ag.P > 0)
+            for (int m = 0; m <= p.L; ++m) items.push_back({{i, ag.groups, m, 0}, (double)(p.L + 2 - m)});
     }
     emit(BS_LEG_ADJ, cfg.adj_nw, items, lds_adj);
+    {
+        hipError_t e = b->precision == VSHT_FP64 ? batch_set_polar<double>(b) : batch_set_polar<float>(b);
+        if (e != hipSuccess) return e;
+    }
     items.clear();
     for (int i = 0; i < F; ++i)
         if (b->f[i]->eq_ring >= 0 && nprod != 0)  // the vector-unit synthesis forms the equator itself

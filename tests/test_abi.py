@@ -147,3 +147,52 @@ def test_batch_calls_reject_null_plan():
     assert lib.vsht_batch_forward(None, None, None, None, None) == B.VSHT_EINVAL
     assert lib.vsht_batch_set_config(None, 4, 0, 1, 256) == B.VSHT_EINVAL
     assert lib.vsht_batch_field_times(None, None, None) == B.VSHT_EINVAL
+
+
+def _shell_plan(precision="fp64"):
+    """A Plan object without a native handle: the binding's argument checks run in
+    Python before any C call, so they can be exercised on the CPU."""
+    import torch
+    p = B.Plan.__new__(B.Plan)
+    p.device = torch.device("cpu")
+    p.L, p.n, p.K = 4, 10, 24
+    p.precision = precision
+    p.dtype = torch.complex128 if precision == "fp64" else torch.complex64
+    p._h = None
+    return p
+
+
+@pytest.mark.parametrize("case", ["short_a", "dtype_b", "noncontig_T", "short_T", "dtype_flm"])
+def test_binding_rejects_bad_outputs(case):
+    """Caller-supplied output tensors are checked (shape, dtype, device, contiguity)
+    before the library is called; a bad one raises instead of being written past its end
+    or into a temporary copy."""
+    import torch
+    p = _shell_plan()
+    c = lambda *s: torch.zeros(s, dtype=torch.complex128)
+    T, a, b = c(10, 3), c(24), c(24)
+    with pytest.raises(ValueError):
+        if case == "short_a":
+            p.forward(T, a=c(23), b=b)
+        elif case == "dtype_b":
+            p.forward(T, a=a, b=torch.zeros(24, dtype=torch.complex64))
+        elif case == "noncontig_T":
+            p.adjoint(a, b, T=c(3, 10).t())
+        elif case == "short_T":
+            p.adjoint(a, b, T=c(9, 3))
+        else:
+            p.sht_forward(torch.zeros(10, dtype=torch.complex128), flm=c(24))
+
+
+def test_binding_rejects_bad_batch_outputs():
+    import torch
+    bp = B.BatchPlan.__new__(B.BatchPlan)
+    bp.device = torch.device("cpu")
+    bp.dtype = torch.complex64
+    bp.Ls, bp.ns, bp.Ks = [4], [10], [24]
+    bp._h = None
+    a = [torch.zeros(24, dtype=torch.complex64)]
+    with pytest.raises(ValueError):
+        bp.adjoint(a, a, T=[torch.zeros(3, 10, dtype=torch.complex64).t()])
+    with pytest.raises(ValueError):
+        bp.forward([torch.zeros(10, 3, dtype=torch.complex64)], a=[torch.zeros(23, dtype=torch.complex64)])

@@ -11,7 +11,14 @@ import vsht_inputs as vi
 pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-11
-FP32_TOL = 2e-5
+# FP32 gradient bound.  The backward of the adjoint is the unit-weight forward,
+# whose spin-frame analysis weights each point by 1 / sin(theta) (on a GL grid
+# the quadrature weight, proportional to sin(theta), cancels it in the weighted
+# forward); the recombination cancels those large polar terms again, so their
+# binary32 rounding is amplified by up to ~L / 2.4 at the polar rings.  Measured
+# at L = 64: 9.1e-7; bound 2e-6.  The FP32 case feeds both sides the same
+# binary32-representable inputs.
+FP32_TOL = 2e-6
 
 
 def rel_l2(x, y):
@@ -116,6 +123,8 @@ def test_oracle_gradient_L64(torch, vsht, orc, precision, tol):
     a_t, b_t, noise = target_field(L, 1, xyz)
     Tt = orc.adjoint(L, a_t[0], b_t[0], xyz) + noise[0]
     a0, b0 = vi.random_coeffs(L, 31)
+    if precision != "fp64":
+        Tt, a0, b0 = (x.astype(np.complex64).astype(np.complex128) for x in (Tt, a0, b0))
     r = orc.adjoint(L, a0, b0, xyz) - Tt
     ga_ref, gb_ref = orc.forward(L, xyz, np.ones(len(xyz)), r)
     ga_ref, gb_ref = 2 * ga_ref, 2 * gb_ref
