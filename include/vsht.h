@@ -152,6 +152,23 @@ vsht_status vsht_forward_unweighted(vsht_plan_t plan, const void *T, void *a, vo
  * (device, n x 3) at every point of the plan, in the plan's point order. */
 vsht_status vsht_adjoint(vsht_plan_t plan, const void *a, const void *b, void *T, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): vsht_forward on a ring plan
+ * with its intermediate buffers (ring-Fourier buffer, coefficient triangle, and
+ * for plans over 1024 ring pairs the partial triangles) in a static device array
+ * of VSHT_STATIC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends, instead of the plan's workspace.  Same arguments,
+ * layouts and results as vsht_forward (the same kernels).  The call performs
+ * no allocation: no hipMalloc/hipFree, no events, no stage timing.
+ *   VSHT_EUNSUPPORTED  scattered plans, or a plan that needs more than
+ *                      VSHT_STATIC_SCRATCH_BYTES (vsht_last_error gives the size);
+ *                      FP64 plans fit up to the GL grid at L = 1024.
+ *   VSHT_ENOWEIGHTS    plan without weights.
+ * All calls on one GPU share the array: calls that overlap on one GPU (on
+ * different streams, or from several threads) race and give wrong results. */
+#define VSHT_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+vsht_status vsht_forward_static(vsht_plan_t plan, const void *T, void *a, void *b, void *stream);
+
 /* Scalar transforms on ring plans, with the same stages (scalar coefficients
  * f_{l,m}, 0 <= l <= L, |m| <= l, at index l^2 + l + m; vsht_num_sht_coeffs(L)
  * = (L+1)^2 of them; complex128 for VSHT_FP64, complex64 otherwise).

@@ -7,13 +7,14 @@ this package only marshals arguments.  PyTorch provides device memory and
 streams.
 """
 from ._binding import (EXPORTED, LIB_PATH, PRECISIONS, BatchPlan, Plan, VshtError, load_library,
-                       vsht_adjoint, vsht_forward, vsht_forward_unweighted, vsht_num_coeffs,
+                       vsht_adjoint, vsht_forward, vsht_forward_unweighted, vsht_forward_static,
+                       vsht_num_coeffs,
                        vsht_plan, vsht_plan_destroy, vsht_plan_info, vsht_forward_many,
                        vsht_adjoint_many, vsht_num_sht_coeffs, vsht_sht_forward,
                        vsht_sht_adjoint, VSHT_UNIT_WEIGHTS, VSHT_TIMES_WEIGHTS)
 
 __all__ = ["Plan", "BatchPlan", "VshtError", "load_library", "vsht_num_coeffs", "vsht_plan", "vsht_forward",
-           "vsht_forward_unweighted", "vsht_adjoint", "vsht_plan_info", "vsht_plan_destroy",
+           "vsht_forward_unweighted", "vsht_forward_static", "vsht_adjoint", "vsht_plan_info", "vsht_plan_destroy",
            "vsht_forward_many", "vsht_adjoint_many", "vsht_num_sht_coeffs", "vsht_sht_forward",
            "vsht_sht_adjoint", "VSHT_UNIT_WEIGHTS", "VSHT_TIMES_WEIGHTS",
            "EXPORTED", "LIB_PATH", "PRECISIONS", "AdjointVSHT", "ForwardVSHT", "adjoint_vsht",

@@ -24,7 +24,7 @@ EXPORTED = ("vsht_num_coeffs", "vsht_plan", "vsht_forward", "vsht_forward_unweig
             "vsht_forward_many", "vsht_adjoint_many", "vsht_plan_batch", "vsht_batch_adjoint",
             "vsht_batch_forward", "vsht_batch_roundtrip", "vsht_batch_set_config",
             "vsht_batch_get_config", "vsht_batch_autotune", "vsht_batch_field_times",
-            "vsht_num_sht_coeffs", "vsht_sht_forward", "vsht_sht_adjoint")
+            "vsht_num_sht_coeffs", "vsht_sht_forward", "vsht_sht_adjoint", "vsht_forward_static")
 VSHT_UNIT_WEIGHTS, VSHT_TIMES_WEIGHTS = 1, 2
 STAGES = ("ring_fwd", "leg_fwd", "recombine", "prep", "leg_adj", "ring_adj", "scattered")
 
@@ -67,7 +67,7 @@ def load_library(path=LIB_PATH):
     lib.vsht_num_coeffs.restype = i64
     lib.vsht_plan.argtypes = [ci, i64, vp, vp, ctypes.POINTER(vsht_opts), ctypes.POINTER(vp)]
     lib.vsht_plan.restype = ci
-    for name in ("vsht_forward", "vsht_forward_unweighted"):
+    for name in ("vsht_forward", "vsht_forward_unweighted", "vsht_forward_static"):
         getattr(lib, name).argtypes = [vp, vp, vp, vp, vp]
         getattr(lib, name).restype = ci
     lib.vsht_adjoint.argtypes = [vp, vp, vp, vp, vp]
@@ -138,6 +138,10 @@ def vsht_forward(plan, T_ptr, a_ptr, b_ptr, stream):
 
 def vsht_forward_unweighted(plan, T_ptr, a_ptr, b_ptr, stream):
     return load_library().vsht_forward_unweighted(plan, T_ptr, a_ptr, b_ptr, stream)
+
+
+def vsht_forward_static(plan, T_ptr, a_ptr, b_ptr, stream):
+    return load_library().vsht_forward_static(plan, T_ptr, a_ptr, b_ptr, stream)
 
 
 def vsht_adjoint(plan, a_ptr, b_ptr, T_ptr, stream):

@@ -775,6 +775,23 @@ vsht_status vsht_forward_unweighted(vsht_plan_t plan, const void *T, void *a, vo
     return e == hipSuccess ? VSHT_OK : hip_fail(e, "forward launch");
 }
 
+vsht_status vsht_forward_static(vsht_plan_t plan, const void *T, void *a, void *b, void *stream) {
+    static_assert(VSHT_STATIC_SCRATCH_BYTES == kStaticScratchBytes, "one scratch size");
+    vsht_status s = check_call(plan, T, a, b);
+    if (s != VSHT_OK) return s;
+    const Plan &P = plan->p;
+    if (!P.has_weights) return fail(VSHT_ENOWEIGHTS, "forward needs a plan created with weights");
+    if (P.kind != VSHT_PLAN_RINGS) return fail(VSHT_EUNSUPPORTED, "the static-scratch forward needs a ring plan");
+    const size_t need = static_forward_bytes(P);
+    if (need > kStaticScratchBytes)
+        return fail(VSHT_EUNSUPPORTED, "the plan needs " + std::to_string(need) +
+                                           " bytes of scratch; the static array holds " +
+                                           std::to_string(kStaticScratchBytes));
+    DeviceGuard guard(P.device);
+    hipError_t e = launch_forward_static(P, T, a, b, (hipStream_t)stream);
+    return e == hipSuccess ? VSHT_OK : hip_fail(e, "static-scratch forward launch");
+}
+
 vsht_status vsht_adjoint(vsht_plan_t plan, const void *a, const void *b, void *T, void *stream) {
     vsht_status s = check_call(plan, a, b, T);
     if (s != VSHT_OK) return s;

@@ -191,8 +191,8 @@ struct StageScope {
     hipStream_t st;
     Plan::StageRecord rec{};
     bool on;
-    StageScope(const Plan &plan, int stage, hipStream_t stream) : p(plan), st(stream) {
-        on = plan.timing != 0;
+    StageScope(const Plan &plan, int stage, hipStream_t stream, bool allowed = true) : p(plan), st(stream) {
+        on = allowed && plan.timing != 0;
         if (on) {
             rec.stage = stage;
             on = hipEventCreate(&rec.start) == hipSuccess;
@@ -223,6 +223,12 @@ hipError_t launch_forward(const Plan &p, const void *T, void *a, void *b, bool w
 hipError_t launch_adjoint(const Plan &p, const void *a, const void *b, void *T, bool weighted,
                           hipStream_t st);
 hipError_t launch_sht_forward(const Plan &p, const void *f, void *flm, hipStream_t st);
+// The weighted forward of a ring plan with its intermediate buffers in the library's
+// static device array (no allocation, no stage timing).  *need receives the bytes the
+// plan needs; hipErrorInvalidValue when they exceed kStaticScratchBytes.
+constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+size_t static_forward_bytes(const Plan &p);
+hipError_t launch_forward_static(const Plan &p, const void *T, void *a, void *b, hipStream_t st);
 hipError_t launch_sht_adjoint(const Plan &p, const void *flm, void *f, hipStream_t st);
 hipError_t launch_seed_kernel(const double *pair_s, int NP, int L, double *seeds, hipStream_t st);
 hipError_t set_kernel_attributes();

@@ -20,6 +20,8 @@
 // the contraction runs in the plan's arithmetic type.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <math.h>
 #include <stdint.h>
 
@@ -3042,8 +3044,15 @@ static NfftArgs<real> make_nfft_args(const Plan &p, const void *Tin, void *Tout,
     return N;
 }
 
+// Intermediate buffers of a forward transform: the plan's workspace, or the
+// static scratch array (allocation-free entry point, no stage timing).
+struct FwdWork {
+    void *rb, *fg, *fpart;
+    bool timed;
+};
+
 template <typename real>
-static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, bool weighted,
+static hipError_t forward_impl(const Plan &p, const FwdWork &ws, const void *T, void *a, void *b, bool weighted,
                                hipStream_t st) {
     const int nprod = bf16_products(p.precision);
     if (p.kind == VSHT_PLAN_SCATTERED) {
@@ -3091,9 +3100,10 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
         }
         return hipGetLastError();
     }
-    const RingArgs<real> R = make_ring_args<real>(p, T, nullptr, weighted);
+    RingArgs<real> R = make_ring_args<real>(p, T, nullptr, weighted);
+    R.buf = static_cast<C2<real> *>(ws.rb);
     {
-        StageScope sc(p, VSHT_STAGE_RING_FWD, st);
+        StageScope sc(p, VSHT_STAGE_RING_FWD, st, ws.timed);
         if (p.ring_nt_min == kRingNTSmall && p.max_fft_len <= kMaxLenSmallRing)
             hipLaunchKernelGGL((k_ring_fwd<real, kRingNTSmall>), dim3((unsigned)p.n_rings), dim3(kRingNTSmall),
                                ring_lds_bytes(p, sizeof(real)), st, R);
@@ -3107,19 +3117,22 @@ static hipError_t forward_impl(const Plan &p, const void *T, void *a, void *b, b
         const int ntile = tiles_of(p);
         const int ngroup = fwd_groups(p);  // at most 16 waves per workgroup
         const int nw = ntile > 0 ? (ntile + ngroup - 1) / ngroup : 1;
-        const LegFwdArgs<real> G = make_leg_fwd_args<real>(p, ngroup);
-        StageScope sc(p, VSHT_STAGE_LEG_FWD, st);
+        LegFwdArgs<real> G = make_leg_fwd_args<real>(p, ngroup);
+        G.RB = static_cast<const real *>(ws.rb);
+        G.F = static_cast<real *>(ngroup > 1 ? ws.fpart : ws.fg);
+        StageScope sc(p, VSHT_STAGE_LEG_FWD, st, ws.timed);
         launch_leg_fwd<real>(G, dim3(p.L + 1, ngroup), nw, nprod, st);
         if (ngroup > 1)
             hipLaunchKernelGGL(k_sum_groups<real>, dim3((unsigned)((p.tri_size * 8 + 255) / 256)), dim3(256), 0,
-                               st, static_cast<const real *>(p.d_fpart), static_cast<real *>(p.d_fg),
+                               st, static_cast<const real *>(ws.fpart), static_cast<real *>(ws.fg),
                                p.tri_size * 8, ngroup);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const CoefArgs<real> C = make_coef_args<real>(p, nullptr, nullptr, a, b);
+    CoefArgs<real> C = make_coef_args<real>(p, nullptr, nullptr, a, b);
+    C.FG = static_cast<const C2<real> *>(ws.fg);
     {
-        StageScope sc(p, VSHT_STAGE_RECOMBINE, st);
+        StageScope sc(p, VSHT_STAGE_RECOMBINE, st, ws.timed);
         hipLaunchKernelGGL(k_recombine<real>, dim3((p.L + kTL - 1) / kTL, (p.L + 1 + kTM - 1) / kTM),
                            dim3(256), 0, st, C);
     }
@@ -3211,8 +3224,9 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
 
 hipError_t launch_forward(const Plan &p, const void *T, void *a, void *b, bool weighted,
                           hipStream_t st) {
-    if (p.precision == VSHT_FP64) return forward_impl<double>(p, T, a, b, weighted, st);
-    return forward_impl<float>(p, T, a, b, weighted, st);
+    const FwdWork ws{p.d_pb, p.d_fg, p.d_fpart, true};
+    if (p.precision == VSHT_FP64) return forward_impl<double>(p, ws, T, a, b, weighted, st);
+    return forward_impl<float>(p, ws, T, a, b, weighted, st);
 }
 
 hipError_t launch_adjoint(const Plan &p, const void *a, const void *b, void *T, bool weighted,
@@ -3311,6 +3325,62 @@ hipError_t launch_sht_forward(const Plan &p, const void *f, void *flm, hipStream
 hipError_t launch_sht_adjoint(const Plan &p, const void *flm, void *f, hipStream_t st) {
     if (p.precision == VSHT_FP64) return sht_adjoint_impl<double>(p, flm, f, st);
     return sht_adjoint_impl<float>(p, flm, f, st);
+}
+
+// ===========================================================================
+// Allocation-free forward: the ring buffer, the triangle and (over 1024 ring
+// pairs) the partial triangles live in `scratch`, a static device array of
+// kStaticScratchBytes that the loader reserves on every GPU the library runs
+// on.  Its device address is looked up once per device (with that device
+// current) and kept; host code uses only that address.  Calls that overlap on
+// one GPU share the array and race.  The forward writes every element it later
+// reads, so nothing needs clearing.
+// ===========================================================================
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // namespace
+
+size_t static_forward_bytes(const Plan &p) {
+    const size_t rsz = p.precision == VSHT_FP64 ? 8 : 4;
+    const int groups = fwd_groups(p);
+    const size_t rb = (size_t)(p.L + 1) * p.n_rings * 8 * rsz;
+    const size_t fg = (size_t)(p.tri_size + kFgPadRows) * 8 * rsz;
+    const size_t part = groups > 1 ? (size_t)groups * p.tri_size * 8 * rsz : 0;
+    return round256(rb) + round256(fg) + round256(part);
+}
+
+hipError_t launch_forward_static(const Plan &p, const void *T, void *a, void *b, hipStream_t st) {
+    if (p.kind != VSHT_PLAN_RINGS || static_forward_bytes(p) > kStaticScratchBytes) return hipErrorInvalidValue;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    unsigned char *base = nullptr;
+    if ((e = scratch_address(dev, reinterpret_cast<void **>(&base))) != hipSuccess) return e;
+    const size_t rsz = p.precision == VSHT_FP64 ? 8 : 4;
+    const size_t rb = round256((size_t)(p.L + 1) * p.n_rings * 8 * rsz);
+    const size_t fg = round256((size_t)(p.tri_size + kFgPadRows) * 8 * rsz);
+    const FwdWork ws{base, base + rb, base + rb + fg, false};
+    if (p.precision == VSHT_FP64) return forward_impl<double>(p, ws, T, a, b, true, st);
+    return forward_impl<float>(p, ws, T, a, b, true, st);
 }
 
 // ===========================================================================
