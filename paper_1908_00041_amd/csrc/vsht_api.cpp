@@ -70,7 +70,7 @@ hipError_t upload(T **dst, const std::vector<T> &src, size_t *bytes) {
 void free_plan_memory(Plan *p) {
     const NfftPlan &nf = p->nfft;
     void *ptrs[] = {p->d_rings, p->d_pairs, p->d_ffts, p->d_tw,  p->d_pair_z, p->d_aprime,
-                    p->d_cscale, p->d_etab, p->d_rsq,  p->d_seeds, p->d_weights, p->d_xyz, p->d_pb,  p->d_fg,  p->d_fglo, p->d_fpart,
+                    p->d_cscale, p->d_etab, p->d_rsq,  p->d_seeds, p->d_weights, p->d_xyz, p->d_pb,  p->d_fg,  p->d_fg64, p->d_fpart,
                     p->d_state, nf.d_ffts, nf.d_tw, nf.d_vpairs, nf.d_vz, nf.d_vs, nf.d_vseeds, nf.d_psihat, nf.d_pts,
                     nf.d_vpb, nf.d_g1, nf.d_g};
     for (void *q : ptrs)
@@ -624,9 +624,10 @@ vsht_status build_plan(Plan &P, int L, int64_t n, const double *xyz, const doubl
             if ((e = hipMalloc(&P.d_pb, pb)) != hipSuccess) goto hip_error;
             if ((e = hipMalloc(&P.d_fg, fg)) != hipSuccess) goto hip_error;
             P.workspace_bytes = pb + fg;
-            if (rsz == 4) {
-                if ((e = hipMalloc(&P.d_fglo, fg)) != hipSuccess) goto hip_error;
-                P.workspace_bytes += fg;
+            if (rsz == 4) {  // the adjoint's g in binary64 as well
+                const size_t fg64 = (size_t)(P.tri_size + kFgPadRows) * 4 * 2 * 8;
+                if ((e = hipMalloc(&P.d_fg64, fg64)) != hipSuccess) goto hip_error;
+                P.workspace_bytes += fg64;
             }
             const int groups = analysis_groups(P.n_pairs, P.eq_ring);
             if (groups > 1) {
@@ -647,8 +648,9 @@ vsht_status build_plan(Plan &P, int L, int64_t n, const double *xyz, const doubl
         if ((e = hipMalloc(&P.d_fg, fg)) != hipSuccess) goto hip_error;
         P.workspace_bytes = fg;
         if (rsz == 4) {
-            if ((e = hipMalloc(&P.d_fglo, fg)) != hipSuccess) goto hip_error;
-            P.workspace_bytes += fg;
+            const size_t fg64 = (size_t)(P.tri_size + kFgPadRows) * 4 * 2 * 8;
+            if ((e = hipMalloc(&P.d_fg64, fg64)) != hipSuccess) goto hip_error;
+            P.workspace_bytes += fg64;
         }
         if (!(flags & VSHT_OPT_SCATTERED_DIRECT) && L <= kMaxNfftL) {
             e = build_nfft(P, n, xyz);

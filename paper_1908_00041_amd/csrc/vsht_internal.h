@@ -125,8 +125,9 @@ struct NfftPlan {
 //  FG   triangle buffer [tri(L)][4] complex, tri index (m, l') for
 //       0 <= m <= L, m <= l' <= L+1: forward F, adjoint prep g; followed by
 //       kFgPadRows rows that the synthesis may load (never use) past the end.
-//  FGlo (binary32 paths) the adjoint's g - hi(g) in binary32, same layout as FG,
-//       read by the binary64 polar group of the synthesis.
+//  FG64 (binary32 paths) the adjoint's g in binary64, FG's layout: the synthesis
+//       runs in binary64 on the vector unit (binary32 path) or, for the pairs next
+//       to the poles, in a binary64 polar wave (split-bf16 paths).
 constexpr int kFgPadRows = 8;
 
 // Workgroups per order of the ring analysis: up to 16 tiles of 64 ring pairs
@@ -170,8 +171,9 @@ struct Plan {
     // workspace
     void *d_pb = nullptr;
     void *d_fg = nullptr;
-    void *d_fglo = nullptr;        // binary32 paths: low parts of the adjoint's FG, [tri][8] float
+    void *d_fg64 = nullptr;        // binary32 paths: the adjoint's g in binary64, [tri][8] double
     void *d_fpart = nullptr;       // analysis split over g > 1 workgroups per order: [g][tri][8]
+
     void *d_state = nullptr;       // Legendre recurrence state
     size_t workspace_bytes = 0;
     int n_ffts = 0;
@@ -231,6 +233,7 @@ size_t static_forward_bytes(const Plan &p);
 hipError_t launch_forward_static(const Plan &p, const void *T, void *a, void *b, hipStream_t st);
 hipError_t launch_sht_adjoint(const Plan &p, const void *flm, void *f, hipStream_t st);
 hipError_t launch_seed_kernel(const double *pair_s, int NP, int L, double *seeds, hipStream_t st);
+
 hipError_t set_kernel_attributes();
 
 // Batches (vsht_kernels.hip): every field of a batch in one launch per stage.

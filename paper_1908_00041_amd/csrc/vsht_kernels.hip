@@ -1221,7 +1221,8 @@ __global__ __launch_bounds__(1024) void k_leg_fwd_mfma(LegFwdArgs<real> A) {
 template <typename real>
 struct LegArgs {
     const real *FG;       // [tri][8]
-    const float *FGlo;    // binary32 paths: FG's low parts (hi + lo = the binary64 g)
+    const double *FG64;   // g as binary64 rows, [tri][8]: FG itself on the binary64 path, the
+                          // plan's binary64 triangle (written by the prep) on the binary32 paths
     real *PB;             // [(L+1)][NP][16]
     const double *seeds;
     const double *pz;
@@ -1229,40 +1230,32 @@ struct LegArgs {
     int L;
     int NP;
     int NPT;              // pairs handled by the tiles (the equator, if any, is pair NPT)
-    int P;                // pairs [0, P) (nearest the poles) go to the binary64 polar group
-    int gpolar;           // workgroup column (blockIdx.x) of the polar group, or -1
+
 };
 
-// Ring pairs of the binary32 syntheses that run in binary64 (the polar group).
+// Ring pairs of the split-bf16 syntheses that run in binary64 (the polar unit).
 // The spin-frame synthesis divides by sin(theta) a sum whose terms near the
-// poles are up to ~1/sin(theta) larger than the sum, so binary32 rounding of the
-// Legendre values and of g is amplified there; over the L + 1 rings of a
-// Gauss-Legendre grid the squared error of ring r falls off as 1/r^2, and the
-// 32 pairs nearest the poles carry all but a few percent of it.
+// poles are up to ~1/sin(theta) larger than the sum, so a rounding of the
+// Legendre values or of g becomes eps / sin(theta) at that ring; over the L + 1
+// rings of a Gauss-Legendre grid the squared error of ring r falls off as 1/r^2,
+// and the 32 pairs nearest the poles carry all but a few percent of it.
 constexpr int kPolarPairs = 32;
-constexpr int kPolarMaxPerLane = 4;  // pairs per lane of a polar group of one wave
 
-// Synthesis on the vector unit.  A workgroup takes one order m; each lane
-// carries AdjPPL<real>::n ring pairs through the degrees l' = m .. L+1, and each degree
-// costs, per pair, the recurrence step and eight FMAs (the four complex columns
-// of g, into the even or the odd sum).  a'_{l'} and g[l'] are the same for the
-// whole workgroup: kAdjChunk degrees at a time are staged in LDS with
-// coalesced loads issued one chunk ahead, and every lane reads them back
-// (broadcast) as vector operands.  On gfx950 the binary64 vector FMA rate
-// equals the binary64 matrix-core rate and the two share one pipe, so this
-// form gives up nothing to the matrix cores and needs neither the LDS staging
-// of the Legendre values nor products on zero parity blocks.
-// Ring pairs per lane: every staged value feeds that many FMAs.  Two in binary64,
-// where the broadcast FMAs share the LDS reads; one in binary32 (twice the waves).
-template <typename real>
-struct AdjPPL {
-    static constexpr int n = sizeof(real) == 8 ? 2 : 1;
-};
+// Synthesis on the vector unit, binary64.  Each lane carries PPL ring pairs
+// through a range of degrees, and each degree costs, per pair, the recurrence
+// step and eight FMAs (the four complex columns of g, into the even or the odd
+// sum).  a'_{l'} and g[l'] are the same for the whole wave: kAdjChunk degrees at a
+// time are staged in the wave's LDS buffer with coalesced loads issued one chunk
+// ahead, and every FMA takes its g value by DPP row broadcast.  On gfx950 the
+// binary64 vector FMA rate equals the binary64 matrix-core rate and the
+// binary32 vector rate (without packed binary32), so this form serves the
+// binary32 path too (g then comes from the plan's binary64 triangle FG64 and only
+// the sums are stored in binary32), and it needs neither the LDS staging of the
+// Legendre values nor products on zero parity blocks.
 constexpr int kAdjChunk = 32;  // degrees per LDS buffer (two buffers)
-template <typename real>
 struct alignas(16) AdjRow {
-    real g[8];  // g[l'] (theta, phi) x (+m, -m), complex
-    double a;   // a'_{l'}
+    double g[8];  // g[l'] (theta, phi) x (+m, -m), complex
+    double a;     // a'_{l'}
 };
 
 // acc += bcast_k(g) * r, where bcast_k(g) is g of lane k of the lane's row of 16
@@ -1287,43 +1280,35 @@ __device__ __forceinline__ void fmac_row_bcast8(double (&S)[8], double g, double
     if constexpr (C + 1 < 8) fmac_row_bcast8<K0, C + 1>(S, g, r);
 }
 
-// Degree l' of one row for the pairs of a lane, into the sums S.
-template <typename real, int kAdjPPL = AdjPPL<real>::n>
-__device__ __forceinline__ void adj_row_step(const AdjRow<real> &R, const double (&z)[kAdjPPL],
-                                             double (&q1)[kAdjPPL], double (&q2)[kAdjPPL],
-                                             real (&S)[kAdjPPL][8]) {
-#pragma unroll
-    for (int u = 0; u < kAdjPPL; ++u) {
-        const double v = fma(R.a * z[u], q1[u], -q2[u]);
-        const real r = (real)v;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) S[u][c] = fma(r, R.g[c], S[u][c]);
-        q2[u] = q1[u];
-        q1[u] = v;
-    }
+template <int K0, int N, int C = 0>
+__device__ __forceinline__ void fmac_row_bcastn(double (&S)[N], double g, double r) {
+    fmac_row_bcast<K0 + C, C == 0>(S[C], g, r);
+    if constexpr (C + 1 < N) fmac_row_bcastn<K0, N, C + 1>(S, g, r);
 }
 
-// One workgroup (any number of waves) of order m; wave w of group `grp` takes
-// ring pairs ((grp * waves + w) * P + u) * 64 + lane, P = AdjPPL<real>::n.  Every wave takes
-// part in the staging and its barriers, also one without pairs.  Group 0 also
-// forms the equator pair (index NPT, when NP > NPT) from the staged rows: at
-// z = 0 the scaled recurrence gives Q_{m+2k} = (-1)^k Q_m and Q_{m+2k+1} = 0,
-// so its even sum is Lambda_{m,m}(0) sum_k (-1)^k g[m + 2k] and its odd sum 0.
-template <typename real>
-__device__ __forceinline__ void adj_valu_body(const LegArgs<real> &A, int m, int grp, AdjRow<real> *buf) {
-    constexpr int kAdjPPL = AdjPPL<real>::n;
-    const int nt = blockDim.x, nw = nt >> 6;
-    const int wave = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
+// One workgroup of order m, all its waves staging g and a' together (kAdjChunk
+// rows at a time, two buffers, coalesced loads one chunk ahead); the calling
+// wave carries PPL pairs per lane, pw + u 64 + lane (u < PPL, pair < pend), and
+// the g columns [C0, C0 + NC) through the degrees l' = m .. L+1, into even (E)
+// and odd (O) sums.  FG: binary64 rows of the triangle (row l' of order m at
+// FG + 8 (tri(m) - m + l')).  eqw: the wave also forms the equator pair (index
+// NPT): at z = 0 the scaled recurrence gives Q_{m+2k} = (-1)^k Q_m and
+// Q_{m+2k+1} = 0, so its even sum is Lambda_{m,m}(0) sum_k (-1)^k g[m + 2k] and
+// its odd sum 0 (lanes = column (lane & 7) x row group (lane >> 3)).
+template <typename out, int PPL, int C0, int NC>
+__device__ __forceinline__ void adj_valu_block(const LegArgs<out> &A, const double *__restrict__ FG, int m, int pw,
+                                               int pend, bool eqw, AdjRow *buf) {
+    const int nt = blockDim.x, lane = threadIdx.x & 63;
     const int L = A.L, NP = A.NP, NPT = A.NPT, Lp1 = L + 1;
     const int64_t t0 = tri_offset(L, m);
-    const real *g = A.FG + (t0 - m) * 8;  // row l' at g + 8 l'
+    const double *g = FG + (t0 - m) * 8;  // row l' at g + 8 l'
     const double *ap = A.aprime + t0 - m;
-    double z[kAdjPPL], q1[kAdjPPL], q2[kAdjPPL];
-    real E[kAdjPPL][8], O[kAdjPPL][8];
+    double z[PPL], q1[PPL], q2[PPL];
+    double E[PPL][NC], O[PPL][NC];
 #pragma unroll
-    for (int u = 0; u < kAdjPPL; ++u) {
-        const int p = A.P + ((grp * nw + wave) * kAdjPPL + u) * kTileP + lane;
-        const bool valid = p < NPT;
+    for (int u = 0; u < PPL; ++u) {
+        const int p = pw + u * kTileP + lane;
+        const bool valid = p < pend;
         z[u] = valid ? A.pz[p] : 0.0;
         q1[u] = 0.0;
         q2[u] = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
@@ -1332,175 +1317,13 @@ __device__ __forceinline__ void adj_valu_body(const LegArgs<real> &A, int m, int
         // wait for the staging loads of the next chunk)
         asm volatile("" : "+v"(z[u]), "+v"(q2[u]));
 #pragma unroll
-        for (int c = 0; c < 8; ++c) E[u][c] = O[u][c] = (real)0;
+        for (int c = 0; c < NC; ++c) E[u][c] = O[u][c] = 0.0;
     }
     const int nl = Lp1 - m + 1;
     const int nchunk = (nl + kAdjChunk - 1) / kAdjChunk;
     // staging: item i < 8 kAdjChunk is g value (i & 7) of row i >> 3; thread t < kAdjChunk
-    // also takes a' of row t (workgroups of 64 threads take two g items each)
-    constexpr int kG = (8 * kAdjChunk + 63) / 64;
-    real sg[kG];
-    double sa = 0.0;
-    auto stage_load = [&](int k) {
-        const int lp0 = m + k * kAdjChunk;
-#pragma unroll
-        for (int r = 0; r < kG; ++r) {
-            const int i = threadIdx.x + r * nt;
-            const int lp = lp0 + (i >> 3);
-            sg[r] = (i < 8 * kAdjChunk && lp <= Lp1) ? g[(int64_t)lp * 8 + (i & 7)] : (real)0;
-        }
-        const int la = lp0 + (int)threadIdx.x;
-        sa = ((int)threadIdx.x < kAdjChunk && la <= Lp1) ? ap[la] : 0.0;
-    };
-    auto stage_store = [&](int k) {
-        AdjRow<real> *b = buf + (k & 1) * kAdjChunk;
-#pragma unroll
-        for (int r = 0; r < kG; ++r) {
-            const int i = threadIdx.x + r * nt;
-            if (i < 8 * kAdjChunk) b[i >> 3].g[i & 7] = sg[r];
-        }
-        if ((int)threadIdx.x < kAdjChunk) b[threadIdx.x].a = sa;
-    };
-    // equator: wave 0, lane = column (lane & 7) x row group (lane >> 3) of the even rows
-    const bool eq = grp == 0 && NP > NPT && wave == 0;
-    real eacc = 0;
-    stage_load(0);
-    stage_store(0);
-    __syncthreads();
-    for (int k = 0; k < nchunk; ++k) {
-        if (k + 1 < nchunk) stage_load(k + 1);  // in flight while chunk k is used
-        const AdjRow<real> *rows = buf + (k & 1) * kAdjChunk;
-        const int nd = min(kAdjChunk, nl - k * kAdjChunk);
-        if (eq) {
-#pragma unroll
-            for (int e = 0; e < kAdjChunk / 16; ++e) {
-                const int d = 2 * ((lane >> 3) + 8 * e);  // even row of the chunk
-                if (d < nd) {
-                    const real v = rows[d].g[lane & 7];
-                    eacc += (((k * kAdjChunk + d) >> 1) & 1) ? -v : v;
-                }
-            }
-        }
-        // the chunk starts an even number of degrees after m: row d has the parity of d
-        if constexpr (sizeof(real) == 8) {
-            // lanes 0-7 of every row of 16 hold g of degree d, lanes 8-15 that of d + 1;
-            // each FMA takes its value by row broadcast
-            const int sel = (lane >> 3) & 1, col = lane & 7;
-            double Gn = rows[sel].g[col], a0n = rows[0].a, a1n = rows[1].a;
-            for (int d = 0; d < nd; d += 2) {
-                const double G = Gn, a0 = a0n, a1 = a1n;
-                // the next step's operands, read while this step computes
-                const int dn = d + 2 < kAdjChunk ? d + 2 : d;
-                Gn = rows[dn + sel].g[col];
-                a0n = rows[dn].a;
-                a1n = rows[dn + 1].a;
-#pragma unroll
-                for (int u = 0; u < kAdjPPL; ++u) {
-                    const double v = fma(a0 * z[u], q1[u], -q2[u]);
-                    fmac_row_bcast8<0>(E[u], G, v);
-                    q2[u] = q1[u];
-                    q1[u] = v;
-                }
-                if (d + 1 < nd) {
-#pragma unroll
-                    for (int u = 0; u < kAdjPPL; ++u) {
-                        const double v = fma(a1 * z[u], q1[u], -q2[u]);
-                        fmac_row_bcast8<8>(O[u], G, v);
-                        q2[u] = q1[u];
-                        q1[u] = v;
-                    }
-                }
-            }
-        } else {
-            // binary32: the chunk's terms go into partial sums that are added to the
-            // totals once per chunk (two-level summation: the rounding of a running
-            // sum over all L degrees would dominate the error)
-            real Ec[kAdjPPL][8], Oc[kAdjPPL][8];
-#pragma unroll
-            for (int u = 0; u < kAdjPPL; ++u)
-#pragma unroll
-                for (int c = 0; c < 8; ++c) Ec[u][c] = Oc[u][c] = (real)0;
-            for (int d = 0; d < nd; d += 2) {
-                const AdjRow<real> R0 = rows[d];
-                adj_row_step(R0, z, q1, q2, Ec);
-                if (d + 1 < nd) {
-                    const AdjRow<real> R1 = rows[d + 1];
-                    adj_row_step(R1, z, q1, q2, Oc);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kAdjPPL; ++u)
-#pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    E[u][c] += Ec[u][c];
-                    O[u][c] += Oc[u][c];
-                }
-        }
-        if (k + 1 < nchunk) stage_store(k + 1);
-        __syncthreads();
-    }
-#pragma unroll
-    for (int u = 0; u < kAdjPPL; ++u) {
-        const int p = A.P + ((grp * nw + wave) * kAdjPPL + u) * kTileP + lane;
-        if (p < NPT) {
-            real *o = A.PB + ((size_t)m * NP + p) * 16;
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                o[c] = E[u][c];
-                o[8 + c] = O[u][c];
-            }
-        }
-    }
-    if (eq) {
-        // the eight row groups of each column (lanes c, c + 8, ..., c + 56)
-        eacc += __shfl_xor(eacc, 8);
-        eacc += __shfl_xor(eacc, 16);
-        eacc += __shfl_xor(eacc, 32);
-        if (lane < 8) {
-            real *o = A.PB + ((size_t)m * NP + NPT) * 16;
-            o[lane] = (real)A.seeds[(size_t)m * NP + NPT] * eacc;
-            o[8 + lane] = 0;
-        }
-    }
-}
-
-// Polar group of the binary32 syntheses: pairs [0, P) of order m in binary64,
-// with g = hi + lo (the binary64 value prep computed) and the recurrence value
-// unrounded, so that the division by sin(theta) near the poles divides an
-// accurate sum.  Lane (p, c) of wave w carries column c = lane >> 3 of g for
-// the pairs w * 8 + (lane & 7) + 8 nw u, u < ceil(P / (8 nw)); g and a' are
-// staged in LDS kAdjChunk degrees at a time, one chunk ahead, as in
-// adj_valu_body.  The E and O sums near the poles are as small as the ring
-// values themselves, so storing them in binary32 keeps their accuracy.
-struct PolarRow {
-    double g[8];
-    double a;
-};
-__device__ __forceinline__ void adj_polar_body(const LegArgs<float> &A, int m, PolarRow *buf) {
-    const int nt = blockDim.x, nw = nt >> 6;
-    const int wave = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int L = A.L, NP = A.NP, Lp1 = L + 1;
-    const int npl = uniform_int((A.P + 8 * nw - 1) / (8 * nw));
-    const int64_t t0 = tri_offset(L, m);
-    const float *gh = A.FG + (t0 - m) * 8, *gl = A.FGlo + (t0 - m) * 8;  // row l' at + 8 l'
-    const double *ap = A.aprime + t0 - m;
-    const int c = lane >> 3;
-    double z[kPolarMaxPerLane], q1[kPolarMaxPerLane], q2[kPolarMaxPerLane];
-    double E[kPolarMaxPerLane], O[kPolarMaxPerLane];
-#pragma unroll
-    for (int u = 0; u < kPolarMaxPerLane; ++u) {
-        const int p = wave * 8 + (lane & 7) + 8 * nw * u;
-        const bool valid = u < npl && p < A.P;
-        z[u] = valid ? A.pz[p] : 0.0;
-        q1[u] = 0.0;
-        q2[u] = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
-        asm volatile("" : "+v"(z[u]), "+v"(q2[u]));
-        E[u] = O[u] = 0.0;
-    }
-    const int nl = Lp1 - m + 1;
-    const int nchunk = (nl + kAdjChunk - 1) / kAdjChunk;
-    constexpr int kItems = 8 * kAdjChunk;
-    constexpr int kG = (kItems + 63) / 64;
+    // also takes a' of row t (workgroups of 64 threads take four g items each)
+    constexpr int kG = 8 * kAdjChunk / 64;
     double sg[kG];
     double sa = 0.0;
     auto stage_load = [&](int k) {
@@ -1509,48 +1332,64 @@ __device__ __forceinline__ void adj_polar_body(const LegArgs<float> &A, int m, P
         for (int r = 0; r < kG; ++r) {
             const int i = threadIdx.x + r * nt;
             const int lp = lp0 + (i >> 3);
-            sg[r] = 0.0;
-            if (i < kItems && lp <= Lp1) {
-                const int64_t o = (int64_t)lp * 8 + (i & 7);
-                sg[r] = (double)gh[o] + (double)gl[o];
-            }
+            sg[r] = (i < 8 * kAdjChunk && lp <= Lp1) ? g[(int64_t)lp * 8 + (i & 7)] : 0.0;
         }
         const int la = lp0 + (int)threadIdx.x;
         sa = ((int)threadIdx.x < kAdjChunk && la <= Lp1) ? ap[la] : 0.0;
     };
     auto stage_store = [&](int k) {
-        PolarRow *b = buf + (k & 1) * kAdjChunk;
+        AdjRow *b = buf + (k & 1) * kAdjChunk;
 #pragma unroll
         for (int r = 0; r < kG; ++r) {
             const int i = threadIdx.x + r * nt;
-            if (i < kItems) b[i >> 3].g[i & 7] = sg[r];
+            if (i < 8 * kAdjChunk) b[i >> 3].g[i & 7] = sg[r];
         }
         if ((int)threadIdx.x < kAdjChunk) b[threadIdx.x].a = sa;
     };
+    double eacc = 0;
     stage_load(0);
     stage_store(0);
     __syncthreads();
     for (int k = 0; k < nchunk; ++k) {
-        if (k + 1 < nchunk) stage_load(k + 1);
-        const PolarRow *rows = buf + (k & 1) * kAdjChunk;
+        if (k + 1 < nchunk) stage_load(k + 1);  // in flight while chunk k is used
+        const AdjRow *rows = buf + (k & 1) * kAdjChunk;
         const int nd = min(kAdjChunk, nl - k * kAdjChunk);
-        for (int d = 0; d < nd; d += 2) {
-            const double a0 = rows[d].a, g0 = rows[d].g[c];
-            const bool odd = d + 1 < nd;
-            const double a1 = odd ? rows[d + 1].a : 0.0, g1 = odd ? rows[d + 1].g[c] : 0.0;
+        if (eqw) {
 #pragma unroll
-            for (int u = 0; u < kPolarMaxPerLane; ++u) {
-                if (u < npl) {
-                    const double v0 = fma(a0 * z[u], q1[u], -q2[u]);
-                    E[u] = fma(v0, g0, E[u]);
+            for (int e = 0; e < kAdjChunk / 16; ++e) {
+                const int d = 2 * ((lane >> 3) + 8 * e);  // even row of the chunk
+                if (d < nd) {
+                    const double v = rows[d].g[lane & 7];
+                    eacc += (((k * kAdjChunk + d) >> 1) & 1) ? -v : v;
+                }
+            }
+        }
+        // the chunk starts an even number of degrees after m: row d has the parity of d;
+        // lanes 0-7 of every row of 16 hold g of degree d, lanes 8-15 that of d + 1, and
+        // each FMA takes its value by row broadcast
+        const int sel = (lane >> 3) & 1, col = lane & 7;
+        double Gn = rows[sel].g[col], a0n = rows[0].a, a1n = rows[1].a;
+        for (int d = 0; d < nd; d += 2) {
+            const double G = Gn, a0 = a0n, a1 = a1n;
+            // the next step's operands, read while this step computes
+            const int dn = d + 2 < kAdjChunk ? d + 2 : d;
+            Gn = rows[dn + sel].g[col];
+            a0n = rows[dn].a;
+            a1n = rows[dn + 1].a;
+#pragma unroll
+            for (int u = 0; u < PPL; ++u) {
+                const double v = fma(a0 * z[u], q1[u], -q2[u]);
+                fmac_row_bcastn<C0, NC>(E[u], G, v);
+                q2[u] = q1[u];
+                q1[u] = v;
+            }
+            if (d + 1 < nd) {
+#pragma unroll
+                for (int u = 0; u < PPL; ++u) {
+                    const double v = fma(a1 * z[u], q1[u], -q2[u]);
+                    fmac_row_bcastn<8 + C0, NC>(O[u], G, v);
                     q2[u] = q1[u];
-                    q1[u] = v0;
-                    if (odd) {
-                        const double v1 = fma(a1 * z[u], q1[u], -q2[u]);
-                        O[u] = fma(v1, g1, O[u]);
-                        q2[u] = q1[u];
-                        q1[u] = v1;
-                    }
+                    q1[u] = v;
                 }
             }
         }
@@ -1558,95 +1397,74 @@ __device__ __forceinline__ void adj_polar_body(const LegArgs<float> &A, int m, P
         __syncthreads();
     }
 #pragma unroll
-    for (int u = 0; u < kPolarMaxPerLane; ++u) {
-        const int p = wave * 8 + (lane & 7) + 8 * nw * u;
-        if (u < npl && p < A.P) {
-            float *o = A.PB + ((size_t)m * NP + p) * 16;
-            o[c] = (float)E[u];
-            o[8 + c] = (float)O[u];
+    for (int u = 0; u < PPL; ++u) {
+        const int p = pw + u * kTileP + lane;
+        if (p < pend) {
+            out *o = A.PB + ((size_t)m * NP + p) * 16;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                o[C0 + c] = (out)E[u][c];
+                o[8 + C0 + c] = (out)O[u][c];
+            }
+        }
+    }
+    if (eqw) {
+        // the eight row groups of each column (lanes c, c + 8, ..., c + 56)
+        eacc += __shfl_xor(eacc, 8);
+        eacc += __shfl_xor(eacc, 16);
+        eacc += __shfl_xor(eacc, 32);
+        if (lane < 8) {
+            out *o = A.PB + ((size_t)m * NP + NPT) * 16;
+            o[lane] = (out)(A.seeds[(size_t)m * NP + NPT] * eacc);
+            o[8 + lane] = 0;
         }
     }
 }
 
-// One wave: pairs [64 tile, 64 tile + 64) of order m, computed in `real`, with
-// FG read and PB written in `store` (binary32 storage with binary64 arithmetic
-// serves the polar tile of the binary32 path).
-template <typename real, typename store>
-__device__ __forceinline__ void adj_tile_mfma(const LegArgs<store> &A, int m, int tile, int lane,
-                                              real *qt) {
-    typedef typename Mfma<real>::acc_t acc_t;
-    const int L = A.L, NP = A.NP, NPT = A.NPT;
+// One wave of the split-bf16 paths' binary32 tile: pairs [p0, p0 + 64) of order
+// m over the degrees [lA, lB) (lA an even number of degrees after m), from the
+// lane's recurrence state (q1, q2), on the binary32 16x16x4 MFMA through the
+// wave's Q tile qt.  Each 16-degree block is summed apart and added to the
+// totals (two-level summation).  acc[b]: lane l, register r -> pair
+// p0 + 16 b + Mfma<float>::row(l, r), column l % 16 (8 even-sum columns, then 8 odd).
+__device__ __forceinline__ void adj_tile_f32(const LegArgs<float> &A, int m, int p0, int lA, int lB, double z,
+                                             double q1, double q2, f32x4 (&acc)[4], float *qt) {
+    const int lane = threadIdx.x & 63;
+    const int L = A.L;
     const int64_t t0 = tri_offset(L, m);
-    const store *g = A.FG + (t0 - m) * 8;  // indexed by l'
-    const int base = A.P;  // the tiles start after the polar group's pairs
-    const int p = base + tile * kTileP + lane;
-    const bool valid = p < NPT;
-    const double z = valid ? A.pz[p] : 0.0;
-    double q1 = 0.0, q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+    const float *g = A.FG + (t0 - m) * 8;  // indexed by l'
     const int j = lane & 15, k = lane >> 4;
-    acc_t acc[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[b] = acc_t{0, 0, 0, 0};
-    const int nl = L + 2 - m;
-    const int nblk = (nl + kRowsB - 1) / kRowsB;
+    for (int b = 0; b < 4; ++b) acc[b] = f32x4{0, 0, 0, 0};
+    const int nblk = (lB - lA + kRowsB - 1) / kRowsB;
     for (int blk = 0; blk < nblk; ++blk) {
-        const int lp0 = m + blk * kRowsB;
+        const int lp0 = lA + blk * kRowsB;
         const int la = lp0 + (lane & 15);
-        const double areg = la <= L + 1 ? A.aprime[t0 + la - m] : 0.0;
+        const double areg = la < lB ? A.aprime[t0 + la - m] : 0.0;
         // B operands: lane (j + 16k) holds g[row 4gg + k][j & 7] if the row's
         // parity matches the column half (row parity == (lp - m) & 1 == k & 1)
-        real bv[4];
+        float bv[4];
 #pragma unroll
         for (int gg = 0; gg < 4; ++gg) {
             const int lp = lp0 + 4 * gg + k;
-            bv[gg] = (lp <= L + 1 && (j >> 3) == (k & 1)) ? (real)g[(int64_t)lp * 8 + (j & 7)] : (real)0;
+            bv[gg] = (lp < lB && (j >> 3) == (k & 1)) ? g[(int64_t)lp * 8 + (j & 7)] : 0.f;
         }
-        recur16<real, SwzAdj>(qt, areg, z, q1, q2, lane);
-        // the block's 16 degrees are summed apart and then added to the totals
-        // (two-level summation over the degrees)
-        acc_t ab[4];
+        recur16<float, SwzAdj>(qt, areg, z, q1, q2, lane);
+        f32x4 ab[4];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) ab[b] = acc_t{0, 0, 0, 0};
+        for (int b = 0; b < 4; ++b) ab[b] = f32x4{0, 0, 0, 0};
 #pragma unroll
         for (int gg = 0; gg < 4; ++gg) {
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 // A: lane (i + 16k) holds Q[row 4gg + k][pair 16b + i]
-                const real a = qt[SwzAdj::at(4 * gg + k, 16 * b + j)];
-                ab[b] = Mfma<real>::mma(a, bv[gg], ab[b]);
+                const float a = qt[SwzAdj::at(4 * gg + k, 16 * b + j)];
+                ab[b] = Mfma<float>::mma(a, bv[gg], ab[b]);
             }
         }
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[b] += ab[b];
     }
-    // accumulator b: lane l, register r -> pair 16b + row, column l%16
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int pp = base + tile * kTileP + 16 * b + Mfma<real>::row(lane, r);
-            if (pp < NPT) A.PB[((size_t)m * NP + pp) * 16 + j] = (store)acc[b][r];
-        }
-    }
-}
-
-// Bytes of LDS per wave of the synthesis kernels (the largest tile any path uses).
-
-template <typename real>
-__global__ __launch_bounds__(256, 4) void k_leg_adj(LegArgs<real> A) {
-    extern __shared__ unsigned char smem_raw[];
-    // workgroups reach the compute units in rounds of about 256; reversing the
-    // order in every other round gives each unit long and short orders alike
-    const int y = blockIdx.y, base = y & ~255, r = y & 255;
-    const int cnt = min(256, A.L + 1 - base);
-    const int m = (y >> 8) & 1 ? base + cnt - 1 - r : y;
-    if constexpr (sizeof(real) == 4) {
-        if ((int)blockIdx.x == A.gpolar) {
-            adj_polar_body(A, m, reinterpret_cast<PolarRow *>(smem_raw));
-            return;
-        }
-    }
-    adj_valu_body<real>(A, m, blockIdx.x, reinterpret_cast<AdjRow<real> *>(smem_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -1894,40 +1712,90 @@ __global__ __launch_bounds__(1024) void k_leg_fwd_bf16(LegFwdArgs<float> A) {
 // distinct banks).
 constexpr int kRowsA = 32;
 
-template <int NPROD>
-__device__ __forceinline__ void adj_tile_bf16(const LegArgs<float> &A, int m, int tile, int lane,
-                                              u32x4_t *th) {
-    constexpr int NS = Bf16<NPROD>::kParts;
+// The split-bf16 paths' polar tile: pairs [p0, p0 + 16 NB) of order m (the pairs
+// next to the poles) over all degrees in binary64 on the 16x16x4 binary64 MFMA,
+// with g from the plan's binary64 triangle, through the wave's Q tile qt (lane =
+// pair for the recurrence; lanes beyond the tile's pairs run it unused).  The
+// sums are stored in binary32.
+template <int NB>
+__device__ __forceinline__ void adj_tile_f64_polar(const LegArgs<float> &A, int m, int p0, int pend, double *qt) {
+    typedef Mfma<double>::acc_t acc_t;
+    const int lane = threadIdx.x & 63;
     const int L = A.L, NP = A.NP;
-    const int NPT = A.NPT;
+    const int64_t t0 = tri_offset(L, m);
+    const double *g = A.FG64 + (t0 - m) * 8;  // indexed by l'
+    const int p = p0 + lane;
+    const bool valid = lane < 16 * NB && p < pend;
+    const double z = valid ? A.pz[p] : 0.0;
+    double q1 = 0.0, q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+    const int j = lane & 15, k = lane >> 4;
+    acc_t acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = acc_t{0, 0, 0, 0};
+    const int nblk = (L + 2 - m + kRowsB - 1) / kRowsB;
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int lp0 = m + blk * kRowsB;
+        const int la = lp0 + (lane & 15);
+        const double areg = la <= L + 1 ? A.aprime[t0 + la - m] : 0.0;
+        // B operands: lane (j + 16k) holds g[row 4gg + k][j & 7] if the row's
+        // parity matches the column half (row parity == (lp - m) & 1 == k & 1)
+        double bv[4];
+#pragma unroll
+        for (int gg = 0; gg < 4; ++gg) {
+            const int lp = lp0 + 4 * gg + k;
+            bv[gg] = (lp <= L + 1 && (j >> 3) == (k & 1)) ? g[(int64_t)lp * 8 + (j & 7)] : 0.0;
+        }
+        recur16<double, SwzAdj>(qt, areg, z, q1, q2, lane);
+#pragma unroll
+        for (int gg = 0; gg < 4; ++gg) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                // A: lane (i + 16k) holds Q[row 4gg + k][pair 16b + i]
+                const double a = qt[SwzAdj::at(4 * gg + k, 16 * b + j)];
+                acc[b] = Mfma<double>::mma(a, bv[gg], acc[b]);
+            }
+        }
+    }
+    // accumulator b: lane l, register r -> pair p0 + 16b + row, column l % 16
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int pp = p0 + 16 * b + Mfma<double>::row(lane, r);
+            if (pp < pend) A.PB[((size_t)m * NP + pp) * 16 + j] = (float)acc[b][r];
+        }
+}
+
+template <int NPROD>
+__device__ __forceinline__ void adj_tile_bf16(const LegArgs<float> &A, int m, int p0, int lA, int lB, double z,
+                                              double q1, double q2, f32x4 (&acc)[4], u32x4_t *th) {
+    // pairs [p0, p0 + 64) over the degrees [lA, lB) (lA an even number of degrees
+    // after m); acc as in adj_tile_f32 (register r of acc[b]: pair 16 b + 4 (l/16) + r)
+    constexpr int NS = Bf16<NPROD>::kParts;
+    const int lane = threadIdx.x & 63;
+    const int L = A.L;
     const int64_t t0 = tri_offset(L, m);
     const float *g = A.FG + (t0 - m) * 8;    // indexed by l'
     const double *ap = A.aprime + t0 - m;    // indexed by l'
-    const int base = A.P;  // the tiles start after the polar group's pairs
-    const int p = base + tile * kTileP + lane;
-    const bool valid = p < NPT;
-    const double z = valid ? A.pz[p] : 0.0;
-    double q1 = 0.0, q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
     const int j = lane & 15, kg = lane >> 4;
-    f32x4 acc[4], acl[4];  // leading products, correction products
+    f32x4 acl[4];  // leading products in acc, correction products in acl
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[b] = acl[b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int nl = L + 2 - m;
-    const int nblk = (nl + kRowsA - 1) / kRowsA;
+    const int nblk = (lB - lA + kRowsA - 1) / kRowsA;
     for (int blk = 0; blk < nblk; ++blk) {
-        const int lp0 = m + blk * kRowsA;
+        const int lp0 = lA + blk * kRowsA;
         // B: lane (j + 16kg) holds g[l' = lp0 + 8kg + t][j & 7] when the parity
         // of l' - m (= t & 1) matches the column half j / 8, else 0
         float bv[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const int lp = lp0 + 8 * kg + t;
-            bv[t] = (lp <= L + 1 && (t & 1) == (j >> 3)) ? g[(int64_t)lp * 8 + (j & 7)] : 0.f;
+            bv[t] = (lp < lB && (t & 1) == (j >> 3)) ? g[(int64_t)lp * 8 + (j & 7)] : 0.f;
         }
         const Split8<NPROD> bs = split8<NPROD>(bv);
         uint32_t hq[NS][16];
         double ab[kRowsA];
-        load_aprime(ap, lp0, L + 1, ab);
+        load_aprime(ap, lp0, lB - 1, ab);
 #pragma unroll
         for (int s = 0; s < kRowsA; s += 2) {
             const double v0 = fma(ab[s] * z, q1, -q2);
@@ -1960,42 +1828,93 @@ __device__ __forceinline__ void adj_tile_bf16(const LegArgs<float> &A, int m, in
         __builtin_amdgcn_wave_barrier();
     }
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int pp = base + tile * kTileP + 16 * b + 4 * kg + r;
-            if (pp < NPT) A.PB[((size_t)m * NP + pp) * 16 + j] = acc[b][r] + acl[b][r];
-        }
-    }
+    for (int b = 0; b < 4; ++b) acc[b] += acl[b];
 }
 
-// BF16x3/BF16x6 synthesis.  The spin-frame form divides the synthesised sums by
-// sin(theta), which near the poles amplifies the rounding of the contraction by
-// up to 1/sin(theta) ~ L.  Pairs are sorted by increasing sin(theta): the first
-// P go to the binary64 polar group (workgroup column gpolar), and the first
-// tile after them (the next 64 pairs) runs on the binary32 MFMA path.
-template <int NP>
-__device__ __forceinline__ void leg_adj_bf16_group(const LegArgs<float> &A, int m, int grp,
-                                                   unsigned char *smem_raw) {
-    if (grp == A.gpolar) {
-        adj_polar_body(A, m, reinterpret_cast<PolarRow *>(smem_raw));
-        return;
-    }
-    const int nw = blockDim.x >> 6;
-    const int wave = uniform_int(threadIdx.x >> 6);
-    const int tile = grp * nw + wave;
-    if (A.P + tile * kTileP >= A.NPT) return;
-    unsigned char *lds = smem_raw + wave * Bf16<NP>::kAdjLdsPerWave;
-    if (tile == 0)
-        adj_tile_mfma<float, float>(A, m, tile, threadIdx.x & 63, reinterpret_cast<float *>(lds));
+// ---------------------------------------------------------------------------
+// The synthesis launch: workgroups of four waves over (column x, order y).
+//   NPROD = 0 (binary64 and binary32 plans): workgroup x takes pairs
+//     [512 x, 512 x + 512), 128 per wave, on the binary64 vector unit; x = 0 also
+//     forms the equator pair.
+//   NPROD = 3, 6 (split-bf16): 64-pair tiles, one per wave, the first (the pairs
+//     next to the poles after the polar ones) on the binary32 MFMA tile, the
+//     others on the split-bf16 tiles; the equator comes from k_equator_adj.
+//     BF16x6 (bar 1e-6) puts the P pairs nearest the poles on a binary64 MFMA
+//     tile in the first wave slot (binary64 vector work would wait behind the
+//     bf16 MFMA stream of the other waves); the tiles then start at P.
+//     BF16x3's bound leaves those pairs on the binary32 tile.
+// The order of m is reversed in every other round of 256 workgroups (the rounds
+// in which workgroups reach the compute units), so that each unit gets long and
+// short orders alike.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int adj_polar_pairs(int NPT, int nprod) {
+    return nprod == 6 ? (NPT < kPolarPairs ? NPT : kPolarPairs) : 0;
+}
+// wave slots of a split-bf16 launch: [polar tile,] binary32 tile, split-bf16 tiles
+__host__ __device__ inline int adj_slots(int NPT, int nprod) {
+    const int P = adj_polar_pairs(NPT, nprod);
+    return (P > 0 ? 1 : 0) + (NPT - P + kTileP - 1) / kTileP;
+}
+template <int NPROD>
+__host__ __device__ constexpr size_t adj_lds_block() {
+    if constexpr (NPROD == 0)
+        return 2 * kAdjChunk * sizeof(AdjRow);
     else
-        adj_tile_bf16<NP>(A, m, tile, threadIdx.x & 63, reinterpret_cast<u32x4_t *>(lds));
+        return 4 * (size_t)Bf16<NPROD>::kAdjLdsPerWave > 2 * kAdjChunk * sizeof(AdjRow)
+                   ? 4 * (size_t)Bf16<NPROD>::kAdjLdsPerWave
+                   : 2 * kAdjChunk * sizeof(AdjRow);
+}
+// workgroup columns of a synthesis launch over NPT tile pairs
+__host__ __device__ inline int adj_columns(int NPT, int nprod) {
+    if (nprod == 0) return NPT > 0 ? (NPT + 8 * kTileP - 1) / (8 * kTileP) : 1;
+    return (adj_slots(NPT, nprod) + 3) / 4;
 }
 
-template <int NP>
-__global__ __launch_bounds__(256) void k_leg_adj_bf16(LegArgs<float> A) {
+template <typename real, int NPROD>
+__device__ __forceinline__ void leg_adj_group(const LegArgs<real> &A, int m, int x, unsigned char *smem) {
+    const int wave = uniform_int(threadIdx.x >> 6);
+    if constexpr (NPROD == 0) {
+        adj_valu_block<real, 2, 0, 8>(A, A.FG64, m, x * 8 * kTileP + wave * 2 * kTileP, A.NPT, x == 0 && wave == 0 && A.NP > A.NPT,
+                                      reinterpret_cast<AdjRow *>(smem));
+    } else {
+        const int P = adj_polar_pairs(A.NPT, NPROD);
+        const int slot = x * 4 + wave;
+        unsigned char *wl = smem + wave * Bf16<NPROD>::kAdjLdsPerWave;
+        if (P > 0 && slot == 0) {
+            adj_tile_f64_polar<kPolarPairs / 16>(A, m, 0, P, reinterpret_cast<double *>(wl));
+            return;
+        }
+        const int tile = slot - (P > 0 ? 1 : 0);
+        const int p0 = P + tile * kTileP;
+        if (p0 >= A.NPT) return;
+        const int lane = threadIdx.x & 63;
+        const int p = p0 + lane;
+        const bool valid = p < A.NPT;
+        const double z = valid ? A.pz[p] : 0.0;
+        const double q2 = valid ? -A.seeds[(size_t)m * A.NP + p] : 0.0;
+        f32x4 acc[4];
+        if (tile == 0)
+            adj_tile_f32(A, m, p0, m, A.L + 2, z, 0.0, q2, acc, reinterpret_cast<float *>(wl));
+        else
+            adj_tile_bf16<NPROD>(A, m, p0, m, A.L + 2, z, 0.0, q2, acc, reinterpret_cast<u32x4_t *>(wl));
+        const int j = lane & 15;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int pp = p0 + 16 * b + Mfma<float>::row(lane, r);
+                if (pp < A.NPT) A.PB[((size_t)m * A.NP + pp) * 16 + j] = acc[b][r];
+            }
+    }
+}
+
+template <typename real, int NPROD>
+__global__ __launch_bounds__(256, NPROD == 0 ? 4 : 1) void k_leg_adj(LegArgs<real> A) {
     extern __shared__ unsigned char smem_raw[];
-    leg_adj_bf16_group<NP>(A, blockIdx.y, blockIdx.x, smem_raw);
+    const int y = blockIdx.y, base = y & ~255, r = y & 255;
+    const int cnt = min(256, A.L + 1 - base);
+    const int m = (y >> 8) & 1 ? base + cnt - 1 - r : y;
+    leg_adj_group<real, NPROD>(A, m, blockIdx.x, smem_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -2015,8 +1934,10 @@ struct CoefArgs {
     const double *cscale;   // [tri] c_{l',m}
     const double *etab;     // [tri] e_{l',m}
     const double *rsq;      // [L+2] 1 / sqrt(l (l+1)), 0 for l = 0
-    float *FGlo;            // binary32 paths: g - hi(g), [tri][8] (prep output)
+    double *FG64;           // binary32 paths: g in binary64, [tri][8] (prep output)
     int L;
+    int fg32;               // binary32 paths: also write g in binary32 to FGout (the split-bf16
+                            // tiles and the direct scattered evaluation read it)
 };
 
 // Both coefficient kernels work on tiles of kTM orders x kTL degrees staged in
@@ -2116,8 +2037,9 @@ template <typename real>
 __device__ __forceinline__ void prep_body(const CoefArgs<real> &A, int bx, int by) {
     // coefficients of degrees l0-1 .. l0+kTL for the tile's orders, [l][sign][a,b][m]; an
     // odd stride between degrees keeps the 16-byte reads of consecutive degrees conflict free.
-    // The map is evaluated in binary64 for every precision: the binary32 paths keep g as
-    // a binary32 pair hi + lo, whose sum the synthesis of the rings next to the poles uses.
+    // The map is evaluated in binary64 for every precision: the binary32 paths store g
+    // both in binary32 (FG, for the split-bf16 tiles) and in binary64 (FG64, for the
+    // binary64 vector-unit synthesis and the polar wave).
     constexpr int kRowP = 4 * kTM + 1;
     __shared__ C2<double> cs[(kTL + 2) * kRowP];
     const int L = A.L;
@@ -2195,12 +2117,13 @@ __device__ __forceinline__ void prep_body(const CoefArgs<real> &A, int bx, int b
                 o[2 * sgn] = {gth.x, gth.y};
                 o[2 * sgn + 1] = {gph.x, gph.y};
             } else {
-                const C2<float> th = {(float)gth.x, (float)gth.y}, ph = {(float)gph.x, (float)gph.y};
-                o[2 * sgn] = th;
-                o[2 * sgn + 1] = ph;
-                C2<float> *lo = reinterpret_cast<C2<float> *>(A.FGlo) + ti * 4;
-                lo[2 * sgn] = {(float)(gth.x - (double)th.x), (float)(gth.y - (double)th.y)};
-                lo[2 * sgn + 1] = {(float)(gph.x - (double)ph.x), (float)(gph.y - (double)ph.y)};
+                if (A.fg32) {
+                    o[2 * sgn] = {(float)gth.x, (float)gth.y};
+                    o[2 * sgn + 1] = {(float)gph.x, (float)gph.y};
+                }
+                C2<double> *o64 = reinterpret_cast<C2<double> *>(A.FG64) + ti * 4;
+                o64[2 * sgn] = gth;
+                o64[2 * sgn + 1] = gph;
             }
         }
     }
@@ -2752,25 +2675,15 @@ __global__ __launch_bounds__(1024) void kb_leg_fwd(const LegFwdArgs<real> *__res
         leg_fwd_body(A, w.x, 0, smem_raw);
 }
 
-// work item (field, tile group, m)
+// work item (field, x, m): the synthesis workgroup column x of order m (leg_adj_group)
 template <typename real, int kBf16>
-__global__ __launch_bounds__(256, 4) void kb_leg_adj(const LegArgs<real> *__restrict__ args,
+__global__ __launch_bounds__(256, kBf16 == 0 ? 4 : 1) void kb_leg_adj(const LegArgs<real> *__restrict__ args,
                                                   const WorkItem *__restrict__ work,
                                                   unsigned long long *) {
     extern __shared__ unsigned char smem_raw[];
     const WorkItem w = ld_const(work + blockIdx.x);
     const LegArgs<real> A = ld_const(args + w.f);
-    if constexpr (kBf16 != 0) {
-        leg_adj_bf16_group<kBf16>(A, w.y, w.x, smem_raw);
-    } else {
-        if constexpr (sizeof(real) == 4) {
-            if (w.x == A.gpolar) {
-                adj_polar_body(A, w.y, reinterpret_cast<PolarRow *>(smem_raw));
-                return;
-            }
-        }
-        adj_valu_body<real>(A, w.y, w.x, reinterpret_cast<AdjRow<real> *>(smem_raw));
-    }
+    leg_adj_group<real, kBf16>(A, w.y, w.x, smem_raw);
 }
 
 template <typename real>
@@ -2796,7 +2709,7 @@ struct ShtArgs {
     const C2<real> *flm_in;
     C2<real> *flm_out;
     C2<real> *FG;           // [tri][4]
-    float *FGlo;            // binary32 paths: low parts of FG (see prep_body)
+    double *FG64;           // binary32 paths: FG in binary64 (see prep_body)
     const double *cscale;   // [tri] c_{l',m}
     int L;
 };
@@ -2827,11 +2740,11 @@ __global__ __launch_bounds__(256) void k_sht_coef_to_fg(ShtArgs<real> A) {
     o[2] = hm;
     o[3] = {0, 0};
     if constexpr (sizeof(real) == 4) {
-        C2<float> *lo = reinterpret_cast<C2<float> *>(A.FGlo) + ti * 4;
-        lo[0] = {(float)(gp.x - (double)hp.x), (float)(gp.y - (double)hp.y)};
-        lo[1] = {0.f, 0.f};
-        lo[2] = {(float)(gm.x - (double)hm.x), (float)(gm.y - (double)hm.y)};
-        lo[3] = {0.f, 0.f};
+        C2<double> *o64 = reinterpret_cast<C2<double> *>(A.FG64) + ti * 4;
+        o64[0] = gp;
+        o64[1] = {0, 0};
+        o64[2] = gm;
+        o64[3] = {0, 0};
     }
 }
 
@@ -2885,11 +2798,6 @@ static int tiles_of(const Plan &p) { return (pairs_in_tiles(p) + kTileP - 1) / k
 static int bf16_products(int precision) {
     return precision == VSHT_BF16X3 ? 3 : precision == VSHT_BF16X6 ? 6 : 0;
 }
-// Waves of the synthesis: 64 pairs each for the split-bf16 modes, 64 AdjPPL on the vector unit.
-static int adj_waves(int pairs, int nprod, size_t rsz) {
-    const int per = kTileP * (nprod ? 1 : rsz == 8 ? AdjPPL<double>::n : AdjPPL<float>::n);
-    return (pairs + per - 1) / per;
-}
 
 // Analysis grid: one workgroup per order m holds up to 16 tiles (waves); plans
 // with more tiles split them over `groups` workgroups, each writing a partial
@@ -2919,8 +2827,8 @@ template <typename real>
 static LegArgs<real> make_leg_adj_args(const Plan &p) {
     LegArgs<real> G{};
     G.FG = static_cast<const real *>(p.d_fg);
-    G.FGlo = static_cast<const float *>(p.d_fglo);
-    G.gpolar = -1;
+    G.FG64 = p.precision == VSHT_FP64 ? static_cast<const double *>(p.d_fg) : static_cast<const double *>(p.d_fg64);
+
     G.PB = static_cast<real *>(p.d_pb);
     G.seeds = p.d_seeds;
     G.pz = p.d_pair_z;
@@ -2944,44 +2852,20 @@ static CoefArgs<real> make_coef_args(const Plan &p, const void *ain, const void 
     C.cscale = p.d_cscale;
     C.etab = p.d_etab;
     C.rsq = p.d_rsq;
-    C.FGlo = static_cast<float *>(p.d_fglo);
+    C.FG64 = static_cast<double *>(p.d_fg64);
+    // the binary32 synthesis reads only FG64; the split-bf16 tiles and the direct
+    // scattered evaluation read the binary32 triangle
+    C.fg32 = p.precision != VSHT_FP32 || (p.kind == VSHT_PLAN_SCATTERED && !p.nfft.on);
     C.L = p.L;
     return C;
 }
 
 static size_t leg_fwd_lds(int nw, size_t rsz) { return (size_t)nw * (kRowsB * kTileP + 2 * 128) * rsz; }
-static size_t leg_adj_lds(int nw, size_t rsz, int nprod) {
-    // the binary32 paths' launches also hold the polar group (PolarRow staging)
-    const size_t polar = rsz == 4 ? 2 * kAdjChunk * sizeof(PolarRow) : 0;
-    if (nprod == 3) return std::max(polar, (size_t)nw * Bf16<3>::kAdjLdsPerWave);
-    if (nprod == 6) return std::max(polar, (size_t)nw * Bf16<6>::kAdjLdsPerWave);
-    return std::max(polar, 2 * kAdjChunk * (rsz == 8 ? sizeof(AdjRow<double>) : sizeof(AdjRow<float>)));
-}
 
-// Synthesis grid: `groups` workgroups of nw waves over the pairs [P, NPT) (at least
-// one: group 0 also forms the equator on the vector-unit path) and, on the binary32
-// paths, the polar group for pairs [0, P) in workgroup column gpolar = groups.
-struct AdjGrid {
-    int P, nw, groups, gx;
-};
-static AdjGrid adj_shape(int NPT, bool has_lo, size_t rsz, int nprod, int nw) {
-    AdjGrid a;
-    a.P = (rsz == 4 && has_lo) ? std::min(NPT, kPolarPairs) : 0;
-    const int ntile = adj_waves(NPT - a.P, nprod, rsz);
-    a.nw = nw;
-    a.groups = std::max(1, (ntile + nw - 1) / nw);
-    a.gx = a.groups + (a.P > 0 ? 1 : 0);
-    return a;
-}
+// Synthesis grid: workgroup columns x orders.
 template <typename real>
-static AdjGrid adj_grid(LegArgs<real> &G, int nprod, int nw_cap) {
-    const bool lo = G.FGlo != nullptr;
-    const int ntile = adj_waves(G.NPT - ((sizeof(real) == 4 && lo) ? std::min(G.NPT, kPolarPairs) : 0),
-                                nprod, sizeof(real));
-    const AdjGrid a = adj_shape(G.NPT, lo, sizeof(real), nprod, std::max(1, std::min(ntile, nw_cap)));
-    G.P = a.P;
-    G.gpolar = a.P > 0 ? a.groups : -1;
-    return a;
+static dim3 adj_grid(const LegArgs<real> &G, int nprod) {
+    return dim3((unsigned)adj_columns(G.NPT, nprod), (unsigned)(G.L + 1));
 }
 
 // Analysis and synthesis launches in the plan's arithmetic.
@@ -2999,17 +2883,16 @@ static void launch_leg_fwd(const LegFwdArgs<real> &G, dim3 grid, int nw, int npr
     }
 }
 template <typename real>
-static void launch_leg_adj(const LegArgs<real> &G, dim3 grid, int nw, int nprod, hipStream_t st) {
-    const size_t lds = leg_adj_lds(nw, sizeof(real), nprod);
+static void launch_leg_adj(const LegArgs<real> &G, dim3 grid, int nprod, hipStream_t st) {
     if constexpr (sizeof(real) == 4) {
         if (nprod == 3)
-            hipLaunchKernelGGL(k_leg_adj_bf16<3>, grid, dim3(nw * 64), lds, st, G);
+            hipLaunchKernelGGL((k_leg_adj<float, 3>), grid, dim3(256), adj_lds_block<3>(), st, G);
         else if (nprod == 6)
-            hipLaunchKernelGGL(k_leg_adj_bf16<6>, grid, dim3(nw * 64), lds, st, G);
+            hipLaunchKernelGGL((k_leg_adj<float, 6>), grid, dim3(256), adj_lds_block<6>(), st, G);
         else
-            hipLaunchKernelGGL(k_leg_adj<real>, grid, dim3(nw * 64), lds, st, G);
+            hipLaunchKernelGGL((k_leg_adj<float, 0>), grid, dim3(256), adj_lds_block<0>(), st, G);
     } else {
-        hipLaunchKernelGGL(k_leg_adj<real>, grid, dim3(nw * 64), lds, st, G);
+        hipLaunchKernelGGL((k_leg_adj<double, 0>), grid, dim3(256), adj_lds_block<0>(), st, G);
     }
 }
 
@@ -3163,11 +3046,11 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
         G.L = p.L;
         G.NP = nf.npv;
         G.NPT = nf.npv;
-        G.FGlo = static_cast<const float *>(p.d_fglo);
+        G.FG64 = p.precision == VSHT_FP64 ? static_cast<const double *>(p.d_fg)
+                                          : static_cast<const double *>(p.d_fg64);
         {
             StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
-            const AdjGrid ag = adj_grid(G, nprod, 4);
-            launch_leg_adj<real>(G, dim3(ag.gx, p.L + 1), ag.nw, nprod, st);
+            launch_leg_adj<real>(G, adj_grid(G, nprod), nprod, st);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -3200,8 +3083,7 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
     LegArgs<real> G = make_leg_adj_args<real>(p);
     {
         StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
-        const AdjGrid ag = adj_grid(G, nprod, 4);
-        launch_leg_adj<real>(G, dim3(ag.gx, p.L + 1), ag.nw, nprod, st);
+        launch_leg_adj<real>(G, adj_grid(G, nprod), nprod, st);
         if (p.eq_ring >= 0 && nprod != 0)  // the vector-unit synthesis forms the equator itself
             hipLaunchKernelGGL(k_equator_adj<real>, dim3(p.L + 1), dim3(256), 0, st, G);
     }
@@ -3283,7 +3165,7 @@ static hipError_t sht_adjoint_impl(const Plan &p, const void *flm, void *f, hipS
     ShtArgs<real> S{};
     S.flm_in = static_cast<const C2<real> *>(flm);
     S.FG = static_cast<C2<real> *>(p.d_fg);
-    S.FGlo = static_cast<float *>(p.d_fglo);
+    S.FG64 = static_cast<double *>(p.d_fg64);
     S.cscale = p.d_cscale;
     S.L = p.L;
     {
@@ -3295,8 +3177,7 @@ static hipError_t sht_adjoint_impl(const Plan &p, const void *flm, void *f, hipS
     LegArgs<real> G = make_leg_adj_args<real>(p);
     {
         StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
-        const AdjGrid ag = adj_grid(G, nprod, 4);
-        launch_leg_adj<real>(G, dim3(ag.gx, p.L + 1), ag.nw, nprod, st);
+        launch_leg_adj<real>(G, adj_grid(G, nprod), nprod, st);
         if (p.eq_ring >= 0 && nprod != 0)
             hipLaunchKernelGGL(k_equator_adj<real>, dim3(p.L + 1), dim3(256), 0, st, G);
     }
@@ -3468,18 +3349,6 @@ void batch_destroy(BatchState *b) {
 
 BatchConfig batch_config(const BatchState *b) { return b->cfg; }
 
-// The synthesis argument blocks' polar group column follows the workgroup width.
-template <typename real>
-static hipError_t batch_set_polar(BatchState *b) {
-    auto *la = reinterpret_cast<LegArgs<real> *>(b->h_ladj.data());
-    for (size_t i = 0; i < b->f.size(); ++i) {
-        const AdjGrid ag = adj_shape(la[i].NPT, la[i].FGlo != nullptr, sizeof(real),
-                                     bf16_products(b->precision), b->cfg.adj_nw);
-        la[i].P = ag.P;
-        la[i].gpolar = ag.P > 0 ? ag.groups : -1;
-    }
-    return hipMemcpy(b->d_ladj, b->h_ladj.data(), b->h_ladj.size(), hipMemcpyHostToDevice);
-}
 
 // Work lists for a configuration.  Item costs (for the longest-first order):
 // ring stages n_phi, Legendre stages (degrees of the order) x (tiles in the
@@ -3516,25 +3385,14 @@ hipError_t batch_configure(BatchState *b, const BatchConfig &cfg) {
     }
     emit(BS_PREP, 4, items, 0);
     items.clear();
-    // Legendre synthesis: one shape for every field; the polar group (binary32
-    // paths) is work item column `groups` of its field
-    size_t lds_adj = leg_adj_lds(cfg.adj_nw, rsz, nprod);
+    // Legendre synthesis: the single plans' workgroups (four waves each) of every field
     for (int i = 0; i < F; ++i) {
         const Plan &p = *b->f[i];
-        const AdjGrid ag = adj_shape(pairs_in_tiles(p), p.d_fglo != nullptr, rsz, nprod, cfg.adj_nw);
-        const int ntile = adj_waves(pairs_in_tiles(p) - ag.P, nprod, rsz);
-        for (int tg = 0; tg < ag.groups; ++tg) {
-            const int nt = std::max(1, std::min(cfg.adj_nw, ntile - tg * cfg.adj_nw));
-            for (int m = 0; m <= p.L; ++m) items.push_back({{i, tg, m, 0}, (double)(p.L + 2 - m) * nt});
-        }
-        if (ag.P > 0)
-            for (int m = 0; m <= p.L; ++m) items.push_back({{i, ag.groups, m, 0}, (double)(p.L + 2 - m)});
+        const int cols = adj_columns(pairs_in_tiles(p), nprod);
+        for (int x = 0; x < cols; ++x)
+            for (int m = 0; m <= p.L; ++m) items.push_back({{i, x, m, 0}, (double)(p.L + 2 - m) * 4});
     }
-    emit(BS_LEG_ADJ, cfg.adj_nw, items, lds_adj);
-    {
-        hipError_t e = b->precision == VSHT_FP64 ? batch_set_polar<double>(b) : batch_set_polar<float>(b);
-        if (e != hipSuccess) return e;
-    }
+    emit(BS_LEG_ADJ, 4, items, nprod == 3 ? adj_lds_block<3>() : nprod == 6 ? adj_lds_block<6>() : adj_lds_block<0>());
     items.clear();
     for (int i = 0; i < F; ++i)
         if (b->f[i]->eq_ring >= 0 && nprod != 0)  // the vector-unit synthesis forms the equator itself
@@ -3790,17 +3648,17 @@ hipError_t set_kernel_attributes() {
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_leg_fwd_mfma<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_leg_adj<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = hipFuncSetAttribute((const void *)k_leg_adj<double, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_leg_fwd_bf16<3>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_leg_fwd_bf16<6>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_leg_adj_bf16<3>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = hipFuncSetAttribute((const void *)k_leg_adj<float, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_leg_adj_bf16<6>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = hipFuncSetAttribute((const void *)k_leg_adj<float, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)k_leg_adj<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    return hipFuncSetAttribute((const void *)k_leg_adj<float, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
 
 }  // namespace vsht
