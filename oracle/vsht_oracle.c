@@ -7,7 +7,8 @@
  * leg of the benchmark do.  It shares no code, table or helper with the HIP
  * library.
  *
- * What it computes (all in IEEE binary64, built with -ffp-contract=off):
+ * What it computes (in IEEE binary64, built with -ffp-contract=off; only the
+ * Legendre recurrence runs in the x87 extended type, for its exponent range):
  *   - scalar spherical harmonics Y_{l,m} of Section 3 (4pi-orthonormal, with
  *     the Condon-Shortley phase; negative orders use the conjugate relation
  *     Y_{l,-m} = (-1)^m conj(Y_{l,m}), the orthonormal reading of the
@@ -42,6 +43,7 @@
 typedef double complex cplx;
 
 static const double ORC_PI = 3.14159265358979323846264338327950288;
+static const long double ORC_PIL = 3.14159265358979323846264338327950288L;
 
 /* ---------------------------------------------------------------------- */
 /* Point geometry: z = cos(theta), s = sin(theta) >= 0, phi = longitude.   */
@@ -64,24 +66,42 @@ static void point_geometry(const double *x, double *z, double *s, double *phi)
 /*   Pbar_{m+1,m} = sqrt(2m+3) z Pbar_{m,m}                                 */
 /*   Pbar_{l,m} = A (z Pbar_{l-1,m} - B Pbar_{l-2,m}),                      */
 /*     A = sqrt((4l^2-1)/(l^2-m^2)),  B = sqrt(((l-1)^2-m^2)/(4(l-1)^2-1)). */
+/* The seed Pbar_{m,m} = O(s^m) leaves binary64's range near the poles     */
+/* long before the functions it starts become negligible (at L ~ 2000 a     */
+/* seed of 1e-400 grows to O(1) by l = L), so the recurrence runs in the   */
+/* x87 extended type (15-bit exponent, down to 1e-4951; a seed below that   */
+/* cannot grow past ~1e-4400 within l <= 4096) and each value is rounded   */
+/* to binary64 once, when stored.                                           */
 /* Table P[m][l] stored as P[m*(Lmax+1) + l] (entries l < m unused).        */
 /* ---------------------------------------------------------------------- */
+typedef long double xreal;
+
+static xreal legendre_step(int l, int m, xreal z, xreal p1, xreal p2)
+{
+    const xreal L = l, M = m;
+    xreal A = sqrtl((4.0L * L * L - 1.0L) / (L * L - M * M));
+    xreal B = sqrtl(((L - 1.0L) * (L - 1.0L) - M * M) / (4.0L * (L - 1.0L) * (L - 1.0L) - 1.0L));
+    return A * (z * p1 - B * p2);
+}
+
 static void legendre_table(int Lmax, double z, double s, double *P)
 {
     const int ld = Lmax + 1;
-    double pmm = sqrt(1.0 / (4.0 * ORC_PI));
+    const xreal zx = z, sx = s;
+    xreal pmm = sqrtl(1.0L / (4.0L * ORC_PIL));
     for (int m = 0; m <= Lmax; ++m) {
         if (m > 0)
-            pmm = -pmm * s * sqrt((2.0 * m + 1.0) / (2.0 * m));
+            pmm = -pmm * sx * sqrtl((2.0L * m + 1.0L) / (2.0L * m));
         double *col = P + (size_t)m * ld;
-        col[m] = pmm;
+        col[m] = (double)pmm;
+        xreal p2 = pmm, p1 = sqrtl(2.0L * m + 3.0L) * zx * pmm;
         if (m + 1 <= Lmax)
-            col[m + 1] = sqrt(2.0 * m + 3.0) * z * pmm;
+            col[m + 1] = (double)p1;
         for (int l = m + 2; l <= Lmax; ++l) {
-            double A = sqrt((4.0 * l * l - 1.0) / ((double)l * l - (double)m * m));
-            double B = sqrt((((double)l - 1.0) * (l - 1.0) - (double)m * m) /
-                            (4.0 * ((double)l - 1.0) * (l - 1.0) - 1.0));
-            col[l] = A * (z * col[l - 1] - B * col[l - 2]);
+            xreal cur = legendre_step(l, m, zx, p1, p2);
+            col[l] = (double)cur;
+            p2 = p1;
+            p1 = cur;
         }
     }
 }
@@ -344,28 +364,26 @@ static int cmp_zkey(const void *p, const void *q)
 }
 
 /* Pbar_{l,am}(z) for l = lo..hi (hi <= Lmax) by the same recurrence as
- * legendre_table, restricted to one order; out[l - lo], zero for l < am. */
+ * legendre_table (extended type), restricted to one order; out[l - lo], zero
+ * for l < am. */
 static void legendre_column(int am, int lo, int hi, double z, double s, double *out)
 {
-    double pmm = sqrt(1.0 / (4.0 * ORC_PI));
+    const xreal zx = z, sx = s;
+    xreal pmm = sqrtl(1.0L / (4.0L * ORC_PIL));
     for (int m = 1; m <= am; ++m)
-        pmm = -pmm * s * sqrt((2.0 * m + 1.0) / (2.0 * m));
-    double p2 = 0.0, p1 = pmm; /* Pbar_{am-1}, Pbar_{am} */
+        pmm = -pmm * sx * sqrtl((2.0L * m + 1.0L) / (2.0L * m));
+    xreal p2 = 0.0L, p1 = pmm; /* Pbar_{l-2}, Pbar_{l-1} once l > am + 1 */
     for (int l = am; l <= hi; ++l) {
-        double cur;
+        xreal cur;
         if (l == am)
             cur = pmm;
         else if (l == am + 1)
-            cur = sqrt(2.0 * am + 3.0) * z * pmm;
-        else {
-            double A = sqrt((4.0 * l * l - 1.0) / ((double)l * l - (double)am * am));
-            double B = sqrt((((double)l - 1.0) * (l - 1.0) - (double)am * am) /
-                            (4.0 * ((double)l - 1.0) * (l - 1.0) - 1.0));
-            cur = A * (z * p1 - B * p2);
-        }
+            cur = sqrtl(2.0L * am + 3.0L) * zx * pmm;
+        else
+            cur = legendre_step(l, am, zx, p1, p2);
         if (l > am) { p2 = p1; p1 = cur; }
         if (l >= lo)
-            out[l - lo] = cur;
+            out[l - lo] = (double)cur;
     }
     for (int l = lo; l <= hi && l < am; ++l)
         out[l - lo] = 0.0;

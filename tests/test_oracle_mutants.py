@@ -10,13 +10,13 @@ import numpy as np
 import pytest
 
 import vsht_inputs as vi
-from test_oracle_pins import brute_vsh, scipy_Y
+from test_oracle_pins import EXTENDED_CASES, brute_vsh, lambda_explicit, point_at, scipy_Y
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
                    "vsht_oracle.c")
 
 MUTANTS = {
-    "no_condon_shortley": ("            pmm = -pmm * s * sqrt", "            pmm = pmm * s * sqrt"),
+    "no_condon_shortley": ("            pmm = -pmm * sx * sqrtl", "            pmm = pmm * sx * sqrtl"),
     "negative_order_no_sign": ("        p = -p; /* Y_{l,-|m|}", "        p = p; /* Y_{l,-|m|}"),
     "cg_sign_C4": ("B0 += dl * -sqrt(", "B0 += dl * sqrt("),
     "cg_index_C1": ("sqrt((L + M) * (L + M - 1.0) / ((2.0 * L)", "sqrt((L + M) * (L + M + 1.0) / ((2.0 * L)"),
@@ -27,8 +27,8 @@ MUTANTS = {
     "forward_no_conj": ("sa += conj(yd[c]) * Tk[c];", "sa += yd[c] * Tk[c];"),
     "forward_no_weight": ("pa[j] += w[k] * sa;", "pa[j] += sa;"),
     "adjoint_dropped_b": ("acc[c] += a[j] * yd[c] + b[j] * yc[c];", "acc[c] += a[j] * yd[c];"),
-    "recurrence_B": ("col[l] = A * (z * col[l - 1] - B * col[l - 2]);",
-                     "col[l] = A * (z * col[l - 1] + B * col[l - 2]);"),
+    "recurrence_B": ("return A * (z * p1 - B * p2);", "return A * (z * p1 + B * p2);"),
+    "binary64_recurrence": ("typedef long double xreal;", "typedef double xreal;"),
 }
 
 
@@ -81,7 +81,25 @@ def pins_pass(lib):
     b2 = np.zeros(K, np.complex128)
     lib.vo_forward(L, len(gw), p(gx), p(gw), p(T), p(a2), p(b2))
     err = np.linalg.norm(np.concatenate([a2 - a, b2 - b])) / np.linalg.norm(np.concatenate([a, b]))
-    return err < 1e-12
+    if err >= 1e-12:
+        return False
+    # one extended-range value (seed below binary64's range, value of order one)
+    theta, l, m = EXTENDED_CASES[0]
+    z, xyz = point_at(theta)
+    sign, lg = explicit_value(theta, l, m)
+    Yb = np.zeros((1, (l + 1) ** 2), np.complex128)
+    lib.vo_sph_harm(l, 1, p(xyz), p(Yb))
+    ref = sign * 10.0 ** lg
+    return abs(Yb[0, l * l + l + m].real - ref) <= 1e-10 * abs(ref)
+
+
+_explicit = {}
+
+
+def explicit_value(theta, l, m):
+    if (theta, l, m) not in _explicit:
+        _explicit[(theta, l, m)] = lambda_explicit(l, m, point_at(theta)[0])
+    return _explicit[(theta, l, m)]
 
 
 @pytest.mark.slow

@@ -19,7 +19,11 @@ Each test names what it pins and which plausible mistake it would catch:
   recombination, coefficients from sympy) -- including the full-range
   reading of nu^(2), nu^(4) and the failure of the literal zero cases;
 * radial invariance, the dot-product adjoint identity, and Tangent Field A's
-  closed-form coefficients (Section 5.2, fixture tests/golden/field_a.txt).
+  closed-form coefficients (Section 5.2, fixture tests/golden/field_a.txt);
+* the Legendre functions at Table 3's bandlimits, where the seed
+  Lambda_{m,m} = O(s^m) lies below binary64's range but the function grows to
+  O(1) by l = L, against the explicit polynomial form of P_l^m summed in exact
+  integer arithmetic -- catches a recurrence that flushes its seeds.
 """
 import math
 import os
@@ -371,3 +375,52 @@ def test_field_a_coefficients(orc):
     assert np.max(np.abs(b - b_ref)) < 1e-7
     assert abs(a_ref[4 * 4 + 4 + 0 - 1] - math.sqrt(20) / 25) < 1e-15
     assert abs(a_ref[6 * 6 + 6 - 3 - 1] - math.sqrt(42) / 25) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Extended exponent range (Section 3's Y_{l,m} at Table 3's bandlimits).
+# P_l^m(z) = (-1)^m (1 - z^2)^{m/2} d^m/dz^m P_l(z) with
+# P_l(z) = 2^-l sum_k (-1)^k C(l,k) C(2l-2k,l) z^{l-2k}: for a binary64 z = N / D
+# the derivative is an exact integer sum over D^(l-m); only the final logarithms
+# round.  Returns (sign, log10 |Lambda_{l,m}(z)|).
+# ---------------------------------------------------------------------------
+def lambda_explicit(l, m, z):
+    num, den = float(z).as_integer_ratio()
+    E = l - m
+    S = 0
+    k = 0
+    while l - 2 * k - m >= 0:
+        e = l - 2 * k - m
+        t = math.comb(l, k) * math.comb(2 * l - 2 * k, l) * math.perm(l - 2 * k, m)
+        t *= num ** e * den ** (E - e)
+        S += -t if k & 1 else t
+        k += 1
+    sign = (-1) ** m * (1 if S > 0 else -1)
+    lg = 0.5 * math.log10((2 * l + 1) / (4 * math.pi))
+    if m > 0:
+        lg -= 0.5 * math.log10(math.prod(range(l - m + 1, l + m + 1)))  # (l-m)!/(l+m)!
+    lg += 0.5 * m * (math.log10(den * den - num * num) - 2 * math.log10(den))
+    lg += math.log10(abs(S)) - l * math.log10(2) - E * math.log10(den)
+    return sign, lg
+
+
+# (theta, l, m): the first three have seeds near 1e-349, 1e-319 and 1e-327 (below
+# binary64's normal range) and values of order one; the fourth is deep in the
+# decaying region (1e-65) from the same 1e-349 seed; the last has a normal seed.
+EXTENDED_CASES = [(0.3, 2250, 660), (0.5, 2250, 1000), (0.4, 2100, 800), (0.3, 1500, 660),
+                  (1.2, 2250, 300)]
+
+
+def point_at(theta):
+    z = math.cos(theta)
+    return z, np.array([[math.sqrt((1 - z) * (1 + z)), 0.0, z]])
+
+
+def test_legendre_extended_range_vs_explicit_polynomial(orc):
+    for theta, l, m in EXTENDED_CASES:
+        z, xyz = point_at(theta)
+        sign, lg = lambda_explicit(l, m, z)
+        ref = sign * 10.0 ** lg
+        v = orc.sph_harm(l, xyz)[0, l * l + l + m]  # Y_{l,m}(theta, 0) = Lambda_{l,m}(z)
+        assert abs(v.imag) == 0.0
+        assert abs(v.real - ref) <= 1e-10 * abs(ref), (theta, l, m, v.real, ref)

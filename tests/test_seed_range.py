@@ -1,10 +1,12 @@
-"""The bandlimit the library serves (L <= 1664) is where flushing seeds that
-leave binary64's normal range loses nothing.  The normalised associated
-Legendre functions (Section 3) are run here by their three-term recurrence in
-degree with a separate decimal exponent, for every order m and every northern
-Gauss-Legendre ring, and every function whose seed Lambda_{m,m} = O(s^m) falls
-below the smallest normal binary64 number must stay below 1e-16 at all degrees
-m <= l <= L+1."""
+"""Why the Legendre stages carry an exponent past the seeds.  The normalised
+associated Legendre functions (Section 3) are run here by their three-term
+recurrence in degree with a separate decimal exponent, for every order m and
+every northern Gauss-Legendre ring.  Up to L = 1664 every function whose seed
+Lambda_{m,m} = O(s^m) falls below the smallest normal binary64 number stays
+below 1e-16 at all degrees m <= l <= L+1, so flushing such seeds would lose
+nothing; above it (Table 3 reaches L = 2250) flushed seeds start functions of
+order one, which is why each (order, ring) starts from a state computed with a
+carried exponent at its first significant degree."""
 import numpy as np
 import pytest
 
