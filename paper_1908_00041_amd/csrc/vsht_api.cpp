@@ -33,16 +33,13 @@ vsht_status hip_fail(hipError_t e, const char *what) {
     return e == hipErrorOutOfMemory ? VSHT_ENOMEM : VSHT_EDEVICE;
 }
 
-// Largest sizes the ring kernels are compiled for.
+// Longest ring the ring kernels are compiled for.
 constexpr int64_t kMaxNphi = 3072;
-constexpr int kMaxLRings = 2047;
-// Largest bandlimit served.  The binary64 seeds Lambda_{m,m} = O(s^m) leave the
-// normal range for large m near the poles; up to this L every such function stays
-// below 1e-16 over all its degrees l <= L+1 on the Gauss-Legendre rings
-// (measured by a log-scaled recurrence: largest 1e-16.2 at L = 1664, 5e-7 at
-// L = 1792), so flushing those seeds loses nothing.  Beyond it the seeds and the
-// recurrence would have to carry an exponent.
-constexpr int kMaxL = 1664;
+// Largest bandlimit served (parity-tested at L = 2250, Table 3's largest, and at
+// this limit).  The Legendre stages start every (order, ring pair) from a state
+// computed with a carried exponent, so seeds Lambda_{m,m} = O(s^m) below
+// binary64's range are no limit.
+constexpr int kMaxL = 4096;
 
 struct DeviceGuard {
     int old = -1;
@@ -70,9 +67,9 @@ hipError_t upload(T **dst, const std::vector<T> &src, size_t *bytes) {
 void free_plan_memory(Plan *p) {
     const NfftPlan &nf = p->nfft;
     void *ptrs[] = {p->d_rings, p->d_pairs, p->d_ffts, p->d_tw,  p->d_pair_z, p->d_aprime,
-                    p->d_cscale, p->d_etab, p->d_rsq,  p->d_seeds, p->d_weights, p->d_xyz, p->d_pb,  p->d_fg,  p->d_fg64, p->d_fpart,
-                    p->d_state, nf.d_ffts, nf.d_tw, nf.d_vpairs, nf.d_vz, nf.d_vs, nf.d_vseeds, nf.d_psihat, nf.d_pts,
-                    nf.d_vpb, nf.d_g1, nf.d_g};
+                    p->d_cscale, p->d_etab, p->d_rsq,  p->d_seeds, p->d_start, p->d_sblk, p->d_weights, p->d_xyz,
+                    p->d_pb, p->d_fg, p->d_fg64, p->d_fpart, p->d_state, nf.d_ffts, nf.d_tw, nf.d_vpairs, nf.d_vz,
+                    nf.d_vs, nf.d_vseeds, nf.d_vstart, nf.d_vsblk, nf.d_psihat, nf.d_pts, nf.d_vpb, nf.d_g1, nf.d_g};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
 }
@@ -229,6 +226,26 @@ int smooth_at_least(int n, int mult) {
     }
 }
 
+// Start blocks and states of the Legendre stages for NP ring pairs (z, s on the
+// device), allocated into *start and *sblk.
+hipError_t build_start_tables(int L, int NP, const double *d_z, const double *d_s, const double *d_aprime,
+                              const double *d_cscale, LegStart **start, int **sblk, size_t *bytes) {
+    const size_t cnt = (size_t)(L + 1) * NP;
+    hipError_t e = hipMalloc((void **)start, sizeof(LegStart) * cnt);
+    if (e != hipSuccess) return e;
+    if ((e = hipMalloc((void **)sblk, sizeof(int) * cnt)) != hipSuccess) return e;
+    *bytes += (sizeof(LegStart) + sizeof(int)) * cnt;
+    int *d_bad = nullptr;
+    if ((e = hipMalloc((void **)&d_bad, sizeof(int))) != hipSuccess) return e;
+    int bad = 0;
+    e = hipMemcpy(d_bad, &bad, sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_start_kernel(d_z, d_s, NP, L, d_aprime, d_cscale, *start, *sblk, d_bad, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost);
+    (void)hipFree(d_bad);
+    if (e == hipSuccess && bad) e = hipErrorNotSupported;  // a start state outside the normal range
+    return e;
+}
+
 // Largest bandlimit the double-Fourier-sphere path serves (its DFT lengths stay
 // within the ring DFT kernels' limits).
 constexpr int kMaxNfftL = 700;
@@ -273,6 +290,9 @@ hipError_t build_nfft(Plan &P, int64_t n, const double *xyz) {
     e = hipMalloc((void **)&nf.d_vseeds, sizeof(double) * (size_t)(L + 1) * nf.npv);
     if (e != hipSuccess) return e;
     if ((e = launch_seed_kernel(nf.d_vs, nf.npv, L, nf.d_vseeds, nullptr)) != hipSuccess) return e;
+    if ((e = build_start_tables(L, nf.npv, nf.d_vz, nf.d_vs, P.d_aprime, P.d_cscale, &nf.d_vstart, &nf.d_vsblk,
+                                &bytes)) != hipSuccess)
+        return e;
     // window transform psih(k) = alpha int_{-1}^{1} exp(beta (sqrt(1 - t^2) - 1)) cos(k alpha t) dt,
     // alpha = w h / 2, with t = sin(u) (a smooth integrand) and composite Simpson
     {
@@ -397,9 +417,7 @@ RingScan scan_rings(int64_t n, const double *xyz, const double *w) {
 vsht_status check_plan_args(int L, int64_t n, const double *xyz, const double *w, int precision) {
     if (L < 1) return fail(VSHT_EINVAL, "L must be >= 1");
     if (L > 65535) return fail(VSHT_EINVAL, "L too large");
-    if (L > kMaxL)
-        return fail(VSHT_EUNSUPPORTED, "L > " + std::to_string(kMaxL) +
-                                           ": binary64 seeds would underflow for functions that matter");
+    if (L > kMaxL) return fail(VSHT_EUNSUPPORTED, "L > " + std::to_string(kMaxL) + " is not served");
     if (n < 1) return fail(VSHT_EINVAL, "n must be >= 1");
     if (w && n < 2) return fail(VSHT_EINVAL, "a quadrature rule needs n >= 2 points");
     if (!xyz) return fail(VSHT_EINVAL, "xyz is NULL");
@@ -451,10 +469,6 @@ vsht_status build_plan(Plan &P, int L, int64_t n, const double *xyz, const doubl
     if (scan.ok && (int64_t)scan.rings.size() * 2 > n && n > 8) {
         scan.ok = false;
         scan.why = "too many rings";
-    }
-    if (scan.ok && L > kMaxLRings) {
-        scan.ok = false;
-        scan.why = "L too large for the ring kernels";
     }
     std::vector<double> tmp;
     hipError_t e = hipSuccess;
@@ -611,6 +625,9 @@ vsht_status build_plan(Plan &P, int L, int64_t n, const double *xyz, const doubl
                 P.table_bytes += sizeof(double) * (size_t)(L + 1) * P.n_pairs;
                 e = launch_seed_kernel(d_ps, (int)P.n_pairs, L, P.d_seeds, nullptr);
             }
+            if (e == hipSuccess)
+                e = build_start_tables(L, (int)P.n_pairs, P.d_pair_z, d_ps, P.d_aprime, P.d_cscale, &P.d_start,
+                                       &P.d_sblk, &P.table_bytes);
             if (e == hipSuccess) e = hipDeviceSynchronize();
             (void)hipFree(d_ps);
             if (e != hipSuccess) goto hip_error;
@@ -657,8 +674,8 @@ vsht_status build_plan(Plan &P, int L, int64_t n, const double *xyz, const doubl
             if (e == hipErrorInvalidValue) {
                 e = hipSuccess;  // grid sizes the DFT kernels cannot take: direct evaluation
                 NfftPlan &nf = P.nfft;
-                void *q[] = {nf.d_ffts, nf.d_tw, nf.d_vpairs, nf.d_vz, nf.d_vs, nf.d_vseeds, nf.d_psihat, nf.d_pts,
-                             nf.d_vpb, nf.d_g1, nf.d_g};
+                void *q[] = {nf.d_ffts, nf.d_tw,     nf.d_vpairs, nf.d_vz,     nf.d_vs, nf.d_vseeds, nf.d_vstart,
+                             nf.d_vsblk, nf.d_psihat, nf.d_pts,    nf.d_vpb, nf.d_g1, nf.d_g};
                 for (void *x : q)
                     if (x) (void)hipFree(x);
                 nf = NfftPlan();

@@ -89,6 +89,22 @@ struct NfftPoint {
     int64_t idx;         // position in the caller's point order
 };
 
+// Where each (order m, ring pair p) enters the Legendre stages.  Degrees are
+// taken in blocks of kStartBlock from l' = m; (m, p) starts at block b with the
+// recurrence state (Q_{l0-1}, Q_{l0-2}), l0 = m + kStartBlock b, and adds
+// nothing before it.  b is the last block boundary at or below the first degree
+// where |Lambda_{l',m}(z_p)| >= 2^kSignificantExp2, or kStartNever when no degree
+// up to L+1 gets there.  The state is computed with a carried exponent, so it
+// exists even where the seed Lambda_{m,m} = O(s^m) lies below binary64's range,
+// and it is bitwise the state the recurrence from the seed would reach if
+// binary64 had no exponent limit (a start at b = 0 is (0, -Lambda_{m,m})).
+struct alignas(16) LegStart {
+    double q1, q2;
+};
+constexpr int kStartBlock = 32;
+constexpr int kStartNever = 1 << 24;
+constexpr int kSignificantExp2 = -64;
+
 // Scattered points through the double Fourier sphere: the synthesis runs on
 // nt equispaced colatitudes theta_t = 2 pi (t + 1/2) / nt of the doubled
 // circle (nt/4 virtual north/south ring pairs), a DFT in theta gives the 2-D
@@ -108,6 +124,8 @@ struct NfftPlan {
     double *d_vz = nullptr;           // z of each virtual pair's northern colatitude
     double *d_vs = nullptr;           // its sin theta
     double *d_vseeds = nullptr;       // Lambda_{m,m}, [(L+1)][npv]
+    LegStart *d_vstart = nullptr;     // start states, [(L+1)][npv]
+    int *d_vsblk = nullptr;           // start blocks, [(L+1)][npv]
     double *d_psihat = nullptr;       // window transform at k = -L..L
     NfftPoint *d_pts = nullptr;
     void *d_vpb = nullptr;            // virtual pair buffer [(L+1)][npv][16] reals (adjoint),
@@ -162,6 +180,8 @@ struct Plan {
     double *d_etab = nullptr;      // e_{l,m} = sqrt((l^2-m^2)/(4l^2-1)), [tri]
     double *d_rsq = nullptr;       // 1/sqrt(l(l+1)), [L+2] (0 at l = 0)
     double *d_seeds = nullptr;     // Lambda_{m,m}(z_p), [(L+1)][NP]
+    LegStart *d_start = nullptr;   // start states of the Legendre stages, [(L+1)][NP]
+    int *d_sblk = nullptr;         // start blocks, [(L+1)][NP]
     double *d_weights = nullptr;   // per-point weights (rings with non-uniform weights)
     double *d_xyz = nullptr;       // points (scattered plans)
     size_t table_bytes = 0;
@@ -233,6 +253,12 @@ size_t static_forward_bytes(const Plan &p);
 hipError_t launch_forward_static(const Plan &p, const void *T, void *a, void *b, hipStream_t st);
 hipError_t launch_sht_adjoint(const Plan &p, const void *flm, void *f, hipStream_t st);
 hipError_t launch_seed_kernel(const double *pair_s, int NP, int L, double *seeds, hipStream_t st);
+// Start blocks and states of every (m, p), p < NP; *bad (device) is set to 1 if a
+// state falls outside binary64's normal range (never expected: it is at least
+// 2^kSignificantExp2 divided by the growth over kStartBlock + 2 degrees).
+hipError_t launch_start_kernel(const double *pair_z, const double *pair_s, int NP, int L,
+                               const double *aprime, const double *cscale, LegStart *start,
+                               int *sblk, int *bad, hipStream_t st);
 
 hipError_t set_kernel_attributes();
 

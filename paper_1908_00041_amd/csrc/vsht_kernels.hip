@@ -103,6 +103,107 @@ __global__ void k_seeds(const double *__restrict__ pair_s, int NP, int L,
 }
 
 // ---------------------------------------------------------------------------
+// Start blocks and states (plan time).  One thread per (p, m): the seed as in
+// k_seeds (same operations, so a start at block 0 is (0, -seeds[m][p]) bit for
+// bit), then the recurrence Q_l = a'_l z Q_{l-1} - Q_{l-2} exactly as the
+// Legendre stages evaluate it, on a state (q1, q2) scaled by 2^E: scaling by a
+// power of two commutes with every rounding in the normal range, so the state
+// saved at each block boundary is the unscaled recurrence's state.  The first
+// degree with |c_l Q_l| >= 2^kSignificantExp2 (Lambda = c Q) fixes the block.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_leg_start(const double *__restrict__ pair_z,
+                                                 const double *__restrict__ pair_s, int NP, int L,
+                                                 const double *__restrict__ aprime,
+                                                 const double *__restrict__ cscale,
+                                                 LegStart *__restrict__ start, int *__restrict__ sblk,
+                                                 int *__restrict__ bad) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    if (p >= NP) return;
+    const double s = pair_s[p], z = pair_z[p];
+    double mant = 0.28209479177387814347403972578;  // 1/sqrt(4 pi)
+    int e2 = 0;
+    for (int k = 1; k <= m; ++k) {
+        mant *= -sqrt((2.0 * k + 1.0) / (2.0 * k)) * s;
+        int ex;
+        mant = frexp(mant, &ex);
+        e2 += ex;
+    }
+    const int64_t t0 = tri_offset(L, m);
+    const double *ap = aprime + t0 - m, *cs = cscale + t0 - m;  // indexed by l'
+    double q1 = 0.0, q2 = -mant;  // true state = (q1, q2) 2^E
+    int E = e2;
+    double bq1 = q1, bq2 = q2;
+    int bE = E, bl = m;
+    int blk = kStartNever;
+    for (int l = m; l <= L + 1; ++l) {
+        if (((l - m) & (kStartBlock - 1)) == 0) {
+            bq1 = q1;
+            bq2 = q2;
+            bE = E;
+            bl = l;
+        }
+        const double v = fma(ap[l] * z, q1, -q2);
+        int ev;
+        (void)frexp(v * cs[l], &ev);  // |c_l v| in [2^(ev-1), 2^ev)
+        if (v != 0.0 && ev - 1 + E >= kSignificantExp2) {
+            blk = (bl - m) / kStartBlock;
+            break;
+        }
+        q2 = q1;
+        q1 = v;
+        int eq;
+        (void)frexp(q1, &eq);
+        if (q1 != 0.0 && (eq > 64 || eq < -64)) {
+            q1 = ldexp(q1, -eq);
+            q2 = ldexp(q2, -eq);
+            E += eq;
+        }
+    }
+    LegStart st{0.0, 0.0};
+    if (blk != kStartNever) {
+        st.q1 = ldexp(bq1, bE);
+        st.q2 = ldexp(bq2, bE);
+        const double lo = 2.2250738585072014e-308;  // smallest normal binary64
+        if (blk > 0 && !(fabs(st.q1) >= lo && fabs(st.q2) >= lo)) *bad = 1;
+    }
+    start[(size_t)m * NP + p] = st;
+    sblk[(size_t)m * NP + p] = blk;
+}
+
+// A lane's start in a Legendre stage: block (kStartNever for lanes without a
+// ring pair) and state.  The lane's recurrence holds (0, 0) until its block
+// boundary, where it takes the state.
+struct LaneStart {
+    double q1, q2;
+    int blk;
+};
+__device__ __forceinline__ LaneStart lane_start(const LegStart *__restrict__ start, const int *__restrict__ sblk,
+                                                size_t idx, bool valid) {
+    LaneStart r{0.0, 0.0, kStartNever};
+    if (valid) {
+        const LegStart v = start[idx];
+        r.q1 = v.q1;
+        r.q2 = v.q2;
+        r.blk = sblk[idx];
+    }
+    return r;
+}
+// first start block of the wave (wave-uniform)
+__device__ __forceinline__ int wave_min_blk(int b) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) b = min(b, __shfl_xor(b, o));
+    return uniform_int(b);
+}
+// entering the degree block that begins d = l' - m degrees after m
+__device__ __forceinline__ void take_start(const LaneStart &S, int d, double &q1, double &q2) {
+    if (d == kStartBlock * S.blk) {
+        q1 = S.q1;
+        q2 = S.q2;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // LDS mixed-radix Stockham DFT of two sequences of length n stored
 // back-to-back in `buf`.  A stage with radix R and span Ns reads x[j + t n/R]
 // (t < R) for butterfly j, multiplies input t by W^t with
@@ -926,7 +1027,9 @@ struct LegFwdArgs {
     const real *RB;        // [(L+1)][NR][8]
     real *F;               // [tri][8]
     const PairDesc *pairs;
-    const double *seeds;   // [(L+1)][NP]
+    const double *seeds;   // [(L+1)][NP] (the equator pair's seed)
+    const LegStart *start; // [(L+1)][NP]
+    const int *sblk;       // [(L+1)][NP]
     const double *pz;
     const double *aprime;  // [tri]
     const double *cscale;  // [tri]
@@ -1006,6 +1109,21 @@ struct SwzQ2Fwd {
     static __device__ __forceinline__ int slot(int pair, int q) { return pair * 8 + (q ^ ((pair >> 1) & 7)); }
 };
 
+// First 16-degree block that the wave (wfirst) and the workgroup (gfirst) of an
+// analysis must contract: earlier blocks hold zeros only.  A wave skips its
+// blocks before wfirst; blocks before gfirst skip the reduction as well.  The
+// waves exchange wfirst through xch (nw ints of the reduction buffer, free again
+// after the second barrier).
+__device__ __forceinline__ void first_blocks(int sblk, int nblk, int wave, int nw, int *xch, int &wfirst,
+                                             int &gfirst) {
+    wfirst = min(wave_min_blk(sblk) * (kStartBlock / kRowsB), nblk);
+    if ((threadIdx.x & 63) == 0) xch[wave] = wfirst;
+    __syncthreads();
+    gfirst = nblk;
+    for (int w = 0; w < nw; ++w) gfirst = min(gfirst, xch[w]);
+    __syncthreads();
+}
+
 // Analysis, binary64: workgroup = order m, waves = tiles of 64 ring pairs.
 // Instruction (row group r, pair step g): block b = (parity pi = b>>1, column
 // half h = b&1), rows = degrees lp0 + 4i + 2r + pi, K = pairs 4g + k,
@@ -1039,12 +1157,15 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
     const int p = tile * kTileP + lane;
     const bool valid = p < NPT;
     const double z = valid ? A.pz[p] : 0.0;
-    double q1 = 0.0, q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+    const LaneStart S = lane_start(A.start, A.sblk, (size_t)m * NP + p, valid);
+    double q1 = 0.0, q2 = 0.0;
     const double seq = A.eq_ring >= 0 ? A.seeds[(size_t)m * NP + NPT] : 0.0;
     const double *xeq = A.eq_ring >= 0 ? RBm + (size_t)A.eq_ring * 8 : nullptr;
     const double *ap = A.aprime + t0 - m;  // indexed by l'
     const int nl = L + 2 - m;
     const int nblk = (nl + kRowsB - 1) / kRowsB;
+    int wfirst, gfirst;
+    first_blocks(S.blk, nblk, wave, nw, reinterpret_cast<int *>(red), wfirst, gfirst);
     // output slots o = threadIdx.x + 64 u (u < 2) of the reduction; their c_{l'} factors
     // are loaded at the start of each block, well before the reduction needs them
     auto out_slot = [&](int o, int &lp_off, int &c) {
@@ -1064,34 +1185,39 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
             const int lp = lp0 + so;
             csc[u] = (o < 128 && (u == 0 || blockDim.x == 64) && lp <= L + 1) ? A.cscale[t0 + lp - m] : 0.0;
         }
-        double ab[kRowsB];
-        load_aprime(ap, lp0, L + 1, ab);
-        double held[2] = {0.0, 0.0};  // rows 4i + pi, waiting for their partner two rows on
-#pragma unroll
-        for (int s = 0; s < kRowsB; ++s) {
-            const double v = fma(ab[s] * z, q1, -q2);
-            if (s & 2)
-                qt[SwzQ2Fwd::slot(lane, 2 * (s >> 2) + (s & 1))] = double2{held[s & 1], v};
-            else
-                held[s & 1] = v;
-            q2 = q1;
-            q1 = v;
-        }
-        __builtin_amdgcn_wave_barrier();
         double acc0 = 0.0, acc1 = 0.0;
+        if (blk >= wfirst) {
+            take_start(S, blk * kRowsB, q1, q2);
+            double ab[kRowsB];
+            load_aprime(ap, lp0, L + 1, ab);
+            double held[2] = {0.0, 0.0};  // rows 4i + pi, waiting for their partner two rows on
 #pragma unroll
-        for (int g = 0; g < 16; ++g) {
-            const double2 av = qt[SwzQ2Fwd::slot(4 * g + k, 2 * i + pi)];
-            const double a0 = av.x, a1 = av.y;
-            acc0 = mma44(a0, bv[g], acc0);
-            acc1 = mma44(a1, bv[g], acc1);
+            for (int s = 0; s < kRowsB; ++s) {
+                const double v = fma(ab[s] * z, q1, -q2);
+                if (s & 2)
+                    qt[SwzQ2Fwd::slot(lane, 2 * (s >> 2) + (s & 1))] = double2{held[s & 1], v};
+                else
+                    held[s & 1] = v;
+                q2 = q1;
+                q1 = v;
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int g = 0; g < 16; ++g) {
+                const double2 av = qt[SwzQ2Fwd::slot(4 * g + k, 2 * i + pi)];
+                const double a0 = av.x, a1 = av.y;
+                acc0 = mma44(a0, bv[g], acc0);
+                acc1 = mma44(a1, bv[g], acc1);
+            }
+            __builtin_amdgcn_wave_barrier();
         }
-        __builtin_amdgcn_wave_barrier();
-        // D lane l: row (l >> 4) of block b -> degree offset 4(l>>4) + 2r + pi, column col
-        double *rw = red + ((blk & 1) * nw + wave) * 128;
-        rw[lane] = acc0;
-        rw[64 + lane] = acc1;
-        __syncthreads();
+        if (blk >= gfirst) {
+            // D lane l: row (l >> 4) of block b -> degree offset 4(l>>4) + 2r + pi, column col
+            double *rw = red + ((blk & 1) * nw + wave) * 128;
+            rw[lane] = acc0;
+            rw[64 + lane] = acc1;
+            __syncthreads();
+        }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int o = threadIdx.x + u * 64;
@@ -1101,9 +1227,11 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
             const int ppi = so & 1;
             const int lp = lp0 + so;
             if (lp <= L + 1) {
-                const double *rb = red + (blk & 1) * nw * 128;
                 double sum = 0.0;
-                for (int w = 0; w < nw; ++w) sum += rb[w * 128 + o];
+                if (blk >= gfirst) {
+                    const double *rb = red + (blk & 1) * nw * 128;
+                    for (int w = 0; w < nw; ++w) sum += rb[w * 128 + o];
+                }
                 const int64_t ti = t0 + lp - m;
                 if (xeq && ppi == 0 && group == 0) {
                     const int kk = (lp - m) >> 1;
@@ -1149,31 +1277,39 @@ __device__ __forceinline__ void leg_fwd_body(const LegFwdArgs<real> &A, int m, i
     const int p = tile * kTileP + lane;
     const bool valid = p < NPT;
     const double z = valid ? A.pz[p] : 0.0;
-    double q1 = 0.0, q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+    const LaneStart S = lane_start(A.start, A.sblk, (size_t)m * NP + p, valid);
+    double q1 = 0.0, q2 = 0.0;
     // equator ring (z = 0): Q_{m+2k} = (-1)^k Lambda_{m,m}(0), odd degrees vanish
     const double seq = A.eq_ring >= 0 ? A.seeds[(size_t)m * NP + NPT] : 0.0;
     const real *xeq = A.eq_ring >= 0 ? RBm + (size_t)A.eq_ring * 8 : nullptr;
     const int nl = L + 2 - m;
     const int nblk = (nl + kRowsB - 1) / kRowsB;
+    int wfirst, gfirst;
+    first_blocks(S.blk, nblk, wave, nw, reinterpret_cast<int *>(red), wfirst, gfirst);
     for (int blk = 0; blk < nblk; ++blk) {
         const int lp0 = m + blk * kRowsB;
-        const int la = lp0 + (lane & 15);
-        const double areg = la <= L + 1 ? A.aprime[t0 + la - m] : 0.0;
-        recur16<real, SwzFwd>(qt, areg, z, q1, q2, lane);
         acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+        if (blk >= wfirst) {
+            take_start(S, blk * kRowsB, q1, q2);
+            const int la = lp0 + (lane & 15);
+            const double areg = la <= L + 1 ? A.aprime[t0 + la - m] : 0.0;
+            recur16<real, SwzFwd>(qt, areg, z, q1, q2, lane);
 #pragma unroll
-        for (int g = 0; g < 16; g += 2) {
-            const real a0 = qt[SwzFwd::at(j, 4 * g + k)];
-            const real a1 = qt[SwzFwd::at(j, 4 * (g + 1) + k)];
-            acc0 = Mfma<real>::mma(a0, bv[g], acc0);
-            acc1 = Mfma<real>::mma(a1, bv[g + 1], acc1);
+            for (int g = 0; g < 16; g += 2) {
+                const real a0 = qt[SwzFwd::at(j, 4 * g + k)];
+                const real a1 = qt[SwzFwd::at(j, 4 * (g + 1) + k)];
+                acc0 = Mfma<real>::mma(a0, bv[g], acc0);
+                acc1 = Mfma<real>::mma(a1, bv[g + 1], acc1);
+            }
         }
-        // valid half of this wave's partial block -> red[blk & 1][wave]
-        real *rw = red + ((blk & 1) * nw + wave) * 128;
+        if (blk >= gfirst) {
+            // valid half of this wave's partial block -> red[blk & 1][wave]
+            real *rw = red + ((blk & 1) * nw + wave) * 128;
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            if (FwdCompact<real>::valid(lane, r)) rw[FwdCompact<real>::slot(lane, r)] = acc0[r] + acc1[r];
-        __syncthreads();
+            for (int r = 0; r < 4; ++r)
+                if (FwdCompact<real>::valid(lane, r)) rw[FwdCompact<real>::slot(lane, r)] = acc0[r] + acc1[r];
+            __syncthreads();
+        }
         // sum over waves and store; the buffer of block blk is rewritten at
         // blk + 2, after the next barrier, so one barrier per block suffices
         for (int o = threadIdx.x; o < 128; o += blockDim.x) {
@@ -1181,9 +1317,11 @@ __device__ __forceinline__ void leg_fwd_body(const LegFwdArgs<real> &A, int m, i
             FwdCompact<real>::rc(o, row, col);
             const int lp = lp0 + row;
             if (lp <= L + 1) {
-                const real *rb = red + (blk & 1) * nw * 128;
                 real sum = 0;
-                for (int w = 0; w < nw; ++w) sum += rb[w * 128 + o];
+                if (blk >= gfirst) {
+                    const real *rb = red + (blk & 1) * nw * 128;
+                    for (int w = 0; w < nw; ++w) sum += rb[w * 128 + o];
+                }
                 const int64_t ti = t0 + lp - m;
                 if (xeq && col < 8 && group == 0) {
                     // even-parity row: the equator adds Q_{lp}(0) X_eq
@@ -1224,7 +1362,9 @@ struct LegArgs {
     const double *FG64;   // g as binary64 rows, [tri][8]: FG itself on the binary64 path, the
                           // plan's binary64 triangle (written by the prep) on the binary32 paths
     real *PB;             // [(L+1)][NP][16]
-    const double *seeds;
+    const double *seeds;  // the equator pair's seed
+    const LegStart *start;
+    const int *sblk;
     const double *pz;
     const double *aprime;
     int L;
@@ -1253,6 +1393,8 @@ constexpr int kPolarPairs = 32;
 // the sums are stored in binary32), and it needs neither the LDS staging of the
 // Legendre values nor products on zero parity blocks.
 constexpr int kAdjChunk = 32;  // degrees per LDS buffer (two buffers)
+static_assert(kAdjChunk == kStartBlock, "a chunk is one start block");
+static_assert(kStartBlock % kRowsB == 0, "start blocks are whole 16-degree blocks");
 struct alignas(16) AdjRow {
     double g[8];  // g[l'] (theta, phi) x (+m, -m), complex
     double a;     // a'_{l'}
@@ -1288,7 +1430,7 @@ __device__ __forceinline__ void fmac_row_bcastn(double (&S)[N], double g, double
 
 // One workgroup of order m, all its waves staging g and a' together (kAdjChunk
 // rows at a time, two buffers, coalesced loads one chunk ahead); the calling
-// wave carries PPL pairs per lane, pw + u 64 + lane (u < PPL, pair < pend), and
+// wave carries PPL pairs per lane, pw + PPL lane + u (u < PPL, pair < pend), and
 // the g columns [C0, C0 + NC) through the degrees l' = m .. L+1, into even (E)
 // and odd (O) sums.  FG: binary64 rows of the triangle (row l' of order m at
 // FG + 8 (tri(m) - m + l')).  eqw: the wave also forms the equator pair (index
@@ -1303,22 +1445,33 @@ __device__ __forceinline__ void adj_valu_block(const LegArgs<out> &A, const doub
     const int64_t t0 = tri_offset(L, m);
     const double *g = FG + (t0 - m) * 8;  // row l' at g + 8 l'
     const double *ap = A.aprime + t0 - m;
+    static_assert(PPL == 1 || PPL == 2, "one or two pairs per lane");
+    // start chunks and states wait in LDS (registers are the limit of the degree loop)
+    __shared__ double2 s_state[4][PPL][kTileP];
+    __shared__ int s_blk[4][PPL][kTileP];
+    const int wave = threadIdx.x >> 6;
     double z[PPL], q1[PPL], q2[PPL];
     double E[PPL][NC], O[PPL][NC];
+    int first = kStartNever;  // first chunk in which the wave's pairs are not all zero
 #pragma unroll
     for (int u = 0; u < PPL; ++u) {
-        const int p = pw + u * kTileP + lane;
+        // the lane's pairs are adjacent, so that both start near the same chunk
+        const int p = pw + PPL * lane + u;
         const bool valid = p < pend;
         z[u] = valid ? A.pz[p] : 0.0;
-        q1[u] = 0.0;
-        q2[u] = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+        q1[u] = q2[u] = 0.0;
+        const LaneStart S = lane_start(A.start, A.sblk, (size_t)m * NP + p, valid);
+        s_state[wave][u][lane] = double2{S.q1, S.q2};
+        s_blk[wave][u][lane] = S.blk;
+        first = min(first, S.blk);
         // re-define the loaded values here, so that the degree loop below does not
         // read registers filled by loads (the wait inserted for those would also
         // wait for the staging loads of the next chunk)
-        asm volatile("" : "+v"(z[u]), "+v"(q2[u]));
+        asm volatile("" : "+v"(z[u]));
 #pragma unroll
         for (int c = 0; c < NC; ++c) E[u][c] = O[u][c] = 0.0;
     }
+    first = wave_min_blk(first);
     const int nl = Lp1 - m + 1;
     const int nchunk = (nl + kAdjChunk - 1) / kAdjChunk;
     // staging: item i < 8 kAdjChunk is g value (i & 7) of row i >> 3; thread t < kAdjChunk
@@ -1366,30 +1519,40 @@ __device__ __forceinline__ void adj_valu_block(const LegArgs<out> &A, const doub
         }
         // the chunk starts an even number of degrees after m: row d has the parity of d;
         // lanes 0-7 of every row of 16 hold g of degree d, lanes 8-15 that of d + 1, and
-        // each FMA takes its value by row broadcast
-        const int sel = (lane >> 3) & 1, col = lane & 7;
-        double Gn = rows[sel].g[col], a0n = rows[0].a, a1n = rows[1].a;
-        for (int d = 0; d < nd; d += 2) {
-            const double G = Gn, a0 = a0n, a1 = a1n;
-            // the next step's operands, read while this step computes
-            const int dn = d + 2 < kAdjChunk ? d + 2 : d;
-            Gn = rows[dn + sel].g[col];
-            a0n = rows[dn].a;
-            a1n = rows[dn + 1].a;
+        // each FMA takes its value by row broadcast.  Chunks before the wave's first
+        // start hold zeros only.
+        if (k >= first) {
 #pragma unroll
-            for (int u = 0; u < PPL; ++u) {
-                const double v = fma(a0 * z[u], q1[u], -q2[u]);
-                fmac_row_bcastn<C0, NC>(E[u], G, v);
-                q2[u] = q1[u];
-                q1[u] = v;
-            }
-            if (d + 1 < nd) {
+            for (int u = 0; u < PPL; ++u)
+                if (s_blk[wave][u][lane] == k) {
+                    const double2 v = s_state[wave][u][lane];
+                    q1[u] = v.x;
+                    q2[u] = v.y;
+                }
+            const int sel = (lane >> 3) & 1, col = lane & 7;
+            double Gn = rows[sel].g[col], a0n = rows[0].a, a1n = rows[1].a;
+            for (int d = 0; d < nd; d += 2) {
+                const double G = Gn, a0 = a0n, a1 = a1n;
+                // the next step's operands, read while this step computes
+                const int dn = d + 2 < kAdjChunk ? d + 2 : d;
+                Gn = rows[dn + sel].g[col];
+                a0n = rows[dn].a;
+                a1n = rows[dn + 1].a;
 #pragma unroll
                 for (int u = 0; u < PPL; ++u) {
-                    const double v = fma(a1 * z[u], q1[u], -q2[u]);
-                    fmac_row_bcastn<8 + C0, NC>(O[u], G, v);
+                    const double v = fma(a0 * z[u], q1[u], -q2[u]);
+                    fmac_row_bcastn<C0, NC>(E[u], G, v);
                     q2[u] = q1[u];
                     q1[u] = v;
+                }
+                if (d + 1 < nd) {
+#pragma unroll
+                    for (int u = 0; u < PPL; ++u) {
+                        const double v = fma(a1 * z[u], q1[u], -q2[u]);
+                        fmac_row_bcastn<8 + C0, NC>(O[u], G, v);
+                        q2[u] = q1[u];
+                        q1[u] = v;
+                    }
                 }
             }
         }
@@ -1398,7 +1561,7 @@ __device__ __forceinline__ void adj_valu_block(const LegArgs<out> &A, const doub
     }
 #pragma unroll
     for (int u = 0; u < PPL; ++u) {
-        const int p = pw + u * kTileP + lane;
+        const int p = pw + PPL * lane + u;
         if (p < pend) {
             out *o = A.PB + ((size_t)m * NP + p) * 16;
 #pragma unroll
@@ -1422,13 +1585,12 @@ __device__ __forceinline__ void adj_valu_block(const LegArgs<out> &A, const doub
 }
 
 // One wave of the split-bf16 paths' binary32 tile: pairs [p0, p0 + 64) of order
-// m over the degrees [lA, lB) (lA an even number of degrees after m), from the
-// lane's recurrence state (q1, q2), on the binary32 16x16x4 MFMA through the
-// wave's Q tile qt.  Each 16-degree block is summed apart and added to the
+// m over the degrees below lB, each lane's pair from its start S, on the
+// binary32 16x16x4 MFMA through the wave's Q tile qt.  Each 16-degree block is summed apart and added to the
 // totals (two-level summation).  acc[b]: lane l, register r -> pair
 // p0 + 16 b + Mfma<float>::row(l, r), column l % 16 (8 even-sum columns, then 8 odd).
-__device__ __forceinline__ void adj_tile_f32(const LegArgs<float> &A, int m, int p0, int lA, int lB, double z,
-                                             double q1, double q2, f32x4 (&acc)[4], float *qt) {
+__device__ __forceinline__ void adj_tile_f32(const LegArgs<float> &A, int m, int p0, int lB, double z,
+                                             const LaneStart &S, f32x4 (&acc)[4], float *qt) {
     const int lane = threadIdx.x & 63;
     const int L = A.L;
     const int64_t t0 = tri_offset(L, m);
@@ -1436,9 +1598,13 @@ __device__ __forceinline__ void adj_tile_f32(const LegArgs<float> &A, int m, int
     const int j = lane & 15, k = lane >> 4;
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[b] = f32x4{0, 0, 0, 0};
+    // degrees before the wave's first start block hold zeros only
+    const int lA = min(m + kStartBlock * wave_min_blk(S.blk), lB);
+    double q1 = 0.0, q2 = 0.0;
     const int nblk = (lB - lA + kRowsB - 1) / kRowsB;
     for (int blk = 0; blk < nblk; ++blk) {
         const int lp0 = lA + blk * kRowsB;
+        take_start(S, lp0 - m, q1, q2);
         const int la = lp0 + (lane & 15);
         const double areg = la < lB ? A.aprime[t0 + la - m] : 0.0;
         // B operands: lane (j + 16k) holds g[row 4gg + k][j & 7] if the row's
@@ -1646,46 +1812,56 @@ __device__ __forceinline__ void leg_fwd_bf16_body(const LegFwdArgs<float> &A, in
     const int p = tile * kTileP + lane;
     const bool valid = p < NPT;
     const double z = valid ? A.pz[p] : 0.0;
-    double q1 = 0.0, q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+    const LaneStart S = lane_start(A.start, A.sblk, (size_t)m * NP + p, valid);
+    double q1 = 0.0, q2 = 0.0;
     const double seq = A.eq_ring >= 0 ? A.seeds[(size_t)m * NP + NPT] : 0.0;
     const float *xeq = A.eq_ring >= 0 ? RBm + (size_t)A.eq_ring * 8 : nullptr;
     const double *ap = A.aprime + t0 - m;  // indexed by l'
     const int nl = L + 2 - m;
     const int nblk = (nl + kRowsB - 1) / kRowsB;
+    int wfirst, gfirst;
+    first_blocks(S.blk, nblk, wave, nw, reinterpret_cast<int *>(red), wfirst, gfirst);
     for (int blk = 0; blk < nblk; ++blk) {
         const int lp0 = m + blk * kRowsB;
-        double ab[kRowsB];
-        load_aprime(ap, lp0, L + 1, ab);
-#pragma unroll
-        for (int s = 0; s < kRowsB; ++s) {
-            const double v = fma(ab[s] * z, q1, -q2);
-            qt[SwzFwd8::at(s, lane)] = (float)v;
-            q2 = q1;
-            q1 = v;
-        }
-        __builtin_amdgcn_wave_barrier();
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        if (blk >= wfirst) {
+            take_start(S, blk * kRowsB, q1, q2);
+            double ab[kRowsB];
+            load_aprime(ap, lp0, L + 1, ab);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const float4 *src = reinterpret_cast<const float4 *>(qt + SwzFwd8::at(j, 32 * c + 8 * kg));
-            const float4 u0 = src[0], u1 = src[1];
-            const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
-            acc = mma_split<NPROD>(split8<NPROD>(v), bx[c], acc);
+            for (int s = 0; s < kRowsB; ++s) {
+                const double v = fma(ab[s] * z, q1, -q2);
+                qt[SwzFwd8::at(s, lane)] = (float)v;
+                q2 = q1;
+                q1 = v;
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const float4 *src = reinterpret_cast<const float4 *>(qt + SwzFwd8::at(j, 32 * c + 8 * kg));
+                const float4 u0 = src[0], u1 = src[1];
+                const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+                acc = mma_split<NPROD>(split8<NPROD>(v), bx[c], acc);
+            }
+            __builtin_amdgcn_wave_barrier();
         }
-        __builtin_amdgcn_wave_barrier();
-        float *rw = red + ((blk & 1) * nw + wave) * 128;
+        if (blk >= gfirst) {
+            float *rw = red + ((blk & 1) * nw + wave) * 128;
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            if (FwdCompact<float>::valid(lane, r)) rw[FwdCompact<float>::slot(lane, r)] = acc[r];
-        __syncthreads();
+            for (int r = 0; r < 4; ++r)
+                if (FwdCompact<float>::valid(lane, r)) rw[FwdCompact<float>::slot(lane, r)] = acc[r];
+            __syncthreads();
+        }
         for (int o = threadIdx.x; o < 128; o += blockDim.x) {
             int row, col;
             FwdCompact<float>::rc(o, row, col);
             const int lp = lp0 + row;
             if (lp <= L + 1) {
-                const float *rb = red + (blk & 1) * nw * 128;
                 float sum = 0.f;
-                for (int w = 0; w < nw; ++w) sum += rb[w * 128 + o];
+                if (blk >= gfirst) {
+                    const float *rb = red + (blk & 1) * nw * 128;
+                    for (int w = 0; w < nw; ++w) sum += rb[w * 128 + o];
+                }
                 const int64_t ti = t0 + lp - m;
                 if (xeq && col < 8 && group == 0) {
                     const int kk = (lp - m) >> 1;
@@ -1711,6 +1887,7 @@ __global__ __launch_bounds__(1024) void k_leg_fwd_bf16(LegFwdArgs<float> A) {
 // p stored at slot q ^ ((p >> 2) & 3) so that 16 lanes of a row group hit
 // distinct banks).
 constexpr int kRowsA = 32;
+static_assert(kRowsA == kStartBlock, "a split-bf16 synthesis block is one start block");
 
 // The split-bf16 paths' polar tile: pairs [p0, p0 + 16 NB) of order m (the pairs
 // next to the poles) over all degrees in binary64 on the 16x16x4 binary64 MFMA,
@@ -1727,14 +1904,17 @@ __device__ __forceinline__ void adj_tile_f64_polar(const LegArgs<float> &A, int 
     const int p = p0 + lane;
     const bool valid = lane < 16 * NB && p < pend;
     const double z = valid ? A.pz[p] : 0.0;
-    double q1 = 0.0, q2 = valid ? -A.seeds[(size_t)m * NP + p] : 0.0;
+    const LaneStart S = lane_start(A.start, A.sblk, (size_t)m * NP + p, valid);
+    double q1 = 0.0, q2 = 0.0;
     const int j = lane & 15, k = lane >> 4;
     acc_t acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = acc_t{0, 0, 0, 0};
     const int nblk = (L + 2 - m + kRowsB - 1) / kRowsB;
-    for (int blk = 0; blk < nblk; ++blk) {
+    const int first = min(wave_min_blk(S.blk) * (kStartBlock / kRowsB), nblk);
+    for (int blk = first; blk < nblk; ++blk) {
         const int lp0 = m + blk * kRowsB;
+        take_start(S, lp0 - m, q1, q2);
         const int la = lp0 + (lane & 15);
         const double areg = la <= L + 1 ? A.aprime[t0 + la - m] : 0.0;
         // B operands: lane (j + 16k) holds g[row 4gg + k][j & 7] if the row's
@@ -1767,10 +1947,10 @@ __device__ __forceinline__ void adj_tile_f64_polar(const LegArgs<float> &A, int 
 }
 
 template <int NPROD>
-__device__ __forceinline__ void adj_tile_bf16(const LegArgs<float> &A, int m, int p0, int lA, int lB, double z,
-                                              double q1, double q2, f32x4 (&acc)[4], u32x4_t *th) {
-    // pairs [p0, p0 + 64) over the degrees [lA, lB) (lA an even number of degrees
-    // after m); acc as in adj_tile_f32 (register r of acc[b]: pair 16 b + 4 (l/16) + r)
+__device__ __forceinline__ void adj_tile_bf16(const LegArgs<float> &A, int m, int p0, int lB, double z,
+                                              const LaneStart &S, f32x4 (&acc)[4], u32x4_t *th) {
+    // pairs [p0, p0 + 64) over the degrees below lB, each from its start S; acc as
+    // in adj_tile_f32 (register r of acc[b]: pair 16 b + 4 (l/16) + r)
     constexpr int NS = Bf16<NPROD>::kParts;
     const int lane = threadIdx.x & 63;
     const int L = A.L;
@@ -1781,9 +1961,12 @@ __device__ __forceinline__ void adj_tile_bf16(const LegArgs<float> &A, int m, in
     f32x4 acl[4];  // leading products in acc, correction products in acl
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[b] = acl[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int lA = min(m + kStartBlock * wave_min_blk(S.blk), lB);
+    double q1 = 0.0, q2 = 0.0;
     const int nblk = (lB - lA + kRowsA - 1) / kRowsA;
     for (int blk = 0; blk < nblk; ++blk) {
         const int lp0 = lA + blk * kRowsA;
+        take_start(S, lp0 - m, q1, q2);
         // B: lane (j + 16kg) holds g[l' = lp0 + 8kg + t][j & 7] when the parity
         // of l' - m (= t & 1) matches the column half j / 8, else 0
         float bv[8];
@@ -1891,12 +2074,12 @@ __device__ __forceinline__ void leg_adj_group(const LegArgs<real> &A, int m, int
         const int p = p0 + lane;
         const bool valid = p < A.NPT;
         const double z = valid ? A.pz[p] : 0.0;
-        const double q2 = valid ? -A.seeds[(size_t)m * A.NP + p] : 0.0;
+        const LaneStart S = lane_start(A.start, A.sblk, (size_t)m * A.NP + p, valid);
         f32x4 acc[4];
         if (tile == 0)
-            adj_tile_f32(A, m, p0, m, A.L + 2, z, 0.0, q2, acc, reinterpret_cast<float *>(wl));
+            adj_tile_f32(A, m, p0, A.L + 2, z, S, acc, reinterpret_cast<float *>(wl));
         else
-            adj_tile_bf16<NPROD>(A, m, p0, m, A.L + 2, z, 0.0, q2, acc, reinterpret_cast<u32x4_t *>(wl));
+            adj_tile_bf16<NPROD>(A, m, p0, A.L + 2, z, S, acc, reinterpret_cast<u32x4_t *>(wl));
         const int j = lane & 15;
 #pragma unroll
         for (int b = 0; b < 4; ++b)
@@ -2187,8 +2370,38 @@ __global__ __launch_bounds__(64) void k_adj_scattered(ScatArgs<real> A) {
         const double *ap = A.aprime + t0 - m;
         double h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (!pole) {
-            double q1 = 0.0, q2 = -ldexp(mant, e2);
-            for (int lp = m; lp <= L + 1; ++lp) {
+            // a seed below 2^-960 runs scaled by 2^-E until its values reach 2^-960
+            // (the smaller ones add nothing at binary64's precision); the state is
+            // then scaled back, exactly
+            double q1 = 0.0, q2;
+            int E = 0, lp = m;
+            if (e2 < -960) {
+                q2 = -mant;
+                E = e2;
+            } else {
+                q2 = -ldexp(mant, e2);
+            }
+            for (; E < 0 && lp <= L + 1; ++lp) {
+                const double v = fma(ap[lp], z * q1, -q2);
+                int ev;
+                (void)frexp(v, &ev);
+                if (v != 0.0 && ev + E > -960) {
+                    q1 = ldexp(q1, E);
+                    q2 = ldexp(q2, E);
+                    E = 0;
+                    break;  // degree lp again, unscaled
+                }
+                q2 = q1;
+                q1 = v;
+                (void)frexp(q1, &ev);
+                if (q1 != 0.0 && (ev > 64 || ev < -64)) {
+                    q1 = ldexp(q1, -ev);
+                    q2 = ldexp(q2, -ev);
+                    E += ev;
+                }
+            }
+            if (E < 0) lp = L + 2;  // never significant
+            for (; lp <= L + 1; ++lp) {
                 const double v = fma(ap[lp], z * q1, -q2);
                 q2 = q1;
                 q1 = v;
@@ -2812,6 +3025,8 @@ static LegFwdArgs<real> make_leg_fwd_args(const Plan &p, int groups) {
     G.gstride = groups > 1 ? p.tri_size * 8 : 0;
     G.pairs = p.d_pairs;
     G.seeds = p.d_seeds;
+    G.start = p.d_start;
+    G.sblk = p.d_sblk;
     G.pz = p.d_pair_z;
     G.aprime = p.d_aprime;
     G.cscale = p.d_cscale;
@@ -2831,6 +3046,8 @@ static LegArgs<real> make_leg_adj_args(const Plan &p) {
 
     G.PB = static_cast<real *>(p.d_pb);
     G.seeds = p.d_seeds;
+    G.start = p.d_start;
+    G.sblk = p.d_sblk;
     G.pz = p.d_pair_z;
     G.aprime = p.d_aprime;
     G.L = p.L;
@@ -2959,6 +3176,8 @@ static hipError_t forward_impl(const Plan &p, const FwdWork &ws, const void *T, 
         G.F = static_cast<real *>(p.d_fg);
         G.pairs = nf.d_vpairs;
         G.seeds = nf.d_vseeds;
+        G.start = nf.d_vstart;
+        G.sblk = nf.d_vsblk;
         G.pz = nf.d_vz;
         G.aprime = p.d_aprime;
         G.cscale = p.d_cscale;
@@ -3041,6 +3260,8 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
         G.FG = static_cast<const real *>(p.d_fg);
         G.PB = static_cast<real *>(nf.d_vpb);
         G.seeds = nf.d_vseeds;
+        G.start = nf.d_vstart;
+        G.sblk = nf.d_vsblk;
         G.pz = nf.d_vz;
         G.aprime = p.d_aprime;
         G.L = p.L;
@@ -3604,9 +3825,25 @@ hipError_t batch_field_times(const BatchState *b, int dirs, std::vector<double> 
     return hipSuccess;
 }
 
+hipError_t launch_start_kernel(const double *pair_z, const double *pair_s, int NP, int L,
+                               const double *aprime, const double *cscale, LegStart *start,
+                               int *sblk, int *bad, hipStream_t st) {
+    hipLaunchKernelGGL(k_leg_start, dim3((NP + 63) / 64, L + 1), dim3(64), 0, st, pair_z, pair_s, NP, L,
+                       aprime, cscale, start, sblk, bad);
+    return hipGetLastError();
+}
+
 hipError_t launch_seed_kernel(const double *pair_s, int NP, int L, double *seeds, hipStream_t st) {
     hipLaunchKernelGGL(k_seeds, dim3((NP + 127) / 128), dim3(128), 0, st, pair_s, NP, L, seeds);
     return hipGetLastError();
+}
+
+// Let kernel k take dynamic LDS up to `total` bytes less its static LDS.
+static hipError_t allow_lds(const void *k, int total) {
+    hipFuncAttributes fa{};
+    hipError_t e = hipFuncGetAttributes(&fa, k);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, total - (int)fa.sharedSizeBytes);
 }
 
 hipError_t set_kernel_attributes() {
@@ -3629,36 +3866,36 @@ hipError_t set_kernel_attributes() {
                                   (const void *)k_nfft_cols_fwd<double>, (const void *)k_nfft_cols_fwd<float>,
                                   (const void *)k_nfft_rows_fwd<double>, (const void *)k_nfft_rows_fwd<float>};
     for (const void *k : nfft_kernels) {
-        e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+        e = allow_lds(k, big);
         if (e != hipSuccess) return e;
     }
     for (const void *k : batched) {
-        e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+        e = allow_lds(k, big);
         if (e != hipSuccess) return e;
     }
-    e = hipFuncSetAttribute((const void *)k_ring_fwd<double, kRingNT>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = allow_lds((const void *)k_ring_fwd<double, kRingNT>, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_ring_fwd<float, kRingNT>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = allow_lds((const void *)k_ring_fwd<float, kRingNT>, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_ring_adj<double, kRingNT>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = allow_lds((const void *)k_ring_adj<double, kRingNT>, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_ring_adj<float, kRingNT>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = allow_lds((const void *)k_ring_adj<float, kRingNT>, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_leg_fwd_mfma<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = allow_lds((const void *)k_leg_fwd_mfma<double>, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_leg_fwd_mfma<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = allow_lds((const void *)k_leg_fwd_mfma<float>, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_leg_adj<double, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = allow_lds((const void *)k_leg_adj<double, 0>, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_leg_fwd_bf16<3>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = allow_lds((const void *)k_leg_fwd_bf16<3>, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_leg_fwd_bf16<6>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = allow_lds((const void *)k_leg_fwd_bf16<6>, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_leg_adj<float, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = allow_lds((const void *)k_leg_adj<float, 3>, big);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_leg_adj<float, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = allow_lds((const void *)k_leg_adj<float, 6>, big);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)k_leg_adj<float, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    return allow_lds((const void *)k_leg_adj<float, 0>, big);
 }
 
 }  // namespace vsht

@@ -81,15 +81,15 @@ def test_plan_rejects_invalid(case):
     assert len(lib.vsht_last_error()) > 0
 
 
-def test_plan_rejects_bandlimit_beyond_seed_range():
-    """Plans above L = 1664 are refused before any device work (host check)."""
+def test_plan_rejects_bandlimit_beyond_limit():
+    """Plans above L = 4096 are refused before any device work (host check)."""
     lib = B.load_library()
     xyz, _ = vi.uniform_points(16, 5)
     xyz = np.ascontiguousarray(xyz, np.float64)
     h = ctypes.c_void_p()
-    st = lib.vsht_plan(1665, len(xyz), xyz.ctypes.data_as(ctypes.c_void_p), None, None, ctypes.byref(h))
+    st = lib.vsht_plan(4097, len(xyz), xyz.ctypes.data_as(ctypes.c_void_p), None, None, ctypes.byref(h))
     assert st == B.VSHT_EUNSUPPORTED and not h.value
-    assert "1664" in B.load_library().vsht_last_error().decode()
+    assert "4096" in B.load_library().vsht_last_error().decode()
 
 
 def test_null_arguments():

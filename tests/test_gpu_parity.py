@@ -339,21 +339,24 @@ def test_ring_path_bitwise_reproducible(torch, vsht, precision):
 
 # ---------------------------------------------------------------------------
 # The largest sizes served: the longest ring the ring kernels take (3072 points,
-# GL at L = 1535 with 2L+2 longitudes, the exact quadrature: round trip too) and
-# the largest bandlimit (L = 1664, here on 1665 GL rings of 3072 points, where
-# the forward is checked as the discrete sum it is).  Sampled against the oracle.
+# GL at L = 1535 with 2L+2 longitudes, the exact quadrature: round trip too),
+# Table 3's largest bandlimit L = 2250 and the library's limit L = 4096, both on
+# L+1 GL rings of 3072 points (the forward is checked as the discrete sum it
+# is).  Above L ~ 1700 the seeds Lambda_{m,m} of functions that reach order one
+# lie below binary64's range, so these cases run through start states computed
+# with a carried exponent.  Sampled against the oracle.
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("L,nphi", [(1535, None), (1664, 3072)])
-def test_largest_sizes_sampled(torch, vsht, orc, L, nphi):
+@pytest.mark.parametrize("L,nphi,nsample", [(1535, None, 32), (2250, 3072, 32), (4096, 3072, 16)])
+def test_largest_sizes_sampled(torch, vsht, orc, L, nphi, nsample):
     print_case("largest sizes", L, nphi)
     xyz, w = vi.gl_grid(L, n_phi=nphi)
     plan = vsht.Plan(L, xyz, w, precision="fp64")
     assert plan.kind == "rings"
     a, b = vi.random_coeffs(L, 5)
     T = run_adjoint(torch, plan, a, b)
-    pidx = vi.sample_indices(len(w), 32, 6)
+    pidx = vi.sample_indices(len(w), nsample, 6)
     e_adj = rel_l2(T[pidx], orc.adjoint(L, a, b, xyz[pidx]))
-    cidx = vi.sample_indices(L * (L + 2), 32, 7)
+    cidx = vi.sample_indices(L * (L + 2), nsample, 7)
     ga, gb = run_forward(torch, plan, T)
     sa, sb = orc.forward_subset(L, xyz, w, T, cidx)
     e_fwd = rel_l2(np.concatenate([ga[cidx], gb[cidx]]), np.concatenate([sa, sb]))
@@ -362,8 +365,35 @@ def test_largest_sizes_sampled(torch, vsht, orc, L, nphi):
         e_rt = rel_l2(np.concatenate([ga, gb]), np.concatenate([a, b]))
         msg += " roundtrip %.3e" % e_rt
         assert e_rt < FP64_TOL
-    print(msg)
+    print(msg, flush=True)
     assert e_adj < FP64_TOL and e_fwd < FP64_TOL
+    plan.close()
+
+
+# ---------------------------------------------------------------------------
+# Table 3's bandlimit on scattered points (the direct evaluation, L > 700): 48
+# points at colatitudes where the seeds of order-one functions lie below
+# binary64's range (theta = 0.3 to 0.6, where Lambda_{2250,m} ~ 1 for seeds
+# near 1e-330), plus random points and both poles.
+# ---------------------------------------------------------------------------
+def test_scattered_direct_L2250(torch, vsht, orc):
+    L = 2250
+    print_case("scattered direct", L)
+    rng = np.random.default_rng(61)
+    th = np.concatenate([np.linspace(0.3, 0.6, 16), np.pi - np.linspace(0.3, 0.6, 8),
+                         np.arccos(rng.uniform(-1, 1, 22))])
+    ph = rng.uniform(0, 2 * np.pi, len(th))
+    xyz = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], axis=1)
+    xyz /= np.linalg.norm(xyz, axis=1, keepdims=True)
+    xyz = np.concatenate([xyz, [[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]]])
+    plan = vsht.Plan(L, xyz, None, precision="fp64")
+    assert plan.kind == "scattered"
+    a, b = vi.random_coeffs(L, 62)
+    T = run_adjoint(torch, plan, a, b)
+    e = rel_l2(T, orc.adjoint(L, a, b, xyz))
+    print("scattered direct L=%d adjoint %.3e" % (L, e), flush=True)
+    assert e < FP64_TOL
+    plan.close()
 
 
 # ---------------------------------------------------------------------------
