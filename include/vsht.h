@@ -127,10 +127,12 @@ int64_t vsht_num_coeffs(int L);
  *   out     receives the plan on success.
  * Requirements: n >= 1; a plan with weights needs n >= 2 (Section 4.1, the
  * quadrature rule has N >= 2 nodes).  Returns VSHT_EINVAL on a violation,
- * VSHT_EUNSUPPORTED for L > 1664 (beyond it binary64 seeds of the Legendre
- * recurrence underflow for functions that reach significant size), VSHT_ENOMEM /
- * VSHT_EDEVICE on allocation or HIP failures.  The same limit holds for the
- * fields of a batch plan. */
+ * VSHT_EUNSUPPORTED for L > 4096, VSHT_ENOMEM / VSHT_EDEVICE on allocation or
+ * HIP failures.  The same limit holds for the fields of a batch plan.  Every
+ * (order, ring) starts its Legendre recurrence at the first 32-degree block in
+ * which the function reaches 2^-64, from a state computed with a carried
+ * exponent, so seeds Lambda_{m,m} below binary64's range (L above ~1700) are
+ * served exactly; terms below 2^-64 are dropped. */
 vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w,
                       const vsht_opts *opts, vsht_plan_t *out);
 
