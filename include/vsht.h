@@ -35,6 +35,9 @@
  * Errors    Every function returns a vsht_status and never throws; on an
  *           error the outputs are unspecified.  vsht_last_error() returns a
  *           thread-local description of the last error on the calling thread.
+ *           A buffer that does not start on a whole complex element (16
+ *           bytes for complex128, 8 for complex64) is refused with
+ *           VSHT_EINVAL before any work is enqueued.
  *
  * Point sets
  * ----------
@@ -142,8 +145,10 @@ vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w,
 vsht_status vsht_forward(vsht_plan_t plan, const void *T, void *a, void *b, void *stream);
 
 /* Forward transform with unit weights, i.e. the exact adjoint (Hermitian
- * transpose) of vsht_adjoint as a linear map C^{2K} -> C^{3n}:
- *   a_{l,m} = sum_k Y^div_{l,m}(x_k)^* T_k, b likewise.
+ * transpose) of vsht_adjoint as a linear map C^{2K} -> C^{3n}: the sum of
+ * Definition 4.1, eq. (fwdvsht2), with every w_k = 1,
+ *   a_{l,m} = sum_k Y^div_{l,m}(x_k)^* T_k, b likewise,
+ * which transposes the synthesis of Definition 4.2, eq. (SLvec).
  * Used as the backward of the adjoint in automatic differentiation.  Works on
  * plans with or without weights; VSHT_EUNSUPPORTED on a scattered plan on the
  * direct path. */
@@ -252,8 +257,9 @@ vsht_status vsht_get_stage_times(vsht_plan_t plan, double *ms, int64_t *count, i
  * vsht_batch_adjoint    a[f], b[f] -> T[f]   (eq. (SLvec))
  * vsht_batch_forward    T[f] -> a[f], b[f]   (eq. (fwdvsht2))
  * vsht_batch_roundtrip  a[f], b[f] -> T[f], then T[f] -> a2[f], b2[f], one graph.
- * vsht_batch_set_config / get_config   launch shape: adj_nw (1, 2 or 4 tiles
- *                   of 64 ring pairs per synthesis workgroup), fwd_merge (1: one
+ * vsht_batch_set_config / get_config   launch shape: adj_nw (1, 2 or 4; kept
+ *                   for the call's shape and without effect: the synthesis
+ *                   workgroups always hold four waves), fwd_merge (1: one
  *                   analysis launch at the widest workgroup; 0: one per tile
  *                   count), lpt (1: longest work items first), ring_nt (256 or
  *                   512 threads per ring workgroup; rings whose DFT is longer

@@ -160,6 +160,30 @@ def test_reduced_ring_grid(torch, vsht, orc, L, precision, tol):
     assert e_adj < tol and e_fwd < tol
 
 
+# HEALPix layout (equal-area rings of 4i points in the caps and 4 N_side in the
+# belt, alternate belt rings shifted by half a step; the layout Section 6 names
+# for future work): the ring path against the oracle's direct sums.  The
+# forward is the weighted sum of eq. (fwdvsht2) with HEALPix's equal weights.
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_healpix_rings(torch, vsht, orc, precision, tol):
+    nside, L = 16, 32
+    print_case("healpix", nside, L, precision)
+    xyz, w = vi.healpix_grid(nside)
+    assert len(w) == 12 * nside * nside
+    plan = vsht.Plan(L, xyz, w, precision=precision)
+    assert plan.kind == "rings"
+    a, b = vi.random_coeffs(L, 13)
+    T = run_adjoint(torch, plan, a, b)
+    e_adj = rel_l2(T, orc.adjoint(L, a, b, xyz))
+    Tr = vi.random_field(len(w), 14)
+    ga, gb = run_forward(torch, plan, Tr)
+    a_ref, b_ref = orc.forward(L, xyz, w, Tr)
+    e_fwd = rel_l2(np.concatenate([ga, gb]), np.concatenate([a_ref, b_ref]))
+    print("healpix nside=%d L=%d %s adjoint %.3e forward %.3e" % (nside, L, precision, e_adj, e_fwd))
+    assert e_adj < tol and e_fwd < tol
+    plan.close()
+
+
 def test_scattered_adjoint_fp64(torch, vsht, orc):
     L = 24
     xyz, _ = vi.uniform_points(700, 2)
@@ -550,3 +574,32 @@ def test_scattered_direct_forward_unsupported(torch, vsht):
     with pytest.raises(B.VshtError) as ei:
         run_forward(torch, plan, vi.random_field(len(w), 52))
     assert ei.value.status == B.VSHT_EUNSUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# Buffers that do not start on a whole complex element are refused before any
+# launch (single plans and the *_many calls).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_misaligned_buffers_rejected(torch, vsht, precision):
+    print_case("misaligned buffers", precision)
+    from paper_1908_00041_amd import _binding as B
+    L = 8
+    xyz, w = vi.gl_grid(L)
+    plan = vsht.Plan(L, xyz, w, precision=precision)
+    K = vi.num_coeffs(L)
+    cdt = plan.dtype
+    T = torch.zeros((len(w) + 1, 3), dtype=cdt, device="cuda")
+    a = torch.zeros(K + 1, dtype=cdt, device="cuda")
+    b = torch.zeros(K + 1, dtype=cdt, device="cuda")
+    half = T.element_size() // 2  # half a complex element
+    bad = T.data_ptr() + half
+    assert B.vsht_forward(plan._h, bad, a.data_ptr(), b.data_ptr(), None) == B.VSHT_EINVAL
+    assert "aligned" in B.load_library().vsht_last_error().decode()
+    assert B.vsht_adjoint(plan._h, a.data_ptr(), b.data_ptr() + half, T.data_ptr(), None) == B.VSHT_EINVAL
+    assert B.vsht_forward_many(plan._h, 1, T.data_ptr(), a.data_ptr() + half, b.data_ptr(), 0,
+                               None) == B.VSHT_EINVAL
+    # aligned buffers still work
+    assert B.vsht_forward(plan._h, T.data_ptr(), a.data_ptr(), b.data_ptr(), None) == B.VSHT_OK
+    torch.cuda.synchronize()
+    plan.close()

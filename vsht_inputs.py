@@ -113,6 +113,37 @@ def reduced_gl_grid(L, min_phi=4):
     return np.concatenate(pts), np.concatenate(wts)
 
 
+def healpix_grid(nside):
+    """HEALPix layout (the equal-area iso-latitude rings of Gorski et al.) with
+    N_side = nside: 4 nside - 1 rings.  Polar-cap ring i < nside has z = 1 - i^2 /
+    (3 nside^2) and 4 i points at phi = (pi / (2 i)) (j + 1/2); belt ring
+    nside <= i <= 2 nside has z = 4/3 - 2 i / (3 nside) and 4 nside points at
+    phi = (pi / (2 nside)) (j + (1 - (i - nside + 1) % 2) / 2).  Southern rings
+    mirror the northern ones (z negated bitwise, same longitudes).  Equal
+    weights 4 pi / (12 nside^2).  Returns (xyz (N,3), w (N,)) as float64,
+    rings from north to south."""
+    N = nside
+    north = []
+    for i in range(1, 2 * N + 1):
+        if i < N:
+            z = 1.0 - i * i / (3.0 * N * N)
+            n = 4 * i
+            phi = (np.pi / (2 * i)) * (np.arange(n) + 0.5)
+        else:
+            z = 4.0 / 3.0 - 2.0 * i / (3.0 * N)
+            n = 4 * N
+            shift = 0.5 * (1 - (i - N + 1) % 2)
+            phi = (np.pi / (2 * N)) * (np.arange(n) + shift)
+        north.append((z, phi))
+    rings = north + [(-z, phi) for z, phi in reversed(north[:-1])]  # ring 2N is the equator
+    pts = []
+    for z, phi in rings:
+        s = np.sqrt((1.0 - z) * (1.0 + z))
+        pts.append(np.stack([s * np.cos(phi), s * np.sin(phi), np.full(len(phi), z)], axis=-1))
+    xyz = np.concatenate(pts)
+    return xyz, np.full(len(xyz), 4.0 * np.pi / (12 * N * N))
+
+
 def uniform_points(M, seed):
     """M points uniform on S^2 and equal weights 4 pi / M."""
     rng = np.random.default_rng(seed)
