@@ -68,7 +68,7 @@ void free_plan_memory(Plan *p) {
     const NfftPlan &nf = p->nfft;
     void *ptrs[] = {p->d_rings, p->d_pairs, p->d_ffts, p->d_tw,  p->d_pair_z, p->d_aprime,
                     p->d_cscale, p->d_etab, p->d_rsq,  p->d_seeds, p->d_start, p->d_sblk, p->d_weights, p->d_xyz,
-                    p->d_pb, p->d_fg, p->d_fg64, p->d_fpart, p->d_state, nf.d_ffts, nf.d_tw, nf.d_vpairs, nf.d_vz,
+                    p->d_pb, p->d_fg, p->d_fg64, p->d_fpart, p->d_many, p->d_state, nf.d_ffts, nf.d_tw, nf.d_vpairs, nf.d_vz,
                     nf.d_vs, nf.d_vseeds, nf.d_vstart, nf.d_vsblk, nf.d_psihat, nf.d_pts, nf.d_vpb, nf.d_g1, nf.d_g};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -852,6 +852,29 @@ vsht_status vsht_sht_adjoint(vsht_plan_t plan, const void *flm, void *f, void *s
 }
 
 
+// Fields per launch of the *_many calls on a ring plan: up to 64, and no more than
+// fit 4 GiB of workspace (at least one).
+static int many_chunk(const Plan &P, int64_t count) {
+    const size_t per = field_ws(P).total();
+    const int64_t fit = std::max<int64_t>(1, (int64_t)(((size_t)4 << 30) / std::max<size_t>(per, 1)));
+    return (int)std::min<int64_t>({count, (int64_t)64, fit});
+}
+
+// The many-field workspace for nf fields (grown on demand; waits for the device
+// before replacing a smaller one, which earlier calls may still use).
+static hipError_t ensure_many(Plan &P, int nf) {
+    const size_t need = field_ws(P).total() * (size_t)nf;
+    if (P.d_many && P.many_bytes >= need) return hipSuccess;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    if (P.d_many) (void)hipFree(P.d_many);
+    P.d_many = nullptr;
+    P.many_bytes = 0;
+    if ((e = hipMalloc(&P.d_many, need)) != hipSuccess) return e;
+    P.many_bytes = need;
+    return hipSuccess;
+}
+
 vsht_status vsht_forward_many(vsht_plan_t plan, int64_t count, const void *T, void *a, void *b,
                               int flags, void *stream) {
     vsht_status s = check_call(plan, T, a, b);
@@ -866,10 +889,18 @@ vsht_status vsht_forward_many(vsht_plan_t plan, int64_t count, const void *T, vo
     DeviceGuard guard(P.device);
     const size_t cb = complex_bytes(P);
     const size_t t_stride = (size_t)P.n * 3 * cb, c_stride = (size_t)vsht_num_coeffs(P.L) * cb;
-    for (int64_t f = 0; f < count; ++f) {
-        hipError_t e = launch_forward(P, static_cast<const char *>(T) + f * t_stride,
-                                      static_cast<char *>(a) + f * c_stride,
-                                      static_cast<char *>(b) + f * c_stride, weighted, (hipStream_t)stream);
+    const int chunk = P.kind == VSHT_PLAN_RINGS ? many_chunk(P, count) : 1;
+    for (int64_t f = 0; f < count; f += chunk) {
+        const int nf = (int)std::min<int64_t>(chunk, count - f);
+        const char *Tf = static_cast<const char *>(T) + f * t_stride;
+        char *af = static_cast<char *>(a) + f * c_stride, *bf = static_cast<char *>(b) + f * c_stride;
+        hipError_t e;
+        if (nf > 1) {
+            if ((e = ensure_many(plan->p, nf)) != hipSuccess) return hip_fail(e, "many-field workspace");
+            e = launch_forward_many(P, nf, P.d_many, Tf, af, bf, weighted, (hipStream_t)stream);
+        } else {
+            e = launch_forward(P, Tf, af, bf, weighted, (hipStream_t)stream);
+        }
         if (e != hipSuccess) return hip_fail(e, "forward launch");
     }
     return VSHT_OK;
@@ -887,10 +918,18 @@ vsht_status vsht_adjoint_many(vsht_plan_t plan, int64_t count, const void *a, co
     DeviceGuard guard(P.device);
     const size_t cb = complex_bytes(P);
     const size_t t_stride = (size_t)P.n * 3 * cb, c_stride = (size_t)vsht_num_coeffs(P.L) * cb;
-    for (int64_t f = 0; f < count; ++f) {
-        hipError_t e = launch_adjoint(P, static_cast<const char *>(a) + f * c_stride,
-                                      static_cast<const char *>(b) + f * c_stride,
-                                      static_cast<char *>(T) + f * t_stride, weighted, (hipStream_t)stream);
+    const int chunk = P.kind == VSHT_PLAN_RINGS ? many_chunk(P, count) : 1;
+    for (int64_t f = 0; f < count; f += chunk) {
+        const int nf = (int)std::min<int64_t>(chunk, count - f);
+        const char *af = static_cast<const char *>(a) + f * c_stride, *bf = static_cast<const char *>(b) + f * c_stride;
+        char *Tf = static_cast<char *>(T) + f * t_stride;
+        hipError_t e;
+        if (nf > 1) {
+            if ((e = ensure_many(plan->p, nf)) != hipSuccess) return hip_fail(e, "many-field workspace");
+            e = launch_adjoint_many(P, nf, P.d_many, af, bf, Tf, weighted, (hipStream_t)stream);
+        } else {
+            e = launch_adjoint(P, af, bf, Tf, weighted, (hipStream_t)stream);
+        }
         if (e != hipSuccess) return hip_fail(e, "adjoint launch");
     }
     return VSHT_OK;

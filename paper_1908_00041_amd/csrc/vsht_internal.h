@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "vsht.h"
@@ -194,6 +195,8 @@ struct Plan {
     void *d_fg64 = nullptr;        // binary32 paths: the adjoint's g in binary64, [tri][8] double
     void *d_fpart = nullptr;       // analysis split over g > 1 workgroups per order: [g][tri][8]
 
+    void *d_many = nullptr;        // workspace of the *_many calls: several fields at once,
+    size_t many_bytes = 0;         // allocated on first use, grown as needed
     void *d_state = nullptr;       // Legendre recurrence state
     size_t workspace_bytes = 0;
     int n_ffts = 0;
@@ -239,6 +242,26 @@ __host__ __device__ inline int64_t tri_offset(int L, int m) {
 }
 __host__ __device__ inline int64_t tri_size(int L) { return tri_offset(L, L + 1); }
 
+// Workspace of one field of a ring plan, bytes (each rounded up to 256): the
+// ring/pair buffer, the triangle FG, FG64 (binary32 plans) and the partial
+// triangles of a split analysis (more than 1024 ring pairs).
+struct ManyWs {
+    size_t pb, fg, fg64, fpart;
+    size_t total() const { return pb + fg + fg64 + fpart; }
+};
+inline size_t round256(size_t x) { return (x + 255) / 256 * 256; }
+inline ManyWs field_ws(const Plan &P) {
+    const size_t rsz = P.precision == VSHT_FP64 ? 8 : 4;
+    const size_t per_m = std::max((size_t)P.n_rings * 4, (size_t)P.n_pairs * 8);
+    ManyWs z{};
+    z.pb = round256((size_t)(P.L + 1) * per_m * 2 * rsz);
+    z.fg = round256((size_t)(P.tri_size + kFgPadRows) * 4 * 2 * rsz);
+    z.fg64 = rsz == 4 ? round256((size_t)(P.tri_size + kFgPadRows) * 4 * 2 * 8) : 0;
+    const int groups = analysis_groups(P.n_pairs, P.eq_ring);
+    z.fpart = groups > 1 ? round256((size_t)groups * P.tri_size * 8 * rsz) : 0;
+    return z;
+}
+
 // Kernel launchers (vsht_kernels.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_forward(const Plan &p, const void *T, void *a, void *b, bool weighted,
                           hipStream_t st);
@@ -252,6 +275,13 @@ constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
 size_t static_forward_bytes(const Plan &p);
 hipError_t launch_forward_static(const Plan &p, const void *T, void *a, void *b, hipStream_t st);
 hipError_t launch_sht_adjoint(const Plan &p, const void *flm, void *f, hipStream_t st);
+// count fields of a ring plan in one launch per stage (fields along the grid's z
+// dimension), with count field workspaces (field_ws) at ws; T, a and b hold count
+// contiguous fields.
+hipError_t launch_forward_many(const Plan &p, int count, void *ws, const void *T, void *a, void *b,
+                               bool weighted, hipStream_t st);
+hipError_t launch_adjoint_many(const Plan &p, int count, void *ws, const void *a, const void *b, void *T,
+                               bool weighted, hipStream_t st);
 hipError_t launch_seed_kernel(const double *pair_s, int NP, int L, double *seeds, hipStream_t st);
 // Start blocks and states of every (m, p), p < NP; *bad (device) is set to 1 if a
 // state falls outside binary64's normal range (never expected: it is at least

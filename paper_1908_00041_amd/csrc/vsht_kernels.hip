@@ -71,6 +71,21 @@ __device__ __forceinline__ T ld_uniform(const T *p) {
     return __builtin_bit_cast(T, w);
 }
 
+// The argument block of field f of a launch over fields (blockIdx.z), kept in
+// scalar registers: the offsets depend only on the workgroup, and without the
+// per-dword readfirstlane the compiler may keep the copy in private memory.
+template <typename T>
+__device__ __forceinline__ T field_args(const T &A, int f) {
+    static_assert(sizeof(T) % 4 == 0, "dword-sized structure");
+    struct Words {
+        uint32_t d[sizeof(T) / 4];
+    };
+    Words w = __builtin_bit_cast(Words, A.at_field(f));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w.d[i] = __builtin_amdgcn_readfirstlane(w.d[i]);
+    return __builtin_bit_cast(T, w);
+}
+
 // Value of a binary64 register in lane `lane` (wave-uniform result).
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
     const long long b = __double_as_longlong(v);
@@ -786,6 +801,18 @@ struct RingArgs {
     int NR;
     int weighted;
     int scalar;  // scalar transforms: one complex value f per point, T_theta = s f, T_phi = 0
+    // launches over several fields (blockIdx.z = field): per-field strides of the
+    // caller's field and of the ring/pair buffer, in complex elements (0 otherwise)
+    int64_t zs_T, zs_buf;
+    __device__ RingArgs at_field(int f) const {
+        RingArgs r = *this;
+        if (f) {
+            if (Tin) r.Tin = Tin + f * zs_T;
+            if (Tout) r.Tout = Tout + f * zs_T;
+            r.buf = buf + f * zs_buf;
+        }
+        return r;
+    }
 };
 
 // Workgroup -> ring of the single-field adjoint ring stage.  Workgroups are
@@ -925,7 +952,7 @@ __device__ __forceinline__ void ring_adj_body(const RingArgs<real> &A, int r, un
 template <typename real, int NT>
 __global__ __launch_bounds__(NT, 2) void k_ring_fwd(RingArgs<real> A) {
     extern __shared__ unsigned char smem_raw[];
-    ring_fwd_body<real, NT>(A, blockIdx.x, smem_raw);
+    ring_fwd_body<real, NT>(field_args(A, blockIdx.z), blockIdx.x, smem_raw);
 }
 
 template <typename real, int NT>
@@ -933,7 +960,7 @@ __global__ __launch_bounds__(NT, 2) void k_ring_adj(RingArgs<real> A) {
     extern __shared__ unsigned char smem_raw[];
     const int r = ring_of_block(A, blockIdx.x);
     if (r < 0) return;
-    ring_adj_body<real, NT>(A, r, smem_raw);
+    ring_adj_body<real, NT>(field_args(A, blockIdx.z), r, smem_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -1040,6 +1067,15 @@ struct LegFwdArgs {
     int eq_ring;           // ring at z = 0 handled in closed form, or -1
     int64_t gstride;       // several workgroups per order m: group g writes its partial
                            // triangle at F + g gstride (summed afterwards); 0 otherwise
+    int64_t zs_RB, zs_F;   // per-field strides (reals) of a launch over fields (blockIdx.z)
+    __device__ LegFwdArgs at_field(int f) const {
+        LegFwdArgs r = *this;
+        if (f) {
+            r.RB = RB + f * zs_RB;
+            r.F = F + f * zs_F;
+        }
+        return r;
+    }
 };
 
 // Valid half of a 16x16 analysis block in compact form: 128 values per wave.
@@ -1339,9 +1375,11 @@ __device__ __forceinline__ void leg_fwd_body(const LegFwdArgs<real> &A, int m, i
 // workgroups per order; deterministic, no atomics)
 template <typename real>
 __global__ __launch_bounds__(256) void k_sum_groups(const real *__restrict__ part, real *__restrict__ F,
-                                                    int64_t n, int groups) {
+                                                    int64_t n, int groups, int64_t zs_part, int64_t zs_F) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    part += blockIdx.z * zs_part;  // field of a launch over fields
+    F += blockIdx.z * zs_F;
     real acc = part[i];
     for (int g = 1; g < groups; ++g) acc += part[(int64_t)g * n + i];
     F[i] = acc;
@@ -1351,9 +1389,9 @@ template <typename real>
 __global__ __launch_bounds__(1024) void k_leg_fwd_mfma(LegFwdArgs<real> A) {
     extern __shared__ unsigned char smem_raw[];
     if constexpr (sizeof(real) == 8)
-        leg_fwd_f64q_body(A, blockIdx.x, blockIdx.y, smem_raw);
+        leg_fwd_f64q_body(field_args(A, blockIdx.z), blockIdx.x, blockIdx.y, smem_raw);
     else
-        leg_fwd_body(A, blockIdx.x, blockIdx.y, smem_raw);
+        leg_fwd_body(field_args(A, blockIdx.z), blockIdx.x, blockIdx.y, smem_raw);
 }
 
 template <typename real>
@@ -1370,7 +1408,16 @@ struct LegArgs {
     int L;
     int NP;
     int NPT;              // pairs handled by the tiles (the equator, if any, is pair NPT)
-
+    int64_t zs_FG, zs_FG64, zs_PB;  // per-field strides (elements) of a launch over fields
+    __device__ LegArgs at_field(int f) const {
+        LegArgs r = *this;
+        if (f) {
+            r.FG = FG + f * zs_FG;
+            r.FG64 = FG64 + f * zs_FG64;
+            r.PB = PB + f * zs_PB;
+        }
+        return r;
+    }
 };
 
 // Ring pairs of the split-bf16 syntheses that run in binary64 (the polar unit).
@@ -1671,7 +1718,7 @@ __device__ __forceinline__ void equator_adj_body(const LegArgs<real> &A, int m) 
 
 template <typename real>
 __global__ __launch_bounds__(256) void k_equator_adj(LegArgs<real> A) {
-    equator_adj_body(A, blockIdx.x);
+    equator_adj_body(field_args(A, blockIdx.z), blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1877,7 +1924,7 @@ __device__ __forceinline__ void leg_fwd_bf16_body(const LegFwdArgs<float> &A, in
 template <int NP>
 __global__ __launch_bounds__(1024) void k_leg_fwd_bf16(LegFwdArgs<float> A) {
     extern __shared__ unsigned char smem_raw[];
-    leg_fwd_bf16_body<NP>(A, blockIdx.x, blockIdx.y, smem_raw);
+    leg_fwd_bf16_body<NP>(field_args(A, blockIdx.z), blockIdx.x, blockIdx.y, smem_raw);
 }
 
 // Synthesis, BF16x3/BF16x6: one wave per 64 ring pairs, degrees in
@@ -2097,7 +2144,7 @@ __global__ __launch_bounds__(256, NPROD == 0 ? 4 : 1) void k_leg_adj(LegArgs<rea
     const int y = blockIdx.y, base = y & ~255, r = y & 255;
     const int cnt = min(256, A.L + 1 - base);
     const int m = (y >> 8) & 1 ? base + cnt - 1 - r : y;
-    leg_adj_group<real, NPROD>(A, m, blockIdx.x, smem_raw);
+    leg_adj_group<real, NPROD>(field_args(A, blockIdx.z), m, blockIdx.x, smem_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -2121,6 +2168,22 @@ struct CoefArgs {
     int L;
     int fg32;               // binary32 paths: also write g in binary32 to FGout (the split-bf16
                             // tiles and the direct scattered evaluation read it)
+    // per-field strides of a launch over fields (blockIdx.z): triangle (complex
+    // elements, FG and FGout), coefficients (complex elements), FG64 (doubles)
+    int64_t zs_FG, zs_coef, zs_FG64;
+    __device__ CoefArgs at_field(int f) const {
+        CoefArgs r = *this;
+        if (f) {
+            r.FG = FG + f * zs_FG;
+            r.FGout = FGout + f * zs_FG;
+            if (ain) r.ain = ain + f * zs_coef;
+            if (bin) r.bin = bin + f * zs_coef;
+            if (aout) r.aout = aout + f * zs_coef;
+            if (bout) r.bout = bout + f * zs_coef;
+            if (FG64) r.FG64 = FG64 + f * zs_FG64;
+        }
+        return r;
+    }
 };
 
 // Both coefficient kernels work on tiles of kTM orders x kTL degrees staged in
@@ -2213,7 +2276,7 @@ __device__ __forceinline__ void recombine_body(const CoefArgs<real> &A, int bx, 
 // ---------------------------------------------------------------------------
 template <typename real>
 __global__ __launch_bounds__(256) void k_recombine(CoefArgs<real> A) {
-    recombine_body(A, blockIdx.x, blockIdx.y);
+    recombine_body(field_args(A, blockIdx.z), blockIdx.x, blockIdx.y);
 }
 
 template <typename real>
@@ -2314,7 +2377,7 @@ __device__ __forceinline__ void prep_body(const CoefArgs<real> &A, int bx, int b
 
 template <typename real>
 __global__ __launch_bounds__(256) void k_prep(CoefArgs<real> A) {
-    prep_body(A, blockIdx.x, blockIdx.y);
+    prep_body(field_args(A, blockIdx.z), blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -3146,9 +3209,21 @@ static NfftArgs<real> make_nfft_args(const Plan &p, const void *Tin, void *Tout,
 
 // Intermediate buffers of a forward transform: the plan's workspace, or the
 // static scratch array (allocation-free entry point, no stage timing).
+// Buffers of one launch sequence.  count fields run together (blockIdx.z); field f
+// uses the workspace at f times the per-field strides (bytes) and the caller's
+// field and coefficients at f times their strides (complex elements).
 struct FwdWork {
     void *rb, *fg, *fpart;
     bool timed;
+    int count = 1;
+    int64_t zb_rb = 0, zb_fg = 0, zb_fpart = 0;
+    int64_t zs_T = 0, zs_coef = 0;
+};
+struct AdjWork {
+    void *pb, *fg, *fg64;
+    int count = 1;
+    int64_t zb_pb = 0, zb_fg = 0, zb_fg64 = 0;
+    int64_t zs_T = 0, zs_coef = 0;
 };
 
 template <typename real>
@@ -3202,15 +3277,18 @@ static hipError_t forward_impl(const Plan &p, const FwdWork &ws, const void *T, 
         }
         return hipGetLastError();
     }
+    const unsigned nf = (unsigned)ws.count;
     RingArgs<real> R = make_ring_args<real>(p, T, nullptr, weighted);
     R.buf = static_cast<C2<real> *>(ws.rb);
+    R.zs_T = ws.zs_T;
+    R.zs_buf = ws.zb_rb / (int64_t)sizeof(C2<real>);
     {
         StageScope sc(p, VSHT_STAGE_RING_FWD, st, ws.timed);
         if (p.ring_nt_min == kRingNTSmall && p.max_fft_len <= kMaxLenSmallRing)
-            hipLaunchKernelGGL((k_ring_fwd<real, kRingNTSmall>), dim3((unsigned)p.n_rings), dim3(kRingNTSmall),
-                               ring_lds_bytes(p, sizeof(real)), st, R);
+            hipLaunchKernelGGL((k_ring_fwd<real, kRingNTSmall>), dim3((unsigned)p.n_rings, 1, nf),
+                               dim3(kRingNTSmall), ring_lds_bytes(p, sizeof(real)), st, R);
         else
-            hipLaunchKernelGGL((k_ring_fwd<real, kRingNT>), dim3((unsigned)p.n_rings), dim3(kRingNT),
+            hipLaunchKernelGGL((k_ring_fwd<real, kRingNT>), dim3((unsigned)p.n_rings, 1, nf), dim3(kRingNT),
                                ring_lds_bytes(p, sizeof(real)), st, R);
     }
     hipError_t e = hipGetLastError();
@@ -3222,33 +3300,45 @@ static hipError_t forward_impl(const Plan &p, const FwdWork &ws, const void *T, 
         LegFwdArgs<real> G = make_leg_fwd_args<real>(p, ngroup);
         G.RB = static_cast<const real *>(ws.rb);
         G.F = static_cast<real *>(ngroup > 1 ? ws.fpart : ws.fg);
+        G.zs_RB = ws.zb_rb / (int64_t)sizeof(real);
+        G.zs_F = (ngroup > 1 ? ws.zb_fpart : ws.zb_fg) / (int64_t)sizeof(real);
         StageScope sc(p, VSHT_STAGE_LEG_FWD, st, ws.timed);
-        launch_leg_fwd<real>(G, dim3(p.L + 1, ngroup), nw, nprod, st);
+        launch_leg_fwd<real>(G, dim3(p.L + 1, ngroup, nf), nw, nprod, st);
         if (ngroup > 1)
-            hipLaunchKernelGGL(k_sum_groups<real>, dim3((unsigned)((p.tri_size * 8 + 255) / 256)), dim3(256), 0,
-                               st, static_cast<const real *>(ws.fpart), static_cast<real *>(ws.fg),
-                               p.tri_size * 8, ngroup);
+            hipLaunchKernelGGL(k_sum_groups<real>, dim3((unsigned)((p.tri_size * 8 + 255) / 256), 1, nf), dim3(256),
+                               0, st, static_cast<const real *>(ws.fpart), static_cast<real *>(ws.fg),
+                               p.tri_size * 8, ngroup, ws.zb_fpart / (int64_t)sizeof(real),
+                               ws.zb_fg / (int64_t)sizeof(real));
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     CoefArgs<real> C = make_coef_args<real>(p, nullptr, nullptr, a, b);
     C.FG = static_cast<const C2<real> *>(ws.fg);
+    C.zs_FG = ws.zb_fg / (int64_t)sizeof(C2<real>);
+    C.zs_coef = ws.zs_coef;
     {
         StageScope sc(p, VSHT_STAGE_RECOMBINE, st, ws.timed);
-        hipLaunchKernelGGL(k_recombine<real>, dim3((p.L + kTL - 1) / kTL, (p.L + 1 + kTM - 1) / kTM),
+        hipLaunchKernelGGL(k_recombine<real>, dim3((p.L + kTL - 1) / kTL, (p.L + 1 + kTM - 1) / kTM, nf),
                            dim3(256), 0, st, C);
     }
     return hipGetLastError();
 }
 
 template <typename real>
-static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void *T, bool weighted,
-                               hipStream_t st) {
+static hipError_t adjoint_impl(const Plan &p, const AdjWork &ws, const void *a, const void *b, void *T,
+                               bool weighted, hipStream_t st) {
     const int nprod = bf16_products(p.precision);
-    const CoefArgs<real> C = make_coef_args<real>(p, a, b, nullptr, nullptr);
+    const unsigned nf = (unsigned)ws.count;
+    CoefArgs<real> C = make_coef_args<real>(p, a, b, nullptr, nullptr);
+    C.FG = static_cast<const C2<real> *>(ws.fg);
+    C.FGout = static_cast<C2<real> *>(ws.fg);
+    C.FG64 = static_cast<double *>(ws.fg64);
+    C.zs_FG = ws.zb_fg / (int64_t)sizeof(C2<real>);
+    C.zs_coef = ws.zs_coef;
+    C.zs_FG64 = ws.zb_fg64 / (int64_t)sizeof(double);
     {
         StageScope sc(p, VSHT_STAGE_PREP, st);
-        hipLaunchKernelGGL(k_prep<real>, dim3((p.L + 2 + kTL - 1) / kTL, (p.L + 1 + kTM - 1) / kTM),
+        hipLaunchKernelGGL(k_prep<real>, dim3((p.L + 2 + kTL - 1) / kTL, (p.L + 1 + kTM - 1) / kTM, nf),
                            dim3(256), 0, st, C);
     }
     hipError_t e = hipGetLastError();
@@ -3302,19 +3392,30 @@ static hipError_t adjoint_impl(const Plan &p, const void *a, const void *b, void
     }
 
     LegArgs<real> G = make_leg_adj_args<real>(p);
+    G.FG = static_cast<const real *>(ws.fg);
+    G.FG64 = p.precision == VSHT_FP64 ? static_cast<const double *>(ws.fg) : static_cast<const double *>(ws.fg64);
+    G.PB = static_cast<real *>(ws.pb);
+    G.zs_FG = ws.zb_fg / (int64_t)sizeof(real);
+    G.zs_FG64 = (p.precision == VSHT_FP64 ? ws.zb_fg : ws.zb_fg64) / (int64_t)sizeof(double);
+    G.zs_PB = ws.zb_pb / (int64_t)sizeof(real);
     {
         StageScope sc(p, VSHT_STAGE_LEG_ADJ, st);
-        launch_leg_adj<real>(G, adj_grid(G, nprod), nprod, st);
+        dim3 grid = adj_grid(G, nprod);
+        grid.z = nf;
+        launch_leg_adj<real>(G, grid, nprod, st);
         if (p.eq_ring >= 0 && nprod != 0)  // the vector-unit synthesis forms the equator itself
-            hipLaunchKernelGGL(k_equator_adj<real>, dim3(p.L + 1), dim3(256), 0, st, G);
+            hipLaunchKernelGGL(k_equator_adj<real>, dim3(p.L + 1, 1, nf), dim3(256), 0, st, G);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
 
-    const RingArgs<real> R = make_ring_args<real>(p, nullptr, T, weighted);
+    RingArgs<real> R = make_ring_args<real>(p, nullptr, T, weighted);
+    R.buf = static_cast<C2<real> *>(ws.pb);
+    R.zs_T = ws.zs_T;
+    R.zs_buf = ws.zb_pb / (int64_t)sizeof(C2<real>);
     {
         StageScope sc(p, VSHT_STAGE_RING_ADJ, st);
-        const dim3 grid((unsigned)(16 * ((p.n_pairs + 7) / 8)));  // ring_of_block's layout
+        const dim3 grid((unsigned)(16 * ((p.n_pairs + 7) / 8)), 1, nf);  // ring_of_block's layout
         if (p.ring_nt_min == kRingNTSmall && p.max_fft_len <= kMaxLenSmallRing)
             hipLaunchKernelGGL((k_ring_adj<real, kRingNTSmall>), grid, dim3(kRingNTSmall),
                                ring_lds_bytes(p, sizeof(real)), st, R);
@@ -3334,8 +3435,54 @@ hipError_t launch_forward(const Plan &p, const void *T, void *a, void *b, bool w
 
 hipError_t launch_adjoint(const Plan &p, const void *a, const void *b, void *T, bool weighted,
                           hipStream_t st) {
-    if (p.precision == VSHT_FP64) return adjoint_impl<double>(p, a, b, T, weighted, st);
-    return adjoint_impl<float>(p, a, b, T, weighted, st);
+    const AdjWork ws{p.d_pb, p.d_fg, p.d_fg64};
+    if (p.precision == VSHT_FP64) return adjoint_impl<double>(p, ws, a, b, T, weighted, st);
+    return adjoint_impl<float>(p, ws, a, b, T, weighted, st);
+}
+
+// count fields of a ring plan in one launch per stage, with the per-field workspace
+// (field_ws_bytes(p) each) at ws, laid out as [count][pb], [count][fg], [count][fg64],
+// [count][fpart].
+static void many_layout(const Plan &p, int count, void *ws, FwdWork *fw, AdjWork *aw) {
+    const ManyWs z = field_ws(p);
+    char *base = static_cast<char *>(ws);
+    char *pb = base, *fg = pb + (size_t)count * z.pb, *fg64 = fg + (size_t)count * z.fg;
+    char *fpart = fg64 + (size_t)count * z.fg64;
+    const int64_t zs_T = p.n * 3, zs_coef = (int64_t)p.L * (p.L + 2);
+    if (fw) {
+        *fw = FwdWork{pb, fg, z.fpart ? fpart : nullptr, true};
+        fw->count = count;
+        fw->zb_rb = (int64_t)z.pb;
+        fw->zb_fg = (int64_t)z.fg;
+        fw->zb_fpart = (int64_t)z.fpart;
+        fw->zs_T = zs_T;
+        fw->zs_coef = zs_coef;
+    }
+    if (aw) {
+        *aw = AdjWork{pb, fg, z.fg64 ? fg64 : nullptr};
+        aw->count = count;
+        aw->zb_pb = (int64_t)z.pb;
+        aw->zb_fg = (int64_t)z.fg;
+        aw->zb_fg64 = (int64_t)z.fg64;
+        aw->zs_T = zs_T;
+        aw->zs_coef = zs_coef;
+    }
+}
+
+hipError_t launch_forward_many(const Plan &p, int count, void *ws, const void *T, void *a, void *b,
+                               bool weighted, hipStream_t st) {
+    FwdWork w{};
+    many_layout(p, count, ws, &w, nullptr);
+    if (p.precision == VSHT_FP64) return forward_impl<double>(p, w, T, a, b, weighted, st);
+    return forward_impl<float>(p, w, T, a, b, weighted, st);
+}
+
+hipError_t launch_adjoint_many(const Plan &p, int count, void *ws, const void *a, const void *b, void *T,
+                               bool weighted, hipStream_t st) {
+    AdjWork w{};
+    many_layout(p, count, ws, nullptr, &w);
+    if (p.precision == VSHT_FP64) return adjoint_impl<double>(p, w, a, b, T, weighted, st);
+    return adjoint_impl<float>(p, w, a, b, T, weighted, st);
 }
 
 // Scalar transforms on ring plans: the ring and Legendre stages of the vector
@@ -3366,7 +3513,7 @@ static hipError_t sht_forward_impl(const Plan &p, const void *f, void *flm, hipS
         if (ngroup > 1)
             hipLaunchKernelGGL(k_sum_groups<real>, dim3((unsigned)((p.tri_size * 8 + 255) / 256)), dim3(256), 0,
                                st, static_cast<const real *>(p.d_fpart), static_cast<real *>(p.d_fg),
-                               p.tri_size * 8, ngroup);
+                               p.tri_size * 8, ngroup, (int64_t)0, (int64_t)0);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -3458,7 +3605,6 @@ hipError_t scratch_address(int dev, void **out) {
     return hipSuccess;
 }
 
-size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
 size_t static_forward_bytes(const Plan &p) {

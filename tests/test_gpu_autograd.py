@@ -201,3 +201,34 @@ def test_scattered_weighted_adjoint(torch, vsht, orc):
     T = plan.adjoint_many(dev(torch, a, torch.complex128), dev(torch, b, torch.complex128),
                           times_weights=True)
     assert rel_l2(T.cpu().numpy(), w[:, None] * orc.adjoint(L, a, b, xyz)) <= FP64_TOL
+
+
+@pytest.mark.parametrize("grid", ["gl40", "rings2101"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "bf16x6"])
+def test_many_fields_bitwise_single(torch, vsht, grid, precision):
+    """The *_many calls run all fields in one launch per stage (fields along the
+    grid's z dimension, each with its own workspace); every field must equal the
+    single-field calls bit for bit, weighted and unit-weight forward, plain and
+    weighted adjoint (rings2101: 1051 ring pairs, the split analysis)."""
+    print("[case] many fields", grid, precision, flush=True)
+    L = 40
+    xyz, w = vi.gl_grid(L) if grid == "gl40" else vi.gl_grid(L, n_theta=2101, n_phi=82)
+    plan = vsht.Plan(L, xyz, w, precision=precision)
+    cdt = plan.dtype
+    F = 5
+    A = np.stack([vi.random_coeffs(L, 70 + f)[0] for f in range(F)])
+    Bc = np.stack([vi.random_coeffs(L, 70 + f)[1] for f in range(F)])
+    Ad, Bd = dev(torch, A, cdt), dev(torch, Bc, cdt)
+    for tw in (False, True):
+        Tm = plan.adjoint_many(Ad, Bd, times_weights=tw)
+        for f in range(F):
+            Ts = plan.adjoint_many(Ad[f:f + 1], Bd[f:f + 1], times_weights=tw)[0]
+            assert torch.equal(Tm[f], Ts), ("adjoint", tw, f)
+    Tin = dev(torch, np.stack([vi.random_field(len(w), 80 + f) for f in range(F)]), cdt)
+    for uw in (False, True):
+        am, bm = plan.forward_many(Tin, unit_weights=uw)
+        for f in range(F):
+            a1, b1 = plan.forward_many(Tin[f:f + 1], unit_weights=uw)
+            assert torch.equal(am[f], a1[0]) and torch.equal(bm[f], b1[0]), ("forward", uw, f)
+    torch.cuda.synchronize()
+    plan.close()
