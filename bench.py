@@ -279,7 +279,8 @@ def main():
     ap.add_argument("--oracle-coeffs", type=int, default=4096)
     ap.add_argument("--oracle-points", type=int, default=4096)
     ap.add_argument("--no-oracle", action="store_true")
-    ap.add_argument("--precisions", default="fp64,fp32,bf16x3,bf16x6")
+    ap.add_argument("--precisions", default="fp64,fp32,bf16x3,bf16x6",
+                    help='L=1024 precisions to time ("" runs only the other legs, without a result line)')
     ap.add_argument("--l256", type=int, default=1,
                     help="also time L=256: GL 257 x 514 forward+adjoint and the adjoint at 4 L^2 scattered points")
     ap.add_argument("--batch-fields", type=int, default=256,
@@ -314,7 +315,7 @@ def main():
     Tr_np = vi.random_field(N, 5)
 
     results = {}
-    for prec in args.precisions.split(","):
+    for prec in [p for p in args.precisions.split(",") if p]:
         log("precision", prec)
         t_plan = time.perf_counter()
         plan = vsht.Plan(L, xyz, w, precision=prec)
@@ -361,6 +362,11 @@ def main():
         torch.cuda.synchronize()
         log("copied %d MiB" % args.copy_mb)
         del src, dst
+
+    if not results:
+        # --precisions "": a run of the other legs alone (for kernel traces); no JSON line
+        log("no L=%d precision requested: the other legs ran, no result line" % L)
+        return
 
     cpu = None
     if not args.no_oracle:
@@ -409,21 +415,26 @@ def main():
         t = st[dom] * 1e-3
         info = r["info"]
         cs = 16 if prec == "fp64" else 8
-        kern_names = {"leg_fwd": "k_leg_fwd_mfma", "leg_adj": "k_leg_adj",
+        real = "double" if prec == "fp64" else "float"
+        nprod = {"bf16x3": 3, "bf16x6": 6}.get(prec, 1)
+        # the names the kernel trace shows (ring and coefficient stages: template prefix)
+        kern_names = {"leg_fwd": "k_leg_fwd_mfma<%s>" % real, "leg_adj": "k_leg_adj<%s, 0>" % real,
                       "ring_fwd": "k_ring_fwd", "ring_adj": "k_ring_adj",
                       "recombine": "k_recombine", "prep": "k_prep"}
-        nprod = {"bf16x3": 3, "bf16x6": 6}.get(prec, 1)
         if nprod > 1:
-            kern_names.update(leg_fwd="k_leg_fwd_bf16<%d>" % nprod, leg_adj="k_leg_adj_bf16<%d>" % nprod)
+            kern_names.update(leg_fwd="k_leg_fwd_bf16<%d>" % nprod, leg_adj="k_leg_adj<float, %d>" % nprod)
         kern = kern_names.get(dom, dom)
         out = {"kernel": kern, "launch_us": round(st[dom] * 1e3, 2)}
         if dom in ("leg_fwd", "leg_adj"):
             flops = 32.0 * nprod * method_elements(L)
             executed = 16.0 * nprod * folded_elements(L, info["n_pairs"])
             peak = peaks.get(prec, BF16_MFMA_TFLOPS)
-            # the binary64/binary32 synthesis runs on the vector unit, whose peaks on
-            # this part equal the matrix-core ones (78.6 / 157.3 TFLOP/s)
-            bound = "alu" if (dom == "leg_adj" and nprod == 1) else "mfma"
+            # the binary64 and binary32 plans' synthesis runs in binary64 on the vector
+            # unit: its peak is the binary64 vector rate (78.6 TFLOP/s, equal to the
+            # binary64 matrix-core peak)
+            bound = "mfma"
+            if dom == "leg_adj" and nprod == 1:
+                bound, peak = "alu", FP64_MFMA_TFLOPS
             ach = flops / t / 1e12
             out.update(bound=bound, achieved=round(ach, 3), peak=peak, unit="TFLOP/s",
                        frac=round(ach / peak, 4), flops_per_launch=flops,
