@@ -57,7 +57,7 @@
  * oversampled grid with the exponential-of-semicircle kernel (width 14 grid
  * points in binary64, 8 otherwise; relative error near 1e-13 resp. 1e-6).
  * VSHT_OPT_SCATTERED_DIRECT selects the direct O(n L^2) evaluation instead; L
- * above 700 always uses it.  The forward transforms at scattered points run
+ * above 1279 always uses it (the grid's DFTs then no longer fit the kernels).  The forward transforms at scattered points run
  * the conjugate transpose of the grid path (spreading instead of gathering);
  * a plan on the direct path serves the adjoint only (VSHT_EUNSUPPORTED).
  */

@@ -246,9 +246,10 @@ hipError_t build_start_tables(int L, int NP, const double *d_z, const double *d_
     return e;
 }
 
-// Largest bandlimit the double-Fourier-sphere path serves (its DFT lengths stay
-// within the ring DFT kernels' limits).
-constexpr int kMaxNfftL = 700;
+// Largest bandlimit the double-Fourier-sphere path serves: its column kernels keep
+// the 2L+1 orders of a row in registers, five per thread of 512 (2L+1 <= 2560).  The
+// DFT lengths must also fit the LDS DFT kernels (checked when the sizes are chosen).
+constexpr int kMaxNfftL = 1279;
 
 // Tables of the double-Fourier-sphere evaluation of a scattered plan.
 hipError_t build_nfft(Plan &P, int64_t n, const double *xyz) {
@@ -257,9 +258,21 @@ hipError_t build_nfft(Plan &P, int64_t n, const double *xyz) {
     const size_t rsz = P.precision == VSHT_FP64 ? 8 : 4;
     nf.w = P.precision == VSHT_FP64 ? 14 : 8;
     nf.beta = 2.30 * nf.w;
+    // the smallest 5-smooth lengths (nt a multiple of 4, ng even) whose DFT stages fit
+    // a 512-thread workgroup and whose two sequences fit its LDS
+    auto fits = [&](int n) {
+        std::map<int, int> fi;
+        std::vector<FftDesc> fd;
+        std::vector<double> t;
+        const int id = fft_descriptor(n, fi, fd, t);
+        const int64_t len = fd[id].blue ? fd[id].M : fd[id].n;
+        return fft_fits(fd[id], fd, 512) && ring_lds_bytes_for(len, rsz) <= kLdsPerWorkgroup;
+    };
     nf.nt = smooth_at_least(2 * L + 2, 4);
+    for (int k = 0; k < 64 && !fits(nf.nt); ++k) nf.nt = smooth_at_least(nf.nt + 4, 4);
     nf.npv = nf.nt / 4;
     nf.ng = smooth_at_least(std::max(2 * (2 * L + 1), 2 * nf.w), 2);
+    for (int k = 0; k < 64 && !fits(nf.ng); ++k) nf.ng = smooth_at_least(nf.ng + 2, 2);
     std::map<int, int> fidx;
     std::vector<FftDesc> ffts;
     std::vector<double> tw;
@@ -267,7 +280,9 @@ hipError_t build_nfft(Plan &P, int64_t n, const double *xyz) {
     nf.fft_ng = fft_descriptor(nf.ng, fidx, ffts, tw);
     auto stored = [&](int id) -> int64_t { return ffts[id].blue ? ffts[id].M : ffts[id].n; };
     nf.lds_stride = std::max(stored(nf.fft_nt), stored(nf.fft_ng));
-    if (!fft_fits(ffts[nf.fft_nt], ffts, 512) || !fft_fits(ffts[nf.fft_ng], ffts, 512)) return hipErrorInvalidValue;
+    if (!fft_fits(ffts[nf.fft_nt], ffts, 512) || !fft_fits(ffts[nf.fft_ng], ffts, 512) ||
+        ring_lds_bytes_for(nf.lds_stride, rsz) > kLdsPerWorkgroup)
+        return hipErrorInvalidValue;
     size_t bytes = 0;
     hipError_t e;
     if ((e = upload(&nf.d_ffts, ffts, &bytes)) != hipSuccess) return e;

@@ -77,6 +77,14 @@ struct FftDesc {
     int64_t rtab_offset;
 };
 
+// LDS bytes of a workgroup that transforms two sequences of stored length len
+// (the kernels' cos/sin table of an odd radix, then the padded sequences).
+inline size_t ring_lds_bytes_for(int64_t len, size_t real_size) {
+    const size_t elems = 2 * (size_t)len;
+    return kSmallTab * 2 * sizeof(double) + (elems + elems / 16 + 1) * 2 * real_size;
+}
+constexpr size_t kLdsPerWorkgroup = 160 * 1024;
+
 // Waves of the first odd stage of radix R on a ring's two sequences of length n:
 // one group of kKU output pairs per wave, over the 2 n / R columns of both sequences.
 __host__ __device__ inline int first_stage_waves(int n, int R) {

@@ -2550,7 +2550,7 @@ struct NfftArgs {
 };
 
 constexpr int kNfftNT = 512;
-constexpr int kNfftMaxK = 3;   // (2L+1) / kNfftNT, rounded up, for L <= 767
+constexpr int kNfftMaxK = 5;   // (2L+1) / kNfftNT, rounded up, for L <= 1279
 constexpr int kNfftMaxW = 16;
 
 // One workgroup per order m in [-L, L]: theta samples of T_theta,m and T_phi,m,
@@ -3044,8 +3044,8 @@ __global__ __launch_bounds__(256) void k_sht_fg_to_coef(ShtArgs<real> A) {
 // launchers
 // ===========================================================================
 static size_t ring_lds_bytes_len(int64_t len, size_t real_size) {
-    const size_t elems = 2 * (size_t)len;
-    return kSmallTab * sizeof(CD) + (elems + elems / 16 + 1) * 2 * real_size;
+    static_assert(sizeof(CD) == 2 * sizeof(double), "cos/sin table entries are two binary64");
+    return ring_lds_bytes_for(len, real_size);
 }
 static size_t ring_lds_bytes(const Plan &p, size_t real_size) { return ring_lds_bytes_len(p.max_fft_len, real_size); }
 

@@ -184,6 +184,38 @@ def test_healpix_rings(torch, vsht, orc, precision, tol):
     plan.close()
 
 
+# The double-Fourier-sphere path at L = 1024 (grid 4500 x 4500, the smallest
+# 5-smooth length of at least 2(2L+1) whose DFT fits the LDS kernels) on 200,000
+# uniform points plus both poles, equal weights: adjoint sampled at 64 points and
+# forward (eq. (fwdvsht2)) sampled at 32 coefficients against the oracle.
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_scattered_grid_L1024(torch, vsht, orc, precision, tol):
+    L = 1024
+    print_case("scattered grid", L, precision)
+    xyz, w = vi.uniform_points(200000, 91)
+    xyz = np.concatenate([xyz, [[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]]])
+    w = np.full(len(xyz), 4 * np.pi / len(xyz))
+    plan = vsht.Plan(L, xyz, w, precision=precision)
+    assert plan.kind == "scattered" and plan.info()["nfft_grid"] > 0
+    a, b = vi.random_coeffs(L, 92)
+    if precision != "fp64":
+        a, b = (x.astype(np.complex64).astype(np.complex128) for x in (a, b))
+    T = run_adjoint(torch, plan, a, b)
+    pidx = np.concatenate([vi.sample_indices(len(w) - 2, 62, 93), [len(w) - 2, len(w) - 1]])
+    e_adj = rel_l2(T[pidx], orc.adjoint(L, a, b, xyz[pidx]))
+    Tr = vi.random_field(len(w), 94)
+    if precision != "fp64":
+        Tr = Tr.astype(np.complex64).astype(np.complex128)
+    ga, gb = run_forward(torch, plan, Tr)
+    cidx = vi.sample_indices(L * (L + 2), 32, 95)
+    sa, sb = orc.forward_subset(L, xyz, w, Tr, cidx)
+    e_fwd = rel_l2(np.concatenate([ga[cidx], gb[cidx]]), np.concatenate([sa, sb]))
+    print("scattered grid L=%d %s grid %d adjoint %.3e forward %.3e"
+          % (L, precision, plan.info()["nfft_grid"], e_adj, e_fwd), flush=True)
+    assert e_adj < tol and e_fwd < tol
+    plan.close()
+
+
 def test_scattered_adjoint_fp64(torch, vsht, orc):
     L = 24
     xyz, _ = vi.uniform_points(700, 2)
