@@ -69,7 +69,8 @@ void free_plan_memory(Plan *p) {
     void *ptrs[] = {p->d_rings, p->d_pairs, p->d_ffts, p->d_tw,  p->d_pair_z, p->d_aprime,
                     p->d_cscale, p->d_etab, p->d_rsq,  p->d_seeds, p->d_start, p->d_sblk, p->d_weights, p->d_xyz,
                     p->d_pb, p->d_fg, p->d_fg64, p->d_fpart, p->d_many, p->d_state, nf.d_ffts, nf.d_tw, nf.d_vpairs, nf.d_vz,
-                    nf.d_vs, nf.d_vseeds, nf.d_vstart, nf.d_vsblk, nf.d_psihat, nf.d_pts, nf.d_vpb, nf.d_g1, nf.d_g};
+                    nf.d_vs, nf.d_vseeds, nf.d_vstart, nf.d_vsblk, nf.d_psihat, nf.d_pts, nf.d_tiles, nf.d_vpb, nf.d_g1,
+                    nf.d_g};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
 }
@@ -349,7 +350,11 @@ hipError_t build_nfft(Plan &P, int64_t n, const double *xyz) {
                 q.phi = 0.0;
             }
             q.idx = k;
-            key[k] = (int64_t)(q.theta / h) * nf.ng + (int64_t)(q.phi / h);
+            // the window's first row and column, as the gather computes them
+            const double hw = 0.5 * nf.w;
+            const int j0 = (int)std::ceil(q.theta / h - hw), i0 = (int)std::ceil(q.phi / h - hw);
+            const int64_t tj = (j0 + nf.w / 2) / kGatherTile, ti = (i0 + nf.w / 2) / kGatherTile;
+            key[k] = ((tj * (nf.ng / kGatherTile + 2) + ti) * nf.ng + j0) * (int64_t)(nf.ng + nf.w) + i0;
         }
         std::vector<int64_t> order(n);
         for (int64_t k = 0; k < n; ++k) order[k] = k;
@@ -357,6 +362,19 @@ hipError_t build_nfft(Plan &P, int64_t n, const double *xyz) {
         std::vector<NfftPoint> sorted(n);
         for (int64_t k = 0; k < n; ++k) sorted[k] = pts[order[k]];
         if ((e = upload(&nf.d_pts, sorted, &bytes)) != hipSuccess) return e;
+        // runs of points in one tile
+        std::vector<NfftTile> tiles;
+        const double hw = 0.5 * nf.w;
+        for (int64_t k = 0; k < n; ++k) {
+            const NfftPoint &q = sorted[k];
+            const int j0 = (int)std::ceil(q.theta / h - hw), i0 = (int)std::ceil(q.phi / h - hw);
+            const int tj = (j0 + nf.w / 2) / kGatherTile, ti = (i0 + nf.w / 2) / kGatherTile;
+            if (tiles.empty() || tiles.back().tj != tj || tiles.back().ti != ti)
+                tiles.push_back(NfftTile{tj, ti, 0, 0, k});
+            ++tiles.back().count;
+        }
+        nf.ntiles = (int)tiles.size();
+        if ((e = upload(&nf.d_tiles, tiles, &bytes)) != hipSuccess) return e;
     }
     const size_t vpb = (size_t)(L + 1) * nf.npv * 16 * rsz;
     const size_t g1 = (size_t)2 * nf.ng * (2 * L + 1) * 2 * rsz;
@@ -690,7 +708,7 @@ vsht_status build_plan(Plan &P, int L, int64_t n, const double *xyz, const doubl
                 e = hipSuccess;  // grid sizes the DFT kernels cannot take: direct evaluation
                 NfftPlan &nf = P.nfft;
                 void *q[] = {nf.d_ffts, nf.d_tw,     nf.d_vpairs, nf.d_vz,     nf.d_vs, nf.d_vseeds, nf.d_vstart,
-                             nf.d_vsblk, nf.d_psihat, nf.d_pts,    nf.d_vpb, nf.d_g1, nf.d_g};
+                             nf.d_vsblk, nf.d_psihat, nf.d_pts,    nf.d_tiles, nf.d_vpb, nf.d_g1, nf.d_g};
                 for (void *x : q)
                     if (x) (void)hipFree(x);
                 nf = NfftPlan();

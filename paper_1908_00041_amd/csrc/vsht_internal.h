@@ -98,6 +98,17 @@ struct NfftPoint {
     int64_t idx;         // position in the caller's point order
 };
 
+// Gather tiles of the double-Fourier-sphere adjoint: a point whose window starts at
+// grid cell (j0, i0) (the first row and column its width-w kernel touches) belongs
+// to tile (tj, ti) = ((j0 + w/2) / kGatherTile, (i0 + w/2) / kGatherTile); the
+// tile's workgroup stages rows and columns [t kGatherTile - w/2, + kGatherTile + w - 1)
+// of both grids in LDS and gathers its points from there.
+constexpr int kGatherTile = 16;
+struct NfftTile {
+    int32_t tj, ti, count, pad;
+    int64_t start;  // first point (index into the sorted points)
+};
+
 // Where each (order m, ring pair p) enters the Legendre stages.  Degrees are
 // taken in blocks of kStartBlock from l' = m; (m, p) starts at block b with the
 // recurrence state (Q_{l0-1}, Q_{l0-2}), l0 = m + kStartBlock b, and adds
@@ -136,7 +147,9 @@ struct NfftPlan {
     LegStart *d_vstart = nullptr;     // start states, [(L+1)][npv]
     int *d_vsblk = nullptr;           // start blocks, [(L+1)][npv]
     double *d_psihat = nullptr;       // window transform at k = -L..L
-    NfftPoint *d_pts = nullptr;
+    NfftPoint *d_pts = nullptr;       // points sorted by gather tile, then by grid cell
+    NfftTile *d_tiles = nullptr;      // the non-empty gather tiles (point ranges of d_pts)
+    int ntiles = 0;
     void *d_vpb = nullptr;            // virtual pair buffer [(L+1)][npv][16] reals (adjoint),
                                       // virtual ring buffer [(L+1)][nt/2][8] reals (forward)
     void *d_g1 = nullptr;             // column pass output [2][ng][2L+1] complex

@@ -2537,6 +2537,7 @@ struct NfftArgs {
     const FftDesc *ffts;
     const double *tw;
     const NfftPoint *pts;
+    const NfftTile *tiles;     // gather tiles (point ranges of pts)
     const double *weights;
     C2<real> *Tout;
     const C2<real> *Tin;       // forward: the field at the points
@@ -2653,40 +2654,80 @@ __global__ __launch_bounds__(kNfftNT, 1) void k_nfft_rows(NfftArgs<real> A) {
 
 // One lane per point (in grid-cell order): window sum of both components,
 // rotation to Cartesian components, store at the caller's index.
+// Gather, one workgroup per tile of kGatherTile x kGatherTile grid cells: the
+// window of both grids that the tile's points touch (kGatherTile + w - 1 rows and
+// columns, periodic in both) is staged in LDS once, and every point of the tile
+// reads its w x w values from there.  A point whose window would leave the tile's
+// (never, when the planner and the kernel agree on its first cell) reads the grids
+// directly; both forms add the same terms in the same order.
+constexpr int kGatherWin = kGatherTile + kNfftMaxW - 1;
 template <typename real>
 __global__ __launch_bounds__(256) void k_nfft_gather(NfftArgs<real> A) {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k >= A.n) return;
-    const NfftPoint P = A.pts[k];
-    const int ng = A.ng, w = A.w;
-    const double hw = 0.5 * w;
-    const double u = P.theta / A.h, v = P.phi / A.h;
-    const int j0 = (int)ceil(u - hw), i0 = (int)ceil(v - hw);
-    real wt[kNfftMaxW], wp[kNfftMaxW];
-#pragma unroll
-    for (int a = 0; a < kNfftMaxW; ++a) {
-        wt[a] = wp[a] = 0;
-        if (a < w) {
-            const double dt = (u - (j0 + a)) / hw, dp = (v - (i0 + a)) / hw;
-            wt[a] = (real)(fabs(dt) < 1.0 ? exp(A.beta * (sqrt((1.0 - dt) * (1.0 + dt)) - 1.0)) : 0.0);
-            wp[a] = (real)(fabs(dp) < 1.0 ? exp(A.beta * (sqrt((1.0 - dp) * (1.0 + dp)) - 1.0)) : 0.0);
-        }
+    __shared__ C2<real> win[2][kGatherWin * kGatherWin];
+    const NfftTile T = ld_uniform(A.tiles + blockIdx.x);
+    const int ng = A.ng, w = A.w, hw2 = w / 2;
+    const int W = kGatherTile + w - 1;
+    const int R0 = T.tj * kGatherTile - hw2, C0 = T.ti * kGatherTile - hw2;
+    for (int e = threadIdx.x; e < W * W; e += 256) {
+        const int r = e / W, c = e - (e / W) * W;
+        int gr = (R0 + r) % ng, gc = (C0 + c) % ng;
+        if (gr < 0) gr += ng;
+        if (gc < 0) gc += ng;
+        win[0][r * kGatherWin + c] = A.g[(size_t)gr * ng + gc];
+        win[1][r * kGatherWin + c] = A.g[((size_t)ng + gr) * ng + gc];
     }
-    real thr = 0, thi = 0, phr = 0, phi_ = 0;
-    int jr = j0 % ng;
-    if (jr < 0) jr += ng;
-    int ir0 = i0 % ng;
-    if (ir0 < 0) ir0 += ng;
+    __syncthreads();
+    const double hw = 0.5 * w;
+    for (int t = threadIdx.x; t < T.count; t += 256) {
+        const NfftPoint P = A.pts[T.start + t];
+        const double u = P.theta / A.h, v = P.phi / A.h;
+        const int j0 = (int)ceil(u - hw), i0 = (int)ceil(v - hw);
+        real wt[kNfftMaxW], wp[kNfftMaxW];
 #pragma unroll
-    for (int a = 0; a < kNfftMaxW; ++a) {
-        if (a < w) {
-            const C2<real> *rt = A.g + (size_t)jr * ng;
-            const C2<real> *rp = A.g + ((size_t)ng + jr) * ng;
-            real str = 0, sti = 0, spr = 0, spi = 0;
-            int ir = ir0;
+        for (int a = 0; a < kNfftMaxW; ++a) {
+            wt[a] = wp[a] = 0;
+            if (a < w) {
+                const double dt = (u - (j0 + a)) / hw, dp = (v - (i0 + a)) / hw;
+                wt[a] = (real)(fabs(dt) < 1.0 ? exp(A.beta * (sqrt((1.0 - dt) * (1.0 + dt)) - 1.0)) : 0.0);
+                wp[a] = (real)(fabs(dp) < 1.0 ? exp(A.beta * (sqrt((1.0 - dp) * (1.0 + dp)) - 1.0)) : 0.0);
+            }
+        }
+        real thr = 0, thi = 0, phr = 0, phi_ = 0;
+        const int lr = j0 - R0, lc = i0 - C0;
+        if (lr >= 0 && lr < kGatherTile && lc >= 0 && lc < kGatherTile) {
 #pragma unroll
-            for (int c = 0; c < kNfftMaxW; ++c) {
-                if (c < w) {
+            for (int a = 0; a < kNfftMaxW; ++a) {
+                if (a < w) {
+                    const C2<real> *rt = win[0] + (lr + a) * kGatherWin + lc;
+                    const C2<real> *rp = win[1] + (lr + a) * kGatherWin + lc;
+                    real str = 0, sti = 0, spr = 0, spi = 0;
+#pragma unroll
+                    for (int c = 0; c < kNfftMaxW; ++c) {
+                        if (c < w) {
+                            const C2<real> gt = rt[c], gp = rp[c];
+                            str += wp[c] * gt.x;
+                            sti += wp[c] * gt.y;
+                            spr += wp[c] * gp.x;
+                            spi += wp[c] * gp.y;
+                        }
+                    }
+                    thr += wt[a] * str;
+                    thi += wt[a] * sti;
+                    phr += wt[a] * spr;
+                    phi_ += wt[a] * spi;
+                }
+            }
+        } else {
+            int jr = j0 % ng;
+            if (jr < 0) jr += ng;
+            int ir0 = i0 % ng;
+            if (ir0 < 0) ir0 += ng;
+            for (int a = 0; a < w; ++a) {
+                const C2<real> *rt = A.g + (size_t)jr * ng;
+                const C2<real> *rp = A.g + ((size_t)ng + jr) * ng;
+                real str = 0, sti = 0, spr = 0, spi = 0;
+                int ir = ir0;
+                for (int c = 0; c < w; ++c) {
                     const C2<real> gt = rt[ir], gp = rp[ir];
                     str += wp[c] * gt.x;
                     sti += wp[c] * gt.y;
@@ -2694,21 +2735,21 @@ __global__ __launch_bounds__(256) void k_nfft_gather(NfftArgs<real> A) {
                     spi += wp[c] * gp.y;
                     if (++ir == ng) ir = 0;
                 }
+                thr += wt[a] * str;
+                thi += wt[a] * sti;
+                phr += wt[a] * spr;
+                phi_ += wt[a] * spi;
+                if (++jr == ng) jr = 0;
             }
-            thr += wt[a] * str;
-            thi += wt[a] * sti;
-            phr += wt[a] * spr;
-            phi_ += wt[a] * spi;
-            if (++jr == ng) jr = 0;
         }
+        const real z = (real)P.z, s = (real)P.s, c = (real)P.c, sn = (real)P.sn;
+        real sc = 1;
+        if (A.weighted) sc = (real)A.weights[P.idx];
+        C2<real> *o = A.Tout + 3 * P.idx;
+        o[0] = {sc * (z * c * thr - sn * phr), sc * (z * c * thi - sn * phi_)};
+        o[1] = {sc * (z * sn * thr + c * phr), sc * (z * sn * thi + c * phi_)};
+        o[2] = {sc * (-s * thr), sc * (-s * thi)};
     }
-    const real z = (real)P.z, s = (real)P.s, c = (real)P.c, sn = (real)P.sn;
-    real sc = 1;
-    if (A.weighted) sc = (real)A.weights[P.idx];
-    C2<real> *o = A.Tout + 3 * P.idx;
-    o[0] = {sc * (z * c * thr - sn * phr), sc * (z * c * thi - sn * phi_)};
-    o[1] = {sc * (z * sn * thr + c * phr), sc * (z * sn * thi + c * phi_)};
-    o[2] = {sc * (-s * thr), sc * (-s * thi)};
 }
 
 // ---------------------------------------------------------------------------
@@ -3189,6 +3230,7 @@ static NfftArgs<real> make_nfft_args(const Plan &p, const void *Tin, void *Tout,
     N.ffts = nf.d_ffts;
     N.tw = nf.d_tw;
     N.pts = nf.d_pts;
+    N.tiles = nf.d_tiles;
     N.weights = p.d_weights;
     N.Tin = static_cast<const C2<real> *>(Tin);
     N.Tout = static_cast<C2<real> *>(Tout);
@@ -3370,7 +3412,7 @@ static hipError_t adjoint_impl(const Plan &p, const AdjWork &ws, const void *a, 
         StageScope sc(p, VSHT_STAGE_SCATTERED, st);
         hipLaunchKernelGGL(k_nfft_cols<real>, dim3(2 * p.L + 1), dim3(kNfftNT), lds, st, N);
         hipLaunchKernelGGL(k_nfft_rows<real>, dim3(nf.ng), dim3(kNfftNT), lds, st, N);
-        hipLaunchKernelGGL(k_nfft_gather<real>, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, st, N);
+        hipLaunchKernelGGL(k_nfft_gather<real>, dim3((unsigned)nf.ntiles), dim3(256), 0, st, N);
         return hipGetLastError();
     }
 
