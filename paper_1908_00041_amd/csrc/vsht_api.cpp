@@ -400,6 +400,18 @@ struct RingScan {
 RingScan scan_rings(int64_t n, const double *xyz, const double *w) {
     RingScan rs;
     const long double two_pi = 6.283185307179586476925286766559005768L;
+    // (cos, sin)(2 pi t / len) per ring length, in extended precision once per length
+    std::map<int64_t, std::vector<std::pair<double, double>>> unit;
+    auto roots = [&](int64_t len) -> const std::vector<std::pair<double, double>> & {
+        auto it = unit.find(len);
+        if (it != unit.end()) return it->second;
+        std::vector<std::pair<double, double>> v(len);
+        for (int64_t t = 0; t < len; ++t) {
+            const long double a = two_pi * (long double)t / (long double)len;
+            v[t] = {(double)cosl(a), (double)sinl(a)};
+        }
+        return unit.emplace(len, std::move(v)).first->second;
+    };
     int64_t i = 0;
     while (i < n) {
         int64_t j = i + 1;
@@ -424,10 +436,12 @@ RingScan scan_rings(int64_t n, const double *xyz, const double *w) {
         r.phi0 = std::atan2(xyz[3 * i + 1], xyz[3 * i]);
         r.c0 = std::cos(r.phi0);
         r.s0 = std::sin(r.phi0);
+        // expected point t: s e^{i (phi0 + 2 pi t / cnt)}, rounding error a few ulp,
+        // far below the 1e-12 tolerance
+        const std::vector<std::pair<double, double>> &u = roots(cnt);
         for (int64_t t = 0; t < cnt; ++t) {
-            const long double ph = (long double)r.phi0 + two_pi * (long double)t / (long double)cnt;
-            const double ex = (double)((long double)r.s * cosl(ph));
-            const double ey = (double)((long double)r.s * sinl(ph));
+            const double ex = r.s * (r.c0 * u[t].first - r.s0 * u[t].second);
+            const double ey = r.s * (r.s0 * u[t].first + r.c0 * u[t].second);
             if (std::fabs(xyz[3 * (i + t)] - ex) > 1e-12 || std::fabs(xyz[3 * (i + t) + 1] - ey) > 1e-12) {
                 rs.ok = false;
                 rs.why = "ring points not equispaced in longitude";

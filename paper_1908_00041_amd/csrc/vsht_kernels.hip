@@ -2094,9 +2094,19 @@ __host__ __device__ constexpr size_t adj_lds_block() {
                    ? 4 * (size_t)Bf16<NPROD>::kAdjLdsPerWave
                    : 2 * kAdjChunk * sizeof(AdjRow);
 }
+// waves per synthesis workgroup: the vector-unit form takes 128 pairs per wave and
+// as many waves (up to four) as the pairs fill; the split-bf16 forms take four
+__host__ __device__ inline int adj_waves(int NPT, int nprod) {
+    if (nprod != 0) return 4;
+    const int w = (NPT + 2 * kTileP - 1) / (2 * kTileP);
+    return w < 1 ? 1 : (w > 4 ? 4 : w);
+}
 // workgroup columns of a synthesis launch over NPT tile pairs
 __host__ __device__ inline int adj_columns(int NPT, int nprod) {
-    if (nprod == 0) return NPT > 0 ? (NPT + 8 * kTileP - 1) / (8 * kTileP) : 1;
+    if (nprod == 0) {
+        const int per = 2 * kTileP * adj_waves(NPT, nprod);
+        return NPT > 0 ? (NPT + per - 1) / per : 1;
+    }
     return (adj_slots(NPT, nprod) + 3) / 4;
 }
 
@@ -2104,8 +2114,9 @@ template <typename real, int NPROD>
 __device__ __forceinline__ void leg_adj_group(const LegArgs<real> &A, int m, int x, unsigned char *smem) {
     const int wave = uniform_int(threadIdx.x >> 6);
     if constexpr (NPROD == 0) {
-        adj_valu_block<real, 2, 0, 8>(A, A.FG64, m, x * 8 * kTileP + wave * 2 * kTileP, A.NPT, x == 0 && wave == 0 && A.NP > A.NPT,
-                                      reinterpret_cast<AdjRow *>(smem));
+        const int nw = blockDim.x >> 6;  // adj_waves(NPT, 0)
+        adj_valu_block<real, 2, 0, 8>(A, A.FG64, m, (x * nw + wave) * 2 * kTileP, A.NPT,
+                                      x == 0 && wave == 0 && A.NP > A.NPT, reinterpret_cast<AdjRow *>(smem));
     } else {
         const int P = adj_polar_pairs(A.NPT, NPROD);
         const int slot = x * 4 + wave;
@@ -3211,9 +3222,10 @@ static void launch_leg_adj(const LegArgs<real> &G, dim3 grid, int nprod, hipStre
         else if (nprod == 6)
             hipLaunchKernelGGL((k_leg_adj<float, 6>), grid, dim3(256), adj_lds_block<6>(), st, G);
         else
-            hipLaunchKernelGGL((k_leg_adj<float, 0>), grid, dim3(256), adj_lds_block<0>(), st, G);
+            hipLaunchKernelGGL((k_leg_adj<float, 0>), grid, dim3(64 * adj_waves(G.NPT, 0)), adj_lds_block<0>(), st,
+                               G);
     } else {
-        hipLaunchKernelGGL((k_leg_adj<double, 0>), grid, dim3(256), adj_lds_block<0>(), st, G);
+        hipLaunchKernelGGL((k_leg_adj<double, 0>), grid, dim3(64 * adj_waves(G.NPT, 0)), adj_lds_block<0>(), st, G);
     }
 }
 
@@ -3794,15 +3806,20 @@ hipError_t batch_configure(BatchState *b, const BatchConfig &cfg) {
     }
     emit(BS_PREP, 4, items, 0);
     items.clear();
-    // Legendre synthesis: the single plans' workgroups (four waves each) of every field
-    for (int i = 0; i < F; ++i) {
-        const Plan &p = *b->f[i];
-        const int cols = adj_columns(pairs_in_tiles(p), nprod);
-        for (int x = 0; x < cols; ++x)
-            for (int m = 0; m <= p.L; ++m) items.push_back({{i, x, m, 0}, (double)(p.L + 2 - m) * 4});
+    // Legendre synthesis: the single plans' workgroups of every field, one launch per
+    // workgroup width (the vector-unit form sizes its workgroups to the field's pairs)
+    for (int nw = 1; nw <= 4; ++nw) {
+        for (int i = 0; i < F; ++i) {
+            const Plan &p = *b->f[i];
+            if (adj_waves(pairs_in_tiles(p), nprod) != nw) continue;
+            const int cols = adj_columns(pairs_in_tiles(p), nprod);
+            for (int x = 0; x < cols; ++x)
+                for (int m = 0; m <= p.L; ++m) items.push_back({{i, x, m, 0}, (double)(p.L + 2 - m) * nw});
+        }
+        emit(BS_LEG_ADJ, nw, items,
+             nprod == 3 ? adj_lds_block<3>() : nprod == 6 ? adj_lds_block<6>() : adj_lds_block<0>());
+        items.clear();
     }
-    emit(BS_LEG_ADJ, 4, items, nprod == 3 ? adj_lds_block<3>() : nprod == 6 ? adj_lds_block<6>() : adj_lds_block<0>());
-    items.clear();
     for (int i = 0; i < F; ++i)
         if (b->f[i]->eq_ring >= 0 && nprod != 0)  // the vector-unit synthesis forms the equator itself
             for (int m = 0; m <= b->f[i]->L; ++m) items.push_back({{i, m, 0, 0}, (double)(b->f[i]->L + 2 - m)});
