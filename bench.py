@@ -232,7 +232,7 @@ def run_differentiable(torch, vsht, vi, args):
         a.grad = None
         b.grad = None
         r = vsht.adjoint_vsht(plan, a, b) - Tt
-        loss = (r.real ** 2 + r.imag ** 2).sum()
+        loss = torch.view_as_real(r).square().sum()  # sum of |r|^2 over points and fields
         loss.backward()
         return loss
 

@@ -93,14 +93,25 @@ typedef enum {
 
 /* Flags of vsht_opts. */
 enum {
-    VSHT_OPT_SCATTERED_DIRECT = 1 /* scattered points: direct evaluation (O(n L^2)) instead of
-                                     the double-Fourier-sphere grid */
+    VSHT_OPT_SCATTERED_DIRECT = 1, /* scattered points: direct evaluation (O(n L^2)) instead of
+                                      the double-Fourier-sphere grid */
+    VSHT_OPT_NO_FOLD = 2           /* ring grids: do not fold north/south mirror rings into pairs
+                                      (every ring is its own pair; same results, about twice the
+                                      Legendre work) */
 };
 
 typedef struct {
-    int precision; /* a vsht_precision value */
-    int device;    /* HIP device ordinal; -1 = the calling thread's current device */
-    int flags;     /* VSHT_OPT_* */
+    int precision;          /* a vsht_precision value */
+    int device;             /* HIP device ordinal; -1 = the calling thread's current device */
+    int flags;              /* VSHT_OPT_* */
+    double nfft_eps;        /* scattered grid path: target relative accuracy of the window
+                               gather, 0 for the default (about 1e-13 in binary64, 1e-7 in
+                               binary32); picks the window width w = ceil(-log10 eps) + 1 rounded
+                               up to even, within [4, 16].  VSHT_EINVAL outside [0, 1). */
+    const char *tune_cache; /* batch plans: a text file in which vsht_batch_autotune keeps the
+                               fastest launch shape per (device architecture, precision, field
+                               shapes); a later autotune of the same batch reads it instead of
+                               timing.  NULL: no cache. */
 } vsht_opts;
 
 /* Plan kinds reported by vsht_plan_info. */
@@ -122,6 +133,10 @@ typedef struct {
 
 /* Number of coefficients of each kind for bandlimit L: L(L+2) (L >= 1), else 0. */
 int64_t vsht_num_coeffs(int L);
+
+/* Device workspace the plan owns (bytes; the *_many calls add their per-field
+ * workspace on first use).  0 for NULL. */
+size_t vsht_workspace_bytes(vsht_plan_t plan);
 
 /* Create a plan for bandlimit L >= 1 on n points.
  *   xyz     host, n x 3 binary64 unit vectors (| |x| - 1 | <= 1e-12), finite.

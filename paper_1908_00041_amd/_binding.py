@@ -24,16 +24,19 @@ EXPORTED = ("vsht_num_coeffs", "vsht_plan", "vsht_forward", "vsht_forward_unweig
             "vsht_forward_many", "vsht_adjoint_many", "vsht_plan_batch", "vsht_batch_adjoint",
             "vsht_batch_forward", "vsht_batch_roundtrip", "vsht_batch_set_config",
             "vsht_batch_get_config", "vsht_batch_autotune", "vsht_batch_field_times",
-            "vsht_num_sht_coeffs", "vsht_sht_forward", "vsht_sht_adjoint", "vsht_forward_static")
+            "vsht_num_sht_coeffs", "vsht_sht_forward", "vsht_sht_adjoint", "vsht_forward_static",
+            "vsht_workspace_bytes")
 VSHT_UNIT_WEIGHTS, VSHT_TIMES_WEIGHTS = 1, 2
 STAGES = ("ring_fwd", "leg_fwd", "recombine", "prep", "leg_adj", "ring_adj", "scattered")
 
 
 class vsht_opts(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int), ("device", ctypes.c_int), ("flags", ctypes.c_int)]
+    _fields_ = [("precision", ctypes.c_int), ("device", ctypes.c_int), ("flags", ctypes.c_int),
+                ("nfft_eps", ctypes.c_double), ("tune_cache", ctypes.c_char_p)]
 
 
 VSHT_OPT_SCATTERED_DIRECT = 1
+VSHT_OPT_NO_FOLD = 2
 
 
 class vsht_plan_info_t(ctypes.Structure):
@@ -101,6 +104,8 @@ def load_library(path=LIB_PATH):
     lib.vsht_batch_field_times.restype = ci
     lib.vsht_plan_info.argtypes = [vp, ctypes.POINTER(vsht_plan_info_t)]
     lib.vsht_plan_info.restype = ci
+    lib.vsht_workspace_bytes.argtypes = [vp]
+    lib.vsht_workspace_bytes.restype = ctypes.c_size_t
     lib.vsht_plan_destroy.argtypes = [vp]
     lib.vsht_plan_destroy.restype = ci
     lib.vsht_status_string.argtypes = [ci]
@@ -190,7 +195,8 @@ class Plan:
     on the current torch stream.
     """
 
-    def __init__(self, L, points, weights=None, precision="fp64", device=None, scattered="grid"):
+    def __init__(self, L, points, weights=None, precision="fp64", device=None, scattered="grid",
+                 nfft_eps=0.0, fold=True):
         torch = _torch()
         if scattered not in ("grid", "direct"):
             raise ValueError("scattered must be 'grid' or 'direct'")
@@ -212,8 +218,8 @@ class Plan:
         self.precision = precision
         self.dtype = torch.complex128 if precision == "fp64" else torch.complex64
         self.K = int(lib.vsht_num_coeffs(self.L))
-        opts = vsht_opts(PRECISIONS[precision], int(device),
-                         VSHT_OPT_SCATTERED_DIRECT if scattered == "direct" else 0)
+        flags = (VSHT_OPT_SCATTERED_DIRECT if scattered == "direct" else 0) | (0 if fold else VSHT_OPT_NO_FOLD)
+        opts = vsht_opts(PRECISIONS[precision], int(device), flags, float(nfft_eps), None)
         h = ctypes.c_void_p()
         st = lib.vsht_plan(self.L, n, pts.ctypes.data_as(ctypes.c_void_p),
                            None if w is None else w.ctypes.data_as(ctypes.c_void_p),
@@ -221,6 +227,10 @@ class Plan:
         _raise_for(st, "vsht_plan")
         self._h = h
         self._info = self.info()
+
+    def workspace_bytes(self):
+        """Device workspace the plan owns (bytes)."""
+        return int(load_library().vsht_workspace_bytes(self._h))
 
     def info(self):
         inf = vsht_plan_info_t()
@@ -366,7 +376,7 @@ class BatchPlan:
     per field (complex128 for 'fp64', complex64 otherwise).
     """
 
-    def __init__(self, Ls, grids, precision="fp64", device=None):
+    def __init__(self, Ls, grids, precision="fp64", device=None, tune_cache=None):
         torch = _torch()
         lib = load_library()
         if precision not in PRECISIONS:
@@ -391,7 +401,8 @@ class BatchPlan:
         narr = (ctypes.c_int64 * F)(*self.ns)
         xarr = (ctypes.c_void_p * F)(*[p_.ctypes.data for p_ in pts])
         warr = (ctypes.c_void_p * F)(*[w_.ctypes.data for w_ in wts])
-        opts = vsht_opts(PRECISIONS[precision], int(device), 0)
+        self._tune_cache = None if tune_cache is None else os.fsencode(tune_cache)
+        opts = vsht_opts(PRECISIONS[precision], int(device), 0, 0.0, self._tune_cache)
         h = ctypes.c_void_p()
         st = lib.vsht_plan_batch(F, Larr, narr, xarr, warr, ctypes.byref(opts), ctypes.byref(h))
         _raise_for(st, "vsht_plan_batch")

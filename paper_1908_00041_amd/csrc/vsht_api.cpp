@@ -253,11 +253,22 @@ hipError_t build_start_tables(int L, int NP, const double *d_z, const double *d_
 constexpr int kMaxNfftL = 1279;
 
 // Tables of the double-Fourier-sphere evaluation of a scattered plan.
-hipError_t build_nfft(Plan &P, int64_t n, const double *xyz) {
+// Window width of the grid path for a target accuracy eps (0: the default of the
+// precision): the exponential-of-semicircle window with beta = 2.3 w on a twice
+// oversampled grid loses about one digit per grid point of width, so
+// w = ceil(-log10 eps) + 1, even, within [4, kNfftMaxW].
+int nfft_width(int precision, double eps) {
+    if (!(eps > 0.0)) return precision == VSHT_FP64 ? 14 : 8;
+    int w = (int)std::ceil(-std::log10(eps)) + 1;
+    w += w & 1;
+    return std::min(16, std::max(4, w));
+}
+
+hipError_t build_nfft(Plan &P, int64_t n, const double *xyz, double nfft_eps) {
     NfftPlan &nf = P.nfft;
     const int L = P.L;
     const size_t rsz = P.precision == VSHT_FP64 ? 8 : 4;
-    nf.w = P.precision == VSHT_FP64 ? 14 : 8;
+    nf.w = nfft_width(P.precision, nfft_eps);
     nf.beta = 2.30 * nf.w;
     // the smallest 5-smooth lengths (nt a multiple of 4, ng even) whose DFT stages fit
     // a 512-thread workgroup and whose two sequences fit its LDS
@@ -503,7 +514,7 @@ vsht_status resolve_device(const vsht_opts *opts, int *dev) {
 
 // Build the tables and workspace of one plan on the current device.
 vsht_status build_plan(Plan &P, int L, int64_t n, const double *xyz, const double *w, int precision,
-                       int dev, int flags) {
+                       int dev, int flags, double nfft_eps) {
     P.L = L;
     P.precision = precision;
     P.device = dev;
@@ -607,7 +618,7 @@ vsht_status build_plan(Plan &P, int L, int64_t n, const double *xyz, const doubl
             if (used[r]) continue;
             used[r] = 1;
             PairDesc pd{r, -1};
-            if (rings[r].z != 0.0) {
+            if (rings[r].z != 0.0 && !(flags & VSHT_OPT_NO_FOLD)) {
                 auto it = byz.find(key(-rings[r].z));
                 if (it != byz.end())
                     for (int c : it->second)
@@ -717,7 +728,7 @@ vsht_status build_plan(Plan &P, int L, int64_t n, const double *xyz, const doubl
             P.workspace_bytes += fg64;
         }
         if (!(flags & VSHT_OPT_SCATTERED_DIRECT) && L <= kMaxNfftL) {
-            e = build_nfft(P, n, xyz);
+            e = build_nfft(P, n, xyz, nfft_eps);
             if (e == hipErrorInvalidValue) {
                 e = hipSuccess;  // grid sizes the DFT kernels cannot take: direct evaluation
                 NfftPlan &nf = P.nfft;
@@ -748,6 +759,7 @@ struct BatchPlan {
     hipGraphExec_t exec[4] = {};        // by direction set: 1 adjoint, 2 forward, 3 both
     std::vector<const void *> bound_adj, bound_fwd;
     int last_dirs = 0;
+    std::string tune_cache;             // autotune results file ("" = none)
 
     void drop_graphs() {
         for (auto &x : exec)
@@ -788,6 +800,14 @@ const char *vsht_status_string(vsht_status s) {
 
 const char *vsht_last_error(void) { return g_last_error.c_str(); }
 
+// Fields of vsht_opts beyond the precision and device.
+static vsht_status check_opts(const vsht_opts *opts) {
+    if (!opts) return VSHT_OK;
+    if (opts->flags & ~(VSHT_OPT_SCATTERED_DIRECT | VSHT_OPT_NO_FOLD)) return fail(VSHT_EINVAL, "unknown flag in opts");
+    if (!(opts->nfft_eps >= 0.0 && opts->nfft_eps < 1.0)) return fail(VSHT_EINVAL, "nfft_eps must lie in [0, 1)");
+    return VSHT_OK;
+}
+
 vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w, const vsht_opts *opts,
                       vsht_plan_t *out) {
     g_last_error.clear();
@@ -796,12 +816,14 @@ vsht_status vsht_plan(int L, int64_t n, const double *xyz, const double *w, cons
     const int precision = opts ? opts->precision : VSHT_FP64;
     vsht_status s = check_plan_args(L, n, xyz, w, precision);
     if (s != VSHT_OK) return s;
+    if ((s = check_opts(opts)) != VSHT_OK) return s;
     int dev = 0;
     if ((s = resolve_device(opts, &dev)) != VSHT_OK) return s;
     DeviceGuard guard(dev);
     auto *h = new (std::nothrow) vsht_plan_s();
     if (!h) return fail(VSHT_ENOMEM, "host allocation");
-    if ((s = build_plan(h->p, L, n, xyz, w, precision, dev, opts ? opts->flags : 0)) != VSHT_OK) {
+    if ((s = build_plan(h->p, L, n, xyz, w, precision, dev, opts ? opts->flags : 0, opts ? opts->nfft_eps : 0.0)) !=
+        VSHT_OK) {
         delete h;
         return s;
     }
@@ -982,6 +1004,16 @@ vsht_status vsht_adjoint_many(vsht_plan_t plan, int64_t count, const void *a, co
     return VSHT_OK;
 }
 
+size_t vsht_workspace_bytes(vsht_plan_t plan) {
+    if (!plan) return 0;
+    if (plan->batch) {
+        size_t t = 0;
+        for (const Plan &f : plan->batch->fields) t += f.workspace_bytes;
+        return t;
+    }
+    return plan->p.workspace_bytes + plan->p.many_bytes;
+}
+
 vsht_status vsht_plan_info(vsht_plan_t plan, vsht_plan_info_t *info) {
     g_last_error.clear();
     if (!plan || !info) return fail(VSHT_EINVAL, "NULL argument");
@@ -1068,6 +1100,7 @@ vsht_status vsht_plan_batch(int nfields, const int *L, const int64_t *n, const d
     *out = nullptr;
     if (nfields < 1) return fail(VSHT_EINVAL, "nfields must be >= 1");
     if (!L || !n || !xyz || !w) return fail(VSHT_EINVAL, "NULL argument");
+    if (vsht_status so = check_opts(opts); so != VSHT_OK) return so;
     const int precision = opts ? opts->precision : VSHT_FP64;
     for (int f = 0; f < nfields; ++f) {
         if (!w[f]) return fail(VSHT_EINVAL, "field " + std::to_string(f) + ": weights are required");
@@ -1089,6 +1122,7 @@ vsht_status vsht_plan_batch(int nfields, const int *L, const int64_t *n, const d
         return fail(VSHT_ENOMEM, "host allocation");
     }
     BatchPlan &B = *h->batch;
+    if (opts && opts->tune_cache) B.tune_cache = opts->tune_cache;
     B.fields.resize(nfields);
     Plan &S = h->p;  // summary
     S.precision = precision;
@@ -1096,7 +1130,8 @@ vsht_status vsht_plan_batch(int nfields, const int *L, const int64_t *n, const d
     S.kind = VSHT_PLAN_BATCH;
     S.has_weights = 1;
     for (int f = 0; f < nfields; ++f) {
-        s = build_plan(B.fields[f], L[f], n[f], xyz[f], w[f], precision, dev, opts ? opts->flags : 0);
+        s = build_plan(B.fields[f], L[f], n[f], xyz[f], w[f], precision, dev, opts ? opts->flags : 0,
+                       opts ? opts->nfft_eps : 0.0);
         if (s == VSHT_OK && B.fields[f].kind != VSHT_PLAN_RINGS)
             s = fail(VSHT_EUNSUPPORTED, "a batch needs iso-latitude ring grids");
         // the batched analysis holds all of a field's ring-pair tiles in one workgroup
@@ -1278,6 +1313,61 @@ vsht_status vsht_batch_get_config(vsht_plan_t plan, int *adj_nw, int *fwd_merge,
     return VSHT_OK;
 }
 
+// Autotune cache: one line per batch, "<key> adj_nw fwd_merge lpt ring_nt ms".  The
+// key names the device architecture, the precision, the field count and an FNV-1a
+// digest of every field's (L, points, rings, longest stored DFT length).
+static std::string tune_key(const BatchPlan &B, int dev) {
+    hipDeviceProp_t prop{};
+    std::string arch = hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.gcnArchName : "unknown";
+    arch = arch.substr(0, arch.find(':'));  // "gfx950" of "gfx950:sramecc+:xnack-"
+    for (char &c : arch)
+        if (c == ' ') c = '_';
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](int64_t v) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (uint64_t)((v >> (8 * i)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    };
+    for (const Plan &f : B.fields) {
+        mix(f.L);
+        mix(f.n);
+        mix(f.n_rings);
+        mix(f.max_fft_len);
+    }
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
+    return arch + ":p" + std::to_string(B.fields.empty() ? 0 : B.fields[0].precision) + ":f" +
+           std::to_string(B.fields.size()) + ":" + buf;
+}
+
+static bool tune_lookup(const std::string &path, const std::string &key, int c[4], double *ms) {
+    std::FILE *fp = std::fopen(path.c_str(), "r");
+    if (!fp) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, fp)) {
+        char k[256];
+        int v[4];
+        double t;
+        if (std::sscanf(line, "%255s %d %d %d %d %lf", k, &v[0], &v[1], &v[2], &v[3], &t) == 6 && key == k) {
+            for (int i = 0; i < 4; ++i) c[i] = v[i];
+            *ms = t;
+            found = true;  // the last entry for a key wins
+        }
+    }
+    std::fclose(fp);
+    return found;
+}
+
+static void tune_store(const std::string &path, const std::string &key, int nw, int fm, int lpt, int rnt,
+                       double ms) {
+    std::FILE *fp = std::fopen(path.c_str(), "a");
+    if (!fp) return;  // the cache is an optimisation: a file that cannot be written is skipped
+    std::fprintf(fp, "%s %d %d %d %d %.6f\n", key.c_str(), nw, fm, lpt, rnt, ms);
+    std::fclose(fp);
+}
+
 vsht_status vsht_batch_autotune(vsht_plan_t plan, const void *const *a, const void *const *b, void *const *T,
                                 void *const *a2, void *const *b2, int reps, double *best_ms, void *stream) {
     vsht_status s = check_batch(plan);
@@ -1288,6 +1378,15 @@ vsht_status vsht_batch_autotune(vsht_plan_t plan, const void *const *a, const vo
                               B.fields.size(), complex_bytes(B.fields[0]))) != VSHT_OK)
         return s;
     DeviceGuard guard(plan->p.device);
+    const std::string key = tune_key(B, plan->p.device);
+    if (!B.tune_cache.empty()) {
+        int c[4];
+        double ms = 0.0;
+        if (tune_lookup(B.tune_cache, key, c, &ms)) {
+            if (best_ms) *best_ms = ms;
+            return vsht_batch_set_config(plan, c[0], c[1], c[2], c[3]);
+        }
+    }
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
@@ -1328,6 +1427,7 @@ vsht_status vsht_batch_autotune(vsht_plan_t plan, const void *const *a, const vo
     (void)hipEventDestroy(e1);
     if (s != VSHT_OK) return s;
     if (best_ms) *best_ms = best;
+    if (!B.tune_cache.empty()) tune_store(B.tune_cache, key, bn, bm, bl, br, best);
     return vsht_batch_set_config(plan, bn, bm, bl, br);
 }
 

@@ -196,3 +196,21 @@ def test_binding_rejects_bad_batch_outputs():
         bp.adjoint(a, a, T=[torch.zeros(3, 10, dtype=torch.complex64).t()])
     with pytest.raises(ValueError):
         bp.forward([torch.zeros(10, 3, dtype=torch.complex64)], a=[torch.zeros(23, dtype=torch.complex64)])
+
+
+def test_opts_checked_on_host():
+    """nfft_eps outside [0, 1) and unknown flags are refused before any device work;
+    vsht_workspace_bytes(NULL) is 0."""
+    lib = B.load_library()
+    xyz, _ = vi.uniform_points(16, 5)
+    xyz = np.ascontiguousarray(xyz, np.float64)
+    h = ctypes.c_void_p()
+    for opts in (B.vsht_opts(0, -1, 0, 1.5, None), B.vsht_opts(0, -1, 0, -1e-3, None),
+                 B.vsht_opts(0, -1, 0, float("nan"), None), B.vsht_opts(0, -1, 8, 0.0, None)):
+        st = lib.vsht_plan(8, len(xyz), xyz.ctypes.data_as(ctypes.c_void_p), None, ctypes.byref(opts),
+                           ctypes.byref(h))
+        assert st == B.VSHT_EINVAL and not h.value
+    assert lib.vsht_workspace_bytes(None) == 0
+    # the C layout: three ints, the double at offset 16, the pointer at 24
+    assert ctypes.sizeof(B.vsht_opts) == 32
+    assert B.vsht_opts.nfft_eps.offset == 16 and B.vsht_opts.tune_cache.offset == 24

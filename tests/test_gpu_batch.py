@@ -128,3 +128,33 @@ def test_batch_autotune_and_field_times(torch, vsht):
     assert t0.shape == (len(Ls),) and np.all(t1 > t0) and np.min(t0) == 0.0
     print("[batch] autotuned", cfg, "%.3f ms" % ms, "latency us", np.round(t1 - t0, 1), flush=True)
     bp.close()
+
+
+def test_batch_tune_cache(torch, vsht, tmp_path):
+    """vsht_opts.tune_cache: the first autotune times the shapes and stores the
+    fastest; a batch of the same field shapes reads it back without timing and
+    takes the same shape; other shapes get their own entry."""
+    print("[case] batch tune cache", flush=True)
+    cache = str(tmp_path / "tune.txt")
+    Ls = [8, 12, 20]
+    grids = [vi.gl_grid(L) for L in Ls]
+
+    def tuned(Ls_, grids_):
+        bp = vsht.BatchPlan(Ls_, grids_, precision="fp32", tune_cache=cache)
+        coeffs = [vi.random_coeffs(L, 300 + i) for i, L in enumerate(Ls_)]
+        a = [dev(torch, c[0], bp.dtype) for c in coeffs]
+        b = [dev(torch, c[1], bp.dtype) for c in coeffs]
+        T, a2, b2 = bp.empty_fields(), bp.empty_coeffs(), bp.empty_coeffs()
+        ms = bp.autotune(a, b, T, a2, b2, reps=2)
+        cfg = bp.config()
+        bp.close()
+        return ms, cfg
+
+    ms1, cfg1 = tuned(Ls, grids)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and lines[0].split()[0].count(":") == 3
+    ms2, cfg2 = tuned(Ls, grids)
+    assert cfg2 == cfg1 and ms2 == pytest.approx(ms1, rel=1e-5)
+    assert len(open(cache).read().splitlines()) == 1  # read, not timed again
+    tuned(Ls[:2], grids[:2])
+    assert len(open(cache).read().splitlines()) == 2

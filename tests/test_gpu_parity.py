@@ -635,3 +635,42 @@ def test_misaligned_buffers_rejected(torch, vsht, precision):
     assert B.vsht_forward(plan._h, T.data_ptr(), a.data_ptr(), b.data_ptr(), None) == B.VSHT_OK
     torch.cuda.synchronize()
     plan.close()
+
+
+# ---------------------------------------------------------------------------
+# Plan options: VSHT_OPT_NO_FOLD (every ring its own pair) gives the oracle's
+# values like the folded plan; nfft_eps sets the scattered grid path's accuracy.
+# ---------------------------------------------------------------------------
+def test_no_fold_option(torch, vsht, orc):
+    L = 24
+    print_case("no fold", L)
+    xyz, w = vi.gl_grid(L)
+    plan = vsht.Plan(L, xyz, w, precision="fp64", fold=False)
+    info = plan.info()
+    assert info["kind"] == 0 and info["n_pairs"] == info["n_rings"] == L + 1
+    assert plan.workspace_bytes() > 0
+    a, b = vi.random_coeffs(L, 71)
+    T = run_adjoint(torch, plan, a, b)
+    e_adj = rel_l2(T, orc.adjoint(L, a, b, xyz))
+    Tr = vi.random_field(len(w), 72)
+    ga, gb = run_forward(torch, plan, Tr)
+    a_ref, b_ref = orc.forward(L, xyz, w, Tr)
+    e_fwd = rel_l2(np.concatenate([ga, gb]), np.concatenate([a_ref, b_ref]))
+    print("no fold L=%d adjoint %.3e forward %.3e" % (L, e_adj, e_fwd), flush=True)
+    assert e_adj < FP64_TOL and e_fwd < FP64_TOL
+    plan.close()
+
+
+@pytest.mark.parametrize("eps", [1e-5, 1e-9])
+def test_nfft_eps_option(torch, vsht, orc, eps):
+    L = 32
+    print_case("nfft_eps", eps)
+    xyz, _ = vi.uniform_points(3000, 73)
+    plan = vsht.Plan(L, xyz, None, precision="fp64", nfft_eps=eps)
+    assert plan.kind == "scattered" and plan.info()["nfft_grid"] > 0
+    a, b = vi.random_coeffs(L, 74)
+    e = rel_l2(run_adjoint(torch, plan, a, b), orc.adjoint(L, a, b, xyz))
+    print("nfft_eps %.0e adjoint %.3e" % (eps, e), flush=True)
+    assert e <= 10 * eps            # the accuracy asked for
+    assert e >= 1e-4 * eps          # and not the default's: the window did narrow
+    plan.close()
