@@ -196,7 +196,8 @@ def run_batched(torch, vsht, vi, args):
                            np.concatenate(coeffs[f])))
         p.close()
     bp.close()
-    log("batch: %.3f ms per batch, %.0f fields/s" % (sec * 1e3, len(Ls) / sec))
+    log("batch: %.3f ms per batch, %.0f fields/s, field latency p50 %.0f us, p99 %.0f us"
+        % (sec * 1e3, len(Ls) / sec, np.percentile(lat, 50), np.percentile(lat, 99)))
     return {"fields": len(Ls), "L_min": min(Ls), "L_max": max(Ls), "L_mean": round(float(np.mean(Ls)), 1),
             "precision": "fp32", "ms_per_batch": round(sec * 1e3, 4),
             "fields_per_s": round(len(Ls) / sec, 1),

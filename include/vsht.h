@@ -278,8 +278,13 @@ vsht_status vsht_get_stage_times(vsht_plan_t plan, double *ms, int64_t *count, i
  *                   analysis launch at the widest workgroup; 0: one per tile
  *                   count), lpt (1: longest work items first), ring_nt (256 or
  *                   512 threads per ring workgroup; rings whose DFT is longer
- *                   than 2048 always take 512).  Results do not depend on the
- *                   shape.  Waits for the device.
+ *                   than 2048 always take 512), chains (1: with three fields or
+ *                   more, the fields are split by cost (L+1)^3 into up to three
+ *                   classes, the cheapest up to 1/8 of the total, the next up to
+ *                   1/2, the rest, and each class runs its stages as a parallel
+ *                   branch of the graph, so that small fields finish early; 0:
+ *                   all fields in one sequence of stages).  Results do not
+ *                   depend on the shape.  Waits for the device.
  * vsht_batch_autotune  times every shape on the caller's buffers (roundtrip,
  *                   `reps` replays each), keeps the fastest and writes its time
  *                   per roundtrip in milliseconds to *best_ms (may be NULL).
@@ -297,8 +302,10 @@ vsht_status vsht_batch_forward(vsht_plan_t plan, const void *const *T, void *con
                                void *stream);
 vsht_status vsht_batch_roundtrip(vsht_plan_t plan, const void *const *a, const void *const *b, void *const *T,
                                  void *const *a2, void *const *b2, void *stream);
-vsht_status vsht_batch_set_config(vsht_plan_t plan, int adj_nw, int fwd_merge, int lpt, int ring_nt);
-vsht_status vsht_batch_get_config(vsht_plan_t plan, int *adj_nw, int *fwd_merge, int *lpt, int *ring_nt);
+vsht_status vsht_batch_set_config(vsht_plan_t plan, int adj_nw, int fwd_merge, int lpt, int ring_nt,
+                                  int chains);
+vsht_status vsht_batch_get_config(vsht_plan_t plan, int *adj_nw, int *fwd_merge, int *lpt, int *ring_nt,
+                                  int *chains);
 vsht_status vsht_batch_autotune(vsht_plan_t plan, const void *const *a, const void *const *b, void *const *T,
                                 void *const *a2, void *const *b2, int reps, double *best_ms, void *stream);
 vsht_status vsht_batch_field_times(vsht_plan_t plan, double *start_us, double *end_us);

@@ -94,9 +94,9 @@ def load_library(path=LIB_PATH):
         getattr(lib, name).restype = ci
     lib.vsht_batch_roundtrip.argtypes = [vp, pp, pp, pp, pp, pp, vp]
     lib.vsht_batch_roundtrip.restype = ci
-    lib.vsht_batch_set_config.argtypes = [vp, ci, ci, ci, ci]
+    lib.vsht_batch_set_config.argtypes = [vp, ci, ci, ci, ci, ci]
     lib.vsht_batch_set_config.restype = ci
-    lib.vsht_batch_get_config.argtypes = [vp, pi, pi, pi, pi]
+    lib.vsht_batch_get_config.argtypes = [vp, pi, pi, pi, pi, pi]
     lib.vsht_batch_get_config.restype = ci
     lib.vsht_batch_autotune.argtypes = [vp, pp, pp, pp, pp, pp, ci, pd, vp]
     lib.vsht_batch_autotune.restype = ci
@@ -485,15 +485,16 @@ class BatchPlan:
         return best.value
 
     def config(self):
-        x, y, z, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        x, y, z, r, c = (ctypes.c_int() for _ in range(5))
         _raise_for(load_library().vsht_batch_get_config(self._h, ctypes.byref(x), ctypes.byref(y),
-                                                        ctypes.byref(z), ctypes.byref(r)),
+                                                        ctypes.byref(z), ctypes.byref(r), ctypes.byref(c)),
                    "vsht_batch_get_config")
-        return {"adj_nw": x.value, "fwd_merge": y.value, "lpt": z.value, "ring_nt": r.value}
+        return {"adj_nw": x.value, "fwd_merge": y.value, "lpt": z.value, "ring_nt": r.value,
+                "chains": c.value}
 
-    def set_config(self, adj_nw=4, fwd_merge=0, lpt=1, ring_nt=256):
+    def set_config(self, adj_nw=4, fwd_merge=0, lpt=1, ring_nt=256, chains=1):
         _raise_for(load_library().vsht_batch_set_config(self._h, int(adj_nw), int(fwd_merge), int(lpt),
-                                                        int(ring_nt)), "vsht_batch_set_config")
+                                                        int(ring_nt), int(chains)), "vsht_batch_set_config")
 
     def field_times(self):
         """(start_us, end_us) per field of the last call, device wall clock."""

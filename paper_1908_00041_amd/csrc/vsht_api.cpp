@@ -1281,7 +1281,8 @@ vsht_status vsht_batch_roundtrip(vsht_plan_t plan, const void *const *a, const v
     return batch_run(B, 3, (hipStream_t)stream);
 }
 
-vsht_status vsht_batch_set_config(vsht_plan_t plan, int adj_nw, int fwd_merge, int lpt, int ring_nt) {
+vsht_status vsht_batch_set_config(vsht_plan_t plan, int adj_nw, int fwd_merge, int lpt, int ring_nt,
+                                  int chains) {
     vsht_status s = check_batch(plan);
     if (s != VSHT_OK) return s;
     if (adj_nw != 1 && adj_nw != 2 && adj_nw != 4) return fail(VSHT_EINVAL, "adj_nw must be 1, 2 or 4");
@@ -1296,26 +1297,30 @@ vsht_status vsht_batch_set_config(vsht_plan_t plan, int adj_nw, int fwd_merge, i
         c.fwd_merge = fwd_merge ? 1 : 0;
         c.lpt = lpt ? 1 : 0;
         c.ring_nt = ring_nt;
+        c.chains = chains ? 1 : 0;
         e = batch_configure(B.st, c);
     }
     return e == hipSuccess ? VSHT_OK : hip_fail(e, "batch configure");
 }
 
-vsht_status vsht_batch_get_config(vsht_plan_t plan, int *adj_nw, int *fwd_merge, int *lpt, int *ring_nt) {
+vsht_status vsht_batch_get_config(vsht_plan_t plan, int *adj_nw, int *fwd_merge, int *lpt, int *ring_nt,
+                                  int *chains) {
     vsht_status s = check_batch(plan);
     if (s != VSHT_OK) return s;
-    if (!adj_nw || !fwd_merge || !lpt || !ring_nt) return fail(VSHT_EINVAL, "NULL argument");
+    if (!adj_nw || !fwd_merge || !lpt || !ring_nt || !chains) return fail(VSHT_EINVAL, "NULL argument");
     const BatchConfig c = batch_config(plan->batch->st);
     *adj_nw = c.adj_nw;
     *fwd_merge = c.fwd_merge;
     *lpt = c.lpt;
     *ring_nt = c.ring_nt;
+    *chains = c.chains;
     return VSHT_OK;
 }
 
-// Autotune cache: one line per batch, "<key> adj_nw fwd_merge lpt ring_nt ms".  The
-// key names the device architecture, the precision, the field count and an FNV-1a
-// digest of every field's (L, points, rings, longest stored DFT length).
+// Autotune cache: one line per batch, "<key> adj_nw fwd_merge lpt ring_nt chains ms".
+// The key names the line format ("b2"), the device architecture, the precision, the
+// field count and an FNV-1a digest of every field's (L, points, rings, longest stored
+// DFT length); lines of another format never match it.
 static std::string tune_key(const BatchPlan &B, int dev) {
     hipDeviceProp_t prop{};
     std::string arch = hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.gcnArchName : "unknown";
@@ -1337,21 +1342,22 @@ static std::string tune_key(const BatchPlan &B, int dev) {
     }
     char buf[64];
     std::snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
-    return arch + ":p" + std::to_string(B.fields.empty() ? 0 : B.fields[0].precision) + ":f" +
+    return "b2:" + arch + ":p" + std::to_string(B.fields.empty() ? 0 : B.fields[0].precision) + ":f" +
            std::to_string(B.fields.size()) + ":" + buf;
 }
 
-static bool tune_lookup(const std::string &path, const std::string &key, int c[4], double *ms) {
+static bool tune_lookup(const std::string &path, const std::string &key, int c[5], double *ms) {
     std::FILE *fp = std::fopen(path.c_str(), "r");
     if (!fp) return false;
     char line[512];
     bool found = false;
     while (std::fgets(line, sizeof line, fp)) {
         char k[256];
-        int v[4];
+        int v[5];
         double t;
-        if (std::sscanf(line, "%255s %d %d %d %d %lf", k, &v[0], &v[1], &v[2], &v[3], &t) == 6 && key == k) {
-            for (int i = 0; i < 4; ++i) c[i] = v[i];
+        if (std::sscanf(line, "%255s %d %d %d %d %d %lf", k, &v[0], &v[1], &v[2], &v[3], &v[4], &t) == 7 &&
+            key == k) {
+            for (int i = 0; i < 5; ++i) c[i] = v[i];
             *ms = t;
             found = true;  // the last entry for a key wins
         }
@@ -1361,10 +1367,10 @@ static bool tune_lookup(const std::string &path, const std::string &key, int c[4
 }
 
 static void tune_store(const std::string &path, const std::string &key, int nw, int fm, int lpt, int rnt,
-                       double ms) {
+                       int ch, double ms) {
     std::FILE *fp = std::fopen(path.c_str(), "a");
     if (!fp) return;  // the cache is an optimisation: a file that cannot be written is skipped
-    std::fprintf(fp, "%s %d %d %d %d %.6f\n", key.c_str(), nw, fm, lpt, rnt, ms);
+    std::fprintf(fp, "%s %d %d %d %d %d %.9g\n", key.c_str(), nw, fm, lpt, rnt, ch, ms);
     std::fclose(fp);
 }
 
@@ -1380,11 +1386,11 @@ vsht_status vsht_batch_autotune(vsht_plan_t plan, const void *const *a, const vo
     DeviceGuard guard(plan->p.device);
     const std::string key = tune_key(B, plan->p.device);
     if (!B.tune_cache.empty()) {
-        int c[4];
+        int c[5];
         double ms = 0.0;
         if (tune_lookup(B.tune_cache, key, c, &ms)) {
             if (best_ms) *best_ms = ms;
-            return vsht_batch_set_config(plan, c[0], c[1], c[2], c[3]);
+            return vsht_batch_set_config(plan, c[0], c[1], c[2], c[3], c[4]);
         }
     }
     hipStream_t st = (hipStream_t)stream;
@@ -1393,14 +1399,15 @@ vsht_status vsht_batch_autotune(vsht_plan_t plan, const void *const *a, const vo
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     float best = -1.f;
-    int bn = 4, bm = 0, bl = 1, br = 256;
+    int bn = 4, bm = 0, bl = 1, br = 256, bc = 1;
     const int nws[1] = {4};  // the synthesis shape is fixed (four waves); adj_nw has no effect
     for (int i = 0; i < 1 && s == VSHT_OK; ++i)
         for (int fm = 0; fm < 2 && s == VSHT_OK; ++fm)
             for (int lpt = 0; lpt < 2 && s == VSHT_OK; ++lpt)
-            for (int rnt : {256, 512}) {
+            for (int rnt : {256, 512})
+            for (int ch = 0; ch < 2; ++ch) {
                 if (s != VSHT_OK) break;
-                s = vsht_batch_set_config(plan, nws[i], fm, lpt, rnt);
+                s = vsht_batch_set_config(plan, nws[i], fm, lpt, rnt, ch);
                 if (s == VSHT_OK) s = vsht_batch_roundtrip(plan, a, b, T, a2, b2, stream);  // capture + warm
                 if (s != VSHT_OK) break;
                 e = hipEventRecord(e0, st);
@@ -1421,14 +1428,15 @@ vsht_status vsht_batch_autotune(vsht_plan_t plan, const void *const *a, const vo
                     bm = fm;
                     bl = lpt;
                     br = rnt;
+                    bc = ch;
                 }
             }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (s != VSHT_OK) return s;
     if (best_ms) *best_ms = best;
-    if (!B.tune_cache.empty()) tune_store(B.tune_cache, key, bn, bm, bl, br, best);
-    return vsht_batch_set_config(plan, bn, bm, bl, br);
+    if (!B.tune_cache.empty()) tune_store(B.tune_cache, key, bn, bm, bl, br, bc, best);
+    return vsht_batch_set_config(plan, bn, bm, bl, br, bc);
 }
 
 vsht_status vsht_batch_field_times(vsht_plan_t plan, double *start_us, double *end_us) {

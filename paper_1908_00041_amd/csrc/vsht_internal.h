@@ -322,7 +322,9 @@ struct BatchConfig {
     int fwd_merge = 0;  // 1: one analysis launch at the widest shape; 0: one launch per tile count
     int lpt = 1;        // 1: work items longest first; 0: field by field
     int ring_nt = 256;  // threads per ring workgroup (256 or 512; rings longer than 2048 always 512)
+    int chains = 1;     // 1: size classes of fields run as parallel chains; 0: one sequence
 };
+constexpr int kBatchChains = 3;
 struct BatchState;
 hipError_t batch_create(const std::vector<const Plan *> &fields, BatchState **out);
 void batch_destroy(BatchState *b);

@@ -3700,13 +3700,22 @@ struct BatchState {
     std::vector<unsigned char> h_prep, h_ladj, h_radj, h_rfwd, h_lfwd, h_rec;
     void *d_prep = nullptr, *d_ladj = nullptr, *d_radj = nullptr, *d_rfwd = nullptr,
          *d_lfwd = nullptr, *d_rec = nullptr;
-    // work lists: launches in execution order (adjoint stages, then forward)
+    // work lists: launches in execution order (adjoint stages, then forward), per chain
     struct Launch {
         int stage;
         int nw;
         int64_t off, cnt;
         size_t lds;
+        int chain;
     };
+    // Size-class chains: the fields are split by cost into up to kBatchChains
+    // classes, each running its whole stage sequence on its own stream (parallel
+    // branches of the captured graph), so that small fields do not wait for the
+    // stages of the large ones.
+    std::vector<int> chain_of;  // per field
+    int nchains = 1;
+    hipStream_t cs[kBatchChains] = {};
+    hipEvent_t fork = nullptr, join[kBatchChains] = {};
     std::vector<WorkItem> work;
     std::vector<Launch> launches;
     WorkItem *d_work = nullptr;
@@ -3750,7 +3759,33 @@ hipError_t batch_create(const std::vector<const Plan *> &fields, BatchState **ou
     b->f = fields;
     b->precision = fields.empty() ? VSHT_FP64 : fields[0]->precision;
     b->rsz = b->precision == VSHT_FP64 ? 8 : 4;
-    hipError_t e = b->precision == VSHT_FP64 ? batch_alloc_args<double>(b) : batch_alloc_args<float>(b);
+    // chains: cost (~L^3) classes of the fields; the first holds the cheapest fields up to
+    // 1/8 of the batch's work, the second up to 1/2, the third the rest
+    const int F = (int)fields.size();
+    b->chain_of.assign(F, 0);
+    if (F >= kBatchChains) {
+        std::vector<int> order(F);
+        for (int i = 0; i < F; ++i) order[i] = i;
+        auto cost = [&](int i) { return std::pow((double)fields[i]->L + 1.0, 3.0); };
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) < cost(y); });
+        double total = 0.0, acc = 0.0;
+        for (int i = 0; i < F; ++i) total += cost(i);
+        for (int i : order) {
+            acc += cost(i);
+            b->chain_of[i] = acc <= total / 8 ? 0 : acc <= total / 2 ? 1 : 2;
+        }
+        b->nchains = 1 + *std::max_element(b->chain_of.begin(), b->chain_of.end());
+    }
+    hipError_t e = hipSuccess;
+    if (b->nchains > 1) {
+        e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        for (int c = 0; c < b->nchains && e == hipSuccess; ++c) {
+            e = hipStreamCreateWithFlags(&b->cs[c], hipStreamNonBlocking);  // default priority
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[c], hipEventDisableTiming);
+        }
+    }
+    if (e == hipSuccess)
+        e = b->precision == VSHT_FP64 ? batch_alloc_args<double>(b) : batch_alloc_args<float>(b);
     if (e == hipSuccess) e = batch_configure(b, BatchConfig{});
     if (e != hipSuccess) {
         batch_destroy(b);
@@ -3762,6 +3797,11 @@ hipError_t batch_create(const std::vector<const Plan *> &fields, BatchState **ou
 
 void batch_destroy(BatchState *b) {
     if (!b) return;
+    for (int c = 0; c < kBatchChains; ++c) {
+        if (b->cs[c]) (void)hipStreamDestroy(b->cs[c]);
+        if (b->join[c]) (void)hipEventDestroy(b->join[c]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
     void *ptrs[] = {b->d_prep, b->d_ladj, b->d_radj, b->d_rfwd, b->d_lfwd, b->d_rec, b->d_work, b->d_stamp};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -3786,92 +3826,103 @@ hipError_t batch_configure(BatchState *b, const BatchConfig &cfg) {
         WorkItem w;
         double cost;
     };
+    const int nchains = cfg.chains ? b->nchains : 1;
+    int chain = 0;
     auto emit = [&](int stage, int nw, std::vector<Item> &items, size_t lds) {
         if (items.empty()) return;
         if (cfg.lpt)
             std::stable_sort(items.begin(), items.end(),
                              [](const Item &x, const Item &y) { return x.cost > y.cost; });
-        BatchState::Launch l{stage, nw, (int64_t)b->work.size(), (int64_t)items.size(), lds};
+        BatchState::Launch l{stage, nw, (int64_t)b->work.size(), (int64_t)items.size(), lds, chain};
         for (auto &it : items) b->work.push_back(it.w);
         b->launches.push_back(l);
     };
     const int F = (int)b->f.size();
     std::vector<Item> items;
-    // prep
-    for (int i = 0; i < F; ++i) {
-        const int L = b->f[i]->L;
-        for (int by = 0; by * kTM <= L; ++by)
-            for (int bx = 0; bx * kTL < L + 2; ++bx)
-                if (!(by * kTM > bx * kTL + kTL - 1)) items.push_back({{i, bx, by, 0}, 1.0});
-    }
-    emit(BS_PREP, 4, items, 0);
-    items.clear();
-    // Legendre synthesis: the single plans' workgroups of every field, one launch per
-    // workgroup width (the vector-unit form sizes its workgroups to the field's pairs)
-    for (int nw = 1; nw <= 4; ++nw) {
+    for (chain = 0; chain < nchains; ++chain) {
+        // the fields of this chain
+        auto skip = [&](int i) { return nchains > 1 && b->chain_of[i] != chain; };
+        // prep
         for (int i = 0; i < F; ++i) {
-            const Plan &p = *b->f[i];
-            if (adj_waves(pairs_in_tiles(p), nprod) != nw) continue;
-            const int cols = adj_columns(pairs_in_tiles(p), nprod);
-            for (int x = 0; x < cols; ++x)
-                for (int m = 0; m <= p.L; ++m) items.push_back({{i, x, m, 0}, (double)(p.L + 2 - m) * nw});
+            if (skip(i)) continue;
+            const int L = b->f[i]->L;
+            for (int by = 0; by * kTM <= L; ++by)
+                for (int bx = 0; bx * kTL < L + 2; ++bx)
+                    if (!(by * kTM > bx * kTL + kTL - 1)) items.push_back({{i, bx, by, 0}, 1.0});
         }
-        emit(BS_LEG_ADJ, nw, items,
-             nprod == 3 ? adj_lds_block<3>() : nprod == 6 ? adj_lds_block<6>() : adj_lds_block<0>());
+        emit(BS_PREP, 4, items, 0);
         items.clear();
-    }
-    for (int i = 0; i < F; ++i)
-        if (b->f[i]->eq_ring >= 0 && nprod != 0)  // the vector-unit synthesis forms the equator itself
-            for (int m = 0; m <= b->f[i]->L; ++m) items.push_back({{i, m, 0, 0}, (double)(b->f[i]->L + 2 - m)});
-    emit(BS_EQUATOR, 4, items, 0);
-    items.clear();
-    // ring stages: one launch per class of stored DFT length (its LDS size) and
-    // workgroup width; fields whose length exceeds the narrow width's limit use 512
-    const int64_t bounds[] = {256, 512, 1024, 2048, 1 << 30};
-    for (int dir = 0; dir < 2; ++dir) {
-        int64_t lo = 0;
-        for (int64_t hi : bounds) {
-            for (int nt : {kRingNTSmall, kRingNT}) {
-                int64_t maxlen = 0;
-                for (int i = 0; i < F; ++i) {
-                    const Plan &p = *b->f[i];
-                    if (p.max_fft_len <= lo || p.max_fft_len > hi) continue;
-                    const int want = (cfg.ring_nt == kRingNTSmall && p.ring_nt_min == kRingNTSmall &&
-                                      p.max_fft_len <= kMaxLenSmallRing)
-                                         ? kRingNTSmall : kRingNT;
-                    if (want != nt) continue;
-                    maxlen = std::max(maxlen, p.max_fft_len);
-                    for (int r = 0; r < p.n_rings; ++r) items.push_back({{i, r, 0, 0}, (double)p.max_fft_len});
-                }
-                emit(dir == 0 ? BS_RING_ADJ : BS_RING_FWD, nt / 64, items, ring_lds_bytes_len(maxlen, rsz));
-                items.clear();
+        // Legendre synthesis: the single plans' workgroups of every field, one launch per
+        // workgroup width (the vector-unit form sizes its workgroups to the field's pairs)
+        for (int nw = 1; nw <= 4; ++nw) {
+            for (int i = 0; i < F; ++i) {
+                const Plan &p = *b->f[i];
+                if (skip(i) || adj_waves(pairs_in_tiles(p), nprod) != nw) continue;
+                const int cols = adj_columns(pairs_in_tiles(p), nprod);
+                for (int x = 0; x < cols; ++x)
+                    for (int m = 0; m <= p.L; ++m) items.push_back({{i, x, m, 0}, (double)(p.L + 2 - m) * nw});
             }
-            lo = hi;
+            emit(BS_LEG_ADJ, nw, items,
+                 nprod == 3 ? adj_lds_block<3>() : nprod == 6 ? adj_lds_block<6>() : adj_lds_block<0>());
+            items.clear();
         }
-    }
-    // Legendre analysis: one workgroup per (field, m) holding all of the field's
-    // tiles; fields grouped by tile count, or merged into the widest shape
-    int maxt = 1;
-    for (int i = 0; i < F; ++i) maxt = std::max(maxt, std::max(1, tiles_of(*b->f[i])));
-    for (int nw = 1; nw <= maxt; ++nw) {
+        for (int i = 0; i < F; ++i)
+            if (!skip(i) && b->f[i]->eq_ring >= 0 && nprod != 0)  // the vector-unit synthesis forms the equator itself
+                for (int m = 0; m <= b->f[i]->L; ++m) items.push_back({{i, m, 0, 0}, (double)(b->f[i]->L + 2 - m)});
+        emit(BS_EQUATOR, 4, items, 0);
+        items.clear();
+        // ring stages: one launch per class of stored DFT length (its LDS size) and
+        // workgroup width; fields whose length exceeds the narrow width's limit use 512
+        const int64_t bounds[] = {256, 512, 1024, 2048, 1 << 30};
+        for (int dir = 0; dir < 2; ++dir) {
+            int64_t lo = 0;
+            for (int64_t hi : bounds) {
+                for (int nt : {kRingNTSmall, kRingNT}) {
+                    int64_t maxlen = 0;
+                    for (int i = 0; i < F; ++i) {
+                        const Plan &p = *b->f[i];
+                        if (skip(i) || p.max_fft_len <= lo || p.max_fft_len > hi) continue;
+                        const int want = (cfg.ring_nt == kRingNTSmall && p.ring_nt_min == kRingNTSmall &&
+                                          p.max_fft_len <= kMaxLenSmallRing)
+                                             ? kRingNTSmall : kRingNT;
+                        if (want != nt) continue;
+                        maxlen = std::max(maxlen, p.max_fft_len);
+                        for (int r = 0; r < p.n_rings; ++r) items.push_back({{i, r, 0, 0}, (double)p.max_fft_len});
+                    }
+                    emit(dir == 0 ? BS_RING_ADJ : BS_RING_FWD, nt / 64, items, ring_lds_bytes_len(maxlen, rsz));
+                    items.clear();
+                }
+                lo = hi;
+            }
+        }
+        // Legendre analysis: one workgroup per (field, m) holding all of the field's
+        // tiles; fields grouped by tile count, or merged into the widest shape
+        int maxt = 1;
+        for (int i = 0; i < F; ++i)
+            if (!skip(i)) maxt = std::max(maxt, std::max(1, tiles_of(*b->f[i])));
+        for (int nw = 1; nw <= maxt; ++nw) {
+            for (int i = 0; i < F; ++i) {
+                if (skip(i)) continue;
+                const Plan &p = *b->f[i];
+                const int nt = std::max(1, tiles_of(p));
+                if (!cfg.fwd_merge && nt != nw) continue;
+                if (cfg.fwd_merge && nw != maxt) continue;
+                for (int m = 0; m <= p.L; ++m) items.push_back({{i, m, 0, 0}, (double)(p.L + 2 - m) * nt});
+            }
+            emit(BS_LEG_FWD, nw, items, leg_fwd_lds(nw, rsz));
+            items.clear();
+        }
+        // recombine
         for (int i = 0; i < F; ++i) {
-            const Plan &p = *b->f[i];
-            const int nt = std::max(1, tiles_of(p));
-            if (!cfg.fwd_merge && nt != nw) continue;
-            if (cfg.fwd_merge && nw != maxt) continue;
-            for (int m = 0; m <= p.L; ++m) items.push_back({{i, m, 0, 0}, (double)(p.L + 2 - m) * nt});
+            if (skip(i)) continue;
+            const int L = b->f[i]->L;
+            for (int by = 0; by * kTM <= L; ++by)
+                for (int bx = 0; bx * kTL < L; ++bx)
+                    if (!(by * kTM > 1 + bx * kTL + kTL - 1)) items.push_back({{i, bx, by, 0}, 1.0});
         }
-        emit(BS_LEG_FWD, nw, items, leg_fwd_lds(nw, rsz));
+        emit(BS_RECOMBINE, 4, items, 0);
         items.clear();
     }
-    // recombine
-    for (int i = 0; i < F; ++i) {
-        const int L = b->f[i]->L;
-        for (int by = 0; by * kTM <= L; ++by)
-            for (int bx = 0; bx * kTL < L; ++bx)
-                if (!(by * kTM > 1 + bx * kTL + kTL - 1)) items.push_back({{i, bx, by, 0}, 1.0});
-    }
-    emit(BS_RECOMBINE, 4, items, 0);
     // device copies
     const size_t need = b->work.size();
     if (need > b->d_work_cap) {
@@ -3934,11 +3985,19 @@ hipError_t batch_bind_forward(BatchState *b, const void *const *T, void *const *
 }
 
 template <typename real, int kBf16>
-static hipError_t batch_launch_impl(const BatchState *b, int dirs, hipStream_t st) {
+static hipError_t batch_launch_impl(const BatchState *b, int dirs, hipStream_t st0) {
+    // chains fork from st0 onto their own streams and join back into it
+    const bool forked = b->cfg.chains && b->nchains > 1;
+    if (forked) {
+        hipError_t e = hipEventRecord(b->fork, st0);
+        for (int c = 0; c < b->nchains && e == hipSuccess; ++c) e = hipStreamWaitEvent(b->cs[c], b->fork, 0);
+        if (e != hipSuccess) return e;
+    }
     for (const auto &l : b->launches) {
         const bool adj = stage_is_adjoint(l.stage);
         if (adj && !(dirs & 1)) continue;
         if (!adj && !(dirs & 2)) continue;
+        hipStream_t st = forked ? b->cs[l.chain] : st0;
         const WorkItem *w = b->d_work + l.off;
         unsigned long long *stamp = b->d_stamp + l.off;
         const dim3 grid((unsigned)l.cnt);
@@ -3983,6 +4042,12 @@ static hipError_t batch_launch_impl(const BatchState *b, int dirs, hipStream_t s
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    if (forked)
+        for (int c = 0; c < b->nchains; ++c) {
+            hipError_t e = hipEventRecord(b->join[c], b->cs[c]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st0, b->join[c], 0);
+            if (e != hipSuccess) return e;
+        }
     return hipSuccess;
 }
 

@@ -145,7 +145,7 @@ def test_batch_calls_reject_null_plan():
     assert lib.vsht_batch_roundtrip(None, None, None, None, None, None, None) == B.VSHT_EINVAL
     assert lib.vsht_batch_adjoint(None, None, None, None, None) == B.VSHT_EINVAL
     assert lib.vsht_batch_forward(None, None, None, None, None) == B.VSHT_EINVAL
-    assert lib.vsht_batch_set_config(None, 4, 0, 1, 256) == B.VSHT_EINVAL
+    assert lib.vsht_batch_set_config(None, 4, 0, 1, 256, 1) == B.VSHT_EINVAL
     assert lib.vsht_batch_field_times(None, None, None) == B.VSHT_EINVAL
 
 

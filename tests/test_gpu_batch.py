@@ -68,8 +68,10 @@ def test_batch_equals_single_plans(torch, vsht, precision):
     print("[case] batch vs single plans", precision, LS_MIXED, flush=True)
     bp, grids, coeffs, a, b = make_batch(torch, vsht, LS_MIXED, precision)
     ref = single_results(torch, vsht, LS_MIXED, grids, a, b, precision)
-    for cfg in [dict(adj_nw=4, fwd_merge=0, lpt=1, ring_nt=256), dict(adj_nw=1, fwd_merge=1, lpt=0, ring_nt=512),
-                dict(adj_nw=2, fwd_merge=1, lpt=1, ring_nt=256)]:
+    for cfg in [dict(adj_nw=4, fwd_merge=0, lpt=1, ring_nt=256, chains=1),
+                dict(adj_nw=1, fwd_merge=1, lpt=0, ring_nt=512, chains=0),
+                dict(adj_nw=2, fwd_merge=1, lpt=1, ring_nt=256, chains=0),
+                dict(adj_nw=4, fwd_merge=1, lpt=0, ring_nt=512, chains=1)]:
         bp.set_config(**cfg)
         assert bp.config() == cfg
         T, a2, b2 = bp.roundtrip(a, b)
@@ -119,7 +121,7 @@ def test_batch_autotune_and_field_times(torch, vsht):
     ms = bp.autotune(a, b, T, a2, b2, reps=2)
     assert ms > 0
     cfg = bp.config()
-    assert cfg["adj_nw"] in (1, 2, 4)
+    assert cfg["adj_nw"] in (1, 2, 4) and cfg["chains"] in (0, 1)
     bp.roundtrip(a, b, T, a2, b2)
     t0, t1 = bp.field_times()
     torch.cuda.synchronize()
@@ -152,7 +154,8 @@ def test_batch_tune_cache(torch, vsht, tmp_path):
 
     ms1, cfg1 = tuned(Ls, grids)
     lines = open(cache).read().splitlines()
-    assert len(lines) == 1 and lines[0].split()[0].count(":") == 3
+    assert len(lines) == 1 and lines[0].startswith("b2:") and lines[0].split()[0].count(":") == 4
+    assert len(lines[0].split()) == 7
     ms2, cfg2 = tuned(Ls, grids)
     assert cfg2 == cfg1 and ms2 == pytest.approx(ms1, rel=1e-5)
     assert len(open(cache).read().splitlines()) == 1  # read, not timed again
