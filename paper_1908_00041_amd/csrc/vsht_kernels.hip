@@ -57,6 +57,42 @@ __device__ __forceinline__ T ld_const(const T *p) {
 #endif
 }
 
+// Accesses of device memory through a pointer the compiler cannot trace to a
+// kernel argument (one that passed through integers, readfirstlane, or was
+// loaded from a table) become flat instructions, and flat instructions count
+// against the LDS wait counter too: every wait for an LDS access then also
+// waits for the global loads in flight.  gld / gst access such a pointer as
+// global memory (all of the library's buffers are).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define VSHT_GLOBAL_AS __attribute__((address_space(1)))
+#else
+#define VSHT_GLOBAL_AS
+#endif
+// (Scalars only: a structure copy becomes a memcpy whose source loses the cast;
+// complex values go through a two-element vector.)
+template <typename T>
+__device__ __forceinline__ T gld(const T *p) {
+    return *(const VSHT_GLOBAL_AS T *)p;
+}
+template <typename T>
+__device__ __forceinline__ void gst(T *p, T v) {
+    *(VSHT_GLOBAL_AS T *)p = v;
+}
+template <typename real>
+__device__ __forceinline__ C2<real> gld(const C2<real> *p) {
+    typedef real V __attribute__((ext_vector_type(2)));
+    const V v = *(const VSHT_GLOBAL_AS V *)p;
+    return {v.x, v.y};
+}
+template <typename real>
+__device__ __forceinline__ void gst(C2<real> *p, C2<real> c) {
+    typedef real V __attribute__((ext_vector_type(2)));
+    V v;
+    v.x = c.x;
+    v.y = c.y;
+    *(VSHT_GLOBAL_AS V *)p = v;
+}
+
 // The same for a structure read through a pointer taken from another table,
 // made wave-uniform dword by dword (keeps its fields in scalar registers).
 template <typename T>
@@ -65,7 +101,10 @@ __device__ __forceinline__ T ld_uniform(const T *p) {
     struct Words {
         uint32_t d[sizeof(T) / 4];
     };
-    Words w = *reinterpret_cast<const Words *>(p);
+    Words w;
+    const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w.d[i] = gld(q + i);
 #pragma unroll
     for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w.d[i] = __builtin_amdgcn_readfirstlane(w.d[i]);
     return __builtin_bit_cast(T, w);
@@ -189,6 +228,8 @@ __global__ __launch_bounds__(64) void k_leg_start(const double *__restrict__ pai
 // A lane's start in a Legendre stage: block (kStartNever for lanes without a
 // ring pair) and state.  The lane's recurrence holds (0, 0) until its block
 // boundary, where it takes the state.
+__device__ __forceinline__ PairDesc ld_pair(const PairDesc *p) { return {gld(&p->rn), gld(&p->rs)}; }
+
 struct LaneStart {
     double q1, q2;
     int blk;
@@ -197,10 +238,9 @@ __device__ __forceinline__ LaneStart lane_start(const LegStart *__restrict__ sta
                                                 size_t idx, bool valid) {
     LaneStart r{0.0, 0.0, kStartNever};
     if (valid) {
-        const LegStart v = start[idx];
-        r.q1 = v.q1;
-        r.q2 = v.q2;
-        r.blk = sblk[idx];
+        r.q1 = gld(&start[idx].q1);
+        r.q2 = gld(&start[idx].q2);
+        r.blk = gld(sblk + idx);
     }
     return r;
 }
@@ -265,7 +305,8 @@ __device__ __forceinline__ C2<real> cadd_i(C2<real> a, C2<real> b, real s) {
     return {a.x - s * b.y, a.y + s * b.x};
 }
 __device__ __forceinline__ CD tw_at(const double *twn, int k, bool inv) {
-    return {twn[2 * k], inv ? -twn[2 * k + 1] : twn[2 * k + 1]};
+    const double re = gld(twn + 2 * k), im = gld(twn + 2 * k + 1);
+    return {re, inv ? -im : im};
 }
 
 // Thread index hidden from loop-invariant code motion: every FFT stage is
@@ -842,22 +883,22 @@ __device__ __forceinline__ void ring_fwd_body(const RingArgs<real> &A, int r, un
     const double *twn = A.tw + 2 * ld_const(&fdp->tw_offset);
     for (int j = threadIdx.x; j < n; j += NT) {
         // e^{i phi_j} = e^{i phi_0} conj(e^{-2 pi i j / n})
-        const double er = twn[2 * j], ei = -twn[2 * j + 1];
+        const double er = gld(twn + 2 * j), ei = -gld(twn + 2 * j + 1);
         const real c = (real)(rd.c0 * er - rd.s0 * ei);
         const real sn = (real)(rd.s0 * er + rd.c0 * ei);
         const int64_t k = rd.offset + j;
         real w = 1;
-        if (A.weighted) w = (real)(rd.uniform_w ? rd.w : A.weights[k]);
+        if (A.weighted) w = (real)(rd.uniform_w ? rd.w : gld(A.weights + k));
         const real z = (real)rd.z, s = (real)rd.s;
         C2<real> th, ph;
         if (A.scalar) {
             // the scalar analysis of f is the theta analysis of T_theta = s f (the
             // output stage divides by s again)
-            const C2<real> f = A.Tin[k];
+            const C2<real> f = gld(A.Tin + k);
             th = {w * s * f.x, w * s * f.y};
             ph = {0, 0};
         } else {
-            const C2<real> t1 = A.Tin[3 * k], t2 = A.Tin[3 * k + 1], t3 = A.Tin[3 * k + 2];
+            const C2<real> t1 = gld(A.Tin + 3 * k), t2 = gld(A.Tin + 3 * k + 1), t3 = gld(A.Tin + 3 * k + 2);
             th.x = w * (z * (c * t1.x + sn * t2.x) - s * t3.x);
             th.y = w * (z * (c * t1.y + sn * t2.y) - s * t3.y);
             ph.x = w * (c * t2.x - sn * t1.x);
@@ -878,10 +919,10 @@ __device__ __forceinline__ void ring_fwd_body(const RingArgs<real> &A, int r, un
         const C2<real> fp = {(real)(cph * inv_s), (real)(-sph * inv_s)};
         const C2<real> fm = {(real)(cph * inv_s), (real)(sph * inv_s)};
         C2<real> *o = A.buf + ((size_t)m * NR + r) * 4;
-        o[0] = cmul(buf[bp], fp);
-        o[1] = cmul(buf[n2 + bp], fp);
-        o[2] = cmul(buf[bm], fm);
-        o[3] = cmul(buf[n2 + bm], fm);
+        gst(o, cmul(buf[bp], fp));
+        gst(o + 1, cmul(buf[n2 + bp], fp));
+        gst(o + 2, cmul(buf[bm], fm));
+        gst(o + 3, cmul(buf[n2 + bm], fm));
     }
 }
 
@@ -907,8 +948,8 @@ __device__ __forceinline__ void ring_adj_body(const RingArgs<real> &A, int r, un
                 const int am = m < 0 ? -m : m;
                 const int slot = m < 0 ? 2 : 0;
                 const C2<real> *e = A.buf + ((size_t)am * A.NP + p) * 8;
-                const C2<real> eth = e[slot], eph = e[slot + 1];
-                const C2<real> oth = e[4 + slot], oph = e[4 + slot + 1];
+                const C2<real> eth = gld(e + slot), eph = gld(e + slot + 1);
+                const C2<real> oth = gld(e + 4 + slot), oph = gld(e + 4 + slot + 1);
                 double cph = 1.0, sph = 0.0;
                 if (rd.phi0 != 0.0) sincos(m * rd.phi0, &sph, &cph);
                 const C2<real> f = {(real)(cph * inv_s), (real)(sph * inv_s)};
@@ -929,23 +970,23 @@ __device__ __forceinline__ void ring_adj_body(const RingArgs<real> &A, int r, un
     fft_lds<real, NT>(buf, n2, A.ffts, fdp, A.tw, wR, true);
     const double *twn = A.tw + 2 * ld_const(&fdp->tw_offset);
     for (int j = threadIdx.x; j < n; j += NT) {
-        const double er = twn[2 * j], ei = -twn[2 * j + 1];
+        const double er = gld(twn + 2 * j), ei = -gld(twn + 2 * j + 1);
         const real c = (real)(rd.c0 * er - rd.s0 * ei);
         const real sn = (real)(rd.s0 * er + rd.c0 * ei);
         const real z = (real)rd.z, s = (real)rd.s;
         C2<real> th = buf[j], ph = buf[n2 + j];
         const int64_t k = rd.offset + j;
         if (A.weighted) {  // W S: the Hermitian transpose of the weighted analysis
-            const real w = (real)(rd.uniform_w ? rd.w : A.weights[k]);
+            const real w = (real)(rd.uniform_w ? rd.w : gld(A.weights + k));
             th.x *= w; th.y *= w; ph.x *= w; ph.y *= w;
         }
         if (A.scalar) {  // f = s T_theta: the synthesised sum before the division by s
-            A.Tout[k] = {s * th.x, s * th.y};
+            gst(A.Tout + k, C2<real>{s * th.x, s * th.y});
             continue;
         }
-        A.Tout[3 * k] = {z * c * th.x - sn * ph.x, z * c * th.y - sn * ph.y};
-        A.Tout[3 * k + 1] = {z * sn * th.x + c * ph.x, z * sn * th.y + c * ph.y};
-        A.Tout[3 * k + 2] = {-s * th.x, -s * th.y};
+        gst(A.Tout + 3 * k, C2<real>{z * c * th.x - sn * ph.x, z * c * th.y - sn * ph.y});
+        gst(A.Tout + 3 * k + 1, C2<real>{z * sn * th.x + c * ph.x, z * sn * th.y + c * ph.y});
+        gst(A.Tout + 3 * k + 2, C2<real>{-s * th.x, -s * th.y});
     }
 }
 
@@ -1123,6 +1164,22 @@ __device__ __forceinline__ void load_aprime(const double *__restrict__ ap, int l
         if (lp0 + s > Lp1) a[s] = 0.0;
 }
 
+// acc += bcast_k(g) * r, where bcast_k(g) is g of lane k of the lane's row of 16
+// (binary64 DPP row broadcast).  The assembler form is the only one that puts
+// the broadcast on the FMA itself.  A DPP read needs two wait states after a
+// vector ALU write of its source, which the compiler does not see inside the
+// assembler text: the first FMA of each group of eight waits them out.
+template <int K, bool kWait>
+__device__ __forceinline__ void fmac_row_bcast(double &acc, double g, double r) {
+    if constexpr (kWait)
+        asm("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+            : "+v"(acc)
+            : "v"(g), "v"(r), "n"(K));
+    else
+        asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+            : "+v"(acc)
+            : "v"(g), "v"(r), "n"(K));
+}
 // ---------------------------------------------------------------------------
 // Binary64 Legendre stages on the four-block 4x4x4 MFMA (v_mfma_f64_4x4x4f64).
 // On gfx950 lane l holds A[block (l>>2)&3][row l&3][k l>>4],
@@ -1160,6 +1217,23 @@ __device__ __forceinline__ void first_blocks(int sblk, int nblk, int wave, int n
     __syncthreads();
 }
 
+// Sixteen recurrence steps of the binary64 analysis on P (see leg_fwd_f64q_body):
+// step s: P <- P_{l-2} + a'_{lp0+s} (z_s P_{l-1}), a' by row broadcast of lane s;
+// rows 4i + pi and 4i + pi + 2 go to the lane's LDS slot 2i + pi together.
+template <int S>
+__device__ __forceinline__ void fwd_steps(double acur, double z_even, double z_odd, double &p1, double &p2,
+                                          double (&held)[2], double2 *qt, int lane) {
+    if constexpr (S < kRowsB) {
+        const double t = ((S & 1) ? z_odd : z_even) * p1;
+        fmac_row_bcast<S, S == 0>(p2, acur, t);  // p2 is now P_{lp0+S}
+        if constexpr ((S & 2) != 0)
+            qt[SwzQ2Fwd::slot(lane, 2 * (S >> 2) + (S & 1))] = double2{held[S & 1], p2};
+        else
+            held[S & 1] = p2;
+        fwd_steps<S + 1>(acur, z_even, z_odd, p2, p1, held, qt, lane);
+    }
+}
+
 // Analysis, binary64: workgroup = order m, waves = tiles of 64 ring pairs.
 // Instruction (row group r, pair step g): block b = (parity pi = b>>1, column
 // half h = b&1), rows = degrees lp0 + 4i + 2r + pi, K = pairs 4g + k,
@@ -1183,60 +1257,74 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
         const int pp = tile * kTileP + 4 * g + k;
         double v = 0.0;
         if (pp < NPT) {
-            const PairDesc pd = A.pairs[pp];
-            const double xn = RBm[(size_t)pd.rn * 8 + col];
-            const double xs = pd.rs >= 0 ? RBm[(size_t)pd.rs * 8 + col] : 0.0;
+            const PairDesc pd = ld_pair(A.pairs + pp);
+            const double xn = gld(RBm + ((size_t)pd.rn * 8 + col));
+            const double xs = pd.rs >= 0 ? gld(RBm + ((size_t)pd.rs * 8 + col)) : 0.0;
             v = pi == 0 ? xn + xs : xn - xs;
         }
         bv[g] = v;
     }
     const int p = tile * kTileP + lane;
     const bool valid = p < NPT;
-    const double z = valid ? A.pz[p] : 0.0;
+    const double z = valid ? gld(A.pz + (p)) : 0.0;
     const LaneStart S = lane_start(A.start, A.sblk, (size_t)m * NP + p, valid);
     double q1 = 0.0, q2 = 0.0;
-    const double seq = A.eq_ring >= 0 ? A.seeds[(size_t)m * NP + NPT] : 0.0;
+    const double seq = A.eq_ring >= 0 ? gld(A.seeds + ((size_t)m * NP + NPT)) : 0.0;
     const double *xeq = A.eq_ring >= 0 ? RBm + (size_t)A.eq_ring * 8 : nullptr;
     const double *ap = A.aprime + t0 - m;  // indexed by l'
     const int nl = L + 2 - m;
     const int nblk = (nl + kRowsB - 1) / kRowsB;
     int wfirst, gfirst;
     first_blocks(S.blk, nblk, wave, nw, reinterpret_cast<int *>(red), wfirst, gfirst);
-    // output slots o = threadIdx.x + 64 u (u < 2) of the reduction; their c_{l'} factors
-    // are loaded at the start of each block, well before the reduction needs them
+    // The recurrence runs on P_l = sigma_l Q_l with sigma_l = -1 for l = 2, 3 (mod 4) and
+    // +1 otherwise: then P_l = P_{l-2} + a'_l (+-z) P_{l-1} (+z for odd l, -z for even l),
+    // one product and one FMA that accumulates into P_{l-2}'s register, and sigma_l is
+    // applied to the reduced sums.  a'_{l'} comes lane-wise (lane j: a'_{lp0 + (j & 15)}, every
+    // row of 16 lanes alike) from a vector load issued one block ahead, and reaches the
+    // FMA by row broadcast; a scalar load would be waited for with the LDS traffic.
+    const double z_even = (m & 1) ? z : -z;  // factor of the even steps s (degree m + 16 blk + s) ...
+    const double z_odd = -z_even;            // ... and of the odd ones
+    // a' of block b, lane-wise, loaded without a branch (the index is clamped into the
+    // order's row, and entries past L+1 are zeroed where they are used)
+    auto load_a = [&](int b) -> double { return gld(ap + min(m + b * kRowsB + (lane & 15), L + 1)); };
+    // output slots o = threadIdx.x + 64 u (u < 2) of the reduction
     auto out_slot = [&](int o, int &lp_off, int &c) {
         const int r = o >> 6, ln = o & 63;
         const int bb = (ln >> 2) & 3;
         lp_off = 4 * (ln >> 4) + 2 * r + (bb >> 1);
         c = 4 * (bb & 1) + (ln & 3);
     };
-    for (int blk = 0; blk < nblk; ++blk) {
+    const int nout = blockDim.x == 64 ? 2 : 1;  // slots per thread (threads >= 128 have none)
+    double xq[2] = {0.0, 0.0};                   // the equator ring's value of each slot's column
+    if (xeq)
+        for (int u = 0; u < nout; ++u) {
+            int so, c;
+            out_slot((threadIdx.x + u * 64) & 127, so, c);
+            xq[u] = gld(xeq + c);
+        }
+    // One 16-degree block; araw holds its a' (loaded one block earlier), anext receives
+    // the next block's.  The loop below alternates two registers between the roles, so
+    // that no copy has to wait for a load in flight.
+    auto block = [&](int blk, double araw, double &anext) {
         const int lp0 = m + blk * kRowsB;
+        // c_{l'} of the thread's slots, loaded here and used after the reduction
         double csc[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int o = threadIdx.x + u * 64;
             int so, c;
-            out_slot(o, so, c);
-            const int lp = lp0 + so;
-            csc[u] = (o < 128 && (u == 0 || blockDim.x == 64) && lp <= L + 1) ? A.cscale[t0 + lp - m] : 0.0;
+            out_slot((threadIdx.x + u * 64) & 127, so, c);
+            csc[u] = gld(A.cscale + (t0 + min(lp0 + so, L + 1) - m));
         }
+        anext = load_a(max(blk + 1, wfirst));
         double acc0 = 0.0, acc1 = 0.0;
         if (blk >= wfirst) {
-            take_start(S, blk * kRowsB, q1, q2);
-            double ab[kRowsB];
-            load_aprime(ap, lp0, L + 1, ab);
-            double held[2] = {0.0, 0.0};  // rows 4i + pi, waiting for their partner two rows on
-#pragma unroll
-            for (int s = 0; s < kRowsB; ++s) {
-                const double v = fma(ab[s] * z, q1, -q2);
-                if (s & 2)
-                    qt[SwzQ2Fwd::slot(lane, 2 * (s >> 2) + (s & 1))] = double2{held[s & 1], v};
-                else
-                    held[s & 1] = v;
-                q2 = q1;
-                q1 = v;
+            if (blk * kRowsB == kStartBlock * S.blk) {  // the lane's start state, as P
+                q1 = ((lp0 - 1) & 2) ? -S.q1 : S.q1;
+                q2 = ((lp0 - 2) & 2) ? -S.q2 : S.q2;
             }
+            const double acur = lp0 + (lane & 15) <= L + 1 ? araw : 0.0;
+            double held[2] = {0.0, 0.0};  // rows 4i + pi, waiting for their partner two rows on
+            fwd_steps<0>(acur, z_even, z_odd, q1, q2, held, qt, lane);
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int g = 0; g < 16; ++g) {
@@ -1254,28 +1342,36 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
             rw[64 + lane] = acc1;
             __syncthreads();
         }
+        // sum over waves and store; the buffer of block blk is rewritten at blk + 2,
+        // after the next barrier, so one barrier per block suffices
+        if (threadIdx.x >= 128) return;
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
+            if (u >= nout) break;
             const int o = threadIdx.x + u * 64;
-            if (o >= 128 || (u == 1 && blockDim.x != 64)) break;
             int so, c;
             out_slot(o, so, c);
-            const int ppi = so & 1;
             const int lp = lp0 + so;
             if (lp <= L + 1) {
                 double sum = 0.0;
                 if (blk >= gfirst) {
                     const double *rb = red + (blk & 1) * nw * 128;
                     for (int w = 0; w < nw; ++w) sum += rb[w * 128 + o];
+                    if (lp & 2) sum = -sum;  // sigma_{l'}
                 }
                 const int64_t ti = t0 + lp - m;
-                if (xeq && ppi == 0 && group == 0) {
+                if (xeq && (so & 1) == 0 && group == 0) {
                     const int kk = (lp - m) >> 1;
-                    sum += ((kk & 1) ? -seq : seq) * xeq[c];
+                    sum += ((kk & 1) ? -seq : seq) * xq[u];
                 }
-                A.F[group * A.gstride + ti * 8 + c] = csc[u] * sum;
+                gst(A.F + (group * A.gstride + ti * 8 + c), csc[u] * sum);
             }
         }
+    };
+    double ra = load_a(wfirst), rb = 0.0;
+    for (int blk = 0; blk < nblk; blk += 2) {
+        block(blk, ra, rb);
+        if (blk + 1 < nblk) block(blk + 1, rb, ra);
     }
 }
 
@@ -1303,20 +1399,20 @@ __device__ __forceinline__ void leg_fwd_body(const LegFwdArgs<real> &A, int m, i
         const int pp = tile * kTileP + 4 * g + k;
         real v = 0;
         if (pp < NPT) {
-            const PairDesc pd = A.pairs[pp];
-            const real xn = RBm[(size_t)pd.rn * 8 + (j & 7)];
-            const real xs = pd.rs >= 0 ? RBm[(size_t)pd.rs * 8 + (j & 7)] : (real)0;
+            const PairDesc pd = ld_pair(A.pairs + pp);
+            const real xn = gld(RBm + ((size_t)pd.rn * 8 + (j & 7)));
+            const real xs = pd.rs >= 0 ? gld(RBm + ((size_t)pd.rs * 8 + (j & 7))) : (real)0;
             v = j < 8 ? xn + xs : xn - xs;
         }
         bv[g] = v;
     }
     const int p = tile * kTileP + lane;
     const bool valid = p < NPT;
-    const double z = valid ? A.pz[p] : 0.0;
+    const double z = valid ? gld(A.pz + (p)) : 0.0;
     const LaneStart S = lane_start(A.start, A.sblk, (size_t)m * NP + p, valid);
     double q1 = 0.0, q2 = 0.0;
     // equator ring (z = 0): Q_{m+2k} = (-1)^k Lambda_{m,m}(0), odd degrees vanish
-    const double seq = A.eq_ring >= 0 ? A.seeds[(size_t)m * NP + NPT] : 0.0;
+    const double seq = A.eq_ring >= 0 ? gld(A.seeds + ((size_t)m * NP + NPT)) : 0.0;
     const real *xeq = A.eq_ring >= 0 ? RBm + (size_t)A.eq_ring * 8 : nullptr;
     const int nl = L + 2 - m;
     const int nblk = (nl + kRowsB - 1) / kRowsB;
@@ -1328,7 +1424,7 @@ __device__ __forceinline__ void leg_fwd_body(const LegFwdArgs<real> &A, int m, i
         if (blk >= wfirst) {
             take_start(S, blk * kRowsB, q1, q2);
             const int la = lp0 + (lane & 15);
-            const double areg = la <= L + 1 ? A.aprime[t0 + la - m] : 0.0;
+            const double areg = la <= L + 1 ? gld(A.aprime + (t0 + la - m)) : 0.0;
             recur16<real, SwzFwd>(qt, areg, z, q1, q2, lane);
 #pragma unroll
             for (int g = 0; g < 16; g += 2) {
@@ -1363,9 +1459,9 @@ __device__ __forceinline__ void leg_fwd_body(const LegFwdArgs<real> &A, int m, i
                     // even-parity row: the equator adds Q_{lp}(0) X_eq
                     const int kk = (lp - m) >> 1;
                     const double qe = (kk & 1) ? -seq : seq;
-                    sum += (real)qe * xeq[col];
+                    sum += (real)qe * gld(xeq + (col));
                 }
-                A.F[group * A.gstride + ti * 8 + (col & 7)] = (real)A.cscale[ti] * sum;
+                gst(A.F + (group * A.gstride + ti * 8 + (col & 7)), (real)gld(A.cscale + (ti)) * sum);
             }
         }
     }
@@ -1447,22 +1543,6 @@ struct alignas(16) AdjRow {
     double a;     // a'_{l'}
 };
 
-// acc += bcast_k(g) * r, where bcast_k(g) is g of lane k of the lane's row of 16
-// (binary64 DPP row broadcast).  The assembler form is the only one that puts
-// the broadcast on the FMA itself.  A DPP read needs two wait states after a
-// vector ALU write of its source, which the compiler does not see inside the
-// assembler text: the first FMA of each group of eight waits them out.
-template <int K, bool kWait>
-__device__ __forceinline__ void fmac_row_bcast(double &acc, double g, double r) {
-    if constexpr (kWait)
-        asm("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
-            : "+v"(acc)
-            : "v"(g), "v"(r), "n"(K));
-    else
-        asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
-            : "+v"(acc)
-            : "v"(g), "v"(r), "n"(K));
-}
 template <int K0, int C = 0>
 __device__ __forceinline__ void fmac_row_bcast8(double (&S)[8], double g, double r) {
     fmac_row_bcast<K0 + C, C == 0>(S[C], g, r);
@@ -1505,7 +1585,7 @@ __device__ __forceinline__ void adj_valu_block(const LegArgs<out> &A, const doub
         // the lane's pairs are adjacent, so that both start near the same chunk
         const int p = pw + PPL * lane + u;
         const bool valid = p < pend;
-        z[u] = valid ? A.pz[p] : 0.0;
+        z[u] = valid ? gld(A.pz + (p)) : 0.0;
         q1[u] = q2[u] = 0.0;
         const LaneStart S = lane_start(A.start, A.sblk, (size_t)m * NP + p, valid);
         s_state[wave][u][lane] = double2{S.q1, S.q2};
@@ -1532,10 +1612,10 @@ __device__ __forceinline__ void adj_valu_block(const LegArgs<out> &A, const doub
         for (int r = 0; r < kG; ++r) {
             const int i = threadIdx.x + r * nt;
             const int lp = lp0 + (i >> 3);
-            sg[r] = (i < 8 * kAdjChunk && lp <= Lp1) ? g[(int64_t)lp * 8 + (i & 7)] : 0.0;
+            sg[r] = (i < 8 * kAdjChunk && lp <= Lp1) ? gld(g + ((int64_t)lp * 8 + (i & 7))) : 0.0;
         }
         const int la = lp0 + (int)threadIdx.x;
-        sa = ((int)threadIdx.x < kAdjChunk && la <= Lp1) ? ap[la] : 0.0;
+        sa = ((int)threadIdx.x < kAdjChunk && la <= Lp1) ? gld(ap + (la)) : 0.0;
     };
     auto stage_store = [&](int k) {
         AdjRow *b = buf + (k & 1) * kAdjChunk;
@@ -1613,8 +1693,8 @@ __device__ __forceinline__ void adj_valu_block(const LegArgs<out> &A, const doub
             out *o = A.PB + ((size_t)m * NP + p) * 16;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                o[C0 + c] = (out)E[u][c];
-                o[8 + C0 + c] = (out)O[u][c];
+                gst(o + (C0 + c), (out)E[u][c]);
+                gst(o + (8 + C0 + c), (out)O[u][c]);
             }
         }
     }
@@ -1625,8 +1705,8 @@ __device__ __forceinline__ void adj_valu_block(const LegArgs<out> &A, const doub
         eacc += __shfl_xor(eacc, 32);
         if (lane < 8) {
             out *o = A.PB + ((size_t)m * NP + NPT) * 16;
-            o[lane] = (out)(A.seeds[(size_t)m * NP + NPT] * eacc);
-            o[8 + lane] = 0;
+            gst(o + (lane), (out)(gld(A.seeds + ((size_t)m * NP + NPT)) * eacc));
+            gst(o + (8 + lane), (out)0);
         }
     }
 }
@@ -1653,14 +1733,14 @@ __device__ __forceinline__ void adj_tile_f32(const LegArgs<float> &A, int m, int
         const int lp0 = lA + blk * kRowsB;
         take_start(S, lp0 - m, q1, q2);
         const int la = lp0 + (lane & 15);
-        const double areg = la < lB ? A.aprime[t0 + la - m] : 0.0;
+        const double areg = la < lB ? gld(A.aprime + (t0 + la - m)) : 0.0;
         // B operands: lane (j + 16k) holds g[row 4gg + k][j & 7] if the row's
         // parity matches the column half (row parity == (lp - m) & 1 == k & 1)
         float bv[4];
 #pragma unroll
         for (int gg = 0; gg < 4; ++gg) {
             const int lp = lp0 + 4 * gg + k;
-            bv[gg] = (lp < lB && (j >> 3) == (k & 1)) ? g[(int64_t)lp * 8 + (j & 7)] : 0.f;
+            bv[gg] = (lp < lB && (j >> 3) == (k & 1)) ? gld(g + ((int64_t)lp * 8 + (j & 7))) : 0.f;
         }
         recur16<float, SwzAdj>(qt, areg, z, q1, q2, lane);
         f32x4 ab[4];
@@ -1700,7 +1780,7 @@ __device__ __forceinline__ void equator_adj_body(const LegArgs<real> &A, int m) 
     real acc = 0;
 #pragma unroll 4
     for (int kk = rg; kk < nk; kk += 32) {
-        const real v = g[(int64_t)(2 * kk) * 8 + c];
+        const real v = gld(g + ((int64_t)(2 * kk) * 8 + c));
         acc += (kk & 1) ? -v : v;
     }
     acc += __shfl_xor(acc, 8);
@@ -1711,8 +1791,8 @@ __device__ __forceinline__ void equator_adj_body(const LegArgs<real> &A, int m) 
     if (t < 8) {
         const real sum = (part[0][t] + part[1][t]) + (part[2][t] + part[3][t]);
         real *o = A.PB + ((size_t)m * NP + A.NPT) * 16;
-        o[t] = (real)A.seeds[(size_t)m * NP + A.NPT] * sum;
-        o[8 + t] = 0;
+        gst(o + (t), (real)gld(A.seeds + ((size_t)m * NP + A.NPT)) * sum);
+        gst(o + (8 + t), (real)0);
     }
 }
 
@@ -1847,9 +1927,9 @@ __device__ __forceinline__ void leg_fwd_bf16_body(const LegFwdArgs<float> &A, in
             const int pp = tile * kTileP + 32 * c + 8 * kg + t;
             float x = 0.f;
             if (pp < NPT) {
-                const PairDesc pd = A.pairs[pp];
-                const float xn = RBm[(size_t)pd.rn * 8 + (j & 7)];
-                const float xs = pd.rs >= 0 ? RBm[(size_t)pd.rs * 8 + (j & 7)] : 0.f;
+                const PairDesc pd = ld_pair(A.pairs + pp);
+                const float xn = gld(RBm + ((size_t)pd.rn * 8 + (j & 7)));
+                const float xs = pd.rs >= 0 ? gld(RBm + ((size_t)pd.rs * 8 + (j & 7))) : 0.f;
                 x = j < 8 ? xn + xs : xn - xs;
             }
             v[t] = x;
@@ -1858,10 +1938,10 @@ __device__ __forceinline__ void leg_fwd_bf16_body(const LegFwdArgs<float> &A, in
     }
     const int p = tile * kTileP + lane;
     const bool valid = p < NPT;
-    const double z = valid ? A.pz[p] : 0.0;
+    const double z = valid ? gld(A.pz + (p)) : 0.0;
     const LaneStart S = lane_start(A.start, A.sblk, (size_t)m * NP + p, valid);
     double q1 = 0.0, q2 = 0.0;
-    const double seq = A.eq_ring >= 0 ? A.seeds[(size_t)m * NP + NPT] : 0.0;
+    const double seq = A.eq_ring >= 0 ? gld(A.seeds + ((size_t)m * NP + NPT)) : 0.0;
     const float *xeq = A.eq_ring >= 0 ? RBm + (size_t)A.eq_ring * 8 : nullptr;
     const double *ap = A.aprime + t0 - m;  // indexed by l'
     const int nl = L + 2 - m;
@@ -1913,9 +1993,9 @@ __device__ __forceinline__ void leg_fwd_bf16_body(const LegFwdArgs<float> &A, in
                 if (xeq && col < 8 && group == 0) {
                     const int kk = (lp - m) >> 1;
                     const double qe = (kk & 1) ? -seq : seq;
-                    sum += (float)qe * xeq[col];
+                    sum += (float)qe * gld(xeq + (col));
                 }
-                A.F[group * A.gstride + ti * 8 + (col & 7)] = (float)A.cscale[ti] * sum;
+                gst(A.F + (group * A.gstride + ti * 8 + (col & 7)), (float)gld(A.cscale + (ti)) * sum);
             }
         }
     }
@@ -1950,7 +2030,7 @@ __device__ __forceinline__ void adj_tile_f64_polar(const LegArgs<float> &A, int 
     const double *g = A.FG64 + (t0 - m) * 8;  // indexed by l'
     const int p = p0 + lane;
     const bool valid = lane < 16 * NB && p < pend;
-    const double z = valid ? A.pz[p] : 0.0;
+    const double z = valid ? gld(A.pz + (p)) : 0.0;
     const LaneStart S = lane_start(A.start, A.sblk, (size_t)m * NP + p, valid);
     double q1 = 0.0, q2 = 0.0;
     const int j = lane & 15, k = lane >> 4;
@@ -1963,14 +2043,14 @@ __device__ __forceinline__ void adj_tile_f64_polar(const LegArgs<float> &A, int 
         const int lp0 = m + blk * kRowsB;
         take_start(S, lp0 - m, q1, q2);
         const int la = lp0 + (lane & 15);
-        const double areg = la <= L + 1 ? A.aprime[t0 + la - m] : 0.0;
+        const double areg = la <= L + 1 ? gld(A.aprime + (t0 + la - m)) : 0.0;
         // B operands: lane (j + 16k) holds g[row 4gg + k][j & 7] if the row's
         // parity matches the column half (row parity == (lp - m) & 1 == k & 1)
         double bv[4];
 #pragma unroll
         for (int gg = 0; gg < 4; ++gg) {
             const int lp = lp0 + 4 * gg + k;
-            bv[gg] = (lp <= L + 1 && (j >> 3) == (k & 1)) ? g[(int64_t)lp * 8 + (j & 7)] : 0.0;
+            bv[gg] = (lp <= L + 1 && (j >> 3) == (k & 1)) ? gld(g + ((int64_t)lp * 8 + (j & 7))) : 0.0;
         }
         recur16<double, SwzAdj>(qt, areg, z, q1, q2, lane);
 #pragma unroll
@@ -1989,7 +2069,7 @@ __device__ __forceinline__ void adj_tile_f64_polar(const LegArgs<float> &A, int 
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int pp = p0 + 16 * b + Mfma<double>::row(lane, r);
-            if (pp < pend) A.PB[((size_t)m * NP + pp) * 16 + j] = (float)acc[b][r];
+            if (pp < pend) gst(A.PB + (((size_t)m * NP + pp) * 16 + j), (float)acc[b][r]);
         }
 }
 
@@ -2020,7 +2100,7 @@ __device__ __forceinline__ void adj_tile_bf16(const LegArgs<float> &A, int m, in
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const int lp = lp0 + 8 * kg + t;
-            bv[t] = (lp < lB && (t & 1) == (j >> 3)) ? g[(int64_t)lp * 8 + (j & 7)] : 0.f;
+            bv[t] = (lp < lB && (t & 1) == (j >> 3)) ? gld(g + ((int64_t)lp * 8 + (j & 7))) : 0.f;
         }
         const Split8<NPROD> bs = split8<NPROD>(bv);
         uint32_t hq[NS][16];
@@ -2131,7 +2211,7 @@ __device__ __forceinline__ void leg_adj_group(const LegArgs<real> &A, int m, int
         const int lane = threadIdx.x & 63;
         const int p = p0 + lane;
         const bool valid = p < A.NPT;
-        const double z = valid ? A.pz[p] : 0.0;
+        const double z = valid ? gld(A.pz + (p)) : 0.0;
         const LaneStart S = lane_start(A.start, A.sblk, (size_t)m * A.NP + p, valid);
         f32x4 acc[4];
         if (tile == 0)
@@ -2144,7 +2224,7 @@ __device__ __forceinline__ void leg_adj_group(const LegArgs<real> &A, int m, int
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int pp = p0 + 16 * b + Mfma<float>::row(lane, r);
-                if (pp < A.NPT) A.PB[((size_t)m * A.NP + pp) * 16 + j] = acc[b][r];
+                if (pp < A.NPT) gst(A.PB + (((size_t)m * A.NP + pp) * 16 + j), acc[b][r]);
             }
     }
 }
@@ -2224,7 +2304,7 @@ __device__ __forceinline__ void recombine_body(const CoefArgs<real> &A, int bx, 
         const int c = idx & 3, i = (idx >> 2) % (kTL + 2), mi = (idx >> 2) / (kTL + 2);
         const int m = m0 + mi, lp = l0 - 1 + i;
         v[q] = {0, 0};
-        if (idx < kItems && m <= L && lp >= m && lp <= L + 1) v[q] = A.FG[(tri_offset(L, m) + lp - m) * 4 + c];
+        if (idx < kItems && m <= L && lp >= m && lp <= L + 1) v[q] = gld(A.FG + ((tri_offset(L, m) + lp - m) * 4 + c));
     }
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
@@ -2243,9 +2323,9 @@ __device__ __forceinline__ void recombine_body(const CoefArgs<real> &A, int bx, 
         cpv[q] = cmv[q] = inv[q] = 0.0;
         if (l <= L && m <= l) {
             const double *et = A.etab + tri_offset(L, m) - m;  // indexed by l'
-            inv[q] = A.rsq[l];
-            cpv[q] = et[l + 1];
-            cmv[q] = l - 1 >= m ? et[l] : 0.0;
+            inv[q] = gld(A.rsq + (l));
+            cpv[q] = gld(et + l + 1);
+            cmv[q] = l - 1 >= m ? gld(et + l) : 0.0;
         }
     }
 #pragma unroll
@@ -2273,8 +2353,8 @@ __device__ __forceinline__ void recombine_body(const CoefArgs<real> &A, int bx, 
             av.y = parity * (cp * th1.y - cm * thm.y - fmu * ph0.x);
             bv.x = parity * (cp * ph1.x - cm * phm.x - fmu * th0.y);
             bv.y = parity * (cp * ph1.y - cm * phm.y + fmu * th0.x);
-            A.aout[base + mu] = av;
-            A.bout[base + mu] = bv;
+            gst(A.aout + (base + mu), av);
+            gst(A.bout + (base + mu), bv);
         }
     }
 }
@@ -2313,7 +2393,7 @@ __device__ __forceinline__ void prep_body(const CoefArgs<real> &A, int bx, int b
         v[q] = {0, 0};
         if (idx < kItems && l >= 1 && l <= L && m <= l) {
             const int mu = sg ? -m : m;
-            v[q] = (ab ? A.bin : A.ain)[(int64_t)l * l + l + mu - 1];
+            v[q] = gld((ab ? A.bin : A.ain) + ((int64_t)l * l + l + mu - 1));
         }
     }
 #pragma unroll
@@ -2322,7 +2402,7 @@ __device__ __forceinline__ void prep_body(const CoefArgs<real> &A, int bx, int b
         if (idx < kItems) {
             const int mi = idx % kTM, r = idx / kTM;
             const int l = l0 - 1 + (r >> 2);
-            const double rs = (l >= 1 && l <= L) ? A.rsq[l] : 0.0;
+            const double rs = (l >= 1 && l <= L) ? gld(A.rsq + (l)) : 0.0;
             cs[(r >> 2) * kRowP + (r & 3) * kTM + mi] = {(double)v[q].x * rs, (double)v[q].y * rs};
         }
     }
@@ -2338,9 +2418,9 @@ __device__ __forceinline__ void prep_body(const CoefArgs<real> &A, int bx, int b
         cscv[q] = e0v[q] = e1v[q] = 0.0;
         if (m <= L && lp >= m && lp <= L + 1) {
             const int64_t ti = tri_offset(L, m) + lp - m;
-            cscv[q] = A.cscale[ti];  // Lambda = c Q: fold c_{l'} in
-            e0v[q] = A.etab[ti];
-            e1v[q] = lp + 1 <= L + 1 ? A.etab[ti + 1] : 0.0;
+            cscv[q] = gld(A.cscale + (ti));  // Lambda = c Q: fold c_{l'} in
+            e0v[q] = gld(A.etab + (ti));
+            e1v[q] = lp + 1 <= L + 1 ? gld(A.etab + (ti + 1)) : 0.0;
         }
     }
 #pragma unroll
@@ -2371,16 +2451,16 @@ __device__ __forceinline__ void prep_body(const CoefArgs<real> &A, int bx, int b
             gph.x = parity * (c1 * bm1.x - c2 * bp1.x - csr * fmu * a0.y);
             gph.y = parity * (c1 * bm1.y - c2 * bp1.y + csr * fmu * a0.x);
             if constexpr (sizeof(real) == 8) {
-                o[2 * sgn] = {gth.x, gth.y};
-                o[2 * sgn + 1] = {gph.x, gph.y};
+                gst(o + (2 * sgn), {gth.x, gth.y});
+                gst(o + (2 * sgn + 1), {gph.x, gph.y});
             } else {
                 if (A.fg32) {
-                    o[2 * sgn] = {(float)gth.x, (float)gth.y};
-                    o[2 * sgn + 1] = {(float)gph.x, (float)gph.y};
+                    gst(o + (2 * sgn), {(float)gth.x, (float)gth.y});
+                    gst(o + (2 * sgn + 1), {(float)gph.x, (float)gph.y});
                 }
                 C2<double> *o64 = reinterpret_cast<C2<double> *>(A.FG64) + ti * 4;
-                o64[2 * sgn] = gth;
-                o64[2 * sgn + 1] = gph;
+                gst(o64 + 2 * sgn, gth);
+                gst(o64 + 2 * sgn + 1, gph);
             }
         }
     }
