@@ -1217,20 +1217,25 @@ __device__ __forceinline__ void first_blocks(int sblk, int nblk, int wave, int n
     __syncthreads();
 }
 
-// Sixteen recurrence steps of the binary64 analysis on P (see leg_fwd_f64q_body):
-// step s: P <- P_{l-2} + a'_{lp0+s} (z_s P_{l-1}), a' by row broadcast of lane s;
-// rows 4i + pi and 4i + pi + 2 go to the lane's LDS slot 2i + pi together.
-template <int S>
-__device__ __forceinline__ void fwd_steps(double acur, double z_even, double z_odd, double &p1, double &p2,
-                                          double (&held)[2], double2 *qt, int lane) {
+// The analyses run the recurrence on P_l = sigma_l Q_l, sigma_l = -1 for l = 2, 3
+// (mod 4) and +1 otherwise: then P_l = P_{l-2} + a'_l (+-z) P_{l-1} (+z for odd l, -z
+// for even l), one product and one FMA that accumulates into P_{l-2}'s register, and
+// sigma_l is applied to the reduced sums.  a'_{l'} comes lane-wise (lane j holds
+// a'_{lp0 + (j & 15)}, every row of 16 lanes alike) from a vector load issued one block
+// ahead, and reaches the FMA by row broadcast (a scalar load would be waited for with
+// the LDS traffic).
+__device__ __forceinline__ double sigma_state(int l, double q) { return (l & 2) ? -q : q; }
+
+// Sixteen steps from degree lp0: step s: P <- P_{l-2} + a'_{lp0+s} (z_s P_{l-1}), with
+// z_s = z_even for even s and -z_even for odd s (the sign is a source modifier of the
+// product); put(s, P_{lp0+s}) stores the value.
+template <int S, typename Put>
+__device__ __forceinline__ void fwd_steps(double acur, double z_even, double &p1, double &p2, Put &&put) {
     if constexpr (S < kRowsB) {
-        const double t = ((S & 1) ? z_odd : z_even) * p1;
+        const double t = ((S & 1) ? -z_even : z_even) * p1;
         fmac_row_bcast<S, S == 0>(p2, acur, t);  // p2 is now P_{lp0+S}
-        if constexpr ((S & 2) != 0)
-            qt[SwzQ2Fwd::slot(lane, 2 * (S >> 2) + (S & 1))] = double2{held[S & 1], p2};
-        else
-            held[S & 1] = p2;
-        fwd_steps<S + 1>(acur, z_even, z_odd, p2, p1, held, qt, lane);
+        put(S, p2);
+        fwd_steps<S + 1>(acur, z_even, p2, p1, put);
     }
 }
 
@@ -1276,14 +1281,8 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
     const int nblk = (nl + kRowsB - 1) / kRowsB;
     int wfirst, gfirst;
     first_blocks(S.blk, nblk, wave, nw, reinterpret_cast<int *>(red), wfirst, gfirst);
-    // The recurrence runs on P_l = sigma_l Q_l with sigma_l = -1 for l = 2, 3 (mod 4) and
-    // +1 otherwise: then P_l = P_{l-2} + a'_l (+-z) P_{l-1} (+z for odd l, -z for even l),
-    // one product and one FMA that accumulates into P_{l-2}'s register, and sigma_l is
-    // applied to the reduced sums.  a'_{l'} comes lane-wise (lane j: a'_{lp0 + (j & 15)}, every
-    // row of 16 lanes alike) from a vector load issued one block ahead, and reaches the
-    // FMA by row broadcast; a scalar load would be waited for with the LDS traffic.
-    const double z_even = (m & 1) ? z : -z;  // factor of the even steps s (degree m + 16 blk + s) ...
-    const double z_odd = -z_even;            // ... and of the odd ones
+    // recurrence on P (fwd_steps)
+    const double z_even = (m & 1) ? z : -z;  // factor of the even steps s (degree m + 16 blk + s)
     // a' of block b, lane-wise, loaded without a branch (the index is clamped into the
     // order's row, and entries past L+1 are zeroed where they are used)
     auto load_a = [&](int b) -> double { return gld(ap + min(m + b * kRowsB + (lane & 15), L + 1)); };
@@ -1303,8 +1302,7 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
             xq[u] = gld(xeq + c);
         }
     // One 16-degree block; araw holds its a' (loaded one block earlier), anext receives
-    // the next block's.  The loop below alternates two registers between the roles, so
-    // that no copy has to wait for a load in flight.
+    // the next block's.
     auto block = [&](int blk, double araw, double &anext) {
         const int lp0 = m + blk * kRowsB;
         // c_{l'} of the thread's slots, loaded here and used after the reduction
@@ -1319,12 +1317,16 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
         double acc0 = 0.0, acc1 = 0.0;
         if (blk >= wfirst) {
             if (blk * kRowsB == kStartBlock * S.blk) {  // the lane's start state, as P
-                q1 = ((lp0 - 1) & 2) ? -S.q1 : S.q1;
-                q2 = ((lp0 - 2) & 2) ? -S.q2 : S.q2;
+                q1 = sigma_state(lp0 - 1, S.q1);
+                q2 = sigma_state(lp0 - 2, S.q2);
             }
             const double acur = lp0 + (lane & 15) <= L + 1 ? araw : 0.0;
             double held[2] = {0.0, 0.0};  // rows 4i + pi, waiting for their partner two rows on
-            fwd_steps<0>(acur, z_even, z_odd, q1, q2, held, qt, lane);
+            // rows 4i + pi and 4i + pi + 2 go to the lane's LDS slot 2i + pi together
+            fwd_steps<0>(acur, z_even, q1, q2, [&](int st, double v) {
+                if (st & 2) qt[SwzQ2Fwd::slot(lane, 2 * (st >> 2) + (st & 1))] = double2{held[st & 1], v};
+                else held[st & 1] = v;
+            });
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int g = 0; g < 16; ++g) {
@@ -1342,6 +1344,10 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
             rw[64 + lane] = acc1;
             __syncthreads();
         }
+        // the next block's a' counts as defined here, after this block's products: the
+        // copy that passes it to the next block cannot be moved up to wait for the load
+        // just issued, and the wait here does not include the stores below
+        asm volatile("" : "+v"(anext)::"memory");
         // sum over waves and store; the buffer of block blk is rewritten at blk + 2,
         // after the next barrier, so one barrier per block suffices
         if (threadIdx.x >= 128) return;
@@ -1368,10 +1374,11 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
             }
         }
     };
-    double ra = load_a(wfirst), rb = 0.0;
-    for (int blk = 0; blk < nblk; blk += 2) {
-        block(blk, ra, rb);
-        if (blk + 1 < nblk) block(blk + 1, rb, ra);
+    double an = load_a(wfirst);
+    asm volatile("" : "+v"(an)::"memory");  // waited for here, once, not in the loop
+    for (int blk = 0; blk < nblk; ++blk) {
+        const double araw = an;
+        block(blk, araw, an);
     }
 }
 
@@ -1418,14 +1425,40 @@ __device__ __forceinline__ void leg_fwd_body(const LegFwdArgs<real> &A, int m, i
     const int nblk = (nl + kRowsB - 1) / kRowsB;
     int wfirst, gfirst;
     first_blocks(S.blk, nblk, wave, nw, reinterpret_cast<int *>(red), wfirst, gfirst);
-    for (int blk = 0; blk < nblk; ++blk) {
+    // recurrence on P (fwd_steps); a' of block b, lane-wise, loaded one block ahead
+    // without a branch (index clamped into the order's row, zeroed where used)
+    const double z_even = (m & 1) ? z : -z;
+    const double *ap = A.aprime + t0 - m;  // indexed by l'
+    auto load_a = [&](int b) -> double { return gld(ap + min(m + b * kRowsB + (lane & 15), L + 1)); };
+    const int nout = blockDim.x == 64 ? 2 : 1;  // output slots per thread (threads >= 128 have none)
+    real xq[2] = {0, 0};                         // the equator ring's value of each slot's column
+    if (xeq)
+        for (int u = 0; u < nout; ++u) {
+            int row, col;
+            FwdCompact<real>::rc((threadIdx.x + u * 64) & 127, row, col);
+            xq[u] = gld(xeq + (col & 7));
+        }
+    // One 16-degree block; araw holds its a' (loaded one block earlier), anext receives
+    // the next block's.
+    auto block = [&](int blk, double araw, double &anext) {
         const int lp0 = m + blk * kRowsB;
+        double csc[2];  // c_{l'} of the thread's slots, used after the reduction
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            int row, col;
+            FwdCompact<real>::rc((threadIdx.x + u * 64) & 127, row, col);
+            csc[u] = gld(A.cscale + (t0 + min(lp0 + row, L + 1) - m));
+        }
+        anext = load_a(max(blk + 1, wfirst));
         acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
         if (blk >= wfirst) {
-            take_start(S, blk * kRowsB, q1, q2);
-            const int la = lp0 + (lane & 15);
-            const double areg = la <= L + 1 ? gld(A.aprime + (t0 + la - m)) : 0.0;
-            recur16<real, SwzFwd>(qt, areg, z, q1, q2, lane);
+            if (blk * kRowsB == kStartBlock * S.blk) {  // the lane's start state, as P
+                q1 = sigma_state(lp0 - 1, S.q1);
+                q2 = sigma_state(lp0 - 2, S.q2);
+            }
+            const double acur = lp0 + (lane & 15) <= L + 1 ? araw : 0.0;
+            fwd_steps<0>(acur, z_even, q1, q2, [&](int st, double v) { qt[SwzFwd::at(st, lane)] = (real)v; });
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int g = 0; g < 16; g += 2) {
                 const real a0 = qt[SwzFwd::at(j, 4 * g + k)];
@@ -1442,9 +1475,14 @@ __device__ __forceinline__ void leg_fwd_body(const LegFwdArgs<real> &A, int m, i
                 if (FwdCompact<real>::valid(lane, r)) rw[FwdCompact<real>::slot(lane, r)] = acc0[r] + acc1[r];
             __syncthreads();
         }
+        asm volatile("" : "+v"(anext)::"memory");  // as in leg_fwd_f64q_body
         // sum over waves and store; the buffer of block blk is rewritten at
         // blk + 2, after the next barrier, so one barrier per block suffices
-        for (int o = threadIdx.x; o < 128; o += blockDim.x) {
+        if (threadIdx.x >= 128) return;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (u >= nout) break;
+            const int o = threadIdx.x + u * 64;
             int row, col;
             FwdCompact<real>::rc(o, row, col);
             const int lp = lp0 + row;
@@ -1453,17 +1491,24 @@ __device__ __forceinline__ void leg_fwd_body(const LegFwdArgs<real> &A, int m, i
                 if (blk >= gfirst) {
                     const real *rb = red + (blk & 1) * nw * 128;
                     for (int w = 0; w < nw; ++w) sum += rb[w * 128 + o];
+                    if (lp & 2) sum = -sum;  // sigma_{l'}
                 }
                 const int64_t ti = t0 + lp - m;
                 if (xeq && col < 8 && group == 0) {
                     // even-parity row: the equator adds Q_{lp}(0) X_eq
                     const int kk = (lp - m) >> 1;
                     const double qe = (kk & 1) ? -seq : seq;
-                    sum += (real)qe * gld(xeq + (col));
+                    sum += (real)qe * xq[u];
                 }
-                gst(A.F + (group * A.gstride + ti * 8 + (col & 7)), (real)gld(A.cscale + (ti)) * sum);
+                gst(A.F + (group * A.gstride + ti * 8 + (col & 7)), (real)csc[u] * sum);
             }
         }
+    };
+    double an = load_a(wfirst);
+    asm volatile("" : "+v"(an)::"memory");  // waited for here, once, not in the loop
+    for (int blk = 0; blk < nblk; ++blk) {
+        const double araw = an;
+        block(blk, araw, an);
     }
 }
 
@@ -1948,20 +1993,38 @@ __device__ __forceinline__ void leg_fwd_bf16_body(const LegFwdArgs<float> &A, in
     const int nblk = (nl + kRowsB - 1) / kRowsB;
     int wfirst, gfirst;
     first_blocks(S.blk, nblk, wave, nw, reinterpret_cast<int *>(red), wfirst, gfirst);
-    for (int blk = 0; blk < nblk; ++blk) {
+    // recurrence on P (fwd_steps); a' of block b, lane-wise, loaded one block ahead
+    // without a branch (index clamped into the order's row, zeroed where used)
+    const double z_even = (m & 1) ? z : -z;
+    auto load_a = [&](int b) -> double { return gld(ap + min(m + b * kRowsB + (lane & 15), L + 1)); };
+    const int nout = blockDim.x == 64 ? 2 : 1;  // output slots per thread (threads >= 128 have none)
+    float xq[2] = {0.f, 0.f};                    // the equator ring's value of each slot's column
+    if (xeq)
+        for (int u = 0; u < nout; ++u) {
+            int row, col;
+            FwdCompact<float>::rc((threadIdx.x + u * 64) & 127, row, col);
+            xq[u] = gld(xeq + (col & 7));
+        }
+    // One 16-degree block; araw holds its a' (loaded one block earlier), anext receives
+    // the next block's.
+    auto block = [&](int blk, double araw, double &anext) {
         const int lp0 = m + blk * kRowsB;
+        float csc[2];  // c_{l'} of the thread's slots, used after the reduction
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            int row, col;
+            FwdCompact<float>::rc((threadIdx.x + u * 64) & 127, row, col);
+            csc[u] = (float)gld(A.cscale + (t0 + min(lp0 + row, L + 1) - m));
+        }
+        anext = load_a(max(blk + 1, wfirst));
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         if (blk >= wfirst) {
-            take_start(S, blk * kRowsB, q1, q2);
-            double ab[kRowsB];
-            load_aprime(ap, lp0, L + 1, ab);
-#pragma unroll
-            for (int s = 0; s < kRowsB; ++s) {
-                const double v = fma(ab[s] * z, q1, -q2);
-                qt[SwzFwd8::at(s, lane)] = (float)v;
-                q2 = q1;
-                q1 = v;
+            if (blk * kRowsB == kStartBlock * S.blk) {  // the lane's start state, as P
+                q1 = sigma_state(lp0 - 1, S.q1);
+                q2 = sigma_state(lp0 - 2, S.q2);
             }
+            const double acur = lp0 + (lane & 15) <= L + 1 ? araw : 0.0;
+            fwd_steps<0>(acur, z_even, q1, q2, [&](int st, double v) { qt[SwzFwd8::at(st, lane)] = (float)v; });
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
@@ -1979,7 +2042,12 @@ __device__ __forceinline__ void leg_fwd_bf16_body(const LegFwdArgs<float> &A, in
                 if (FwdCompact<float>::valid(lane, r)) rw[FwdCompact<float>::slot(lane, r)] = acc[r];
             __syncthreads();
         }
-        for (int o = threadIdx.x; o < 128; o += blockDim.x) {
+        asm volatile("" : "+v"(anext)::"memory");  // as in leg_fwd_f64q_body
+        if (threadIdx.x >= 128) return;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (u >= nout) break;
+            const int o = threadIdx.x + u * 64;
             int row, col;
             FwdCompact<float>::rc(o, row, col);
             const int lp = lp0 + row;
@@ -1988,16 +2056,23 @@ __device__ __forceinline__ void leg_fwd_bf16_body(const LegFwdArgs<float> &A, in
                 if (blk >= gfirst) {
                     const float *rb = red + (blk & 1) * nw * 128;
                     for (int w = 0; w < nw; ++w) sum += rb[w * 128 + o];
+                    if (lp & 2) sum = -sum;  // sigma_{l'}
                 }
                 const int64_t ti = t0 + lp - m;
                 if (xeq && col < 8 && group == 0) {
                     const int kk = (lp - m) >> 1;
                     const double qe = (kk & 1) ? -seq : seq;
-                    sum += (float)qe * gld(xeq + (col));
+                    sum += (float)qe * xq[u];
                 }
-                gst(A.F + (group * A.gstride + ti * 8 + (col & 7)), (float)gld(A.cscale + (ti)) * sum);
+                gst(A.F + (group * A.gstride + ti * 8 + (col & 7)), csc[u] * sum);
             }
         }
+    };
+    double an = load_a(wfirst);
+    asm volatile("" : "+v"(an)::"memory");  // waited for here, once, not in the loop
+    for (int blk = 0; blk < nblk; ++blk) {
+        const double araw = an;
+        block(blk, araw, an);
     }
 }
 
