@@ -2166,32 +2166,50 @@ __device__ __forceinline__ void adj_tile_bf16(const LegArgs<float> &A, int m, in
     const int lA = min(m + kStartBlock * wave_min_blk(S.blk), lB);
     double q1 = 0.0, q2 = 0.0;
     const int nblk = (lB - lA + kRowsA - 1) / kRowsA;
+    // The recurrence runs on P = sigma Q (fwd_steps) and sigma_{l'} goes into g: the
+    // products sum sigma_{l'} P_{l'} g_{l'} = Q_{l'} g_{l'}.  a' comes lane-wise for the two
+    // 16-degree halves of a block, loaded one block ahead without a branch.
+    const double z_even = (lA & 1) ? z : -z;  // factor of the even steps (degree parity of lA)
+    auto load_a = [&](int b, int half) -> double {
+        return gld(ap + min(lA + b * kRowsA + 16 * half + (lane & 15), lB - 1));
+    };
+    double an0 = load_a(0, 0), an1 = load_a(0, 1);
+    asm volatile("" : "+v"(an0), "+v"(an1)::"memory");  // waited for here, once
     for (int blk = 0; blk < nblk; ++blk) {
         const int lp0 = lA + blk * kRowsA;
-        take_start(S, lp0 - m, q1, q2);
-        // B: lane (j + 16kg) holds g[l' = lp0 + 8kg + t][j & 7] when the parity
+        if (lp0 - m == kStartBlock * S.blk) {  // the lane's start state, as P
+            q1 = sigma_state(lp0 - 1, S.q1);
+            q2 = sigma_state(lp0 - 2, S.q2);
+        }
+        // B: lane (j + 16kg) holds sigma_{l'} g[l' = lp0 + 8kg + t][j & 7] when the parity
         // of l' - m (= t & 1) matches the column half j / 8, else 0
         float bv[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const int lp = lp0 + 8 * kg + t;
-            bv[t] = (lp < lB && (t & 1) == (j >> 3)) ? gld(g + ((int64_t)lp * 8 + (j & 7))) : 0.f;
+            const float x = (lp < lB && (t & 1) == (j >> 3)) ? gld(g + ((int64_t)lp * 8 + (j & 7))) : 0.f;
+            bv[t] = (lp & 2) ? -x : x;
         }
         const Split8<NPROD> bs = split8<NPROD>(bv);
+        // a' past lB - 1 is zeroed (P then repeats and stays bounded; its g is zero)
+        const double a0 = lp0 + (lane & 15) <= lB - 1 ? an0 : 0.0;
+        const double a1 = lp0 + 16 + (lane & 15) <= lB - 1 ? an1 : 0.0;
+        an0 = load_a(blk + 1, 0);
+        an1 = load_a(blk + 1, 1);
         uint32_t hq[NS][16];
-        double ab[kRowsA];
-        load_aprime(ap, lp0, lB - 1, ab);
+        double held = 0.0;  // the even step's value, split together with the odd one's
+        auto put = [&](int st, double v) {
+            if ((st & 1) == 0) {
+                held = v;
+            } else {
+                uint32_t o[NS];
+                split2<NS>((float)held, (float)v, o);
 #pragma unroll
-        for (int s = 0; s < kRowsA; s += 2) {
-            const double v0 = fma(ab[s] * z, q1, -q2);
-            const double v1 = fma(ab[s + 1] * z, v0, -q1);
-            q2 = v0;
-            q1 = v1;
-            uint32_t o[NS];
-            split2<NS>((float)v0, (float)v1, o);
-#pragma unroll
-            for (int k = 0; k < NS; ++k) hq[k][s >> 1] = o[k];
-        }
+                for (int k = 0; k < NS; ++k) hq[k][st >> 1] = o[k];
+            }
+        };
+        fwd_steps<0>(a0, z_even, q1, q2, put);
+        fwd_steps<0>(a1, z_even, q1, q2, [&](int st, double v) { put(st + 16, v); });
         const int sw = (lane >> 2) & 3;
 #pragma unroll
         for (int k = 0; k < NS; ++k)
@@ -2211,6 +2229,7 @@ __device__ __forceinline__ void adj_tile_bf16(const LegArgs<float> &A, int m, in
             mma_split2<NPROD>(qa, bs, acc[b], acl[b]);
         }
         __builtin_amdgcn_wave_barrier();
+        asm volatile("" : "+v"(an0), "+v"(an1)::"memory");  // as in leg_fwd_f64q_body
     }
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[b] += acl[b];
