@@ -1717,14 +1717,15 @@ __device__ __forceinline__ void adj_valu_block(const LegArgs<out> &A, const doub
                     q2[u] = q1[u];
                     q1[u] = v;
                 }
-                if (d + 1 < nd) {
+                // the odd step runs also past the last degree (nd odd): that row was
+                // staged with g = 0 and a' = 0, so it adds zeros, and without the branch
+                // the two steps need no register moves
 #pragma unroll
-                    for (int u = 0; u < PPL; ++u) {
-                        const double v = fma(a1 * z[u], q1[u], -q2[u]);
-                        fmac_row_bcastn<8 + C0, NC>(O[u], G, v);
-                        q2[u] = q1[u];
-                        q1[u] = v;
-                    }
+                for (int u = 0; u < PPL; ++u) {
+                    const double v = fma(a1 * z[u], q1[u], -q2[u]);
+                    fmac_row_bcastn<8 + C0, NC>(O[u], G, v);
+                    q2[u] = q1[u];
+                    q1[u] = v;
                 }
             }
         }
