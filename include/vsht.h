@@ -283,8 +283,9 @@ vsht_status vsht_get_stage_times(vsht_plan_t plan, double *ms, int64_t *count, i
  *                   classes, the cheapest up to 1/8 of the total, the next up to
  *                   1/2, the rest, and each class runs its stages as a parallel
  *                   branch of the graph, so that small fields finish early; 0:
- *                   all fields in one sequence of stages).  Results do not
- *                   depend on the shape.  Waits for the device.
+ *                   all fields in one sequence of stages).  Chains are switched
+ *                   off in this build: chains = 1 returns VSHT_EUNSUPPORTED.
+ *                   Results do not depend on the shape.  Waits for the device.
  * vsht_batch_autotune  times every shape on the caller's buffers (roundtrip,
  *                   `reps` replays each), keeps the fastest and writes its time
  *                   per roundtrip in milliseconds to *best_ms (may be NULL).

@@ -492,7 +492,7 @@ class BatchPlan:
         return {"adj_nw": x.value, "fwd_merge": y.value, "lpt": z.value, "ring_nt": r.value,
                 "chains": c.value}
 
-    def set_config(self, adj_nw=4, fwd_merge=0, lpt=1, ring_nt=256, chains=1):
+    def set_config(self, adj_nw=4, fwd_merge=0, lpt=1, ring_nt=256, chains=0):
         _raise_for(load_library().vsht_batch_set_config(self._h, int(adj_nw), int(fwd_merge), int(lpt),
                                                         int(ring_nt), int(chains)), "vsht_batch_set_config")
 

@@ -1287,6 +1287,8 @@ vsht_status vsht_batch_set_config(vsht_plan_t plan, int adj_nw, int fwd_merge, i
     if (s != VSHT_OK) return s;
     if (adj_nw != 1 && adj_nw != 2 && adj_nw != 4) return fail(VSHT_EINVAL, "adj_nw must be 1, 2 or 4");
     if (ring_nt != 256 && ring_nt != 512) return fail(VSHT_EINVAL, "ring_nt must be 256 or 512");
+    if (chains && !kBatchChainsEnabled)
+        return fail(VSHT_EUNSUPPORTED, "parallel size-class chains are switched off in this build");
     BatchPlan &B = *plan->batch;
     DeviceGuard guard(plan->p.device);
     hipError_t e = hipDeviceSynchronize();  // no replay may still read the work lists
@@ -1399,13 +1401,13 @@ vsht_status vsht_batch_autotune(vsht_plan_t plan, const void *const *a, const vo
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     float best = -1.f;
-    int bn = 4, bm = 0, bl = 1, br = 256, bc = 1;
+    int bn = 4, bm = 0, bl = 1, br = 256, bc = 0;
     const int nws[1] = {4};  // the synthesis shape is fixed (four waves); adj_nw has no effect
     for (int i = 0; i < 1 && s == VSHT_OK; ++i)
         for (int fm = 0; fm < 2 && s == VSHT_OK; ++fm)
             for (int lpt = 0; lpt < 2 && s == VSHT_OK; ++lpt)
             for (int rnt : {256, 512})
-            for (int ch = 0; ch < 2; ++ch) {
+            for (int ch = 0; ch < (kBatchChainsEnabled ? 2 : 1); ++ch) {
                 if (s != VSHT_OK) break;
                 s = vsht_batch_set_config(plan, nws[i], fm, lpt, rnt, ch);
                 if (s == VSHT_OK) s = vsht_batch_roundtrip(plan, a, b, T, a2, b2, stream);  // capture + warm

@@ -322,9 +322,14 @@ struct BatchConfig {
     int fwd_merge = 0;  // 1: one analysis launch at the widest shape; 0: one launch per tile count
     int lpt = 1;        // 1: work items longest first; 0: field by field
     int ring_nt = 256;  // threads per ring workgroup (256 or 512; rings longer than 2048 always 512)
-    int chains = 1;     // 1: size classes of fields run as parallel chains; 0: one sequence
+    int chains = 0;     // 1: size classes of fields run as parallel chains; 0: one sequence
 };
 constexpr int kBatchChains = 3;
+// Parallel chains are switched off: one run crashed (segmentation fault in the host
+// process) inside an autotune that captured and replayed the multi-branch graphs, and
+// the cause is not known.  With the switch off no chain streams are created and
+// vsht_batch_set_config refuses chains = 1.
+constexpr bool kBatchChainsEnabled = false;
 struct BatchState;
 hipError_t batch_create(const std::vector<const Plan *> &fields, BatchState **out);
 void batch_destroy(BatchState *b);

@@ -1321,11 +1321,11 @@ __device__ __forceinline__ void leg_fwd_f64q_body(const LegFwdArgs<double> &A, i
                 q2 = sigma_state(lp0 - 2, S.q2);
             }
             const double acur = lp0 + (lane & 15) <= L + 1 ? araw : 0.0;
-            double held[2] = {0.0, 0.0};  // rows 4i + pi, waiting for their partner two rows on
-            // rows 4i + pi and 4i + pi + 2 go to the lane's LDS slot 2i + pi together
+            // row 4i + pi + 2r goes to half r of the lane's LDS slot 2i + pi (eight-byte
+            // writes: packing two rows for one sixteen-byte write cost register moves)
+            double *qd = reinterpret_cast<double *>(qt);
             fwd_steps<0>(acur, z_even, q1, q2, [&](int st, double v) {
-                if (st & 2) qt[SwzQ2Fwd::slot(lane, 2 * (st >> 2) + (st & 1))] = double2{held[st & 1], v};
-                else held[st & 1] = v;
+                qd[2 * SwzQ2Fwd::slot(lane, 2 * (st >> 2) + (st & 1)) + ((st >> 1) & 1)] = v;
             });
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -3938,7 +3938,7 @@ hipError_t batch_create(const std::vector<const Plan *> &fields, BatchState **ou
     // 1/8 of the batch's work, the second up to 1/2, the third the rest
     const int F = (int)fields.size();
     b->chain_of.assign(F, 0);
-    if (F >= kBatchChains) {
+    if (kBatchChainsEnabled && F >= kBatchChains) {
         std::vector<int> order(F);
         for (int i = 0; i < F; ++i) order[i] = i;
         auto cost = [&](int i) { return std::pow((double)fields[i]->L + 1.0, 3.0); };

@@ -68,10 +68,9 @@ def test_batch_equals_single_plans(torch, vsht, precision):
     print("[case] batch vs single plans", precision, LS_MIXED, flush=True)
     bp, grids, coeffs, a, b = make_batch(torch, vsht, LS_MIXED, precision)
     ref = single_results(torch, vsht, LS_MIXED, grids, a, b, precision)
-    for cfg in [dict(adj_nw=4, fwd_merge=0, lpt=1, ring_nt=256, chains=1),
+    for cfg in [dict(adj_nw=4, fwd_merge=0, lpt=1, ring_nt=256, chains=0),
                 dict(adj_nw=1, fwd_merge=1, lpt=0, ring_nt=512, chains=0),
-                dict(adj_nw=2, fwd_merge=1, lpt=1, ring_nt=256, chains=0),
-                dict(adj_nw=4, fwd_merge=1, lpt=0, ring_nt=512, chains=1)]:
+                dict(adj_nw=2, fwd_merge=1, lpt=1, ring_nt=256, chains=0)]:
         bp.set_config(**cfg)
         assert bp.config() == cfg
         T, a2, b2 = bp.roundtrip(a, b)
@@ -80,6 +79,24 @@ def test_batch_equals_single_plans(torch, vsht, precision):
             assert np.array_equal(T[f].cpu().numpy(), ref[f][0]), (cfg, f)
             assert np.array_equal(a2[f].cpu().numpy(), ref[f][1]), (cfg, f)
             assert np.array_equal(b2[f].cpu().numpy(), ref[f][2]), (cfg, f)
+    bp.close()
+
+
+@pytest.mark.skip(reason="parallel size-class chains are switched off in the library: one run crashed "
+                         "(segmentation fault in the host process) during an autotune that captured and "
+                         "replayed the multi-branch graphs, and the cause is not found")
+def test_batch_chains_equal_single_plans(torch, vsht):
+    """Size-class chains (three parallel branches of the captured graph) give the
+    single plans' results bit for bit."""
+    print("[case] batch chains vs single plans fp32", LS_MIXED, flush=True)
+    bp, grids, coeffs, a, b = make_batch(torch, vsht, LS_MIXED, "fp32")
+    ref = single_results(torch, vsht, LS_MIXED, grids, a, b, "fp32")
+    bp.set_config(adj_nw=4, fwd_merge=1, lpt=0, ring_nt=512, chains=1)
+    T, a2, b2 = bp.roundtrip(a, b)
+    torch.cuda.synchronize()
+    for f in range(len(LS_MIXED)):
+        assert np.array_equal(T[f].cpu().numpy(), ref[f][0]), f
+        assert np.array_equal(a2[f].cpu().numpy(), ref[f][1]), f
     bp.close()
 
 
@@ -121,7 +138,9 @@ def test_batch_autotune_and_field_times(torch, vsht):
     ms = bp.autotune(a, b, T, a2, b2, reps=2)
     assert ms > 0
     cfg = bp.config()
-    assert cfg["adj_nw"] in (1, 2, 4) and cfg["chains"] in (0, 1)
+    assert cfg["adj_nw"] in (1, 2, 4) and cfg["chains"] == 0
+    with pytest.raises(RuntimeError, match="EUNSUPPORTED"):
+        bp.set_config(chains=1)  # parallel chains are switched off
     bp.roundtrip(a, b, T, a2, b2)
     t0, t1 = bp.field_times()
     torch.cuda.synchronize()
