@@ -1153,17 +1153,6 @@ struct FwdCompact<float> {
     }
 };
 
-// a'_{lp0+s}, s < N, as wave-uniform values (scalar loads); entries beyond
-// L+1 read the table's padding or the next order's entries and are zeroed.
-template <int N>
-__device__ __forceinline__ void load_aprime(const double *__restrict__ ap, int lp0, int Lp1, double (&a)[N]) {
-#pragma unroll
-    for (int s = 0; s < N; ++s) a[s] = ld_const(ap + lp0 + s);
-#pragma unroll
-    for (int s = 0; s < N; ++s)
-        if (lp0 + s > Lp1) a[s] = 0.0;
-}
-
 // acc += bcast_k(g) * r, where bcast_k(g) is g of lane k of the lane's row of 16
 // (binary64 DPP row broadcast).  The assembler form is the only one that puts
 // the broadcast on the FMA itself.  A DPP read needs two wait states after a
