@@ -33,8 +33,11 @@ vsht_status hip_fail(hipError_t e, const char *what) {
     return e == hipErrorOutOfMemory ? VSHT_ENOMEM : VSHT_EDEVICE;
 }
 
-// Longest ring the ring kernels are compiled for.
-constexpr int64_t kMaxNphi = 3072;
+// Longest ring: the ring stages' DFT core holds up to 4096 points per sequence
+// (each length's stages are checked against its per-thread limits by fft_fits;
+// lengths above kMaxBluesteinN never take Bluestein's longer convolution, so a
+// ring's two sequences stay within the LDS of a workgroup).
+constexpr int64_t kMaxNphi = 4096;
 // Largest bandlimit served (parity-tested at L = 2250, Table 3's largest, and at
 // this limit).  The Legendre stages start every (order, ring pair) from a state
 // computed with a carried exponent, so seeds Lambda_{m,m} = O(s^m) below
@@ -527,6 +530,21 @@ vsht_status build_plan(Plan &P, int L, int64_t n, const double *xyz, const doubl
     if (scan.ok && (int64_t)scan.rings.size() * 2 > n && n > 8) {
         scan.ok = false;
         scan.why = "too many rings";
+    }
+    if (scan.ok) {
+        // every ring length must fit the ring DFT stages of a 512-thread workgroup;
+        // a point set with one that does not is planned as scattered points
+        std::map<int, int> fi;
+        std::vector<FftDesc> fd;
+        std::vector<double> t;
+        for (const RingDesc &r : scan.rings) {
+            const int id = fft_descriptor(r.nphi, fi, fd, t);
+            if (!fft_fits(fd[id], fd, 512)) {
+                scan.ok = false;
+                scan.why = "ring length " + std::to_string(r.nphi) + " does not fit the ring DFT stages";
+                break;
+            }
+        }
     }
     std::vector<double> tmp;
     hipError_t e = hipSuccess;

@@ -394,15 +394,17 @@ def test_ring_path_bitwise_reproducible(torch, vsht, precision):
 
 
 # ---------------------------------------------------------------------------
-# The largest sizes served: the longest ring the ring kernels take (3072 points,
-# GL at L = 1535 with 2L+2 longitudes, the exact quadrature: round trip too),
-# Table 3's largest bandlimit L = 2250 and the library's limit L = 4096, both on
-# L+1 GL rings of 3072 points (the forward is checked as the discrete sum it
-# is).  Above L ~ 1700 the seeds Lambda_{m,m} of functions that reach order one
+# The largest sizes served: GL grids with 2L+2 longitudes, the exact quadrature
+# (round trip too), at L = 1535 (3072-point rings), at Table 3's L = 1750 (3502
+# points, a radix-103 stage) and at L = 2047 (4096 points, the longest ring the
+# ring kernels take); Table 3's largest bandlimit L = 2250 and the library's
+# limit L = 4096, both on L+1 GL rings of 3072 points (the forward is checked as
+# the discrete sum it is).  Above L ~ 1700 the seeds Lambda_{m,m} of functions that reach order one
 # lie below binary64's range, so these cases run through start states computed
 # with a carried exponent.  Sampled against the oracle.
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("L,nphi,nsample", [(1535, None, 32), (2250, 3072, 32), (4096, 3072, 16)])
+@pytest.mark.parametrize("L,nphi,nsample", [(1535, None, 32), (1750, None, 16), (2047, None, 16),
+                                             (2250, 3072, 32), (4096, 3072, 16)])
 def test_largest_sizes_sampled(torch, vsht, orc, L, nphi, nsample):
     print_case("largest sizes", L, nphi)
     xyz, w = vi.gl_grid(L, n_phi=nphi)
