@@ -156,6 +156,37 @@ def run_l256(torch, vsht, vi, args):
     return out
 
 
+def run_table3(torch, vsht, vi, args):
+    """The bandlimits of the paper's timing table: FP64 forward+adjoint on the GL grid
+    (L+1) x (2L+2) (N = 2(L+1)^2 points, M = L^2 + 2L coefficients), random coefficients
+    scaled 1/l.  Bandlimits whose rings do not fit the ring DFT stages (L = 2000: 4002
+    points per ring, L = 2250: 4502) run on the scattered path and are not timed."""
+    dev = torch.device("cuda", 0)
+    out = []
+    for L in [int(x) for x in args.table3.split(",") if x]:
+        xyz, w = vi.gl_grid(L)
+        t0 = time.perf_counter()
+        plan = vsht.Plan(L, xyz, w, precision="fp64")
+        t_plan = time.perf_counter() - t0
+        if plan.kind != "rings":
+            log("table3: L=%d planned as %s, not timed" % (L, plan.kind))
+            out.append({"L": L, "points": len(w), "plan": plan.kind})
+            plan.close()
+            continue
+        a_np, b_np = vi.random_coeffs(L, 0)
+        a = torch.from_numpy(a_np).to(dev)
+        b = torch.from_numpy(b_np).to(dev)
+        sec, T, a2, b2 = time_steps(torch, plan, a, b, max(3, args.steps // 4), 1)
+        rt = rel_l2(np.concatenate([a2.cpu().numpy(), b2.cpu().numpy()]), np.concatenate([a_np, b_np]))
+        plan.close()
+        del T, a2, b2
+        log("table3: L=%d, %d points: fwd+adj %.3f ms, round trip %.2e, plan %.2f s"
+            % (L, len(w), sec * 1e3, rt, t_plan))
+        out.append({"L": L, "points": len(w), "coefficients": L * (L + 2), "ms_per_fwd_adj": round(sec * 1e3, 4),
+                    "roundtrip_rel_l2": rt, "plan_s": round(t_plan, 2)})
+    return out
+
+
 def run_batched(torch, vsht, vi, args):
     """Many fields of uneven bandlimit, each on its own GL grid (L+1) x (2L+2), complex64,
     coefficients scaled 1/l: adjoint then forward of every field, one graph replay."""
@@ -288,6 +319,9 @@ def main():
                     help="batched workload: this many complex64 fields, L uniform in [32, 512] (0: skip)")
     ap.add_argument("--grad-fields", type=int, default=8,
                     help="differentiable workload: this many fields at L=512, FP32 (0: skip)")
+    ap.add_argument("--table3", default="",
+                    help="comma-separated bandlimits: FP64 forward+adjoint on their GL grids "
+                         "(e.g. 250,500,750,1000,1250,1500,1750; empty: skip)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -351,6 +385,7 @@ def main():
     differentiable = None
     if args.grad_fields > 0:
         differentiable = run_differentiable(torch, vsht, vi, args)
+    table3 = run_table3(torch, vsht, vi, args) if args.table3 else None
 
     if args.copy_mb > 0:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the
@@ -518,6 +553,8 @@ def main():
         out["batched"] = batched
     if differentiable:
         out["differentiable"] = differentiable
+    if table3:
+        out["table3"] = table3
     print(json.dumps(out), flush=True)
 
 
